@@ -1,0 +1,247 @@
+"""Seeded synthetic inputs: media, forcing and problem presets.
+
+This module holds no arithmetic of the method: it only draws materials and
+sources, in float64 NumPy on the host, and is shared by the tests, the
+benchmark and the CPU oracle's callers, so both sides see identical inputs.
+
+The paper's workloads are analytic (Sec. 5: constant or piecewise media,
+Gaussian and discrete-delta sources); nothing here stands in for a dataset.
+Recipes (all seeded with numpy PCG64):
+
+* Gaussian random field GRF(l, seed): white noise on a periodic grid padded
+  by six correlation lengths, filtered in Fourier space by sqrt(S(k)) with
+  S(k) ~ exp(-l^2 |k|^2 / 2) (Gaussian covariance, l = 0.1), cropped to the
+  node grid and normalised to zero mean and unit sample standard deviation.
+* Random log-normal media: rho = exp(0.2 g1), mu = exp(0.2 g2),
+  lambda = mu * clip(2 exp(0.2 g3), 1, 3)  (median c_s ~ 1, c_p ~ 2).
+* Three-layer 3-D medium along z: [0,1/3) c_s = 2, rho = 1.5; [1/3,2/3)
+  c_s = 1.5, rho = 1.2; [2/3,1] c_s = 1, rho = 1; mu = rho c_s^2,
+  lambda = 2 mu; each of rho, lambda, mu times (1 + 0.05 g), g a GRF clipped
+  at +-3.
+* Gaussian point sources  f(x) = exp(-|x - x0|^2 / (2 w^2)) e,  e a unit
+  direction, amplitude 1 (the problem is linear).
+
+Arrays use the node layout [component][z][y][x] (2-D: [c][y][x]) over
+(n+1)^d nodes, x fastest.  Boundary faces are ordered -x,+x,-y,+y,-z,+z with
+0 = Dirichlet, 1 = traction-free.
+"""
+
+import math
+from dataclasses import dataclass, field
+from typing import Optional, Tuple
+
+import numpy as np
+
+DIRICHLET = 0
+FREE = 1
+BC_ALL_DIRICHLET_2D = (0, 0, 0, 0)
+BC_FREE_TOP_2D = (0, 0, 0, 1)        # Dirichlet sides and bottom, free top
+BC_ALL_DIRICHLET_3D = (0, 0, 0, 0, 0, 0)
+
+
+@dataclass
+class Case:
+    name: str
+    dim: int
+    n: Tuple[int, ...]
+    omega: float
+    rho: np.ndarray
+    lam: np.ndarray
+    mu: np.ndarray
+    f: np.ndarray
+    bc: Tuple[int, ...]
+    length: Tuple[float, ...] = None
+    tol: float = 1e-10
+    meta: dict = field(default_factory=dict)
+
+    def __post_init__(self):
+        if self.length is None:
+            self.length = (1.0,) * self.dim
+
+    @property
+    def h(self):
+        return tuple(self.length[a] / self.n[a] for a in range(self.dim))
+
+    @property
+    def node_shape(self):
+        return tuple(self.n[a] + 1 for a in reversed(range(self.dim)))
+
+
+def _fast_len(m):
+    """Smallest 2^a 3^b 5^c >= m (FFT friendly)."""
+    best = None
+    p2 = 1
+    while p2 < 2 * m:
+        p3 = p2
+        while p3 < 2 * m:
+            p5 = p3
+            while p5 < 2 * m:
+                if p5 >= m and (best is None or p5 < best):
+                    best = p5
+                p5 *= 5
+            p3 *= 3
+        p2 *= 2
+    return best
+
+
+def grf(node_shape, h, ell=0.1, seed=0, rng=None):
+    """Gaussian random field on the node grid (see module docstring)."""
+    import scipy.fft as sfft
+    rng = np.random.default_rng(seed) if rng is None else rng
+    dim = len(node_shape)
+    hs = tuple(reversed(h)) if len(h) == dim else (h[0],) * dim   # per NumPy axis
+    pad = [_fast_len(node_shape[k] + int(math.ceil(6 * ell / hs[k]))) for k in range(dim)]
+    noise = rng.standard_normal(pad)
+    spec = sfft.rfftn(noise, workers=-1)
+    ks = []
+    for k in range(dim):
+        if k == dim - 1:
+            kk = 2 * math.pi * np.fft.rfftfreq(pad[k], d=hs[k])
+        else:
+            kk = 2 * math.pi * np.fft.fftfreq(pad[k], d=hs[k])
+        shape = [1] * dim
+        shape[k] = kk.size
+        ks.append(kk.reshape(shape))
+    k2 = sum(kk * kk for kk in ks)
+    spec *= np.exp(-0.25 * ell * ell * k2)           # sqrt of exp(-l^2 k^2 / 2)
+    g = sfft.irfftn(spec, s=pad, workers=-1)
+    g = g[tuple(slice(0, s) for s in node_shape)]
+    g = g - g.mean()
+    return g / g.std()
+
+
+def media_random(node_shape, h, seed):
+    """Random log-normal (rho, lambda, mu), correlation length 0.1, sigma 0.2,
+    lambda / mu in [1, 3]."""
+    rng = np.random.default_rng(seed)
+    g1 = grf(node_shape, h, 0.1, rng=rng)
+    g2 = grf(node_shape, h, 0.1, rng=rng)
+    g3 = grf(node_shape, h, 0.1, rng=rng)
+    rho = np.exp(0.2 * g1)
+    mu = np.exp(0.2 * g2)
+    lam = mu * np.clip(2.0 * np.exp(0.2 * g3), 1.0, 3.0)
+    return rho, lam, mu
+
+
+def media_layered3d(n, seed):
+    """Three-layer medium along z with 5% smooth perturbations."""
+    rng = np.random.default_rng(seed)
+    shape = (n + 1,) * 3
+    h = (1.0 / n,) * 3
+    z = (np.arange(n + 1) / n).reshape(-1, 1, 1)
+    cs = np.where(z < 1 / 3, 2.0, np.where(z < 2 / 3, 1.5, 1.0)) * np.ones(shape)
+    rho0 = np.where(z < 1 / 3, 1.5, np.where(z < 2 / 3, 1.2, 1.0)) * np.ones(shape)
+    mu0 = rho0 * cs * cs
+    out = []
+    for base in (rho0, 2.0 * mu0, mu0):
+        g = np.clip(grf(shape, h, 0.1, rng=rng), -3.0, 3.0)
+        out.append(base * (1.0 + 0.05 * g))
+    rho, lam, mu = out
+    return rho, lam, mu
+
+
+def gaussian_sources(dim, n, length, centers, widths, directions):
+    """Sum of Gaussian point sources, one direction vector per source."""
+    shape = tuple(n[a] + 1 for a in reversed(range(dim)))
+    coords = [np.arange(n[a] + 1) * (length[a] / n[a]) for a in range(dim)]
+    grids = list(reversed(np.meshgrid(*[coords[a] for a in reversed(range(dim))], indexing="ij")))
+    f = np.zeros((dim,) + shape)
+    for x0, w, e in zip(centers, widths, directions):
+        r2 = sum((grids[a] - x0[a]) ** 2 for a in range(dim))
+        g = np.exp(-r2 / (2.0 * w * w))
+        for c in range(dim):
+            f[c] += e[c] * g
+    return f
+
+
+def unit_vector(rng, dim):
+    v = rng.standard_normal(dim)
+    return v / np.linalg.norm(v)
+
+
+def min_shear_speed(rho, mu):
+    return float(np.sqrt(np.asarray(mu) / np.asarray(rho)).min())
+
+
+# --------------------------------------------------------------------------
+# presets, shaped like the paper's experiments
+# --------------------------------------------------------------------------
+
+def config1():
+    """2-D unit square, 64 x 64 cells, rho = 1, lambda = 2, mu = 1, omega = 10,
+    all Dirichlet; Gaussian of width 0.05 in x-displacement at (0.5, 0.5);
+    CG to 1e-10."""
+    n = (64, 64)
+    shape = (65, 65)
+    f = gaussian_sources(2, n, (1.0, 1.0), [(0.5, 0.5)], [0.05], [(1.0, 0.0)])
+    return Case("cfg1_square64_const", 2, n, 10.0, np.ones(shape), np.full(shape, 2.0),
+                np.ones(shape), f, BC_ALL_DIRICHLET_2D, tol=1e-10)
+
+
+def config2(n=1024, seed=2, ppw=10.0):
+    """2-D n x n cells, random log-normal media, omega for ~ppw points per
+    shear wavelength at the slowest shear speed; Dirichlet sides and bottom,
+    traction-free top; one seeded Gaussian of width 3.2 h."""
+    h = 1.0 / n
+    shape = (n + 1, n + 1)
+    rho, lam, mu = media_random(shape, (h, h), seed)
+    rng = np.random.default_rng(1000 + seed)
+    x0 = rng.uniform(0.3, 0.7, size=2)
+    e = unit_vector(rng, 2)
+    f = gaussian_sources(2, (n, n), (1.0, 1.0), [x0], [3.2 * h], [e])
+    omega = 2 * math.pi * min_shear_speed(rho, mu) / (ppw * h)
+    return Case(f"cfg2_square{n}_random", 2, (n, n), omega, rho, lam, mu, f, BC_FREE_TOP_2D,
+                tol=1e-8, meta={"seed": seed, "center": x0.tolist(), "direction": e.tolist()})
+
+
+def config3(n=256, seed=3, ppw=8.0):
+    """3-D n^3 cells, three-layer medium with 5% perturbations, all
+    Dirichlet; omega for ~ppw points per shear wavelength; one Gaussian."""
+    h = 1.0 / n
+    rho, lam, mu = media_layered3d(n, seed)
+    rng = np.random.default_rng(1000 + seed)
+    x0 = rng.uniform(0.3, 0.7, size=3)
+    e = unit_vector(rng, 3)
+    f = gaussian_sources(3, (n, n, n), (1.0, 1.0, 1.0), [x0], [3.2 * h], [e])
+    omega = 2 * math.pi * min_shear_speed(rho, mu) / (ppw * h)
+    return Case(f"cfg3_cube{n}_layered", 3, (n, n, n), omega, rho, lam, mu, f, BC_ALL_DIRICHLET_3D,
+                tol=1e-8, meta={"seed": seed, "center": x0.tolist(), "direction": e.tolist()})
+
+
+def random_problem_2d(n, omega, seed, nsrc=None, width_h=(3.2, 3.2), rng=None):
+    """One random 2-D problem: config-2 media, 1-4 Gaussians in [0.2,0.8]^2."""
+    h = 1.0 / n
+    shape = (n + 1, n + 1)
+    rho, lam, mu = media_random(shape, (h, h), seed)
+    rng = np.random.default_rng(10_000 + seed) if rng is None else rng
+    k = int(rng.integers(1, 5)) if nsrc is None else nsrc
+    centers = [rng.uniform(0.2, 0.8, size=2) for _ in range(k)]
+    dirs = [unit_vector(rng, 2) for _ in range(k)]
+    widths = [rng.uniform(width_h[0], width_h[1]) * h for _ in range(k)]
+    f = gaussian_sources(2, (n, n), (1.0, 1.0), centers, widths, dirs)
+    return Case(f"rand2d_n{n}_s{seed}", 2, (n, n), float(omega), rho, lam, mu, f, BC_FREE_TOP_2D,
+                tol=1e-8, meta={"seed": seed, "nsrc": k})
+
+
+def config4(nprob=48, seed=4, nmin=256, nmax=1024, wmin=10.0, wmax=80.0):
+    """Batch of problems with n ~ U{nmin..nmax}, omega ~ U[wmin, wmax]."""
+    rng = np.random.default_rng(seed)
+    cases = []
+    for p in range(nprob):
+        n = int(rng.integers(nmin, nmax + 1))
+        om = float(rng.uniform(wmin, wmax))
+        cases.append(random_problem_2d(n, om, seed=100 * seed + p))
+    return cases
+
+
+def config5_problem(seed, n=256):
+    """Warm-start training/evaluation problem: n = 256, omega ~ U[20, 60],
+    config-2 media, 1-4 Gaussians of width U[2h, 6h]."""
+    rng = np.random.default_rng(50_000 + seed)
+    om = float(rng.uniform(20.0, 60.0))
+    return random_problem_2d(n, om, seed=seed, width_h=(2.0, 6.0), rng=rng)
+
+
+def random_field(shape, seed):
+    """Plain standard-normal test vector (for operator-level parity tests)."""
+    return np.random.default_rng(seed).standard_normal(shape)
