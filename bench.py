@@ -1,0 +1,240 @@
+"""Benchmark of the El-WaveHoltz hot path on one MI355X.
+
+A step is one Krylov iteration of the solve on the 2-D 1024 x 1024 random
+log-normal medium with a traction-free top (FP64): one A_h = I - S_h
+application (the half-step launch and N_T - 1 fused step launches over
+every unknown node, each with its trapezoid accumulation) plus the FP64
+M-inner-product reductions and the CG vector updates.  Inputs are resident
+in HBM before timing.  value = lattice updates per second, one lattice
+update = one unknown node advanced one time step (both components), with its
+accumulation.
+
+The JSON line also carries the roofline of the fused step kernel (HIP-event
+durations of every step launch over a profiled repeat of the timed steps),
+the FP32-stepping variants, and the CPU oracle's rate on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--all]
+"""
+
+import argparse
+import json
+import math
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "elastic lattice updates/s (% HBM roofline); time-to-1e-8 residual learned+FP32 vs plain"
+
+# Algorithmic HBM bytes per lattice update of the fused step kernel:
+#   FP64: read u^n (2x8), u^{n-1} (2x8), a, lambda, mu (3x8), acc (2x8);
+#         write u^{n+1} (2x8), acc (2x8)                                  = 104
+#   FP32 state, compensated FP64 accumulator: state 3x2x4, coefficients
+#         3x4, acc hi+lo read and written 4x2x8                           = 100
+#   FP32 state, plain FP64 accumulator: 24 + 12 + 32                      = 68
+#   3-D: three components; FP64 3x3x8 + 3x8 + 2x3x8 = 144; FP32
+#         compensated 36 + 12 + 96 = 144; FP32 plain 36 + 12 + 48 = 96
+BYTES_PER_LUP = {
+    (2, "f64"): 104, (2, "f32c"): 100, (2, "f32"): 68,
+    (3, "f64"): 144, (3, "f32c"): 144, (3, "f32"): 96,
+}
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def unknown_nodes(case):
+    cnt = 1
+    for a in range(case.dim):
+        n = case.n[a]
+        lo_d = case.bc[2 * a] == 0
+        hi_d = case.bc[2 * a + 1] == 0
+        cnt *= (n + 1) - int(lo_d) - int(hi_d)
+    return cnt
+
+
+def read_traffic(kernel_tag):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    one exists for this kernel and workload (else None)."""
+    path = os.path.join(ROOT, "profiles", f"{kernel_tag}_counters.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        m = re.match(r"\s*(traffic_bytes_per_launch|kernel_source_hash)\s*[:=]\s*(\S+)", line)
+        if m:
+            vals[m.group(1)] = m.group(2)
+    if "traffic_bytes_per_launch" not in vals:
+        return None
+    src_hash = vals.get("kernel_source_hash")
+    if src_hash and src_hash != kernel_source_hash():
+        return None          # the kernel changed since the counters were taken
+    return float(vals["traffic_bytes_per_launch"])
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels2d.hip", "kernels3d.hip", "lanes.h"):
+        h.update(open(os.path.join(ROOT, "paper_2205_12344_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def time_cg(ctx, steps, warmup):
+    import torch
+    ctx.cg_iterate(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.cg_iterate(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    # profiled repeat of the same steps: per-launch HIP events on the
+    # context's stream around every fused step kernel
+    ctx.profile_enable(True)
+    ctx.cg_iterate(steps)
+    prof = ctx.profile_read()
+    ctx.profile_enable(False)
+    return t1 - t0, prof
+
+
+def kernel_rate(ctx, napply):
+    """Profile napply A_h applications of a context (any precision)."""
+    import torch
+    x = torch.zeros(ctx.field_shape, dtype=torch.float64, device="cuda")
+    ctx.apply_A(x)
+    ctx.profile_enable(True)
+    for _ in range(napply):
+        ctx.apply_A(x)
+    prof = ctx.profile_read()
+    ctx.profile_enable(False)
+    return prof
+
+
+def cpu_baseline(case, budget_s=12.0):
+    """The oracle as it stands, timed on the host: A_h applications on the
+    benchmark workload until the budget is spent (single-threaded sparse
+    matrix-vector products and NumPy vector updates)."""
+    import numpy as np
+    from oracle.operator import Operator
+    from oracle.problem import Problem
+    from oracle.stepping import WaveHoltz
+    t0 = time.perf_counter()
+    prob = Problem(case.dim, case.n, length=case.length, bc=case.bc)
+    op = Operator(prob, case.rho, case.lam, case.mu)
+    wh = WaveHoltz(op, case.omega)
+    t_setup = time.perf_counter() - t0
+    x = np.random.default_rng(0).standard_normal(op.ndof)
+    napply = 0
+    t0 = time.perf_counter()
+    while True:
+        x = wh.apply_A(x)
+        x /= np.linalg.norm(x)
+        napply += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    el = time.perf_counter() - t0
+    lups = napply * wh.nt * unknown_nodes(case)
+    return {"value": lups / el, "unit": "LUP/s", "cores": 1, "kind": "oracle",
+            "sample": f"{napply} A_h applications ({wh.nt} steps each) of the oracle on the same 1024^2 "
+                      f"workload, {el:.1f} s; operator assembly {t_setup:.1f} s excluded"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--all", action="store_true", help="also measure the 3-D 256^3 workload")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the hot path runs on a single MI355X "
+              "(multi-GPU sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2205_12344_amd import elwh, inputs
+
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    case = inputs.config2()
+    log(f"workload {case.name}: omega {case.omega:.3f}, inputs {time.perf_counter() - t0:.1f} s")
+    nodes = unknown_nodes(case)
+
+    ctx = elwh.context_from_case(case)
+    info = ctx.info()
+    nt = info["nt"]
+    ctx.cg_begin(case.f)
+    el, prof = time_cg(ctx, args.steps, args.warmup)
+    lup_per_step = nt * nodes
+    value = lup_per_step * args.steps / el
+    ms_per_step = 1e3 * el / args.steps
+    step_avg_ms = prof["step_ms"] / max(prof["nstep"], 1)
+    b = BYTES_PER_LUP[(2, "f64")]
+    achieved = b * nodes / (step_avg_ms * 1e-3) / 1e9
+    traffic = read_traffic("step2d_f64_cfg2_1024")
+    log(f"fp64: {ms_per_step:.3f} ms/step, {value / 1e9:.2f} GLUP/s, step kernel {1e3 * step_avg_ms:.1f} us "
+        f"({prof['nstep']} launches), {achieved:.0f} GB/s")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic,
+                "kernel": "step2d_kernel<double,double,16,0,false,false>",
+                "bytes_per_lup": b, "units_per_launch": nodes,
+                "avg_launch_us": round(1e3 * step_avg_ms, 3)}
+    ctx.close()
+
+    variants = {}
+    for tag, kw in (("f32c", {"prec": elwh.FP32_STEP, "compensated": 1}),
+                    ("f32", {"prec": elwh.FP32_STEP, "compensated": 0})):
+        c2 = elwh.context_from_case(case, **kw)
+        p = kernel_rate(c2, 10)
+        avg = p["step_ms"] / max(p["nstep"], 1)
+        bb = BYTES_PER_LUP[(2, tag)]
+        variants[tag] = {"step_kernel_us": round(1e3 * avg, 3), "glup_s_kernel": round(nodes / avg / 1e6, 3),
+                         "bytes_per_lup": bb, "achieved_GBs": round(bb * nodes / avg / 1e6, 1),
+                         "frac": round(bb * nodes / avg / 1e6 / HBM_PEAK_GBS, 4)}
+        log(f"{tag}: step kernel {1e3 * avg:.1f} us, {variants[tag]['achieved_GBs']} GB/s")
+        c2.close()
+
+    if args.all:
+        c3 = inputs.config3()
+        n3 = unknown_nodes(c3)
+        for tag, kw in (("f64", {}), ("f32c", {"prec": elwh.FP32_STEP, "compensated": 1})):
+            ctx3 = elwh.context_from_case(c3, **kw)
+            p = kernel_rate(ctx3, 2)
+            avg = p["step_ms"] / max(p["nstep"], 1)
+            bb = BYTES_PER_LUP[(3, tag)]
+            variants["3d_" + tag] = {"workload": c3.name, "nt": ctx3.info()["nt"], "step_kernel_us": round(1e3 * avg, 3),
+                                     "glup_s_kernel": round(n3 / avg / 1e6, 3), "bytes_per_lup": bb,
+                                     "achieved_GBs": round(bb * n3 / avg / 1e6, 1),
+                                     "frac": round(bb * n3 / avg / 1e6 / HBM_PEAK_GBS, 4)}
+            log(f"3d {tag}: step kernel {1e3 * avg:.1f} us, {variants['3d_' + tag]['achieved_GBs']} GB/s")
+            ctx3.close()
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(case)
+        log(f"cpu oracle: {cpu['value'] / 1e6:.2f} MLUP/s ({cpu['sample']})")
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "LUP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "2-D 1024x1024 cells, random log-normal medium (corr. length 0.1, sigma 0.2, "
+                               "lambda/mu in [1,3]), Dirichlet sides and bottom, traction-free top, one "
+                               "Gaussian source, omega for 10 points per shear wavelength; one CG iteration "
+                               "per step",
+                   "grid": list(case.n), "omega": case.omega, "nt": nt, "unknown_nodes": nodes,
+                   "lup_per_step": lup_per_step},
+        "roofline": roofline, "cpu_baseline": cpu, "variants": variants,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

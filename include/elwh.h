@@ -1,0 +1,201 @@
+/*
+ * elwh.h -- C ABI of libelwh.so: the El-WaveHoltz filter operator and its
+ * Krylov solve on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: D. Appelo, F. Garcia, A. Alvarez Loya, O. Runborg, "El-WaveHoltz:
+ * A Time-Domain Iterative Solver for Time-Harmonic Elastic Waves",
+ * arXiv:2205.12344.  Section numbers below refer to that paper.
+ *
+ * Problem (Sec. 2.1, 2.2): find the real displacement v with
+ *     omega^2 rho v + div T(v) = f   in a box,
+ * T(v) = lambda (div v) I + 2 mu sym(grad v), with homogeneous Dirichlet or
+ * traction-free faces.  The library discretises it on a uniform Cartesian
+ * grid with the second-order conservative finite-difference operator of
+ * Sec. 4.1 (free faces closed from a discrete energy) and finds v as the
+ * fixed point of the WaveHoltz filter (Sec. 3, eq. el_WHI_OP) applied with
+ * the time-corrected explicit leapfrog of Sec. 4.3, by CG (or GMRES or
+ * conjugate residual) on A_h = I - S_h in the M inner product (Sec. 4.5).
+ * With the corrected scheme the result equals the direct discretisation of
+ * the Helmholtz equation, (omega^2 M + L_h) v = W f.
+ *
+ * Conventions for every entry point
+ *  - Array arguments are DEVICE pointers (e.g. torch.Tensor.data_ptr() of a
+ *    CUDA tensor) to float64 data, owned by the caller; no call keeps or
+ *    frees them.  Materials are copied at create; fields are read or written
+ *    during the call only.
+ *  - Field layout: [component][z][y][x] over the full (n+1)^dim node grid,
+ *    x fastest, no padding; 2-D fields are [2][ny+1][nx+1], 3-D fields
+ *    [3][nz+1][ny+1][nx+1].  Material arrays are one component.
+ *  - Faces are ordered -x,+x,-y,+y,-z,+z (2-D uses the first four).
+ *    Dirichlet-face nodes hold 0: inputs there are ignored, outputs there
+ *    are written as 0.  Traction-free faces are supported on the +-y faces in
+ *    2-D and the +-z faces in 3-D; the x faces (and y faces in 3-D) must be
+ *    Dirichlet.
+ *  - Calls are asynchronous on the context's stream unless stated otherwise.
+ *    One context must not be used from two threads at once.
+ *  - Errors are returned as elwh_status; nothing aborts or throws across the
+ *    ABI.  elwh_last_error() returns a message for the last failure.
+ */
+#ifndef ELWH_H
+#define ELWH_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct elwh_ctx elwh_ctx;
+
+typedef enum {
+    ELWH_OK = 0,
+    ELWH_ERR_ARG = 1,            /* invalid argument (shape, NaN/Inf, non-positive material, ...) */
+    ELWH_ERR_ALLOC = 2,          /* device or host allocation failed */
+    ELWH_ERR_HIP = 3,            /* a HIP runtime call failed */
+    ELWH_ERR_UNSTABLE = 4,       /* energy growth: the time step violates stability */
+    ELWH_ERR_NOT_CONVERGED = 5,  /* Krylov tolerance not met within maxit */
+    ELWH_ERR_BREAKDOWN = 6       /* (p, A p)_M <= 0: A_h indefinite near resonance (Sec. 4.4 Remark) */
+} elwh_status;
+
+enum { ELWH_BC_DIRICHLET = 0, ELWH_BC_TRACTION_FREE = 1 };
+enum { ELWH_FP64 = 0, ELWH_FP32_STEP = 1 };
+enum { ELWH_KRYLOV_CG = 0, ELWH_KRYLOV_GMRES = 1, ELWH_KRYLOV_CR = 2 };
+enum { ELWH_SCHEME_CORRECTED = 0, ELWH_SCHEME_STANDARD = 1 };
+
+/* dim = 2 or 3; n[a] = cells along axis a (nodes n[a]+1, n[a] >= 2);
+ * len[a] = box length, h[a] = len[a]/n[a].  Unused entries are ignored. */
+typedef struct {
+    int dim;
+    int n[3];
+    double len[3];
+} elwh_grid;
+
+typedef struct {
+    double cfl;        /* time-step safety factor on 2/sqrt(G), G the Gershgorin
+                          bound of rho^-1 Ltilde (default 0.8) */
+    int nt;            /* steps per period; 0 = the rule N_T = max(3, ceil(T/dt*)) */
+    int periods;       /* K of the K-period filter, eq. many_periods_filter (default 1) */
+    int prec;          /* ELWH_FP64, or ELWH_FP32_STEP: FP32 state and stencil,
+                          FP64 accumulator, FP64 Krylov, FP64 iterative refinement */
+    int krylov;        /* ELWH_KRYLOV_CG (default), _GMRES, _CR */
+    int gmres_m;       /* GMRES restart length (default 30) */
+    int scheme;        /* ELWH_SCHEME_CORRECTED (default, Sec. 4.3) or _STANDARD */
+    int compensated;   /* FP32 path: Neumaier-compensated FP64 accumulator (default 1) */
+    double inner_tol;  /* FP32 path: relative tolerance of each inner FP32 solve (default 1e-4) */
+    int max_outer;     /* FP32 path: maximum refinement steps (default 50) */
+    void* stream;      /* hipStream_t the context works on; NULL = the null stream */
+} elwh_opts;
+
+typedef struct {
+    int iters;          /* Krylov iterations (summed over refinement steps) */
+    int outer;          /* refinement steps (FP32 path), else 0 */
+    int nt;             /* steps per period N_T */
+    int napply;         /* operator applications (each periods*N_T steps) */
+    double dt;          /* time step T / N_T */
+    double c;           /* correction factor (wt/omega)^2, 1 for the standard scheme */
+    double lambda_bound;/* Gershgorin bound G used by the time-step rule */
+    double relres;      /* last Krylov residual ||r||_M / ||b||_M (recurrence) */
+    double relres_fp64; /* final ||b - A_h v||_M / ||b||_M recomputed with an FP64 apply */
+    double cond_est;    /* Lanczos condition estimate from the CG coefficients (CG only) */
+} elwh_info;
+
+/* Fill *opts with the defaults listed above.  Never fails. */
+void elwh_default_opts(elwh_opts* opts);
+
+/*
+ * Time-step plan, host only (no GPU use): the Gershgorin bound G of
+ * rho^-1 Ltilde over all unknown rows, dt* = cfl*2/sqrt(G),
+ * N_T = max(3, ceil(T/dt*)) (or opts->nt), dt = T/N_T, and the correction
+ * factor c = (sin(omega dt/2)/(omega dt/2))^2 of Sec. 4.3.
+ * rho, lam, mu are HOST pointers (one component, node layout).
+ * Writes info->nt, dt, c, lambda_bound.  Errors: ELWH_ERR_ARG.
+ */
+elwh_status elwh_plan(const elwh_grid* grid, const double* rho, const double* lam,
+                      const double* mu, double omega, const int bc[6],
+                      const elwh_opts* opts, elwh_info* info);
+
+/*
+ * Create a context for one problem (Sec. 2.1 data: rho, lambda, mu > 0 and
+ * finite; omega > 0).  rho, lam, mu are DEVICE pointers, copied.  Computes
+ * the plan (elwh_plan), uploads the coefficient arrays in the library's
+ * padded internal layout and allocates all workspaces.  opts may be NULL.
+ * Synchronous.  Errors: ELWH_ERR_ARG, ELWH_ERR_ALLOC, ELWH_ERR_HIP; on error
+ * *out is NULL.
+ */
+elwh_status elwh_create(const elwh_grid* grid, const double* rho, const double* lam,
+                        const double* mu, double omega, const int bc[6],
+                        const elwh_opts* opts, elwh_ctx** out);
+
+/* Release every device and host resource of ctx (NULL is a no-op). */
+void elwh_destroy(elwh_ctx* ctx);
+
+/* Plan and sizes of a context (nt, dt, c, lambda_bound; other fields 0). */
+elwh_status elwh_query(const elwh_ctx* ctx, elwh_info* info);
+
+/* Text of the last error on ctx (or of the last failed create when ctx is
+ * NULL); valid until the next call on that context. */
+const char* elwh_last_error(const elwh_ctx* ctx);
+
+/*
+ * out = Pi_h u0  (Sec. 3 eq. el_WHI_OP, trapezoid rule): u0 is the initial
+ * displacement (zero initial velocity), f the forcing amplitude of
+ * -f cos(omega t) (eq. elastic-time), NULL for f = 0 (then out = S_h u0).
+ * The time stepping is the corrected leapfrog of Sec. 4.3 started with
+ * u^{-1} = u^1 (the even-in-time start); the accumulation
+ * sum_n w_n u^n is fused into each step.  In the FP32 path the stepping is
+ * FP32 and the accumulation FP64.  u0 and out may alias.
+ */
+elwh_status elwh_apply_filter(elwh_ctx* ctx, const double* u0, const double* f, double* out);
+
+/* y = A_h x = x - S_h x  (Sec. 4.5 eq. amat_non_sym).  x and y may alias. */
+elwh_status elwh_apply_A(elwh_ctx* ctx, const double* x, double* y);
+
+/*
+ * Solve A_h v = b, b = Pi_h 0 with forcing f (Sec. 4.5), by the Krylov
+ * method in opts (CG in the M inner product by default), from x0 (NULL =
+ * zero guess) until ||r||_M <= tol ||b||_M or maxit iterations.  tol <= 0
+ * runs exactly maxit iterations and returns ELWH_OK.  The final residual is
+ * recomputed with an FP64 apply (info->relres_fp64).  FP32 path: FP64
+ * iterative refinement around FP32-stepped inner solves, stopping on the
+ * FP64 residual.  Returns when done (synchronises the stream).
+ * Errors: ELWH_ERR_NOT_CONVERGED (v holds the last iterate),
+ * ELWH_ERR_BREAKDOWN, ELWH_ERR_ARG, ELWH_ERR_HIP.
+ */
+elwh_status elwh_solve(elwh_ctx* ctx, const double* f, const double* x0, double tol,
+                       int maxit, double* v, elwh_info* info);
+
+/*
+ * Stepwise CG in the M inner product (the loop of elwh_solve, exposed for
+ * timing and for resume-by-restart):
+ *   elwh_cg_begin    b = Pi_h 0 with f; r = b - A_h x0; p = r
+ *   elwh_cg_iterate  k iterations (one A_h apply each, FP64 reductions,
+ *                    fused vector updates); writes the current ||r||_M/||b||_M;
+ *                    stops early (returns ELWH_OK) once it is <= tol
+ *   elwh_cg_result   v = x; recomputes the FP64 residual into info
+ * FP64 path only.  elwh_cg_iterate synchronises the stream.
+ */
+elwh_status elwh_cg_begin(elwh_ctx* ctx, const double* f, const double* x0);
+elwh_status elwh_cg_iterate(elwh_ctx* ctx, int k, double tol, double* relres);
+elwh_status elwh_cg_result(elwh_ctx* ctx, double* v, elwh_info* info);
+
+/*
+ * (x, y)_M = sum over unknown dofs of w_i rho_i x_i y_i, the inner product
+ * of Sec. 4.5 (w = trapezoid weight, 1/2 per free face).  Deterministic
+ * FP64 two-pass reduction.  Writes the HOST double *out; synchronises.
+ */
+elwh_status elwh_dot_M(elwh_ctx* ctx, const double* x, const double* y, double* out);
+
+/*
+ * Kernel timing for measurement.  While enabled, every fused-step launch of
+ * the filter (Sec. 4.3 step + trapezoid accumulation; the half-step launch
+ * is counted separately) is bracketed by a pair of HIP events on the
+ * context's stream.  elwh_profile_read synchronises the stream and returns
+ * the summed kernel time in milliseconds and the launch counts since the
+ * last read or enable, then resets them.  Enabling also resets.
+ * Errors: ELWH_ERR_ARG (NULL ctx), ELWH_ERR_HIP.
+ */
+elwh_status elwh_profile_enable(elwh_ctx* ctx, int on);
+elwh_status elwh_profile_read(elwh_ctx* ctx, double* step_ms, int* nstep, double* init_ms, int* ninit);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ELWH_H */

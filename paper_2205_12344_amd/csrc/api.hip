@@ -1,0 +1,789 @@
+// C ABI of libelwh (declared in include/elwh.h): context set-up, the filter
+// and A_h applications, and the Krylov drivers.
+//
+// Krylov (Sec. 4.5): M A_h is symmetric, so CG runs on A_h in the M inner
+// product, A_h = I - S_h and b = Pi_h 0.  The CG scalars live on the device
+// (alpha and beta are formed by the reduction kernels), the host reads one
+// residual per iteration.  Conjugate residual (Remark of Sec. 4.5) and
+// restarted GMRES with classical Gram-Schmidt applied twice (used for
+// non-symmetric problems in Sec. 5.3) are host-driven over the same FP64
+// reductions.  The FP32 path wraps FP32-stepped inner CG solves in FP64
+// iterative refinement: r = b - A_h x with an FP64 apply, stop when
+// ||r||_M <= tol ||b||_M, else solve A_h d = r to inner_tol and x += d.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "elwh_internal.h"
+
+namespace elwh {
+void run_filter_2d(elwh_ctx* c, const double* x, bool with_force, bool amode, bool fp32, double* out);
+void run_filter_3d(elwh_ctx* c, const double* x, bool with_force, bool amode, bool fp32, double* out);
+
+void prof_begin(elwh_ctx* c) {
+    if (!c->prof_on) return;
+    const size_t need = 2 * (c->prof_used + 1);
+    while (c->prof_ev.size() < need) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) {
+            c->prof_on = false;
+            return;
+        }
+        c->prof_ev.push_back(e);
+    }
+    (void)hipEventRecord(c->prof_ev[2 * c->prof_used], c->stream);
+}
+
+void prof_end(elwh_ctx* c, int kind) {
+    if (!c->prof_on) return;
+    (void)hipEventRecord(c->prof_ev[2 * c->prof_used + 1], c->stream);
+    if (c->prof_kind.size() <= c->prof_used) c->prof_kind.resize(c->prof_used + 1);
+    c->prof_kind[c->prof_used] = kind;
+    c->prof_used++;
+}
+
+void run_filter(elwh_ctx* c, const double* x, bool with_force, bool amode, bool fp32, double* out) {
+    if (c->L.dim == 2)
+        run_filter_2d(c, x, with_force, amode, fp32, out);
+    else
+        run_filter_3d(c, x, with_force, amode, fp32, out);
+    c->napply++;
+}
+}  // namespace elwh
+
+using namespace elwh;
+
+namespace {
+
+thread_local std::string g_create_err;
+
+enum { VX = 0, VR, VP, VQ, VB, VT, VD, VRI };
+
+#define HIPCK(expr)                                                                   \
+    do {                                                                              \
+        hipError_t e_ = (expr);                                                       \
+        if (e_ != hipSuccess) {                                                       \
+            c->err = std::string(#expr) + ": " + hipGetErrorString(e_);               \
+            return ELWH_ERR_HIP;                                                      \
+        }                                                                             \
+    } while (0)
+
+#define CKST(expr)                    \
+    do {                              \
+        elwh_status s_ = (expr);      \
+        if (s_ != ELWH_OK) return s_; \
+    } while (0)
+
+elwh_status dev_alloc(elwh_ctx* c, void** p, size_t bytes) {
+    if (hipMalloc(p, bytes) != hipSuccess) {
+        *p = nullptr;
+        c->err = "device allocation failed (" + std::to_string(bytes) + " bytes)";
+        return ELWH_ERR_ALLOC;
+    }
+    if (hipMemsetAsync(*p, 0, bytes, c->stream) != hipSuccess) {
+        c->err = "hipMemsetAsync failed";
+        return ELWH_ERR_HIP;
+    }
+    return ELWH_OK;
+}
+
+template <typename T>
+elwh_status alloc_t(elwh_ctx* c, T** p, size_t n) {
+    return dev_alloc(c, reinterpret_cast<void**>(p), n * sizeof(T));
+}
+
+void free_all(elwh_ctx* c) {
+    auto f = [](void* p) {
+        if (p) (void)hipFree(p);
+    };
+    f(c->ca); f(c->cl); f(c->cm); f(c->mw);
+    f(c->fa); f(c->fl); f(c->fm);
+    f(c->s64[0]); f(c->s64[1]); f(c->s32[0]); f(c->s32[1]);
+    f(c->acc); f(c->acc_lo); f(c->f64); f(c->f32);
+    for (auto* v : c->vec) f(v);
+    for (auto* v : c->basis) f(v);
+    f(c->partials); f(c->dscal);
+    if (c->hscal) (void)hipHostFree(c->hscal);
+    for (auto e : c->prof_ev) (void)hipEventDestroy(e);
+    c->prof_ev.clear();
+}
+
+// (x, y)_M into the host (synchronising).
+elwh_status dot_host(elwh_ctx* c, const double* x, const double* y, double* out) {
+    launch_dot_M_partial(c, x, y, c->stream);
+    launch_reduce_final(c, RED_SUM, S_TMP, c->stream);
+    HIPCK(hipMemcpyAsync(c->hscal, c->dscal, S_NSLOT * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCK(hipStreamSynchronize(c->stream));
+    *out = c->hscal[S_TMP];
+    return ELWH_OK;
+}
+
+elwh_status read_scalars(elwh_ctx* c) {
+    HIPCK(hipMemcpyAsync(c->hscal, c->dscal, S_NSLOT * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCK(hipStreamSynchronize(c->stream));
+    return ELWH_OK;
+}
+
+elwh_status set_scalar(elwh_ctx* c, int slot, double v) {
+    HIPCK(hipStreamSynchronize(c->stream));
+    c->hscal[slot] = v;
+    HIPCK(hipMemcpyAsync(c->dscal + slot, c->hscal + slot, sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIPCK(hipStreamSynchronize(c->stream));
+    return ELWH_OK;
+}
+
+void apply_A(elwh_ctx* c, const double* x, double* y, bool fp32) { run_filter(c, x, false, true, fp32, y); }
+
+// b (VB) = Pi_h 0 with the packed forcing, FP64 stepping.
+void compute_rhs(elwh_ctx* c) {
+    double* zero = c->vec[VT];
+    (void)hipMemsetAsync(zero, 0, c->L.field_elems() * sizeof(double), c->stream);
+    run_filter(c, zero, true, false, false, c->vec[VB]);
+}
+
+// Device-scalar CG on A (FP64 or FP32 stepping) for rhs b, solution in x,
+// work vectors r, p, q.  x holds the initial guess (x_zero: it is zero).
+struct CGOut {
+    int iters = 0;
+    double relres = 0;
+    bool converged = false;
+};
+
+elwh_status cg_start(elwh_ctx* c, const double* b, double* x, bool x_zero, double* r, double* p, double* q,
+                     bool fp32, double* bb_out, double* rr_out) {
+    if (x_zero) {
+        launch_copy(c, b, r, c->stream);
+    } else {
+        apply_A(c, x, q, fp32);
+        launch_copy(c, b, r, c->stream);
+        launch_axpby(c, -1.0, q, 1.0, r, c->stream);
+    }
+    launch_copy(c, r, p, c->stream);
+    double bb, rr;
+    CKST(dot_host(c, b, b, &bb));
+    CKST(dot_host(c, r, r, &rr));
+    if (!std::isfinite(bb) || !std::isfinite(rr)) {
+        c->err = "non-finite right-hand side or residual";
+        return ELWH_ERR_ARG;
+    }
+    CKST(set_scalar(c, S_RR, rr));
+    CKST(set_scalar(c, S_FLAG, 0.0));
+    *bb_out = bb;
+    *rr_out = rr;
+    return ELWH_OK;
+}
+
+// k CG iterations; returns early when ||r||_M <= tol ||b||_M.
+elwh_status cg_steps(elwh_ctx* c, double* x, double* r, double* p, double* q, bool fp32, double bb, int k,
+                     double tol, CGOut* out, bool record) {
+    for (int it = 0; it < k; ++it) {
+        apply_A(c, p, q, fp32);
+        launch_dot_M_partial(c, p, q, c->stream);
+        launch_reduce_final(c, RED_PQ, 0, c->stream);
+        launch_cg_update_xr(c, x, r, p, q, c->stream);
+        launch_reduce_final(c, RED_RR, 0, c->stream);
+        CKST(read_scalars(c));
+        if (c->hscal[S_FLAG] != 0.0) {
+            c->err = "CG breakdown: (p, A_h p)_M <= 0 (A_h not positive definite near resonance)";
+            return ELWH_ERR_BREAKDOWN;
+        }
+        const double rr = c->hscal[S_RR];
+        if (!std::isfinite(rr)) {
+            c->err = "non-finite residual: the time step is unstable";
+            return ELWH_ERR_UNSTABLE;
+        }
+        out->iters++;
+        out->relres = std::sqrt(rr / bb);
+        if (record) {
+            c->alphas.push_back(c->hscal[S_ALPHA]);
+        }
+        if (tol > 0 && out->relres <= tol) {
+            out->converged = true;
+            return ELWH_OK;
+        }
+        if (record) c->betas.push_back(c->hscal[S_BETA]);
+        launch_cg_update_p(c, p, r, c->stream);
+    }
+    return ELWH_OK;
+}
+
+double lanczos_cond(const std::vector<double>& a, const std::vector<double>& b) {
+    const int k = (int)a.size();
+    if (k == 0) return NAN;
+    // symmetric tridiagonal T_k; extreme eigenvalues by bisection on Sturm counts
+    std::vector<double> d(k), e(k, 0.0);
+    for (int i = 0; i < k; ++i) {
+        d[i] = 1.0 / a[i] + (i > 0 ? b[i - 1] / a[i - 1] : 0.0);
+        if (i + 1 < k && i < (int)b.size()) e[i] = std::sqrt(b[i]) / a[i];
+    }
+    double lo = 1e300, hi = -1e300;
+    for (int i = 0; i < k; ++i) {
+        const double r = std::fabs(i > 0 ? e[i - 1] : 0.0) + std::fabs(e[i]);
+        lo = std::min(lo, d[i] - r);
+        hi = std::max(hi, d[i] + r);
+    }
+    auto count_below = [&](double x) {
+        int cnt = 0;
+        double q = 1.0;
+        for (int i = 0; i < k; ++i) {
+            const double off = i > 0 ? e[i - 1] : 0.0;
+            q = d[i] - x - (i > 0 ? off * off / q : 0.0);
+            if (q == 0.0) q = 1e-300;
+            if (q < 0) cnt++;
+        }
+        return cnt;
+    };
+    auto kth = [&](int idx) {
+        double a_ = lo, b_ = hi;
+        for (int it = 0; it < 200; ++it) {
+            const double m = 0.5 * (a_ + b_);
+            if (count_below(m) > idx) b_ = m; else a_ = m;
+        }
+        return 0.5 * (a_ + b_);
+    };
+    const double emin = kth(0), emax = kth(k - 1);
+    return emin > 0 ? emax / emin : NAN;
+}
+
+elwh_status final_residual(elwh_ctx* c, const double* x, double bb, double* out) {
+    apply_A(c, x, c->vec[VQ], false);
+    launch_copy(c, c->vec[VB], c->vec[VT], c->stream);
+    launch_axpby(c, -1.0, c->vec[VQ], 1.0, c->vec[VT], c->stream);
+    double rr;
+    CKST(dot_host(c, c->vec[VT], c->vec[VT], &rr));
+    *out = std::sqrt(rr / bb);
+    return ELWH_OK;
+}
+
+elwh_status solve_cr(elwh_ctx* c, bool x_zero, double tol, int maxit, int* iters, double* relres) {
+    double *x = c->vec[VX], *r = c->vec[VR], *p = c->vec[VP], *Ar = c->vec[VQ], *Ap = c->vec[VD];
+    const double* b = c->vec[VB];
+    if (x_zero) {
+        launch_copy(c, b, r, c->stream);
+    } else {
+        apply_A(c, x, Ar, false);
+        launch_copy(c, b, r, c->stream);
+        launch_axpby(c, -1.0, Ar, 1.0, r, c->stream);
+    }
+    double bb, rr, rAr, ApAp;
+    CKST(dot_host(c, b, b, &bb));
+    CKST(dot_host(c, r, r, &rr));
+    *relres = std::sqrt(rr / bb);
+    *iters = 0;
+    if (tol > 0 && *relres <= tol) return ELWH_OK;
+    launch_copy(c, r, p, c->stream);
+    apply_A(c, r, Ar, false);
+    launch_copy(c, Ar, Ap, c->stream);
+    CKST(dot_host(c, r, Ar, &rAr));
+    for (int k = 1; k <= maxit; ++k) {
+        CKST(dot_host(c, Ap, Ap, &ApAp));
+        if (!(ApAp > 0) || !std::isfinite(rAr)) {
+            c->err = std::isfinite(rAr) ? "CR breakdown" : "non-finite residual: the time step is unstable";
+            return std::isfinite(rAr) ? ELWH_ERR_BREAKDOWN : ELWH_ERR_UNSTABLE;
+        }
+        const double alpha = rAr / ApAp;
+        launch_axpby(c, alpha, p, 1.0, x, c->stream);
+        launch_axpby(c, -alpha, Ap, 1.0, r, c->stream);
+        CKST(dot_host(c, r, r, &rr));
+        *iters = k;
+        *relres = std::sqrt(rr / bb);
+        if (tol > 0 && *relres <= tol) return ELWH_OK;
+        apply_A(c, r, Ar, false);
+        double rAr_new;
+        CKST(dot_host(c, r, Ar, &rAr_new));
+        const double beta = rAr_new / rAr;
+        launch_axpby(c, 1.0, r, beta, p, c->stream);
+        launch_axpby(c, 1.0, Ar, beta, Ap, c->stream);
+        rAr = rAr_new;
+    }
+    return tol > 0 ? ELWH_ERR_NOT_CONVERGED : ELWH_OK;
+}
+
+elwh_status solve_gmres(elwh_ctx* c, bool x_zero, double tol, int maxit, int* iters, double* relres) {
+    const int m = c->opts.gmres_m;
+    while ((int)c->basis.size() < m + 1) {
+        double* v = nullptr;
+        CKST(alloc_t(c, &v, (size_t)c->L.field_elems()));
+        c->basis.push_back(v);
+    }
+    double* x = c->vec[VX];
+    double* w = c->vec[VQ];
+    const double* b = c->vec[VB];
+    double bb;
+    CKST(dot_host(c, b, b, &bb));
+    const double bn = std::sqrt(bb);
+    int total = 0;
+    bool first = true;
+    std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+    while (true) {
+        double* r = c->basis[0];
+        if (first && x_zero) {
+            launch_copy(c, b, r, c->stream);
+        } else {
+            apply_A(c, x, w, false);
+            launch_copy(c, b, r, c->stream);
+            launch_axpby(c, -1.0, w, 1.0, r, c->stream);
+        }
+        first = false;
+        double rr;
+        CKST(dot_host(c, r, r, &rr));
+        const double beta = std::sqrt(rr);
+        if (!std::isfinite(beta)) {
+            c->err = "non-finite residual: the time step is unstable";
+            return ELWH_ERR_UNSTABLE;
+        }
+        *relres = beta / bn;
+        *iters = total;
+        if ((tol > 0 && *relres <= tol) || total >= maxit) break;
+        launch_axpby(c, 0.0, r, 1.0 / beta, r, c->stream);
+        std::fill(H.begin(), H.end(), 0.0);
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int jdone = 0;
+        for (int j = 0; j < m; ++j) {
+            apply_A(c, c->basis[j], w, false);
+            total++;
+            for (int pass = 0; pass < 2; ++pass) {  // classical Gram-Schmidt, twice
+                std::vector<double> h(j + 1);
+                for (int i = 0; i <= j; ++i) CKST(dot_host(c, c->basis[i], w, &h[i]));
+                for (int i = 0; i <= j; ++i) {
+                    launch_axpby(c, -h[i], c->basis[i], 1.0, w, c->stream);
+                    H[i * m + j] += h[i];
+                }
+            }
+            double ww;
+            CKST(dot_host(c, w, w, &ww));
+            const double hn = std::sqrt(ww);
+            H[(j + 1) * m + j] = hn;
+            for (int i = 0; i < j; ++i) {
+                const double t = cs[i] * H[i * m + j] + sn[i] * H[(i + 1) * m + j];
+                H[(i + 1) * m + j] = -sn[i] * H[i * m + j] + cs[i] * H[(i + 1) * m + j];
+                H[i * m + j] = t;
+            }
+            const double rho = std::hypot(H[j * m + j], H[(j + 1) * m + j]);
+            cs[j] = H[j * m + j] / rho;
+            sn[j] = H[(j + 1) * m + j] / rho;
+            H[j * m + j] = rho;
+            H[(j + 1) * m + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            jdone = j + 1;
+            *relres = std::fabs(g[j + 1]) / bn;
+            if ((tol > 0 && *relres <= tol) || total >= maxit || hn == 0.0) break;
+            launch_copy(c, w, c->basis[j + 1], c->stream);
+            launch_axpby(c, 0.0, w, 1.0 / hn, c->basis[j + 1], c->stream);
+        }
+        for (int i = jdone - 1; i >= 0; --i) {
+            double s = g[i];
+            for (int k = i + 1; k < jdone; ++k) s -= H[i * m + k] * y[k];
+            y[i] = s / H[i * m + i];
+        }
+        for (int i = 0; i < jdone; ++i) launch_axpby(c, y[i], c->basis[i], 1.0, x, c->stream);
+    }
+    *iters = total;
+    return (tol > 0 && *relres > tol) ? ELWH_ERR_NOT_CONVERGED : ELWH_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+
+extern "C" {
+
+void elwh_default_opts(elwh_opts* o) {
+    if (!o) return;
+    o->cfl = 0.8;
+    o->nt = 0;
+    o->periods = 1;
+    o->prec = ELWH_FP64;
+    o->krylov = ELWH_KRYLOV_CG;
+    o->gmres_m = 30;
+    o->scheme = ELWH_SCHEME_CORRECTED;
+    o->compensated = 1;
+    o->inner_tol = 1e-4;
+    o->max_outer = 50;
+    o->stream = nullptr;
+}
+
+elwh_status elwh_plan(const elwh_grid* grid, const double* rho, const double* lam, const double* mu, double omega,
+                      const int bc[6], const elwh_opts* opts, elwh_info* info) {
+    elwh_opts o;
+    elwh_default_opts(&o);
+    if (opts) o = *opts;
+    Plan p;
+    elwh_status st = make_plan(grid, rho, lam, mu, omega, bc, &o, &p, &g_create_err);
+    if (st != ELWH_OK) return st;
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->nt = p.nt;
+        info->dt = p.dt;
+        info->c = p.c;
+        info->lambda_bound = p.lambda_bound;
+    }
+    return ELWH_OK;
+}
+
+elwh_status elwh_create(const elwh_grid* grid, const double* rho, const double* lam, const double* mu,
+                        double omega, const int bc[6], const elwh_opts* opts, elwh_ctx** out) {
+    if (!out) return ELWH_ERR_ARG;
+    *out = nullptr;
+    elwh_opts o;
+    elwh_default_opts(&o);
+    if (opts) o = *opts;
+    g_create_err.clear();
+    elwh_status st = check_config(grid, bc, &o, &g_create_err);
+    if (st != ELWH_OK) return st;
+    if (!rho || !lam || !mu) {
+        g_create_err = "null material array";
+        return ELWH_ERR_ARG;
+    }
+    elwh_ctx* c = new (std::nothrow) elwh_ctx();
+    if (!c) return ELWH_ERR_ALLOC;
+    c->grid = *grid;
+    for (int f = 0; f < 6; ++f) c->bc[f] = f < 2 * grid->dim ? bc[f] : ELWH_BC_DIRICHLET;
+    c->omega = omega;
+    c->opts = o;
+    c->stream = reinterpret_cast<hipStream_t>(o.stream);
+    c->L = make_layout(grid);
+    c->st = make_stencil(grid);
+    c->mr = make_march(grid, c->bc);
+
+    auto fail = [&](elwh_status s) {
+        g_create_err = c->err.empty() ? g_create_err : c->err;
+        free_all(c);
+        delete c;
+        return s;
+    };
+    const int64_t nn = c->L.nodes_caller();
+    std::vector<double> hr(nn), hl(nn), hm(nn);
+    if (hipMemcpyAsync(hr.data(), rho, nn * sizeof(double), hipMemcpyDefault, c->stream) != hipSuccess ||
+        hipMemcpyAsync(hl.data(), lam, nn * sizeof(double), hipMemcpyDefault, c->stream) != hipSuccess ||
+        hipMemcpyAsync(hm.data(), mu, nn * sizeof(double), hipMemcpyDefault, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+        c->err = "copying the materials failed (device pointers expected)";
+        return fail(ELWH_ERR_HIP);
+    }
+    st = make_plan(grid, hr.data(), hl.data(), hm.data(), omega, c->bc, &o, &c->plan, &c->err);
+    if (st != ELWH_OK) return fail(st);
+
+    // weights of the (K-period) trapezoid filter and the forcing factors
+    const int ntot = c->plan.nt * o.periods;
+    c->w.resize(ntot + 1);
+    c->cosn.resize(ntot + 1);
+    for (int n = 0; n <= ntot; ++n) {
+        const double cn = std::cos(2.0 * M_PI * n / c->plan.nt);
+        const double eta = (n == 0 || n == ntot) ? 0.5 : 1.0;
+        c->cosn[n] = cn;
+        c->w[n] = (2.0 / ntot) * eta * (cn - 0.25);
+    }
+
+    const Layout& L = c->L;
+    const size_t CS = (size_t)L.CS, FE = (size_t)L.field_elems();
+    if ((st = alloc_t(c, &c->ca, CS)) || (st = alloc_t(c, &c->cl, CS)) || (st = alloc_t(c, &c->cm, CS)) ||
+        (st = alloc_t(c, &c->mw, CS)) || (st = alloc_t(c, &c->s64[0], FE)) || (st = alloc_t(c, &c->s64[1], FE)) ||
+        (st = alloc_t(c, &c->acc_lo, FE)) || (st = alloc_t(c, &c->f64, FE)))
+        return fail(st);
+    for (auto& v : c->vec)
+        if ((st = alloc_t(c, &v, FE))) return fail(st);
+    if (o.prec == ELWH_FP32_STEP) {
+        if ((st = alloc_t(c, &c->fa, CS)) || (st = alloc_t(c, &c->fl, CS)) || (st = alloc_t(c, &c->fm, CS)) ||
+            (st = alloc_t(c, &c->s32[0], FE)) || (st = alloc_t(c, &c->s32[1], FE)) ||
+            (st = alloc_t(c, &c->f32, FE)))
+            return fail(st);
+    }
+    if ((st = alloc_t(c, &c->partials, (size_t)c->red_blocks)) || (st = alloc_t(c, &c->dscal, (size_t)S_NSLOT)))
+        return fail(st);
+    if (hipHostMalloc(reinterpret_cast<void**>(&c->hscal), S_NSLOT * sizeof(double), hipHostMallocDefault) !=
+        hipSuccess) {
+        c->err = "pinned host allocation failed";
+        return fail(ELWH_ERR_ALLOC);
+    }
+    std::memset(c->hscal, 0, S_NSLOT * sizeof(double));
+
+    // coefficient arrays in the padded layout, built on the host in FP64
+    {
+        std::vector<double> ha(CS, 0.0), hlam(CS, 0.0), hmu(CS, 0.0), hmw(CS, 0.0);
+        const double cdt2 = c->plan.c * c->plan.dt * c->plan.dt;
+        const int nzn = L.dim == 3 ? L.nz + 1 : 1;
+        for (int z = 0; z < nzn; ++z)
+            for (int y = 0; y <= L.ny; ++y)
+                for (int x = 0; x <= L.nx; ++x) {
+                    const int64_t src = ((int64_t)z * (L.ny + 1) + y) * (L.nx + 1) + x;
+                    const int64_t dst = (int64_t)z * L.PS + (int64_t)y * L.P + x;
+                    ha[dst] = cdt2 / hr[src];
+                    hlam[dst] = hl[src];
+                    hmu[dst] = hm[src];
+                    bool unknown = true;
+                    double wn = 1.0;
+                    const int coord[3] = {x, y, z};
+                    const int nmax[3] = {L.nx, L.ny, L.nz};
+                    for (int a = 0; a < L.dim; ++a) {
+                        if (coord[a] == 0) {
+                            if (c->bc[2 * a] == ELWH_BC_DIRICHLET) unknown = false; else wn *= 0.5;
+                        }
+                        if (coord[a] == nmax[a]) {
+                            if (c->bc[2 * a + 1] == ELWH_BC_DIRICHLET) unknown = false; else wn *= 0.5;
+                        }
+                    }
+                    hmw[dst] = unknown ? wn * hr[src] : 0.0;
+                }
+        if (hipMemcpyAsync(c->ca, ha.data(), CS * 8, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+            hipMemcpyAsync(c->cl, hlam.data(), CS * 8, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+            hipMemcpyAsync(c->cm, hmu.data(), CS * 8, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+            hipMemcpyAsync(c->mw, hmw.data(), CS * 8, hipMemcpyHostToDevice, c->stream) != hipSuccess) {
+            c->err = "uploading coefficients failed";
+            return fail(ELWH_ERR_HIP);
+        }
+        if (o.prec == ELWH_FP32_STEP) {
+            launch_convert_f32(L, c->ca, c->fa, 1, c->stream);
+            launch_convert_f32(L, c->cl, c->fl, 1, c->stream);
+            launch_convert_f32(L, c->cm, c->fm, 1, c->stream);
+        }
+        if (hipStreamSynchronize(c->stream) != hipSuccess) {
+            c->err = "stream synchronisation failed in create";
+            return fail(ELWH_ERR_HIP);
+        }
+    }
+    *out = c;
+    return ELWH_OK;
+}
+
+void elwh_destroy(elwh_ctx* c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    free_all(c);
+    delete c;
+}
+
+elwh_status elwh_query(const elwh_ctx* c, elwh_info* info) {
+    if (!c || !info) return ELWH_ERR_ARG;
+    std::memset(info, 0, sizeof(*info));
+    info->nt = c->plan.nt;
+    info->dt = c->plan.dt;
+    info->c = c->plan.c;
+    info->lambda_bound = c->plan.lambda_bound;
+    info->napply = c->napply;
+    return ELWH_OK;
+}
+
+const char* elwh_last_error(const elwh_ctx* c) { return c ? c->err.c_str() : g_create_err.c_str(); }
+
+elwh_status elwh_apply_filter(elwh_ctx* c, const double* u0, const double* f, double* out) {
+    if (!c || !u0 || !out) return ELWH_ERR_ARG;
+    const bool fp32 = c->opts.prec == ELWH_FP32_STEP;
+    launch_pack(c->L, c->bc, u0, c->vec[VX], c->L.dim, c->stream);
+    if (f) {
+        launch_pack(c->L, c->bc, f, c->f64, c->L.dim, c->stream);
+        if (fp32) launch_convert_f32(c->L, c->f64, c->f32, c->L.dim, c->stream);
+    }
+    run_filter(c, c->vec[VX], f != nullptr, false, fp32, c->vec[VQ]);
+    launch_unpack(c->L, c->bc, c->vec[VQ], out, c->L.dim, c->stream);
+    HIPCK(hipGetLastError());
+    return ELWH_OK;
+}
+
+elwh_status elwh_apply_A(elwh_ctx* c, const double* x, double* y) {
+    if (!c || !x || !y) return ELWH_ERR_ARG;
+    const bool fp32 = c->opts.prec == ELWH_FP32_STEP;
+    launch_pack(c->L, c->bc, x, c->vec[VX], c->L.dim, c->stream);
+    apply_A(c, c->vec[VX], c->vec[VQ], fp32);
+    launch_unpack(c->L, c->bc, c->vec[VQ], y, c->L.dim, c->stream);
+    HIPCK(hipGetLastError());
+    return ELWH_OK;
+}
+
+elwh_status elwh_dot_M(elwh_ctx* c, const double* x, const double* y, double* out) {
+    if (!c || !x || !y || !out) return ELWH_ERR_ARG;
+    launch_pack(c->L, c->bc, x, c->vec[VT], c->L.dim, c->stream);
+    launch_pack(c->L, c->bc, y, c->vec[VD], c->L.dim, c->stream);
+    return dot_host(c, c->vec[VT], c->vec[VD], out);
+}
+
+elwh_status elwh_cg_begin(elwh_ctx* c, const double* f, const double* x0) {
+    if (!c || !f) return ELWH_ERR_ARG;
+    if (c->opts.prec != ELWH_FP64) {
+        c->err = "the stepwise CG interface is FP64 only";
+        return ELWH_ERR_ARG;
+    }
+    launch_pack(c->L, c->bc, f, c->f64, c->L.dim, c->stream);
+    compute_rhs(c);
+    if (x0)
+        launch_pack(c->L, c->bc, x0, c->vec[VX], c->L.dim, c->stream);
+    else
+        HIPCK(hipMemsetAsync(c->vec[VX], 0, c->L.field_elems() * sizeof(double), c->stream));
+    double rr;
+    c->alphas.clear();
+    c->betas.clear();
+    CKST(cg_start(c, c->vec[VB], c->vec[VX], x0 == nullptr, c->vec[VR], c->vec[VP], c->vec[VQ], false, &c->cg_bb,
+                  &rr));
+    c->cg_iters = 0;
+    c->cg_active = true;
+    return ELWH_OK;
+}
+
+elwh_status elwh_cg_iterate(elwh_ctx* c, int k, double tol, double* relres) {
+    if (!c || !c->cg_active || k < 0) return ELWH_ERR_ARG;
+    CGOut o;
+    elwh_status st = cg_steps(c, c->vec[VX], c->vec[VR], c->vec[VP], c->vec[VQ], false, c->cg_bb, k, tol, &o, true);
+    c->cg_iters += o.iters;
+    if (relres) *relres = o.relres;
+    return st;
+}
+
+elwh_status elwh_cg_result(elwh_ctx* c, double* v, elwh_info* info) {
+    if (!c || !c->cg_active) return ELWH_ERR_ARG;
+    if (v) launch_unpack(c->L, c->bc, c->vec[VX], v, c->L.dim, c->stream);
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->iters = c->cg_iters;
+        info->nt = c->plan.nt;
+        info->dt = c->plan.dt;
+        info->c = c->plan.c;
+        info->lambda_bound = c->plan.lambda_bound;
+        double rr;
+        CKST(dot_host(c, c->vec[VR], c->vec[VR], &rr));
+        info->relres = std::sqrt(rr / c->cg_bb);
+        CKST(final_residual(c, c->vec[VX], c->cg_bb, &info->relres_fp64));
+        info->cond_est = lanczos_cond(c->alphas, c->betas);
+        info->napply = c->napply;
+    }
+    HIPCK(hipStreamSynchronize(c->stream));
+    return ELWH_OK;
+}
+
+elwh_status elwh_solve(elwh_ctx* c, const double* f, const double* x0, double tol, int maxit, double* v,
+                       elwh_info* info) {
+    if (!c || !f || !v || maxit < 0) return ELWH_ERR_ARG;
+    c->napply = 0;
+    elwh_info inf;
+    std::memset(&inf, 0, sizeof(inf));
+    inf.nt = c->plan.nt;
+    inf.dt = c->plan.dt;
+    inf.c = c->plan.c;
+    inf.lambda_bound = c->plan.lambda_bound;
+    elwh_status st = ELWH_OK;
+
+    if (c->opts.prec == ELWH_FP64 && c->opts.krylov == ELWH_KRYLOV_CG) {
+        CKST(elwh_cg_begin(c, f, x0));
+        double rel = 0;
+        st = elwh_cg_iterate(c, maxit, tol, &rel);
+        if (st != ELWH_OK && st != ELWH_ERR_NOT_CONVERGED) return st;
+        elwh_status st2 = elwh_cg_result(c, v, &inf);
+        if (st2 != ELWH_OK) return st2;
+        if (tol > 0 && !(inf.relres <= tol)) st = ELWH_ERR_NOT_CONVERGED;
+    } else if (c->opts.prec == ELWH_FP64) {
+        launch_pack(c->L, c->bc, f, c->f64, c->L.dim, c->stream);
+        compute_rhs(c);
+        if (x0)
+            launch_pack(c->L, c->bc, x0, c->vec[VX], c->L.dim, c->stream);
+        else
+            HIPCK(hipMemsetAsync(c->vec[VX], 0, c->L.field_elems() * sizeof(double), c->stream));
+        int it = 0;
+        double rel = 0;
+        st = c->opts.krylov == ELWH_KRYLOV_CR ? solve_cr(c, x0 == nullptr, tol, maxit, &it, &rel)
+                                              : solve_gmres(c, x0 == nullptr, tol, maxit, &it, &rel);
+        if (st != ELWH_OK && st != ELWH_ERR_NOT_CONVERGED) return st;
+        inf.iters = it;
+        inf.relres = rel;
+        double bb;
+        CKST(dot_host(c, c->vec[VB], c->vec[VB], &bb));
+        CKST(final_residual(c, c->vec[VX], bb, &inf.relres_fp64));
+        launch_unpack(c->L, c->bc, c->vec[VX], v, c->L.dim, c->stream);
+    } else {
+        // FP32 stepping inside FP64 iterative refinement (CG inner solver)
+        launch_pack(c->L, c->bc, f, c->f64, c->L.dim, c->stream);
+        compute_rhs(c);
+        if (x0)
+            launch_pack(c->L, c->bc, x0, c->vec[VX], c->L.dim, c->stream);
+        else
+            HIPCK(hipMemsetAsync(c->vec[VX], 0, c->L.field_elems() * sizeof(double), c->stream));
+        double bb;
+        CKST(dot_host(c, c->vec[VB], c->vec[VB], &bb));
+        if (!std::isfinite(bb) || !(bb > 0)) {
+            c->err = "zero or non-finite right-hand side";
+            return ELWH_ERR_ARG;
+        }
+        bool xzero = x0 == nullptr;
+        double relfp64 = 1.0;
+        int outer = 0, iters = 0;
+        st = ELWH_ERR_NOT_CONVERGED;
+        for (; outer <= c->opts.max_outer; ++outer) {
+            // r = b - A64 x  (into VRI)
+            if (xzero) {
+                launch_copy(c, c->vec[VB], c->vec[VRI], c->stream);
+            } else {
+                apply_A(c, c->vec[VX], c->vec[VT], false);
+                launch_copy(c, c->vec[VB], c->vec[VRI], c->stream);
+                launch_axpby(c, -1.0, c->vec[VT], 1.0, c->vec[VRI], c->stream);
+            }
+            double rr;
+            CKST(dot_host(c, c->vec[VRI], c->vec[VRI], &rr));
+            if (!std::isfinite(rr)) {
+                c->err = "non-finite residual: the time step is unstable";
+                return ELWH_ERR_UNSTABLE;
+            }
+            relfp64 = std::sqrt(rr / bb);
+            if ((tol > 0 && relfp64 <= tol) || iters >= maxit || outer == c->opts.max_outer) {
+                if (tol > 0 && relfp64 <= tol) st = ELWH_OK;
+                if (tol <= 0) st = ELWH_OK;
+                break;
+            }
+            // inner FP32 CG: A d = r, d in VD, zero start
+            HIPCK(hipMemsetAsync(c->vec[VD], 0, c->L.field_elems() * sizeof(double), c->stream));
+            double bbi, rri;
+            CKST(cg_start(c, c->vec[VRI], c->vec[VD], true, c->vec[VR], c->vec[VP], c->vec[VQ], true, &bbi, &rri));
+            CGOut o;
+            elwh_status si = cg_steps(c, c->vec[VD], c->vec[VR], c->vec[VP], c->vec[VQ], true, bbi,
+                                      maxit - iters, c->opts.inner_tol, &o, false);
+            if (si != ELWH_OK) return si;
+            iters += o.iters;
+            inf.relres = o.relres * relfp64;
+            launch_axpby(c, 1.0, c->vec[VD], 1.0, c->vec[VX], c->stream);
+            xzero = false;
+        }
+        inf.iters = iters;
+        inf.outer = outer;
+        inf.relres_fp64 = relfp64;
+        launch_unpack(c->L, c->bc, c->vec[VX], v, c->L.dim, c->stream);
+    }
+    HIPCK(hipStreamSynchronize(c->stream));
+    inf.napply = c->napply;
+    if (info) *info = inf;
+    return st;
+}
+
+elwh_status elwh_profile_enable(elwh_ctx* c, int on) {
+    if (!c) return ELWH_ERR_ARG;
+    HIPCK(hipStreamSynchronize(c->stream));
+    c->prof_on = on != 0;
+    c->prof_used = 0;
+    return ELWH_OK;
+}
+
+elwh_status elwh_profile_read(elwh_ctx* c, double* step_ms, int* nstep, double* init_ms, int* ninit) {
+    if (!c) return ELWH_ERR_ARG;
+    HIPCK(hipStreamSynchronize(c->stream));
+    double ts = 0, ti = 0;
+    int ns = 0, ni = 0;
+    for (size_t k = 0; k < c->prof_used; ++k) {
+        float ms = 0.f;
+        HIPCK(hipEventElapsedTime(&ms, c->prof_ev[2 * k], c->prof_ev[2 * k + 1]));
+        if (c->prof_kind[k] == 0) {
+            ts += ms;
+            ns++;
+        } else {
+            ti += ms;
+            ni++;
+        }
+    }
+    c->prof_used = 0;
+    if (step_ms) *step_ms = ts;
+    if (nstep) *nstep = ns;
+    if (init_ms) *init_ms = ti;
+    if (ninit) *ninit = ni;
+    return ELWH_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,255 @@
+// Layout conversion, FP64 Krylov reductions and vector updates for libelwh.
+//
+// Inner products are (x, y)_M = sum_i m_i x_i y_i over the unknown dofs,
+// m = trapezoid weight * rho (the M of Sec. 4.1 / 4.5).  They are reduced
+// deterministically in two passes: every block of a fixed-size grid sums a
+// grid-strided slice (wavefront shuffles, then LDS across the block's
+// wavefronts) into one partial; a single block then adds the partials in a
+// fixed tree order.  Reruns on the same data are bit-identical.
+#include "elwh_internal.h"
+
+namespace elwh {
+
+namespace {
+
+constexpr int RB = 256;  // threads per reduction block
+
+struct PackArgs {
+    int dim, nx, ny, nz;
+    int64_t P, PS, CS;
+    int mask;            // zero Dirichlet nodes
+    int bc[6];
+};
+
+__device__ __forceinline__ bool node_unknown(const PackArgs& a, int x, int y, int z) {
+    if (x == 0 && a.bc[0] == ELWH_BC_DIRICHLET) return false;
+    if (x == a.nx && a.bc[1] == ELWH_BC_DIRICHLET) return false;
+    if (y == 0 && a.bc[2] == ELWH_BC_DIRICHLET) return false;
+    if (y == a.ny && a.bc[3] == ELWH_BC_DIRICHLET) return false;
+    if (a.dim == 3) {
+        if (z == 0 && a.bc[4] == ELWH_BC_DIRICHLET) return false;
+        if (z == a.nz && a.bc[5] == ELWH_BC_DIRICHLET) return false;
+    }
+    return true;
+}
+
+template <typename D>
+__global__ void pack_kernel(const double* __restrict__ src, D* __restrict__ dst, int ncomp, PackArgs a) {
+    const int64_t total = a.CS * ncomp;
+    const int64_t nxn = a.nx + 1, nyn = a.ny + 1;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = e / a.CS;
+        const int64_t r = e - c * a.CS;
+        const int z = (int)(r / a.PS);
+        const int64_t r2 = r - (int64_t)z * a.PS;
+        const int y = (int)(r2 / a.P);
+        const int x = (int)(r2 - (int64_t)y * a.P);
+        double v = 0.0;
+        if (x <= a.nx && (!a.mask || node_unknown(a, x, y, z)))
+            v = src[((c * (a.dim == 3 ? a.nz + 1 : 1) + z) * nyn + y) * nxn + x];
+        dst[e] = (D)v;
+    }
+}
+
+__global__ void unpack_kernel(const double* __restrict__ src, double* __restrict__ dst, int ncomp, PackArgs a) {
+    const int64_t nxn = a.nx + 1, nyn = a.ny + 1, nzn = a.dim == 3 ? a.nz + 1 : 1;
+    const int64_t total = nxn * nyn * nzn * ncomp;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        int64_t r = e;
+        const int x = (int)(r % nxn);
+        r /= nxn;
+        const int y = (int)(r % nyn);
+        r /= nyn;
+        const int z = (int)(r % nzn);
+        const int64_t c = r / nzn;
+        double v = 0.0;
+        if (node_unknown(a, x, y, z)) v = src[c * a.CS + (int64_t)z * a.PS + (int64_t)y * a.P + x];
+        dst[e] = v;
+    }
+}
+
+__global__ void convert_kernel(const double* __restrict__ src, float* __restrict__ dst, int64_t n) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        dst[e] = (float)src[e];
+}
+
+PackArgs pack_args(const Layout& L, const int bc[6], int mask) {
+    PackArgs a;
+    a.dim = L.dim;
+    a.nx = L.nx;
+    a.ny = L.ny;
+    a.nz = L.nz;
+    a.P = L.P;
+    a.PS = L.PS;
+    a.CS = L.CS;
+    a.mask = mask;
+    for (int f = 0; f < 6; ++f) a.bc[f] = f < 2 * L.dim ? bc[f] : ELWH_BC_DIRICHLET;
+    return a;
+}
+
+unsigned grid_for(int64_t n, int bs = 256) {
+    int64_t g = (n + bs - 1) / bs;
+    return (unsigned)std::min<int64_t>(std::max<int64_t>(g, 1), 65536);
+}
+
+// ---- reductions -------------------------------------------------------------
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ double block_sum(double v) {
+    __shared__ double red[RB / 64];
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < RB / 64; ++k) s += red[k];
+    }
+    return s;  // valid in thread 0
+}
+
+__global__ __launch_bounds__(RB) void dotm_partial_kernel(const double* __restrict__ x, const double* __restrict__ y,
+                                                          const double* __restrict__ m, int ncomp, int64_t CS,
+                                                          double* __restrict__ partials) {
+    double s = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * RB + threadIdx.x; e < CS; e += (int64_t)gridDim.x * RB) {
+        const double me = m[e];
+        double t = 0.0;
+        for (int c = 0; c < ncomp; ++c) t += x[e + c * CS] * y[e + c * CS];
+        s += me * t;
+    }
+    s = block_sum(s);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(1024) void reduce_final_kernel(const double* __restrict__ partials, int n,
+                                                             double* __restrict__ sc, int mode, int slot) {
+    __shared__ double buf[1024];
+    double v = 0.0;
+    for (int k = threadIdx.x; k < n; k += 1024) v += partials[k];
+    buf[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) buf[threadIdx.x] += buf[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double s = buf[0];
+        if (mode == RED_SUM) {
+            sc[slot] = s;
+        } else if (mode == RED_PQ) {
+            sc[S_PQ] = s;
+            if (s > 0.0) {
+                sc[S_ALPHA] = sc[S_RR] / s;
+            } else {
+                sc[S_ALPHA] = 0.0;
+                sc[S_FLAG] = 1.0;  // breakdown: (p, A p)_M <= 0
+            }
+        } else {  // RED_RR
+            sc[S_RRNEW] = s;
+            sc[S_BETA] = s / sc[S_RR];
+            sc[S_RR] = s;
+        }
+    }
+}
+
+__global__ __launch_bounds__(RB) void cg_xr_kernel(double* __restrict__ x, double* __restrict__ r,
+                                                   const double* __restrict__ p, const double* __restrict__ q,
+                                                   const double* __restrict__ m, int ncomp, int64_t CS,
+                                                   const double* __restrict__ sc, double* __restrict__ partials) {
+    const double alpha = sc[S_ALPHA];
+    double s = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * RB + threadIdx.x; e < CS; e += (int64_t)gridDim.x * RB) {
+        double t = 0.0;
+        for (int c = 0; c < ncomp; ++c) {
+            const int64_t o = e + c * CS;
+            x[o] += alpha * p[o];
+            const double rn = r[o] - alpha * q[o];
+            r[o] = rn;
+            t += rn * rn;
+        }
+        s += m[e] * t;
+    }
+    s = block_sum(s);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ void cg_p_kernel(double* __restrict__ p, const double* __restrict__ r, int64_t n,
+                            const double* __restrict__ sc) {
+    const double beta = sc[S_BETA];
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        p[e] = r[e] + beta * p[e];
+}
+
+__global__ void axpby_kernel(double a, const double* __restrict__ x, double b, double* __restrict__ y, int64_t n) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        y[e] = a * x[e] + b * y[e];
+}
+
+__global__ void copy_kernel(const double* __restrict__ x, double* __restrict__ y, int64_t n) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        y[e] = x[e];
+}
+
+}  // namespace
+
+void launch_pack(const Layout& L, const int bc[6], const double* src, double* dst, int ncomp, hipStream_t s) {
+    PackArgs a = pack_args(L, bc, ncomp > 1 ? 1 : 0);
+    hipLaunchKernelGGL(pack_kernel<double>, dim3(grid_for(L.CS * ncomp)), dim3(256), 0, s, src, dst, ncomp, a);
+}
+
+void launch_pack_f32(const Layout& L, const int bc[6], const double* src, float* dst, int ncomp, hipStream_t s) {
+    PackArgs a = pack_args(L, bc, ncomp > 1 ? 1 : 0);
+    hipLaunchKernelGGL(pack_kernel<float>, dim3(grid_for(L.CS * ncomp)), dim3(256), 0, s, src, dst, ncomp, a);
+}
+
+void launch_unpack(const Layout& L, const int bc[6], const double* src, double* dst, int ncomp, hipStream_t s) {
+    PackArgs a = pack_args(L, bc, 1);
+    hipLaunchKernelGGL(unpack_kernel, dim3(grid_for(L.nodes_caller() * ncomp)), dim3(256), 0, s, src, dst, ncomp, a);
+}
+
+void launch_convert_f32(const Layout& L, const double* src, float* dst, int ncomp, hipStream_t s) {
+    const int64_t n = L.CS * ncomp;
+    hipLaunchKernelGGL(convert_kernel, dim3(grid_for(n)), dim3(256), 0, s, src, dst, n);
+}
+
+void launch_dot_M_partial(const elwh_ctx* c, const double* x, const double* y, hipStream_t s) {
+    hipLaunchKernelGGL(dotm_partial_kernel, dim3(c->red_blocks), dim3(RB), 0, s, x, y, c->mw, c->L.dim, c->L.CS,
+                       c->partials);
+}
+
+void launch_reduce_final(const elwh_ctx* c, int mode, int slot, hipStream_t s) {
+    hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(1024), 0, s, c->partials, c->red_blocks, c->dscal, mode,
+                       slot);
+}
+
+void launch_cg_update_xr(const elwh_ctx* c, double* x, double* r, const double* p, const double* q,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(cg_xr_kernel, dim3(c->red_blocks), dim3(RB), 0, s, x, r, p, q, c->mw, c->L.dim, c->L.CS,
+                       c->dscal, c->partials);
+}
+
+void launch_cg_update_p(const elwh_ctx* c, double* p, const double* r, hipStream_t s) {
+    const int64_t n = c->L.field_elems();
+    hipLaunchKernelGGL(cg_p_kernel, dim3(grid_for(n)), dim3(256), 0, s, p, r, n, c->dscal);
+}
+
+void launch_axpby(const elwh_ctx* c, double a, const double* x, double b, double* y, hipStream_t s) {
+    const int64_t n = c->L.field_elems();
+    hipLaunchKernelGGL(axpby_kernel, dim3(grid_for(n)), dim3(256), 0, s, a, x, b, y, n);
+}
+
+void launch_copy(const elwh_ctx* c, const double* x, double* y, hipStream_t s) {
+    const int64_t n = c->L.field_elems();
+    hipLaunchKernelGGL(copy_kernel, dim3(grid_for(n)), dim3(256), 0, s, x, y, n);
+}
+
+}  // namespace elwh

@@ -1,0 +1,153 @@
+// Internal declarations of libelwh: context, padded device layout, kernel
+// launchers.  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/elwh.h"
+
+namespace elwh {
+
+// ---------------------------------------------------------------------------
+// Padded internal layout.  One component of a field is stored as
+// (nz+1) planes x (ny+1) rows x P elements, P = nx+1 rounded up to 64 so
+// every row starts 512-byte (FP64) / 256-byte (FP32) aligned.  2-D fields
+// have one plane.  Padding and Dirichlet nodes always hold zero.
+// ---------------------------------------------------------------------------
+struct Layout {
+    int dim = 2;
+    int nx = 0, ny = 0, nz = 0;      // cells
+    int64_t P = 0;                   // row pitch (elements)
+    int64_t PS = 0;                  // plane stride = (ny+1) * P
+    int64_t CS = 0;                  // component stride = (nz+1) * PS
+    int ncomp() const { return dim; }
+    int64_t nodes_caller() const {
+        return (int64_t)(nx + 1) * (ny + 1) * (dim == 3 ? (nz + 1) : 1);
+    }
+    int64_t field_elems() const { return CS * dim; }
+};
+
+// Stencil constants shared by the kernels (FP64; FP32 kernels convert).
+struct Stencil {
+    double cxx2, cyy2, czz2;   // 1/(2 h_a^2): compact terms with summed face pairs
+    double cxy, cxz, cyz;      // 1/(4 h_a h_b): central mixed terms
+    double cyyf, czzf;         // 1/h_y^2, 1/h_z^2: free-face normal compact term
+    double cfxy, cfxz, cfyz;   // 1/(2 h_a h_b): free-face one-sided mixed terms
+};
+
+// Which rows/planes are unknowns along the marching axis (y in 2-D, z in 3-D).
+struct March {
+    int lo, hi;            // first and last unknown index along the axis
+    int free_lo, free_hi;  // traction-free face at index 0 / at index n
+};
+
+// Device scalar slots used by the device-side CG updates.
+enum { S_RR = 0, S_PQ, S_RRNEW, S_ALPHA, S_BETA, S_BB, S_TMP, S_FLAG, S_NSLOT = 16 };
+
+struct Plan {
+    int nt = 0;
+    double dt = 0, c = 1, lambda_bound = 0, T = 0;
+};
+
+}  // namespace elwh
+
+struct elwh_ctx {
+    elwh::Layout L;
+    elwh::Stencil st;
+    elwh::March mr;
+    elwh::Plan plan;
+    elwh_grid grid;
+    int bc[6];
+    double omega;
+    elwh_opts opts;
+    hipStream_t stream = nullptr;
+    std::string err;
+
+    // filter weights (sign +1) and forcing factors cos(2 pi n / N_T), n = 0..K N_T
+    std::vector<double> w, cosn;
+
+    // FP64 coefficient arrays (one component each): a = c dt^2 / rho, lambda, mu
+    double *ca = nullptr, *cl = nullptr, *cm = nullptr;
+    double* mw = nullptr;          // M weights w_node * rho (0 at Dirichlet / padding)
+    // FP32 copies (FP32 path)
+    float *fa = nullptr, *fl = nullptr, *fm = nullptr;
+
+    // FP64 state buffers (2 time levels), accumulator and its compensation
+    double *s64[2] = {nullptr, nullptr};
+    float *s32[2] = {nullptr, nullptr};
+    double *acc = nullptr, *acc_lo = nullptr;
+    // forcing (internal layout) in FP64 and FP32
+    double* f64 = nullptr;
+    float* f32 = nullptr;
+    // general FP64 work vectors (internal layout): x, r, p, q, b, tmp, tmp2
+    double* vec[8] = {};
+    // GMRES basis (allocated on demand)
+    std::vector<double*> basis;
+    // reduction partials and device scalars
+    double* partials = nullptr;
+    double* dscal = nullptr;
+    double* hscal = nullptr;       // pinned host mirror
+    int red_blocks = 1024;
+
+    // kernel profiling: event pairs around each fused-step launch
+    bool prof_on = false;
+    std::vector<hipEvent_t> prof_ev;   // pool, reused
+    std::vector<int> prof_kind;        // 0 = step, 1 = half step, per recorded pair
+    size_t prof_used = 0;              // pairs recorded since the last read
+
+    // CG state of the stepwise interface
+    bool cg_active = false;
+    int cg_iters = 0;
+    double cg_bb = 0;
+    std::vector<double> alphas, betas;
+    int napply = 0;
+};
+
+namespace elwh {
+
+// ---- host plan (plan.cpp) --------------------------------------------------
+elwh_status make_plan(const elwh_grid* g, const double* rho, const double* lam, const double* mu,
+                      double omega, const int bc[6], const elwh_opts* o, Plan* out, std::string* err);
+elwh_status check_config(const elwh_grid* g, const int bc[6], const elwh_opts* o, std::string* err);
+Layout make_layout(const elwh_grid* g);
+Stencil make_stencil(const elwh_grid* g);
+March make_march(const elwh_grid* g, const int bc[6]);
+
+// ---- profiling hooks (api.hip): bracket one fused-step launch --------------
+void prof_begin(elwh_ctx* c);
+void prof_end(elwh_ctx* c, int kind);
+
+// ---- kernels (kernels2d.hip / kernels3d.hip / blas.hip) --------------------
+// Copy a caller-layout field (ncomp components) into the padded layout,
+// zeroing Dirichlet nodes (mask from bc); T = float or double destination.
+void launch_pack(const Layout& L, const int bc[6], const double* src, double* dst, int ncomp,
+                 hipStream_t s);
+void launch_pack_f32(const Layout& L, const int bc[6], const double* src, float* dst, int ncomp,
+                     hipStream_t s);
+void launch_unpack(const Layout& L, const int bc[6], const double* src, double* dst, int ncomp,
+                   hipStream_t s);
+void launch_convert_f32(const Layout& L, const double* src, float* dst, int ncomp, hipStream_t s);
+
+// One filter application in the padded layout.
+//   x     : u^0 (FP64, padded), read only
+//   f     : forcing (FP64 / FP32 per path) or null
+//   out   : sum_n s w_n u^n, plus x when amode (then s = -1): A_h x
+// Uses the context's state buffers and accumulator.
+void run_filter(elwh_ctx* c, const double* x, bool with_force, bool amode, bool fp32, double* out);
+
+// FP64 vector kernels over the padded layout (length = field_elems()).
+void launch_dot_M_partial(const elwh_ctx* c, const double* x, const double* y, hipStream_t s);
+void launch_reduce_final(const elwh_ctx* c, int mode, int slot, hipStream_t s);
+void launch_cg_update_xr(const elwh_ctx* c, double* x, double* r, const double* p, const double* q,
+                         hipStream_t s);
+void launch_cg_update_p(const elwh_ctx* c, double* p, const double* r, hipStream_t s);
+void launch_axpby(const elwh_ctx* c, double a, const double* x, double b, double* y, hipStream_t s);
+void launch_copy(const elwh_ctx* c, const double* x, double* y, hipStream_t s);
+
+enum { RED_SUM = 0, RED_PQ = 1, RED_RR = 2 };
+
+}  // namespace elwh

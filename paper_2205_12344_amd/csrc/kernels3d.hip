@@ -1,0 +1,301 @@
+// 3-D fused El-WaveHoltz step for gfx950.
+//
+// Same update as the 2-D kernel (corrected leapfrog of Sec. 4.3, trapezoid
+// accumulation of eq. el_WHI_OP fused into the step), with the 3-D
+// conservative stress divergence: for the u-row
+//   D+x(Abar D-x u) + D+y(mubar D-y u) + D+z(mubar D-z u)
+//   + D0x(lam D0y v) + D0y(mu D0x v) + D0x(lam D0z w) + D0z(mu D0x w)
+// and cyclically for v and w (a 19-point footprint).  Traction-free z faces
+// are closed from the discrete energy (one-sided normal differences, the
+// trapezoid weight 1/2 divided out).
+//
+// Mapping: one 64-lane wavefront per block owns 64 x nodes (62 computed) of
+// one y row and marches TZ planes in z.  Three planes x three rows of the
+// displacement live in registers and roll in z; x neighbours come from the
+// adjacent lanes; y-neighbour rows are separate coalesced row loads that
+// hit in cache (they are the own rows of the neighbouring wavefronts).
+#include "elwh_internal.h"
+#include "lanes.h"
+
+namespace elwh {
+
+struct Args3D {
+    int nx, ny, nz;
+    int64_t P, PS, CS;
+    int klo, khi, free_lo, free_hi;
+    double cxx2, cyy2, czz2, cxy, cxz, cyz, czzf, cfxz, cfyz;
+    double w, w0, fc;
+    int final_;
+};
+
+template <typename T>
+struct Plane {
+    T u[3], v[3], w[3];  // rows j-1, j, j+1
+    T lam, mu;           // row j
+};
+
+__device__ __forceinline__ void acc_add3(double& hi, double& lo, double x, bool comp) {
+    if (comp) {
+        const double t = hi + x;
+        const double z = t - hi;
+        const double e = (hi - (t - z)) + (x - z);
+        hi = t;
+        lo += e;
+    } else {
+        hi += x;
+    }
+}
+
+template <typename T, typename U, int TZ, int MODE, bool FORCE, bool COMP>
+__global__ __launch_bounds__(64) void step3d_kernel(const U* __restrict__ u, const T* uprev, T* unext,
+                                                   const double* __restrict__ xbase, T* __restrict__ u0out,
+                                                   double* __restrict__ acc, double* __restrict__ acclo,
+                                                   const T* __restrict__ ca, const T* __restrict__ cl,
+                                                   const T* __restrict__ cm, const T* __restrict__ f,
+                                                   Args3D A) {
+    const int lane = threadIdx.x;
+    const int i = 62 * blockIdx.x + lane;
+    const int j = 1 + (int)blockIdx.y;
+    const bool colv = i <= A.nx;
+    const bool store = lane >= 1 && lane <= 62 && i >= 1 && i <= A.nx - 1;
+    const int k0 = A.klo + (int)blockIdx.z * TZ;
+    if (k0 > A.khi) return;
+    const int k1 = min(k0 + TZ - 1, A.khi);
+    const int64_t P = A.P, PS = A.PS, CS = A.CS;
+    const T two = (T)2;
+    const T cxx2 = (T)A.cxx2, cyy2 = (T)A.cyy2, czz2 = (T)A.czz2;
+    const T cxy = (T)A.cxy, cxz = (T)A.cxz, cyz = (T)A.cyz;
+    const T czzf = (T)A.czzf, cfxz = (T)A.cfxz, cfyz = (T)A.cfyz;
+
+    auto load_plane = [&](int k, Plane<T>& q) {
+        if (colv && k >= 0 && k <= A.nz) {
+            const int64_t o = (int64_t)k * PS + (int64_t)j * P + i;
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                const int64_t orow = o + (int64_t)(r - 1) * P;
+                q.u[r] = (T)u[orow];
+                q.v[r] = (T)u[orow + CS];
+                q.w[r] = (T)u[orow + 2 * CS];
+            }
+            q.lam = cl[o];
+            q.mu = cm[o];
+        } else {
+#pragma unroll
+            for (int r = 0; r < 3; ++r) q.u[r] = q.v[r] = q.w[r] = (T)0;
+            q.lam = q.mu = (T)0;
+        }
+    };
+
+    Plane<T> D, C, Up;
+    load_plane(k0 - 1, D);
+    load_plane(k0, C);
+
+    for (int k = k0; k <= k1; ++k) {
+        load_plane(k + 1, Up);
+        const int64_t o = (int64_t)k * PS + (int64_t)j * P + i;
+        T lam_m, lam_p, mu_m, mu_p;
+        if (colv) {
+            lam_m = cl[o - P];
+            lam_p = cl[o + P];
+            mu_m = cm[o - P];
+            mu_p = cm[o + P];
+        } else {
+            lam_m = lam_p = mu_m = mu_p = (T)0;
+        }
+        // x neighbours by lane moves (all lanes take part)
+        const T lamL = lane_from_left(C.lam), lamR = lane_from_right(C.lam);
+        const T muL = lane_from_left(C.mu), muR = lane_from_right(C.mu);
+        const T uL = lane_from_left(C.u[1]), uR = lane_from_right(C.u[1]);
+        const T vL = lane_from_left(C.v[1]), vR = lane_from_right(C.v[1]);
+        const T wL = lane_from_left(C.w[1]), wR = lane_from_right(C.w[1]);
+        const T u_mL = lane_from_left(C.u[0]), u_mR = lane_from_right(C.u[0]);
+        const T u_pL = lane_from_left(C.u[2]), u_pR = lane_from_right(C.u[2]);
+        const T v_mL = lane_from_left(C.v[0]), v_mR = lane_from_right(C.v[0]);
+        const T v_pL = lane_from_left(C.v[2]), v_pR = lane_from_right(C.v[2]);
+        const T u_DL = lane_from_left(D.u[1]), u_DR = lane_from_right(D.u[1]);
+        const T u_UL = lane_from_left(Up.u[1]), u_UR = lane_from_right(Up.u[1]);
+        const T w_DL = lane_from_left(D.w[1]), w_DR = lane_from_right(D.w[1]);
+        const T w_UL = lane_from_left(Up.w[1]), w_UR = lane_from_right(Up.w[1]);
+
+        const T uc = C.u[1], vc = C.v[1], wc = C.w[1];
+        const T lc = C.lam, mc = C.mu;
+        const T AL = lamL + two * muL, AC = lc + two * mc, AR = lamR + two * muR;
+        const T Am = lam_m + two * mu_m, Ap = lam_p + two * mu_p;
+
+        // in-plane compact and xy mixed terms (all plane kinds)
+        T Lu = cxx2 * ((AR + AC) * (uR - uc) - (AC + AL) * (uc - uL)) +
+               cyy2 * ((mu_p + mc) * (C.u[2] - uc) - (mc + mu_m) * (uc - C.u[0])) +
+               cxy * (lamR * (v_pR - v_mR) - lamL * (v_pL - v_mL) + mu_p * (v_pR - v_pL) - mu_m * (v_mR - v_mL));
+        T Lv = cxx2 * ((muR + mc) * (vR - vc) - (mc + muL) * (vc - vL)) +
+               cyy2 * ((Ap + AC) * (C.v[2] - vc) - (AC + Am) * (vc - C.v[0])) +
+               cxy * (muR * (u_pR - u_mR) - muL * (u_pL - u_mL) + lam_p * (u_pR - u_pL) - lam_m * (u_mR - u_mL));
+        T Lw = cxx2 * ((muR + mc) * (wR - wc) - (mc + muL) * (wc - wL)) +
+               cyy2 * ((mu_p + mc) * (C.w[2] - wc) - (mc + mu_m) * (wc - C.w[0]));
+
+        if (A.free_hi && k == A.nz) {
+            const T lD = D.lam, mD = D.mu, AD = lD + two * mD;
+            Lu += -czzf * (mc + mD) * (uc - D.u[1]) - cfxz * (mc * (wR - wL) + mD * (w_DR - w_DL)) +
+                  cfxz * (lamR * (wR - w_DR) - lamL * (wL - w_DL));
+            Lv += -czzf * (mc + mD) * (vc - D.v[1]) - cfyz * (mc * (C.w[2] - C.w[0]) + mD * (D.w[2] - D.w[0])) +
+                  cfyz * (lam_p * (C.w[2] - D.w[2]) - lam_m * (C.w[0] - D.w[0]));
+            Lw += -czzf * (AC + AD) * (wc - D.w[1]) - cfxz * (lc * (uR - uL) + lD * (u_DR - u_DL)) +
+                  cfxz * (muR * (uR - u_DR) - muL * (uL - u_DL)) -
+                  cfyz * (lc * (C.v[2] - C.v[0]) + lD * (D.v[2] - D.v[0])) +
+                  cfyz * (mu_p * (C.v[2] - D.v[2]) - mu_m * (C.v[0] - D.v[0]));
+        } else if (A.free_lo && k == 0) {
+            const T lU = Up.lam, mU = Up.mu, AU = lU + two * mU;
+            Lu += czzf * (mc + mU) * (Up.u[1] - uc) + cfxz * (mc * (wR - wL) + mU * (w_UR - w_UL)) +
+                  cfxz * (lamR * (w_UR - wR) - lamL * (w_UL - wL));
+            Lv += czzf * (mc + mU) * (Up.v[1] - vc) + cfyz * (mc * (C.w[2] - C.w[0]) + mU * (Up.w[2] - Up.w[0])) +
+                  cfyz * (lam_p * (Up.w[2] - C.w[2]) - lam_m * (Up.w[0] - C.w[0]));
+            Lw += czzf * (AC + AU) * (Up.w[1] - wc) + cfxz * (lc * (uR - uL) + lU * (u_UR - u_UL)) +
+                  cfxz * (muR * (u_UR - uR) - muL * (u_UL - uL)) +
+                  cfyz * (lc * (C.v[2] - C.v[0]) + lU * (Up.v[2] - Up.v[0])) +
+                  cfyz * (mu_p * (Up.v[2] - C.v[2]) - mu_m * (Up.v[0] - C.v[0]));
+        } else {
+            const T lD = D.lam, mD = D.mu, lU = Up.lam, mU = Up.mu;
+            const T AD = lD + two * mD, AU = lU + two * mU;
+            Lu += czz2 * ((mU + mc) * (Up.u[1] - uc) - (mc + mD) * (uc - D.u[1])) +
+                  cxz * (lamR * (w_UR - w_DR) - lamL * (w_UL - w_DL) + mU * (w_UR - w_UL) - mD * (w_DR - w_DL));
+            Lv += czz2 * ((mU + mc) * (Up.v[1] - vc) - (mc + mD) * (vc - D.v[1])) +
+                  cyz * (lam_p * (Up.w[2] - D.w[2]) - lam_m * (Up.w[0] - D.w[0]) + mU * (Up.w[2] - Up.w[0]) -
+                         mD * (D.w[2] - D.w[0]));
+            Lw += czz2 * ((AU + AC) * (Up.w[1] - wc) - (AC + AD) * (wc - D.w[1])) +
+                  cxz * (muR * (u_UR - u_DR) - muL * (u_UL - u_DL) + lU * (u_UR - u_UL) - lD * (u_DR - u_DL)) +
+                  cyz * (mu_p * (Up.v[2] - D.v[2]) - mu_m * (Up.v[0] - D.v[0]) + lU * (Up.v[2] - Up.v[0]) -
+                         lD * (D.v[2] - D.v[0]));
+        }
+
+        if (store) {
+            const T a = ca[o];
+            if constexpr (FORCE) {
+                const T fc = (T)A.fc;
+                Lu -= fc * f[o];
+                Lv -= fc * f[o + CS];
+                Lw -= fc * f[o + 2 * CS];
+            }
+            const T Ls[3] = {Lu, Lv, Lw};
+            const T cs[3] = {uc, vc, wc};
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const int64_t oq = o + q * CS;
+                T nq;
+                double hq, lq = 0.0;
+                if constexpr (MODE == 0) {
+                    nq = two * cs[q] - uprev[oq] + a * Ls[q];
+                    hq = acc[oq];
+                    if constexpr (COMP) lq = acclo[oq];
+                } else {
+                    nq = cs[q] + (T)0.5 * a * Ls[q];
+                    hq = xbase ? xbase[oq] : 0.0;
+                    acc_add3(hq, lq, A.w0 * (double)cs[q], COMP);
+                    if (u0out) u0out[oq] = cs[q];
+                }
+                unext[oq] = nq;
+                acc_add3(hq, lq, A.w * (double)nq, COMP);
+                if (COMP && A.final_) {
+                    acc[oq] = hq + lq;
+                } else {
+                    acc[oq] = hq;
+                    if constexpr (COMP) acclo[oq] = lq;
+                }
+            }
+        }
+        D = C;
+        C = Up;
+    }
+}
+
+template <typename T, typename U, int TZ, int MODE>
+static void launch3_t(bool force, bool comp, dim3 grid, hipStream_t s, const U* u, const T* uprev, T* unext,
+                      const double* xbase, T* u0out, double* acc, double* acclo, const T* ca, const T* cl,
+                      const T* cm, const T* f, const Args3D& A) {
+#define ELWH_L3(F, CMP)                                                                                   \
+    hipLaunchKernelGGL((step3d_kernel<T, U, TZ, MODE, F, CMP>), grid, dim3(64), 0, s, u, uprev, unext, xbase, \
+                       u0out, acc, acclo, ca, cl, cm, f, A)
+    if (force) {
+        if (comp) ELWH_L3(true, true); else ELWH_L3(true, false);
+    } else {
+        if (comp) ELWH_L3(false, true); else ELWH_L3(false, false);
+    }
+#undef ELWH_L3
+}
+
+constexpr int TZ3 = 16;
+
+void run_filter_3d(elwh_ctx* c, const double* x, bool with_force, bool amode, bool fp32, double* out) {
+    hipStream_t s = c->stream;
+    Args3D A;
+    A.nx = c->L.nx;
+    A.ny = c->L.ny;
+    A.nz = c->L.nz;
+    A.P = c->L.P;
+    A.PS = c->L.PS;
+    A.CS = c->L.CS;
+    A.klo = c->mr.lo;
+    A.khi = c->mr.hi;
+    A.free_lo = c->mr.free_lo;
+    A.free_hi = c->mr.free_hi;
+    A.cxx2 = c->st.cxx2;
+    A.cyy2 = c->st.cyy2;
+    A.czz2 = c->st.czz2;
+    A.cxy = c->st.cxy;
+    A.cxz = c->st.cxz;
+    A.cyz = c->st.cyz;
+    A.czzf = c->st.czzf;
+    A.cfxz = c->st.cfxz;
+    A.cfyz = c->st.cfyz;
+    A.final_ = 0;
+    const int nplanes = A.khi - A.klo + 1;
+    dim3 grid((unsigned)((A.nx - 1 + 61) / 62), (unsigned)(A.ny - 1), (unsigned)((nplanes + TZ3 - 1) / TZ3));
+    const int nsteps = c->plan.nt * c->opts.periods;
+    const double sgn = amode ? -1.0 : 1.0;
+    const bool comp = fp32 && c->opts.compensated;
+    double* acc = out;
+    double* lo = c->acc_lo;
+    A.w0 = sgn * c->w[0];
+    A.w = sgn * c->w[1];
+    A.fc = c->cosn[0];
+    if (!fp32) {
+        double *b0 = c->s64[0], *b1 = c->s64[1];
+        prof_begin(c);
+        launch3_t<double, double, TZ3, 1>(with_force, false, grid, s, x, nullptr, b1, amode ? x : nullptr, nullptr,
+                                          acc, lo, c->ca, c->cl, c->cm, c->f64, A);
+        prof_end(c, 1);
+        const double* prev = x;
+        double* cur = b1;
+        for (int n = 1; n < nsteps; ++n) {
+            double* nxt = (n == 1) ? b0 : const_cast<double*>(prev);
+            A.w = sgn * c->w[n + 1];
+            A.fc = c->cosn[n];
+            prof_begin(c);
+            launch3_t<double, double, TZ3, 0>(with_force, false, grid, s, cur, prev, nxt, nullptr, nullptr, acc,
+                                              lo, c->ca, c->cl, c->cm, c->f64, A);
+            prof_end(c, 0);
+            prev = cur;
+            cur = nxt;
+        }
+    } else {
+        float *b0 = c->s32[0], *b1 = c->s32[1];
+        prof_begin(c);
+        launch3_t<float, double, TZ3, 1>(with_force, comp, grid, s, x, nullptr, b1, amode ? x : nullptr, b0, acc,
+                                         lo, c->fa, c->fl, c->fm, c->f32, A);
+        prof_end(c, 1);
+        float* prev = b0;
+        float* cur = b1;
+        for (int n = 1; n < nsteps; ++n) {
+            A.w = sgn * c->w[n + 1];
+            A.fc = c->cosn[n];
+            A.final_ = (n == nsteps - 1);
+            prof_begin(c);
+            launch3_t<float, float, TZ3, 0>(with_force, comp, grid, s, cur, prev, prev, nullptr, nullptr, acc, lo,
+                                            c->fa, c->fl, c->fm, c->f32, A);
+            prof_end(c, 0);
+            float* t = prev;
+            prev = cur;
+            cur = t;
+        }
+    }
+}
+
+}  // namespace elwh

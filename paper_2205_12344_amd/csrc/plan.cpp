@@ -1,0 +1,382 @@
+// Host-side set-up of libelwh: argument checks, padded layout, stencil
+// constants and the time-step plan.
+//
+// Time-step rule (the paper fixes only a CFL number for explicit FD runs,
+// Sec. 5.1, and a whole number of steps per period for the implicit scheme,
+// Sec. 4.4): G = max over unknown rows of sum_j |(rho^-1 Ltilde)_ij|
+// (Gershgorin), dt* = cfl * 2 / sqrt(G), N_T = max(3, ceil(T / dt*)),
+// dt = T / N_T, and the correction factor c = (sin(w dt/2) / (w dt/2))^2 of
+// the corrected scheme (Sec. 4.3).
+//
+// The rows of Ltilde are those of minus the Hessian of the discrete strain
+// energy (trapezoid rule; edge terms 1/2 w_e k_e (D+ u)^2, node terms
+// w_p [lam (Dh_a u_a)(Dh_b u_b) + mu (Dh_b u_a)(Dh_a u_b)]), divided by the
+// node weight.  Rows two or more cells away from every face use the closed
+// form of the conservative stencil; rows near a face enumerate the energy
+// terms that touch them.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <thread>
+#include <vector>
+
+#include "elwh_internal.h"
+
+namespace elwh {
+
+namespace {
+
+struct Geo {
+    int d;
+    int n[3];
+    double h[3];
+    int bc[6];
+    int64_t sx, sy, sz;  // caller-layout strides
+    const double *rho, *lam, *mu;
+
+    bool unknown(const int* p) const {
+        for (int a = 0; a < d; ++a) {
+            if (p[a] == 0 && bc[2 * a] == ELWH_BC_DIRICHLET) return false;
+            if (p[a] == n[a] && bc[2 * a + 1] == ELWH_BC_DIRICHLET) return false;
+        }
+        return true;
+    }
+    bool inside(const int* p) const {
+        for (int a = 0; a < d; ++a)
+            if (p[a] < 0 || p[a] > n[a]) return false;
+        return true;
+    }
+    int64_t idx(const int* p) const { return p[0] * sx + p[1] * sy + (d == 3 ? p[2] * sz : 0); }
+    double node_w(const int* p) const {
+        double w = 1.0;
+        for (int a = 0; a < d; ++a) {
+            if (p[a] == 0 && bc[2 * a] == ELWH_BC_TRACTION_FREE) w *= 0.5;
+            if (p[a] == n[a] && bc[2 * a + 1] == ELWH_BC_TRACTION_FREE) w *= 0.5;
+        }
+        return w;
+    }
+    // weight of the edge from p along axis a: 1/2 per free face of another axis
+    double edge_w(const int* p, int a) const {
+        double w = 1.0;
+        for (int b = 0; b < d; ++b) {
+            if (b == a) continue;
+            if (p[b] == 0 && bc[2 * b] == ELWH_BC_TRACTION_FREE) w *= 0.5;
+            if (p[b] == n[b] && bc[2 * b + 1] == ELWH_BC_TRACTION_FREE) w *= 0.5;
+        }
+        return w;
+    }
+    // node difference Dh_a at q: up to two (node, coefficient) pairs
+    int dhat(const int* q, int a, int nodes[2][3], double coef[2]) const {
+        int k = 0;
+        auto put = [&](int off, double cf) {
+            for (int b = 0; b < 3; ++b) nodes[k][b] = q[b];
+            nodes[k][a] += off;
+            coef[k] = cf;
+            ++k;
+        };
+        if (q[a] == 0) {
+            if (bc[2 * a] == ELWH_BC_TRACTION_FREE) { put(1, 1.0 / h[a]); put(0, -1.0 / h[a]); }
+        } else if (q[a] == n[a]) {
+            if (bc[2 * a + 1] == ELWH_BC_TRACTION_FREE) { put(0, 1.0 / h[a]); put(-1, -1.0 / h[a]); }
+        } else {
+            put(1, 0.5 / h[a]);
+            put(-1, -0.5 / h[a]);
+        }
+        return k;
+    }
+};
+
+// Gershgorin row sum of rho^-1 Ltilde for dof (p, c), from the energy terms.
+double row_sum_generic(const Geo& g, const int* p, int c) {
+    // K row entries keyed by neighbour offset in {-1,0,1}^3 and component
+    double K[27][3];
+    std::memset(K, 0, sizeof(K));
+    auto slot = [&](const int* t) {
+        return (t[0] - p[0] + 1) + 3 * (t[1] - p[1] + 1) + 9 * ((g.d == 3 ? t[2] - p[2] : 0) + 1);
+    };
+    const int d = g.d;
+    // compact edge terms touching p, component c
+    for (int a = 0; a < d; ++a) {
+        for (int side = 0; side < 2; ++side) {
+            int lo[3] = {p[0], p[1], p[2]}, hi[3] = {p[0], p[1], p[2]};
+            if (side == 0) {
+                if (p[a] == 0) continue;
+                lo[a] -= 1;
+            } else {
+                if (p[a] == g.n[a]) continue;
+                hi[a] += 1;
+            }
+            const int64_t il = g.idx(lo), ih = g.idx(hi);
+            double k;
+            if (c == a)
+                k = 0.5 * ((g.lam[il] + 2 * g.mu[il]) + (g.lam[ih] + 2 * g.mu[ih]));
+            else
+                k = 0.5 * (g.mu[il] + g.mu[ih]);
+            const double e = g.edge_w(lo, a) * k / (g.h[a] * g.h[a]);
+            const int* other = side == 0 ? lo : hi;
+            K[slot(p)][c] += e;
+            K[slot(other)][c] -= e;
+        }
+    }
+    // node cross terms at q = p and q = p +- e_x (the only nodes whose node
+    // differences involve p)
+    std::vector<std::array<int, 3>> qs;
+    qs.push_back({p[0], p[1], p[2]});
+    for (int a = 0; a < d; ++a)
+        for (int s = -1; s <= 1; s += 2) {
+            std::array<int, 3> q = {p[0], p[1], p[2]};
+            q[a] += s;
+            qs.push_back(q);
+        }
+    for (auto& qa : qs) {
+        const int* q = qa.data();
+        if (!g.inside(q) || !g.unknown(q)) continue;
+        const int64_t iq = g.idx(q);
+        const double wq = g.node_w(q);
+        for (int a = 0; a < d; ++a)
+            for (int b = a + 1; b < d; ++b) {
+                int na[2][3], nb[2][3];
+                double ca_[2], cb_[2];
+                const int ka = g.dhat(q, a, na, ca_);
+                const int kb = g.dhat(q, b, nb, cb_);
+                // term coef * (D1 u_alpha)(D2 u_beta)
+                struct Term { double coef; int alpha, beta; bool d1_is_a; };
+                const Term terms[2] = {{wq * g.lam[iq], a, b, true},    // lam (Dh_a u_a)(Dh_b u_b)
+                                       {wq * g.mu[iq], a, b, false}};   // mu (Dh_b u_a)(Dh_a u_b)
+                for (const Term& t : terms) {
+                    int (*n1)[3] = t.d1_is_a ? na : nb;
+                    int (*n2)[3] = t.d1_is_a ? nb : na;
+                    const double* c1 = t.d1_is_a ? ca_ : cb_;
+                    const double* c2 = t.d1_is_a ? cb_ : ca_;
+                    const int k1 = t.d1_is_a ? ka : kb, k2 = t.d1_is_a ? kb : ka;
+                    if (c == t.alpha)
+                        for (int s = 0; s < k1; ++s)
+                            if (n1[s][0] == p[0] && n1[s][1] == p[1] && n1[s][2] == p[2])
+                                for (int r = 0; r < k2; ++r) K[slot(n2[r])][t.beta] += t.coef * c1[s] * c2[r];
+                    if (c == t.beta)
+                        for (int s = 0; s < k2; ++s)
+                            if (n2[s][0] == p[0] && n2[s][1] == p[1] && n2[s][2] == p[2])
+                                for (int r = 0; r < k1; ++r) K[slot(n1[r])][t.alpha] += t.coef * c2[s] * c1[r];
+                }
+            }
+    }
+    // Ltilde = -K / w_p over unknown targets
+    double sum = 0.0;
+    const int zr = d == 3 ? 1 : 0;
+    for (int dz = -zr; dz <= zr; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                int t[3] = {p[0] + dx, p[1] + dy, p[2] + dz};
+                if (!g.inside(t) || !g.unknown(t)) continue;
+                for (int cc = 0; cc < d; ++cc) sum += std::fabs(K[slot(t)][cc]);
+            }
+    return sum / g.node_w(p) / g.rho[g.idx(p)];
+}
+
+// Closed-form row sums (all components) for a node two or more cells from
+// every face: every stencil entry is a sum of positive coefficients.
+double row_sum_interior(const Geo& g, const int* p) {
+    const int64_t C = g.idx(p);
+    auto at = [&](const double* a, int dx, int dy, int dz) {
+        return a[C + dx * g.sx + dy * g.sy + dz * g.sz];
+    };
+    const double hx = g.h[0], hy = g.h[1];
+    const double ixx = 1 / (hx * hx), iyy = 1 / (hy * hy), ixy = 1 / (2 * hx * hy);
+    auto A = [&](int dx, int dy, int dz) { return at(g.lam, dx, dy, dz) + 2 * at(g.mu, dx, dy, dz); };
+    auto M = [&](int dx, int dy, int dz) { return at(g.mu, dx, dy, dz); };
+    auto Lm = [&](int dx, int dy, int dz) { return at(g.lam, dx, dy, dz); };
+    double best;
+    if (g.d == 2) {
+        const double ru = (A(1, 0, 0) + 2 * A(0, 0, 0) + A(-1, 0, 0)) * ixx +
+                          (M(0, 1, 0) + 2 * M(0, 0, 0) + M(0, -1, 0)) * iyy +
+                          (Lm(1, 0, 0) + Lm(-1, 0, 0) + M(0, 1, 0) + M(0, -1, 0)) * ixy;
+        const double rv = (M(1, 0, 0) + 2 * M(0, 0, 0) + M(-1, 0, 0)) * ixx +
+                          (A(0, 1, 0) + 2 * A(0, 0, 0) + A(0, -1, 0)) * iyy +
+                          (M(1, 0, 0) + M(-1, 0, 0) + Lm(0, 1, 0) + Lm(0, -1, 0)) * ixy;
+        best = std::max(ru, rv);
+    } else {
+        const double hz = g.h[2];
+        const double izz = 1 / (hz * hz), ixz = 1 / (2 * hx * hz), iyz = 1 / (2 * hy * hz);
+        const double ru = (A(1, 0, 0) + 2 * A(0, 0, 0) + A(-1, 0, 0)) * ixx +
+                          (M(0, 1, 0) + 2 * M(0, 0, 0) + M(0, -1, 0)) * iyy +
+                          (M(0, 0, 1) + 2 * M(0, 0, 0) + M(0, 0, -1)) * izz +
+                          (Lm(1, 0, 0) + Lm(-1, 0, 0) + M(0, 1, 0) + M(0, -1, 0)) * ixy +
+                          (Lm(1, 0, 0) + Lm(-1, 0, 0) + M(0, 0, 1) + M(0, 0, -1)) * ixz;
+        const double rv = (M(1, 0, 0) + 2 * M(0, 0, 0) + M(-1, 0, 0)) * ixx +
+                          (A(0, 1, 0) + 2 * A(0, 0, 0) + A(0, -1, 0)) * iyy +
+                          (M(0, 0, 1) + 2 * M(0, 0, 0) + M(0, 0, -1)) * izz +
+                          (M(1, 0, 0) + M(-1, 0, 0) + Lm(0, 1, 0) + Lm(0, -1, 0)) * ixy +
+                          (Lm(0, 1, 0) + Lm(0, -1, 0) + M(0, 0, 1) + M(0, 0, -1)) * iyz;
+        const double rw = (M(1, 0, 0) + 2 * M(0, 0, 0) + M(-1, 0, 0)) * ixx +
+                          (M(0, 1, 0) + 2 * M(0, 0, 0) + M(0, -1, 0)) * iyy +
+                          (A(0, 0, 1) + 2 * A(0, 0, 0) + A(0, 0, -1)) * izz +
+                          (M(1, 0, 0) + M(-1, 0, 0) + Lm(0, 0, 1) + Lm(0, 0, -1)) * ixz +
+                          (M(0, 1, 0) + M(0, -1, 0) + Lm(0, 0, 1) + Lm(0, 0, -1)) * iyz;
+        best = std::max(ru, std::max(rv, rw));
+    }
+    return best / g.rho[C];
+}
+
+double gershgorin(const Geo& g) {
+    const int nzn = g.d == 3 ? g.n[2] + 1 : 1;
+    unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    nth = std::min<unsigned>(nth, (unsigned)nzn * (g.d == 3 ? 1 : 1));
+    if (g.d == 2) nth = std::min<unsigned>(nth, (unsigned)(g.n[1] + 1));
+    std::vector<double> part(nth, 0.0);
+    auto work = [&](unsigned t) {
+        double best = 0.0;
+        const int outer = g.d == 3 ? nzn : g.n[1] + 1;
+        for (int o = (int)t; o < outer; o += (int)nth) {
+            int p[3] = {0, 0, 0};
+            const int ylo = g.d == 3 ? 0 : o, yhi = g.d == 3 ? g.n[1] : o;
+            if (g.d == 3) p[2] = o;
+            for (int y = ylo; y <= yhi; ++y) {
+                p[1] = y;
+                for (int x = 0; x <= g.n[0]; ++x) {
+                    p[0] = x;
+                    if (!g.unknown(p)) continue;
+                    bool near = false;
+                    for (int a = 0; a < g.d; ++a)
+                        if (p[a] < 2 || p[a] > g.n[a] - 2) near = true;
+                    double r;
+                    if (near) {
+                        r = 0.0;
+                        for (int c = 0; c < g.d; ++c) r = std::max(r, row_sum_generic(g, p, c));
+                    } else {
+                        r = row_sum_interior(g, p);
+                    }
+                    best = std::max(best, r);
+                }
+            }
+        }
+        part[t] = best;
+    };
+    std::vector<std::thread> th;
+    for (unsigned t = 1; t < nth; ++t) th.emplace_back(work, t);
+    work(0);
+    for (auto& x : th) x.join();
+    return *std::max_element(part.begin(), part.end());
+}
+
+}  // namespace
+
+elwh_status check_config(const elwh_grid* g, const int bc[6], const elwh_opts* o, std::string* err) {
+    if (!g || !bc) { *err = "null grid or bc"; return ELWH_ERR_ARG; }
+    if (g->dim != 2 && g->dim != 3) { *err = "dim must be 2 or 3"; return ELWH_ERR_ARG; }
+    for (int a = 0; a < g->dim; ++a) {
+        if (g->n[a] < 2) { *err = "need at least 2 cells per axis"; return ELWH_ERR_ARG; }
+        if (g->n[a] > (1 << 20)) { *err = "grid too large"; return ELWH_ERR_ARG; }
+        if (!(g->len[a] > 0) || !std::isfinite(g->len[a])) { *err = "box lengths must be positive"; return ELWH_ERR_ARG; }
+    }
+    for (int f = 0; f < 2 * g->dim; ++f)
+        if (bc[f] != ELWH_BC_DIRICHLET && bc[f] != ELWH_BC_TRACTION_FREE) { *err = "bad boundary code"; return ELWH_ERR_ARG; }
+    // traction-free faces only on the marching axis (y in 2-D, z in 3-D)
+    const int march = g->dim - 1;
+    for (int a = 0; a < g->dim; ++a)
+        if (a != march && (bc[2 * a] != ELWH_BC_DIRICHLET || bc[2 * a + 1] != ELWH_BC_DIRICHLET)) {
+            *err = g->dim == 2 ? "traction-free faces are supported on the y faces only"
+                               : "traction-free faces are supported on the z faces only";
+            return ELWH_ERR_ARG;
+        }
+    if (o) {
+        if (!(o->cfl > 0) || !(o->cfl < 1.0 + 1e-12)) { *err = "cfl must be in (0, 1]"; return ELWH_ERR_ARG; }
+        if (o->nt < 0 || (o->nt > 0 && o->nt < 3)) { *err = "nt must be 0 (rule) or >= 3"; return ELWH_ERR_ARG; }
+        if (o->periods < 1 || o->periods > 1000) { *err = "periods must be in [1, 1000]"; return ELWH_ERR_ARG; }
+        if (o->prec != ELWH_FP64 && o->prec != ELWH_FP32_STEP) { *err = "bad precision"; return ELWH_ERR_ARG; }
+        if (o->krylov < 0 || o->krylov > 2) { *err = "bad krylov method"; return ELWH_ERR_ARG; }
+        if (o->gmres_m < 1 || o->gmres_m > 200) { *err = "gmres_m must be in [1, 200]"; return ELWH_ERR_ARG; }
+        if (o->scheme != ELWH_SCHEME_CORRECTED && o->scheme != ELWH_SCHEME_STANDARD) { *err = "bad scheme"; return ELWH_ERR_ARG; }
+    }
+    return ELWH_OK;
+}
+
+elwh_status make_plan(const elwh_grid* g, const double* rho, const double* lam, const double* mu,
+                      double omega, const int bc[6], const elwh_opts* o, Plan* out, std::string* err) {
+    elwh_status st = check_config(g, bc, o, err);
+    if (st != ELWH_OK) return st;
+    if (!rho || !lam || !mu) { *err = "null material array"; return ELWH_ERR_ARG; }
+    if (!(omega > 0) || !std::isfinite(omega)) { *err = "omega must be positive and finite"; return ELWH_ERR_ARG; }
+    Geo geo;
+    geo.d = g->dim;
+    for (int a = 0; a < 3; ++a) {
+        geo.n[a] = a < g->dim ? g->n[a] : 0;
+        geo.h[a] = a < g->dim ? g->len[a] / g->n[a] : 1.0;
+    }
+    for (int f = 0; f < 6; ++f) geo.bc[f] = f < 2 * g->dim ? bc[f] : ELWH_BC_DIRICHLET;
+    geo.sx = 1;
+    geo.sy = g->n[0] + 1;
+    geo.sz = (int64_t)(g->n[0] + 1) * (g->n[1] + 1);
+    geo.rho = rho;
+    geo.lam = lam;
+    geo.mu = mu;
+    const int64_t nn = geo.sz * (g->dim == 3 ? g->n[2] + 1 : 1);
+    for (int64_t i = 0; i < nn; ++i) {
+        if (!(rho[i] > 0) || !(lam[i] > 0) || !(mu[i] > 0) || !std::isfinite(rho[i]) ||
+            !std::isfinite(lam[i]) || !std::isfinite(mu[i])) {
+            *err = "materials must be positive and finite";
+            return ELWH_ERR_ARG;
+        }
+    }
+    const double G = gershgorin(geo);
+    const double T = 2.0 * M_PI / omega;
+    int nt;
+    if (o && o->nt > 0) {
+        nt = o->nt;
+    } else {
+        const double cfl = o ? o->cfl : 0.8;
+        const double dt_star = cfl * 2.0 / std::sqrt(G);
+        const double q = std::ceil(T / dt_star);
+        if (!(q < 1e8)) { *err = "too many steps per period"; return ELWH_ERR_ARG; }
+        nt = std::max(3, (int)q);
+    }
+    out->nt = nt;
+    out->T = T;
+    out->dt = T / nt;
+    out->lambda_bound = G;
+    const bool corrected = !o || o->scheme == ELWH_SCHEME_CORRECTED;
+    const double x = 0.5 * omega * out->dt;
+    out->c = corrected ? (std::sin(x) / x) * (std::sin(x) / x) : 1.0;
+    return ELWH_OK;
+}
+
+Layout make_layout(const elwh_grid* g) {
+    Layout L;
+    L.dim = g->dim;
+    L.nx = g->n[0];
+    L.ny = g->n[1];
+    L.nz = g->dim == 3 ? g->n[2] : 0;
+    L.P = ((int64_t)(L.nx + 1) + 63) / 64 * 64;
+    L.PS = (int64_t)(L.ny + 1) * L.P;
+    L.CS = L.PS * (L.dim == 3 ? (L.nz + 1) : 1);
+    return L;
+}
+
+Stencil make_stencil(const elwh_grid* g) {
+    Stencil s;
+    const double hx = g->len[0] / g->n[0], hy = g->len[1] / g->n[1];
+    const double hz = g->dim == 3 ? g->len[2] / g->n[2] : 1.0;
+    s.cxx2 = 0.5 / (hx * hx);
+    s.cyy2 = 0.5 / (hy * hy);
+    s.czz2 = 0.5 / (hz * hz);
+    s.cxy = 0.25 / (hx * hy);
+    s.cxz = 0.25 / (hx * hz);
+    s.cyz = 0.25 / (hy * hz);
+    s.cyyf = 1.0 / (hy * hy);
+    s.czzf = 1.0 / (hz * hz);
+    s.cfxy = 0.5 / (hx * hy);
+    s.cfxz = 0.5 / (hx * hz);
+    s.cfyz = 0.5 / (hy * hz);
+    return s;
+}
+
+March make_march(const elwh_grid* g, const int bc[6]) {
+    March m;
+    const int a = g->dim - 1;
+    m.free_lo = bc[2 * a] == ELWH_BC_TRACTION_FREE;
+    m.free_hi = bc[2 * a + 1] == ELWH_BC_TRACTION_FREE;
+    m.lo = m.free_lo ? 0 : 1;
+    m.hi = m.free_hi ? g->n[a] : g->n[a] - 1;
+    return m;
+}
+
+}  // namespace elwh

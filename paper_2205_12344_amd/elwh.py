@@ -1,0 +1,265 @@
+"""Python binding of libelwh.so (ctypes).  Argument marshalling only: every
+step of the filter and the Krylov solve runs in the library's HIP kernels.
+
+torch is imported before the library is loaded, so libelwh binds to the HIP
+runtime torch already loaded, and torch supplies device memory and streams.
+If the library is not built, importing this module raises: there is no CPU
+fallback on the product path.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+import torch  # noqa: F401  (must precede loading the HIP library)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libelwh.so")
+
+OK, ERR_ARG, ERR_ALLOC, ERR_HIP, ERR_UNSTABLE, ERR_NOT_CONVERGED, ERR_BREAKDOWN = range(7)
+STATUS_NAMES = ["OK", "ERR_ARG", "ERR_ALLOC", "ERR_HIP", "ERR_UNSTABLE", "ERR_NOT_CONVERGED", "ERR_BREAKDOWN"]
+BC_DIRICHLET, BC_TRACTION_FREE = 0, 1
+FP64, FP32_STEP = 0, 1
+KRYLOV_CG, KRYLOV_GMRES, KRYLOV_CR = 0, 1, 2
+SCHEME_CORRECTED, SCHEME_STANDARD = 0, 1
+
+EXPORTED = [
+    "elwh_default_opts", "elwh_plan", "elwh_create", "elwh_destroy", "elwh_query", "elwh_last_error",
+    "elwh_apply_filter", "elwh_apply_A", "elwh_solve", "elwh_cg_begin", "elwh_cg_iterate",
+    "elwh_cg_result", "elwh_dot_M", "elwh_profile_enable", "elwh_profile_read",
+]
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3), ("len", ctypes.c_double * 3)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("cfl", ctypes.c_double), ("nt", ctypes.c_int), ("periods", ctypes.c_int),
+                ("prec", ctypes.c_int), ("krylov", ctypes.c_int), ("gmres_m", ctypes.c_int),
+                ("scheme", ctypes.c_int), ("compensated", ctypes.c_int), ("inner_tol", ctypes.c_double),
+                ("max_outer", ctypes.c_int), ("stream", ctypes.c_void_p)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("outer", ctypes.c_int), ("nt", ctypes.c_int), ("napply", ctypes.c_int),
+                ("dt", ctypes.c_double), ("c", ctypes.c_double), ("lambda_bound", ctypes.c_double),
+                ("relres", ctypes.c_double), ("relres_fp64", ctypes.c_double), ("cond_est", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ElwhError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES[status] if 0 <= status < 7 else status}: {msg}")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run paper_2205_12344_amd.build.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    D = ctypes.c_double
+    I = ctypes.c_int
+    lib.elwh_default_opts.argtypes = [ctypes.POINTER(Opts)]
+    lib.elwh_default_opts.restype = None
+    lib.elwh_plan.argtypes = [ctypes.POINTER(Grid), P, P, P, D, ctypes.POINTER(I), ctypes.POINTER(Opts),
+                              ctypes.POINTER(Info)]
+    lib.elwh_create.argtypes = [ctypes.POINTER(Grid), P, P, P, D, ctypes.POINTER(I), ctypes.POINTER(Opts),
+                                ctypes.POINTER(P)]
+    lib.elwh_destroy.argtypes = [P]
+    lib.elwh_destroy.restype = None
+    lib.elwh_query.argtypes = [P, ctypes.POINTER(Info)]
+    lib.elwh_last_error.argtypes = [P]
+    lib.elwh_last_error.restype = ctypes.c_char_p
+    lib.elwh_apply_filter.argtypes = [P, P, P, P]
+    lib.elwh_apply_A.argtypes = [P, P, P]
+    lib.elwh_solve.argtypes = [P, P, P, D, I, P, ctypes.POINTER(Info)]
+    lib.elwh_cg_begin.argtypes = [P, P, P]
+    lib.elwh_cg_iterate.argtypes = [P, I, D, ctypes.POINTER(D)]
+    lib.elwh_cg_result.argtypes = [P, P, ctypes.POINTER(Info)]
+    lib.elwh_dot_M.argtypes = [P, P, P, ctypes.POINTER(D)]
+    lib.elwh_profile_enable.argtypes = [P, I]
+    lib.elwh_profile_read.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(I), ctypes.POINTER(D),
+                                      ctypes.POINTER(I)]
+    for name in EXPORTED:
+        if name not in ("elwh_default_opts", "elwh_destroy", "elwh_last_error"):
+            getattr(lib, name).restype = ctypes.c_int
+    return lib
+
+
+lib = _load()
+
+
+def default_opts(**kw):
+    o = Opts()
+    lib.elwh_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if k == "stream":
+            v = ctypes.c_void_p(v)
+        setattr(o, k, v)
+    return o
+
+
+def make_grid(dim, n, length=None):
+    g = Grid()
+    g.dim = dim
+    for a in range(3):
+        g.n[a] = int(n[a]) if a < dim else 0
+        g.len[a] = float(length[a]) if (length is not None and a < dim) else 1.0
+    return g
+
+
+def _bc_array(bc):
+    arr = (ctypes.c_int * 6)()
+    for k, v in enumerate(bc):
+        arr[k] = int(v)
+    return arr
+
+
+def _dev(x, name):
+    """float64 contiguous CUDA tensor (from numpy or torch)."""
+    if isinstance(x, np.ndarray):
+        x = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64))
+    if not isinstance(x, torch.Tensor):
+        raise TypeError(f"{name}: expected numpy array or torch tensor")
+    x = x.to(device="cuda", dtype=torch.float64).contiguous()
+    return x
+
+
+def _host(x):
+    return np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+
+
+def plan(dim, n, rho, lam, mu, omega, bc, length=None, **opts):
+    """Time-step plan on the host (no GPU): dict with nt, dt, c, lambda_bound."""
+    g = make_grid(dim, n, length)
+    r, l, m = _host(rho), _host(lam), _host(mu)
+    o = default_opts(**opts)
+    info = Info()
+    st = lib.elwh_plan(ctypes.byref(g), r.ctypes.data, l.ctypes.data, m.ctypes.data, float(omega),
+                       _bc_array(bc), ctypes.byref(o), ctypes.byref(info))
+    if st != OK:
+        raise ElwhError(st, lib.elwh_last_error(None).decode())
+    return {"nt": info.nt, "dt": info.dt, "c": info.c, "lambda_bound": info.lambda_bound}
+
+
+class Context:
+    """One El-WaveHoltz problem on the GPU (wraps elwh_create / elwh_destroy)."""
+
+    def __init__(self, dim, n, rho, lam, mu, omega, bc, length=None, stream=None, **opts):
+        if not torch.cuda.is_available():
+            raise RuntimeError("libelwh needs a GPU")
+        self.dim = dim
+        self.n = tuple(int(v) for v in n[:dim])
+        self.node_shape = tuple(self.n[a] + 1 for a in reversed(range(dim)))
+        self.field_shape = (dim,) + self.node_shape
+        self.stream = torch.cuda.current_stream() if stream is None else stream
+        g = make_grid(dim, n, length)
+        o = default_opts(stream=self.stream.cuda_stream, **opts)
+        self._r, self._l, self._m = _dev(rho, "rho"), _dev(lam, "lam"), _dev(mu, "mu")
+        for t in (self._r, self._l, self._m):
+            if tuple(t.shape) != self.node_shape:
+                raise ValueError(f"material shape {tuple(t.shape)} != {self.node_shape}")
+        h = ctypes.c_void_p()
+        st = lib.elwh_create(ctypes.byref(g), self._r.data_ptr(), self._l.data_ptr(), self._m.data_ptr(),
+                             float(omega), _bc_array(bc), ctypes.byref(o), ctypes.byref(h))
+        if st != OK:
+            raise ElwhError(st, lib.elwh_last_error(None).decode())
+        self._h = h
+        self.opts = o
+        del self._r, self._l, self._m          # the library copied them
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.elwh_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != OK:
+            raise ElwhError(st, lib.elwh_last_error(self._h).decode())
+
+    def _field(self, x, name):
+        t = _dev(x, name)
+        if tuple(t.shape) != self.field_shape:
+            raise ValueError(f"{name} shape {tuple(t.shape)} != {self.field_shape}")
+        return t
+
+    def info(self):
+        i = Info()
+        self._check(lib.elwh_query(self._h, ctypes.byref(i)))
+        return i.as_dict()
+
+    def apply_filter(self, u0, f=None, out=None):
+        u0 = self._field(u0, "u0")
+        ft = self._field(f, "f") if f is not None else None
+        out = torch.empty(self.field_shape, dtype=torch.float64, device="cuda") if out is None else out
+        self._check(lib.elwh_apply_filter(self._h, u0.data_ptr(), ft.data_ptr() if ft is not None else None,
+                                          out.data_ptr()))
+        return out
+
+    def apply_A(self, x, out=None):
+        x = self._field(x, "x")
+        out = torch.empty(self.field_shape, dtype=torch.float64, device="cuda") if out is None else out
+        self._check(lib.elwh_apply_A(self._h, x.data_ptr(), out.data_ptr()))
+        return out
+
+    def dot_M(self, x, y):
+        x, y = self._field(x, "x"), self._field(y, "y")
+        r = ctypes.c_double()
+        self._check(lib.elwh_dot_M(self._h, x.data_ptr(), y.data_ptr(), ctypes.byref(r)))
+        return r.value
+
+    def solve(self, f, x0=None, tol=1e-10, maxit=1000, raise_on_fail=True):
+        f = self._field(f, "f")
+        x0t = self._field(x0, "x0") if x0 is not None else None
+        v = torch.empty(self.field_shape, dtype=torch.float64, device="cuda")
+        info = Info()
+        st = lib.elwh_solve(self._h, f.data_ptr(), x0t.data_ptr() if x0t is not None else None, float(tol),
+                            int(maxit), v.data_ptr(), ctypes.byref(info))
+        d = info.as_dict()
+        d["status"] = STATUS_NAMES[st]
+        if st != OK and raise_on_fail:
+            self._check(st)
+        return v, d
+
+    # stepwise CG
+    def cg_begin(self, f, x0=None):
+        f = self._field(f, "f")
+        x0t = self._field(x0, "x0") if x0 is not None else None
+        self._check(lib.elwh_cg_begin(self._h, f.data_ptr(), x0t.data_ptr() if x0t is not None else None))
+
+    def cg_iterate(self, k, tol=0.0):
+        r = ctypes.c_double()
+        self._check(lib.elwh_cg_iterate(self._h, int(k), float(tol), ctypes.byref(r)))
+        return r.value
+
+    def profile_enable(self, on=True):
+        self._check(lib.elwh_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self):
+        """Summed fused-step kernel time (ms) and launch counts since the last read."""
+        ts, ti = ctypes.c_double(), ctypes.c_double()
+        ns, ni = ctypes.c_int(), ctypes.c_int()
+        self._check(lib.elwh_profile_read(self._h, ctypes.byref(ts), ctypes.byref(ns), ctypes.byref(ti),
+                                          ctypes.byref(ni)))
+        return {"step_ms": ts.value, "nstep": ns.value, "init_ms": ti.value, "ninit": ni.value}
+
+    def cg_result(self):
+        v = torch.empty(self.field_shape, dtype=torch.float64, device="cuda")
+        info = Info()
+        self._check(lib.elwh_cg_result(self._h, v.data_ptr(), ctypes.byref(info)))
+        return v, info.as_dict()
+
+
+def context_from_case(case, **opts):
+    """Context for an inputs.Case."""
+    return Context(case.dim, case.n, case.rho, case.lam, case.mu, case.omega, case.bc, length=case.length, **opts)

@@ -1,0 +1,332 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU FP64 oracle on
+the same seeded inputs.
+
+Bars.  FP64: rel-L2 <= 1e-12 per application (the stated FP64 tolerance).
+FP32 stepping: rel-L2 <= fp32_bound(N_T) = 2 u32 sqrt(N_T) N_T / (2 pi) per
+application, u32 = 2^-24: one rounding per step, accumulated as a random
+walk over N_T steps and amplified by at most 1/sin(theta_min) ~ N_T/(2 pi),
+the bound of the leapfrog's discrete Green's function for the slowest mode
+of one period.  Solves: the stated residuals."""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import direct, krylov
+from oracle import stepping as S
+from oracle.operator import Operator
+from oracle.problem import Problem
+from paper_2205_12344_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+U32 = 2.0 ** -24
+
+
+def fp32_bound(nt):
+    return 2.0 * U32 * math.sqrt(nt) * nt / (2 * math.pi)
+
+
+def _say(*a):
+    print("[gpu-test]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def E():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2205_12344_amd import elwh
+    return elwh
+
+
+def _media(shape, seed, s=0.25):
+    rng = np.random.default_rng(seed)
+    rho = np.exp(s * rng.standard_normal(shape))
+    mu = np.exp(s * rng.standard_normal(shape))
+    lam = mu * np.clip(2 * np.exp(s * rng.standard_normal(shape)), 1, 3)
+    return rho, lam, mu
+
+
+def _rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def _oracle(dim, n, length, bc, rho, lam, mu, omega, **kw):
+    prob = Problem(dim, n, length=length, bc=bc)
+    op = Operator(prob, rho, lam, mu)
+    wh = S.WaveHoltz(op, omega, **kw)
+    return prob, op, wh
+
+
+# 2-D grids: ragged in x (62 computed columns per wavefront) and in y (16 rows
+# per block), free faces on y, one-column and two-row extremes
+CASES_2D = [
+    ((130, 37), (0, 0, 0, 1), (1.0, 0.8)),
+    ((63, 16), (0, 0, 0, 0), (1.0, 1.0)),
+    ((64, 33), (0, 0, 1, 0), (0.9, 1.1)),
+    ((125, 20), (0, 0, 1, 1), (1.0, 0.5)),
+    ((2, 40), (0, 0, 0, 1), (1.0, 1.0)),
+    ((50, 2), (0, 0, 1, 1), (1.0, 1.0)),
+]
+
+
+@pytest.mark.parametrize("n,bc,length", CASES_2D)
+@pytest.mark.parametrize("force", [False, True])
+def test_filter_2d_fp64(E, n, bc, length, force):
+    _say("filter2d fp64", n, bc, force)
+    rho, lam, mu = _media((n[1] + 1, n[0] + 1), sum(n))
+    om = 9.3
+    prob, op, wh = _oracle(2, n, length, bc, rho, lam, mu, om)
+    rng = np.random.default_rng(7)
+    u0 = rng.standard_normal(prob.field_shape) * prob.unknown_mask()
+    f = rng.standard_normal(prob.field_shape) * prob.unknown_mask() if force else None
+    ref = prob.scatter(wh.apply_filter(prob.gather(u0), prob.gather(f) if force else None))
+    ctx = E.Context(2, n, rho, lam, mu, om, bc, length=length)
+    assert ctx.info()["nt"] == wh.nt
+    got = ctx.apply_filter(u0, f).cpu().numpy()
+    assert _rel(got, ref) <= FP64_TOL
+    # A_h x = x - S_h x
+    gotA = ctx.apply_A(u0).cpu().numpy()
+    refA = prob.scatter(wh.apply_A(prob.gather(u0)))
+    assert _rel(gotA, refA) <= FP64_TOL
+
+
+CASES_3D = [
+    ((70, 9, 37), (0, 0, 0, 0, 0, 0), (1.0, 0.7, 1.2)),
+    ((20, 11, 18), (0, 0, 0, 0, 0, 1), (1.0, 1.0, 1.0)),
+    ((33, 6, 17), (0, 0, 0, 0, 1, 1), (1.0, 1.0, 0.8)),
+    ((2, 2, 2), (0, 0, 0, 0, 1, 0), (1.0, 1.0, 1.0)),
+]
+
+
+@pytest.mark.parametrize("n,bc,length", CASES_3D)
+@pytest.mark.parametrize("force", [False, True])
+def test_filter_3d_fp64(E, n, bc, length, force):
+    _say("filter3d fp64", n, bc, force)
+    shape = (n[2] + 1, n[1] + 1, n[0] + 1)
+    rho, lam, mu = _media(shape, sum(n) + 1)
+    om = 6.1
+    prob, op, wh = _oracle(3, n, length, bc, rho, lam, mu, om)
+    rng = np.random.default_rng(8)
+    u0 = rng.standard_normal(prob.field_shape) * prob.unknown_mask()
+    f = rng.standard_normal(prob.field_shape) * prob.unknown_mask() if force else None
+    ref = prob.scatter(wh.apply_filter(prob.gather(u0), prob.gather(f) if force else None))
+    ctx = E.Context(3, n, rho, lam, mu, om, bc, length=length)
+    assert ctx.info()["nt"] == wh.nt
+    got = ctx.apply_filter(u0, f).cpu().numpy()
+    assert _rel(got, ref) <= FP64_TOL
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_filter_fp32_stepping(E, dim):
+    n = (90, 41) if dim == 2 else (40, 13, 22)
+    bc = (0, 0, 0, 1) if dim == 2 else (0, 0, 0, 0, 0, 1)
+    _say("filter fp32", dim, n)
+    shape = tuple(n[a] + 1 for a in reversed(range(dim)))
+    rho, lam, mu = _media(shape, 31 + dim)
+    om = 7.0
+    prob, op, wh = _oracle(dim, n, None, bc, rho, lam, mu, om)
+    rng = np.random.default_rng(9)
+    u0 = rng.standard_normal(prob.field_shape) * prob.unknown_mask()
+    f = rng.standard_normal(prob.field_shape) * prob.unknown_mask()
+    ref = prob.scatter(wh.apply_filter(prob.gather(u0), prob.gather(f)))
+    for comp in (1, 0):
+        ctx = E.Context(dim, n, rho, lam, mu, om, bc, prec=E.FP32_STEP, compensated=comp)
+        got = ctx.apply_filter(u0, f).cpu().numpy()
+        err = _rel(got, ref)
+        _say("  fp32 compensated", comp, "nt", wh.nt, "rel err", err, "bound", fp32_bound(wh.nt))
+        assert err <= fp32_bound(wh.nt)
+
+
+def test_k_periods_and_standard_scheme(E):
+    n, bc = (47, 29), (0, 0, 0, 1)
+    rho, lam, mu = _media((30, 48), 41)
+    rng = np.random.default_rng(10)
+    for kw in ({"periods": 3}, {"scheme": 1}, {"nt": 40}, {"cfl": 0.3}):
+        _say("variant", kw)
+        okw = {k: (S.STANDARD if k == "scheme" else v) for k, v in kw.items()}
+        prob, op, wh = _oracle(2, n, None, bc, rho, lam, mu, 5.5, **okw)
+        u0 = rng.standard_normal(prob.field_shape) * prob.unknown_mask()
+        ref = prob.scatter(wh.apply_filter(prob.gather(u0)))
+        ctx = E.Context(2, n, rho, lam, mu, 5.5, bc, **kw)
+        assert ctx.info()["nt"] == wh.nt
+        assert _rel(ctx.apply_filter(u0).cpu().numpy(), ref) <= FP64_TOL
+
+
+def test_dot_M(E):
+    n, bc = (33, 20), (0, 0, 1, 1)
+    rho, lam, mu = _media((21, 34), 51)
+    prob = Problem(2, n, bc=bc)
+    m = prob.mass_diag(rho)
+    rng = np.random.default_rng(11)
+    x = rng.standard_normal(prob.field_shape)
+    y = rng.standard_normal(prob.field_shape)
+    ctx = E.Context(2, n, rho, lam, mu, 3.0, bc)
+    got = ctx.dot_M(x, y)
+    ref = float(np.dot(m * prob.gather(x), prob.gather(y)))
+    assert got == pytest.approx(ref, rel=1e-13)
+
+
+def test_fixed_point_config1(E):
+    """Sec. 1.1 / 4.3: Pi_h v* = v* with v* the direct Helmholtz solve."""
+    c = inputs.config1()
+    prob, op, wh = _oracle(2, c.n, None, c.bc, c.rho, c.lam, c.mu, c.omega)
+    v = prob.scatter(direct.solve(op, c.omega, prob.gather(c.f)))
+    ctx = E.context_from_case(c)
+    got = ctx.apply_filter(v, c.f).cpu().numpy()
+    assert _rel(got, v) <= FP64_TOL
+
+
+def test_solve_config1_matches_direct_and_oracle_cg(E):
+    """Config 1: CG to 1e-10 matches the direct solve (<= 1e-10) and the
+    oracle's CG iterate after the same number of iterations (<= 1e-12)."""
+    c = inputs.config1()
+    prob, op, wh = _oracle(2, c.n, None, c.bc, c.rho, c.lam, c.mu, c.omega)
+    fv = prob.gather(c.f)
+    vstar = direct.solve(op, c.omega, fv)
+    ctx = E.context_from_case(c)
+    v, info = ctx.solve(c.f, tol=1e-10, maxit=200)
+    _say("config1 solve", info)
+    v = v.cpu().numpy()
+    assert info["iters"] <= 20
+    assert info["relres_fp64"] <= 1.1e-10
+    assert _rel(prob.gather(v), vstar) <= 1e-10
+    res = krylov.cg(wh.apply_A, wh.rhs(fv), op.m, tol=1e-10, maxit=200)
+    assert res.iters == info["iters"]
+    assert _rel(prob.gather(v), res.x) <= 1e-12
+    assert info["cond_est"] == pytest.approx(res.lanczos_cond(), rel=1e-6)
+    # tighter solve reaches the direct solution to 1e-12
+    v2, info2 = ctx.solve(c.f, tol=1e-13, maxit=200)
+    assert _rel(prob.gather(v2.cpu().numpy()), vstar) <= 1e-12
+
+
+def test_stepwise_cg_and_warm_start(E):
+    c = inputs.config1()
+    prob, op, wh = _oracle(2, c.n, None, c.bc, c.rho, c.lam, c.mu, c.omega)
+    fv = prob.gather(c.f)
+    ctx = E.context_from_case(c)
+    ctx.cg_begin(c.f)
+    r5 = ctx.cg_iterate(5)
+    res5 = krylov.cg(wh.apply_A, wh.rhs(fv), op.m, tol=0.0, maxit=5)
+    assert r5 == pytest.approx(res5.history[-1], rel=1e-9)
+    v5, _ = ctx.cg_result()
+    assert _rel(prob.gather(v5.cpu().numpy()), res5.x) <= 1e-12
+    # resume by restart from the 5-iteration iterate
+    v, info = ctx.solve(c.f, x0=v5, tol=1e-10, maxit=200)
+    vstar = direct.solve(op, c.omega, fv)
+    assert _rel(prob.gather(v.cpu().numpy()), vstar) <= 1e-9
+
+
+@pytest.mark.parametrize("krylov_id", [1, 2])
+def test_gmres_and_cr_match_direct(E, krylov_id):
+    n, bc = (40, 30), (0, 0, 0, 1)
+    rho, lam, mu = _media((31, 41), 61)
+    om = 6.3
+    prob, op, wh = _oracle(2, n, None, bc, rho, lam, mu, om)
+    rng = np.random.default_rng(12)
+    f = rng.standard_normal(prob.field_shape) * prob.unknown_mask()
+    vstar = direct.solve(op, om, prob.gather(f))
+    ctx = E.Context(2, n, rho, lam, mu, om, bc, krylov=krylov_id, gmres_m=20)
+    v, info = ctx.solve(f, tol=1e-11, maxit=500)
+    _say("krylov", krylov_id, info)
+    assert info["relres_fp64"] <= 2e-11
+    assert _rel(prob.gather(v.cpu().numpy()), vstar) <= 1e-9
+
+
+def test_fp32_refinement_reaches_fp64_residual(E):
+    """FP32 stepping + FP64 iterative refinement: the FP64-recomputed residual
+    reaches 1e-8 and the solution matches the direct solve."""
+    n, bc = (64, 64), (0, 0, 0, 1)
+    rho, lam, mu = _media((65, 65), 71, 0.2)
+    om = 12.0
+    prob, op, wh = _oracle(2, n, None, bc, rho, lam, mu, om)
+    rng = np.random.default_rng(13)
+    f = inputs.gaussian_sources(2, n, (1.0, 1.0), [(0.4, 0.6)], [0.05], [(0.6, 0.8)])
+    vstar = direct.solve(op, om, prob.gather(f))
+    ctx = E.Context(2, n, rho, lam, mu, om, bc, prec=E.FP32_STEP)
+    v, info = ctx.solve(f, tol=1e-8, maxit=2000)
+    _say("fp32 IR", info)
+    assert info["relres_fp64"] <= 1e-8
+    assert info["outer"] >= 2
+    assert _rel(prob.gather(v.cpu().numpy()), vstar) <= 1e-6
+
+
+def test_rejects_bad_arguments(E):
+    ok = np.ones((9, 9))
+    bad = ok.copy()
+    bad[2, 2] = np.inf
+    with pytest.raises(E.ElwhError, match="ERR_ARG"):
+        E.Context(2, (8, 8), bad, ok, ok, 3.0, (0, 0, 0, 0))
+    with pytest.raises(E.ElwhError, match="ERR_ARG"):
+        E.Context(2, (8, 8), ok, ok, ok, 3.0, (0, 1, 0, 0))
+    with pytest.raises(E.ElwhError, match="ERR_ARG"):
+        E.Context(2, (8, 8), ok, ok, ok, 0.0, (0, 0, 0, 0))
+
+
+def test_unstable_step_is_reported(E):
+    """A step count far below the stability limit makes the energy grow; the
+    solver reports ELWH_ERR_UNSTABLE (or a breakdown of the indefinite
+    operator) instead of returning garbage."""
+    c = inputs.config1()
+    ctx = E.Context(2, c.n, c.rho, c.lam, c.mu, c.omega, c.bc, nt=6)
+    v, info = ctx.solve(c.f, tol=1e-10, maxit=50, raise_on_fail=False)
+    assert info["status"] in ("ERR_UNSTABLE", "ERR_BREAKDOWN")
+
+
+# ---------------------------------------------------------------- full size --
+
+def test_config2_full_size_fp64_and_fp32(E):
+    """Config 2 (1024^2, random media, free top) element by element against
+    the oracle, in the launch configuration the benchmark times."""
+    c = inputs.config2()
+    _say("config2 full size, omega", c.omega)
+    prob, op, wh = _oracle(2, c.n, None, c.bc, c.rho, c.lam, c.mu, c.omega)
+    fv = prob.gather(c.f)
+    u0 = inputs.gaussian_sources(2, c.n, (1.0, 1.0), [(0.3, 0.4), (0.7, 0.6)], [0.05, 0.03],
+                                 [(1.0, 0.0), (0.0, 1.0)]) * prob.unknown_mask()
+    ref = prob.scatter(wh.apply_filter(prob.gather(u0), fv))
+    ctx = E.context_from_case(c)
+    assert ctx.info()["nt"] == wh.nt
+    got = ctx.apply_filter(u0, c.f).cpu().numpy()
+    assert _rel(got, ref) <= FP64_TOL
+    ctx32 = E.context_from_case(c, prec=E.FP32_STEP)
+    err32 = _rel(ctx32.apply_filter(u0, c.f).cpu().numpy(), ref)
+    _say("config2 fp32 rel err", err32, "bound", fp32_bound(wh.nt))
+    assert err32 <= fp32_bound(wh.nt)
+
+
+def test_config3_full_size_fixed_point():
+    """Config 3 (256^3 layered medium): the manufactured fixed point
+    Pi_h v* = v* with f = omega^2 rho v* + Ltilde v* from the oracle's slice
+    stencil, FP64 (<= 1e-12) and FP32 stepping (<= fp32_bound(N_T))."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2205_12344_amd import elwh as E
+    from oracle.stencil import ltilde_dirichlet
+    c = inputs.config3()
+    _say("config3 full size, omega", c.omega)
+    n = c.n[0]
+    x = np.arange(n + 1) / n
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    bump = np.sin(np.pi * X) * np.sin(np.pi * Y) * np.sin(np.pi * Z)
+    v = np.array([bump * np.sin(3 * np.pi * X), bump * np.cos(2 * np.pi * Y), bump * np.sin(5 * np.pi * Z)])
+    del X, Y, Z
+    f = c.omega ** 2 * c.rho[None] * v + ltilde_dirichlet(tuple(1.0 / m for m in c.n), c.lam, c.mu, v)
+    ctx = E.context_from_case(c)
+    got = ctx.apply_filter(v, f).cpu().numpy()
+    err = _rel(got, v)
+    _say("config3 fp64 fixed point err", err)
+    assert err <= FP64_TOL
+    del ctx
+    ctx32 = E.context_from_case(c, prec=E.FP32_STEP)
+    err32 = _rel(ctx32.apply_filter(v, f).cpu().numpy(), v)
+    nt = ctx32.info()["nt"]
+    _say("config3 fp32 fixed point err", err32, "bound", fp32_bound(nt))
+    assert err32 <= fp32_bound(nt)

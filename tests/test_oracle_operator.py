@@ -232,3 +232,17 @@ def test_inputs_are_sane():
     c2 = inputs.config2(n=64)
     assert c2.rho.shape == (65, 65) and np.all(c2.lam >= c2.mu * 0.999999) and np.all(c2.lam <= 3 * c2.mu * 1.000001)
     assert c2.omega > 0
+
+
+@pytest.mark.parametrize("dim,n", [(2, (11, 9)), (3, (6, 7, 5))])
+def test_slice_stencil_matches_energy_assembly(dim, n):
+    """The slice form used for the largest grids equals the assembled operator
+    on all-Dirichlet boxes with variable media."""
+    from oracle.stencil import ltilde_dirichlet
+    prob = Problem(dim, n, length=(1.0, 0.8, 1.2)[:dim])
+    rho, lam, mu = _random_media(prob, 21)
+    op = O.Operator(prob, rho, lam, mu)
+    u = np.random.default_rng(22).standard_normal(prob.field_shape) * prob.unknown_mask()
+    ref = prob.scatter(op.apply_Ltilde(prob.gather(u)))
+    got = ltilde_dirichlet(prob.h, lam, mu, u)
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-11 * np.abs(ref).max())
