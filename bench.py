@@ -169,6 +169,7 @@ def main():
     ctx = elwh.context_from_case(case)
     info = ctx.info()
     nt = info["nt"]
+    tv, tr = ctx.get_tile(elwh.FP64)
     ctx.cg_begin(case.f)
     el, prof = time_cg(ctx, args.steps, args.warmup)
     lup_per_step = nt * nodes
@@ -178,12 +179,13 @@ def main():
     b = BYTES_PER_LUP[(2, "f64")]
     achieved = b * nodes / (step_avg_ms * 1e-3) / 1e9
     traffic = read_traffic("step2d_f64_cfg2_1024")
+    log(f"tile V={tv} TY={tr}")
     log(f"fp64: {ms_per_step:.3f} ms/step, {value / 1e9:.2f} GLUP/s, step kernel {1e3 * step_avg_ms:.1f} us "
         f"({prof['nstep']} launches), {achieved:.0f} GB/s")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic,
-                "kernel": "step2d_kernel<double,double,16,0,false,false>",
+                "kernel": f"step2d_kernel<double,double,V={tv},TY={tr},MODE=0,FORCE=0,COMP=0>",
                 "bytes_per_lup": b, "units_per_launch": nodes,
                 "avg_launch_us": round(1e3 * step_avg_ms, 3)}
     ctx.close()
@@ -193,9 +195,11 @@ def main():
                     ("f32", {"prec": elwh.FP32_STEP, "compensated": 0})):
         c2 = elwh.context_from_case(case, **kw)
         p = kernel_rate(c2, 10)
+        v32 = c2.get_tile(elwh.FP32_STEP)
         avg = p["step_ms"] / max(p["nstep"], 1)
         bb = BYTES_PER_LUP[(2, tag)]
-        variants[tag] = {"step_kernel_us": round(1e3 * avg, 3), "glup_s_kernel": round(nodes / avg / 1e6, 3),
+        variants[tag] = {"tile": list(v32), "step_kernel_us": round(1e3 * avg, 3),
+                         "glup_s_kernel": round(nodes / avg / 1e6, 3),
                          "bytes_per_lup": bb, "achieved_GBs": round(bb * nodes / avg / 1e6, 1),
                          "frac": round(bb * nodes / avg / 1e6 / HBM_PEAK_GBS, 4)}
         log(f"{tag}: step kernel {1e3 * avg:.1f} us, {variants[tag]['achieved_GBs']} GB/s")
@@ -209,12 +213,30 @@ def main():
             p = kernel_rate(ctx3, 2)
             avg = p["step_ms"] / max(p["nstep"], 1)
             bb = BYTES_PER_LUP[(3, tag)]
-            variants["3d_" + tag] = {"workload": c3.name, "nt": ctx3.info()["nt"], "step_kernel_us": round(1e3 * avg, 3),
+            t3 = ctx3.get_tile(elwh.FP32_STEP if tag != "f64" else elwh.FP64)
+            variants["3d_" + tag] = {"workload": c3.name, "nt": ctx3.info()["nt"], "tile": list(t3),
+                                     "step_kernel_us": round(1e3 * avg, 3),
                                      "glup_s_kernel": round(n3 / avg / 1e6, 3), "bytes_per_lup": bb,
                                      "achieved_GBs": round(bb * n3 / avg / 1e6, 1),
                                      "frac": round(bb * n3 / avg / 1e6 / HBM_PEAK_GBS, 4)}
             log(f"3d {tag}: step kernel {1e3 * avg:.1f} us, {variants['3d_' + tag]['achieved_GBs']} GB/s")
             ctx3.close()
+
+    # practical HBM ceiling: a plain device-to-device copy of 2 GiB (beyond
+    # the 256 MB last-level cache)
+    x = torch.empty(2 ** 28, dtype=torch.float64, device="cuda").fill_(1.0)
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * x.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del x, y
+    log(f"copy ceiling: {copy_gbs:.0f} GB/s")
 
     cpu = None
     if not args.no_cpu:
@@ -232,6 +254,7 @@ def main():
                    "grid": list(case.n), "omega": case.omega, "nt": nt, "unknown_nodes": nodes,
                    "lup_per_step": lup_per_step},
         "roofline": roofline, "cpu_baseline": cpu, "variants": variants,
+        "copy_ceiling_GBs": round(copy_gbs, 1),
     }
     print(json.dumps(out))
 

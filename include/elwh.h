@@ -82,6 +82,7 @@ typedef struct {
     double inner_tol;  /* FP32 path: relative tolerance of each inner FP32 solve (default 1e-4) */
     int max_outer;     /* FP32 path: maximum refinement steps (default 50) */
     void* stream;      /* hipStream_t the context works on; NULL = the null stream */
+    int autotune;      /* 1 (default): pick the step-kernel tiling by timing at create */
 } elwh_opts;
 
 typedef struct {
@@ -194,6 +195,22 @@ elwh_status elwh_dot_M(elwh_ctx* ctx, const double* x, const double* y, double* 
  */
 elwh_status elwh_profile_enable(elwh_ctx* ctx, int on);
 elwh_status elwh_profile_read(elwh_ctx* ctx, double* step_ms, int* nstep, double* init_ms, int* ninit);
+
+/*
+ * Tiling of the fused step kernel for precision prec (ELWH_FP64 or
+ * ELWH_FP32_STEP): vec nodes per lane along x (2-D: 1 or 2, FP32 also 4;
+ * 3-D: 1) and rows (2-D: 4, 8, 16 rows; 3-D: 4, 8, 16, 32 planes) marched
+ * per wavefront.  The tiling changes speed only, never results.
+ * elwh_autotune times every supported tiling on reps operator applications
+ * (HIP events) and keeps the fastest; results are cached per process by
+ * (dim, precision, accumulator, grid size) and, when the environment
+ * variable ELWH_TUNE_CACHE names a file, in that file as JSON lines keyed by
+ * (arch, dim, precision, accumulator, grid size).  Synchronous.
+ * Errors: ELWH_ERR_ARG (unsupported tiling), ELWH_ERR_HIP.
+ */
+elwh_status elwh_set_tile(elwh_ctx* ctx, int prec, int vec, int rows);
+elwh_status elwh_get_tile(const elwh_ctx* ctx, int prec, int* vec, int* rows);
+elwh_status elwh_autotune(elwh_ctx* ctx, int prec, int reps, double* best_step_us);
 
 #ifdef __cplusplus
 }

@@ -12,8 +12,12 @@
 // ||r||_M <= tol ||b||_M, else solve A_h d = r to inner_tol and x += d.
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
+#include <tuple>
 #include <vector>
 
 #include "elwh_internal.h"
@@ -22,26 +26,25 @@ namespace elwh {
 void run_filter_2d(elwh_ctx* c, const double* x, bool with_force, bool amode, bool fp32, double* out);
 void run_filter_3d(elwh_ctx* c, const double* x, bool with_force, bool amode, bool fp32, double* out);
 
-void prof_begin(elwh_ctx* c) {
+void prof_mark(elwh_ctx* c, int phase, int nsteps) {
     if (!c->prof_on) return;
-    const size_t need = 2 * (c->prof_used + 1);
-    while (c->prof_ev.size() < need) {
-        hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) {
-            c->prof_on = false;
-            return;
+    const size_t base = 3 * c->prof_used;
+    if (phase == 0) {
+        while (c->prof_ev.size() < base + 3) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) {
+                c->prof_on = false;
+                return;
+            }
+            c->prof_ev.push_back(e);
         }
-        c->prof_ev.push_back(e);
     }
-    (void)hipEventRecord(c->prof_ev[2 * c->prof_used], c->stream);
-}
-
-void prof_end(elwh_ctx* c, int kind) {
-    if (!c->prof_on) return;
-    (void)hipEventRecord(c->prof_ev[2 * c->prof_used + 1], c->stream);
-    if (c->prof_kind.size() <= c->prof_used) c->prof_kind.resize(c->prof_used + 1);
-    c->prof_kind[c->prof_used] = kind;
-    c->prof_used++;
+    (void)hipEventRecord(c->prof_ev[base + phase], c->stream);
+    if (phase == 2) {
+        if (c->prof_nsteps.size() <= c->prof_used) c->prof_nsteps.resize(c->prof_used + 1);
+        c->prof_nsteps[c->prof_used] = nsteps;
+        c->prof_used++;
+    }
 }
 
 void run_filter(elwh_ctx* c, const double* x, bool with_force, bool amode, bool fp32, double* out) {
@@ -405,6 +408,7 @@ void elwh_default_opts(elwh_opts* o) {
     o->inner_tol = 1e-4;
     o->max_outer = 50;
     o->stream = nullptr;
+    o->autotune = 1;
 }
 
 elwh_status elwh_plan(const elwh_grid* grid, const double* rho, const double* lam, const double* mu, double omega,
@@ -545,6 +549,19 @@ elwh_status elwh_create(const elwh_grid* grid, const double* rho, const double* 
             c->err = "stream synchronisation failed in create";
             return fail(ELWH_ERR_HIP);
         }
+    }
+    // default tiling, then (optionally) the timed choice
+    if (c->L.dim == 2) {
+        c->tile64 = Tile{2, 8};
+        c->tile32 = Tile{4, 8};
+    } else {
+        c->tile64 = Tile{1, 16};
+        c->tile32 = Tile{1, 16};
+    }
+    if (o.autotune) {
+        if ((st = elwh_autotune(c, ELWH_FP64, 2, nullptr)) != ELWH_OK) return fail(st);
+        if (o.prec == ELWH_FP32_STEP && (st = elwh_autotune(c, ELWH_FP32_STEP, 2, nullptr)) != ELWH_OK)
+            return fail(st);
     }
     *out = c;
     return ELWH_OK;
@@ -768,21 +785,173 @@ elwh_status elwh_profile_read(elwh_ctx* c, double* step_ms, int* nstep, double* 
     double ts = 0, ti = 0;
     int ns = 0, ni = 0;
     for (size_t k = 0; k < c->prof_used; ++k) {
-        float ms = 0.f;
-        HIPCK(hipEventElapsedTime(&ms, c->prof_ev[2 * k], c->prof_ev[2 * k + 1]));
-        if (c->prof_kind[k] == 0) {
-            ts += ms;
-            ns++;
-        } else {
-            ti += ms;
-            ni++;
-        }
+        float m1 = 0.f, m2 = 0.f;
+        HIPCK(hipEventElapsedTime(&m1, c->prof_ev[3 * k], c->prof_ev[3 * k + 1]));
+        HIPCK(hipEventElapsedTime(&m2, c->prof_ev[3 * k + 1], c->prof_ev[3 * k + 2]));
+        ti += m1;
+        ni++;
+        ts += m2;
+        ns += c->prof_nsteps[k];
     }
     c->prof_used = 0;
     if (step_ms) *step_ms = ts;
     if (nstep) *nstep = ns;
     if (init_ms) *init_ms = ti;
     if (ninit) *ninit = ni;
+    return ELWH_OK;
+}
+
+elwh_status elwh_set_tile(elwh_ctx* c, int prec, int vec, int rows) {
+    if (!c) return ELWH_ERR_ARG;
+    const bool fp32 = prec == ELWH_FP32_STEP;
+    const bool ok = c->L.dim == 2 ? tile_valid_2d(fp32, vec, rows) : tile_valid_3d(fp32, vec, rows);
+    if (!ok) {
+        c->err = "unsupported tile";
+        return ELWH_ERR_ARG;
+    }
+    Tile& t = fp32 ? c->tile32 : c->tile64;
+    t.V = vec;
+    t.TY = rows;
+    return ELWH_OK;
+}
+
+}  // extern "C"
+
+namespace {
+using TuneKey = std::tuple<int, int, int, int, int, int>;   // dim, prec, comp, nx, ny, nz
+std::mutex g_tune_mu;
+std::map<TuneKey, Tile> g_tune;
+
+std::string device_arch() {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string a = prop.gcnArchName;
+    const size_t colon = a.find(':');
+    return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
+bool file_lookup(const TuneKey& k, const std::string& arch, Tile* t) {
+    const char* path = std::getenv("ELWH_TUNE_CACHE");
+    if (!path) return false;
+    FILE* fp = std::fopen(path, "r");
+    if (!fp) return false;
+    char line[512], a[64];
+    bool found = false;
+    while (std::fgets(line, sizeof line, fp)) {
+        int dim, prec, comp, nx, ny, nz, V, rows;
+        double us;
+        if (std::sscanf(line, "{\"arch\": \"%63[^\"]\", \"dim\": %d, \"prec\": %d, \"comp\": %d, \"n\": [%d, %d, %d], "
+                              "\"V\": %d, \"rows\": %d, \"us\": %lf}",
+                        a, &dim, &prec, &comp, &nx, &ny, &nz, &V, &rows, &us) == 10 &&
+            arch == a && k == TuneKey(dim, prec, comp, nx, ny, nz)) {
+            t->V = V;
+            t->TY = rows;
+            found = true;
+        }
+    }
+    std::fclose(fp);
+    return found;
+}
+
+void file_store(const TuneKey& k, const std::string& arch, const Tile& t, double us) {
+    const char* path = std::getenv("ELWH_TUNE_CACHE");
+    if (!path) return;
+    FILE* fp = std::fopen(path, "a");
+    if (!fp) return;
+    std::fprintf(fp,
+                 "{\"arch\": \"%s\", \"dim\": %d, \"prec\": %d, \"comp\": %d, \"n\": [%d, %d, %d], \"V\": %d, "
+                 "\"rows\": %d, \"us\": %.3f}\n",
+                 arch.c_str(), std::get<0>(k), std::get<1>(k), std::get<2>(k), std::get<3>(k), std::get<4>(k),
+                 std::get<5>(k), t.V, t.TY, us);
+    std::fclose(fp);
+}
+}  // namespace
+
+extern "C" {
+
+elwh_status elwh_autotune(elwh_ctx* c, int prec, int reps, double* best_step_us) {
+    if (!c || reps < 1) return ELWH_ERR_ARG;
+    const bool fp32 = prec == ELWH_FP32_STEP;
+    if (fp32 && c->opts.prec != ELWH_FP32_STEP) {
+        c->err = "FP32 tiling needs an FP32 context";
+        return ELWH_ERR_ARG;
+    }
+    const int comp = fp32 ? (c->opts.compensated ? 1 : 0) : 0;
+    const TuneKey key(c->L.dim, fp32 ? 1 : 0, comp, c->L.nx, c->L.ny, c->L.nz);
+    Tile& dst = fp32 ? c->tile32 : c->tile64;
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            dst = it->second;
+            if (best_step_us) *best_step_us = -1.0;
+            return ELWH_OK;
+        }
+    }
+    const std::string arch = device_arch();
+    Tile ft;
+    if (file_lookup(key, arch, &ft)) {
+        dst = ft;
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        g_tune[key] = ft;
+        if (best_step_us) *best_step_us = -1.0;
+        return ELWH_OK;
+    }
+    std::vector<Tile> cands;
+    if (c->L.dim == 2) {
+        for (int V : {1, 2, 4})
+            for (int TY : {4, 8, 16})
+                if (tile_valid_2d(fp32, V, TY)) cands.push_back(Tile{V, TY});
+    } else {
+        for (int TZ : {4, 8, 16, 32}) cands.push_back(Tile{1, TZ});
+    }
+    double* in = c->vec[VT];
+    double* out = c->vec[VD];
+    HIPCK(hipMemsetAsync(in, 0, c->L.field_elems() * sizeof(double), c->stream));
+    hipEvent_t e0, e1;
+    HIPCK(hipEventCreate(&e0));
+    HIPCK(hipEventCreate(&e1));
+    const bool prof = c->prof_on;
+    c->prof_on = false;
+    const int napply = c->napply;
+    double best = 1e300;
+    Tile bt = dst;
+    for (const Tile& t : cands) {
+        dst = t;
+        apply_A(c, in, out, fp32);   // warm-up (first launch of this instantiation)
+        (void)hipEventRecord(e0, c->stream);
+        for (int r = 0; r < reps; ++r) apply_A(c, in, out, fp32);
+        (void)hipEventRecord(e1, c->stream);
+        if (hipEventSynchronize(e1) != hipSuccess) break;
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        const double us = 1e3 * ms / reps / (c->plan.nt * c->opts.periods);
+        if (us < best) {
+            best = us;
+            bt = t;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->prof_on = prof;
+    c->napply = napply;
+    dst = bt;
+    HIPCK(hipGetLastError());
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        g_tune[key] = bt;
+    }
+    file_store(key, arch, bt, best);
+    if (best_step_us) *best_step_us = best;
+    return ELWH_OK;
+}
+
+elwh_status elwh_get_tile(const elwh_ctx* c, int prec, int* vec, int* rows) {
+    if (!c || !vec || !rows) return ELWH_ERR_ARG;
+    const Tile& t = prec == ELWH_FP32_STEP ? c->tile32 : c->tile64;
+    *vec = t.V;
+    *rows = t.TY;
     return ELWH_OK;
 }
 

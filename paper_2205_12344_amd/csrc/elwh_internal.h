@@ -14,9 +14,10 @@ namespace elwh {
 
 // ---------------------------------------------------------------------------
 // Padded internal layout.  One component of a field is stored as
-// (nz+1) planes x (ny+1) rows x P elements, P = nx+1 rounded up to 64 so
-// every row starts 512-byte (FP64) / 256-byte (FP32) aligned.  2-D fields
-// have one plane.  Padding and Dirichlet nodes always hold zero.
+// (nz+1) planes x (ny+1) rows x P elements, P = nx+4 rounded up to 64 so
+// every row starts 512-byte (FP64) / 256-byte (FP32) aligned and a 4-wide
+// vector starting at any node stays in its row.  2-D fields have one plane.
+// Padding and Dirichlet nodes always hold zero.
 // ---------------------------------------------------------------------------
 struct Layout {
     int dim = 2;
@@ -47,6 +48,12 @@ struct March {
 
 // Device scalar slots used by the device-side CG updates.
 enum { S_RR = 0, S_PQ, S_RRNEW, S_ALPHA, S_BETA, S_BB, S_TMP, S_FLAG, S_NSLOT = 16 };
+
+// Tiling of the fused step kernels: V nodes per lane along x, TY rows (2-D)
+// or TZ planes (3-D) marched per wavefront.
+struct Tile {
+    int V = 1, TY = 8;
+};
 
 struct Plan {
     int nt = 0;
@@ -93,11 +100,15 @@ struct elwh_ctx {
     double* hscal = nullptr;       // pinned host mirror
     int red_blocks = 1024;
 
-    // kernel profiling: event pairs around each fused-step launch
+    // tiling of the fused step kernels (set by elwh_set_tile / elwh_autotune)
+    elwh::Tile tile64, tile32;
+
+    // kernel profiling: three events per filter application (start, after the
+    // half step, after the last step) on the context's stream
     bool prof_on = false;
     std::vector<hipEvent_t> prof_ev;   // pool, reused
-    std::vector<int> prof_kind;        // 0 = step, 1 = half step, per recorded pair
-    size_t prof_used = 0;              // pairs recorded since the last read
+    std::vector<int> prof_nsteps;      // step launches per recorded application
+    size_t prof_used = 0;              // applications recorded since the last read
 
     // CG state of the stepwise interface
     bool cg_active = false;
@@ -117,9 +128,12 @@ Layout make_layout(const elwh_grid* g);
 Stencil make_stencil(const elwh_grid* g);
 March make_march(const elwh_grid* g, const int bc[6]);
 
-// ---- profiling hooks (api.hip): bracket one fused-step launch --------------
-void prof_begin(elwh_ctx* c);
-void prof_end(elwh_ctx* c, int kind);
+// ---- profiling hooks (api.hip) ---------------------------------------------
+// phase 0: before the half step; 1: after it; 2: after the last step
+// (nsteps = number of step launches of this application).
+void prof_mark(elwh_ctx* c, int phase, int nsteps = 0);
+bool tile_valid_2d(bool fp32, int V, int TY);
+bool tile_valid_3d(bool fp32, int V, int TZ);
 
 // ---- kernels (kernels2d.hip / kernels3d.hip / blas.hip) --------------------
 // Copy a caller-layout field (ncomp components) into the padded layout,

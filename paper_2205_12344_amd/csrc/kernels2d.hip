@@ -4,22 +4,25 @@
 // leapfrog (Sec. 4.3, eq. elastic-time-explicit-corrected)
 //     u^{n+1} = 2 u^n - u^{n-1} + a (Ltilde u^n - f cos(omega t_n)),   a = c dt^2 / rho,
 // and adds w_{n+1} u^{n+1} into the FP64 filter accumulator (trapezoid rule
-// of eq. el_WHI_OP), in the same pass.  The initial launch computes the
+// of eq. el_WHI_OP) in the same pass.  The half-step launch computes the
 // even-in-time start u^1 = u^0 + (a/2)(Ltilde u^0 - f) and seeds the
 // accumulator with w_0 u^0 + w_1 u^1 (or x - w_0 u^0 - w_1 u^1 for A_h x).
 //
 // Ltilde is the conservative second-order stress divergence
 //     u-row: D+x(Abar D-x u) + D+y(mubar D-y u) + D0x(lam D0y v) + D0y(mu D0x v)
 //     v-row: D+x(mubar D-x v) + D+y(Abar D-y v) + D0x(mu D0y u) + D0y(lam D0x u)
-// (A = lam + 2 mu, bars = two-point means), with the traction-free rows of a
-// free y face closed from the discrete energy (one-sided normal
-// differences, trapezoid weight 1/2 divided out).
+// (A = lam + 2 mu, bars = two-point means), with the rows of a traction-free
+// y face closed from the discrete energy (one-sided normal differences, the
+// trapezoid weight 1/2 divided out).
 //
-// Mapping: one 64-lane wavefront per block owns 64 consecutive x nodes of
-// which lanes 1..62 are computed (lanes 0 and 63 are the x halo), and
-// marches up TY rows in y.  Rows j-1, j, j+1 live in registers and roll;
-// x neighbours come from the adjacent lanes by cross-lane moves, so every
-// array element is loaded by one lane of one wavefront per row visit.
+// Mapping.  One 64-lane wavefront per block; each lane owns V consecutive x
+// nodes (one vector load per array and row), so a wavefront covers 64 V
+// columns of which the outer halo columns are loaded but not computed
+// (W = 62, 126, 252 computed columns for V = 1, 2, 4).  The wavefront marches
+// TY rows up in y: rows j-1, j, j+1 live in registers and roll, the loads of
+// row j+2 and of the centre-row arrays of row j+1 are issued one iteration
+// ahead, and x neighbours across lanes come from DPP wavefront shifts.
+// Every array element is read from memory once per row visit.
 #include "elwh_internal.h"
 #include "lanes.h"
 
@@ -34,17 +37,62 @@ struct Args2D {
     int final_;
 };
 
-template <typename T>
-struct Row {
-    T u, v, uL, uR, vL, vR, lam, mu;
+template <typename T, int V>
+struct alignas(sizeof(T) * V) VecT {
+    T x[V];
 };
 
+template <typename S, typename T, int V>
+__device__ __forceinline__ void vload(const S* __restrict__ p, T (&o)[V]) {
+    const VecT<S, V> v = *reinterpret_cast<const VecT<S, V>*>(p);
+#pragma unroll
+    for (int k = 0; k < V; ++k) o[k] = (T)v.x[k];
+}
+
+template <typename T, int V>
+__device__ __forceinline__ void vzero(T (&o)[V]) {
+#pragma unroll
+    for (int k = 0; k < V; ++k) o[k] = (T)0;
+}
+
+template <typename T, int V>
+struct RawRow {
+    T u[V], v[V], l[V], m[V];
+};
+
+template <typename T, int V>
+struct Row {
+    T u[V], v[V], l[V], m[V];
+    T uL, uR, vL, vR;   // neighbours of node 0 (left) and node V-1 (right)
+};
+
+template <typename T, int V, bool COMP, bool FORCE, int MODE>
+struct Centre {
+    T a[V];
+    T up[V], vp[V];             // u^{n-1} (MODE 0)
+    double hu[V], hv[V];        // accumulator (MODE 0) or base x (MODE 1)
+    double lu[V], lv[V];        // compensation (MODE 0, COMP)
+    T fu[V], fv[V];             // forcing
+};
+
+// Stencil values of one node in one row.
 template <typename T>
-__device__ __forceinline__ void neighbours(Row<T>& r) {
-    r.uL = lane_from_left(r.u);
-    r.uR = lane_from_right(r.u);
-    r.vL = lane_from_left(r.v);
-    r.vR = lane_from_right(r.v);
+struct Nb {
+    T u, v, uL, uR, vL, vR, l, m;
+};
+
+template <typename T, int V>
+__device__ __forceinline__ Nb<T> node_of(const Row<T, V>& r, int k) {
+    Nb<T> n;
+    n.u = r.u[k];
+    n.v = r.v[k];
+    n.uL = k > 0 ? r.u[k > 0 ? k - 1 : 0] : r.uL;
+    n.uR = k < V - 1 ? r.u[k < V - 1 ? k + 1 : 0] : r.uR;
+    n.vL = k > 0 ? r.v[k > 0 ? k - 1 : 0] : r.vL;
+    n.vR = k < V - 1 ? r.v[k < V - 1 ? k + 1 : 0] : r.vR;
+    n.l = r.l[k];
+    n.m = r.m[k];
+    return n;
 }
 
 __device__ __forceinline__ void acc_add(double& hi, double& lo, double x, bool comp) {
@@ -60,144 +108,216 @@ __device__ __forceinline__ void acc_add(double& hi, double& lo, double x, bool c
     }
 }
 
-// MODE 0: time step; MODE 1: initial half step.
-// U: element type of the u^n input (double for the half step from an FP64
-// vector; T otherwise).
-template <typename T, typename U, int TY, int MODE, bool FORCE, bool COMP>
+// kind 0: interior row; 1: traction-free top row (S below); 2: traction-free bottom row (N above)
+template <typename T>
+__device__ __forceinline__ void stencil2d(int kind, const Nb<T>& S, const Nb<T>& C, const Nb<T>& N, T lamL, T lamR,
+                                          T muL, T muR, T cxx2, T cyy2, T cxy, T cyyf, T cfx, T& Lu, T& Lv) {
+    const T two = (T)2;
+    const T AL = lamL + two * muL, AC = C.l + two * C.m, AR = lamR + two * muR;
+    const T xu = cxx2 * ((AR + AC) * (C.uR - C.u) - (AC + AL) * (C.u - C.uL));
+    const T xv = cxx2 * ((muR + C.m) * (C.vR - C.v) - (C.m + muL) * (C.v - C.vL));
+    if (kind == 1) {
+        const T AS = S.l + two * S.m;
+        Lu = xu - cyyf * (C.m + S.m) * (C.u - S.u) - cfx * (C.m * (C.vR - C.vL) + S.m * (S.vR - S.vL)) +
+             cfx * (lamR * (C.vR - S.vR) - lamL * (C.vL - S.vL));
+        Lv = xv - cyyf * (AC + AS) * (C.v - S.v) - cfx * (C.l * (C.uR - C.uL) + S.l * (S.uR - S.uL)) +
+             cfx * (muR * (C.uR - S.uR) - muL * (C.uL - S.uL));
+    } else if (kind == 2) {
+        const T AN = N.l + two * N.m;
+        Lu = xu + cyyf * (C.m + N.m) * (N.u - C.u) + cfx * (C.m * (C.vR - C.vL) + N.m * (N.vR - N.vL)) +
+             cfx * (lamR * (N.vR - C.vR) - lamL * (N.vL - C.vL));
+        Lv = xv + cyyf * (AC + AN) * (N.v - C.v) + cfx * (C.l * (C.uR - C.uL) + N.l * (N.uR - N.uL)) +
+             cfx * (muR * (N.uR - C.uR) - muL * (N.uL - C.uL));
+    } else {
+        const T AN = N.l + two * N.m, AS = S.l + two * S.m;
+        Lu = xu + cyy2 * ((N.m + C.m) * (N.u - C.u) - (C.m + S.m) * (C.u - S.u)) +
+             cxy * (lamR * (N.vR - S.vR) - lamL * (N.vL - S.vL) + N.m * (N.vR - N.vL) - S.m * (S.vR - S.vL));
+        Lv = xv + cyy2 * ((AN + AC) * (N.v - C.v) - (AC + AS) * (C.v - S.v)) +
+             cxy * (muR * (N.uR - S.uR) - muL * (N.uL - S.uL) + N.l * (N.uR - N.uL) - S.l * (S.uR - S.uL));
+    }
+}
+
+template <int V>
+struct Cols {
+    static constexpr int W = V == 4 ? 252 : 64 * V - 2;   // computed columns per wavefront
+};
+
+// MODE 0: time step; MODE 1: initial half step.  U: element type of the
+// u^n input (double for the half step from an FP64 vector, T otherwise).
+template <typename T, typename U, int V, int TY, int MODE, bool FORCE, bool COMP>
 __global__ __launch_bounds__(64) void step2d_kernel(const U* __restrict__ u, const T* uprev, T* unext,
                                                    const double* __restrict__ xbase, T* __restrict__ u0out,
                                                    double* __restrict__ acc, double* __restrict__ acclo,
                                                    const T* __restrict__ ca, const T* __restrict__ cl,
-                                                   const T* __restrict__ cm, const T* __restrict__ f,
-                                                   Args2D A) {
+                                                   const T* __restrict__ cm, const T* __restrict__ f, Args2D A) {
+    constexpr int W = Cols<V>::W;
     const int lane = threadIdx.x;
-    const int i = 62 * blockIdx.x + lane;
-    const bool colv = i <= A.nx;
-    const bool store = lane >= 1 && lane <= 62 && i >= 1 && i <= A.nx - 1;
+    const int c0 = W * (int)blockIdx.x;
+    const int col = c0 + V * lane;                // first column of this lane
+    const bool colv = col <= A.nx;                // vector lies in the padded row
     const int j0 = A.jlo + (int)blockIdx.y * TY;
     if (j0 > A.jhi) return;
     const int j1 = min(j0 + TY - 1, A.jhi);
-    const int64_t P = A.P, CS = A.CS;
-
+    const int P = (int)A.P;
+    const int64_t CS = A.CS;
     const T cxx2 = (T)A.cxx2, cyy2 = (T)A.cyy2, cxy = (T)A.cxy, cyyf = (T)A.cyyf, cfx = (T)A.cfx;
     const T two = (T)2;
+    const int ilo = max(c0 + 1, 1), ihi = min(c0 + W, A.nx - 1);   // computed column range
 
-    auto load_row = [&](int j, Row<T>& r) {
+    auto load_raw = [&](int j, RawRow<T, V>& r) {
         if (colv && j >= 0 && j <= A.ny) {
-            const int64_t o = (int64_t)j * P + i;
-            r.u = (T)u[o];
-            r.v = (T)u[o + CS];
-            r.lam = cl[o];
-            r.mu = cm[o];
+            const int64_t o = (int64_t)j * P + col;
+            vload<U, T, V>(u + o, r.u);
+            vload<U, T, V>(u + o + CS, r.v);
+            vload<T, T, V>(cl + o, r.l);
+            vload<T, T, V>(cm + o, r.m);
         } else {
-            r.u = r.v = r.lam = r.mu = (T)0;
+            vzero<T, V>(r.u);
+            vzero<T, V>(r.v);
+            vzero<T, V>(r.l);
+            vzero<T, V>(r.m);
         }
-        neighbours(r);
+    };
+    auto finish = [&](const RawRow<T, V>& r, Row<T, V>& o) {
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            o.u[k] = r.u[k];
+            o.v[k] = r.v[k];
+            o.l[k] = r.l[k];
+            o.m[k] = r.m[k];
+        }
+        o.uL = lane_from_left(r.u[V - 1]);
+        o.uR = lane_from_right(r.u[0]);
+        o.vL = lane_from_left(r.v[V - 1]);
+        o.vR = lane_from_right(r.v[0]);
+    };
+    using Ctr = Centre<T, V, COMP, FORCE, MODE>;
+    auto load_ctr = [&](int j, Ctr& c) {
+        if (colv && j <= A.jhi) {
+            const int64_t o = (int64_t)j * P + col;
+            vload<T, T, V>(ca + o, c.a);
+            if constexpr (MODE == 0) {
+                vload<T, T, V>(uprev + o, c.up);
+                vload<T, T, V>(uprev + o + CS, c.vp);
+                vload<double, double, V>(acc + o, c.hu);
+                vload<double, double, V>(acc + o + CS, c.hv);
+                if constexpr (COMP) {
+                    vload<double, double, V>(acclo + o, c.lu);
+                    vload<double, double, V>(acclo + o + CS, c.lv);
+                }
+            } else {
+                if (xbase) {
+                    vload<double, double, V>(xbase + o, c.hu);
+                    vload<double, double, V>(xbase + o + CS, c.hv);
+                } else {
+                    vzero<double, V>(c.hu);
+                    vzero<double, V>(c.hv);
+                }
+            }
+            if constexpr (FORCE) {
+                vload<T, T, V>(f + o, c.fu);
+                vload<T, T, V>(f + o + CS, c.fv);
+            }
+        }
     };
 
-    Row<T> S, C, N;
-    load_row(j0 - 1, S);
-    load_row(j0, C);
+    Row<T, V> S, C, N;
+    {
+        RawRow<T, V> r;
+        load_raw(j0 - 1, r);
+        finish(r, S);
+        load_raw(j0, r);
+        finish(r, C);
+    }
+    RawRow<T, V> rawN;
+    load_raw(j0 + 1, rawN);
+    Ctr ctr;
+    load_ctr(j0, ctr);
 
     for (int j = j0; j <= j1; ++j) {
-        load_row(j + 1, N);
-        const T lamL = lane_from_left(C.lam), lamR = lane_from_right(C.lam);
-        const T muL = lane_from_left(C.mu), muR = lane_from_right(C.mu);
-        const int64_t o = (int64_t)j * P + i;
-
-        T Lu, Lv;
-        const T AL = lamL + two * muL, AC = C.lam + two * C.mu, AR = lamR + two * muR;
-        // in-row compact x terms (all row kinds)
-        const T xu = cxx2 * ((AR + AC) * (C.uR - C.u) - (AC + AL) * (C.u - C.uL));
-        const T xv = cxx2 * ((muR + C.mu) * (C.vR - C.v) - (C.mu + muL) * (C.v - C.vL));
-        if (A.free_hi && j == A.ny) {
-            // traction-free top row: S is the row below
-            const T AS = S.lam + two * S.mu;
-            Lu = xu - cyyf * (C.mu + S.mu) * (C.u - S.u) -
-                 cfx * (C.mu * (C.vR - C.vL) + S.mu * (S.vR - S.vL)) +
-                 cfx * (lamR * (C.vR - S.vR) - lamL * (C.vL - S.vL));
-            Lv = xv - cyyf * (AC + AS) * (C.v - S.v) -
-                 cfx * (C.lam * (C.uR - C.uL) + S.lam * (S.uR - S.uL)) +
-                 cfx * (muR * (C.uR - S.uR) - muL * (C.uL - S.uL));
-        } else if (A.free_lo && j == 0) {
-            // traction-free bottom row: N is the row above
-            const T AN = N.lam + two * N.mu;
-            Lu = xu + cyyf * (C.mu + N.mu) * (N.u - C.u) +
-                 cfx * (C.mu * (C.vR - C.vL) + N.mu * (N.vR - N.vL)) +
-                 cfx * (lamR * (N.vR - C.vR) - lamL * (N.vL - C.vL));
-            Lv = xv + cyyf * (AC + AN) * (N.v - C.v) +
-                 cfx * (C.lam * (C.uR - C.uL) + N.lam * (N.uR - N.uL)) +
-                 cfx * (muR * (N.uR - C.uR) - muL * (N.uL - C.uL));
-        } else {
-            const T AN = N.lam + two * N.mu, AS = S.lam + two * S.mu;
-            Lu = xu + cyy2 * ((N.mu + C.mu) * (N.u - C.u) - (C.mu + S.mu) * (C.u - S.u)) +
-                 cxy * (lamR * (N.vR - S.vR) - lamL * (N.vL - S.vL) + N.mu * (N.vR - N.vL) -
-                        S.mu * (S.vR - S.vL));
-            Lv = xv + cyy2 * ((AN + AC) * (N.v - C.v) - (AC + AS) * (C.v - S.v)) +
-                 cxy * (muR * (N.uR - S.uR) - muL * (N.uL - S.uL) + N.lam * (N.uR - N.uL) -
-                        S.lam * (S.uR - S.uL));
+        // issue the loads of the next iteration before computing this one
+        RawRow<T, V> rawNN;
+        Ctr ctrN;
+        if (j + 1 <= j1) {
+            load_raw(j + 2, rawNN);
+            load_ctr(j + 1, ctrN);
         }
+        finish(rawN, N);
+        const T lamL0 = lane_from_left(C.l[V - 1]), lamR0 = lane_from_right(C.l[0]);
+        const T muL0 = lane_from_left(C.m[V - 1]), muR0 = lane_from_right(C.m[0]);
+        const int kind = (A.free_hi && j == A.ny) ? 1 : ((A.free_lo && j == 0) ? 2 : 0);
+        const int64_t o = (int64_t)j * P + col;
 
-        if (store) {
-            const T a = ca[o];
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            const int i = col + k;
+            if (i < ilo || i > ihi || !colv) continue;
+            const Nb<T> s = node_of<T, V>(S, k), cc = node_of<T, V>(C, k), nn = node_of<T, V>(N, k);
+            const T lamL = k > 0 ? C.l[k > 0 ? k - 1 : 0] : lamL0;
+            const T lamR = k < V - 1 ? C.l[k < V - 1 ? k + 1 : 0] : lamR0;
+            const T muL = k > 0 ? C.m[k > 0 ? k - 1 : 0] : muL0;
+            const T muR = k < V - 1 ? C.m[k < V - 1 ? k + 1 : 0] : muR0;
+            T Lu, Lv;
+            stencil2d<T>(kind, s, cc, nn, lamL, lamR, muL, muR, cxx2, cyy2, cxy, cyyf, cfx, Lu, Lv);
             if constexpr (FORCE) {
                 const T fc = (T)A.fc;
-                Lu -= fc * f[o];
-                Lv -= fc * f[o + CS];
+                Lu -= fc * ctr.fu[k];
+                Lv -= fc * ctr.fv[k];
             }
+            const T a = ctr.a[k];
             T nu, nv;
-            double hu, hv, lu = 0.0, lv = 0.0;
+            double hu = ctr.hu[k], hv = ctr.hv[k], lu = 0.0, lv = 0.0;
             if constexpr (MODE == 0) {
-                nu = two * C.u - uprev[o] + a * Lu;
-                nv = two * C.v - uprev[o + CS] + a * Lv;
-                hu = acc[o];
-                hv = acc[o + CS];
+                nu = two * cc.u - ctr.up[k] + a * Lu;
+                nv = two * cc.v - ctr.vp[k] + a * Lv;
                 if constexpr (COMP) {
-                    lu = acclo[o];
-                    lv = acclo[o + CS];
+                    lu = ctr.lu[k];
+                    lv = ctr.lv[k];
                 }
             } else {
                 const T ha = (T)0.5 * a;
-                nu = C.u + ha * Lu;
-                nv = C.v + ha * Lv;
-                hu = xbase ? xbase[o] : 0.0;
-                hv = xbase ? xbase[o + CS] : 0.0;
-                acc_add(hu, lu, A.w0 * (double)C.u, COMP);
-                acc_add(hv, lv, A.w0 * (double)C.v, COMP);
+                nu = cc.u + ha * Lu;
+                nv = cc.v + ha * Lv;
+                acc_add(hu, lu, A.w0 * (double)cc.u, COMP);
+                acc_add(hv, lv, A.w0 * (double)cc.v, COMP);
                 if (u0out) {
-                    u0out[o] = C.u;
-                    u0out[o + CS] = C.v;
+                    u0out[o + k] = cc.u;
+                    u0out[o + k + CS] = cc.v;
                 }
             }
-            unext[o] = nu;
-            unext[o + CS] = nv;
+            unext[o + k] = nu;
+            unext[o + k + CS] = nv;
             acc_add(hu, lu, A.w * (double)nu, COMP);
             acc_add(hv, lv, A.w * (double)nv, COMP);
             if (COMP && A.final_) {
-                acc[o] = hu + lu;
-                acc[o + CS] = hv + lv;
+                acc[o + k] = hu + lu;
+                acc[o + k + CS] = hv + lv;
             } else {
-                acc[o] = hu;
-                acc[o + CS] = hv;
+                acc[o + k] = hu;
+                acc[o + k + CS] = hv;
                 if constexpr (COMP) {
-                    acclo[o] = lu;
-                    acclo[o + CS] = lv;
+                    acclo[o + k] = lu;
+                    acclo[o + k + CS] = lv;
                 }
             }
         }
         S = C;
         C = N;
+        if (j + 1 <= j1) {
+            rawN = rawNN;
+            ctr = ctrN;
+        }
     }
 }
 
 // ---------------------------------------------------------------------------
 
-template <typename T, typename U, int TY, int MODE>
+template <typename T, typename U, int V, int TY, int MODE>
 static void launch_t(bool force, bool comp, dim3 grid, hipStream_t s, const U* u, const T* uprev, T* unext,
                      const double* xbase, T* u0out, double* acc, double* acclo, const T* ca, const T* cl,
                      const T* cm, const T* f, const Args2D& A) {
-#define ELWH_L2(F, CMP)                                                                           \
-    hipLaunchKernelGGL((step2d_kernel<T, U, TY, MODE, F, CMP>), grid, dim3(64), 0, s, u, uprev, unext, \
+#define ELWH_L2(F, CMP)                                                                                  \
+    hipLaunchKernelGGL((step2d_kernel<T, U, V, TY, MODE, F, CMP>), grid, dim3(64), 0, s, u, uprev, unext, \
                        xbase, u0out, acc, acclo, ca, cl, cm, f, A)
     if (force) {
         if (comp) ELWH_L2(true, true); else ELWH_L2(true, false);
@@ -207,14 +327,33 @@ static void launch_t(bool force, bool comp, dim3 grid, hipStream_t s, const U* u
 #undef ELWH_L2
 }
 
-struct Sweep2D {
-    dim3 grid;
-    Args2D A;
-};
+// Dispatch over the tunable (V, TY) pairs.
+template <typename T, typename U, int MODE>
+static void launch_v(int V, int TY, bool force, bool comp, int nx, int nrows, hipStream_t s, const U* u,
+                     const T* uprev, T* unext, const double* xbase, T* u0out, double* acc, double* acclo,
+                     const T* ca, const T* cl, const T* cm, const T* f, const Args2D& A) {
+    auto grid_for = [&](int W, int ty) {
+        return dim3((unsigned)((nx - 1 + W - 1) / W), (unsigned)((nrows + ty - 1) / ty), 1);
+    };
+#define ELWH_CASE(VV, TT)                                                                                \
+    if (V == VV && TY == TT) {                                                                           \
+        launch_t<T, U, VV, TT, MODE>(force, comp, grid_for(Cols<VV>::W, TT), s, u, uprev, unext, xbase, u0out, \
+                                     acc, acclo, ca, cl, cm, f, A);                                      \
+        return;                                                                                          \
+    }
+    ELWH_CASE(1, 4) ELWH_CASE(1, 8) ELWH_CASE(1, 16)
+    ELWH_CASE(2, 4) ELWH_CASE(2, 8) ELWH_CASE(2, 16)
+    if constexpr (sizeof(T) == 4) {
+        ELWH_CASE(4, 4) ELWH_CASE(4, 8) ELWH_CASE(4, 16)
+    }
+#undef ELWH_CASE
+    // unreachable for validated tiles; fall back to the smallest tile
+    launch_t<T, U, 1, 8, MODE>(force, comp, grid_for(Cols<1>::W, 8), s, u, uprev, unext, xbase, u0out, acc, acclo,
+                               ca, cl, cm, f, A);
+}
 
-static Sweep2D setup2d(const elwh_ctx* c, int ty) {
-    Sweep2D s;
-    Args2D& A = s.A;
+static Args2D args2d(const elwh_ctx* c) {
+    Args2D A;
     A.nx = c->L.nx;
     A.ny = c->L.ny;
     A.P = c->L.P;
@@ -230,18 +369,20 @@ static Sweep2D setup2d(const elwh_ctx* c, int ty) {
     A.cfx = c->st.cfxy;
     A.w = A.w0 = A.fc = 0;
     A.final_ = 0;
-    const int nrows = A.jhi - A.jlo + 1;
-    s.grid = dim3((unsigned)((A.nx - 1 + 61) / 62), (unsigned)((nrows + ty - 1) / ty), 1);
-    return s;
+    return A;
 }
 
-constexpr int TY2 = 16;
+bool tile_valid_2d(bool fp32, int V, int TY) {
+    const bool v_ok = V == 1 || V == 2 || (fp32 && V == 4);
+    return v_ok && (TY == 4 || TY == 8 || TY == 16);
+}
 
 // One filter application (2-D), see elwh_internal.h.
 void run_filter_2d(elwh_ctx* c, const double* x, bool with_force, bool amode, bool fp32, double* out) {
     hipStream_t s = c->stream;
-    Sweep2D sw = setup2d(c, TY2);
-    Args2D& A = sw.A;
+    Args2D A = args2d(c);
+    const int nrows = A.jhi - A.jlo + 1;
+    const Tile t = fp32 ? c->tile32 : c->tile64;
     const int nsteps = c->plan.nt * c->opts.periods;
     const double sgn = amode ? -1.0 : 1.0;
     const bool comp = fp32 && c->opts.compensated;
@@ -250,12 +391,12 @@ void run_filter_2d(elwh_ctx* c, const double* x, bool with_force, bool amode, bo
     A.w0 = sgn * c->w[0];
     A.w = sgn * c->w[1];
     A.fc = c->cosn[0];
+    prof_mark(c, 0);
     if (!fp32) {
         double *b0 = c->s64[0], *b1 = c->s64[1];
-        prof_begin(c);
-        launch_t<double, double, TY2, 1>(with_force, false, sw.grid, s, x, nullptr, b1, amode ? x : nullptr,
-                                         nullptr, acc, lo, c->ca, c->cl, c->cm, c->f64, A);
-        prof_end(c, 1);
+        launch_v<double, double, 1>(t.V, t.TY, with_force, false, A.nx, nrows, s, x, nullptr, b1,
+                                    amode ? x : nullptr, nullptr, acc, lo, c->ca, c->cl, c->cm, c->f64, A);
+        prof_mark(c, 1);
         // step 1 reads u^0 from x itself and writes u^2 into b0; from step 2
         // on u^{n+1} overwrites u^{n-1} in place
         const double* prev = x;
@@ -264,34 +405,30 @@ void run_filter_2d(elwh_ctx* c, const double* x, bool with_force, bool amode, bo
             double* nxt = (n == 1) ? b0 : const_cast<double*>(prev);
             A.w = sgn * c->w[n + 1];
             A.fc = c->cosn[n];
-            prof_begin(c);
-            launch_t<double, double, TY2, 0>(with_force, false, sw.grid, s, cur, prev, nxt, nullptr, nullptr,
-                                             acc, lo, c->ca, c->cl, c->cm, c->f64, A);
-            prof_end(c, 0);
+            launch_v<double, double, 0>(t.V, t.TY, with_force, false, A.nx, nrows, s, cur, prev, nxt, nullptr,
+                                        nullptr, acc, lo, c->ca, c->cl, c->cm, c->f64, A);
             prev = cur;
             cur = nxt;
         }
     } else {
         float *b0 = c->s32[0], *b1 = c->s32[1];
-        prof_begin(c);
-        launch_t<float, double, TY2, 1>(with_force, comp, sw.grid, s, x, nullptr, b1, amode ? x : nullptr, b0,
-                                        acc, lo, c->fa, c->fl, c->fm, c->f32, A);
-        prof_end(c, 1);
+        launch_v<float, double, 1>(t.V, t.TY, with_force, comp, A.nx, nrows, s, x, nullptr, b1,
+                                   amode ? x : nullptr, b0, acc, lo, c->fa, c->fl, c->fm, c->f32, A);
+        prof_mark(c, 1);
         float* prev = b0;
         float* cur = b1;
         for (int n = 1; n < nsteps; ++n) {
             A.w = sgn * c->w[n + 1];
             A.fc = c->cosn[n];
             A.final_ = (n == nsteps - 1);
-            prof_begin(c);
-            launch_t<float, float, TY2, 0>(with_force, comp, sw.grid, s, cur, prev, prev, nullptr, nullptr, acc,
-                                           lo, c->fa, c->fl, c->fm, c->f32, A);
-            prof_end(c, 0);
-            float* t = prev;
+            launch_v<float, float, 0>(t.V, t.TY, with_force, comp, A.nx, nrows, s, cur, prev, prev, nullptr,
+                                      nullptr, acc, lo, c->fa, c->fl, c->fm, c->f32, A);
+            float* tmp = prev;
             prev = cur;
-            cur = t;
+            cur = tmp;
         }
     }
+    prof_mark(c, 2, nsteps - 1);
 }
 
 }  // namespace elwh

@@ -34,6 +34,14 @@ struct Plane {
     T lam, mu;           // row j
 };
 
+template <typename T, bool COMP, bool FORCE, int MODE>
+struct Centre3 {
+    T a, lam_m, lam_p, mu_m, mu_p;   // a; lambda, mu at rows j-1, j+1 of the plane
+    T up[3];
+    double h[3], l[3];
+    T f[3];
+};
+
 __device__ __forceinline__ void acc_add3(double& hi, double& lo, double x, bool comp) {
     if (comp) {
         const double t = hi + x;
@@ -85,23 +93,48 @@ __global__ __launch_bounds__(64) void step3d_kernel(const U* __restrict__ u, con
             q.lam = q.mu = (T)0;
         }
     };
+    using Ctr = Centre3<T, COMP, FORCE, MODE>;
+    auto load_ctr = [&](int k, Ctr& c) {
+        if (colv && k <= A.khi) {
+            const int64_t o = (int64_t)k * PS + (int64_t)j * P + i;
+            c.a = ca[o];
+            c.lam_m = cl[o - P];
+            c.lam_p = cl[o + P];
+            c.mu_m = cm[o - P];
+            c.mu_p = cm[o + P];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                if constexpr (MODE == 0) {
+                    c.up[q] = uprev[o + q * CS];
+                    c.h[q] = acc[o + q * CS];
+                    if constexpr (COMP) c.l[q] = acclo[o + q * CS];
+                } else {
+                    c.h[q] = xbase ? xbase[o + q * CS] : 0.0;
+                }
+                if constexpr (FORCE) c.f[q] = f[o + q * CS];
+            }
+        } else {
+            c.a = c.lam_m = c.lam_p = c.mu_m = c.mu_p = (T)0;
+        }
+    };
 
     Plane<T> D, C, Up;
     load_plane(k0 - 1, D);
     load_plane(k0, C);
+    load_plane(k0 + 1, Up);
+    Ctr ctr;
+    load_ctr(k0, ctr);
 
     for (int k = k0; k <= k1; ++k) {
-        load_plane(k + 1, Up);
-        const int64_t o = (int64_t)k * PS + (int64_t)j * P + i;
-        T lam_m, lam_p, mu_m, mu_p;
-        if (colv) {
-            lam_m = cl[o - P];
-            lam_p = cl[o + P];
-            mu_m = cm[o - P];
-            mu_p = cm[o + P];
-        } else {
-            lam_m = lam_p = mu_m = mu_p = (T)0;
+        // issue the loads of the next plane before computing this one
+        Plane<T> Up2;
+        Ctr ctrN;
+        if (k + 1 <= k1) {
+            load_plane(k + 2, Up2);
+            load_ctr(k + 1, ctrN);
         }
+        const int64_t o = (int64_t)k * PS + (int64_t)j * P + i;
+        const T lam_m = ctr.lam_m, lam_p = ctr.lam_p, mu_m = ctr.mu_m, mu_p = ctr.mu_p;
         // x neighbours by lane moves (all lanes take part)
         const T lamL = lane_from_left(C.lam), lamR = lane_from_right(C.lam);
         const T muL = lane_from_left(C.mu), muR = lane_from_right(C.mu);
@@ -167,12 +200,12 @@ __global__ __launch_bounds__(64) void step3d_kernel(const U* __restrict__ u, con
         }
 
         if (store) {
-            const T a = ca[o];
+            const T a = ctr.a;
             if constexpr (FORCE) {
                 const T fc = (T)A.fc;
-                Lu -= fc * f[o];
-                Lv -= fc * f[o + CS];
-                Lw -= fc * f[o + 2 * CS];
+                Lu -= fc * ctr.f[0];
+                Lv -= fc * ctr.f[1];
+                Lw -= fc * ctr.f[2];
             }
             const T Ls[3] = {Lu, Lv, Lw};
             const T cs[3] = {uc, vc, wc};
@@ -180,14 +213,12 @@ __global__ __launch_bounds__(64) void step3d_kernel(const U* __restrict__ u, con
             for (int q = 0; q < 3; ++q) {
                 const int64_t oq = o + q * CS;
                 T nq;
-                double hq, lq = 0.0;
+                double hq = ctr.h[q], lq = 0.0;
                 if constexpr (MODE == 0) {
-                    nq = two * cs[q] - uprev[oq] + a * Ls[q];
-                    hq = acc[oq];
-                    if constexpr (COMP) lq = acclo[oq];
+                    nq = two * cs[q] - ctr.up[q] + a * Ls[q];
+                    if constexpr (COMP) lq = ctr.l[q];
                 } else {
                     nq = cs[q] + (T)0.5 * a * Ls[q];
-                    hq = xbase ? xbase[oq] : 0.0;
                     acc_add3(hq, lq, A.w0 * (double)cs[q], COMP);
                     if (u0out) u0out[oq] = cs[q];
                 }
@@ -203,6 +234,10 @@ __global__ __launch_bounds__(64) void step3d_kernel(const U* __restrict__ u, con
         }
         D = C;
         C = Up;
+        if (k + 1 <= k1) {
+            Up = Up2;
+            ctr = ctrN;
+        }
     }
 }
 
@@ -221,7 +256,29 @@ static void launch3_t(bool force, bool comp, dim3 grid, hipStream_t s, const U* 
 #undef ELWH_L3
 }
 
-constexpr int TZ3 = 16;
+bool tile_valid_3d(bool fp32, int V, int TZ) {
+    (void)fp32;
+    return V == 1 && (TZ == 4 || TZ == 8 || TZ == 16 || TZ == 32);
+}
+
+template <typename T, typename U, int MODE>
+static void launch3_z(int TZ, bool force, bool comp, const Args3D& A, hipStream_t s, const U* u, const T* uprev,
+                      T* unext, const double* xbase, T* u0out, double* acc, double* acclo, const T* ca, const T* cl,
+                      const T* cm, const T* f) {
+    const int nplanes = A.khi - A.klo + 1;
+    auto grid = [&](int tz) {
+        return dim3((unsigned)((A.nx - 1 + 61) / 62), (unsigned)(A.ny - 1), (unsigned)((nplanes + tz - 1) / tz));
+    };
+#define ELWH_Z(TT)                                                                                              \
+    if (TZ == TT) {                                                                                             \
+        launch3_t<T, U, TT, MODE>(force, comp, grid(TT), s, u, uprev, unext, xbase, u0out, acc, acclo, ca, cl, cm, \
+                                  f, A);                                                                        \
+        return;                                                                                                 \
+    }
+    ELWH_Z(4) ELWH_Z(8) ELWH_Z(16) ELWH_Z(32)
+#undef ELWH_Z
+    launch3_t<T, U, 16, MODE>(force, comp, grid(16), s, u, uprev, unext, xbase, u0out, acc, acclo, ca, cl, cm, f, A);
+}
 
 void run_filter_3d(elwh_ctx* c, const double* x, bool with_force, bool amode, bool fp32, double* out) {
     hipStream_t s = c->stream;
@@ -246,8 +303,7 @@ void run_filter_3d(elwh_ctx* c, const double* x, bool with_force, bool amode, bo
     A.cfxz = c->st.cfxz;
     A.cfyz = c->st.cfyz;
     A.final_ = 0;
-    const int nplanes = A.khi - A.klo + 1;
-    dim3 grid((unsigned)((A.nx - 1 + 61) / 62), (unsigned)(A.ny - 1), (unsigned)((nplanes + TZ3 - 1) / TZ3));
+    const int TZ = fp32 ? c->tile32.TY : c->tile64.TY;
     const int nsteps = c->plan.nt * c->opts.periods;
     const double sgn = amode ? -1.0 : 1.0;
     const bool comp = fp32 && c->opts.compensated;
@@ -258,44 +314,41 @@ void run_filter_3d(elwh_ctx* c, const double* x, bool with_force, bool amode, bo
     A.fc = c->cosn[0];
     if (!fp32) {
         double *b0 = c->s64[0], *b1 = c->s64[1];
-        prof_begin(c);
-        launch3_t<double, double, TZ3, 1>(with_force, false, grid, s, x, nullptr, b1, amode ? x : nullptr, nullptr,
-                                          acc, lo, c->ca, c->cl, c->cm, c->f64, A);
-        prof_end(c, 1);
+        prof_mark(c, 0);
+        launch3_z<double, double, 1>(TZ, with_force, false, A, s, x, nullptr, b1, amode ? x : nullptr, nullptr, acc,
+                                     lo, c->ca, c->cl, c->cm, c->f64);
+        prof_mark(c, 1);
         const double* prev = x;
         double* cur = b1;
         for (int n = 1; n < nsteps; ++n) {
             double* nxt = (n == 1) ? b0 : const_cast<double*>(prev);
             A.w = sgn * c->w[n + 1];
             A.fc = c->cosn[n];
-            prof_begin(c);
-            launch3_t<double, double, TZ3, 0>(with_force, false, grid, s, cur, prev, nxt, nullptr, nullptr, acc,
-                                              lo, c->ca, c->cl, c->cm, c->f64, A);
-            prof_end(c, 0);
+            launch3_z<double, double, 0>(TZ, with_force, false, A, s, cur, prev, nxt, nullptr, nullptr, acc, lo,
+                                         c->ca, c->cl, c->cm, c->f64);
             prev = cur;
             cur = nxt;
         }
     } else {
         float *b0 = c->s32[0], *b1 = c->s32[1];
-        prof_begin(c);
-        launch3_t<float, double, TZ3, 1>(with_force, comp, grid, s, x, nullptr, b1, amode ? x : nullptr, b0, acc,
-                                         lo, c->fa, c->fl, c->fm, c->f32, A);
-        prof_end(c, 1);
+        prof_mark(c, 0);
+        launch3_z<float, double, 1>(TZ, with_force, comp, A, s, x, nullptr, b1, amode ? x : nullptr, b0, acc, lo,
+                                    c->fa, c->fl, c->fm, c->f32);
+        prof_mark(c, 1);
         float* prev = b0;
         float* cur = b1;
         for (int n = 1; n < nsteps; ++n) {
             A.w = sgn * c->w[n + 1];
             A.fc = c->cosn[n];
             A.final_ = (n == nsteps - 1);
-            prof_begin(c);
-            launch3_t<float, float, TZ3, 0>(with_force, comp, grid, s, cur, prev, prev, nullptr, nullptr, acc, lo,
-                                            c->fa, c->fl, c->fm, c->f32, A);
-            prof_end(c, 0);
+            launch3_z<float, float, 0>(TZ, with_force, comp, A, s, cur, prev, prev, nullptr, nullptr, acc, lo,
+                                       c->fa, c->fl, c->fm, c->f32);
             float* t = prev;
             prev = cur;
             cur = t;
         }
     }
+    prof_mark(c, 2, nsteps - 1);
 }
 
 }  // namespace elwh

@@ -15,6 +15,7 @@
 // form of the conservative stencil; rows near a face enumerate the energy
 // terms that touch them.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <thread>
@@ -345,7 +346,9 @@ Layout make_layout(const elwh_grid* g) {
     L.nx = g->n[0];
     L.ny = g->n[1];
     L.nz = g->dim == 3 ? g->n[2] : 0;
-    L.P = ((int64_t)(L.nx + 1) + 63) / 64 * 64;
+    // at least 3 padding elements, so a 4-wide vector starting at any node
+    // column stays inside its row
+    L.P = ((int64_t)(L.nx + 4) + 63) / 64 * 64;
     L.PS = (int64_t)(L.ny + 1) * L.P;
     L.CS = L.PS * (L.dim == 3 ? (L.nz + 1) : 1);
     return L;

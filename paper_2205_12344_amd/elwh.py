@@ -27,6 +27,7 @@ EXPORTED = [
     "elwh_default_opts", "elwh_plan", "elwh_create", "elwh_destroy", "elwh_query", "elwh_last_error",
     "elwh_apply_filter", "elwh_apply_A", "elwh_solve", "elwh_cg_begin", "elwh_cg_iterate",
     "elwh_cg_result", "elwh_dot_M", "elwh_profile_enable", "elwh_profile_read",
+    "elwh_set_tile", "elwh_get_tile", "elwh_autotune",
 ]
 
 
@@ -38,7 +39,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("cfl", ctypes.c_double), ("nt", ctypes.c_int), ("periods", ctypes.c_int),
                 ("prec", ctypes.c_int), ("krylov", ctypes.c_int), ("gmres_m", ctypes.c_int),
                 ("scheme", ctypes.c_int), ("compensated", ctypes.c_int), ("inner_tol", ctypes.c_double),
-                ("max_outer", ctypes.c_int), ("stream", ctypes.c_void_p)]
+                ("max_outer", ctypes.c_int), ("stream", ctypes.c_void_p), ("autotune", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -81,6 +82,9 @@ def _load():
     lib.elwh_cg_iterate.argtypes = [P, I, D, ctypes.POINTER(D)]
     lib.elwh_cg_result.argtypes = [P, P, ctypes.POINTER(Info)]
     lib.elwh_dot_M.argtypes = [P, P, P, ctypes.POINTER(D)]
+    lib.elwh_set_tile.argtypes = [P, I, I, I]
+    lib.elwh_get_tile.argtypes = [P, I, ctypes.POINTER(I), ctypes.POINTER(I)]
+    lib.elwh_autotune.argtypes = [P, I, I, ctypes.POINTER(D)]
     lib.elwh_profile_enable.argtypes = [P, I]
     lib.elwh_profile_read.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(I), ctypes.POINTER(D),
                                       ctypes.POINTER(I)]
@@ -241,6 +245,19 @@ class Context:
         r = ctypes.c_double()
         self._check(lib.elwh_cg_iterate(self._h, int(k), float(tol), ctypes.byref(r)))
         return r.value
+
+    def set_tile(self, prec, vec, rows):
+        self._check(lib.elwh_set_tile(self._h, int(prec), int(vec), int(rows)))
+
+    def get_tile(self, prec):
+        v, r = ctypes.c_int(), ctypes.c_int()
+        self._check(lib.elwh_get_tile(self._h, int(prec), ctypes.byref(v), ctypes.byref(r)))
+        return v.value, r.value
+
+    def autotune(self, prec, reps=2):
+        us = ctypes.c_double()
+        self._check(lib.elwh_autotune(self._h, int(prec), int(reps), ctypes.byref(us)))
+        return us.value
 
     def profile_enable(self, on=True):
         self._check(lib.elwh_profile_enable(self._h, 1 if on else 0))

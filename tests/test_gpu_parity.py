@@ -330,3 +330,55 @@ def test_config3_full_size_fixed_point():
     nt = ctx32.info()["nt"]
     _say("config3 fp32 fixed point err", err32, "bound", fp32_bound(nt))
     assert err32 <= fp32_bound(nt)
+
+
+# ------------------------------------------------------------- tilings --------
+
+def _tiles(dim, fp32):
+    if dim == 2:
+        vs = (1, 2, 4) if fp32 else (1, 2)
+        return [(v, ty) for v in vs for ty in (4, 8, 16)]
+    return [(1, tz) for tz in (4, 8, 16, 32)]
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_every_tiling_matches_oracle(E, dim, prec):
+    """Every supported (nodes per lane, rows per wavefront) tiling of the
+    fused step gives the oracle's result; grids ragged for every tiling."""
+    if dim == 2:
+        n, bc = (257, 45), (0, 0, 0, 1)
+    else:
+        n, bc = (67, 7, 41), (0, 0, 0, 0, 1, 1)
+    shape = tuple(n[a] + 1 for a in reversed(range(dim)))
+    rho, lam, mu = _media(shape, 90 + dim)
+    om = 8.1
+    prob, op, wh = _oracle(dim, n, None, bc, rho, lam, mu, om)
+    rng = np.random.default_rng(14)
+    u0 = rng.standard_normal(prob.field_shape) * prob.unknown_mask()
+    f = rng.standard_normal(prob.field_shape) * prob.unknown_mask()
+    ref = prob.scatter(wh.apply_filter(prob.gather(u0), prob.gather(f)))
+    ctx = E.Context(dim, n, rho, lam, mu, om, bc, prec=prec, autotune=0)
+    tol = FP64_TOL if prec == 0 else fp32_bound(wh.nt)
+    outs = []
+    for v, rows in _tiles(dim, prec == 1):
+        ctx.set_tile(prec, v, rows)
+        got = ctx.apply_filter(u0, f).cpu().numpy()
+        err = _rel(got, ref)
+        _say("tile", dim, prec, v, rows, err)
+        assert err <= tol
+        outs.append(got)
+    # tilings differ only in how the compiler contracts multiply-adds
+    for o in outs[1:]:
+        assert _rel(o, outs[0]) <= (FP64_TOL if prec == 0 else 2 * fp32_bound(wh.nt))
+    with pytest.raises(E.ElwhError, match="ERR_ARG"):
+        ctx.set_tile(prec, 3, 8)
+
+
+def test_autotune_choice_is_valid_and_cached(E):
+    c = inputs.config1()
+    ctx = E.context_from_case(c, prec=E.FP32_STEP)
+    v64, r64 = ctx.get_tile(0)
+    v32, r32 = ctx.get_tile(1)
+    assert (v64, r64) in _tiles(2, False) and (v32, r32) in _tiles(2, True)
+    assert ctx.autotune(0) == -1.0          # cached per process
