@@ -58,18 +58,21 @@ def unknown_nodes(case):
     return cnt
 
 
-def read_traffic(kernel_tag):
+def read_traffic(kernel_tag, tile):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    one exists for this kernel and workload (else None)."""
+    one exists for this kernel, workload and tiling and the kernel sources
+    have not changed since (else None)."""
     path = os.path.join(ROOT, "profiles", f"{kernel_tag}_counters.txt")
     if not os.path.exists(path):
         return None
     vals = {}
     for line in open(path):
-        m = re.match(r"\s*(traffic_bytes_per_launch|kernel_source_hash)\s*[:=]\s*(\S+)", line)
+        m = re.match(r"\s*(traffic_bytes_per_launch|kernel_source_hash|tile)\s*[:=]\s*(\S+)", line)
         if m:
             vals[m.group(1)] = m.group(2)
     if "traffic_bytes_per_launch" not in vals:
+        return None
+    if vals.get("tile") != f"{tile[0]},{tile[1]}":
         return None
     src_hash = vals.get("kernel_source_hash")
     if src_hash and src_hash != kernel_source_hash():
@@ -144,6 +147,27 @@ def cpu_baseline(case, budget_s=12.0):
                       f"workload, {el:.1f} s; operator assembly {t_setup:.1f} s excluded"}
 
 
+def counters_pass(tile):
+    """Dispatches for the HBM-traffic counters: a plain copy of 256 MiB (the
+    scale reference: 262144 KiB read, 262144 KiB written) and three A_h
+    applications of the benchmark workload with a fixed tiling."""
+    import torch
+    from paper_2205_12344_amd import elwh, inputs
+    v, ty = (int(t) for t in tile.split(","))
+    x = torch.ones(2 ** 25, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    case = inputs.config2()
+    ctx = elwh.context_from_case(case, autotune=0)
+    ctx.set_tile(elwh.FP64, v, ty)
+    z = torch.zeros(ctx.field_shape, dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        ctx.apply_A(z)
+    torch.cuda.synchronize()
+    log(f"counters pass done (tile V={v} TY={ty})")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -151,6 +175,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--all", action="store_true", help="also measure the 3-D 256^3 workload")
+    ap.add_argument("--counters", default=None, metavar="V,TY",
+                    help="counter-collection pass for rocprofv3 --pmc: a 256 MiB calibration copy, then 3 "
+                         "A_h applications of the benchmark workload with the fixed FP64 tiling V,TY")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the hot path runs on a single MI355X "
@@ -161,6 +188,9 @@ def main():
     from paper_2205_12344_amd import elwh, inputs
 
     torch.cuda.set_device(0)
+    if args.counters:
+        counters_pass(args.counters)
+        return
     t0 = time.perf_counter()
     case = inputs.config2()
     log(f"workload {case.name}: omega {case.omega:.3f}, inputs {time.perf_counter() - t0:.1f} s")
@@ -178,7 +208,7 @@ def main():
     step_avg_ms = prof["step_ms"] / max(prof["nstep"], 1)
     b = BYTES_PER_LUP[(2, "f64")]
     achieved = b * nodes / (step_avg_ms * 1e-3) / 1e9
-    traffic = read_traffic("step2d_f64_cfg2_1024")
+    traffic = read_traffic("step2d_f64_cfg2_1024", (tv, tr))
     log(f"tile V={tv} TY={tr}")
     log(f"fp64: {ms_per_step:.3f} ms/step, {value / 1e9:.2f} GLUP/s, step kernel {1e3 * step_avg_ms:.1f} us "
         f"({prof['nstep']} launches), {achieved:.0f} GB/s")
