@@ -212,6 +212,44 @@ elwh_status elwh_set_tile(elwh_ctx* ctx, int prec, int vec, int rows);
 elwh_status elwh_get_tile(const elwh_ctx* ctx, int prec, int* vec, int* rows);
 elwh_status elwh_autotune(elwh_ctx* ctx, int prec, int reps, double* best_step_us);
 
+/*
+ * Ragged batch of independent 2-D problems (sizes, media, omega and N_T may
+ * all differ), solved together: one launch per time step advances every
+ * unfinished problem by one step of its own filter application; a problem
+ * whose application ends runs its CG update on the device in the same
+ * step and starts its next application at the next one; converged problems
+ * drop out.  The CG phase is captured as a hipGraph of several steps and
+ * replayed (elwh_batch_set_graph(b, 0) runs the same launches eagerly).
+ * Each problem's solve is the one of elwh_solve (Sec. 4.5): CG on A_h in the
+ * M inner product with b = Pi_h 0; FP64, or (opts->prec = ELWH_FP32_STEP)
+ * FP64 iterative refinement around FP32-stepped CG.
+ *
+ * elwh_batch_create: nprob problems; grids[i], rho[i], lam[i], mu[i]
+ *   (DEVICE pointers, copied), omega[i], bc[6*i .. 6*i+5]; opts shared
+ *   (opts->stream is the caller's stream; the batch works on its own stream
+ *   and orders itself after / before the caller's stream).  Picks the batch
+ *   tiling by timing when opts->autotune.  Errors: ELWH_ERR_ARG (also for a
+ *   3-D problem), ELWH_ERR_ALLOC, ELWH_ERR_HIP.
+ * elwh_batch_solve: f[i], x0[i] (x0 or any x0[i] may be NULL: zero guess),
+ *   v[i] outputs (DEVICE pointers, caller layout); tol, maxit per problem as
+ *   in elwh_solve; infos (nullable) receives nprob records.  Synchronous.
+ *   Returns ELWH_OK when every problem converged, else the first failure.
+ * elwh_batch_stats: wall seconds of the last solve, number of batched steps
+ *   (ticks), and the FP64 / FP32 tilings {vec, rows}.
+ */
+typedef struct elwh_batch elwh_batch;
+elwh_status elwh_batch_create(int nprob, const elwh_grid* grids, const double* const* rho,
+                              const double* const* lam, const double* const* mu, const double* omega,
+                              const int* bc, const elwh_opts* opts, elwh_batch** out);
+elwh_status elwh_batch_solve(elwh_batch* b, const double* const* f, const double* const* x0, double tol,
+                             int maxit, double* const* v, elwh_info* infos);
+elwh_status elwh_batch_set_graph(elwh_batch* b, int on);
+elwh_status elwh_batch_info(const elwh_batch* b, int i, elwh_info* info);
+elwh_status elwh_batch_stats(const elwh_batch* b, double* seconds, long long* ticks, int* tile64,
+                             int* tile32);
+const char* elwh_batch_last_error(const elwh_batch* b);
+void elwh_batch_destroy(elwh_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

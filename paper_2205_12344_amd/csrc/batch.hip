@@ -1,0 +1,598 @@
+// Ragged batch of 2-D El-WaveHoltz problems (C ABI in include/elwh.h).
+//
+// Every problem keeps its own context (coefficients, state buffers, work
+// vectors, filter weights and N_T).  One "tick" is one batched step launch
+// that advances every active problem by one time step of its own filter
+// application, followed by the device-side CG updates of the problems whose
+// application ended in that tick (Sec. 4.5: alpha = (r,r)_M/(p,A p)_M,
+// x += alpha p, r -= alpha A p, beta, p = r + beta p, all in FP64 with
+// per-problem two-pass reductions).  A problem that converges drops out; the
+// others continue.  The CG phase is captured as a hipGraph of several ticks
+// and replayed until no problem is active; the host reads one counter per
+// replay.  FP32 batches run FP64 iterative refinement around FP32-stepped
+// batched CG solves (r = b - A_h x in FP64, stop on the FP64 residual).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "elwh_internal.h"
+
+using namespace elwh;
+
+namespace {
+enum { VX = 0, VR, VP, VQ, VB, VT, VD, VRI };
+constexpr int GRAPH_TICKS = 8;
+}  // namespace
+
+struct elwh_batch {
+    int np = 0;
+    std::vector<elwh_ctx*> ctx;
+    elwh_opts opts;
+    hipStream_t stream = nullptr;   // own stream (graph capture needs a non-null stream)
+    hipStream_t user = nullptr;     // caller's stream
+    std::string err;
+    bool use_graph = true;
+    Tile tile[2];                   // [0] FP64, [1] FP32
+    std::vector<BProb2D> h_pr;
+    BProb2D* d_pr = nullptr;
+    std::vector<BState> h_st;
+    BState* d_st = nullptr;
+    int* d_mask = nullptr;
+    int* d_active = nullptr;
+    int* h_active = nullptr;        // pinned
+    double* d_partials = nullptr;
+    double* d_dots = nullptr;
+    double* h_dots = nullptr;       // pinned
+    std::vector<double*> d_w, d_cos;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    int gblocks[2] = {0, 0};
+    std::vector<elwh_info> info;
+    double seconds = 0;
+    long long ticks = 0;
+};
+
+namespace {
+
+thread_local std::string g_batch_err;
+
+#define BCK(expr)                                                               \
+    do {                                                                        \
+        hipError_t e_ = (expr);                                                 \
+        if (e_ != hipSuccess) {                                                 \
+            b->err = std::string(#expr) + ": " + hipGetErrorString(e_);         \
+            return ELWH_ERR_HIP;                                                \
+        }                                                                       \
+    } while (0)
+#define BST(expr)                     \
+    do {                              \
+        elwh_status s_ = (expr);      \
+        if (s_ != ELWH_OK) return s_; \
+    } while (0)
+
+// Descriptors of every problem for one phase (precision fp32), vector roles
+// given by indices into the context's work vectors.
+elwh_status set_phase(elwh_batch* b, bool fp32, int isrc, int iout, int ix, int ir, int ip, int* nblocks) {
+    const Tile& t = b->tile[fp32 ? 1 : 0];
+    const int W = batch_cols(t.V);
+    int off = 0;
+    b->h_pr.resize(b->np);
+    for (int p = 0; p < b->np; ++p) {
+        elwh_ctx* c = b->ctx[p];
+        BProb2D& q = b->h_pr[p];
+        std::memset(&q, 0, sizeof(q));
+        q.A = make_args2d(c);
+        q.nbx = (q.A.nx - 1 + W - 1) / W;
+        const int nrows = q.A.jhi - q.A.jlo + 1;
+        q.nblk = q.nbx * ((nrows + t.TY - 1) / t.TY);
+        q.off = off;
+        off += q.nblk;
+        q.nsteps = c->plan.nt * c->opts.periods;
+        q.w = b->d_w[p];
+        q.cosn = b->d_cos[p];
+        if (fp32) {
+            q.s0 = c->s32[0];
+            q.s1 = c->s32[1];
+            q.ca = c->fa;
+            q.cl = c->fl;
+            q.cm = c->fm;
+            q.f = c->f32;
+        } else {
+            q.s0 = c->s64[0];
+            q.s1 = c->s64[1];
+            q.ca = c->ca;
+            q.cl = c->cl;
+            q.cm = c->cm;
+            q.f = c->f64;
+        }
+        q.src = c->vec[isrc];
+        q.out = c->vec[iout];
+        q.lo = c->acc_lo;
+        q.m = c->mw;
+        q.cx = ix >= 0 ? c->vec[ix] : nullptr;
+        q.cr = ir >= 0 ? c->vec[ir] : nullptr;
+        q.cp = ip >= 0 ? c->vec[ip] : nullptr;
+        for (int k = 0; k < 8; ++k) q.vec[k] = c->vec[k];
+    }
+    *nblocks = off;
+    BCK(hipMemcpyAsync(b->d_pr, b->h_pr.data(), sizeof(BProb2D) * b->np, hipMemcpyHostToDevice, b->stream));
+    BCK(hipStreamSynchronize(b->stream));   // h_pr is rewritten by the next phase
+    return ELWH_OK;
+}
+
+elwh_status upload_states(elwh_batch* b) {
+    BCK(hipMemcpyAsync(b->d_st, b->h_st.data(), sizeof(BState) * b->np, hipMemcpyHostToDevice, b->stream));
+    BCK(hipStreamSynchronize(b->stream));
+    return ELWH_OK;
+}
+
+elwh_status download_states(elwh_batch* b) {
+    BCK(hipMemcpyAsync(b->h_st.data(), b->d_st, sizeof(BState) * b->np, hipMemcpyDeviceToHost, b->stream));
+    BCK(hipStreamSynchronize(b->stream));
+    return ELWH_OK;
+}
+
+elwh_status upload_mask(elwh_batch* b, const std::vector<int>& mask) {
+    BCK(hipMemcpyAsync(b->d_mask, mask.data(), sizeof(int) * b->np, hipMemcpyHostToDevice, b->stream));
+    BCK(hipStreamSynchronize(b->stream));
+    return ELWH_OK;
+}
+
+// One filter application per selected problem: out = Pi_h src (with the
+// forcing) or A_h src.  Ragged: runs max N_T ticks.
+elwh_status run_apply(elwh_batch* b, bool fp32, bool force, bool amode, int isrc, int iout,
+                      const std::vector<int>& sel) {
+    int nblocks = 0;
+    BST(set_phase(b, fp32, isrc, iout, -1, -1, -1, &nblocks));
+    int maxsteps = 0;
+    for (int p = 0; p < b->np; ++p) {
+        BState& s = b->h_st[p];
+        s.n = 0;
+        s.end = 0;
+        s.active = sel[p] ? 1 : 0;
+        if (sel[p]) maxsteps = std::max(maxsteps, b->h_pr[p].nsteps);
+    }
+    BST(upload_states(b));
+    const Tile& t = b->tile[fp32 ? 1 : 0];
+    const bool comp = fp32 && b->opts.compensated;
+    for (int k = 0; k < maxsteps; ++k) {
+        launch_batch_step(fp32, t.V, t.TY, force, comp, nblocks, b->stream, b->d_pr, b->d_st, b->np,
+                          amode ? -1.0 : 1.0, amode ? 1 : 0);
+        launch_batch_advance(b->stream, b->d_pr, b->d_st, b->np, 1);
+        b->ticks++;
+    }
+    BCK(hipGetLastError());
+    return ELWH_OK;
+}
+
+elwh_status dots(elwh_batch* b, const std::vector<int>& sel, int ia, int ib, std::vector<double>& out) {
+    int nb = 0;
+    BST(set_phase(b, false, VT, VQ, -1, -1, -1, &nb));
+    BST(upload_mask(b, sel));
+    launch_batch_dot(b->stream, b->d_pr, b->np, b->d_mask, ia, ib, b->d_partials, b->d_dots);
+    BCK(hipMemcpyAsync(b->h_dots, b->d_dots, sizeof(double) * b->np, hipMemcpyDeviceToHost, b->stream));
+    BCK(hipStreamSynchronize(b->stream));
+    out.assign(b->h_dots, b->h_dots + b->np);
+    for (int p = 0; p < b->np; ++p)
+        if (!sel[p]) out[p] = 0.0;
+    return ELWH_OK;
+}
+
+elwh_status lincomb(elwh_batch* b, const std::vector<int>& sel, int idst, int ia, double alpha, int ib,
+                    double beta) {
+    int nb = 0;
+    BST(set_phase(b, false, VT, VQ, -1, -1, -1, &nb));
+    BST(upload_mask(b, sel));
+    launch_batch_lincomb(b->stream, b->d_pr, b->np, b->d_mask, idst, ia, alpha, ib, beta);
+    BCK(hipGetLastError());
+    return ELWH_OK;
+}
+
+void enqueue_ticks(elwh_batch* b, bool fp32, int nblocks, int nticks) {
+    const Tile& t = b->tile[fp32 ? 1 : 0];
+    const bool comp = fp32 && b->opts.compensated;
+    for (int k = 0; k < nticks; ++k) {
+        launch_batch_step(fp32, t.V, t.TY, false, comp, nblocks, b->stream, b->d_pr, b->d_st, b->np, -1.0, 1);
+        launch_batch_advance(b->stream, b->d_pr, b->d_st, b->np, 0);
+        launch_batch_cg(b->stream, 0, b->d_pr, b->d_st, b->np, b->d_partials, b->d_active);
+        launch_batch_cg(b->stream, 1, b->d_pr, b->d_st, b->np, b->d_partials, b->d_active);
+        launch_batch_cg(b->stream, 2, b->d_pr, b->d_st, b->np, b->d_partials, b->d_active);
+    }
+}
+
+elwh_status graph_for(elwh_batch* b, bool fp32, int nblocks) {
+    const int k = fp32 ? 1 : 0;
+    if (b->gexec[k] && b->gblocks[k] == nblocks) return ELWH_OK;
+    if (b->gexec[k]) {
+        (void)hipGraphExecDestroy(b->gexec[k]);
+        b->gexec[k] = nullptr;
+    }
+    hipGraph_t g;
+    BCK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    enqueue_ticks(b, fp32, nblocks, GRAPH_TICKS);
+    BCK(hipStreamEndCapture(b->stream, &g));
+    hipError_t e = hipGraphInstantiate(&b->gexec[k], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        b->err = std::string("hipGraphInstantiate: ") + hipGetErrorString(e);
+        b->gexec[k] = nullptr;
+        return ELWH_ERR_HIP;
+    }
+    b->gblocks[k] = nblocks;
+    return ELWH_OK;
+}
+
+// Ragged CG phase: the states (active, rr, bb, tol2, maxit) are set by the caller.
+elwh_status run_cg(elwh_batch* b, bool fp32, int ix, int ir, int ip, int iq, long long max_ticks) {
+    int nblocks = 0;
+    BST(set_phase(b, fp32, ip, iq, ix, ir, ip, &nblocks));
+    int nact = 0;
+    for (int p = 0; p < b->np; ++p) {
+        BState& s = b->h_st[p];
+        s.n = 0;
+        s.end = 0;
+        nact += s.active;
+    }
+    BST(upload_states(b));
+    *b->h_active = nact;
+    BCK(hipMemcpyAsync(b->d_active, b->h_active, sizeof(int), hipMemcpyHostToDevice, b->stream));
+    BCK(hipStreamSynchronize(b->stream));
+    if (nact == 0) return ELWH_OK;
+    if (b->use_graph) BST(graph_for(b, fp32, nblocks));
+    long long ticks = 0;
+    while (true) {
+        if (b->use_graph) {
+            BCK(hipGraphLaunch(b->gexec[fp32 ? 1 : 0], b->stream));
+        } else {
+            enqueue_ticks(b, fp32, nblocks, GRAPH_TICKS);
+        }
+        ticks += GRAPH_TICKS;
+        b->ticks += GRAPH_TICKS;
+        BCK(hipMemcpyAsync(b->h_active, b->d_active, sizeof(int), hipMemcpyDeviceToHost, b->stream));
+        BCK(hipStreamSynchronize(b->stream));
+        if (*b->h_active <= 0) break;
+        if (ticks >= max_ticks) {
+            b->err = "batched CG exceeded its tick budget";
+            break;
+        }
+    }
+    BST(download_states(b));
+    return ELWH_OK;
+}
+
+void free_batch(elwh_batch* b) {
+    for (auto* c : b->ctx) elwh_destroy(c);
+    for (auto* p : b->d_w) if (p) (void)hipFree(p);
+    for (auto* p : b->d_cos) if (p) (void)hipFree(p);
+    auto f = [](void* p) {
+        if (p) (void)hipFree(p);
+    };
+    f(b->d_pr); f(b->d_st); f(b->d_mask); f(b->d_active); f(b->d_partials); f(b->d_dots);
+    if (b->h_active) (void)hipHostFree(b->h_active);
+    if (b->h_dots) (void)hipHostFree(b->h_dots);
+    for (auto& g : b->gexec)
+        if (g) (void)hipGraphExecDestroy(g);
+    if (b->stream) (void)hipStreamDestroy(b->stream);
+}
+
+elwh_status autotune_batch(elwh_batch* b, bool fp32) {
+    std::vector<int> all(b->np, 1);
+    std::vector<Tile> cands;
+    for (int V : {1, 2, 4})
+        for (int TY : {4, 8, 16})
+            if (batch_tile_valid(fp32, V, TY)) cands.push_back(Tile{V, TY});
+    for (int p = 0; p < b->np; ++p)
+        BCK(hipMemsetAsync(b->ctx[p]->vec[VT], 0, b->ctx[p]->L.field_elems() * sizeof(double), b->stream));
+    hipEvent_t e0, e1;
+    BCK(hipEventCreate(&e0));
+    BCK(hipEventCreate(&e1));
+    double best = 1e300;
+    Tile bt = b->tile[fp32 ? 1 : 0];
+    for (const Tile& t : cands) {
+        b->tile[fp32 ? 1 : 0] = t;
+        BST(run_apply(b, fp32, false, true, VT, VD, all));   // warm-up
+        (void)hipEventRecord(e0, b->stream);
+        BST(run_apply(b, fp32, false, true, VT, VD, all));
+        (void)hipEventRecord(e1, b->stream);
+        BCK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best) {
+            best = ms;
+            bt = t;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    b->tile[fp32 ? 1 : 0] = bt;
+    return ELWH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+elwh_status elwh_batch_create(int nprob, const elwh_grid* grids, const double* const* rho, const double* const* lam,
+                              const double* const* mu, const double* omega, const int* bc, const elwh_opts* opts,
+                              elwh_batch** out) {
+    if (!out) return ELWH_ERR_ARG;
+    *out = nullptr;
+    g_batch_err.clear();
+    if (nprob < 1 || nprob > 4096 || !grids || !rho || !lam || !mu || !omega || !bc) {
+        g_batch_err = "bad batch arguments";
+        return ELWH_ERR_ARG;
+    }
+    elwh_opts o;
+    elwh_default_opts(&o);
+    if (opts) o = *opts;
+    elwh_batch* b = new (std::nothrow) elwh_batch();
+    if (!b) return ELWH_ERR_ALLOC;
+    b->np = nprob;
+    b->opts = o;
+    b->user = reinterpret_cast<hipStream_t>(o.stream);
+    auto fail = [&](elwh_status s, const std::string& msg) {
+        g_batch_err = msg;
+        free_batch(b);
+        delete b;
+        return s;
+    };
+    if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess)
+        return fail(ELWH_ERR_HIP, "stream creation failed");
+    elwh_opts co = o;
+    co.stream = b->stream;
+    co.autotune = 0;
+    for (int p = 0; p < nprob; ++p) {
+        if (grids[p].dim != 2) return fail(ELWH_ERR_ARG, "batches hold 2-D problems");
+        elwh_ctx* c = nullptr;
+        const elwh_status st = elwh_create(&grids[p], rho[p], lam[p], mu[p], omega[p], bc + 6 * p, &co, &c);
+        if (st != ELWH_OK) return fail(st, "problem " + std::to_string(p) + ": " + elwh_last_error(nullptr));
+        b->ctx.push_back(c);
+    }
+    auto dalloc = [&](void** ptr, size_t bytes) { return hipMalloc(ptr, bytes) == hipSuccess; };
+    bool ok = dalloc(reinterpret_cast<void**>(&b->d_pr), sizeof(BProb2D) * nprob) &&
+              dalloc(reinterpret_cast<void**>(&b->d_st), sizeof(BState) * nprob) &&
+              dalloc(reinterpret_cast<void**>(&b->d_mask), sizeof(int) * nprob) &&
+              dalloc(reinterpret_cast<void**>(&b->d_active), sizeof(int)) &&
+              dalloc(reinterpret_cast<void**>(&b->d_partials), sizeof(double) * nprob * BATCH_RED_BLOCKS) &&
+              dalloc(reinterpret_cast<void**>(&b->d_dots), sizeof(double) * nprob) &&
+              hipHostMalloc(reinterpret_cast<void**>(&b->h_active), sizeof(int), hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc(reinterpret_cast<void**>(&b->h_dots), sizeof(double) * nprob, hipHostMallocDefault) ==
+                  hipSuccess;
+    if (!ok) return fail(ELWH_ERR_ALLOC, "batch allocation failed");
+    for (int p = 0; p < nprob; ++p) {
+        elwh_ctx* c = b->ctx[p];
+        double *w = nullptr, *cs = nullptr;
+        const size_t n = c->w.size();
+        if (!dalloc(reinterpret_cast<void**>(&w), n * sizeof(double)) ||
+            !dalloc(reinterpret_cast<void**>(&cs), n * sizeof(double)))
+            return fail(ELWH_ERR_ALLOC, "batch allocation failed");
+        b->d_w.push_back(w);
+        b->d_cos.push_back(cs);
+        if (hipMemcpyAsync(w, c->w.data(), n * sizeof(double), hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+            hipMemcpyAsync(cs, c->cosn.data(), n * sizeof(double), hipMemcpyHostToDevice, b->stream) != hipSuccess)
+            return fail(ELWH_ERR_HIP, "uploading weights failed");
+    }
+    b->h_st.assign(nprob, BState{});
+    b->info.assign(nprob, elwh_info{});
+    b->tile[0] = Tile{2, 8};
+    b->tile[1] = Tile{2, 8};
+    if (o.autotune) {
+        if (autotune_batch(b, false) != ELWH_OK) return fail(ELWH_ERR_HIP, b->err);
+        if (o.prec == ELWH_FP32_STEP && autotune_batch(b, true) != ELWH_OK) return fail(ELWH_ERR_HIP, b->err);
+    }
+    if (hipStreamSynchronize(b->stream) != hipSuccess) return fail(ELWH_ERR_HIP, "synchronisation failed");
+    *out = b;
+    return ELWH_OK;
+}
+
+void elwh_batch_destroy(elwh_batch* b) {
+    if (!b) return;
+    (void)hipStreamSynchronize(b->stream);
+    free_batch(b);
+    delete b;
+}
+
+const char* elwh_batch_last_error(const elwh_batch* b) { return b ? b->err.c_str() : g_batch_err.c_str(); }
+
+elwh_status elwh_batch_set_graph(elwh_batch* b, int on) {
+    if (!b) return ELWH_ERR_ARG;
+    b->use_graph = on != 0;
+    return ELWH_OK;
+}
+
+elwh_status elwh_batch_info(const elwh_batch* b, int i, elwh_info* info) {
+    if (!b || !info || i < 0 || i >= b->np) return ELWH_ERR_ARG;
+    *info = b->info[i];
+    return ELWH_OK;
+}
+
+elwh_status elwh_batch_stats(const elwh_batch* b, double* seconds, long long* ticks, int* tile64, int* tile32) {
+    if (!b) return ELWH_ERR_ARG;
+    if (seconds) *seconds = b->seconds;
+    if (ticks) *ticks = b->ticks;
+    if (tile64) {
+        tile64[0] = b->tile[0].V;
+        tile64[1] = b->tile[0].TY;
+    }
+    if (tile32) {
+        tile32[0] = b->tile[1].V;
+        tile32[1] = b->tile[1].TY;
+    }
+    return ELWH_OK;
+}
+
+elwh_status elwh_batch_solve(elwh_batch* b, const double* const* f, const double* const* x0, double tol, int maxit,
+                             double* const* v, elwh_info* infos) {
+    if (!b || !f || !v || maxit < 0) return ELWH_ERR_ARG;
+    const auto t0 = std::chrono::steady_clock::now();
+    b->ticks = 0;
+    const int np = b->np;
+    const bool fp32 = b->opts.prec == ELWH_FP32_STEP;
+    // order after the caller's pending work
+    hipEvent_t ev;
+    BCK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    BCK(hipEventRecord(ev, b->user));
+    BCK(hipStreamWaitEvent(b->stream, ev, 0));
+    std::vector<int> all(np, 1);
+    for (int p = 0; p < np; ++p) {
+        elwh_ctx* c = b->ctx[p];
+        if (!f[p] || !v[p]) {
+            (void)hipEventDestroy(ev);
+            b->err = "null forcing or output pointer";
+            return ELWH_ERR_ARG;
+        }
+        launch_pack(c->L, c->bc, f[p], c->f64, 2, b->stream);
+        if (fp32) launch_convert_f32(c->L, c->f64, c->f32, 2, b->stream);
+        if (x0 && x0[p])
+            launch_pack(c->L, c->bc, x0[p], c->vec[VX], 2, b->stream);
+        else
+            BCK(hipMemsetAsync(c->vec[VX], 0, c->L.field_elems() * sizeof(double), b->stream));
+        BCK(hipMemsetAsync(c->vec[VT], 0, c->L.field_elems() * sizeof(double), b->stream));
+        c->napply = 0;
+    }
+    // b = Pi_h 0 with the forcing (FP64)
+    BST(run_apply(b, false, true, false, VT, VB, all));
+    std::vector<double> bb, rr;
+    BST(dots(b, all, VB, VB, bb));
+    std::vector<int> iters(np, 0), outer(np, 0), status(np, ELWH_ERR_NOT_CONVERGED);
+    std::vector<double> relres(np, 1.0), relfp64(np, 1.0);
+    std::vector<int> has_x(np, 0);
+    for (int p = 0; p < np; ++p) has_x[p] = (x0 && x0[p]) ? 1 : 0;
+    long long max_nsteps = 0;
+    for (auto* c : b->ctx) max_nsteps = std::max<long long>(max_nsteps, (long long)c->plan.nt * c->opts.periods);
+    const long long tick_budget = (long long)(maxit + 2) * max_nsteps + 64;
+
+    if (!fp32) {
+        // r = b - A x0, p = r
+        bool anyx = false;
+        for (int p = 0; p < np; ++p) anyx |= has_x[p] != 0;
+        if (anyx) {
+            BST(run_apply(b, false, false, true, VX, VQ, has_x));
+            BST(lincomb(b, has_x, VR, VB, 1.0, VQ, -1.0));
+        }
+        std::vector<int> nox(np);
+        for (int p = 0; p < np; ++p) nox[p] = !has_x[p];
+        BST(lincomb(b, nox, VR, VB, 1.0, -1, 0.0));
+        BST(lincomb(b, all, VP, VR, 1.0, -1, 0.0));
+        BST(dots(b, all, VR, VR, rr));
+        for (int p = 0; p < np; ++p) {
+            BState& s = b->h_st[p];
+            std::memset(&s, 0, sizeof(s));
+            s.rr = rr[p];
+            s.bb = bb[p];
+            s.tol2 = tol > 0 ? tol * tol : -1.0;
+            s.maxit = maxit;
+            s.status = ELWH_ERR_NOT_CONVERGED;
+            const bool done = !(bb[p] > 0) || (tol > 0 && rr[p] <= s.tol2 * bb[p]) || maxit == 0;
+            s.active = done ? 0 : 1;
+            if (done) s.status = (bb[p] > 0 || maxit == 0) ? ELWH_OK : ELWH_ERR_ARG;
+        }
+        BST(run_cg(b, false, VX, VR, VP, VQ, tick_budget));
+        for (int p = 0; p < np; ++p) {
+            iters[p] = b->h_st[p].iters;
+            status[p] = b->h_st[p].status;
+            if (tol <= 0 && status[p] == ELWH_ERR_NOT_CONVERGED) status[p] = ELWH_OK;
+            relres[p] = bb[p] > 0 ? std::sqrt(b->h_st[p].rr / bb[p]) : 0.0;
+        }
+        // final residual recomputed with an FP64 apply
+        BST(run_apply(b, false, false, true, VX, VQ, all));
+        BST(lincomb(b, all, VT, VB, 1.0, VQ, -1.0));
+        BST(dots(b, all, VT, VT, rr));
+        for (int p = 0; p < np; ++p) relfp64[p] = bb[p] > 0 ? std::sqrt(rr[p] / bb[p]) : 0.0;
+    } else {
+        std::vector<int> xnz = has_x;
+        for (int o = 0; o <= b->opts.max_outer; ++o) {
+            // FP64 residual of the current iterate
+            std::vector<int> need(np, 0), pending(np, 0);
+            bool anyx = false;
+            for (int p = 0; p < np; ++p) {
+                need[p] = xnz[p] && (status[p] == ELWH_ERR_NOT_CONVERGED);
+                anyx |= need[p] != 0;
+            }
+            if (anyx) {
+                BST(run_apply(b, false, false, true, VX, VQ, need));
+                BST(lincomb(b, need, VRI, VB, 1.0, VQ, -1.0));
+            }
+            std::vector<int> fresh(np);
+            for (int p = 0; p < np; ++p) fresh[p] = !xnz[p] && status[p] == ELWH_ERR_NOT_CONVERGED;
+            BST(lincomb(b, fresh, VRI, VB, 1.0, -1, 0.0));
+            std::vector<int> live(np);
+            for (int p = 0; p < np; ++p) live[p] = status[p] == ELWH_ERR_NOT_CONVERGED;
+            BST(dots(b, live, VRI, VRI, rr));
+            bool any = false;
+            for (int p = 0; p < np; ++p) {
+                if (!live[p]) continue;
+                relfp64[p] = bb[p] > 0 ? std::sqrt(rr[p] / bb[p]) : 0.0;
+                if (!(bb[p] > 0) || (tol > 0 && relfp64[p] <= tol)) {
+                    status[p] = ELWH_OK;
+                } else if (!std::isfinite(relfp64[p])) {
+                    status[p] = ELWH_ERR_UNSTABLE;
+                } else if (iters[p] >= maxit || o == b->opts.max_outer) {
+                    status[p] = tol > 0 ? ELWH_ERR_NOT_CONVERGED : ELWH_OK;
+                    if (tol <= 0) live[p] = 0;
+                } else {
+                    pending[p] = 1;
+                    any = true;
+                }
+            }
+            if (!any) break;
+            // inner FP32 CG on A d = r (zero start)
+            BST(lincomb(b, pending, VD, VRI, 0.0, -1, 0.0));
+            BST(lincomb(b, pending, VR, VRI, 1.0, -1, 0.0));
+            BST(lincomb(b, pending, VP, VRI, 1.0, -1, 0.0));
+            for (int p = 0; p < np; ++p) {
+                BState& s = b->h_st[p];
+                std::memset(&s, 0, sizeof(s));
+                s.active = pending[p];
+                s.rr = rr[p];
+                s.bb = rr[p];
+                s.tol2 = b->opts.inner_tol * b->opts.inner_tol;
+                s.maxit = std::max(1, maxit - iters[p]);
+                s.status = ELWH_ERR_NOT_CONVERGED;
+            }
+            BST(run_cg(b, true, VD, VR, VP, VQ, tick_budget));
+            for (int p = 0; p < np; ++p) {
+                if (!pending[p]) continue;
+                iters[p] += b->h_st[p].iters;
+                outer[p] = o + 1;
+                relres[p] = relfp64[p] * std::sqrt(b->h_st[p].rr / std::max(rr[p], 1e-300));
+                if (b->h_st[p].status == ELWH_ERR_BREAKDOWN || b->h_st[p].status == ELWH_ERR_UNSTABLE)
+                    status[p] = b->h_st[p].status;
+            }
+            BST(lincomb(b, pending, VX, VX, 1.0, VD, 1.0));
+            for (int p = 0; p < np; ++p)
+                if (pending[p]) xnz[p] = 1;
+        }
+    }
+    for (int p = 0; p < np; ++p) launch_unpack(b->ctx[p]->L, b->ctx[p]->bc, b->ctx[p]->vec[VX], v[p], 2, b->stream);
+    BCK(hipEventRecord(ev, b->stream));
+    BCK(hipStreamWaitEvent(b->user, ev, 0));
+    BCK(hipStreamSynchronize(b->stream));
+    (void)hipEventDestroy(ev);
+    b->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    elwh_status worst = ELWH_OK;
+    for (int p = 0; p < np; ++p) {
+        elwh_info& in = b->info[p];
+        std::memset(&in, 0, sizeof(in));
+        elwh_ctx* c = b->ctx[p];
+        in.iters = iters[p];
+        in.outer = outer[p];
+        in.nt = c->plan.nt;
+        in.dt = c->plan.dt;
+        in.c = c->plan.c;
+        in.lambda_bound = c->plan.lambda_bound;
+        in.relres = relres[p];
+        in.relres_fp64 = relfp64[p];
+        in.cond_est = NAN;
+        if (infos) infos[p] = in;
+        if (status[p] != ELWH_OK && worst == ELWH_OK) worst = (elwh_status)status[p];
+        if (status[p] == ELWH_ERR_BREAKDOWN || status[p] == ELWH_ERR_UNSTABLE) worst = (elwh_status)status[p];
+    }
+    if (worst != ELWH_OK && b->err.empty()) b->err = "at least one problem did not converge";
+    return worst;
+}
+
+}  // extern "C"

@@ -55,6 +55,39 @@ struct Tile {
     int V = 1, TY = 8;
 };
 
+// Kernel arguments of the 2-D fused step.
+struct Args2D {
+    int nx, ny;
+    int64_t P, CS;
+    int jlo, jhi, free_lo, free_hi;
+    double cxx2, cyy2, cxy, cyyf, cfx;
+    double w, w0, fc;
+    int final_;
+};
+
+// Batched problem descriptor (device copy built by the host per phase).
+struct BProb2D {
+    Args2D A;                 // geometry and stencil constants
+    int nbx, nblk, off;       // blocks along x, blocks per step launch, first block
+    int nsteps;               // launches per application (K N_T)
+    const double* w;          // filter weights w_n (sign +1), n = 0..nsteps
+    const double* cosn;       // forcing factors cos(2 pi n / N_T)
+    void *s0, *s1;            // state buffers (FP64 or FP32)
+    const double* src;        // u^0 of the application
+    double* out;              // accumulator = result of the application (q in CG)
+    double* lo;               // compensation
+    const void *ca, *cl, *cm, *f;
+    const double* m;          // M weights
+    double *cx, *cr, *cp;     // CG iterate, residual, direction
+    double* vec[8];           // the problem's FP64 work vectors
+};
+
+// Per-problem device state of the ragged CG.
+struct BState {
+    int n, end, active, status, iters, maxit;
+    double rr, pq, alpha, beta, bb, tol2;
+};
+
 struct Plan {
     int nt = 0;
     double dt = 0, c = 1, lambda_bound = 0, T = 0;
@@ -163,5 +196,20 @@ void launch_axpby(const elwh_ctx* c, double a, const double* x, double b, double
 void launch_copy(const elwh_ctx* c, const double* x, double* y, hipStream_t s);
 
 enum { RED_SUM = 0, RED_PQ = 1, RED_RR = 2 };
+
+// ---- ragged batch (kernels2d.hip) --------------------------------------------
+bool batch_tile_valid(bool fp32, int V, int TY);
+int batch_cols(int V);
+Args2D make_args2d(const elwh_ctx* c);
+void launch_batch_step(bool fp32, int V, int TY, bool force, bool comp, int nblocks, hipStream_t s,
+                       const BProb2D* pr, const BState* st, int np, double sgn, int amode);
+void launch_batch_advance(hipStream_t s, const BProb2D* pr, BState* st, int np, int single);
+void launch_batch_cg(hipStream_t s, int mode, const BProb2D* pr, BState* st, int np, double* partials,
+                     int* n_active);
+void launch_batch_lincomb(hipStream_t s, const BProb2D* pr, int np, const int* mask, int idst, int ia,
+                          double alpha, int ib, double beta);
+void launch_batch_dot(hipStream_t s, const BProb2D* pr, int np, const int* mask, int ia, int ib,
+                      double* partials, double* out);
+constexpr int BATCH_RED_BLOCKS = 64;
 
 }  // namespace elwh

@@ -28,15 +28,6 @@
 
 namespace elwh {
 
-struct Args2D {
-    int nx, ny;
-    int64_t P, CS;
-    int jlo, jhi, free_lo, free_hi;
-    double cxx2, cyy2, cxy, cyyf, cfx;
-    double w, w0, fc;
-    int final_;
-};
-
 template <typename T, int V>
 struct alignas(sizeof(T) * V) VecT {
     T x[V];
@@ -142,20 +133,21 @@ struct Cols {
     static constexpr int W = V == 4 ? 252 : 64 * V - 2;   // computed columns per wavefront
 };
 
+// One wavefront's share of one step: the x-strip bx and row chunk by.
 // MODE 0: time step; MODE 1: initial half step.  U: element type of the
 // u^n input (double for the half step from an FP64 vector, T otherwise).
 template <typename T, typename U, int V, int TY, int MODE, bool FORCE, bool COMP>
-__global__ __launch_bounds__(64) void step2d_kernel(const U* __restrict__ u, const T* uprev, T* unext,
-                                                   const double* __restrict__ xbase, T* __restrict__ u0out,
-                                                   double* __restrict__ acc, double* __restrict__ acclo,
-                                                   const T* __restrict__ ca, const T* __restrict__ cl,
-                                                   const T* __restrict__ cm, const T* __restrict__ f, Args2D A) {
+__device__ __forceinline__ void step2d_body(int bx, int by, const U* __restrict__ u, const T* uprev, T* unext,
+                                            const double* __restrict__ xbase, T* __restrict__ u0out,
+                                            double* __restrict__ acc, double* __restrict__ acclo,
+                                            const T* __restrict__ ca, const T* __restrict__ cl,
+                                            const T* __restrict__ cm, const T* __restrict__ f, const Args2D& A) {
     constexpr int W = Cols<V>::W;
     const int lane = threadIdx.x;
-    const int c0 = W * (int)blockIdx.x;
+    const int c0 = W * bx;
     const int col = c0 + V * lane;                // first column of this lane
     const bool colv = col <= A.nx;                // vector lies in the padded row
-    const int j0 = A.jlo + (int)blockIdx.y * TY;
+    const int j0 = A.jlo + by * TY;
     if (j0 > A.jhi) return;
     const int j1 = min(j0 + TY - 1, A.jhi);
     const int P = (int)A.P;
@@ -310,6 +302,16 @@ __global__ __launch_bounds__(64) void step2d_kernel(const U* __restrict__ u, con
     }
 }
 
+template <typename T, typename U, int V, int TY, int MODE, bool FORCE, bool COMP>
+__global__ __launch_bounds__(64) void step2d_kernel(const U* __restrict__ u, const T* uprev, T* unext,
+                                                   const double* __restrict__ xbase, T* __restrict__ u0out,
+                                                   double* __restrict__ acc, double* __restrict__ acclo,
+                                                   const T* __restrict__ ca, const T* __restrict__ cl,
+                                                   const T* __restrict__ cm, const T* __restrict__ f, Args2D A) {
+    step2d_body<T, U, V, TY, MODE, FORCE, COMP>((int)blockIdx.x, (int)blockIdx.y, u, uprev, unext, xbase, u0out,
+                                                acc, acclo, ca, cl, cm, f, A);
+}
+
 // ---------------------------------------------------------------------------
 
 template <typename T, typename U, int V, int TY, int MODE>
@@ -352,7 +354,7 @@ static void launch_v(int V, int TY, bool force, bool comp, int nx, int nrows, hi
                                ca, cl, cm, f, A);
 }
 
-static Args2D args2d(const elwh_ctx* c) {
+Args2D make_args2d(const elwh_ctx* c) {
     Args2D A;
     A.nx = c->L.nx;
     A.ny = c->L.ny;
@@ -377,10 +379,273 @@ bool tile_valid_2d(bool fp32, int V, int TY) {
     return v_ok && (TY == 4 || TY == 8 || TY == 16);
 }
 
+// ===========================================================================
+// Ragged batch: many 2-D problems of different size, medium, omega and N_T in
+// one launch per time step.  Each problem keeps its own step counter and CG
+// scalars in device memory (BState); block b of a launch belongs to the
+// problem whose block range contains b.  A problem that finishes an
+// application in a tick runs its CG update in the same tick and starts its
+// next application in the next one, independently of the others.
+// ===========================================================================
+
+// Problem lookup: offsets ascending, np <= a few hundred.
+__device__ __forceinline__ int batch_problem(const BProb2D* __restrict__ pr, int np, int b) {
+    int p = 0;
+    while (p + 1 < np && b >= pr[p + 1].off) ++p;
+    return p;
+}
+
+template <typename T, int V, int TY, bool FORCE, bool COMP>
+__global__ __launch_bounds__(64) void batch_step2d_kernel(const BProb2D* __restrict__ pr, const BState* __restrict__ st,
+                                                          int np, double sgn, int amode) {
+    const int b = (int)blockIdx.x;
+    const int p = batch_problem(pr, np, b);
+    const BProb2D& q = pr[p];
+    if (!st[p].active) return;
+    const int neff = st[p].end ? 0 : st[p].n;
+    const int local = b - q.off;
+    if (local >= q.nblk) return;
+    const int bx = local % q.nbx, by = local / q.nbx;
+    Args2D A = q.A;
+    T* s0 = reinterpret_cast<T*>(q.s0);
+    T* s1 = reinterpret_cast<T*>(q.s1);
+    const T* ca = reinterpret_cast<const T*>(q.ca);
+    const T* cl = reinterpret_cast<const T*>(q.cl);
+    const T* cm = reinterpret_cast<const T*>(q.cm);
+    const T* f = reinterpret_cast<const T*>(q.f);
+    if (neff == 0) {
+        A.w0 = sgn * q.w[0];
+        A.w = sgn * q.w[1];
+        A.fc = q.cosn[0];
+        A.final_ = 0;
+        step2d_body<T, double, V, TY, 1, FORCE, COMP>(bx, by, q.src, nullptr, s1, amode ? q.src : nullptr,
+                                                      sizeof(T) == 4 ? s0 : nullptr, q.out, q.lo, ca, cl, cm, f, A);
+    } else {
+        A.w = sgn * q.w[neff + 1];
+        A.fc = q.cosn[neff];
+        A.final_ = neff == q.nsteps - 1;
+        T* cur = (neff & 1) ? s1 : s0;
+        T* nxt = (neff & 1) ? s0 : s1;
+        const T* prev = (sizeof(T) == 8 && neff == 1) ? reinterpret_cast<const T*>(q.src) : nxt;
+        step2d_body<T, T, V, TY, 0, FORCE, COMP>(bx, by, cur, prev, nxt, nullptr, nullptr, q.out, q.lo, ca, cl, cm, f,
+                                                 A);
+    }
+}
+
+// Advance the step counters after a batched step launch.  single: the phase
+// is one application per problem (deactivate when it completes).
+__global__ void batch_advance_kernel(const BProb2D* __restrict__ pr, BState* __restrict__ st, int np, int single) {
+    const int p = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (p >= np || !st[p].active) return;
+    const int neff = st[p].end ? 0 : st[p].n;
+    st[p].n = neff + 1;
+    st[p].end = st[p].n == pr[p].nsteps;
+    if (single && st[p].end) st[p].active = 0;
+}
+
+constexpr int BRB = 64;   // reduction blocks per problem
+
+// mode 0: partial (p, q)_M; mode 1: x += alpha p, r -= alpha q, partial (r, r)_M;
+// mode 2: p = r + beta p.  Only problems that finished an application this tick.
+template <int MODE>
+__global__ __launch_bounds__(256) void batch_cg_kernel(const BProb2D* __restrict__ pr, const BState* __restrict__ st,
+                                                       int np, double* __restrict__ partials) {
+    const int p = (int)blockIdx.x / BRB, k = (int)blockIdx.x % BRB;
+    if (p >= np || !st[p].active || !st[p].end) return;
+    const BProb2D& q = pr[p];
+    const int64_t CS = q.A.CS;
+    double s = 0.0;
+    const double alpha = st[p].alpha, beta = st[p].beta;
+    for (int64_t e = (int64_t)k * 256 + threadIdx.x; e < CS; e += (int64_t)BRB * 256) {
+        const double me = q.m[e];
+        double t = 0.0;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int64_t o = e + c * CS;
+            if (MODE == 0) {
+                t += q.cp[o] * q.out[o];
+            } else if (MODE == 1) {
+                q.cx[o] += alpha * q.cp[o];
+                const double rn = q.cr[o] - alpha * q.out[o];
+                q.cr[o] = rn;
+                t += rn * rn;
+            } else {
+                q.cp[o] = q.cr[o] + beta * q.cp[o];
+            }
+        }
+        s += me * t;
+    }
+    if (MODE == 2) return;
+    // wavefront then block reduction
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    __shared__ double red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) partials[p * BRB + k] = red[0] + red[1] + red[2] + red[3];
+}
+
+// Finish the reductions of the ending problems.  mode 0: alpha = rr / pq;
+// mode 1: rr, beta, iteration count and the stopping tests.
+template <int MODE>
+__global__ __launch_bounds__(64) void batch_cg_final_kernel(BState* __restrict__ st, int np,
+                                                            const double* __restrict__ partials,
+                                                            int* __restrict__ n_active) {
+    const int p = (int)blockIdx.x;
+    if (p >= np || !st[p].active || !st[p].end) return;
+    double s = partials[p * BRB + threadIdx.x];   // BRB == 64 == blockDim
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if (threadIdx.x != 0) return;
+    BState& b = st[p];
+    if (MODE == 0) {
+        b.pq = s;
+        if (s > 0.0 && isfinite(s)) {
+            b.alpha = b.rr / s;
+        } else {
+            b.status = isfinite(s) ? ELWH_ERR_BREAKDOWN : ELWH_ERR_UNSTABLE;
+            b.active = 0;
+            atomicSub(n_active, 1);
+        }
+    } else {
+        b.beta = s / b.rr;
+        b.rr = s;
+        b.iters++;
+        if (!isfinite(s)) {
+            b.status = ELWH_ERR_UNSTABLE;
+        } else if (s <= b.tol2 * b.bb) {
+            b.status = ELWH_OK;
+        } else if (b.iters >= b.maxit) {
+            b.status = ELWH_ERR_NOT_CONVERGED;
+        } else {
+            return;
+        }
+        b.active = 0;
+        atomicSub(n_active, 1);
+    }
+}
+
+// dst = alpha a + beta b over the whole padded field of every selected problem
+// (vector indices into BProb2D::vec; ib < 0: no b).  sel: problems with a
+// non-zero flag in mask.
+__global__ __launch_bounds__(256) void batch_lincomb_kernel(const BProb2D* __restrict__ pr, int np,
+                                                            const int* __restrict__ mask, int idst, int ia,
+                                                            double alpha, int ib, double beta) {
+    const int p = (int)blockIdx.x / BRB, k = (int)blockIdx.x % BRB;
+    if (p >= np || (mask && !mask[p])) return;
+    const BProb2D& q = pr[p];
+    double* d = q.vec[idst];
+    const double* a = q.vec[ia];
+    const double* bb = ib >= 0 ? q.vec[ib] : nullptr;
+    const int64_t n = 2 * q.A.CS;
+    for (int64_t e = (int64_t)k * 256 + threadIdx.x; e < n; e += (int64_t)BRB * 256)
+        d[e] = alpha * a[e] + (bb ? beta * bb[e] : 0.0);
+}
+
+// Per-problem (a, b)_M into out[p] (two passes: partials, then one block).
+__global__ __launch_bounds__(256) void batch_dot_partial_kernel(const BProb2D* __restrict__ pr, int np,
+                                                                const int* __restrict__ mask, int ia, int ib,
+                                                                double* __restrict__ partials) {
+    const int p = (int)blockIdx.x / BRB, k = (int)blockIdx.x % BRB;
+    if (p >= np || (mask && !mask[p])) return;
+    const BProb2D& q = pr[p];
+    const double* a = q.vec[ia];
+    const double* b = q.vec[ib];
+    const int64_t CS = q.A.CS;
+    double s = 0.0;
+    for (int64_t e = (int64_t)k * 256 + threadIdx.x; e < CS; e += (int64_t)BRB * 256)
+        s += q.m[e] * (a[e] * b[e] + a[e + CS] * b[e + CS]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    __shared__ double red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) partials[p * BRB + k] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ __launch_bounds__(64) void batch_dot_final_kernel(int np, const int* __restrict__ mask,
+                                                             const double* __restrict__ partials,
+                                                             double* __restrict__ out) {
+    const int p = (int)blockIdx.x;
+    if (p >= np || (mask && !mask[p])) return;
+    double s = partials[p * BRB + threadIdx.x];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if (threadIdx.x == 0) out[p] = s;
+}
+
+template <typename T, int V, int TY>
+static void batch_step_t(bool force, bool comp, int nblocks, hipStream_t s, const BProb2D* pr, const BState* st,
+                         int np, double sgn, int amode) {
+#define ELWH_B2(F, C) \
+    hipLaunchKernelGGL((batch_step2d_kernel<T, V, TY, F, C>), dim3(nblocks), dim3(64), 0, s, pr, st, np, sgn, amode)
+    if (force) {
+        if (comp) ELWH_B2(true, true); else ELWH_B2(true, false);
+    } else {
+        if (comp) ELWH_B2(false, true); else ELWH_B2(false, false);
+    }
+#undef ELWH_B2
+}
+
+bool batch_tile_valid(bool fp32, int V, int TY) {
+    if (V == 1 && (TY == 4 || TY == 8)) return true;
+    if (V == 2 && (TY == 4 || TY == 8 || TY == 16)) return true;
+    return fp32 && V == 4 && TY == 8;
+}
+
+int batch_cols(int V) { return V == 1 ? Cols<1>::W : (V == 2 ? Cols<2>::W : Cols<4>::W); }
+
+void launch_batch_step(bool fp32, int V, int TY, bool force, bool comp, int nblocks, hipStream_t s,
+                       const BProb2D* pr, const BState* st, int np, double sgn, int amode) {
+#define ELWH_BT(T, VV, TT) \
+    if (V == VV && TY == TT) { batch_step_t<T, VV, TT>(force, comp, nblocks, s, pr, st, np, sgn, amode); return; }
+    if (fp32) {
+        ELWH_BT(float, 1, 4) ELWH_BT(float, 1, 8) ELWH_BT(float, 2, 4) ELWH_BT(float, 2, 8) ELWH_BT(float, 2, 16)
+        ELWH_BT(float, 4, 8)
+    } else {
+        ELWH_BT(double, 1, 4) ELWH_BT(double, 1, 8) ELWH_BT(double, 2, 4) ELWH_BT(double, 2, 8)
+        ELWH_BT(double, 2, 16)
+    }
+#undef ELWH_BT
+}
+
+void launch_batch_advance(hipStream_t s, const BProb2D* pr, BState* st, int np, int single) {
+    hipLaunchKernelGGL(batch_advance_kernel, dim3((np + 63) / 64), dim3(64), 0, s, pr, st, np, single);
+}
+
+void launch_batch_cg(hipStream_t s, int mode, const BProb2D* pr, BState* st, int np, double* partials,
+                     int* n_active) {
+    const dim3 g((unsigned)(np * BRB));
+    if (mode == 0) {
+        hipLaunchKernelGGL(batch_cg_kernel<0>, g, dim3(256), 0, s, pr, st, np, partials);
+        hipLaunchKernelGGL(batch_cg_final_kernel<0>, dim3(np), dim3(64), 0, s, st, np, partials, n_active);
+    } else if (mode == 1) {
+        hipLaunchKernelGGL(batch_cg_kernel<1>, g, dim3(256), 0, s, pr, st, np, partials);
+        hipLaunchKernelGGL(batch_cg_final_kernel<1>, dim3(np), dim3(64), 0, s, st, np, partials, n_active);
+    } else {
+        hipLaunchKernelGGL(batch_cg_kernel<2>, g, dim3(256), 0, s, pr, st, np, partials);
+    }
+}
+
+void launch_batch_lincomb(hipStream_t s, const BProb2D* pr, int np, const int* mask, int idst, int ia, double alpha,
+                          int ib, double beta) {
+    hipLaunchKernelGGL(batch_lincomb_kernel, dim3((unsigned)(np * BRB)), dim3(256), 0, s, pr, np, mask, idst, ia,
+                       alpha, ib, beta);
+}
+
+void launch_batch_dot(hipStream_t s, const BProb2D* pr, int np, const int* mask, int ia, int ib, double* partials,
+                      double* out) {
+    hipLaunchKernelGGL(batch_dot_partial_kernel, dim3((unsigned)(np * BRB)), dim3(256), 0, s, pr, np, mask, ia, ib,
+                       partials);
+    hipLaunchKernelGGL(batch_dot_final_kernel, dim3(np), dim3(64), 0, s, np, mask, partials, out);
+}
+
+Args2D make_args2d(const elwh_ctx* c);
+
 // One filter application (2-D), see elwh_internal.h.
 void run_filter_2d(elwh_ctx* c, const double* x, bool with_force, bool amode, bool fp32, double* out) {
     hipStream_t s = c->stream;
-    Args2D A = args2d(c);
+    Args2D A = make_args2d(c);
     const int nrows = A.jhi - A.jlo + 1;
     const Tile t = fp32 ? c->tile32 : c->tile64;
     const int nsteps = c->plan.nt * c->opts.periods;

@@ -28,6 +28,8 @@ EXPORTED = [
     "elwh_apply_filter", "elwh_apply_A", "elwh_solve", "elwh_cg_begin", "elwh_cg_iterate",
     "elwh_cg_result", "elwh_dot_M", "elwh_profile_enable", "elwh_profile_read",
     "elwh_set_tile", "elwh_get_tile", "elwh_autotune",
+    "elwh_batch_create", "elwh_batch_solve", "elwh_batch_set_graph", "elwh_batch_info", "elwh_batch_stats",
+    "elwh_batch_last_error", "elwh_batch_destroy",
 ]
 
 
@@ -85,11 +87,24 @@ def _load():
     lib.elwh_set_tile.argtypes = [P, I, I, I]
     lib.elwh_get_tile.argtypes = [P, I, ctypes.POINTER(I), ctypes.POINTER(I)]
     lib.elwh_autotune.argtypes = [P, I, I, ctypes.POINTER(D)]
+    PP = ctypes.POINTER(P)
+    lib.elwh_batch_create.argtypes = [I, ctypes.POINTER(Grid), PP, PP, PP, ctypes.POINTER(D), ctypes.POINTER(I),
+                                      ctypes.POINTER(Opts), ctypes.POINTER(P)]
+    lib.elwh_batch_solve.argtypes = [P, PP, PP, D, I, PP, ctypes.POINTER(Info)]
+    lib.elwh_batch_set_graph.argtypes = [P, I]
+    lib.elwh_batch_info.argtypes = [P, I, ctypes.POINTER(Info)]
+    lib.elwh_batch_stats.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(I),
+                                     ctypes.POINTER(I)]
+    lib.elwh_batch_last_error.argtypes = [P]
+    lib.elwh_batch_last_error.restype = ctypes.c_char_p
+    lib.elwh_batch_destroy.argtypes = [P]
+    lib.elwh_batch_destroy.restype = None
     lib.elwh_profile_enable.argtypes = [P, I]
     lib.elwh_profile_read.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(I), ctypes.POINTER(D),
                                       ctypes.POINTER(I)]
     for name in EXPORTED:
-        if name not in ("elwh_default_opts", "elwh_destroy", "elwh_last_error"):
+        if name not in ("elwh_default_opts", "elwh_destroy", "elwh_last_error", "elwh_batch_last_error",
+                        "elwh_batch_destroy"):
             getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -280,3 +295,76 @@ class Context:
 def context_from_case(case, **opts):
     """Context for an inputs.Case."""
     return Context(case.dim, case.n, case.rho, case.lam, case.mu, case.omega, case.bc, length=case.length, **opts)
+
+
+def _ptr_array(ts):
+    arr = (ctypes.c_void_p * len(ts))()
+    for k, t in enumerate(ts):
+        arr[k] = t.data_ptr() if t is not None else None
+    return arr
+
+
+class Batch:
+    """A ragged batch of 2-D problems solved together (elwh_batch_*)."""
+
+    def __init__(self, cases, stream=None, **opts):
+        if not torch.cuda.is_available():
+            raise RuntimeError("libelwh needs a GPU")
+        self.cases = list(cases)
+        n = len(self.cases)
+        grids = (Grid * n)()
+        bc = (ctypes.c_int * (6 * n))()
+        om = (ctypes.c_double * n)()
+        keep = []
+        for k, c in enumerate(self.cases):
+            if c.dim != 2:
+                raise ValueError("batches hold 2-D problems")
+            g = make_grid(2, c.n, c.length)
+            grids[k] = g
+            for q in range(6):
+                bc[6 * k + q] = int(c.bc[q]) if q < 4 else 0
+            om[k] = float(c.omega)
+            keep.append((_dev(c.rho, "rho"), _dev(c.lam, "lam"), _dev(c.mu, "mu")))
+        self.field_shapes = [(2,) + c.node_shape for c in self.cases]
+        self.stream = torch.cuda.current_stream() if stream is None else stream
+        o = default_opts(stream=self.stream.cuda_stream, **opts)
+        h = ctypes.c_void_p()
+        st = lib.elwh_batch_create(n, grids, _ptr_array([k[0] for k in keep]), _ptr_array([k[1] for k in keep]),
+                                   _ptr_array([k[2] for k in keep]), om, bc, ctypes.byref(o), ctypes.byref(h))
+        if st != OK:
+            raise ElwhError(st, lib.elwh_batch_last_error(None).decode())
+        self._h = h
+        self.n = n
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.elwh_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_graph(self, on):
+        lib.elwh_batch_set_graph(self._h, 1 if on else 0)
+
+    def solve(self, fs, x0s=None, tol=1e-8, maxit=1000, raise_on_fail=False):
+        ft = [_dev(f, "f") for f in fs]
+        xt = [(_dev(x, "x0") if x is not None else None) for x in (x0s or [None] * self.n)]
+        vs = [torch.empty(s, dtype=torch.float64, device="cuda") for s in self.field_shapes]
+        infos = (Info * self.n)()
+        st = lib.elwh_batch_solve(self._h, _ptr_array(ft), _ptr_array(xt) if x0s is not None else None, float(tol),
+                                  int(maxit), _ptr_array(vs), infos)
+        if st != OK and raise_on_fail:
+            raise ElwhError(st, lib.elwh_batch_last_error(self._h).decode())
+        return vs, [infos[k].as_dict() for k in range(self.n)], STATUS_NAMES[st]
+
+    def stats(self):
+        sec = ctypes.c_double()
+        ticks = ctypes.c_longlong()
+        t64 = (ctypes.c_int * 2)()
+        t32 = (ctypes.c_int * 2)()
+        lib.elwh_batch_stats(self._h, ctypes.byref(sec), ctypes.byref(ticks), t64, t32)
+        return {"seconds": sec.value, "ticks": ticks.value, "tile64": list(t64), "tile32": list(t32)}

@@ -1,0 +1,104 @@
+"""GPU tests of the ragged batch (one launch per step for many problems of
+different size, omega and N_T; device-side CG per problem; hipGraph replay)."""
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import direct, krylov
+from oracle import stepping as S
+from oracle.operator import Operator
+from oracle.problem import Problem
+from paper_2205_12344_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[gpu-batch]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def E():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2205_12344_amd import elwh
+    return elwh
+
+
+def _cases():
+    spec = [(24, 6.0), (40, 9.5), (33, 4.2), (50, 12.0), (29, 7.7), (64, 15.0)]
+    return [inputs.random_problem_2d(n, om, seed=200 + k) for k, (n, om) in enumerate(spec)]
+
+
+def _direct(c):
+    prob = Problem(2, c.n, bc=c.bc)
+    op = Operator(prob, c.rho, c.lam, c.mu)
+    return prob, op, direct.solve(op, c.omega, prob.gather(c.f))
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def test_batch_fp64_matches_direct_and_oracle_cg(E):
+    cases = _cases()
+    bt = E.Batch(cases)
+    _say("tiles", bt.stats())
+    vs, infos, status = bt.solve([c.f for c in cases], tol=1e-10, maxit=500)
+    assert status == "OK"
+    for c, v, info in zip(cases, vs, infos):
+        prob, op, vstar = _direct(c)
+        got = prob.gather(v.cpu().numpy())
+        wh = S.WaveHoltz(op, c.omega)
+        res = krylov.cg(wh.apply_A, wh.rhs(prob.gather(c.f)), op.m, tol=1e-10, maxit=500)
+        _say(c.name, info["iters"], res.iters, info["relres_fp64"], _rel(got, vstar))
+        assert info["nt"] == wh.nt
+        assert abs(info["iters"] - res.iters) <= 1
+        assert info["relres_fp64"] <= 2e-10
+        assert _rel(got, vstar) <= 1e-8
+        assert _rel(got, res.x) <= 1e-8
+
+
+def test_batch_graph_replay_equals_eager(E):
+    """The captured hipGraph of batched steps, replayed many times with host
+    synchronisations in between, gives exactly the eager launches' result."""
+    cases = _cases()[:4]
+    bt = E.Batch(cases)
+    f = [c.f for c in cases]
+    v1, i1, s1 = bt.solve(f, tol=1e-9, maxit=300)
+    v2, i2, s2 = bt.solve(f, tol=1e-9, maxit=300)
+    bt.set_graph(False)
+    v3, i3, s3 = bt.solve(f, tol=1e-9, maxit=300)
+    assert s1 == s2 == s3 == "OK"
+    for a, b, c in zip(v1, v2, v3):
+        assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
+        assert np.array_equal(a.cpu().numpy(), c.cpu().numpy())
+    assert [x["iters"] for x in i1] == [x["iters"] for x in i3]
+
+
+def test_batch_warm_start_and_fixed_iterations(E):
+    cases = _cases()[:3]
+    bt = E.Batch(cases)
+    f = [c.f for c in cases]
+    v, info, st = bt.solve(f, tol=0.0, maxit=7)
+    assert st == "OK" and all(x["iters"] == 7 for x in info)
+    v2, info2, st2 = bt.solve(f, x0s=v, tol=1e-10, maxit=500)
+    assert st2 == "OK"
+    for c, x in zip(cases, v2):
+        prob, op, vstar = _direct(c)
+        assert _rel(prob.gather(x.cpu().numpy()), vstar) <= 1e-8
+
+
+def test_batch_fp32_refinement(E):
+    cases = _cases()
+    bt = E.Batch(cases, prec=E.FP32_STEP)
+    vs, infos, status = bt.solve([c.f for c in cases], tol=1e-8, maxit=2000)
+    _say("fp32 batch", status, [(i["iters"], i["outer"], i["relres_fp64"]) for i in infos], bt.stats())
+    assert status == "OK"
+    for c, v, info in zip(cases, vs, infos):
+        prob, op, vstar = _direct(c)
+        assert info["relres_fp64"] <= 1e-8
+        assert _rel(prob.gather(v.cpu().numpy()), vstar) <= 1e-6
