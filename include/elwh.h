@@ -250,6 +250,59 @@ elwh_status elwh_batch_stats(const elwh_batch* b, double* seconds, long long* ti
 const char* elwh_batch_last_error(const elwh_batch* b);
 void elwh_batch_destroy(elwh_batch* b);
 
+/*
+ * Learned warm start (not part of the paper: an initial guess x0 for the
+ * solve).  A convolutional encoder-decoder over an H x W pixel grid
+ * (H, W multiples of 16): five resolution levels of two 3x3 convolutions
+ * with bias and SiLU (widths 32, 64, 96, 128, 128), 2x2 average pooling,
+ * nearest upsampling with skip concatenation, and a 3x3 output convolution
+ * to 2 channels; 1 644 578 parameters.  Convolutions are implicit GEMMs on
+ * MFMA (BF16 operands, FP32 accumulation); master weights, activations,
+ * gradients and the Adam state are FP32.  Tensors are NHWC float32 device
+ * arrays: inputs x [B][H][W][7], outputs y [B][H][W][2], loss weights
+ * w [B][H][W].  The flat parameter vector holds, per layer in order,
+ * W[(ky*3+kx)*cin + ci][cout] then bias[cout].
+ *
+ * Mapping to a problem of n x n cells with H = W = n (Dirichlet sides and
+ * bottom, free top): pixel (py, px) is node (i = px, j = py + 1).
+ *   elwh_ws_features  x = (log rho / 0.2, log mu / 0.2, log(lambda/mu) / 0.5,
+ *                     f_x / max|f|, f_y / max|f|, 5 omega / n, omega / 60),
+ *                     w = M weight of the node (0 on Dirichlet nodes)
+ *   elwh_ws_from_field targets y = v omega^2 / (max|f| k), k the output scale
+ *   elwh_ws_predict   forward pass, then x0 = y max|f| k / omega^2 on the
+ *                     unknown nodes (0 elsewhere), written to x0[b] (caller
+ *                     layout [2][n+1][n+1])
+ * Field arguments are host arrays of DEVICE pointers (one per sample);
+ * omega_dev is a device array of B doubles.
+ *   elwh_ws_loss_grad  L = (1/B) sum_b ||y_hat - y||_w^2 / ||y||_w^2 and its
+ *                      gradient (copied to grad_host when non-null)
+ *   elwh_ws_train_step one Adam step (beta 0.9, 0.999, eps 1e-8) at rate lr
+ *   elwh_ws_params     read (get) / write (set) the FP32 parameters (setting
+ *                      resets the Adam state) and the output scale k
+ * Calls run on the given stream; forward/train/loss_grad/params synchronise
+ * when they return host data.  Errors: ELWH_ERR_ARG, ELWH_ERR_ALLOC,
+ * ELWH_ERR_HIP.
+ */
+typedef struct elwh_ws elwh_ws;
+elwh_status elwh_ws_create(int max_batch, int H, int W, unsigned long long seed, void* stream, elwh_ws** out);
+void elwh_ws_destroy(elwh_ws* ws);
+const char* elwh_ws_last_error(const elwh_ws* ws);
+long long elwh_ws_num_params(const elwh_ws* ws);
+elwh_status elwh_ws_params(elwh_ws* ws, float* get, const float* set, double* out_scale_get,
+                           const double* out_scale_set);
+elwh_status elwh_ws_forward(elwh_ws* ws, int B, const float* x, float* y);
+elwh_status elwh_ws_loss_grad(elwh_ws* ws, int B, const float* x, const float* y, const float* w, float* loss,
+                              float* grad_host);
+elwh_status elwh_ws_train_step(elwh_ws* ws, int B, const float* x, const float* y, const float* w, float lr,
+                               float* loss);
+elwh_status elwh_ws_features(elwh_ws* ws, int B, int n, const double* const* rho, const double* const* lam,
+                             const double* const* mu, const double* const* f, const double* omega_dev, float* x,
+                             float* w);
+elwh_status elwh_ws_from_field(elwh_ws* ws, int B, int n, const double* const* f, const double* const* v,
+                               const double* omega_dev, float* y);
+elwh_status elwh_ws_predict(elwh_ws* ws, int B, int n, const float* x, const double* const* f,
+                            const double* omega_dev, double* const* x0);
+
 #ifdef __cplusplus
 }
 #endif

@@ -30,6 +30,9 @@ EXPORTED = [
     "elwh_set_tile", "elwh_get_tile", "elwh_autotune",
     "elwh_batch_create", "elwh_batch_solve", "elwh_batch_set_graph", "elwh_batch_info", "elwh_batch_stats",
     "elwh_batch_last_error", "elwh_batch_destroy",
+    "elwh_ws_create", "elwh_ws_destroy", "elwh_ws_last_error", "elwh_ws_num_params", "elwh_ws_params",
+    "elwh_ws_forward", "elwh_ws_loss_grad", "elwh_ws_train_step", "elwh_ws_features", "elwh_ws_from_field",
+    "elwh_ws_predict",
 ]
 
 
@@ -99,12 +102,27 @@ def _load():
     lib.elwh_batch_last_error.restype = ctypes.c_char_p
     lib.elwh_batch_destroy.argtypes = [P]
     lib.elwh_batch_destroy.restype = None
+    F = ctypes.POINTER(ctypes.c_float)
+    lib.elwh_ws_create.argtypes = [I, I, I, ctypes.c_ulonglong, P, ctypes.POINTER(P)]
+    lib.elwh_ws_destroy.argtypes = [P]
+    lib.elwh_ws_destroy.restype = None
+    lib.elwh_ws_last_error.argtypes = [P]
+    lib.elwh_ws_last_error.restype = ctypes.c_char_p
+    lib.elwh_ws_num_params.argtypes = [P]
+    lib.elwh_ws_num_params.restype = ctypes.c_longlong
+    lib.elwh_ws_params.argtypes = [P, P, P, ctypes.POINTER(D), ctypes.POINTER(D)]
+    lib.elwh_ws_forward.argtypes = [P, I, P, P]
+    lib.elwh_ws_loss_grad.argtypes = [P, I, P, P, P, F, P]
+    lib.elwh_ws_train_step.argtypes = [P, I, P, P, P, ctypes.c_float, F]
+    lib.elwh_ws_features.argtypes = [P, I, I, PP, PP, PP, PP, P, P, P]
+    lib.elwh_ws_from_field.argtypes = [P, I, I, PP, PP, P, P]
+    lib.elwh_ws_predict.argtypes = [P, I, I, P, PP, P, PP]
     lib.elwh_profile_enable.argtypes = [P, I]
     lib.elwh_profile_read.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(I), ctypes.POINTER(D),
                                       ctypes.POINTER(I)]
     for name in EXPORTED:
         if name not in ("elwh_default_opts", "elwh_destroy", "elwh_last_error", "elwh_batch_last_error",
-                        "elwh_batch_destroy"):
+                        "elwh_batch_destroy", "elwh_ws_destroy", "elwh_ws_last_error", "elwh_ws_num_params"):
             getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -368,3 +386,84 @@ class Batch:
         t32 = (ctypes.c_int * 2)()
         lib.elwh_batch_stats(self._h, ctypes.byref(sec), ctypes.byref(ticks), t64, t32)
         return {"seconds": sec.value, "ticks": ticks.value, "tile64": list(t64), "tile32": list(t32)}
+
+
+class WarmStartNet:
+    """The warm-start network of the library (elwh_ws_*).  Tensors are torch
+    float32 CUDA tensors in NHWC layout."""
+
+    def __init__(self, max_batch, H, W=None, seed=0, stream=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("libelwh needs a GPU")
+        W = H if W is None else W
+        self.H, self.W, self.max_batch = H, W, max_batch
+        self.stream = torch.cuda.current_stream() if stream is None else stream
+        h = ctypes.c_void_p()
+        st = lib.elwh_ws_create(int(max_batch), int(H), int(W), int(seed), ctypes.c_void_p(self.stream.cuda_stream),
+                                ctypes.byref(h))
+        if st != OK:
+            raise ElwhError(st, lib.elwh_ws_last_error(None).decode())
+        self._h = h
+        self.nparam = lib.elwh_ws_num_params(h)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.elwh_ws_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != OK:
+            raise ElwhError(st, lib.elwh_ws_last_error(self._h).decode())
+
+    def get_params(self):
+        out = np.empty(self.nparam, dtype=np.float32)
+        k = ctypes.c_double()
+        self._check(lib.elwh_ws_params(self._h, out.ctypes.data, None, ctypes.byref(k), None))
+        return out, k.value
+
+    def set_params(self, theta=None, out_scale=None):
+        t = None if theta is None else np.ascontiguousarray(theta, dtype=np.float32)
+        k = None if out_scale is None else ctypes.byref(ctypes.c_double(float(out_scale)))
+        self._check(lib.elwh_ws_params(self._h, None, t.ctypes.data if t is not None else None, None, k))
+
+    def forward(self, x):
+        B = x.shape[0]
+        y = torch.empty((B, self.H, self.W, 2), dtype=torch.float32, device="cuda")
+        self._check(lib.elwh_ws_forward(self._h, B, x.data_ptr(), y.data_ptr()))
+        return y
+
+    def loss_grad(self, x, y, w, want_grad=True):
+        loss = ctypes.c_float()
+        g = np.empty(self.nparam, dtype=np.float32) if want_grad else None
+        self._check(lib.elwh_ws_loss_grad(self._h, x.shape[0], x.data_ptr(), y.data_ptr(), w.data_ptr(),
+                                          ctypes.byref(loss), g.ctypes.data if g is not None else None))
+        return loss.value, g
+
+    def train_step(self, x, y, w, lr):
+        loss = ctypes.c_float()
+        self._check(lib.elwh_ws_train_step(self._h, x.shape[0], x.data_ptr(), y.data_ptr(), w.data_ptr(),
+                                           float(lr), ctypes.byref(loss)))
+        return loss.value
+
+    def features(self, cases_dev, omega_dev, x_out, w_out):
+        """cases_dev: list of (rho, lam, mu, f) CUDA float64 tensors."""
+        B = len(cases_dev)
+        n = self.H
+        self._check(lib.elwh_ws_features(self._h, B, n, _ptr_array([c[0] for c in cases_dev]),
+                                         _ptr_array([c[1] for c in cases_dev]), _ptr_array([c[2] for c in cases_dev]),
+                                         _ptr_array([c[3] for c in cases_dev]), omega_dev.data_ptr(),
+                                         x_out.data_ptr(), w_out.data_ptr()))
+
+    def from_field(self, fs, vs, omega_dev, y_out):
+        self._check(lib.elwh_ws_from_field(self._h, len(fs), self.H, _ptr_array(fs), _ptr_array(vs),
+                                           omega_dev.data_ptr(), y_out.data_ptr()))
+
+    def predict(self, x, fs, omega_dev, x0s):
+        self._check(lib.elwh_ws_predict(self._h, len(fs), self.H, x.data_ptr(), _ptr_array(fs),
+                                        omega_dev.data_ptr(), _ptr_array(x0s)))

@@ -234,6 +234,11 @@ def config4(nprob=48, seed=4, nmin=256, nmax=1024, wmin=10.0, wmax=80.0):
     return cases
 
 
+def config5_omega(seed):
+    """The omega that config5_problem(seed) draws (its first draw)."""
+    return float(np.random.default_rng(50_000 + seed).uniform(20.0, 60.0))
+
+
 def config5_problem(seed, n=256):
     """Warm-start training/evaluation problem: n = 256, omega ~ U[20, 60],
     config-2 media, 1-4 Gaussians of width U[2h, 6h]."""

@@ -1,0 +1,249 @@
+"""Learned warm start: dataset generation with the batched solver, training
+with the library's network kernels, and the held-out comparison of
+time-to-residual against the plain solve.
+
+Every numerical step runs in libelwh (batched El-WaveHoltz solves, feature
+maps, network forward/backward/Adam, prediction); this module sequences the
+calls and keeps the tensors (torch provides the device memory).
+
+Workload (seeded, synthetic): 2-D problems of 256 x 256 cells, random
+log-normal media, omega ~ U[20, 60], one to four Gaussian sources of width
+U[2h, 6h], Dirichlet sides and bottom, traction-free top.  Training labels are
+the FP64 solutions to relative residual 1e-10 produced by the method itself.
+"""
+
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import elwh, inputs
+
+N_CELLS = 256
+WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "warmstart_unet.npz")
+
+
+def log(*a):
+    print("[warmstart]", *a, file=sys.stderr, flush=True)
+
+
+def _dev_case(c):
+    return tuple(torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (c.rho, c.lam, c.mu, c.f))
+
+
+def make_dataset(seeds, net, batch=48, tol=1e-10, maxit=4000, time_budget=None):
+    """Solve every seed's problem in batches (FP64, tol) and return network
+    inputs x, targets y (unscaled: output scale 1), loss weights w and
+    per-problem iteration counts.  Seeds are grouped by omega so the problems
+    of one batch need similar work (the solve of a batch lasts as long as its
+    slowest problem).  Stops early (keeping what is done) past time_budget s."""
+    n = net.H
+    seeds = sorted(seeds, key=inputs.config5_omega)
+    N = len(seeds)
+    x = torch.empty((N, n, n, 7), dtype=torch.float32, device="cuda")
+    y = torch.empty((N, n, n, 2), dtype=torch.float32, device="cuda")
+    w = torch.empty((N, n, n), dtype=torch.float32, device="cuda")
+    iters = []
+    t0 = time.time()
+    for k in range(0, N, batch):
+        chunk = seeds[k:k + batch]
+        cases = [inputs.config5_problem(s, n=n) for s in chunk]
+        bt = elwh.Batch(cases)
+        vs, infos, status = bt.solve([c.f for c in cases], tol=tol, maxit=maxit)
+        bt.close()
+        if status != "OK":
+            log(f"batch at {k}: status {status}")
+        iters += [i["iters"] for i in infos]
+        dev = [_dev_case(c) for c in cases]
+        om = torch.tensor([c.omega for c in cases], dtype=torch.float64, device="cuda")
+        B = len(cases)
+        net.features(dev, om, x[k:k + B], w[k:k + B])
+        net.from_field([d[3] for d in dev], vs, om, y[k:k + B])
+        log(f"data {k + B}/{N}: {time.time() - t0:.1f} s, mean iters {np.mean(iters):.1f}")
+        if time_budget is not None and time.time() - t0 > time_budget:
+            N = k + B
+            log(f"time budget reached: keeping {N} samples")
+            break
+    return {"x": x[:N], "y": y[:N], "w": w[:N], "iters": np.array(iters), "seeds": seeds[:N]}
+
+
+def train(net, data, epochs=20, bs=16, lr=3e-4, lr_min=1e-5, seed=0, log_every=1, time_budget=None):
+    """Adam on the relative M-weighted error, cosine-decayed learning rate;
+    stops after the epoch that passes time_budget seconds."""
+    N = data["x"].shape[0]
+    rng = np.random.default_rng(seed)
+    steps = epochs * (N // bs)
+    hist = []
+    step = 0
+    t0 = time.time()
+    for ep in range(epochs):
+        if time_budget is not None and time.time() - t0 > time_budget:
+            log(f"time budget reached after {ep} epochs")
+            break
+        perm = rng.permutation(N)
+        tot = 0.0
+        for b in range(N // bs):
+            idx = torch.from_numpy(np.sort(perm[b * bs:(b + 1) * bs])).cuda()
+            xb = data["x"].index_select(0, idx).contiguous()
+            yb = data["y"].index_select(0, idx).contiguous()
+            wb = data["w"].index_select(0, idx).contiguous()
+            lr_t = lr_min + 0.5 * (lr - lr_min) * (1 + math.cos(math.pi * step / max(steps, 1)))
+            tot += net.train_step(xb, yb, wb, lr_t)
+            step += 1
+        hist.append(tot / (N // bs))
+        if (ep + 1) % log_every == 0:
+            log(f"epoch {ep + 1}/{epochs}: loss {hist[-1]:.4f} ({time.time() - t0:.1f} s)")
+    return hist
+
+
+def eval_loss(net, data, bs=16):
+    N = data["x"].shape[0]
+    tot = 0.0
+    for b in range(0, N - bs + 1, bs):
+        tot += net.loss_grad(data["x"][b:b + bs], data["y"][b:b + bs], data["w"][b:b + bs], want_grad=False)[0]
+    return tot / (N // bs)
+
+
+def save_weights(net, path=WEIGHTS, meta=None):
+    theta, k = net.get_params()
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    np.savez(path, theta=theta.astype(np.float32), out_scale=np.array([k]),
+             meta=np.array(json.dumps(meta or {})))
+
+
+def load_weights(net, path=WEIGHTS):
+    z = np.load(path, allow_pickle=False)
+    net.set_params(z["theta"], out_scale=float(z["out_scale"][0]))
+    return json.loads(str(z["meta"])) if "meta" in z else {}
+
+
+def predict_x0(net, cases):
+    """Initial guesses for a list of problems (device fields)."""
+    n = net.H
+    dev = [_dev_case(c) for c in cases]
+    om = torch.tensor([c.omega for c in cases], dtype=torch.float64, device="cuda")
+    B = len(cases)
+    x = torch.empty((B, n, n, 7), dtype=torch.float32, device="cuda")
+    w = torch.empty((B, n, n), dtype=torch.float32, device="cuda")
+    net.features(dev, om, x, w)
+    x0 = [torch.empty((2, n + 1, n + 1), dtype=torch.float64, device="cuda") for _ in cases]
+    net.predict(x, [d[3] for d in dev], om, x0)
+    return x0
+
+
+def evaluate(net, seeds, batch=48, tol=1e-8, maxit=4000):
+    """Held-out comparison on the same GPU, per batch of problems:
+    plain   FP64 stepping, zero initial guess
+    learned FP32 stepping + FP64 refinement from the network's x0 (the time
+            includes feature maps and inference)
+    plus the two controls (FP64 from x0; FP32 from zero) that separate the
+    warm start's effect from the precision's.  Batch creation is excluded."""
+    res = {k: {"seconds": 0.0, "iters": [], "relres": [], "status": []}
+           for k in ("plain_fp64", "learned_fp32", "learned_fp64", "zero_fp32")}
+    for k in range(0, len(seeds), batch):
+        cases = [inputs.config5_problem(s, n=net.H) for s in seeds[k:k + batch]]
+        f = [c.f for c in cases]
+        b64 = elwh.Batch(cases)
+        b32 = elwh.Batch(cases, prec=elwh.FP32_STEP)
+        torch.cuda.synchronize()
+        _, inf, st = b64.solve(f, tol=tol, maxit=maxit)
+        res["plain_fp64"]["seconds"] += b64.stats()["seconds"]
+        res["plain_fp64"]["iters"] += [i["iters"] for i in inf]
+        res["plain_fp64"]["relres"] += [i["relres_fp64"] for i in inf]
+        res["plain_fp64"]["status"].append(st)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x0 = predict_x0(net, cases)
+        torch.cuda.synchronize()
+        t_inf = time.perf_counter() - t0
+        _, inf, st = b32.solve(f, x0s=x0, tol=tol, maxit=maxit)
+        res["learned_fp32"]["seconds"] += t_inf + b32.stats()["seconds"]
+        res["learned_fp32"]["iters"] += [i["iters"] for i in inf]
+        res["learned_fp32"]["relres"] += [i["relres_fp64"] for i in inf]
+        res["learned_fp32"]["status"].append(st)
+        _, inf, st = b64.solve(f, x0s=x0, tol=tol, maxit=maxit)
+        res["learned_fp64"]["seconds"] += t_inf + b64.stats()["seconds"]
+        res["learned_fp64"]["iters"] += [i["iters"] for i in inf]
+        res["learned_fp64"]["relres"] += [i["relres_fp64"] for i in inf]
+        res["learned_fp64"]["status"].append(st)
+        _, inf, st = b32.solve(f, tol=tol, maxit=maxit)
+        res["zero_fp32"]["seconds"] += b32.stats()["seconds"]
+        res["zero_fp32"]["iters"] += [i["iters"] for i in inf]
+        res["zero_fp32"]["relres"] += [i["relres_fp64"] for i in inf]
+        res["zero_fp32"]["status"].append(st)
+        b64.close()
+        b32.close()
+        log(f"eval {k + len(cases)}/{len(seeds)}: plain {res['plain_fp64']['seconds']:.1f} s, "
+            f"learned {res['learned_fp32']['seconds']:.1f} s")
+    out = {}
+    z = np.array(res["plain_fp64"]["iters"], float)
+    for key, r in res.items():
+        it = np.array(r["iters"], float)
+        out[key] = {"seconds": r["seconds"], "mean_iters": float(it.mean()), "median_iters": float(np.median(it)),
+                    "max_relres_fp64": float(np.max(r["relres"])), "all_ok": all(s == "OK" for s in r["status"])}
+    lf = np.array(res["learned_fp64"]["iters"], float)
+    out["iteration_reduction_fp64"] = {"mean": float(np.mean(1 - lf / z)), "median": float(np.median(1 - lf / z))}
+    out["speedup_learned_fp32_vs_plain_fp64"] = res["plain_fp64"]["seconds"] / res["learned_fp32"]["seconds"]
+    out["n_problems"] = len(seeds)
+    return out
+
+
+def main(argv=None):
+    import argparse
+    ap = argparse.ArgumentParser(description="learned warm start: train or evaluate")
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("train")
+    t.add_argument("--n-train", type=int, default=4096)
+    t.add_argument("--n-val", type=int, default=96)
+    t.add_argument("--batch", type=int, default=96)
+    t.add_argument("--epochs", type=int, default=40)
+    t.add_argument("--gen-budget", type=float, default=660.0)
+    t.add_argument("--train-budget", type=float, default=300.0)
+    t.add_argument("--out", default=WEIGHTS)
+    e = sub.add_parser("eval")
+    e.add_argument("--first-seed", type=int, default=4096)
+    e.add_argument("--n", type=int, default=512)
+    e.add_argument("--batch", type=int, default=48)
+    e.add_argument("--weights", default=WEIGHTS)
+    e.add_argument("--json", default=None)
+    a = ap.parse_args(argv)
+    torch.cuda.set_device(0)
+    net = WarmStart = elwh.WarmStartNet(max_batch=96, H=N_CELLS, seed=1234)
+    if a.cmd == "train":
+        t0 = time.time()
+        data = make_dataset(list(range(a.n_train)), net, batch=a.batch, time_budget=a.gen_budget)
+        val = make_dataset(list(range(a.n_train, a.n_train + a.n_val)), net, batch=a.batch)
+        # output scale: unit RMS targets
+        k = float(torch.sqrt(torch.mean(data["y"].double() ** 2)).item())
+        data["y"] /= k
+        val["y"] /= k
+        net.set_params(out_scale=k)
+        log(f"dataset {data['x'].shape[0]} + {val['x'].shape[0]} samples in {time.time() - t0:.1f} s, "
+            f"output scale {k:.4f}, mean plain iterations {data['iters'].mean():.1f}")
+        v0 = eval_loss(net, val)
+        hist = train(net, data, epochs=a.epochs, time_budget=a.train_budget)
+        v1 = eval_loss(net, val)
+        log(f"validation loss {v0:.4f} -> {v1:.4f}")
+        meta = {"n_train": int(data["x"].shape[0]), "n_val": int(val["x"].shape[0]), "epochs": len(hist),
+                "train_loss": [round(h, 5) for h in hist], "val_loss_before": v0, "val_loss_after": v1,
+                "output_scale": k, "label_tol": 1e-10, "seed_range_train": [0, a.n_train],
+                "seed_range_val": [a.n_train, a.n_train + a.n_val]}
+        save_weights(net, a.out, meta)
+        print(json.dumps(meta))
+    else:
+        meta = load_weights(net, a.weights)
+        seeds = list(range(a.first_seed, a.first_seed + a.n))
+        out = evaluate(net, seeds, batch=a.batch)
+        out["weights_meta"] = {k: meta.get(k) for k in ("n_train", "epochs", "val_loss_after")}
+        print(json.dumps(out))
+        if a.json:
+            with open(a.json, "w") as fh:
+                json.dump(out, fh, indent=1)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,138 @@
+"""GPU checks of the warm-start network kernels against the FP64 oracle
+network (forward values and gradients), training progress, and the maps
+between problem data and network tensors."""
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import unet
+from paper_2205_12344_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[gpu-ws]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def E():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2205_12344_amd import elwh
+    return elwh
+
+
+def _setup(seed, B, H):
+    rng = np.random.default_rng(seed)
+    theta = np.zeros(unet.num_params())
+    off = 0
+    for ci, co, _ in unet.LAYERS:
+        theta[off:off + 9 * ci * co] = rng.standard_normal(9 * ci * co) * np.sqrt(2.0 / (9 * ci))
+        off += 9 * ci * co
+        theta[off:off + co] = 0.1 * rng.standard_normal(co)
+        off += co
+    theta = theta.astype(np.float32).astype(np.float64)
+    x = rng.standard_normal((B, H, H, 7)).astype(np.float32)
+    y = rng.standard_normal((B, H, H, 2)).astype(np.float32)
+    w = rng.uniform(0.5, 1.5, (B, H, H)).astype(np.float32)
+    return theta, x, y, w
+
+
+def _t(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def test_forward_and_gradient_match_oracle(E):
+    """BF16 GEMM operands: forward within 3e-2 and the gradient within 1e-1
+    (relative L2) of the FP64 oracle, gradient direction cosine >= 0.99."""
+    B, H = 2, 32
+    theta, x, y, w = _setup(3, B, H)
+    net = E.WarmStartNet(B, H)
+    assert net.nparam == unet.num_params()
+    net.set_params(theta)
+    yh = net.forward(_t(x)).cpu().numpy().astype(np.float64)
+    L, g = net.loss_grad(_t(x), _t(y), _t(w))
+    Lr, gr, yr = unet.loss_and_grad(theta, x.astype(np.float64), y.astype(np.float64), w.astype(np.float64))
+    ef = np.linalg.norm(yh - yr) / np.linalg.norm(yr)
+    eg = np.linalg.norm(g - gr) / np.linalg.norm(gr)
+    cos = float(np.dot(g, gr) / (np.linalg.norm(g) * np.linalg.norm(gr)))
+    _say("forward rel err", ef, "loss", L, Lr, "grad rel err", eg, "cos", cos)
+    assert ef <= 3e-2
+    assert L == pytest.approx(Lr, rel=3e-2)
+    assert eg <= 1e-1 and cos >= 0.99
+    # per layer: every layer's gradient is close, not only the largest ones
+    off = 0
+    for k, (ci, co, _) in enumerate(unet.LAYERS):
+        n = 9 * ci * co + co
+        a, b = g[off:off + n], gr[off:off + n]
+        c = float(np.dot(a, b) / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-300))
+        assert c >= 0.97, (k, c)
+        off += n
+
+
+def test_adam_step_is_exact(E):
+    """One training step moves every parameter by the Adam update of the
+    gradient at the start (first step: -lr g / (|g| + eps))."""
+    B, H = 2, 32
+    theta, x, y, w = _setup(6, B, H)
+    net = E.WarmStartNet(B, H)
+    net.set_params(theta)
+    xs, ys, ws = _t(x), _t(y), _t(w)
+    _, g = net.loss_grad(xs, ys, ws)
+    lr = 1e-3
+    net.train_step(xs, ys, ws, lr)
+    t1, _ = net.get_params()
+    g = g.astype(np.float64)
+    expect = theta - lr * g / (np.abs(g) + 1e-8)
+    np.testing.assert_allclose(t1, expect, rtol=0, atol=2e-6 + 1e-5 * np.abs(theta).max())
+
+
+def test_training_reduces_loss(E):
+    B, H = 4, 32
+    theta, x, y, w = _setup(4, B, H)
+    y = 0.3 * np.tanh(x[..., :2]).astype(np.float32)        # a learnable target
+    net = E.WarmStartNet(B, H, seed=5)
+    xs, ys, ws = _t(x), _t(y), _t(w)
+    l0 = net.loss_grad(xs, ys, ws, want_grad=False)[0]
+    hist = [net.train_step(xs, ys, ws, 3e-4) for _ in range(80)]
+    l1 = net.loss_grad(xs, ys, ws, want_grad=False)[0]
+    _say("training loss", l0, "->", l1, [round(h, 3) for h in hist[::10]])
+    assert l1 < 0.5 * l0
+
+
+def test_feature_and_field_maps(E):
+    import torch
+    n = 32
+    cases = [inputs.random_problem_2d(n, 11.0 + 3 * k, seed=300 + k) for k in range(2)]
+    net = E.WarmStartNet(2, n)
+    dev = [tuple(torch.from_numpy(a).cuda() for a in (c.rho, c.lam, c.mu, c.f)) for c in cases]
+    om = torch.tensor([c.omega for c in cases], dtype=torch.float64, device="cuda")
+    x = torch.empty((2, n, n, 7), dtype=torch.float32, device="cuda")
+    w = torch.empty((2, n, n), dtype=torch.float32, device="cuda")
+    net.features(dev, om, x, w)
+    x = x.cpu().numpy()
+    w = w.cpu().numpy()
+    for b, c in enumerate(cases):
+        fm = np.abs(c.f).max()
+        sl = (slice(1, n + 1), slice(0, n))      # node rows j = 1..n, columns i = 0..n-1
+        np.testing.assert_allclose(x[b, ..., 0], np.log(c.rho[sl]) / 0.2, rtol=1e-6, atol=1e-6)
+        np.testing.assert_allclose(x[b, ..., 2], np.log(c.lam[sl] / c.mu[sl]) / 0.5, rtol=1e-6, atol=1e-6)
+        np.testing.assert_allclose(x[b, ..., 4], c.f[1][sl] / fm, rtol=1e-6, atol=1e-7)
+        assert np.allclose(x[b, ..., 6], c.omega / 60)
+        assert np.all(w[b, :, 0] == 0) and np.all(w[b, :, 1:] > 0)
+        np.testing.assert_allclose(w[b, -1, 1:], 0.5 * c.rho[n, 1:n], rtol=1e-6)
+    # from_field then predict-style inverse map on a random field: round trip
+    rng = np.random.default_rng(0)
+    v = [torch.from_numpy(rng.standard_normal((2, n + 1, n + 1))).cuda() for _ in cases]
+    y = torch.empty((2, n, n, 2), dtype=torch.float32, device="cuda")
+    net.set_params(out_scale=0.37)
+    net.from_field([d[3] for d in dev], v, om, y)
+    yy = y.cpu().numpy()
+    for b, c in enumerate(cases):
+        s = c.omega ** 2 / (np.abs(c.f).max() * 0.37)
+        np.testing.assert_allclose(yy[b, ..., 1], v[b].cpu().numpy()[1][1:, :n] * s, rtol=1e-5, atol=1e-5)
