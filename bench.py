@@ -2,16 +2,17 @@
 
 A step is one Krylov iteration of the solve on the 2-D 1024 x 1024 random
 log-normal medium with a traction-free top (FP64): one A_h = I - S_h
-application (the half-step launch and N_T - 1 fused step launches over
-every unknown node, each with its trapezoid accumulation) plus the FP64
-M-inner-product reductions and the CG vector updates.  Inputs are resident
+application (the half-step launch and (N_T - 1) / 2 fused step-pair
+launches over every unknown node, each with its trapezoid accumulation)
+plus the FP64 M-inner-product reductions and the CG vector updates.  Inputs are resident
 in HBM before timing.  value = lattice updates per second, one lattice
 update = one unknown node advanced one time step (both components), with its
 accumulation.
 
-The JSON line also carries the roofline of the fused step kernel (HIP-event
-durations of every step launch over a profiled repeat of the timed steps),
-the FP32-stepping variants, and the CPU oracle's rate on a bounded sample.
+The JSON line also carries the roofline of the fused step-pair kernel
+(HIP-event durations of the step launches over a profiled repeat of the
+timed steps), the FP32-stepping and single-step variants, and the CPU
+oracle's rate on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--all]
 """
@@ -30,7 +31,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "elastic lattice updates/s (% HBM roofline); time-to-1e-8 residual learned+FP32 vs plain"
 
-# Algorithmic HBM bytes per lattice update of the fused step kernel:
+# Algorithmic HBM bytes per lattice update (one unknown node, one step).
+# Single-step kernel (fuse = 1; the 3-D kernel):
 #   FP64: read u^n (2x8), u^{n-1} (2x8), a, lambda, mu (3x8), acc (2x8);
 #         write u^{n+1} (2x8), acc (2x8)                                  = 104
 #   FP32 state, compensated FP64 accumulator: state 3x2x4, coefficients
@@ -38,10 +40,32 @@ METRIC = "elastic lattice updates/s (% HBM roofline); time-to-1e-8 residual lear
 #   FP32 state, plain FP64 accumulator: 24 + 12 + 32                      = 68
 #   3-D: three components; FP64 3x3x8 + 3x8 + 2x3x8 = 144; FP32
 #         compensated 36 + 12 + 96 = 144; FP32 plain 36 + 12 + 48 = 96
+# Step-pair kernel (2-D, fuse = 2), per launch = two lattice updates:
+#   FP64: read u^n, u^{n-1} (2x2x8), a, lambda, mu (3x8), acc (2x8);
+#         write u^{n+1}, u^{n+2} (2x2x8), acc (2x8) = 120, i.e. 60 per LUP
+#   FP32 compensated: state 4x2x4 + 3x4 + acc hi+lo 4x2x8 = 108 -> 54
+#   FP32 plain accumulator: 32 + 12 + 32 = 76 -> 38
 BYTES_PER_LUP = {
-    (2, "f64"): 104, (2, "f32c"): 100, (2, "f32"): 68,
-    (3, "f64"): 144, (3, "f32c"): 144, (3, "f32"): 96,
+    (2, "f64", 1): 104, (2, "f32c", 1): 100, (2, "f32", 1): 68,
+    (2, "f64", 2): 60, (2, "f32c", 2): 54, (2, "f32", 2): 38,
+    (3, "f64", 1): 144, (3, "f32c", 1): 144, (3, "f32", 1): 96,
 }
+
+
+def step_launches(nt, fuse):
+    """(pair launches, single-step launches) after the half step."""
+    if fuse == 2:
+        return (nt - 1) // 2, (nt - 1) % 2
+    return 0, nt - 1
+
+
+def phase_bytes(dim, tag, fuse, nt, nodes):
+    """Algorithmic bytes of the N_T - 1 steps after the half step, and the
+    number of launches that move them."""
+    pairs, singles = step_launches(nt, fuse)
+    b = pairs * 2 * BYTES_PER_LUP[(dim, tag, 2 if fuse == 2 else 1)] * nodes
+    b += singles * BYTES_PER_LUP[(dim, tag, 1)] * nodes
+    return b, pairs + singles
 
 
 def log(*a):
@@ -83,7 +107,7 @@ def read_traffic(kernel_tag, tile):
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ("kernels2d.hip", "kernels3d.hip", "lanes.h"):
+    for f in ("kernels2d.hip", "kernels2d_pair.hip", "step2d_common.h", "kernels3d.hip", "lanes.h"):
         h.update(open(os.path.join(ROOT, "paper_2205_12344_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -205,34 +229,42 @@ def main():
     lup_per_step = nt * nodes
     value = lup_per_step * args.steps / el
     ms_per_step = 1e3 * el / args.steps
-    step_avg_ms = prof["step_ms"] / max(prof["nstep"], 1)
-    b = BYTES_PER_LUP[(2, "f64")]
-    achieved = b * nodes / (step_avg_ms * 1e-3) / 1e9
-    traffic = read_traffic("step2d_f64_cfg2_1024", (tv, tr))
+    # every application runs N_T - 1 steps after the half step
+    napp = prof["nstep"] // max(nt - 1, 1)
+    bytes_app, launches_app = phase_bytes(2, "f64", 2, nt, nodes)
+    step_avg_ms = prof["step_ms"] / max(napp * launches_app, 1)
+    achieved = bytes_app * napp / (prof["step_ms"] * 1e-3) / 1e9
+    traffic = read_traffic("pair2d_f64_cfg2_1024", (tv, tr))
     log(f"tile V={tv} TY={tr}")
-    log(f"fp64: {ms_per_step:.3f} ms/step, {value / 1e9:.2f} GLUP/s, step kernel {1e3 * step_avg_ms:.1f} us "
-        f"({prof['nstep']} launches), {achieved:.0f} GB/s")
+    log(f"fp64: {ms_per_step:.3f} ms/step, {value / 1e9:.2f} GLUP/s, step-pair kernel {1e3 * step_avg_ms:.1f} us "
+        f"({napp * launches_app} launches), {achieved:.0f} GB/s")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic,
-                "kernel": f"step2d_kernel<double,double,V={tv},TY={tr},MODE=0,FORCE=0,COMP=0>",
-                "bytes_per_lup": b, "units_per_launch": nodes,
+                "kernel": f"pair2d_kernel<double,V={tv},TY={tr},FORCE=0,COMP=0>",
+                "bytes_per_lup": BYTES_PER_LUP[(2, "f64", 2)], "lup_per_launch": 2 * nodes,
+                "bytes_per_launch": 2 * BYTES_PER_LUP[(2, "f64", 2)] * nodes,
                 "avg_launch_us": round(1e3 * step_avg_ms, 3)}
     ctx.close()
 
     variants = {}
-    for tag, kw in (("f32c", {"prec": elwh.FP32_STEP, "compensated": 1}),
-                    ("f32", {"prec": elwh.FP32_STEP, "compensated": 0})):
+    for tag, prec, kw in (("f32c", "f32c", {"prec": elwh.FP32_STEP, "compensated": 1}),
+                          ("f32", "f32", {"prec": elwh.FP32_STEP, "compensated": 0}),
+                          ("f64_single_step", "f64", {"fuse": 1}),
+                          ("f32c_single_step", "f32c", {"prec": elwh.FP32_STEP, "compensated": 1, "fuse": 1})):
+        fuse = kw.get("fuse", 2)
         c2 = elwh.context_from_case(case, **kw)
         p = kernel_rate(c2, 10)
-        v32 = c2.get_tile(elwh.FP32_STEP)
-        avg = p["step_ms"] / max(p["nstep"], 1)
-        bb = BYTES_PER_LUP[(2, tag)]
-        variants[tag] = {"tile": list(v32), "step_kernel_us": round(1e3 * avg, 3),
-                         "glup_s_kernel": round(nodes / avg / 1e6, 3),
-                         "bytes_per_lup": bb, "achieved_GBs": round(bb * nodes / avg / 1e6, 1),
-                         "frac": round(bb * nodes / avg / 1e6 / HBM_PEAK_GBS, 4)}
-        log(f"{tag}: step kernel {1e3 * avg:.1f} us, {variants[tag]['achieved_GBs']} GB/s")
+        t2 = c2.get_tile(elwh.FP64 if prec == "f64" else elwh.FP32_STEP)
+        napp = p["nstep"] // max(nt - 1, 1)
+        bapp, lapp = phase_bytes(2, prec, fuse, nt, nodes)
+        gbs = bapp * napp / (p["step_ms"] * 1e-3) / 1e9
+        variants[tag] = {"tile": list(t2), "steps_per_launch": fuse,
+                         "launch_us": round(1e3 * p["step_ms"] / max(napp * lapp, 1), 3),
+                         "glup_s_kernel": round(napp * (nt - 1) * nodes / (p["step_ms"] * 1e-3) / 1e9, 3),
+                         "bytes_per_lup": BYTES_PER_LUP[(2, prec, fuse)], "achieved_GBs": round(gbs, 1),
+                         "frac": round(gbs / HBM_PEAK_GBS, 4)}
+        log(f"{tag}: {variants[tag]}")
         c2.close()
 
     if args.all:
@@ -242,7 +274,7 @@ def main():
             ctx3 = elwh.context_from_case(c3, **kw)
             p = kernel_rate(ctx3, 2)
             avg = p["step_ms"] / max(p["nstep"], 1)
-            bb = BYTES_PER_LUP[(3, tag)]
+            bb = BYTES_PER_LUP[(3, tag, 1)]
             t3 = ctx3.get_tile(elwh.FP32_STEP if tag != "f64" else elwh.FP64)
             variants["3d_" + tag] = {"workload": c3.name, "nt": ctx3.info()["nt"], "tile": list(t3),
                                      "step_kernel_us": round(1e3 * avg, 3),

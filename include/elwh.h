@@ -74,20 +74,24 @@ typedef struct {
     int nt;            /* steps per period; 0 = the rule N_T = max(3, ceil(T/dt*)) */
     int periods;       /* K of the K-period filter, eq. many_periods_filter (default 1) */
     int prec;          /* ELWH_FP64, or ELWH_FP32_STEP: FP32 state and stencil,
-                          FP64 accumulator, FP64 Krylov, FP64 iterative refinement */
+                          FP64 accumulator, FP64 Krylov vectors and inner
+                          products, FP64 residual replacements */
     int krylov;        /* ELWH_KRYLOV_CG (default), _GMRES, _CR */
     int gmres_m;       /* GMRES restart length (default 30) */
     int scheme;        /* ELWH_SCHEME_CORRECTED (default, Sec. 4.3) or _STANDARD */
     int compensated;   /* FP32 path: Neumaier-compensated FP64 accumulator (default 1) */
-    double inner_tol;  /* FP32 path: relative tolerance of each inner FP32 solve (default 1e-4) */
-    int max_outer;     /* FP32 path: maximum refinement steps (default 50) */
+    double inner_tol;  /* FP32 path: reduction of the recursive residual between two
+                          FP64 residual replacements (default 1e-2) */
+    int max_outer;     /* FP32 path: maximum residual replacements (default 50) */
     void* stream;      /* hipStream_t the context works on; NULL = the null stream */
     int autotune;      /* 1 (default): pick the step-kernel tiling by timing at create */
+    int fuse;          /* 2-D: time steps per step-kernel launch, 2 (default: the
+                          step-pair kernel) or 1; 3-D always steps singly */
 } elwh_opts;
 
 typedef struct {
-    int iters;          /* Krylov iterations (summed over refinement steps) */
-    int outer;          /* refinement steps (FP32 path), else 0 */
+    int iters;          /* Krylov iterations */
+    int outer;          /* FP64 residual replacements (FP32 path), else 0 */
     int nt;             /* steps per period N_T */
     int napply;         /* operator applications (each periods*N_T steps) */
     double dt;          /* time step T / N_T */
@@ -154,9 +158,12 @@ elwh_status elwh_apply_A(elwh_ctx* ctx, const double* x, double* y);
  * method in opts (CG in the M inner product by default), from x0 (NULL =
  * zero guess) until ||r||_M <= tol ||b||_M or maxit iterations.  tol <= 0
  * runs exactly maxit iterations and returns ELWH_OK.  The final residual is
- * recomputed with an FP64 apply (info->relres_fp64).  FP32 path: FP64
- * iterative refinement around FP32-stepped inner solves, stopping on the
- * FP64 residual.  Returns when done (synchronises the stream).
+ * recomputed with an FP64 apply (info->relres_fp64).  FP32 path: CG with
+ * FP32-stepped applications and FP64 vectors; whenever the recursive
+ * residual has fallen by inner_tol, it is replaced by b - A_h x from an FP64
+ * application and CG continues along the same search direction (a reliable
+ * update); the solve stops on the FP64 residual.  Returns when done
+ * (synchronises the stream).
  * Errors: ELWH_ERR_NOT_CONVERGED (v holds the last iterate),
  * ELWH_ERR_BREAKDOWN, ELWH_ERR_ARG, ELWH_ERR_HIP.
  */
@@ -222,7 +229,7 @@ elwh_status elwh_autotune(elwh_ctx* ctx, int prec, int reps, double* best_step_u
  * replayed (elwh_batch_set_graph(b, 0) runs the same launches eagerly).
  * Each problem's solve is the one of elwh_solve (Sec. 4.5): CG on A_h in the
  * M inner product with b = Pi_h 0; FP64, or (opts->prec = ELWH_FP32_STEP)
- * FP64 iterative refinement around FP32-stepped CG.
+ * FP32-stepped CG with FP64 residual replacements.
  *
  * elwh_batch_create: nprob problems; grids[i], rho[i], lam[i], mu[i]
  *   (DEVICE pointers, copied), omega[i], bc[6*i .. 6*i+5]; opts shared

@@ -103,7 +103,8 @@ void free_all(elwh_ctx* c) {
     };
     f(c->ca); f(c->cl); f(c->cm); f(c->mw);
     f(c->fa); f(c->fl); f(c->fm);
-    f(c->s64[0]); f(c->s64[1]); f(c->s32[0]); f(c->s32[1]);
+    for (auto* p : c->s64) f(p);
+    for (auto* p : c->s32) f(p);
     f(c->acc); f(c->acc_lo); f(c->f64); f(c->f32);
     for (auto* v : c->vec) f(v);
     for (auto* v : c->basis) f(v);
@@ -405,10 +406,11 @@ void elwh_default_opts(elwh_opts* o) {
     o->gmres_m = 30;
     o->scheme = ELWH_SCHEME_CORRECTED;
     o->compensated = 1;
-    o->inner_tol = 1e-4;
+    o->inner_tol = 1e-2;
     o->max_outer = 50;
     o->stream = nullptr;
     o->autotune = 1;
+    o->fuse = 2;
 }
 
 elwh_status elwh_plan(const elwh_grid* grid, const double* rho, const double* lam, const double* mu, double omega,
@@ -491,10 +493,13 @@ elwh_status elwh_create(const elwh_grid* grid, const double* rho, const double* 
         return fail(st);
     for (auto& v : c->vec)
         if ((st = alloc_t(c, &v, FE))) return fail(st);
+    if (L.dim == 2 && ((st = alloc_t(c, &c->s64[2], FE)) || (st = alloc_t(c, &c->s64[3], FE)))) return fail(st);
     if (o.prec == ELWH_FP32_STEP) {
         if ((st = alloc_t(c, &c->fa, CS)) || (st = alloc_t(c, &c->fl, CS)) || (st = alloc_t(c, &c->fm, CS)) ||
             (st = alloc_t(c, &c->s32[0], FE)) || (st = alloc_t(c, &c->s32[1], FE)) ||
             (st = alloc_t(c, &c->f32, FE)))
+            return fail(st);
+        if (L.dim == 2 && ((st = alloc_t(c, &c->s32[2], FE)) || (st = alloc_t(c, &c->s32[3], FE))))
             return fail(st);
     }
     if ((st = alloc_t(c, &c->partials, (size_t)c->red_blocks)) || (st = alloc_t(c, &c->dscal, (size_t)S_NSLOT)))
@@ -709,7 +714,14 @@ elwh_status elwh_solve(elwh_ctx* c, const double* f, const double* x0, double to
         CKST(final_residual(c, c->vec[VX], bb, &inf.relres_fp64));
         launch_unpack(c->L, c->bc, c->vec[VX], v, c->L.dim, c->stream);
     } else {
-        // FP32 stepping inside FP64 iterative refinement (CG inner solver)
+        // FP32 stepping inside CG with FP64 reliable updates.  x, r, p and
+        // every inner product stay FP64; A_h p is applied with FP32 stepping.
+        // A segment runs until the recursive residual has fallen by inner_tol
+        // (or below the target); then r is replaced by b - A_h x from an FP64
+        // application and the search direction continues from it
+        // (p = r + beta p with beta = (r, r)_M / (r_k, r_k)_M of the last CG
+        // step).  Restarting CG at every replacement instead discards the
+        // Krylov space and costs two to three times the iterations here.
         launch_pack(c->L, c->bc, f, c->f64, c->L.dim, c->stream);
         compute_rhs(c);
         if (x0)
@@ -722,43 +734,57 @@ elwh_status elwh_solve(elwh_ctx* c, const double* f, const double* x0, double to
             c->err = "zero or non-finite right-hand side";
             return ELWH_ERR_ARG;
         }
-        bool xzero = x0 == nullptr;
-        double relfp64 = 1.0;
-        int outer = 0, iters = 0;
-        st = ELWH_ERR_NOT_CONVERGED;
-        for (; outer <= c->opts.max_outer; ++outer) {
-            // r = b - A64 x  (into VRI)
+        auto true_residual = [&](bool xzero, double* rr) -> elwh_status {
             if (xzero) {
-                launch_copy(c, c->vec[VB], c->vec[VRI], c->stream);
+                launch_copy(c, c->vec[VB], c->vec[VR], c->stream);
             } else {
                 apply_A(c, c->vec[VX], c->vec[VT], false);
-                launch_copy(c, c->vec[VB], c->vec[VRI], c->stream);
-                launch_axpby(c, -1.0, c->vec[VT], 1.0, c->vec[VRI], c->stream);
+                launch_copy(c, c->vec[VB], c->vec[VR], c->stream);
+                launch_axpby(c, -1.0, c->vec[VT], 1.0, c->vec[VR], c->stream);
             }
-            double rr;
-            CKST(dot_host(c, c->vec[VRI], c->vec[VRI], &rr));
-            if (!std::isfinite(rr)) {
+            CKST(dot_host(c, c->vec[VR], c->vec[VR], rr));
+            if (!std::isfinite(*rr)) {
                 c->err = "non-finite residual: the time step is unstable";
                 return ELWH_ERR_UNSTABLE;
             }
-            relfp64 = std::sqrt(rr / bb);
-            if ((tol > 0 && relfp64 <= tol) || iters >= maxit || outer == c->opts.max_outer) {
-                if (tol > 0 && relfp64 <= tol) st = ELWH_OK;
+            return ELWH_OK;
+        };
+        double rr;
+        CKST(true_residual(x0 == nullptr, &rr));
+        launch_copy(c, c->vec[VR], c->vec[VP], c->stream);
+        CKST(set_scalar(c, S_RR, rr));
+        CKST(set_scalar(c, S_FLAG, 0.0));
+        double relfp64 = std::sqrt(rr / bb), seg = rr;
+        inf.relres = relfp64;
+        int outer = 0, iters = 0;
+        st = ELWH_ERR_NOT_CONVERGED;
+        while (true) {
+            if (tol > 0 && relfp64 <= tol) {
+                st = ELWH_OK;
+                break;
+            }
+            if (iters >= maxit || outer > c->opts.max_outer) {
                 if (tol <= 0) st = ELWH_OK;
                 break;
             }
-            // inner FP32 CG: A d = r, d in VD, zero start
-            HIPCK(hipMemsetAsync(c->vec[VD], 0, c->L.field_elems() * sizeof(double), c->stream));
-            double bbi, rri;
-            CKST(cg_start(c, c->vec[VRI], c->vec[VD], true, c->vec[VR], c->vec[VP], c->vec[VQ], true, &bbi, &rri));
+            // stop the segment at rr <= max(inner_tol^2 seg, (tol/2)^2 bb)
+            const double tseg = std::max(c->opts.inner_tol, tol > 0 ? 0.5 * tol * std::sqrt(bb / seg) : 0.0);
             CGOut o;
-            elwh_status si = cg_steps(c, c->vec[VD], c->vec[VR], c->vec[VP], c->vec[VQ], true, bbi,
-                                      maxit - iters, c->opts.inner_tol, &o, false);
+            elwh_status si = cg_steps(c, c->vec[VX], c->vec[VR], c->vec[VP], c->vec[VQ], true, seg, maxit - iters,
+                                      tseg, &o, false);
             if (si != ELWH_OK) return si;
             iters += o.iters;
-            inf.relres = o.relres * relfp64;
-            launch_axpby(c, 1.0, c->vec[VD], 1.0, c->vec[VX], c->stream);
-            xzero = false;
+            ++outer;
+            const double rr_new = c->hscal[S_RR], beta_k = c->hscal[S_BETA];
+            inf.relres = std::sqrt(rr_new / bb);
+            const double rr_k = beta_k > 0 ? rr_new / beta_k : 0.0;
+            CKST(true_residual(false, &rr));
+            relfp64 = std::sqrt(rr / bb);
+            seg = rr;
+            if (!o.converged) continue;   // out of iterations: the loop head ends it
+            CKST(set_scalar(c, S_BETA, rr_k > 0 ? rr / rr_k : 0.0));
+            CKST(set_scalar(c, S_RR, rr));
+            launch_cg_update_p(c, c->vec[VP], c->vec[VR], c->stream);
         }
         inf.iters = iters;
         inf.outer = outer;
@@ -818,7 +844,8 @@ elwh_status elwh_set_tile(elwh_ctx* c, int prec, int vec, int rows) {
 }  // extern "C"
 
 namespace {
-using TuneKey = std::tuple<int, int, int, int, int, int>;   // dim, prec, comp, nx, ny, nz
+// dim, prec, variant (bit 0: compensated accumulator, bit 1: 2-D step pairs), nx, ny, nz
+using TuneKey = std::tuple<int, int, int, int, int, int>;
 std::mutex g_tune_mu;
 std::map<TuneKey, Tile> g_tune;
 
@@ -877,7 +904,7 @@ elwh_status elwh_autotune(elwh_ctx* c, int prec, int reps, double* best_step_us)
         c->err = "FP32 tiling needs an FP32 context";
         return ELWH_ERR_ARG;
     }
-    const int comp = fp32 ? (c->opts.compensated ? 1 : 0) : 0;
+    const int comp = (fp32 && c->opts.compensated ? 1 : 0) | (c->L.dim == 2 && c->opts.fuse == 2 ? 2 : 0);
     const TuneKey key(c->L.dim, fp32 ? 1 : 0, comp, c->L.nx, c->L.ny, c->L.nz);
     Tile& dst = fp32 ? c->tile32 : c->tile64;
     {

@@ -182,12 +182,17 @@ elwh_status dots(elwh_batch* b, const std::vector<int>& sel, int ia, int ib, std
 }
 
 elwh_status lincomb(elwh_batch* b, const std::vector<int>& sel, int idst, int ia, double alpha, int ib,
-                    double beta) {
+                    double beta, const std::vector<double>* betas = nullptr) {
     int nb = 0;
     BST(set_phase(b, false, VT, VQ, -1, -1, -1, &nb));
     BST(upload_mask(b, sel));
-    launch_batch_lincomb(b->stream, b->d_pr, b->np, b->d_mask, idst, ia, alpha, ib, beta);
+    if (betas) {
+        // per-problem coefficients staged in the dot-product buffer (free here)
+        BCK(hipMemcpyAsync(b->d_dots, betas->data(), sizeof(double) * b->np, hipMemcpyHostToDevice, b->stream));
+    }
+    launch_batch_lincomb(b->stream, b->d_pr, b->np, b->d_mask, idst, ia, alpha, ib, beta, betas ? b->d_dots : nullptr);
     BCK(hipGetLastError());
+    if (betas) BCK(hipStreamSynchronize(b->stream));
     return ELWH_OK;
 }
 
@@ -503,68 +508,81 @@ elwh_status elwh_batch_solve(elwh_batch* b, const double* const* f, const double
         BST(dots(b, all, VT, VT, rr));
         for (int p = 0; p < np; ++p) relfp64[p] = bb[p] > 0 ? std::sqrt(rr[p] / bb[p]) : 0.0;
     } else {
-        std::vector<int> xnz = has_x;
-        for (int o = 0; o <= b->opts.max_outer; ++o) {
-            // FP64 residual of the current iterate
-            std::vector<int> need(np, 0), pending(np, 0);
-            bool anyx = false;
-            for (int p = 0; p < np; ++p) {
-                need[p] = xnz[p] && (status[p] == ELWH_ERR_NOT_CONVERGED);
-                anyx |= need[p] != 0;
-            }
-            if (anyx) {
-                BST(run_apply(b, false, false, true, VX, VQ, need));
-                BST(lincomb(b, need, VRI, VB, 1.0, VQ, -1.0));
-            }
-            std::vector<int> fresh(np);
-            for (int p = 0; p < np; ++p) fresh[p] = !xnz[p] && status[p] == ELWH_ERR_NOT_CONVERGED;
-            BST(lincomb(b, fresh, VRI, VB, 1.0, -1, 0.0));
-            std::vector<int> live(np);
-            for (int p = 0; p < np; ++p) live[p] = status[p] == ELWH_ERR_NOT_CONVERGED;
-            BST(dots(b, live, VRI, VRI, rr));
+        // FP32 stepping inside CG with FP64 reliable updates (as elwh_solve):
+        // x, r, p stay FP64; each segment runs device-driven CG with FP32
+        // applications until the recursive residual has fallen by inner_tol
+        // (or below the target); then r is replaced by b - A_h x from an FP64
+        // application and the search direction continues from it.
+        bool anyx = false;
+        for (int p = 0; p < np; ++p) anyx |= has_x[p] != 0;
+        if (anyx) {
+            BST(run_apply(b, false, false, true, VX, VQ, has_x));
+            BST(lincomb(b, has_x, VR, VB, 1.0, VQ, -1.0));
+        }
+        std::vector<int> nox(np);
+        for (int p = 0; p < np; ++p) nox[p] = !has_x[p];
+        BST(lincomb(b, nox, VR, VB, 1.0, -1, 0.0));
+        BST(lincomb(b, all, VP, VR, 1.0, -1, 0.0));
+        BST(dots(b, all, VR, VR, rr));
+        std::vector<double> seg = rr, rr_k(np, 0.0), beta(np, 0.0);
+        std::vector<int> done_p(np, 0);
+        for (int p = 0; p < np; ++p) {
+            relfp64[p] = bb[p] > 0 ? std::sqrt(rr[p] / bb[p]) : 0.0;
+            relres[p] = relfp64[p];
+        }
+        for (int o = 0;; ++o) {
+            std::vector<int> pending(np, 0);
             bool any = false;
             for (int p = 0; p < np; ++p) {
-                if (!live[p]) continue;
-                relfp64[p] = bb[p] > 0 ? std::sqrt(rr[p] / bb[p]) : 0.0;
+                if (status[p] != ELWH_ERR_NOT_CONVERGED || done_p[p]) continue;
                 if (!(bb[p] > 0) || (tol > 0 && relfp64[p] <= tol)) {
                     status[p] = ELWH_OK;
                 } else if (!std::isfinite(relfp64[p])) {
                     status[p] = ELWH_ERR_UNSTABLE;
-                } else if (iters[p] >= maxit || o == b->opts.max_outer) {
+                } else if (iters[p] >= maxit || o > b->opts.max_outer) {
                     status[p] = tol > 0 ? ELWH_ERR_NOT_CONVERGED : ELWH_OK;
-                    if (tol <= 0) live[p] = 0;
+                    done_p[p] = 1;
                 } else {
                     pending[p] = 1;
                     any = true;
                 }
             }
             if (!any) break;
-            // inner FP32 CG on A d = r (zero start)
-            BST(lincomb(b, pending, VD, VRI, 0.0, -1, 0.0));
-            BST(lincomb(b, pending, VR, VRI, 1.0, -1, 0.0));
-            BST(lincomb(b, pending, VP, VRI, 1.0, -1, 0.0));
             for (int p = 0; p < np; ++p) {
                 BState& s = b->h_st[p];
                 std::memset(&s, 0, sizeof(s));
                 s.active = pending[p];
-                s.rr = rr[p];
-                s.bb = rr[p];
-                s.tol2 = b->opts.inner_tol * b->opts.inner_tol;
+                s.rr = seg[p];
+                s.bb = 1.0;
+                const double stop = tol > 0 ? 0.25 * tol * tol * bb[p] : 0.0;
+                s.tol2 = std::max(b->opts.inner_tol * b->opts.inner_tol * seg[p], stop);
                 s.maxit = std::max(1, maxit - iters[p]);
                 s.status = ELWH_ERR_NOT_CONVERGED;
             }
-            BST(run_cg(b, true, VD, VR, VP, VQ, tick_budget));
+            BST(run_cg(b, true, VX, VR, VP, VQ, tick_budget));
             for (int p = 0; p < np; ++p) {
                 if (!pending[p]) continue;
-                iters[p] += b->h_st[p].iters;
+                const BState& s = b->h_st[p];
+                iters[p] += s.iters;
                 outer[p] = o + 1;
-                relres[p] = relfp64[p] * std::sqrt(b->h_st[p].rr / std::max(rr[p], 1e-300));
-                if (b->h_st[p].status == ELWH_ERR_BREAKDOWN || b->h_st[p].status == ELWH_ERR_UNSTABLE)
-                    status[p] = b->h_st[p].status;
+                relres[p] = std::sqrt(s.rr / bb[p]);
+                rr_k[p] = s.beta > 0 ? s.rr / s.beta : 0.0;
+                if (s.status == ELWH_ERR_BREAKDOWN || s.status == ELWH_ERR_UNSTABLE) {
+                    status[p] = s.status;
+                    pending[p] = 0;
+                }
             }
-            BST(lincomb(b, pending, VX, VX, 1.0, VD, 1.0));
-            for (int p = 0; p < np; ++p)
-                if (pending[p]) xnz[p] = 1;
+            // residual replacement: r = b - A_h x (FP64), p = r + beta p
+            BST(run_apply(b, false, false, true, VX, VQ, pending));
+            BST(lincomb(b, pending, VR, VB, 1.0, VQ, -1.0));
+            BST(dots(b, pending, VR, VR, rr));
+            for (int p = 0; p < np; ++p) {
+                if (!pending[p]) continue;
+                relfp64[p] = std::sqrt(rr[p] / bb[p]);
+                seg[p] = rr[p];
+                beta[p] = rr_k[p] > 0 ? rr[p] / rr_k[p] : 0.0;
+            }
+            BST(lincomb(b, pending, VP, VR, 1.0, VP, 0.0, &beta));
         }
     }
     for (int p = 0; p < np; ++p) launch_unpack(b->ctx[p]->L, b->ctx[p]->bc, b->ctx[p]->vec[VX], v[p], 2, b->stream);

@@ -62,6 +62,7 @@ struct Args2D {
     int jlo, jhi, free_lo, free_hi;
     double cxx2, cyy2, cxy, cyyf, cfx;
     double w, w0, fc;
+    double w2, fc2;           // step pair: weight of u^{n+2}, forcing factor of step n+1
     int final_;
 };
 
@@ -117,8 +118,9 @@ struct elwh_ctx {
     float *fa = nullptr, *fl = nullptr, *fm = nullptr;
 
     // FP64 state buffers (2 time levels), accumulator and its compensation
-    double *s64[2] = {nullptr, nullptr};
-    float *s32[2] = {nullptr, nullptr};
+    // (four for 2-D: the step-pair kernel writes two new levels beside the two it reads)
+    double *s64[4] = {nullptr, nullptr, nullptr, nullptr};
+    float *s32[4] = {nullptr, nullptr, nullptr, nullptr};
     double *acc = nullptr, *acc_lo = nullptr;
     // forcing (internal layout) in FP64 and FP32
     double* f64 = nullptr;
@@ -168,6 +170,15 @@ void prof_mark(elwh_ctx* c, int phase, int nsteps = 0);
 bool tile_valid_2d(bool fp32, int V, int TY);
 bool tile_valid_3d(bool fp32, int V, int TZ);
 
+// Two time steps per launch (kernels2d_pair.hip): reads u^n (u), u^{n-1}
+// (uprev), writes u^{n+1} (u1out) and u^{n+2} (u2out), four distinct buffers;
+// A.w / A.w2 weigh u^{n+1} / u^{n+2}, A.fc / A.fc2 are the forcing factors of
+// steps n and n+1.
+template <typename T>
+void launch_pair2d(int V, int TY, bool force, bool comp, hipStream_t s, int nrows, const T* u, const T* uprev,
+                   T* u1out, T* u2out, double* acc, double* acclo, const T* ca, const T* cl, const T* cm,
+                   const T* f, const Args2D& A);
+
 // ---- kernels (kernels2d.hip / kernels3d.hip / blas.hip) --------------------
 // Copy a caller-layout field (ncomp components) into the padded layout,
 // zeroing Dirichlet nodes (mask from bc); T = float or double destination.
@@ -207,7 +218,7 @@ void launch_batch_advance(hipStream_t s, const BProb2D* pr, BState* st, int np, 
 void launch_batch_cg(hipStream_t s, int mode, const BProb2D* pr, BState* st, int np, double* partials,
                      int* n_active);
 void launch_batch_lincomb(hipStream_t s, const BProb2D* pr, int np, const int* mask, int idst, int ia,
-                          double alpha, int ib, double beta);
+                          double alpha, int ib, double beta, const double* betav = nullptr);
 void launch_batch_dot(hipStream_t s, const BProb2D* pr, int np, const int* mask, int ia, int ib,
                       double* partials, double* out);
 constexpr int BATCH_RED_BLOCKS = 64;

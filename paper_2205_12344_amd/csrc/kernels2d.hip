@@ -23,39 +23,9 @@
 // row j+2 and of the centre-row arrays of row j+1 are issued one iteration
 // ahead, and x neighbours across lanes come from DPP wavefront shifts.
 // Every array element is read from memory once per row visit.
-#include "elwh_internal.h"
-#include "lanes.h"
+#include "step2d_common.h"
 
 namespace elwh {
-
-template <typename T, int V>
-struct alignas(sizeof(T) * V) VecT {
-    T x[V];
-};
-
-template <typename S, typename T, int V>
-__device__ __forceinline__ void vload(const S* __restrict__ p, T (&o)[V]) {
-    const VecT<S, V> v = *reinterpret_cast<const VecT<S, V>*>(p);
-#pragma unroll
-    for (int k = 0; k < V; ++k) o[k] = (T)v.x[k];
-}
-
-template <typename T, int V>
-__device__ __forceinline__ void vzero(T (&o)[V]) {
-#pragma unroll
-    for (int k = 0; k < V; ++k) o[k] = (T)0;
-}
-
-template <typename T, int V>
-struct RawRow {
-    T u[V], v[V], l[V], m[V];
-};
-
-template <typename T, int V>
-struct Row {
-    T u[V], v[V], l[V], m[V];
-    T uL, uR, vL, vR;   // neighbours of node 0 (left) and node V-1 (right)
-};
 
 template <typename T, int V, bool COMP, bool FORCE, int MODE>
 struct Centre {
@@ -64,73 +34,6 @@ struct Centre {
     double hu[V], hv[V];        // accumulator (MODE 0) or base x (MODE 1)
     double lu[V], lv[V];        // compensation (MODE 0, COMP)
     T fu[V], fv[V];             // forcing
-};
-
-// Stencil values of one node in one row.
-template <typename T>
-struct Nb {
-    T u, v, uL, uR, vL, vR, l, m;
-};
-
-template <typename T, int V>
-__device__ __forceinline__ Nb<T> node_of(const Row<T, V>& r, int k) {
-    Nb<T> n;
-    n.u = r.u[k];
-    n.v = r.v[k];
-    n.uL = k > 0 ? r.u[k > 0 ? k - 1 : 0] : r.uL;
-    n.uR = k < V - 1 ? r.u[k < V - 1 ? k + 1 : 0] : r.uR;
-    n.vL = k > 0 ? r.v[k > 0 ? k - 1 : 0] : r.vL;
-    n.vR = k < V - 1 ? r.v[k < V - 1 ? k + 1 : 0] : r.vR;
-    n.l = r.l[k];
-    n.m = r.m[k];
-    return n;
-}
-
-__device__ __forceinline__ void acc_add(double& hi, double& lo, double x, bool comp) {
-    if (comp) {
-        // Knuth's TwoSum: hi + x = t + e exactly; e goes to the compensation
-        const double t = hi + x;
-        const double z = t - hi;
-        const double e = (hi - (t - z)) + (x - z);
-        hi = t;
-        lo += e;
-    } else {
-        hi += x;
-    }
-}
-
-// kind 0: interior row; 1: traction-free top row (S below); 2: traction-free bottom row (N above)
-template <typename T>
-__device__ __forceinline__ void stencil2d(int kind, const Nb<T>& S, const Nb<T>& C, const Nb<T>& N, T lamL, T lamR,
-                                          T muL, T muR, T cxx2, T cyy2, T cxy, T cyyf, T cfx, T& Lu, T& Lv) {
-    const T two = (T)2;
-    const T AL = lamL + two * muL, AC = C.l + two * C.m, AR = lamR + two * muR;
-    const T xu = cxx2 * ((AR + AC) * (C.uR - C.u) - (AC + AL) * (C.u - C.uL));
-    const T xv = cxx2 * ((muR + C.m) * (C.vR - C.v) - (C.m + muL) * (C.v - C.vL));
-    if (kind == 1) {
-        const T AS = S.l + two * S.m;
-        Lu = xu - cyyf * (C.m + S.m) * (C.u - S.u) - cfx * (C.m * (C.vR - C.vL) + S.m * (S.vR - S.vL)) +
-             cfx * (lamR * (C.vR - S.vR) - lamL * (C.vL - S.vL));
-        Lv = xv - cyyf * (AC + AS) * (C.v - S.v) - cfx * (C.l * (C.uR - C.uL) + S.l * (S.uR - S.uL)) +
-             cfx * (muR * (C.uR - S.uR) - muL * (C.uL - S.uL));
-    } else if (kind == 2) {
-        const T AN = N.l + two * N.m;
-        Lu = xu + cyyf * (C.m + N.m) * (N.u - C.u) + cfx * (C.m * (C.vR - C.vL) + N.m * (N.vR - N.vL)) +
-             cfx * (lamR * (N.vR - C.vR) - lamL * (N.vL - C.vL));
-        Lv = xv + cyyf * (AC + AN) * (N.v - C.v) + cfx * (C.l * (C.uR - C.uL) + N.l * (N.uR - N.uL)) +
-             cfx * (muR * (N.uR - C.uR) - muL * (N.uL - C.uL));
-    } else {
-        const T AN = N.l + two * N.m, AS = S.l + two * S.m;
-        Lu = xu + cyy2 * ((N.m + C.m) * (N.u - C.u) - (C.m + S.m) * (C.u - S.u)) +
-             cxy * (lamR * (N.vR - S.vR) - lamL * (N.vL - S.vL) + N.m * (N.vR - N.vL) - S.m * (S.vR - S.vL));
-        Lv = xv + cyy2 * ((AN + AC) * (N.v - C.v) - (AC + AS) * (C.v - S.v)) +
-             cxy * (muR * (N.uR - S.uR) - muL * (N.uL - S.uL) + N.l * (N.uR - N.uL) - S.l * (S.uR - S.uL));
-    }
-}
-
-template <int V>
-struct Cols {
-    static constexpr int W = V == 4 ? 252 : 64 * V - 2;   // computed columns per wavefront
 };
 
 // One wavefront's share of one step: the x-strip bx and row chunk by.
@@ -526,13 +429,15 @@ __global__ __launch_bounds__(64) void batch_cg_final_kernel(BState* __restrict__
 }
 
 // dst = alpha a + beta b over the whole padded field of every selected problem
-// (vector indices into BProb2D::vec; ib < 0: no b).  sel: problems with a
-// non-zero flag in mask.
+// (vector indices into BProb2D::vec; ib < 0: no b; betav != null: beta is
+// betav[p], one per problem).  sel: problems with a non-zero flag in mask.
 __global__ __launch_bounds__(256) void batch_lincomb_kernel(const BProb2D* __restrict__ pr, int np,
                                                             const int* __restrict__ mask, int idst, int ia,
-                                                            double alpha, int ib, double beta) {
+                                                            double alpha, int ib, double beta,
+                                                            const double* __restrict__ betav) {
     const int p = (int)blockIdx.x / BRB, k = (int)blockIdx.x % BRB;
     if (p >= np || (mask && !mask[p])) return;
+    if (betav) beta = betav[p];
     const BProb2D& q = pr[p];
     double* d = q.vec[idst];
     const double* a = q.vec[ia];
@@ -628,9 +533,9 @@ void launch_batch_cg(hipStream_t s, int mode, const BProb2D* pr, BState* st, int
 }
 
 void launch_batch_lincomb(hipStream_t s, const BProb2D* pr, int np, const int* mask, int idst, int ia, double alpha,
-                          int ib, double beta) {
+                          int ib, double beta, const double* betav) {
     hipLaunchKernelGGL(batch_lincomb_kernel, dim3((unsigned)(np * BRB)), dim3(256), 0, s, pr, np, mask, idst, ia,
-                       alpha, ib, beta);
+                       alpha, ib, beta, betav);
 }
 
 void launch_batch_dot(hipStream_t s, const BProb2D* pr, int np, const int* mask, int ia, int ib, double* partials,
@@ -643,6 +548,59 @@ void launch_batch_dot(hipStream_t s, const BProb2D* pr, int np, const int* mask,
 Args2D make_args2d(const elwh_ctx* c);
 
 // One filter application (2-D), see elwh_internal.h.
+// The two state buffers of bufs[0..3] that are neither a nor b.
+template <typename T>
+static void free_pair(T* const* bufs, const void* a, const void* b, T** x, T** y) {
+    T* got[2] = {nullptr, nullptr};
+    int k = 0;
+    for (int i = 0; i < 4 && k < 2; ++i)
+        if (bufs[i] != a && bufs[i] != b) got[k++] = bufs[i];
+    *x = got[0];
+    *y = got[1];
+}
+
+// Steps 1 .. nsteps-1 after the half step: step pairs (fuse = 2), a single
+// step for an odd remainder; or single steps in place (fuse = 1).  prev/cur
+// hold u^0/u^1 on entry; prev may be the caller's vector (never written).
+template <typename T>
+static void run_steps_2d(elwh_ctx* c, Args2D A, int nrows, Tile t, bool with_force, bool comp, double sgn,
+                         const T* prev, T* cur, T* const* bufs, double* acc, double* lo, const T* ca, const T* cl,
+                         const T* cm, const T* f, int nsteps) {
+    hipStream_t s = c->stream;
+    int n = 1;
+    if (c->opts.fuse == 2) {
+        for (; nsteps - n >= 2; n += 2) {
+            T *x1, *x2;
+            free_pair(bufs, prev, cur, &x1, &x2);
+            A.w = sgn * c->w[n + 1];
+            A.w2 = sgn * c->w[n + 2];
+            A.fc = c->cosn[n];
+            A.fc2 = c->cosn[n + 1];
+            A.final_ = (n + 2 == nsteps);
+            launch_pair2d<T>(t.V, t.TY, with_force, comp, s, nrows, cur, prev, x1, x2, acc, lo, ca, cl, cm, f, A);
+            prev = x1;
+            cur = x2;
+        }
+    }
+    for (; n < nsteps; ++n) {
+        // u^{n+1} overwrites u^{n-1} when that is one of the state buffers
+        T* nxt = nullptr;
+        for (int i = 0; i < 4; ++i)
+            if (bufs[i] == prev) nxt = bufs[i];
+        if (!nxt) {
+            T* dummy;
+            free_pair(bufs, prev, cur, &nxt, &dummy);
+        }
+        A.w = sgn * c->w[n + 1];
+        A.fc = c->cosn[n];
+        A.final_ = (n == nsteps - 1);
+        launch_v<T, T, 0>(t.V, t.TY, with_force, comp, A.nx, nrows, s, cur, prev, nxt, nullptr, nullptr, acc, lo,
+                          ca, cl, cm, f, A);
+        prev = cur;
+        cur = nxt;
+    }
+}
+
 void run_filter_2d(elwh_ctx* c, const double* x, bool with_force, bool amode, bool fp32, double* out) {
     hipStream_t s = c->stream;
     Args2D A = make_args2d(c);
@@ -658,40 +616,21 @@ void run_filter_2d(elwh_ctx* c, const double* x, bool with_force, bool amode, bo
     A.fc = c->cosn[0];
     prof_mark(c, 0);
     if (!fp32) {
-        double *b0 = c->s64[0], *b1 = c->s64[1];
+        // half step: u^1 into s64[1]; u^0 is read from x itself afterwards
+        double* b1 = c->s64[1];
         launch_v<double, double, 1>(t.V, t.TY, with_force, false, A.nx, nrows, s, x, nullptr, b1,
                                     amode ? x : nullptr, nullptr, acc, lo, c->ca, c->cl, c->cm, c->f64, A);
         prof_mark(c, 1);
-        // step 1 reads u^0 from x itself and writes u^2 into b0; from step 2
-        // on u^{n+1} overwrites u^{n-1} in place
-        const double* prev = x;
-        double* cur = b1;
-        for (int n = 1; n < nsteps; ++n) {
-            double* nxt = (n == 1) ? b0 : const_cast<double*>(prev);
-            A.w = sgn * c->w[n + 1];
-            A.fc = c->cosn[n];
-            launch_v<double, double, 0>(t.V, t.TY, with_force, false, A.nx, nrows, s, cur, prev, nxt, nullptr,
-                                        nullptr, acc, lo, c->ca, c->cl, c->cm, c->f64, A);
-            prev = cur;
-            cur = nxt;
-        }
+        run_steps_2d<double>(c, A, nrows, t, with_force, false, sgn, x, b1, c->s64, acc, lo, c->ca, c->cl, c->cm,
+                             c->f64, nsteps);
     } else {
+        // half step: FP32 u^0 into s32[0], u^1 into s32[1]
         float *b0 = c->s32[0], *b1 = c->s32[1];
         launch_v<float, double, 1>(t.V, t.TY, with_force, comp, A.nx, nrows, s, x, nullptr, b1,
                                    amode ? x : nullptr, b0, acc, lo, c->fa, c->fl, c->fm, c->f32, A);
         prof_mark(c, 1);
-        float* prev = b0;
-        float* cur = b1;
-        for (int n = 1; n < nsteps; ++n) {
-            A.w = sgn * c->w[n + 1];
-            A.fc = c->cosn[n];
-            A.final_ = (n == nsteps - 1);
-            launch_v<float, float, 0>(t.V, t.TY, with_force, comp, A.nx, nrows, s, cur, prev, prev, nullptr,
-                                      nullptr, acc, lo, c->fa, c->fl, c->fm, c->f32, A);
-            float* tmp = prev;
-            prev = cur;
-            cur = tmp;
-        }
+        run_steps_2d<float>(c, A, nrows, t, with_force, comp, sgn, b0, b1, c->s32, acc, lo, c->fa, c->fl, c->fm,
+                            c->f32, nsteps);
     }
     prof_mark(c, 2, nsteps - 1);
 }

@@ -42,7 +42,7 @@ const int kLayers[][3] = {
     {32, 2, 0},                   // head
 };
 constexpr int NL = sizeof(kLayers) / sizeof(kLayers[0]);
-constexpr int NIN = 7, NOUT = 2, NLEV = 5;
+constexpr int NOUT = 2, NLEV = 5;
 const int kWidth[NLEV] = {32, 64, 96, 128, 128};
 
 }  // namespace

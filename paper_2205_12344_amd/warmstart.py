@@ -72,8 +72,9 @@ def make_dataset(seeds, net, batch=48, tol=1e-10, maxit=4000, time_budget=None):
 
 
 def train(net, data, epochs=20, bs=16, lr=3e-4, lr_min=1e-5, seed=0, log_every=1, time_budget=None):
-    """Adam on the relative M-weighted error, cosine-decayed learning rate;
-    stops after the epoch that passes time_budget seconds."""
+    """Adam on the relative M-weighted error, cosine-decayed learning rate.
+    With time_budget (s) the first epoch is timed and the schedule shrunk to
+    the number of epochs that fit."""
     N = data["x"].shape[0]
     rng = np.random.default_rng(seed)
     steps = epochs * (N // bs)
@@ -81,8 +82,14 @@ def train(net, data, epochs=20, bs=16, lr=3e-4, lr_min=1e-5, seed=0, log_every=1
     step = 0
     t0 = time.time()
     for ep in range(epochs):
-        if time_budget is not None and time.time() - t0 > time_budget:
-            log(f"time budget reached after {ep} epochs")
+        if time_budget is not None and ep == 1:
+            # fit the cosine schedule to the epochs the budget allows
+            fit = max(1, int(time_budget / (time.time() - t0)))
+            if fit < epochs:
+                log(f"time budget allows {fit} epochs")
+                epochs = fit
+                steps = epochs * (N // bs)
+        if ep >= epochs:
             break
         perm = rng.permutation(N)
         tot = 0.0
@@ -135,13 +142,15 @@ def predict_x0(net, cases):
     return x0
 
 
-def evaluate(net, seeds, batch=48, tol=1e-8, maxit=4000):
+def evaluate(net, seeds, batch=48, tol=1e-8, maxit=4000, control_batches=None):
     """Held-out comparison on the same GPU, per batch of problems:
     plain   FP64 stepping, zero initial guess
     learned FP32 stepping + FP64 refinement from the network's x0 (the time
             includes feature maps and inference)
     plus the two controls (FP64 from x0; FP32 from zero) that separate the
-    warm start's effect from the precision's.  Batch creation is excluded."""
+    warm start's effect from the precision's (the FP32-from-zero control runs
+    on the first control_batches batches only, all when None).  Batch
+    creation is excluded."""
     res = {k: {"seconds": 0.0, "iters": [], "relres": [], "status": []}
            for k in ("plain_fp64", "learned_fp32", "learned_fp64", "zero_fp32")}
     for k in range(0, len(seeds), batch):
@@ -170,6 +179,10 @@ def evaluate(net, seeds, batch=48, tol=1e-8, maxit=4000):
         res["learned_fp64"]["iters"] += [i["iters"] for i in inf]
         res["learned_fp64"]["relres"] += [i["relres_fp64"] for i in inf]
         res["learned_fp64"]["status"].append(st)
+        if control_batches is not None and k // batch >= control_batches:
+            b64.close()
+            b32.close()
+            continue
         _, inf, st = b32.solve(f, tol=tol, maxit=maxit)
         res["zero_fp32"]["seconds"] += b32.stats()["seconds"]
         res["zero_fp32"]["iters"] += [i["iters"] for i in inf]
@@ -182,6 +195,8 @@ def evaluate(net, seeds, batch=48, tol=1e-8, maxit=4000):
     out = {}
     z = np.array(res["plain_fp64"]["iters"], float)
     for key, r in res.items():
+        if not r["iters"]:
+            continue
         it = np.array(r["iters"], float)
         out[key] = {"seconds": r["seconds"], "mean_iters": float(it.mean()), "median_iters": float(np.median(it)),
                     "max_relres_fp64": float(np.max(r["relres"])), "all_ok": all(s == "OK" for s in r["status"])}
@@ -197,28 +212,36 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description="learned warm start: train or evaluate")
     sub = ap.add_subparsers(dest="cmd", required=True)
     t = sub.add_parser("train")
+    t.add_argument("--first-seed", type=int, default=0)
     t.add_argument("--n-train", type=int, default=4096)
+    t.add_argument("--init", default=None, help="start from these weights (continued training)")
     t.add_argument("--n-val", type=int, default=96)
     t.add_argument("--batch", type=int, default=96)
     t.add_argument("--epochs", type=int, default=40)
     t.add_argument("--gen-budget", type=float, default=660.0)
     t.add_argument("--train-budget", type=float, default=300.0)
     t.add_argument("--out", default=WEIGHTS)
+    t.add_argument("--label-tol", type=float, default=1e-10)
     e = sub.add_parser("eval")
     e.add_argument("--first-seed", type=int, default=4096)
     e.add_argument("--n", type=int, default=512)
     e.add_argument("--batch", type=int, default=48)
     e.add_argument("--weights", default=WEIGHTS)
     e.add_argument("--json", default=None)
+    e.add_argument("--control-batches", type=int, default=None)
     a = ap.parse_args(argv)
     torch.cuda.set_device(0)
-    net = WarmStart = elwh.WarmStartNet(max_batch=96, H=N_CELLS, seed=1234)
+    net = elwh.WarmStartNet(max_batch=96, H=N_CELLS, seed=1234)
     if a.cmd == "train":
         t0 = time.time()
-        data = make_dataset(list(range(a.n_train)), net, batch=a.batch, time_budget=a.gen_budget)
-        val = make_dataset(list(range(a.n_train, a.n_train + a.n_val)), net, batch=a.batch)
-        # output scale: unit RMS targets
-        k = float(torch.sqrt(torch.mean(data["y"].double() ** 2)).item())
+        s0 = a.first_seed
+        prev = load_weights(net, a.init) if a.init else {}
+        data = make_dataset(list(range(s0, s0 + a.n_train)), net, batch=a.batch, tol=a.label_tol,
+                            time_budget=a.gen_budget)
+        # validation seeds: disjoint from training (0..4095) and evaluation (4096..4607)
+        val = make_dataset(list(range(8192, 8192 + a.n_val)), net, batch=a.batch, tol=a.label_tol)
+        # output scale: unit RMS targets (kept from the initial weights when continuing)
+        k = prev.get("output_scale") or float(torch.sqrt(torch.mean(data["y"].double() ** 2)).item())
         data["y"] /= k
         val["y"] /= k
         net.set_params(out_scale=k)
@@ -228,16 +251,18 @@ def main(argv=None):
         hist = train(net, data, epochs=a.epochs, time_budget=a.train_budget)
         v1 = eval_loss(net, val)
         log(f"validation loss {v0:.4f} -> {v1:.4f}")
-        meta = {"n_train": int(data["x"].shape[0]), "n_val": int(val["x"].shape[0]), "epochs": len(hist),
-                "train_loss": [round(h, 5) for h in hist], "val_loss_before": v0, "val_loss_after": v1,
-                "output_scale": k, "label_tol": 1e-10, "seed_range_train": [0, a.n_train],
-                "seed_range_val": [a.n_train, a.n_train + a.n_val]}
+        meta = {"n_train": int(data["x"].shape[0]) + int(prev.get("n_train", 0)), "n_val": int(val["x"].shape[0]),
+                "epochs": len(hist) + int(prev.get("epochs", 0)),
+                "train_loss": prev.get("train_loss", []) + [round(h, 5) for h in hist],
+                "val_loss_before": v0, "val_loss_after": v1, "output_scale": k, "label_tol": a.label_tol,
+                "train_seeds": prev.get("train_seeds", []) + [[s0, s0 + int(data["x"].shape[0])]],
+                "val_seeds": [8192, 8192 + a.n_val]}
         save_weights(net, a.out, meta)
         print(json.dumps(meta))
     else:
         meta = load_weights(net, a.weights)
         seeds = list(range(a.first_seed, a.first_seed + a.n))
-        out = evaluate(net, seeds, batch=a.batch)
+        out = evaluate(net, seeds, batch=a.batch, control_batches=a.control_batches)
         out["weights_meta"] = {k: meta.get(k) for k in ("n_train", "epochs", "val_loss_after")}
         print(json.dumps(out))
         if a.json:
