@@ -211,7 +211,11 @@ __global__ __launch_bounds__(64) void step2d_kernel(const U* __restrict__ u, con
                                                    double* __restrict__ acc, double* __restrict__ acclo,
                                                    const T* __restrict__ ca, const T* __restrict__ cl,
                                                    const T* __restrict__ cm, const T* __restrict__ f, Args2D A) {
-    step2d_body<T, U, V, TY, MODE, FORCE, COMP>((int)blockIdx.x, (int)blockIdx.y, u, uprev, unext, xbase, u0out,
+    const int nbx = (A.nx - 1 + Cols<V>::W - 1) / Cols<V>::W;
+    const int nby = (A.jhi - A.jlo + 1 + TY - 1) / TY;
+    int t;
+    if (!xcd_tile((int)blockIdx.x, nbx * nby, t)) return;
+    step2d_body<T, U, V, TY, MODE, FORCE, COMP>(t % nbx, t / nbx, u, uprev, unext, xbase, u0out,
                                                 acc, acclo, ca, cl, cm, f, A);
 }
 
@@ -238,7 +242,7 @@ static void launch_v(int V, int TY, bool force, bool comp, int nx, int nrows, hi
                      const T* uprev, T* unext, const double* xbase, T* u0out, double* acc, double* acclo,
                      const T* ca, const T* cl, const T* cm, const T* f, const Args2D& A) {
     auto grid_for = [&](int W, int ty) {
-        return dim3((unsigned)((nx - 1 + W - 1) / W), (unsigned)((nrows + ty - 1) / ty), 1);
+        return dim3((unsigned)xcd_grid(((nx - 1 + W - 1) / W) * ((nrows + ty - 1) / ty)), 1, 1);
     };
 #define ELWH_CASE(VV, TT)                                                                                \
     if (V == VV && TY == TT) {                                                                           \
@@ -300,8 +304,10 @@ __device__ __forceinline__ int batch_problem(const BProb2D* __restrict__ pr, int
 
 template <typename T, int V, int TY, bool FORCE, bool COMP>
 __global__ __launch_bounds__(64) void batch_step2d_kernel(const BProb2D* __restrict__ pr, const BState* __restrict__ st,
-                                                          int np, double sgn, int amode) {
-    const int b = (int)blockIdx.x;
+                                                          int np, int ntiles, double sgn, int amode) {
+    // XCD bands over the concatenated tiles of all problems
+    int b;
+    if (!xcd_tile((int)blockIdx.x, ntiles, b)) return;
     const int p = batch_problem(pr, np, b);
     const BProb2D& q = pr[p];
     if (!st[p].active) return;
@@ -483,7 +489,8 @@ template <typename T, int V, int TY>
 static void batch_step_t(bool force, bool comp, int nblocks, hipStream_t s, const BProb2D* pr, const BState* st,
                          int np, double sgn, int amode) {
 #define ELWH_B2(F, C) \
-    hipLaunchKernelGGL((batch_step2d_kernel<T, V, TY, F, C>), dim3(nblocks), dim3(64), 0, s, pr, st, np, sgn, amode)
+    hipLaunchKernelGGL((batch_step2d_kernel<T, V, TY, F, C>), dim3((unsigned)xcd_grid(nblocks)), dim3(64), 0, s, pr, st, \
+                       np, nblocks, sgn, amode)
     if (force) {
         if (comp) ELWH_B2(true, true); else ELWH_B2(true, false);
     } else {

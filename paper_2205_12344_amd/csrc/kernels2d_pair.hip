@@ -313,7 +313,12 @@ __global__ __launch_bounds__(64) void pair2d_kernel(const T* __restrict__ u, con
                                                    double* __restrict__ acc, double* __restrict__ acclo,
                                                    const T* __restrict__ ca, const T* __restrict__ cl,
                                                    const T* __restrict__ cm, const T* __restrict__ f, Args2D A) {
-    pair2d_body<T, V, TY, FORCE, COMP>((int)blockIdx.x, (int)blockIdx.y, u, uprev, u1out, u2out, acc, acclo, ca, cl,
+    constexpr int W = PairCols<V>::W;
+    const int nbx = (A.nx - 1 + W) / W;
+    const int nby = (A.jhi - A.jlo + 1 + TY - 1) / TY;
+    int t;
+    if (!xcd_tile((int)blockIdx.x, nbx * nby, t)) return;
+    pair2d_body<T, V, TY, FORCE, COMP>(t % nbx, t / nbx, u, uprev, u1out, u2out, acc, acclo, ca, cl,
                                        cm, f, A);
 }
 
@@ -322,7 +327,7 @@ static void pair_launch_t(bool force, bool comp, hipStream_t s, int nrows, const
                           T* u2out, double* acc, double* acclo, const T* ca, const T* cl, const T* cm, const T* f,
                           const Args2D& A) {
     constexpr int W = PairCols<V>::W;
-    const dim3 grid((unsigned)((A.nx - 1 + W) / W), (unsigned)((nrows + TY - 1) / TY), 1);
+    const dim3 grid((unsigned)xcd_grid(((A.nx - 1 + W) / W) * ((nrows + TY - 1) / TY)), 1, 1);
 #define ELWH_LP(F, CMP)                                                                                        \
     hipLaunchKernelGGL((pair2d_kernel<T, V, TY, F, CMP>), grid, dim3(64), 0, s, u, uprev, u1out, u2out, acc, \
                        acclo, ca, cl, cm, f, A)

@@ -16,6 +16,7 @@
 // hit in cache (they are the own rows of the neighbouring wavefronts).
 #include "elwh_internal.h"
 #include "lanes.h"
+#include "xcd.h"
 
 namespace elwh {
 
@@ -62,11 +63,16 @@ __global__ __launch_bounds__(64) void step3d_kernel(const U* __restrict__ u, con
                                                    const T* __restrict__ cm, const T* __restrict__ f,
                                                    Args3D A) {
     const int lane = threadIdx.x;
-    const int i = 62 * blockIdx.x + lane;
-    const int j = 1 + (int)blockIdx.y;
+    // tiles (x-strip, y-row, z-chunk) in XCD bands, x fastest
+    const int nbx = (A.nx - 1 + 61) / 62, nyr = A.ny - 1;
+    const int nzc = (A.khi - A.klo + 1 + TZ - 1) / TZ;
+    int t;
+    if (!xcd_tile((int)blockIdx.x, nbx * nyr * nzc, t)) return;
+    const int i = 62 * (t % nbx) + lane;
+    const int j = 1 + (t / nbx) % nyr;
     const bool colv = i <= A.nx;
     const bool store = lane >= 1 && lane <= 62 && i >= 1 && i <= A.nx - 1;
-    const int k0 = A.klo + (int)blockIdx.z * TZ;
+    const int k0 = A.klo + (t / (nbx * nyr)) * TZ;
     if (k0 > A.khi) return;
     const int k1 = min(k0 + TZ - 1, A.khi);
     const int64_t P = A.P, PS = A.PS, CS = A.CS;
@@ -267,7 +273,7 @@ static void launch3_z(int TZ, bool force, bool comp, const Args3D& A, hipStream_
                       const T* cm, const T* f) {
     const int nplanes = A.khi - A.klo + 1;
     auto grid = [&](int tz) {
-        return dim3((unsigned)((A.nx - 1 + 61) / 62), (unsigned)(A.ny - 1), (unsigned)((nplanes + tz - 1) / tz));
+        return dim3((unsigned)xcd_grid(((A.nx - 1 + 61) / 62) * (A.ny - 1) * ((nplanes + tz - 1) / tz)), 1, 1);
     };
 #define ELWH_Z(TT)                                                                                              \
     if (TZ == TT) {                                                                                             \

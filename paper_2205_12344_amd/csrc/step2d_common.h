@@ -4,6 +4,7 @@
 #pragma once
 #include "elwh_internal.h"
 #include "lanes.h"
+#include "xcd.h"
 
 namespace elwh {
 
