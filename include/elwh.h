@@ -87,6 +87,12 @@ typedef struct {
     int autotune;      /* 1 (default): pick the step-kernel tiling by timing at create */
     int fuse;          /* 2-D: time steps per step-kernel launch, 2 (default: the
                           step-pair kernel) or 1; 3-D always steps singly */
+    int scale_x0;      /* CG paths: 1 = replace a given x0 by alpha x0 with
+                          alpha = (x0, b)_M / (x0, A_h x0)_M, the factor that
+                          minimises the A_h-norm error along x0 (0 when
+                          (x0, A_h x0)_M <= 0), so the start is never worse than
+                          x0 = 0 in that norm; costs no extra application
+                          (default 0) */
 } elwh_opts;
 
 typedef struct {

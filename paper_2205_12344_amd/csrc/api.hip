@@ -155,12 +155,25 @@ struct CGOut {
     bool converged = false;
 };
 
+// x <- alpha x, q <- alpha q with alpha = (x, b)_M / (x, q)_M (q = A_h x);
+// alpha = 0 when (x, q)_M <= 0.
+elwh_status scale_start(elwh_ctx* c, const double* b, double* x, double* q) {
+    double xb, xq;
+    CKST(dot_host(c, x, b, &xb));
+    CKST(dot_host(c, x, q, &xq));
+    const double alpha = (xq > 0 && std::isfinite(xb) && std::isfinite(xq)) ? xb / xq : 0.0;
+    launch_axpby(c, 0.0, x, alpha, x, c->stream);
+    launch_axpby(c, 0.0, q, alpha, q, c->stream);
+    return ELWH_OK;
+}
+
 elwh_status cg_start(elwh_ctx* c, const double* b, double* x, bool x_zero, double* r, double* p, double* q,
                      bool fp32, double* bb_out, double* rr_out) {
     if (x_zero) {
         launch_copy(c, b, r, c->stream);
     } else {
         apply_A(c, x, q, fp32);
+        if (c->opts.scale_x0) CKST(scale_start(c, b, x, q));
         launch_copy(c, b, r, c->stream);
         launch_axpby(c, -1.0, q, 1.0, r, c->stream);
     }
@@ -411,6 +424,7 @@ void elwh_default_opts(elwh_opts* o) {
     o->stream = nullptr;
     o->autotune = 1;
     o->fuse = 2;
+    o->scale_x0 = 0;
 }
 
 elwh_status elwh_plan(const elwh_grid* grid, const double* rho, const double* lam, const double* mu, double omega,
@@ -734,11 +748,12 @@ elwh_status elwh_solve(elwh_ctx* c, const double* f, const double* x0, double to
             c->err = "zero or non-finite right-hand side";
             return ELWH_ERR_ARG;
         }
-        auto true_residual = [&](bool xzero, double* rr) -> elwh_status {
+        auto true_residual = [&](bool xzero, double* rr, bool first) -> elwh_status {
             if (xzero) {
                 launch_copy(c, c->vec[VB], c->vec[VR], c->stream);
             } else {
                 apply_A(c, c->vec[VX], c->vec[VT], false);
+                if (first && c->opts.scale_x0) CKST(scale_start(c, c->vec[VB], c->vec[VX], c->vec[VT]));
                 launch_copy(c, c->vec[VB], c->vec[VR], c->stream);
                 launch_axpby(c, -1.0, c->vec[VT], 1.0, c->vec[VR], c->stream);
             }
@@ -750,7 +765,7 @@ elwh_status elwh_solve(elwh_ctx* c, const double* f, const double* x0, double to
             return ELWH_OK;
         };
         double rr;
-        CKST(true_residual(x0 == nullptr, &rr));
+        CKST(true_residual(x0 == nullptr, &rr, true));
         launch_copy(c, c->vec[VR], c->vec[VP], c->stream);
         CKST(set_scalar(c, S_RR, rr));
         CKST(set_scalar(c, S_FLAG, 0.0));
@@ -778,7 +793,7 @@ elwh_status elwh_solve(elwh_ctx* c, const double* f, const double* x0, double to
             const double rr_new = c->hscal[S_RR], beta_k = c->hscal[S_BETA];
             inf.relres = std::sqrt(rr_new / bb);
             const double rr_k = beta_k > 0 ? rr_new / beta_k : 0.0;
-            CKST(true_residual(false, &rr));
+            CKST(true_residual(false, &rr, false));
             relfp64 = std::sqrt(rr / bb);
             seg = rr;
             if (!o.converged) continue;   // out of iterations: the loop head ends it

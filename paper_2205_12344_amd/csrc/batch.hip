@@ -196,6 +196,19 @@ elwh_status lincomb(elwh_batch* b, const std::vector<int>& sel, int idst, int ia
     return ELWH_OK;
 }
 
+// x <- alpha x, q <- alpha q per selected problem, alpha = (x, b)_M / (x, q)_M
+// (q = A_h x in VQ), 0 when (x, q)_M <= 0.
+elwh_status scale_start(elwh_batch* b, const std::vector<int>& sel) {
+    std::vector<double> xb, xq, alpha(b->np, 0.0);
+    BST(dots(b, sel, VX, VB, xb));
+    BST(dots(b, sel, VX, VQ, xq));
+    for (int p = 0; p < b->np; ++p)
+        if (sel[p] && xq[p] > 0 && std::isfinite(xb[p]) && std::isfinite(xq[p])) alpha[p] = xb[p] / xq[p];
+    BST(lincomb(b, sel, VX, VX, 0.0, VX, 0.0, &alpha));
+    BST(lincomb(b, sel, VQ, VQ, 0.0, VQ, 0.0, &alpha));
+    return ELWH_OK;
+}
+
 void enqueue_ticks(elwh_batch* b, bool fp32, int nblocks, int nticks) {
     const Tile& t = b->tile[fp32 ? 1 : 0];
     const bool comp = fp32 && b->opts.compensated;
@@ -476,6 +489,7 @@ elwh_status elwh_batch_solve(elwh_batch* b, const double* const* f, const double
         for (int p = 0; p < np; ++p) anyx |= has_x[p] != 0;
         if (anyx) {
             BST(run_apply(b, false, false, true, VX, VQ, has_x));
+            if (b->opts.scale_x0) BST(scale_start(b, has_x));
             BST(lincomb(b, has_x, VR, VB, 1.0, VQ, -1.0));
         }
         std::vector<int> nox(np);
@@ -517,6 +531,7 @@ elwh_status elwh_batch_solve(elwh_batch* b, const double* const* f, const double
         for (int p = 0; p < np; ++p) anyx |= has_x[p] != 0;
         if (anyx) {
             BST(run_apply(b, false, false, true, VX, VQ, has_x));
+            if (b->opts.scale_x0) BST(scale_start(b, has_x));
             BST(lincomb(b, has_x, VR, VB, 1.0, VQ, -1.0));
         }
         std::vector<int> nox(np);

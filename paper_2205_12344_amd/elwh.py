@@ -45,7 +45,7 @@ class Opts(ctypes.Structure):
                 ("prec", ctypes.c_int), ("krylov", ctypes.c_int), ("gmres_m", ctypes.c_int),
                 ("scheme", ctypes.c_int), ("compensated", ctypes.c_int), ("inner_tol", ctypes.c_double),
                 ("max_outer", ctypes.c_int), ("stream", ctypes.c_void_p), ("autotune", ctypes.c_int),
-                ("fuse", ctypes.c_int)]
+                ("fuse", ctypes.c_int), ("scale_x0", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):

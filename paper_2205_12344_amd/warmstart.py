@@ -37,17 +37,22 @@ def _dev_case(c):
 
 def make_dataset(seeds, net, batch=48, tol=1e-10, maxit=4000, time_budget=None):
     """Solve every seed's problem in batches (FP64, tol) and return network
-    inputs x, targets y (unscaled: output scale 1), loss weights w and
-    per-problem iteration counts.  Seeds are grouped by omega so the problems
-    of one batch need similar work (the solve of a batch lasts as long as its
-    slowest problem).  Stops early (keeping what is done) past time_budget s."""
+    inputs x, targets y, loss weights w and per-problem iteration counts.
+    Targets are normalised to unit w-weighted RMS per sample: the amplitude
+    of a solution near a resonance of the cavity is not predictable from
+    local data, and the solver rescales the network's guess optimally
+    (scale_x0).  Problems whose solve did not reach 10 tol (CG breakdown
+    near resonance: A_h slightly indefinite) are left out.  Seeds are grouped
+    by omega so the problems of one batch need similar work.  Stops early
+    (keeping what is done) past time_budget s."""
     n = net.H
     seeds = sorted(seeds, key=inputs.config5_omega)
     N = len(seeds)
     x = torch.empty((N, n, n, 7), dtype=torch.float32, device="cuda")
     y = torch.empty((N, n, n, 2), dtype=torch.float32, device="cuda")
     w = torch.empty((N, n, n), dtype=torch.float32, device="cuda")
-    iters = []
+    iters, used = [], []
+    kept = 0
     t0 = time.time()
     for k in range(0, N, batch):
         chunk = seeds[k:k + batch]
@@ -55,20 +60,28 @@ def make_dataset(seeds, net, batch=48, tol=1e-10, maxit=4000, time_budget=None):
         bt = elwh.Batch(cases)
         vs, infos, status = bt.solve([c.f for c in cases], tol=tol, maxit=maxit)
         bt.close()
-        if status != "OK":
-            log(f"batch at {k}: status {status}")
-        iters += [i["iters"] for i in infos]
-        dev = [_dev_case(c) for c in cases]
-        om = torch.tensor([c.omega for c in cases], dtype=torch.float64, device="cuda")
+        good = [i for i, inf in enumerate(infos) if inf["relres_fp64"] <= 10 * tol]
+        if len(good) < len(cases):
+            log(f"batch at {k}: status {status}, {len(cases) - len(good)} problem(s) left out")
+        iters += [infos[i]["iters"] for i in good]
+        cases = [cases[i] for i in good]
+        vs = [vs[i] for i in good]
         B = len(cases)
-        net.features(dev, om, x[k:k + B], w[k:k + B])
-        net.from_field([d[3] for d in dev], vs, om, y[k:k + B])
-        log(f"data {k + B}/{N}: {time.time() - t0:.1f} s, mean iters {np.mean(iters):.1f}")
+        if B:
+            dev = [_dev_case(c) for c in cases]
+            om = torch.tensor([c.omega for c in cases], dtype=torch.float64, device="cuda")
+            net.features(dev, om, x[kept:kept + B], w[kept:kept + B])
+            net.from_field([d[3] for d in dev], vs, om, y[kept:kept + B])
+            yb, wb = y[kept:kept + B], w[kept:kept + B]
+            rms = torch.sqrt((wb[..., None] * yb * yb).sum(dim=(1, 2, 3)) / (2 * wb.sum(dim=(1, 2))))
+            yb /= rms[:, None, None, None]
+            used += [seeds[k + i] for i in good]
+            kept += B
+        log(f"data {k + len(chunk)}/{N}: kept {kept}, {time.time() - t0:.1f} s, mean iters {np.mean(iters):.1f}")
         if time_budget is not None and time.time() - t0 > time_budget:
-            N = k + B
-            log(f"time budget reached: keeping {N} samples")
+            log(f"time budget reached: keeping {kept} samples")
             break
-    return {"x": x[:N], "y": y[:N], "w": w[:N], "iters": np.array(iters), "seeds": seeds[:N]}
+    return {"x": x[:kept], "y": y[:kept], "w": w[:kept], "iters": np.array(iters), "seeds": used}
 
 
 def train(net, data, epochs=20, bs=16, lr=3e-4, lr_min=1e-5, seed=0, log_every=1, time_budget=None):
@@ -145,8 +158,9 @@ def predict_x0(net, cases):
 def evaluate(net, seeds, batch=48, tol=1e-8, maxit=4000, control_batches=None):
     """Held-out comparison on the same GPU, per batch of problems:
     plain   FP64 stepping, zero initial guess
-    learned FP32 stepping + FP64 refinement from the network's x0 (the time
-            includes feature maps and inference)
+    learned FP32 stepping with FP64 residual replacements from the network's
+            x0, rescaled by the solver (scale_x0; the time includes feature
+            maps and inference)
     plus the two controls (FP64 from x0; FP32 from zero) that separate the
     warm start's effect from the precision's (the FP32-from-zero control runs
     on the first control_batches batches only, all when None).  Batch
@@ -156,8 +170,9 @@ def evaluate(net, seeds, batch=48, tol=1e-8, maxit=4000, control_batches=None):
     for k in range(0, len(seeds), batch):
         cases = [inputs.config5_problem(s, n=net.H) for s in seeds[k:k + batch]]
         f = [c.f for c in cases]
-        b64 = elwh.Batch(cases)
-        b32 = elwh.Batch(cases, prec=elwh.FP32_STEP)
+        # scale_x0 acts on given starts only: the zero-start runs are unchanged
+        b64 = elwh.Batch(cases, scale_x0=1)
+        b32 = elwh.Batch(cases, prec=elwh.FP32_STEP, scale_x0=1)
         torch.cuda.synchronize()
         _, inf, st = b64.solve(f, tol=tol, maxit=maxit)
         res["plain_fp64"]["seconds"] += b64.stats()["seconds"]
@@ -240,10 +255,8 @@ def main(argv=None):
                             time_budget=a.gen_budget)
         # validation seeds: disjoint from training (0..4095) and evaluation (4096..4607)
         val = make_dataset(list(range(8192, 8192 + a.n_val)), net, batch=a.batch, tol=a.label_tol)
-        # output scale: unit RMS targets (kept from the initial weights when continuing)
-        k = prev.get("output_scale") or float(torch.sqrt(torch.mean(data["y"].double() ** 2)).item())
-        data["y"] /= k
-        val["y"] /= k
+        # targets have unit RMS per sample; the solver picks the amplitude
+        k = 1.0
         net.set_params(out_scale=k)
         log(f"dataset {data['x'].shape[0]} + {val['x'].shape[0]} samples in {time.time() - t0:.1f} s, "
             f"output scale {k:.4f}, mean plain iterations {data['iters'].mean():.1f}")

@@ -102,3 +102,38 @@ def test_batch_fp32_refinement(E):
         prob, op, vstar = _direct(c)
         assert info["relres_fp64"] <= 1e-8
         assert _rel(prob.gather(v.cpu().numpy()), vstar) <= 1e-6
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_scaled_warm_start(E, prec):
+    """scale_x0: a start along the solution but 7x too large is rescaled to
+    (almost) the solution, so CG stops at once; a start of pure noise is
+    scaled towards zero and never costs more than one iteration over the
+    zero start (the A_h-norm error of alpha x0 is at most that of 0)."""
+    import torch
+    cases = _cases()[:4]
+    f = [c.f for c in cases]
+    tol = 1e-8
+    bt = E.Batch(cases, prec=prec, scale_x0=1)
+    ref = E.Batch(cases, prec=prec)
+    _, i0, s0 = ref.solve(f, tol=tol, maxit=2000)
+    vstar = []
+    for c in cases:
+        prob, op, v = _direct(c)
+        vstar.append(prob.scatter(v))
+    x_big = [torch.from_numpy(7.0 * v).cuda() for v in vstar]
+    v1, i1, s1 = bt.solve(f, x0s=x_big, tol=tol, maxit=2000)
+    _say("scaled start along v*", [x["iters"] for x in i1], "zero start", [x["iters"] for x in i0])
+    assert s0 == s1 == "OK"
+    for x in i1:
+        assert x["iters"] <= 2
+    rng = np.random.default_rng(5)
+    x_noise = [torch.from_numpy(rng.standard_normal(v.shape) * np.abs(v).max()).cuda() for v in vstar]
+    v2, i2, s2 = bt.solve(f, x0s=x_noise, tol=tol, maxit=2000)
+    _say("scaled noise start", [x["iters"] for x in i2])
+    assert s2 == "OK"
+    for a, z in zip(i2, i0):
+        assert a["iters"] <= z["iters"] + (1 if prec == 0 else 0.2 * z["iters"] + 5)
+    for c, x in zip(cases, v2):
+        prob, op, vs = _direct(c)
+        assert _rel(prob.gather(x.cpu().numpy()), vs) <= 1e-6

@@ -245,6 +245,23 @@ def test_solve_config1_matches_direct_and_oracle_cg(E):
     assert _rel(prob.gather(v2.cpu().numpy()), vstar) <= 1e-12
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_scaled_start_single_context(E, prec):
+    """scale_x0 on elwh_solve: 3 v* as the start is rescaled to v* (no
+    iteration needed); the unscaled 3 v* start needs several."""
+    c = inputs.config1()
+    prob, op, wh = _oracle(2, c.n, None, c.bc, c.rho, c.lam, c.mu, c.omega)
+    vstar = direct.solve(op, c.omega, prob.gather(c.f))
+    x0 = 3.0 * prob.scatter(vstar)
+    ctx = E.context_from_case(c, prec=prec, scale_x0=1)
+    v, info = ctx.solve(c.f, x0=x0, tol=1e-8, maxit=200)
+    plain = E.context_from_case(c, prec=prec)
+    _, info_plain = plain.solve(c.f, x0=x0, tol=1e-8, maxit=200)
+    _say("scaled start", info["iters"], "unscaled", info_plain["iters"])
+    assert info["iters"] <= 1 < info_plain["iters"]
+    assert _rel(prob.gather(v.cpu().numpy()), vstar) <= 1e-7
+
+
 def test_stepwise_cg_and_warm_start(E):
     c = inputs.config1()
     prob, op, wh = _oracle(2, c.n, None, c.bc, c.rho, c.lam, c.mu, c.omega)
