@@ -40,32 +40,35 @@ METRIC = "elastic lattice updates/s (% HBM roofline); time-to-1e-8 residual lear
 #   FP32 state, plain FP64 accumulator: 24 + 12 + 32                      = 68
 #   3-D: three components; FP64 3x3x8 + 3x8 + 2x3x8 = 144; FP32
 #         compensated 36 + 12 + 96 = 144; FP32 plain 36 + 12 + 48 = 96
-# Step-pair kernel (2-D, fuse = 2), per launch = two lattice updates:
+# K-step kernel (2-D, fuse = K = 2..4), per node and launch (K lattice
+# updates), independent of K:
 #   FP64: read u^n, u^{n-1} (2x2x8), a, lambda, mu (3x8), acc (2x8);
-#         write u^{n+1}, u^{n+2} (2x2x8), acc (2x8) = 120, i.e. 60 per LUP
-#   FP32 compensated: state 4x2x4 + 3x4 + acc hi+lo 4x2x8 = 108 -> 54
-#   FP32 plain accumulator: 32 + 12 + 32 = 76 -> 38
+#         write u^{n+K-1}, u^{n+K} (2x2x8), acc (2x8) = 120, i.e. 120/K per LUP
+#   FP32 compensated: state 4x2x4 + 3x4 + acc hi+lo 4x2x8 = 108
+#   FP32 plain accumulator: 32 + 12 + 32 = 76
 BYTES_PER_LUP = {
     (2, "f64", 1): 104, (2, "f32c", 1): 100, (2, "f32", 1): 68,
-    (2, "f64", 2): 60, (2, "f32c", 2): 54, (2, "f32", 2): 38,
     (3, "f64", 1): 144, (3, "f32c", 1): 144, (3, "f32", 1): 96,
 }
+BYTES_PER_MULTI_LAUNCH = {"f64": 120, "f32c": 108, "f32": 76}
 
 
 def step_launches(nt, fuse):
-    """(pair launches, single-step launches) after the half step."""
-    if fuse == 2:
-        return (nt - 1) // 2, (nt - 1) % 2
-    return 0, nt - 1
+    """Steps per launch of the N_T - 1 steps after the half step."""
+    out, rem = [], nt - 1
+    while fuse >= 2 and rem >= 2:
+        k = min(fuse, rem)
+        out.append(k)
+        rem -= k
+    return out + [1] * rem
 
 
 def phase_bytes(dim, tag, fuse, nt, nodes):
     """Algorithmic bytes of the N_T - 1 steps after the half step, and the
     number of launches that move them."""
-    pairs, singles = step_launches(nt, fuse)
-    b = pairs * 2 * BYTES_PER_LUP[(dim, tag, 2 if fuse == 2 else 1)] * nodes
-    b += singles * BYTES_PER_LUP[(dim, tag, 1)] * nodes
-    return b, pairs + singles
+    ks = step_launches(nt, fuse)
+    b = sum((BYTES_PER_MULTI_LAUNCH[tag] if k >= 2 else BYTES_PER_LUP[(dim, tag, 1)]) * nodes for k in ks)
+    return b, len(ks)
 
 
 def log(*a):
@@ -107,7 +110,7 @@ def read_traffic(kernel_tag, tile):
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ("kernels2d.hip", "kernels2d_pair.hip", "step2d_common.h", "kernels3d.hip", "lanes.h"):
+    for f in ("kernels2d.hip", "kernels2d_multi.hip", "step2d_common.h", "xcd.h", "kernels3d.hip", "lanes.h"):
         h.update(open(os.path.join(ROOT, "paper_2205_12344_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -231,38 +234,42 @@ def main():
     ms_per_step = 1e3 * el / args.steps
     # every application runs N_T - 1 steps after the half step
     napp = prof["nstep"] // max(nt - 1, 1)
-    bytes_app, launches_app = phase_bytes(2, "f64", 2, nt, nodes)
+    fuse = elwh.default_opts().fuse
+    bytes_app, launches_app = phase_bytes(2, "f64", fuse, nt, nodes)
     step_avg_ms = prof["step_ms"] / max(napp * launches_app, 1)
     achieved = bytes_app * napp / (prof["step_ms"] * 1e-3) / 1e9
-    traffic = read_traffic("pair2d_f64_cfg2_1024", (tv, tr))
+    traffic = read_traffic(f"multi2d_k{fuse}_f64_cfg2_1024", (tv, tr))
     log(f"tile V={tv} TY={tr}")
-    log(f"fp64: {ms_per_step:.3f} ms/step, {value / 1e9:.2f} GLUP/s, step-pair kernel {1e3 * step_avg_ms:.1f} us "
+    log(f"fp64: {ms_per_step:.3f} ms/step, {value / 1e9:.2f} GLUP/s, {fuse}-step kernel {1e3 * step_avg_ms:.1f} us "
         f"({napp * launches_app} launches), {achieved:.0f} GB/s")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic,
-                "kernel": f"pair2d_kernel<double,V={tv},TY={tr},FORCE=0,COMP=0>",
-                "bytes_per_lup": BYTES_PER_LUP[(2, "f64", 2)], "lup_per_launch": 2 * nodes,
-                "bytes_per_launch": 2 * BYTES_PER_LUP[(2, "f64", 2)] * nodes,
+                "kernel": f"multi2d_kernel<double,V={tv},TY={tr},K={fuse},FORCE=0,COMP=0>",
+                "bytes_per_lup": BYTES_PER_MULTI_LAUNCH["f64"] / fuse, "lup_per_launch": fuse * nodes,
+                "bytes_per_launch": BYTES_PER_MULTI_LAUNCH["f64"] * nodes,
                 "avg_launch_us": round(1e3 * step_avg_ms, 3)}
     ctx.close()
 
     variants = {}
-    for tag, prec, kw in (("f32c", "f32c", {"prec": elwh.FP32_STEP, "compensated": 1}),
-                          ("f32", "f32", {"prec": elwh.FP32_STEP, "compensated": 0}),
-                          ("f64_single_step", "f64", {"fuse": 1}),
-                          ("f32c_single_step", "f32c", {"prec": elwh.FP32_STEP, "compensated": 1, "fuse": 1})):
-        fuse = kw.get("fuse", 2)
+    vlist = [("f32c", "f32c", {"prec": elwh.FP32_STEP, "compensated": 1}),
+             ("f32", "f32", {"prec": elwh.FP32_STEP, "compensated": 0})]
+    for k in (1, 2, 3, 4):
+        if k != fuse:
+            vlist.append((f"f64_fuse{k}", "f64", {"fuse": k}))
+    vlist.append(("f32c_fuse1", "f32c", {"prec": elwh.FP32_STEP, "compensated": 1, "fuse": 1}))
+    for tag, prec, kw in vlist:
+        fuse_v = kw.setdefault("fuse", fuse)
         c2 = elwh.context_from_case(case, **kw)
         p = kernel_rate(c2, 10)
         t2 = c2.get_tile(elwh.FP64 if prec == "f64" else elwh.FP32_STEP)
         napp = p["nstep"] // max(nt - 1, 1)
-        bapp, lapp = phase_bytes(2, prec, fuse, nt, nodes)
+        bapp, lapp = phase_bytes(2, prec, fuse_v, nt, nodes)
         gbs = bapp * napp / (p["step_ms"] * 1e-3) / 1e9
-        variants[tag] = {"tile": list(t2), "steps_per_launch": fuse,
+        variants[tag] = {"tile": list(t2), "steps_per_launch": fuse_v,
                          "launch_us": round(1e3 * p["step_ms"] / max(napp * lapp, 1), 3),
                          "glup_s_kernel": round(napp * (nt - 1) * nodes / (p["step_ms"] * 1e-3) / 1e9, 3),
-                         "bytes_per_lup": BYTES_PER_LUP[(2, prec, fuse)], "achieved_GBs": round(gbs, 1),
+                         "bytes_per_lup": round(bapp / ((nt - 1) * nodes), 2), "achieved_GBs": round(gbs, 1),
                          "frac": round(gbs / HBM_PEAK_GBS, 4)}
         log(f"{tag}: {variants[tag]}")
         c2.close()

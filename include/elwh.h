@@ -85,8 +85,8 @@ typedef struct {
     int max_outer;     /* FP32 path: maximum residual replacements (default 50) */
     void* stream;      /* hipStream_t the context works on; NULL = the null stream */
     int autotune;      /* 1 (default): pick the step-kernel tiling by timing at create */
-    int fuse;          /* 2-D: time steps per step-kernel launch, 2 (default: the
-                          step-pair kernel) or 1; 3-D always steps singly */
+    int fuse;          /* 2-D: time steps per step-kernel launch, 1 to 4 (default
+                          2); 3-D always steps singly */
     int scale_x0;      /* CG paths: 1 = replace a given x0 by alpha x0 with
                           alpha = (x0, b)_M / (x0, A_h x0)_M, the factor that
                           minimises the A_h-norm error along x0 (0 when

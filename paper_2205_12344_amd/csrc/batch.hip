@@ -9,8 +9,10 @@
 // per-problem two-pass reductions).  A problem that converges drops out; the
 // others continue.  The CG phase is captured as a hipGraph of several ticks
 // and replayed until no problem is active; the host reads one counter per
-// replay.  FP32 batches run FP64 iterative refinement around FP32-stepped
-// batched CG solves (r = b - A_h x in FP64, stop on the FP64 residual).
+// replay.  FP32 batches run the same batched CG with FP32-stepped
+// applications and FP64 vectors, in segments: after each segment the
+// residual of every unfinished problem is replaced by b - A_h x from an FP64
+// application and its search direction continues (stop on that residual).
 #include <algorithm>
 #include <chrono>
 #include <cmath>

@@ -62,7 +62,7 @@ struct Args2D {
     int jlo, jhi, free_lo, free_hi;
     double cxx2, cyy2, cxy, cyyf, cfx;
     double w, w0, fc;
-    double w2, fc2;           // step pair: weight of u^{n+2}, forcing factor of step n+1
+    double wk[4], fck[4];     // K-step launch: weight of u^{n+s}, forcing factor of step n+s-1 (s = 1..K)
     int final_;
 };
 
@@ -170,14 +170,14 @@ void prof_mark(elwh_ctx* c, int phase, int nsteps = 0);
 bool tile_valid_2d(bool fp32, int V, int TY);
 bool tile_valid_3d(bool fp32, int V, int TZ);
 
-// Two time steps per launch (kernels2d_pair.hip): reads u^n (u), u^{n-1}
-// (uprev), writes u^{n+1} (u1out) and u^{n+2} (u2out), four distinct buffers;
-// A.w / A.w2 weigh u^{n+1} / u^{n+2}, A.fc / A.fc2 are the forcing factors of
-// steps n and n+1.
+// K = 2..4 time steps per launch (kernels2d_multi.hip): reads u^n (u) and
+// u^{n-1} (uprev), writes u^{n+K-1} (outA) and u^{n+K} (outB), four distinct
+// buffers; A.wk[s-1] weighs u^{n+s}, A.fck[s-1] is the forcing factor of
+// step n+s-1.
 template <typename T>
-void launch_pair2d(int V, int TY, bool force, bool comp, hipStream_t s, int nrows, const T* u, const T* uprev,
-                   T* u1out, T* u2out, double* acc, double* acclo, const T* ca, const T* cl, const T* cm,
-                   const T* f, const Args2D& A);
+void launch_multi2d(int K, int V, int TY, bool force, bool comp, hipStream_t s, int nrows, const T* u,
+                    const T* uprev, T* outA, T* outB, double* acc, double* acclo, const T* ca, const T* cl,
+                    const T* cm, const T* f, const Args2D& A);
 
 // ---- kernels (kernels2d.hip / kernels3d.hip / blas.hip) --------------------
 // Copy a caller-layout field (ncomp components) into the padded layout,

@@ -277,6 +277,7 @@ Args2D make_args2d(const elwh_ctx* c) {
     A.cyyf = c->st.cyyf;
     A.cfx = c->st.cfxy;
     A.w = A.w0 = A.fc = 0;
+    for (int q = 0; q < 4; ++q) A.wk[q] = A.fck[q] = 0;
     A.final_ = 0;
     return A;
 }
@@ -566,27 +567,30 @@ static void free_pair(T* const* bufs, const void* a, const void* b, T** x, T** y
     *y = got[1];
 }
 
-// Steps 1 .. nsteps-1 after the half step: step pairs (fuse = 2), a single
-// step for an odd remainder; or single steps in place (fuse = 1).  prev/cur
-// hold u^0/u^1 on entry; prev may be the caller's vector (never written).
+// Steps 1 .. nsteps-1 after the half step: launches of K = fuse steps (a
+// shorter multi-step launch, or a single step, for the remainder); or single
+// steps in place (fuse = 1).  prev/cur hold u^0/u^1 on entry; prev may be the
+// caller's vector (never written).
 template <typename T>
 static void run_steps_2d(elwh_ctx* c, Args2D A, int nrows, Tile t, bool with_force, bool comp, double sgn,
                          const T* prev, T* cur, T* const* bufs, double* acc, double* lo, const T* ca, const T* cl,
                          const T* cm, const T* f, int nsteps) {
     hipStream_t s = c->stream;
     int n = 1;
-    if (c->opts.fuse == 2) {
-        for (; nsteps - n >= 2; n += 2) {
+    if (c->opts.fuse >= 2) {
+        while (nsteps - n >= 2) {
+            const int k = std::min(c->opts.fuse, nsteps - n);
             T *x1, *x2;
             free_pair(bufs, prev, cur, &x1, &x2);
-            A.w = sgn * c->w[n + 1];
-            A.w2 = sgn * c->w[n + 2];
-            A.fc = c->cosn[n];
-            A.fc2 = c->cosn[n + 1];
-            A.final_ = (n + 2 == nsteps);
-            launch_pair2d<T>(t.V, t.TY, with_force, comp, s, nrows, cur, prev, x1, x2, acc, lo, ca, cl, cm, f, A);
+            for (int q = 1; q <= k; ++q) {
+                A.wk[q - 1] = sgn * c->w[n + q];
+                A.fck[q - 1] = c->cosn[n + q - 1];
+            }
+            A.final_ = (n + k == nsteps);
+            launch_multi2d<T>(k, t.V, t.TY, with_force, comp, s, nrows, cur, prev, x1, x2, acc, lo, ca, cl, cm, f, A);
             prev = x1;
             cur = x2;
+            n += k;
         }
     }
     for (; n < nsteps; ++n) {

@@ -287,7 +287,7 @@ elwh_status check_config(const elwh_grid* g, const int bc[6], const elwh_opts* o
         if (o->krylov < 0 || o->krylov > 2) { *err = "bad krylov method"; return ELWH_ERR_ARG; }
         if (o->gmres_m < 1 || o->gmres_m > 200) { *err = "gmres_m must be in [1, 200]"; return ELWH_ERR_ARG; }
         if (o->scheme != ELWH_SCHEME_CORRECTED && o->scheme != ELWH_SCHEME_STANDARD) { *err = "bad scheme"; return ELWH_ERR_ARG; }
-        if (o->fuse != 1 && o->fuse != 2) { *err = "fuse must be 1 or 2"; return ELWH_ERR_ARG; }
+        if (o->fuse < 1 || o->fuse > 4) { *err = "fuse must be in [1, 4]"; return ELWH_ERR_ARG; }
     }
     return ELWH_OK;
 }

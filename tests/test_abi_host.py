@@ -46,6 +46,7 @@ def test_struct_sizes_match_header(elwh):
 def test_default_opts(elwh):
     o = elwh.default_opts()
     assert o.cfl == 0.8 and o.periods == 1 and o.nt == 0 and o.prec == 0 and o.compensated == 1 and o.autotune == 1
+    assert o.fuse == 2 and o.scale_x0 == 0 and o.inner_tol == 1e-2
 
 
 def _media(shape, seed):
@@ -103,6 +104,9 @@ def test_plan_rejects_bad_input(elwh):
         elwh.plan(2, (8, 8), ok, ok, ok, 3.0, (1, 0, 0, 0))
     with pytest.raises(elwh.ElwhError, match="ERR_ARG"):
         elwh.plan(2, (8, 8), ok, ok, ok, 3.0, (0, 0, 0, 0), nt=2)
+    for fuse in (0, 5):
+        with pytest.raises(elwh.ElwhError, match="ERR_ARG"):
+            elwh.plan(2, (8, 8), ok, ok, ok, 3.0, (0, 0, 0, 0), fuse=fuse)
 
 
 def test_plan_nt_override_and_standard(elwh):

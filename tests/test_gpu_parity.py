@@ -81,7 +81,7 @@ CASES_2D = [
 
 @pytest.mark.parametrize("n,bc,length", CASES_2D)
 @pytest.mark.parametrize("force", [False, True])
-@pytest.mark.parametrize("fuse", [2, 1])
+@pytest.mark.parametrize("fuse", [2, 1, 3, 4])
 def test_filter_2d_fp64(E, n, bc, length, force, fuse):
     _say("filter2d fp64", n, bc, force, "fuse", fuse)
     rho, lam, mu = _media((n[1] + 1, n[0] + 1), sum(n))
@@ -141,7 +141,7 @@ def test_filter_fp32_stepping(E, dim):
     f = rng.standard_normal(prob.field_shape) * prob.unknown_mask()
     ref = prob.scatter(wh.apply_filter(prob.gather(u0), prob.gather(f)))
     for comp in (1, 0):
-        for fuse in ((2, 1) if dim == 2 else (2,)):
+        for fuse in ((2, 1, 3, 4) if dim == 2 else (2,)):
             ctx = E.Context(dim, n, rho, lam, mu, om, bc, prec=E.FP32_STEP, compensated=comp, fuse=fuse)
             got = ctx.apply_filter(u0, f).cpu().numpy()
             err = _rel(got, ref)
@@ -151,11 +151,12 @@ def test_filter_fp32_stepping(E, dim):
 
 @pytest.mark.parametrize("nt", [3, 4, 5, 8, 9])
 @pytest.mark.parametrize("prec", [0, 1])
-def test_step_pairs_every_step_count(E, nt, prec):
-    """Half step + step pairs (+ one single step when N_T - 1 is odd) give the
-    oracle's filter and A_h for odd and even N_T, with forcing, and agree
-    with single-step launches.  omega is chosen so that the time-step rule
-    itself gives N_T (a smaller N_T than the rule's would be unstable)."""
+def test_multi_step_every_step_count(E, nt, prec):
+    """Half step + K-step launches (with a shorter launch or a single step
+    for the remainder of N_T - 1) give the oracle's filter and A_h for every
+    N_T and K = 2, 3, 4, with forcing, and agree with single-step launches.
+    omega is chosen so that the time-step rule itself gives N_T (a smaller
+    N_T than the rule's would be unstable)."""
     n, bc = (131, 23), (0, 0, 1, 1)
     rho, lam, mu = _media((24, 132), 300 + nt)
     prob = Problem(2, n, bc=bc)
@@ -171,7 +172,7 @@ def test_step_pairs_every_step_count(E, nt, prec):
     refA = prob.scatter(wh.apply_A(prob.gather(u0)))
     tol = FP64_TOL if prec == 0 else fp32_bound(nt)
     outs = {}
-    for fuse in (2, 1):
+    for fuse in (2, 3, 4, 1):
         ctx = E.Context(2, n, rho, lam, mu, om, bc, prec=prec, fuse=fuse, autotune=0)
         assert ctx.info()["nt"] == nt
         got = ctx.apply_filter(u0, f).cpu().numpy()
@@ -180,7 +181,8 @@ def test_step_pairs_every_step_count(E, nt, prec):
         assert _rel(got, ref) <= tol
         assert _rel(gotA, refA) <= tol
         outs[fuse] = got
-    assert _rel(outs[2], outs[1]) <= 2 * tol
+    for k in (2, 3, 4):
+        assert _rel(outs[k], outs[1]) <= 2 * tol
 
 
 def test_k_periods_and_standard_scheme(E):
@@ -423,7 +425,7 @@ def test_every_tiling_matches_oracle(E, dim, prec):
     ref = prob.scatter(wh.apply_filter(prob.gather(u0), prob.gather(f)))
     tol = FP64_TOL if prec == 0 else fp32_bound(wh.nt)
     outs = []
-    for fuse in ((2, 1) if dim == 2 else (2,)):
+    for fuse in ((2, 1, 3, 4) if dim == 2 else (2,)):
         ctx = E.Context(dim, n, rho, lam, mu, om, bc, prec=prec, autotune=0, fuse=fuse)
         for v, rows in _tiles(dim, prec == 1):
             ctx.set_tile(prec, v, rows)
