@@ -94,17 +94,17 @@ def read_traffic(kernel_tag, tile):
         return None
     vals = {}
     for line in open(path):
-        m = re.match(r"\s*(traffic_bytes_per_launch|kernel_source_hash|tile)\s*[:=]\s*(\S+)", line)
+        # "traffic_bytes_per_launch[V,TY]: bytes" per tiling, "kernel_source_hash: h"
+        m = re.match(r"\s*(traffic_bytes_per_launch\[\d+,\d+\]|kernel_source_hash)\s*[:=]\s*(\S+)", line)
         if m:
             vals[m.group(1)] = m.group(2)
-    if "traffic_bytes_per_launch" not in vals:
-        return None
-    if vals.get("tile") != f"{tile[0]},{tile[1]}":
+    key = f"traffic_bytes_per_launch[{tile[0]},{tile[1]}]"
+    if key not in vals:
         return None
     src_hash = vals.get("kernel_source_hash")
     if src_hash and src_hash != kernel_source_hash():
         return None          # the kernel changed since the counters were taken
-    return float(vals["traffic_bytes_per_launch"])
+    return float(vals[key])
 
 
 def kernel_source_hash():
@@ -174,6 +174,47 @@ def cpu_baseline(case, budget_s=12.0):
                       f"workload, {el:.1f} s; operator assembly {t_setup:.1f} s excluded"}
 
 
+def batch_cfg4(elwh, inputs):
+    """Config 4: 48 problems (256^2..1024^2 cells, omega in [10, 80], 1-4
+    sources) solved to 1e-8 as one batch (one launch per tick for all
+    problems, CG phase replayed as a hipGraph), FP32 stepping and FP64."""
+    import torch
+    cases = inputs.config4()
+    out = {"workload": "config 4: 48 problems, n ~ U{256..1024}, omega ~ U[10, 80], 1-4 Gaussian sources, "
+                       "random log-normal media, free top", "tol": 1e-8}
+    for tag, kw in (("fp32", {"prec": elwh.FP32_STEP}), ("fp64", {})):
+        bt = elwh.Batch(cases, **kw)
+        fs = [c.f for c in cases]
+        torch.cuda.synchronize()
+        _, infos, st = bt.solve(fs, tol=1e-8, maxit=4000)
+        s = bt.stats()
+        lup = sum(i["iters"] * i["nt"] * unknown_nodes(c) for i, c in zip(infos, cases))
+        out[tag] = {"seconds": round(s["seconds"], 3), "status": st, "ticks": s["ticks"],
+                    "tiles": {"fp64": s["tile64"], "fp32": s["tile32"]},
+                    "iters_mean": round(sum(i["iters"] for i in infos) / len(infos), 1),
+                    "max_relres_fp64": max(i["relres_fp64"] for i in infos),
+                    "aggregate_glup_s": round(lup / s["seconds"] / 1e9, 2)}
+        log(f"config 4 {tag}: {out[tag]}")
+        bt.close()
+    return out
+
+
+def time_to_tol(elwh, nprob=24, first_seed=4096):
+    """Wall time to relative residual 1e-8 on held-out warm-start problems
+    (config 5, seeds first_seed..): plain FP64 from zero against the learned
+    start with FP32 stepping (and with FP64), one batch each."""
+    from paper_2205_12344_amd import warmstart
+    net = elwh.WarmStartNet(max_batch=nprob, H=warmstart.N_CELLS, seed=0)
+    meta = warmstart.load_weights(net)
+    r = warmstart.evaluate(net, list(range(first_seed, first_seed + nprob)), batch=nprob, tol=1e-8,
+                           zero_fp32=False)
+    net.close()
+    r["workload"] = (f"config 5: {nprob} held-out problems (seeds {first_seed}..{first_seed + nprob - 1}), 256^2 "
+                     f"cells, omega ~ U[20, 60], 1-4 Gaussian sources of width U[2h, 6h]")
+    r["weights"] = {k: meta.get(k) for k in ("n_train", "epochs", "val_loss_after")}
+    return r
+
+
 def counters_pass(tile):
     """Dispatches for the HBM-traffic counters: a plain copy of 256 MiB (the
     scale reference: 262144 KiB read, 262144 KiB written) and three A_h
@@ -202,6 +243,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--all", action="store_true", help="also measure the 3-D 256^3 workload")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the batch (config 4) and time-to-1e-8 (config 5) measurements")
     ap.add_argument("--counters", default=None, metavar="V,TY",
                     help="counter-collection pass for rocprofv3 --pmc: a 256 MiB calibration copy, then 3 "
                          "A_h applications of the benchmark workload with the fixed FP64 tiling V,TY")
@@ -291,6 +334,12 @@ def main():
             log(f"3d {tag}: step kernel {1e3 * avg:.1f} us, {variants['3d_' + tag]['achieved_GBs']} GB/s")
             ctx3.close()
 
+    extra = {}
+    if not args.no_extra:
+        extra["batch_config4"] = batch_cfg4(elwh, inputs)
+        extra["time_to_1e-8"] = time_to_tol(elwh)
+        log(f"time to 1e-8: {json.dumps(extra['time_to_1e-8'])}")
+
     # practical HBM ceiling: a plain device-to-device copy of 2 GiB (beyond
     # the 256 MB last-level cache)
     x = torch.empty(2 ** 28, dtype=torch.float64, device="cuda").fill_(1.0)
@@ -322,7 +371,7 @@ def main():
                                "per step",
                    "grid": list(case.n), "omega": case.omega, "nt": nt, "unknown_nodes": nodes,
                    "lup_per_step": lup_per_step},
-        "roofline": roofline, "cpu_baseline": cpu, "variants": variants,
+        "roofline": roofline, "cpu_baseline": cpu, "variants": variants, **extra,
         "copy_ceiling_GBs": round(copy_gbs, 1),
     }
     print(json.dumps(out))

@@ -155,70 +155,76 @@ def predict_x0(net, cases):
     return x0
 
 
-def evaluate(net, seeds, batch=48, tol=1e-8, maxit=4000, control_batches=None):
+def evaluate(net, seeds, batch=48, tol=1e-8, maxit=4000, fp32_batches=None, zero_fp32=True):
     """Held-out comparison on the same GPU, per batch of problems:
-    plain   FP64 stepping, zero initial guess
-    learned FP32 stepping with FP64 residual replacements from the network's
-            x0, rescaled by the solver (scale_x0; the time includes feature
-            maps and inference)
-    plus the two controls (FP64 from x0; FP32 from zero) that separate the
-    warm start's effect from the precision's (the FP32-from-zero control runs
-    on the first control_batches batches only, all when None).  Batch
-    creation is excluded."""
-    res = {k: {"seconds": 0.0, "iters": [], "relres": [], "status": []}
-           for k in ("plain_fp64", "learned_fp32", "learned_fp64", "zero_fp32")}
+    plain_fp64    FP64 stepping, zero initial guess
+    learned_fp64  FP64 stepping from the network's x0
+    learned_fp32  FP32 stepping with FP64 residual replacements from x0
+    zero_fp32     FP32 stepping from zero (separates the precision's effect)
+    The learned starts are rescaled by the solver (scale_x0) and their times
+    include the feature maps and inference.  The FP32 runs cover the first
+    fp32_batches batches only (all when None).  Batch creation is excluded."""
+    keys = ("plain_fp64", "learned_fp64", "learned_fp32", "zero_fp32")
+    res = {k: {"seconds": 0.0, "iters": [], "relres": [], "status": [], "seeds": []} for k in keys}
+    plain_batch_s = []
+
+    def record(key, b, inf, st, extra_s, chunk):
+        r = res[key]
+        r["seconds"] += extra_s + b.stats()["seconds"]
+        r["iters"] += [i["iters"] for i in inf]
+        r["relres"] += [i["relres_fp64"] for i in inf]
+        r["status"].append(st)
+        r["seeds"] += chunk
+        log(f"  {key}: {b.stats()['seconds'] + extra_s:.1f} s, status {st}, mean iters "
+            f"{np.mean([i['iters'] for i in inf]):.1f}")
+
     for k in range(0, len(seeds), batch):
-        cases = [inputs.config5_problem(s, n=net.H) for s in seeds[k:k + batch]]
+        chunk = seeds[k:k + batch]
+        cases = [inputs.config5_problem(s, n=net.H) for s in chunk]
         f = [c.f for c in cases]
         # scale_x0 acts on given starts only: the zero-start runs are unchanged
         b64 = elwh.Batch(cases, scale_x0=1)
-        b32 = elwh.Batch(cases, prec=elwh.FP32_STEP, scale_x0=1)
         torch.cuda.synchronize()
         _, inf, st = b64.solve(f, tol=tol, maxit=maxit)
-        res["plain_fp64"]["seconds"] += b64.stats()["seconds"]
-        res["plain_fp64"]["iters"] += [i["iters"] for i in inf]
-        res["plain_fp64"]["relres"] += [i["relres_fp64"] for i in inf]
-        res["plain_fp64"]["status"].append(st)
+        record("plain_fp64", b64, inf, st, 0.0, chunk)
+        plain_batch_s.append(b64.stats()["seconds"])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         x0 = predict_x0(net, cases)
         torch.cuda.synchronize()
         t_inf = time.perf_counter() - t0
-        _, inf, st = b32.solve(f, x0s=x0, tol=tol, maxit=maxit)
-        res["learned_fp32"]["seconds"] += t_inf + b32.stats()["seconds"]
-        res["learned_fp32"]["iters"] += [i["iters"] for i in inf]
-        res["learned_fp32"]["relres"] += [i["relres_fp64"] for i in inf]
-        res["learned_fp32"]["status"].append(st)
         _, inf, st = b64.solve(f, x0s=x0, tol=tol, maxit=maxit)
-        res["learned_fp64"]["seconds"] += t_inf + b64.stats()["seconds"]
-        res["learned_fp64"]["iters"] += [i["iters"] for i in inf]
-        res["learned_fp64"]["relres"] += [i["relres_fp64"] for i in inf]
-        res["learned_fp64"]["status"].append(st)
-        if control_batches is not None and k // batch >= control_batches:
-            b64.close()
-            b32.close()
-            continue
-        _, inf, st = b32.solve(f, tol=tol, maxit=maxit)
-        res["zero_fp32"]["seconds"] += b32.stats()["seconds"]
-        res["zero_fp32"]["iters"] += [i["iters"] for i in inf]
-        res["zero_fp32"]["relres"] += [i["relres_fp64"] for i in inf]
-        res["zero_fp32"]["status"].append(st)
+        record("learned_fp64", b64, inf, st, t_inf, chunk)
         b64.close()
-        b32.close()
-        log(f"eval {k + len(cases)}/{len(seeds)}: plain {res['plain_fp64']['seconds']:.1f} s, "
-            f"learned {res['learned_fp32']['seconds']:.1f} s")
-    out = {}
-    z = np.array(res["plain_fp64"]["iters"], float)
+        if fp32_batches is None or k // batch < fp32_batches:
+            b32 = elwh.Batch(cases, prec=elwh.FP32_STEP, scale_x0=1)
+            _, inf, st = b32.solve(f, x0s=x0, tol=tol, maxit=maxit)
+            record("learned_fp32", b32, inf, st, t_inf, chunk)
+            if zero_fp32:
+                _, inf, st = b32.solve(f, tol=tol, maxit=maxit)
+                record("zero_fp32", b32, inf, st, 0.0, chunk)
+            b32.close()
+        log(f"eval {k + len(cases)}/{len(seeds)}")
+    out = {"n_problems": len(seeds), "tol": tol}
     for key, r in res.items():
         if not r["iters"]:
             continue
         it = np.array(r["iters"], float)
-        out[key] = {"seconds": r["seconds"], "mean_iters": float(it.mean()), "median_iters": float(np.median(it)),
-                    "max_relres_fp64": float(np.max(r["relres"])), "all_ok": all(s == "OK" for s in r["status"])}
+        out[key] = {"n": len(r["iters"]), "seconds": r["seconds"], "mean_iters": float(it.mean()),
+                    "median_iters": float(np.median(it)), "max_relres_fp64": float(np.max(r["relres"])),
+                    "all_ok": all(s == "OK" for s in r["status"])}
+    z = np.array(res["plain_fp64"]["iters"], float)
     lf = np.array(res["learned_fp64"]["iters"], float)
-    out["iteration_reduction_fp64"] = {"mean": float(np.mean(1 - lf / z)), "median": float(np.median(1 - lf / z))}
-    out["speedup_learned_fp32_vs_plain_fp64"] = res["plain_fp64"]["seconds"] / res["learned_fp32"]["seconds"]
-    out["n_problems"] = len(seeds)
+    out["iteration_reduction_learned_vs_zero_fp64"] = {"mean": float(np.mean(1 - lf / z)),
+                                                       "median": float(np.median(1 - lf / z))}
+    if res["learned_fp32"]["iters"]:
+        # wall time to tol on the problems the FP32 runs covered
+        plain_s = sum(plain_batch_s[:len(res["learned_fp32"]["status"])])
+        out["time_to_tol_same_problems"] = {
+            "problems": len(res["learned_fp32"]["iters"]), "plain_fp64_s": plain_s,
+            "learned_fp32_s": res["learned_fp32"]["seconds"],
+            "speedup_learned_fp32_vs_plain_fp64": plain_s / res["learned_fp32"]["seconds"]}
+    out["speedup_learned_fp64_vs_plain_fp64"] = res["plain_fp64"]["seconds"] / res["learned_fp64"]["seconds"]
     return out
 
 
@@ -243,7 +249,7 @@ def main(argv=None):
     e.add_argument("--batch", type=int, default=48)
     e.add_argument("--weights", default=WEIGHTS)
     e.add_argument("--json", default=None)
-    e.add_argument("--control-batches", type=int, default=None)
+    e.add_argument("--fp32-batches", type=int, default=None)
     a = ap.parse_args(argv)
     torch.cuda.set_device(0)
     net = elwh.WarmStartNet(max_batch=96, H=N_CELLS, seed=1234)
@@ -275,7 +281,7 @@ def main(argv=None):
     else:
         meta = load_weights(net, a.weights)
         seeds = list(range(a.first_seed, a.first_seed + a.n))
-        out = evaluate(net, seeds, batch=a.batch, control_batches=a.control_batches)
+        out = evaluate(net, seeds, batch=a.batch, fp32_batches=a.fp32_batches)
         out["weights_meta"] = {k: meta.get(k) for k in ("n_train", "epochs", "val_loss_after")}
         print(json.dumps(out))
         if a.json:
