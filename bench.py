@@ -182,7 +182,8 @@ def batch_cfg4(elwh, inputs):
     cases = inputs.config4()
     out = {"workload": "config 4: 48 problems, n ~ U{256..1024}, omega ~ U[10, 80], 1-4 Gaussian sources, "
                        "random log-normal media, free top", "tol": 1e-8}
-    for tag, kw in (("fp32", {"prec": elwh.FP32_STEP}), ("fp64", {})):
+    for tag, kw in (("fp64", {}), ("fp32", {"prec": elwh.FP32_STEP})):
+        log(f"config 4 {tag}: solving")
         bt = elwh.Batch(cases, **kw)
         fs = [c.f for c in cases]
         torch.cuda.synchronize()
@@ -243,8 +244,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--all", action="store_true", help="also measure the 3-D 256^3 workload")
-    ap.add_argument("--no-extra", action="store_true",
-                    help="skip the batch (config 4) and time-to-1e-8 (config 5) measurements")
+    ap.add_argument("--no-extra", action="store_true", help="skip the time-to-1e-8 (config 5) measurement")
+    ap.add_argument("--batch", action="store_true",
+                    help="also solve the config-4 batch (48 problems) in FP32 and FP64 (several minutes)")
     ap.add_argument("--counters", default=None, metavar="V,TY",
                     help="counter-collection pass for rocprofv3 --pmc: a 256 MiB calibration copy, then 3 "
                          "A_h applications of the benchmark workload with the fixed FP64 tiling V,TY")
@@ -336,9 +338,10 @@ def main():
 
     extra = {}
     if not args.no_extra:
-        extra["batch_config4"] = batch_cfg4(elwh, inputs)
         extra["time_to_1e-8"] = time_to_tol(elwh)
         log(f"time to 1e-8: {json.dumps(extra['time_to_1e-8'])}")
+    if args.batch:
+        extra["batch_config4"] = batch_cfg4(elwh, inputs)
 
     # practical HBM ceiling: a plain device-to-device copy of 2 GiB (beyond
     # the 256 MB last-level cache)

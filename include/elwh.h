@@ -243,7 +243,8 @@ elwh_status elwh_autotune(elwh_ctx* ctx, int prec, int reps, double* best_step_u
  *   and orders itself after / before the caller's stream).  Picks the batch
  *   tiling by timing when opts->autotune.  Errors: ELWH_ERR_ARG (also for a
  *   3-D problem), ELWH_ERR_ALLOC, ELWH_ERR_HIP.
- * elwh_batch_solve: f[i], x0[i] (x0 or any x0[i] may be NULL: zero guess),
+ * elwh_batch_solve (with ELWH_PROGRESS=1 in the environment it prints a progress
+ *   line to stderr at most every 10 s): f[i], x0[i] (x0 or any x0[i] may be NULL: zero guess),
  *   v[i] outputs (DEVICE pointers, caller layout); tol, maxit per problem as
  *   in elwh_solve; infos (nullable) receives nprob records.  Synchronous.
  *   Returns ELWH_OK when every problem converged, else the first failure.

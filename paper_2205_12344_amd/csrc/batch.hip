@@ -16,6 +16,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -263,6 +265,12 @@ elwh_status run_cg(elwh_batch* b, bool fp32, int ix, int ir, int ip, int iq, lon
     if (nact == 0) return ELWH_OK;
     if (b->use_graph) BST(graph_for(b, fp32, nblocks));
     long long ticks = 0;
+    // optional progress lines on stderr (ELWH_PROGRESS=1), at most every 10 s
+    static const bool progress = [] {
+        const char* e = std::getenv("ELWH_PROGRESS");
+        return e && e[0] == '1';
+    }();
+    auto last = std::chrono::steady_clock::now();
     while (true) {
         if (b->use_graph) {
             BCK(hipGraphLaunch(b->gexec[fp32 ? 1 : 0], b->stream));
@@ -274,6 +282,11 @@ elwh_status run_cg(elwh_batch* b, bool fp32, int ix, int ir, int ip, int iq, lon
         BCK(hipMemcpyAsync(b->h_active, b->d_active, sizeof(int), hipMemcpyDeviceToHost, b->stream));
         BCK(hipStreamSynchronize(b->stream));
         if (*b->h_active <= 0) break;
+        if (progress && std::chrono::steady_clock::now() - last > std::chrono::seconds(10)) {
+            last = std::chrono::steady_clock::now();
+            std::fprintf(stderr, "[elwh batch] %s CG: %lld ticks, %d of %d problems active\n", fp32 ? "FP32" : "FP64",
+                         ticks, *b->h_active, b->np);
+        }
         if (ticks >= max_ticks) {
             b->err = "batched CG exceeded its tick budget";
             break;

@@ -137,3 +137,26 @@ def test_scaled_warm_start(E, prec):
     for c, x in zip(cases, v2):
         prob, op, vs = _direct(c)
         assert _rel(prob.gather(x.cpu().numpy()), vs) <= 1e-6
+
+
+def test_config4_full_size_matches_single_contexts(E):
+    """Config 4 at full size (48 problems, 256^2..1024^2 cells, omega in
+    [10, 80], N_T up to ~3000) in one batch: two CG iterations of every
+    problem equal those of the single-problem path (itself pinned to the
+    oracle), which runs other kernels (K-step launches)."""
+    cases = inputs.config4()
+    bt = E.Batch(cases)
+    _say("config 4 batch tiles", bt.stats())
+    vs, infos, st = bt.solve([c.f for c in cases], tol=0.0, maxit=2)
+    assert st == "OK"
+    worst = 0.0
+    for c, v, info in zip(cases, vs, infos):
+        ctx = E.context_from_case(c, autotune=0)
+        assert ctx.info()["nt"] == info["nt"]
+        ctx.cg_begin(c.f)
+        ctx.cg_iterate(2)
+        v1, _ = ctx.cg_result()
+        worst = max(worst, _rel(v.cpu().numpy(), v1.cpu().numpy()))
+        ctx.close()
+    _say("config 4: worst rel diff batch vs single", worst)
+    assert worst <= 1e-12
