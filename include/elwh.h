@@ -93,6 +93,12 @@ typedef struct {
                           (x0, A_h x0)_M <= 0), so the start is never worse than
                           x0 = 0 in that norm; costs no extra application
                           (default 0) */
+    int cr_fallback;   /* CG paths: 1 (default) = when CG breaks down ((p, A_h p)_M
+                          <= 0: A_h slightly indefinite near resonance, the
+                          remark of Sec. 4.4), continue from the current iterate
+                          with the conjugate residual method in FP64 (the
+                          MINRES-type remedy the remark recommends); 0 = return
+                          ELWH_ERR_BREAKDOWN */
 } elwh_opts;
 
 typedef struct {
@@ -106,6 +112,7 @@ typedef struct {
     double relres;      /* last Krylov residual ||r||_M / ||b||_M (recurrence) */
     double relres_fp64; /* final ||b - A_h v||_M / ||b||_M recomputed with an FP64 apply */
     double cond_est;    /* Lanczos condition estimate from the CG coefficients (CG only) */
+    int cr_iters;       /* conjugate-residual iterations after a CG breakdown (cr_fallback), else 0 */
 } elwh_info;
 
 /* Fill *opts with the defaults listed above.  Never fails. */

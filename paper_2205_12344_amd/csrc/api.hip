@@ -197,11 +197,15 @@ elwh_status cg_steps(elwh_ctx* c, double* x, double* r, double* p, double* q, bo
                      double tol, CGOut* out, bool record) {
     for (int it = 0; it < k; ++it) {
         apply_A(c, p, q, fp32);
-        launch_dot_M_partial(c, p, q, c->stream);
+        launch_dot_pq_pp_partial(c, p, q, c->stream);
         launch_reduce_final(c, RED_PQ, 0, c->stream);
         launch_cg_update_xr(c, x, r, p, q, c->stream);
         launch_reduce_final(c, RED_RR, 0, c->stream);
         CKST(read_scalars(c));
+        if (c->hscal[S_FLAG] == 2.0) {
+            c->err = "(p, A_h p)_M / (p, p)_M lies outside the spectrum of a stable step: the time step is unstable";
+            return ELWH_ERR_UNSTABLE;
+        }
         if (c->hscal[S_FLAG] != 0.0) {
             c->err = "CG breakdown: (p, A_h p)_M <= 0 (A_h not positive definite near resonance)";
             return ELWH_ERR_BREAKDOWN;
@@ -407,6 +411,14 @@ elwh_status solve_gmres(elwh_ctx* c, bool x_zero, double tol, int maxit, int* it
 
 // ============================================================================
 
+namespace elwh {
+// Conjugate residual in FP64 from the iterate in VX (right-hand side in VB),
+// for the batch's fallback after a CG breakdown.
+elwh_status ctx_solve_cr(elwh_ctx* c, double tol, int maxit, int* iters, double* relres) {
+    return solve_cr(c, false, tol, maxit, iters, relres);
+}
+}  // namespace elwh
+
 extern "C" {
 
 void elwh_default_opts(elwh_opts* o) {
@@ -425,6 +437,7 @@ void elwh_default_opts(elwh_opts* o) {
     o->autotune = 1;
     o->fuse = 2;
     o->scale_x0 = 0;
+    o->cr_fallback = 1;
 }
 
 elwh_status elwh_plan(const elwh_grid* grid, const double* rho, const double* lam, const double* mu, double omega,
@@ -516,7 +529,7 @@ elwh_status elwh_create(const elwh_grid* grid, const double* rho, const double* 
         if (L.dim == 2 && ((st = alloc_t(c, &c->s32[2], FE)) || (st = alloc_t(c, &c->s32[3], FE))))
             return fail(st);
     }
-    if ((st = alloc_t(c, &c->partials, (size_t)c->red_blocks)) || (st = alloc_t(c, &c->dscal, (size_t)S_NSLOT)))
+    if ((st = alloc_t(c, &c->partials, 2 * (size_t)c->red_blocks)) || (st = alloc_t(c, &c->dscal, (size_t)S_NSLOT)))
         return fail(st);
     if (hipHostMalloc(reinterpret_cast<void**>(&c->hscal), S_NSLOT * sizeof(double), hipHostMallocDefault) !=
         hipSuccess) {
@@ -654,6 +667,7 @@ elwh_status elwh_cg_begin(elwh_ctx* c, const double* f, const double* x0) {
     c->betas.clear();
     CKST(cg_start(c, c->vec[VB], c->vec[VX], x0 == nullptr, c->vec[VR], c->vec[VP], c->vec[VQ], false, &c->cg_bb,
                   &rr));
+
     c->cg_iters = 0;
     c->cg_active = true;
     return ELWH_OK;
@@ -705,10 +719,24 @@ elwh_status elwh_solve(elwh_ctx* c, const double* f, const double* x0, double to
         CKST(elwh_cg_begin(c, f, x0));
         double rel = 0;
         st = elwh_cg_iterate(c, maxit, tol, &rel);
-        if (st != ELWH_OK && st != ELWH_ERR_NOT_CONVERGED) return st;
-        elwh_status st2 = elwh_cg_result(c, v, &inf);
-        if (st2 != ELWH_OK) return st2;
-        if (tol > 0 && !(inf.relres <= tol)) st = ELWH_ERR_NOT_CONVERGED;
+        if (st == ELWH_ERR_BREAKDOWN && c->opts.cr_fallback) {
+            // A_h slightly indefinite: conjugate residual from the last CG iterate
+            int it = 0;
+            double relcr = 1.0;
+            st = solve_cr(c, false, tol, std::max(1, maxit - c->cg_iters), &it, &relcr);
+            inf.cr_iters = it;
+            if (st != ELWH_OK && st != ELWH_ERR_NOT_CONVERGED) return st;
+            elwh_status st2 = elwh_cg_result(c, v, &inf);
+            if (st2 != ELWH_OK) return st2;
+            inf.cr_iters = it;
+            inf.relres = relcr;
+            if (tol > 0 && !(relcr <= tol)) st = ELWH_ERR_NOT_CONVERGED;
+        } else {
+            if (st != ELWH_OK && st != ELWH_ERR_NOT_CONVERGED) return st;
+            elwh_status st2 = elwh_cg_result(c, v, &inf);
+            if (st2 != ELWH_OK) return st2;
+            if (tol > 0 && !(inf.relres <= tol)) st = ELWH_ERR_NOT_CONVERGED;
+        }
     } else if (c->opts.prec == ELWH_FP64) {
         launch_pack(c->L, c->bc, f, c->f64, c->L.dim, c->stream);
         compute_rhs(c);
@@ -787,6 +815,19 @@ elwh_status elwh_solve(elwh_ctx* c, const double* f, const double* x0, double to
             CGOut o;
             elwh_status si = cg_steps(c, c->vec[VX], c->vec[VR], c->vec[VP], c->vec[VQ], true, seg, maxit - iters,
                                       tseg, &o, false);
+            if (si == ELWH_ERR_BREAKDOWN && c->opts.cr_fallback) {
+                // conjugate residual in FP64 from the current iterate
+                iters += o.iters;
+                int it = 0;
+                double relcr = 1.0;
+                st = solve_cr(c, false, tol, std::max(1, maxit - iters), &it, &relcr);
+                if (st != ELWH_OK && st != ELWH_ERR_NOT_CONVERGED) return st;
+                inf.cr_iters = it;
+                inf.relres = relcr;
+                CKST(final_residual(c, c->vec[VX], bb, &relfp64));
+                if (tol > 0) st = relfp64 <= tol ? ELWH_OK : ELWH_ERR_NOT_CONVERGED;
+                break;
+            }
             if (si != ELWH_OK) return si;
             iters += o.iters;
             ++outer;

@@ -213,6 +213,39 @@ elwh_status scale_start(elwh_batch* b, const std::vector<int>& sel) {
     return ELWH_OK;
 }
 
+// Problems whose CG broke down ((p, A_h p)_M <= 0) continue from their
+// current iterate with the conjugate residual method in FP64, one after the
+// other on the batch stream; their FP64 residual is then recomputed.
+elwh_status cr_fallback(elwh_batch* b, std::vector<int>& status, std::vector<int>& iters, std::vector<int>& cr_iters,
+                        std::vector<double>& relres, std::vector<double>& relfp64, const std::vector<double>& bb,
+                        double tol, int maxit) {
+    std::vector<int> sel(b->np, 0);
+    bool any = false;
+    for (int p = 0; p < b->np; ++p) {
+        if (status[p] != ELWH_ERR_BREAKDOWN) continue;
+        int it = 0;
+        double rel = 1.0;
+        elwh_status st = ctx_solve_cr(b->ctx[p], tol, std::max(1, maxit - iters[p]), &it, &rel);
+        if (st != ELWH_OK && st != ELWH_ERR_NOT_CONVERGED && st != ELWH_ERR_BREAKDOWN) {
+            b->err = elwh_last_error(b->ctx[p]);
+            return st;
+        }
+        cr_iters[p] = it;
+        relres[p] = rel;
+        status[p] = (tol <= 0 && st == ELWH_ERR_NOT_CONVERGED) ? ELWH_OK : st;
+        sel[p] = 1;
+        any = true;
+    }
+    if (!any) return ELWH_OK;
+    std::vector<double> rr;
+    BST(run_apply(b, false, false, true, VX, VQ, sel));
+    BST(lincomb(b, sel, VT, VB, 1.0, VQ, -1.0));
+    BST(dots(b, sel, VT, VT, rr));
+    for (int p = 0; p < b->np; ++p)
+        if (sel[p]) relfp64[p] = bb[p] > 0 ? std::sqrt(rr[p] / bb[p]) : 0.0;
+    return ELWH_OK;
+}
+
 void enqueue_ticks(elwh_batch* b, bool fp32, int nblocks, int nticks) {
     const Tile& t = b->tile[fp32 ? 1 : 0];
     const bool comp = fp32 && b->opts.compensated;
@@ -389,7 +422,7 @@ elwh_status elwh_batch_create(int nprob, const elwh_grid* grids, const double* c
               dalloc(reinterpret_cast<void**>(&b->d_st), sizeof(BState) * nprob) &&
               dalloc(reinterpret_cast<void**>(&b->d_mask), sizeof(int) * nprob) &&
               dalloc(reinterpret_cast<void**>(&b->d_active), sizeof(int)) &&
-              dalloc(reinterpret_cast<void**>(&b->d_partials), sizeof(double) * nprob * BATCH_RED_BLOCKS) &&
+              dalloc(reinterpret_cast<void**>(&b->d_partials), 2 * sizeof(double) * nprob * BATCH_RED_BLOCKS) &&
               dalloc(reinterpret_cast<void**>(&b->d_dots), sizeof(double) * nprob) &&
               hipHostMalloc(reinterpret_cast<void**>(&b->h_active), sizeof(int), hipHostMallocDefault) == hipSuccess &&
               hipHostMalloc(reinterpret_cast<void**>(&b->h_dots), sizeof(double) * nprob, hipHostMallocDefault) ==
@@ -490,7 +523,7 @@ elwh_status elwh_batch_solve(elwh_batch* b, const double* const* f, const double
     BST(run_apply(b, false, true, false, VT, VB, all));
     std::vector<double> bb, rr;
     BST(dots(b, all, VB, VB, bb));
-    std::vector<int> iters(np, 0), outer(np, 0), status(np, ELWH_ERR_NOT_CONVERGED);
+    std::vector<int> iters(np, 0), outer(np, 0), status(np, ELWH_ERR_NOT_CONVERGED), cr_iters(np, 0);
     std::vector<double> relres(np, 1.0), relfp64(np, 1.0);
     std::vector<int> has_x(np, 0);
     for (int p = 0; p < np; ++p) has_x[p] = (x0 && x0[p]) ? 1 : 0;
@@ -536,6 +569,7 @@ elwh_status elwh_batch_solve(elwh_batch* b, const double* const* f, const double
         BST(lincomb(b, all, VT, VB, 1.0, VQ, -1.0));
         BST(dots(b, all, VT, VT, rr));
         for (int p = 0; p < np; ++p) relfp64[p] = bb[p] > 0 ? std::sqrt(rr[p] / bb[p]) : 0.0;
+        if (b->opts.cr_fallback) BST(cr_fallback(b, status, iters, cr_iters, relres, relfp64, bb, tol, maxit));
     } else {
         // FP32 stepping inside CG with FP64 reliable updates (as elwh_solve):
         // x, r, p stay FP64; each segment runs device-driven CG with FP32
@@ -614,6 +648,7 @@ elwh_status elwh_batch_solve(elwh_batch* b, const double* const* f, const double
             }
             BST(lincomb(b, pending, VP, VR, 1.0, VP, 0.0, &beta));
         }
+        if (b->opts.cr_fallback) BST(cr_fallback(b, status, iters, cr_iters, relres, relfp64, bb, tol, maxit));
     }
     for (int p = 0; p < np; ++p) launch_unpack(b->ctx[p]->L, b->ctx[p]->bc, b->ctx[p]->vec[VX], v[p], 2, b->stream);
     BCK(hipEventRecord(ev, b->stream));
@@ -635,6 +670,7 @@ elwh_status elwh_batch_solve(elwh_batch* b, const double* const* f, const double
         in.relres = relres[p];
         in.relres_fp64 = relfp64[p];
         in.cond_est = NAN;
+        in.cr_iters = cr_iters[p];
         if (infos) infos[p] = in;
         if (status[p] != ELWH_OK && worst == ELWH_OK) worst = (elwh_status)status[p];
         if (status[p] == ELWH_ERR_BREAKDOWN || status[p] == ELWH_ERR_UNSTABLE) worst = (elwh_status)status[p];

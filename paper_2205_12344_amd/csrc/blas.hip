@@ -130,15 +130,49 @@ __global__ __launch_bounds__(RB) void dotm_partial_kernel(const double* __restri
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
+// (p, q)_M into partials[0, gridDim) and (p, p)_M into partials[gridDim, 2 gridDim).
+__global__ __launch_bounds__(RB) void dot_pq_pp_partial_kernel(const double* __restrict__ p,
+                                                               const double* __restrict__ q,
+                                                               const double* __restrict__ m, int ncomp, int64_t CS,
+                                                               double* __restrict__ partials) {
+    double s = 0.0, s2 = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * RB + threadIdx.x; e < CS; e += (int64_t)gridDim.x * RB) {
+        const double me = m[e];
+        double t = 0.0, t2 = 0.0;
+        for (int c = 0; c < ncomp; ++c) {
+            const double pv = p[e + c * CS];
+            t += pv * q[e + c * CS];
+            t2 += pv * pv;
+        }
+        s += me * t;
+        s2 += me * t2;
+    }
+    s = block_sum(s);
+    s2 = block_sum(s2);
+    if (threadIdx.x == 0) {
+        partials[blockIdx.x] = s;
+        partials[gridDim.x + blockIdx.x] = s2;
+    }
+}
+
+// RED_PQ reduces two partial arrays: (p, q)_M from partials[0, n) and
+// (p, p)_M from partials[n, 2n).
 __global__ __launch_bounds__(1024) void reduce_final_kernel(const double* __restrict__ partials, int n,
                                                              double* __restrict__ sc, int mode, int slot) {
-    __shared__ double buf[1024];
-    double v = 0.0;
-    for (int k = threadIdx.x; k < n; k += 1024) v += partials[k];
+    __shared__ double buf[1024], buf2[1024];
+    double v = 0.0, v2 = 0.0;
+    for (int k = threadIdx.x; k < n; k += 1024) {
+        v += partials[k];
+        if (mode == RED_PQ) v2 += partials[n + k];
+    }
     buf[threadIdx.x] = v;
+    buf2[threadIdx.x] = v2;
     __syncthreads();
     for (int w = 512; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) buf[threadIdx.x] += buf[threadIdx.x + w];
+        if ((int)threadIdx.x < w) {
+            buf[threadIdx.x] += buf[threadIdx.x + w];
+            buf2[threadIdx.x] += buf2[threadIdx.x + w];
+        }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
@@ -146,8 +180,13 @@ __global__ __launch_bounds__(1024) void reduce_final_kernel(const double* __rest
         if (mode == RED_SUM) {
             sc[slot] = s;
         } else if (mode == RED_PQ) {
+            const double pp = buf2[0];
             sc[S_PQ] = s;
-            if (s > 0.0) {
+            sc[S_PP] = pp;
+            if (!(s <= kStableRayleighHi * pp && s >= kStableRayleighLo * pp)) {
+                sc[S_ALPHA] = 0.0;
+                sc[S_FLAG] = 2.0;  // Rayleigh quotient beyond a stable step's spectrum
+            } else if (s > 0.0) {
                 sc[S_ALPHA] = sc[S_RR] / s;
             } else {
                 sc[S_ALPHA] = 0.0;
@@ -224,6 +263,11 @@ void launch_convert_f32(const Layout& L, const double* src, float* dst, int ncom
 void launch_dot_M_partial(const elwh_ctx* c, const double* x, const double* y, hipStream_t s) {
     hipLaunchKernelGGL(dotm_partial_kernel, dim3(c->red_blocks), dim3(RB), 0, s, x, y, c->mw, c->L.dim, c->L.CS,
                        c->partials);
+}
+
+void launch_dot_pq_pp_partial(const elwh_ctx* c, const double* p, const double* q, hipStream_t s) {
+    hipLaunchKernelGGL(dot_pq_pp_partial_kernel, dim3(c->red_blocks), dim3(RB), 0, s, p, q, c->mw, c->L.dim,
+                       c->L.CS, c->partials);
 }
 
 void launch_reduce_final(const elwh_ctx* c, int mode, int slot, hipStream_t s) {

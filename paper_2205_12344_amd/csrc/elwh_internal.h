@@ -47,7 +47,9 @@ struct March {
 };
 
 // Device scalar slots used by the device-side CG updates.
-enum { S_RR = 0, S_PQ, S_RRNEW, S_ALPHA, S_BETA, S_BB, S_TMP, S_FLAG, S_NSLOT = 16 };
+// S_FLAG: 1 = CG breakdown ((p, A p)_M <= 0), 2 = unstable step (Rayleigh
+// quotient (p, A p)_M / (p, p)_M outside a stable step's spectrum)
+enum { S_RR = 0, S_PQ, S_RRNEW, S_ALPHA, S_BETA, S_BB, S_TMP, S_FLAG, S_PP, S_NSLOT = 16 };
 
 // Tiling of the fused step kernels: V nodes per lane along x, TY rows (2-D)
 // or TZ planes (3-D) marched per wavefront.
@@ -88,6 +90,12 @@ struct BState {
     int n, end, active, status, iters, maxit;
     double rr, pq, alpha, beta, bb, tol2;
 };
+
+// For a stable step every eigenvalue of A_h = I - S_h lies in [-3/2, 7/2]
+// (|beta_h(theta)| <= sum |w_n| <= 5/2), so a Rayleigh quotient
+// (p, A_h p)_M / (p, p)_M outside [kStableRayleighLo, kStableRayleighHi]
+// reveals an unstable time step; CG tests it at every iteration.
+constexpr double kStableRayleighLo = -2.0, kStableRayleighHi = 4.0;
 
 struct Plan {
     int nt = 0;
@@ -168,6 +176,9 @@ March make_march(const elwh_grid* g, const int bc[6]);
 // (nsteps = number of step launches of this application).
 void prof_mark(elwh_ctx* c, int phase, int nsteps = 0);
 bool tile_valid_2d(bool fp32, int V, int TY);
+// Conjugate residual (FP64 applications) from the iterate in vec[0] with the
+// right-hand side in vec[4], on the context's stream (api.hip).
+elwh_status ctx_solve_cr(elwh_ctx* c, double tol, int maxit, int* iters, double* relres);
 bool tile_valid_3d(bool fp32, int V, int TZ);
 
 // K = 2..4 time steps per launch (kernels2d_multi.hip): reads u^n (u) and
@@ -199,6 +210,8 @@ void run_filter(elwh_ctx* c, const double* x, bool with_force, bool amode, bool 
 
 // FP64 vector kernels over the padded layout (length = field_elems()).
 void launch_dot_M_partial(const elwh_ctx* c, const double* x, const double* y, hipStream_t s);
+// Partials of (p, q)_M and (p, p)_M in one pass (for RED_PQ).
+void launch_dot_pq_pp_partial(const elwh_ctx* c, const double* p, const double* q, hipStream_t s);
 void launch_reduce_final(const elwh_ctx* c, int mode, int slot, hipStream_t s);
 void launch_cg_update_xr(const elwh_ctx* c, double* x, double* r, const double* p, const double* q,
                          hipStream_t s);

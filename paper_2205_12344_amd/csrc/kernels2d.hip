@@ -355,8 +355,9 @@ __global__ void batch_advance_kernel(const BProb2D* __restrict__ pr, BState* __r
 
 constexpr int BRB = 64;   // reduction blocks per problem
 
-// mode 0: partial (p, q)_M; mode 1: x += alpha p, r -= alpha q, partial (r, r)_M;
-// mode 2: p = r + beta p.  Only problems that finished an application this tick.
+// mode 0: partials (p, q)_M (partials[p BRB + k]) and (p, p)_M (partials[(np + p) BRB + k]);
+// mode 1: x += alpha p, r -= alpha q, partial (r, r)_M; mode 2: p = r + beta p.
+// Only problems that finished an application this tick.
 template <int MODE>
 __global__ __launch_bounds__(256) void batch_cg_kernel(const BProb2D* __restrict__ pr, const BState* __restrict__ st,
                                                        int np, double* __restrict__ partials) {
@@ -364,16 +365,18 @@ __global__ __launch_bounds__(256) void batch_cg_kernel(const BProb2D* __restrict
     if (p >= np || !st[p].active || !st[p].end) return;
     const BProb2D& q = pr[p];
     const int64_t CS = q.A.CS;
-    double s = 0.0;
+    double s = 0.0, s2 = 0.0;
     const double alpha = st[p].alpha, beta = st[p].beta;
     for (int64_t e = (int64_t)k * 256 + threadIdx.x; e < CS; e += (int64_t)BRB * 256) {
         const double me = q.m[e];
-        double t = 0.0;
+        double t = 0.0, t2 = 0.0;
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
             const int64_t o = e + c * CS;
             if (MODE == 0) {
-                t += q.cp[o] * q.out[o];
+                const double pv = q.cp[o];
+                t += pv * q.out[o];
+                t2 += pv * pv;
             } else if (MODE == 1) {
                 q.cx[o] += alpha * q.cp[o];
                 const double rn = q.cr[o] - alpha * q.out[o];
@@ -384,15 +387,25 @@ __global__ __launch_bounds__(256) void batch_cg_kernel(const BProb2D* __restrict
             }
         }
         s += me * t;
+        s2 += me * t2;
     }
     if (MODE == 2) return;
     // wavefront then block reduction
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-    __shared__ double red[4];
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    for (int off = 32; off > 0; off >>= 1) {
+        s += __shfl_down(s, off, 64);
+        s2 += __shfl_down(s2, off, 64);
+    }
+    __shared__ double red[4], red2[4];
+    if ((threadIdx.x & 63) == 0) {
+        red[threadIdx.x >> 6] = s;
+        red2[threadIdx.x >> 6] = s2;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) partials[p * BRB + k] = red[0] + red[1] + red[2] + red[3];
+    if (threadIdx.x == 0) {
+        partials[p * BRB + k] = red[0] + red[1] + red[2] + red[3];
+        if (MODE == 0) partials[(np + p) * BRB + k] = red2[0] + red2[1] + red2[2] + red2[3];
+    }
 }
 
 // Finish the reductions of the ending problems.  mode 0: alpha = rr / pq;
@@ -404,13 +417,21 @@ __global__ __launch_bounds__(64) void batch_cg_final_kernel(BState* __restrict__
     const int p = (int)blockIdx.x;
     if (p >= np || !st[p].active || !st[p].end) return;
     double s = partials[p * BRB + threadIdx.x];   // BRB == 64 == blockDim
+    double s2 = MODE == 0 ? partials[(np + p) * BRB + threadIdx.x] : 0.0;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    for (int off = 32; off > 0; off >>= 1) {
+        s += __shfl_down(s, off, 64);
+        s2 += __shfl_down(s2, off, 64);
+    }
     if (threadIdx.x != 0) return;
     BState& b = st[p];
     if (MODE == 0) {
         b.pq = s;
-        if (s > 0.0 && isfinite(s)) {
+        if (!(s <= kStableRayleighHi * s2 && s >= kStableRayleighLo * s2)) {
+            b.status = ELWH_ERR_UNSTABLE;   // Rayleigh quotient beyond a stable step's spectrum
+            b.active = 0;
+            atomicSub(n_active, 1);
+        } else if (s > 0.0 && isfinite(s)) {
             b.alpha = b.rr / s;
         } else {
             b.status = isfinite(s) ? ELWH_ERR_BREAKDOWN : ELWH_ERR_UNSTABLE;

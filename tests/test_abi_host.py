@@ -40,13 +40,13 @@ def test_struct_sizes_match_header(elwh):
     # the ctypes mirrors must have the C layout (checked against field offsets)
     assert ctypes.sizeof(elwh.Grid) == 40 and elwh.Grid.len.offset == 16
     assert elwh.Opts.stream.offset == 56
-    assert ctypes.sizeof(elwh.Info) == 4 * 4 + 6 * 8
+    assert ctypes.sizeof(elwh.Info) == 4 * 4 + 6 * 8 + 8
 
 
 def test_default_opts(elwh):
     o = elwh.default_opts()
     assert o.cfl == 0.8 and o.periods == 1 and o.nt == 0 and o.prec == 0 and o.compensated == 1 and o.autotune == 1
-    assert o.fuse == 2 and o.scale_x0 == 0 and o.inner_tol == 1e-2
+    assert o.fuse == 2 and o.scale_x0 == 0 and o.inner_tol == 1e-2 and o.cr_fallback == 1
 
 
 def _media(shape, seed):

@@ -160,3 +160,33 @@ def test_config4_full_size_matches_single_contexts(E):
         ctx.close()
     _say("config 4: worst rel diff batch vs single", worst)
     assert worst <= 1e-12
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_cr_fallback_after_cg_breakdown(E, prec):
+    """A near-resonant warm-start problem (config 5, seed 4115, coarsened to
+    64^2: omega = 59.0, N_T = 31) makes A_h slightly indefinite and CG break
+    down (the oracle's CG does too); with cr_fallback the solve continues with
+    conjugate residual in FP64 and reaches the residual target, alone and in
+    a batch with other problems.  The system is nearly singular (a mode
+    within ~1e-5 of resonance), so a residual of 1e-8 bounds the error only
+    to ~1e-4 (the oracle's CR from zero happens to land at 2e-7); the check
+    on the solution is accordingly |v - v*| / |v*| <= 1e-3."""
+    c = inputs.config5_problem(4115, n=64)
+    prob, op, vstar = _direct(c)
+    with pytest.raises(E.ElwhError, match="BREAKDOWN"):
+        E.context_from_case(c, prec=prec, cr_fallback=0).solve(c.f, tol=1e-8, maxit=3000)
+    v, info = E.context_from_case(c, prec=prec).solve(c.f, tol=1e-8, maxit=3000)
+    _say("single: cg iters", info["iters"], "cr iters", info["cr_iters"], "relres", info["relres_fp64"])
+    assert info["cr_iters"] > 0 and info["relres_fp64"] <= 2e-8
+    assert _rel(prob.gather(v.cpu().numpy()), vstar) <= 1e-3
+    cases = [c] + [inputs.config5_problem(s, n=64) for s in (4099, 4096)]
+    bt = E.Batch(cases, prec=prec)
+    vs, infos, st = bt.solve([x.f for x in cases], tol=1e-8, maxit=3000)
+    _say("batch:", st, [(i["iters"], i["cr_iters"], i["relres_fp64"]) for i in infos])
+    assert st == "OK"
+    assert infos[0]["cr_iters"] > 0
+    for x, vv, info in zip(cases, vs, infos):
+        prob, op, vs_ = _direct(x)
+        assert info["relres_fp64"] <= 2e-8
+        assert _rel(prob.gather(vv.cpu().numpy()), vs_) <= 1e-3

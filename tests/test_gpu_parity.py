@@ -334,14 +334,20 @@ def test_rejects_bad_arguments(E):
         E.Context(2, (8, 8), ok, ok, ok, 0.0, (0, 0, 0, 0))
 
 
-def test_unstable_step_is_reported(E):
-    """A step count far below the stability limit makes the energy grow; the
-    solver reports ELWH_ERR_UNSTABLE (or a breakdown of the indefinite
-    operator) instead of returning garbage."""
+@pytest.mark.parametrize("prec", [0, 1])
+def test_unstable_step_is_reported(E, prec):
+    """A step count far below the stability limit (N_T = 6 where the rule
+    gives 121) makes the solution grow by orders of magnitude per step; the
+    first Rayleigh quotient (b, A_h b)_M / (b, b)_M then exceeds 4, which no
+    stable step allows (|beta_h| <= 5/2), and the solver reports
+    ELWH_ERR_UNSTABLE, alone and in a batch, instead of returning garbage."""
     c = inputs.config1()
-    ctx = E.Context(2, c.n, c.rho, c.lam, c.mu, c.omega, c.bc, nt=6)
+    ctx = E.Context(2, c.n, c.rho, c.lam, c.mu, c.omega, c.bc, nt=6, prec=prec)
     v, info = ctx.solve(c.f, tol=1e-10, maxit=50, raise_on_fail=False)
-    assert info["status"] in ("ERR_UNSTABLE", "ERR_BREAKDOWN")
+    assert info["status"] == "ERR_UNSTABLE"
+    bt = E.Batch([c, inputs.config1()], nt=6, prec=prec)
+    _, infos, st = bt.solve([c.f, c.f], tol=1e-10, maxit=50)
+    assert st == "ERR_UNSTABLE"
 
 
 # ---------------------------------------------------------------- full size --
