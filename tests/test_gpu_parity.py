@@ -454,3 +454,21 @@ def test_autotune_choice_is_valid_and_cached(E):
     v32, r32 = ctx.get_tile(1)
     assert (v64, r64) in _tiles(2, False) and (v32, r32) in _tiles(2, True)
     assert ctx.autotune(0) == -1.0          # cached per process
+
+
+@pytest.mark.parametrize("K", [1, 2, 5])
+def test_k_period_solve_matches_oracle(E, K):
+    """K-period filter (eq. many_periods_filter) inside CG on the FD bar of
+    the Table 3 analogue: the library's iteration count equals the oracle's
+    (+-1) and the solutions agree."""
+    n, length, bc = (128, 16), (8.0, 1.0), (0, 0, 1, 1)
+    shape = (17, 129)
+    rho, lam, mu = np.ones(shape), 2.0 * np.ones(shape), np.ones(shape)
+    f = inputs.gaussian_sources(2, n, length, [(1.0, 0.5)], [0.25], [(1.0, 0.0)])
+    prob, op, wh = _oracle(2, n, length, bc, rho, lam, mu, 5.123, periods=K)
+    res = krylov.cg(wh.apply_A, wh.rhs(prob.gather(f)), op.m, tol=1e-10, maxit=2000)
+    ctx = E.Context(2, n, rho, lam, mu, 5.123, bc, length=length, periods=K)
+    v, info = ctx.solve(f, tol=1e-10, maxit=2000)
+    _say("K periods", K, "iters", info["iters"], "oracle", res.iters)
+    assert abs(info["iters"] - res.iters) <= 1
+    assert _rel(prob.gather(v.cpu().numpy()), res.x) <= 1e-8
