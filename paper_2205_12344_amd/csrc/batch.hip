@@ -53,7 +53,7 @@ struct elwh_batch {
     double* h_dots = nullptr;       // pinned
     std::vector<double*> d_w, d_cos;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
-    int gblocks[2] = {0, 0};
+    int gblocks[2] = {0, 0}, gblocks2[2] = {0, 0};
     std::vector<elwh_info> info;
     double seconds = 0;
     long long ticks = 0;
@@ -79,10 +79,11 @@ thread_local std::string g_batch_err;
 
 // Descriptors of every problem for one phase (precision fp32), vector roles
 // given by indices into the context's work vectors.
-elwh_status set_phase(elwh_batch* b, bool fp32, int isrc, int iout, int ix, int ir, int ip, int* nblocks) {
+elwh_status set_phase(elwh_batch* b, bool fp32, int isrc, int iout, int ix, int ir, int ip, int* nblocks,
+                      int* nblocks2 = nullptr) {
     const Tile& t = b->tile[fp32 ? 1 : 0];
-    const int W = batch_cols(t.V);
-    int off = 0;
+    const int W = batch_cols(t.V), W2 = batch_cols2(t.V);
+    int off = 0, off2 = 0;
     b->h_pr.resize(b->np);
     for (int p = 0; p < b->np; ++p) {
         elwh_ctx* c = b->ctx[p];
@@ -94,19 +95,21 @@ elwh_status set_phase(elwh_batch* b, bool fp32, int isrc, int iout, int ix, int 
         q.nblk = q.nbx * ((nrows + t.TY - 1) / t.TY);
         q.off = off;
         off += q.nblk;
+        q.nbx2 = (q.A.nx - 1 + W2) / W2;
+        q.nblk2 = q.nbx2 * ((nrows + t.TY - 1) / t.TY);
+        q.off2 = off2;
+        off2 += q.nblk2;
         q.nsteps = c->plan.nt * c->opts.periods;
         q.w = b->d_w[p];
         q.cosn = b->d_cos[p];
         if (fp32) {
-            q.s0 = c->s32[0];
-            q.s1 = c->s32[1];
+            for (int k = 0; k < 4; ++k) q.s[k] = c->s32[k];
             q.ca = c->fa;
             q.cl = c->fl;
             q.cm = c->fm;
             q.f = c->f32;
         } else {
-            q.s0 = c->s64[0];
-            q.s1 = c->s64[1];
+            for (int k = 0; k < 4; ++k) q.s[k] = c->s64[k];
             q.ca = c->ca;
             q.cl = c->cl;
             q.cm = c->cm;
@@ -122,6 +125,7 @@ elwh_status set_phase(elwh_batch* b, bool fp32, int isrc, int iout, int ix, int 
         for (int k = 0; k < 8; ++k) q.vec[k] = c->vec[k];
     }
     *nblocks = off;
+    if (nblocks2) *nblocks2 = off2;
     BCK(hipMemcpyAsync(b->d_pr, b->h_pr.data(), sizeof(BProb2D) * b->np, hipMemcpyHostToDevice, b->stream));
     BCK(hipStreamSynchronize(b->stream));   // h_pr is rewritten by the next phase
     return ELWH_OK;
@@ -145,27 +149,39 @@ elwh_status upload_mask(elwh_batch* b, const std::vector<int>& mask) {
     return ELWH_OK;
 }
 
+// Ticks of one application: the half step, then two-step ticks while two or
+// more steps are left (fuse2), single steps otherwise.
+int ticks_per_application(int nsteps, int fuse2) {
+    const int rest = nsteps - 1;
+    return 1 + (fuse2 ? rest / 2 + rest % 2 : rest);
+}
+
 // One filter application per selected problem: out = Pi_h src (with the
 // forcing) or A_h src.  Ragged: runs max N_T ticks.
 elwh_status run_apply(elwh_batch* b, bool fp32, bool force, bool amode, int isrc, int iout,
                       const std::vector<int>& sel) {
-    int nblocks = 0;
-    BST(set_phase(b, fp32, isrc, iout, -1, -1, -1, &nblocks));
-    int maxsteps = 0;
+    int nblocks = 0, nblocks2 = 0;
+    BST(set_phase(b, fp32, isrc, iout, -1, -1, -1, &nblocks, &nblocks2));
+    const int fuse2 = b->opts.fuse >= 2 ? 1 : 0;
+    int maxticks = 0;
     for (int p = 0; p < b->np; ++p) {
         BState& s = b->h_st[p];
         s.n = 0;
         s.end = 0;
         s.active = sel[p] ? 1 : 0;
-        if (sel[p]) maxsteps = std::max(maxsteps, b->h_pr[p].nsteps);
+        if (sel[p]) maxticks = std::max(maxticks, ticks_per_application(b->h_pr[p].nsteps, fuse2));
     }
     BST(upload_states(b));
     const Tile& t = b->tile[fp32 ? 1 : 0];
     const bool comp = fp32 && b->opts.compensated;
-    for (int k = 0; k < maxsteps; ++k) {
-        launch_batch_step(fp32, t.V, t.TY, force, comp, nblocks, b->stream, b->d_pr, b->d_st, b->np,
-                          amode ? -1.0 : 1.0, amode ? 1 : 0);
-        launch_batch_advance(b->stream, b->d_pr, b->d_st, b->np, 1);
+    const double sgn = amode ? -1.0 : 1.0;
+    for (int k = 0; k < maxticks; ++k) {
+        launch_batch_step(fp32, t.V, t.TY, force, comp, nblocks, b->stream, b->d_pr, b->d_st, b->np, sgn,
+                          amode ? 1 : 0, fuse2);
+        if (fuse2)
+            launch_batch_multi(fp32, t.V, t.TY, force, comp, nblocks2, b->stream, b->d_pr, b->d_st, b->np, sgn,
+                               amode ? 1 : 0);
+        launch_batch_advance(b->stream, b->d_pr, b->d_st, b->np, 1, fuse2, fp32 ? 1 : 0);
         b->ticks++;
     }
     BCK(hipGetLastError());
@@ -246,28 +262,31 @@ elwh_status cr_fallback(elwh_batch* b, std::vector<int>& status, std::vector<int
     return ELWH_OK;
 }
 
-void enqueue_ticks(elwh_batch* b, bool fp32, int nblocks, int nticks) {
+void enqueue_ticks(elwh_batch* b, bool fp32, int nblocks, int nblocks2, int nticks) {
     const Tile& t = b->tile[fp32 ? 1 : 0];
     const bool comp = fp32 && b->opts.compensated;
+    const int fuse2 = b->opts.fuse >= 2 ? 1 : 0;
     for (int k = 0; k < nticks; ++k) {
-        launch_batch_step(fp32, t.V, t.TY, false, comp, nblocks, b->stream, b->d_pr, b->d_st, b->np, -1.0, 1);
-        launch_batch_advance(b->stream, b->d_pr, b->d_st, b->np, 0);
+        launch_batch_step(fp32, t.V, t.TY, false, comp, nblocks, b->stream, b->d_pr, b->d_st, b->np, -1.0, 1, fuse2);
+        if (fuse2)
+            launch_batch_multi(fp32, t.V, t.TY, false, comp, nblocks2, b->stream, b->d_pr, b->d_st, b->np, -1.0, 1);
+        launch_batch_advance(b->stream, b->d_pr, b->d_st, b->np, 0, fuse2, fp32 ? 1 : 0);
         launch_batch_cg(b->stream, 0, b->d_pr, b->d_st, b->np, b->d_partials, b->d_active);
         launch_batch_cg(b->stream, 1, b->d_pr, b->d_st, b->np, b->d_partials, b->d_active);
         launch_batch_cg(b->stream, 2, b->d_pr, b->d_st, b->np, b->d_partials, b->d_active);
     }
 }
 
-elwh_status graph_for(elwh_batch* b, bool fp32, int nblocks) {
+elwh_status graph_for(elwh_batch* b, bool fp32, int nblocks, int nblocks2) {
     const int k = fp32 ? 1 : 0;
-    if (b->gexec[k] && b->gblocks[k] == nblocks) return ELWH_OK;
+    if (b->gexec[k] && b->gblocks[k] == nblocks && b->gblocks2[k] == nblocks2) return ELWH_OK;
     if (b->gexec[k]) {
         (void)hipGraphExecDestroy(b->gexec[k]);
         b->gexec[k] = nullptr;
     }
     hipGraph_t g;
     BCK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-    enqueue_ticks(b, fp32, nblocks, GRAPH_TICKS);
+    enqueue_ticks(b, fp32, nblocks, nblocks2, GRAPH_TICKS);
     BCK(hipStreamEndCapture(b->stream, &g));
     hipError_t e = hipGraphInstantiate(&b->gexec[k], g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
@@ -277,13 +296,14 @@ elwh_status graph_for(elwh_batch* b, bool fp32, int nblocks) {
         return ELWH_ERR_HIP;
     }
     b->gblocks[k] = nblocks;
+    b->gblocks2[k] = nblocks2;
     return ELWH_OK;
 }
 
 // Ragged CG phase: the states (active, rr, bb, tol2, maxit) are set by the caller.
 elwh_status run_cg(elwh_batch* b, bool fp32, int ix, int ir, int ip, int iq, long long max_ticks) {
-    int nblocks = 0;
-    BST(set_phase(b, fp32, ip, iq, ix, ir, ip, &nblocks));
+    int nblocks = 0, nblocks2 = 0;
+    BST(set_phase(b, fp32, ip, iq, ix, ir, ip, &nblocks, &nblocks2));
     int nact = 0;
     for (int p = 0; p < b->np; ++p) {
         BState& s = b->h_st[p];
@@ -296,7 +316,7 @@ elwh_status run_cg(elwh_batch* b, bool fp32, int ix, int ir, int ip, int iq, lon
     BCK(hipMemcpyAsync(b->d_active, b->h_active, sizeof(int), hipMemcpyHostToDevice, b->stream));
     BCK(hipStreamSynchronize(b->stream));
     if (nact == 0) return ELWH_OK;
-    if (b->use_graph) BST(graph_for(b, fp32, nblocks));
+    if (b->use_graph) BST(graph_for(b, fp32, nblocks, nblocks2));
     long long ticks = 0;
     // optional progress lines on stderr (ELWH_PROGRESS=1), at most every 10 s
     static const bool progress = [] {
@@ -308,7 +328,7 @@ elwh_status run_cg(elwh_batch* b, bool fp32, int ix, int ir, int ip, int iq, lon
         if (b->use_graph) {
             BCK(hipGraphLaunch(b->gexec[fp32 ? 1 : 0], b->stream));
         } else {
-            enqueue_ticks(b, fp32, nblocks, GRAPH_TICKS);
+            enqueue_ticks(b, fp32, nblocks, nblocks2, GRAPH_TICKS);
         }
         ticks += GRAPH_TICKS;
         b->ticks += GRAPH_TICKS;

@@ -71,11 +71,12 @@ struct Args2D {
 // Batched problem descriptor (device copy built by the host per phase).
 struct BProb2D {
     Args2D A;                 // geometry and stencil constants
-    int nbx, nblk, off;       // blocks along x, blocks per step launch, first block
-    int nsteps;               // launches per application (K N_T)
+    int nbx, nblk, off;       // single-step launch: blocks along x, blocks, first block
+    int nbx2, nblk2, off2;    // two-step launch: the same for its tiling
+    int nsteps;               // steps per application (K N_T)
     const double* w;          // filter weights w_n (sign +1), n = 0..nsteps
     const double* cosn;       // forcing factors cos(2 pi n / N_T)
-    void *s0, *s1;            // state buffers (FP64 or FP32)
+    void* s[4];               // state buffers (FP64 or FP32)
     const double* src;        // u^0 of the application
     double* out;              // accumulator = result of the application (q in CG)
     double* lo;               // compensation
@@ -88,6 +89,7 @@ struct BProb2D {
 // Per-problem device state of the ragged CG.
 struct BState {
     int n, end, active, status, iters, maxit;
+    int ic, ip;               // state buffers holding u^n and u^{n-1} (ip = -1: u^{n-1} = src)
     double rr, pq, alpha, beta, bb, tol2;
 };
 
@@ -226,8 +228,14 @@ bool batch_tile_valid(bool fp32, int V, int TY);
 int batch_cols(int V);
 Args2D make_args2d(const elwh_ctx* c);
 void launch_batch_step(bool fp32, int V, int TY, bool force, bool comp, int nblocks, hipStream_t s,
-                       const BProb2D* pr, const BState* st, int np, double sgn, int amode);
-void launch_batch_advance(hipStream_t s, const BProb2D* pr, BState* st, int np, int single);
+                       const BProb2D* pr, const BState* st, int np, double sgn, int amode, int fuse2);
+// fuse2: problems with two or more steps left take a two-step launch
+void launch_batch_advance(hipStream_t s, const BProb2D* pr, BState* st, int np, int single, int fuse2, int fp32);
+int batch_cols2(int V);
+// Two-step tick of every active problem with at least two steps left in its
+// application (kernels2d_multi.hip); nblocks2 = tiles of the two-step tiling.
+void launch_batch_multi(bool fp32, int V, int TY, bool force, bool comp, int nblocks2, hipStream_t s,
+                        const BProb2D* pr, const BState* st, int np, double sgn, int amode);
 void launch_batch_cg(hipStream_t s, int mode, const BProb2D* pr, BState* st, int np, double* partials,
                      int* n_active);
 void launch_batch_lincomb(hipStream_t s, const BProb2D* pr, int np, const int* mask, int idst, int ia,

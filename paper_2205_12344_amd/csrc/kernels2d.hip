@@ -296,61 +296,79 @@ bool tile_valid_2d(bool fp32, int V, int TY) {
 // next application in the next one, independently of the others.
 // ===========================================================================
 
-// Problem lookup: offsets ascending, np <= a few hundred.
-__device__ __forceinline__ int batch_problem(const BProb2D* __restrict__ pr, int np, int b) {
-    int p = 0;
-    while (p + 1 < np && b >= pr[p + 1].off) ++p;
-    return p;
-}
-
+// Single-step tick: the half step that starts an application, and every
+// step of problems that do not take a two-step launch this tick (fuse2 = 0,
+// or one step left).  u^{n+1} overwrites u^{n-1} when that is a state buffer.
 template <typename T, int V, int TY, bool FORCE, bool COMP>
 __global__ __launch_bounds__(64) void batch_step2d_kernel(const BProb2D* __restrict__ pr, const BState* __restrict__ st,
-                                                          int np, int ntiles, double sgn, int amode) {
+                                                          int np, int ntiles, double sgn, int amode, int fuse2) {
     // XCD bands over the concatenated tiles of all problems
     int b;
     if (!xcd_tile((int)blockIdx.x, ntiles, b)) return;
-    const int p = batch_problem(pr, np, b);
+    const int p = batch_problem_of(pr, np, b, false);
     const BProb2D& q = pr[p];
     if (!st[p].active) return;
     const int neff = st[p].end ? 0 : st[p].n;
+    if (batch_two_step(neff, q.nsteps, fuse2)) return;
     const int local = b - q.off;
     if (local >= q.nblk) return;
     const int bx = local % q.nbx, by = local / q.nbx;
     Args2D A = q.A;
-    T* s0 = reinterpret_cast<T*>(q.s0);
-    T* s1 = reinterpret_cast<T*>(q.s1);
     const T* ca = reinterpret_cast<const T*>(q.ca);
     const T* cl = reinterpret_cast<const T*>(q.cl);
     const T* cm = reinterpret_cast<const T*>(q.cm);
     const T* f = reinterpret_cast<const T*>(q.f);
     if (neff == 0) {
+        // u^1 into s[1]; FP32 also keeps u^0 in s[0]
         A.w0 = sgn * q.w[0];
         A.w = sgn * q.w[1];
         A.fc = q.cosn[0];
         A.final_ = 0;
-        step2d_body<T, double, V, TY, 1, FORCE, COMP>(bx, by, q.src, nullptr, s1, amode ? q.src : nullptr,
-                                                      sizeof(T) == 4 ? s0 : nullptr, q.out, q.lo, ca, cl, cm, f, A);
+        step2d_body<T, double, V, TY, 1, FORCE, COMP>(bx, by, q.src, nullptr, reinterpret_cast<T*>(q.s[1]),
+                                                      amode ? q.src : nullptr,
+                                                      sizeof(T) == 4 ? reinterpret_cast<T*>(q.s[0]) : nullptr, q.out,
+                                                      q.lo, ca, cl, cm, f, A);
     } else {
         A.w = sgn * q.w[neff + 1];
         A.fc = q.cosn[neff];
         A.final_ = neff == q.nsteps - 1;
-        T* cur = (neff & 1) ? s1 : s0;
-        T* nxt = (neff & 1) ? s0 : s1;
-        const T* prev = (sizeof(T) == 8 && neff == 1) ? reinterpret_cast<const T*>(q.src) : nxt;
+        const int ic = st[p].ic, ip = st[p].ip;
+        T* cur = reinterpret_cast<T*>(q.s[ic]);
+        T* nxt = reinterpret_cast<T*>(q.s[batch_single_target(ic, ip)]);
+        const T* prev = ip >= 0 ? reinterpret_cast<const T*>(q.s[ip]) : reinterpret_cast<const T*>(q.src);
         step2d_body<T, T, V, TY, 0, FORCE, COMP>(bx, by, cur, prev, nxt, nullptr, nullptr, q.out, q.lo, ca, cl, cm, f,
                                                  A);
     }
 }
 
-// Advance the step counters after a batched step launch.  single: the phase
-// is one application per problem (deactivate when it completes).
-__global__ void batch_advance_kernel(const BProb2D* __restrict__ pr, BState* __restrict__ st, int np, int single) {
+// Advance the step counters and the roles of the state buffers after a tick
+// (the same rules the step kernels applied).  single: the phase is one
+// application per problem (deactivate when it completes).  After the half
+// step u^{n-1} = u^0 is src in FP64 and s[0] in FP32.
+__global__ void batch_advance_kernel(const BProb2D* __restrict__ pr, BState* __restrict__ st, int np, int single,
+                                     int fuse2, int fp32) {
     const int p = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (p >= np || !st[p].active) return;
-    const int neff = st[p].end ? 0 : st[p].n;
-    st[p].n = neff + 1;
-    st[p].end = st[p].n == pr[p].nsteps;
-    if (single && st[p].end) st[p].active = 0;
+    BState& s = st[p];
+    const int neff = s.end ? 0 : s.n;
+    int steps = 1;
+    if (neff == 0) {
+        s.ip = fp32 ? 0 : -1;
+        s.ic = 1;
+    } else if (batch_two_step(neff, pr[p].nsteps, fuse2)) {
+        int x1, x2;
+        batch_free_two(s.ic, s.ip, x1, x2);
+        s.ip = x1;
+        s.ic = x2;
+        steps = 2;
+    } else {
+        const int nxt = batch_single_target(s.ic, s.ip);
+        s.ip = s.ic;
+        s.ic = nxt;
+    }
+    s.n = neff + steps;
+    s.end = s.n == pr[p].nsteps;
+    if (single && s.end) s.active = 0;
 }
 
 constexpr int BRB = 64;   // reduction blocks per problem
@@ -509,10 +527,10 @@ __global__ __launch_bounds__(64) void batch_dot_final_kernel(int np, const int* 
 
 template <typename T, int V, int TY>
 static void batch_step_t(bool force, bool comp, int nblocks, hipStream_t s, const BProb2D* pr, const BState* st,
-                         int np, double sgn, int amode) {
+                         int np, double sgn, int amode, int fuse2) {
 #define ELWH_B2(F, C) \
     hipLaunchKernelGGL((batch_step2d_kernel<T, V, TY, F, C>), dim3((unsigned)xcd_grid(nblocks)), dim3(64), 0, s, pr, st, \
-                       np, nblocks, sgn, amode)
+                       np, nblocks, sgn, amode, fuse2)
     if (force) {
         if (comp) ELWH_B2(true, true); else ELWH_B2(true, false);
     } else {
@@ -530,9 +548,12 @@ bool batch_tile_valid(bool fp32, int V, int TY) {
 int batch_cols(int V) { return V == 1 ? Cols<1>::W : (V == 2 ? Cols<2>::W : Cols<4>::W); }
 
 void launch_batch_step(bool fp32, int V, int TY, bool force, bool comp, int nblocks, hipStream_t s,
-                       const BProb2D* pr, const BState* st, int np, double sgn, int amode) {
-#define ELWH_BT(T, VV, TT) \
-    if (V == VV && TY == TT) { batch_step_t<T, VV, TT>(force, comp, nblocks, s, pr, st, np, sgn, amode); return; }
+                       const BProb2D* pr, const BState* st, int np, double sgn, int amode, int fuse2) {
+#define ELWH_BT(T, VV, TT)                                                                          \
+    if (V == VV && TY == TT) {                                                                      \
+        batch_step_t<T, VV, TT>(force, comp, nblocks, s, pr, st, np, sgn, amode, fuse2);            \
+        return;                                                                                     \
+    }
     if (fp32) {
         ELWH_BT(float, 1, 4) ELWH_BT(float, 1, 8) ELWH_BT(float, 2, 4) ELWH_BT(float, 2, 8) ELWH_BT(float, 2, 16)
         ELWH_BT(float, 4, 8)
@@ -543,8 +564,8 @@ void launch_batch_step(bool fp32, int V, int TY, bool force, bool comp, int nblo
 #undef ELWH_BT
 }
 
-void launch_batch_advance(hipStream_t s, const BProb2D* pr, BState* st, int np, int single) {
-    hipLaunchKernelGGL(batch_advance_kernel, dim3((np + 63) / 64), dim3(64), 0, s, pr, st, np, single);
+void launch_batch_advance(hipStream_t s, const BProb2D* pr, BState* st, int np, int single, int fuse2, int fp32) {
+    hipLaunchKernelGGL(batch_advance_kernel, dim3((np + 63) / 64), dim3(64), 0, s, pr, st, np, single, fuse2, fp32);
 }
 
 void launch_batch_cg(hipStream_t s, int mode, const BProb2D* pr, BState* st, int np, double* partials,

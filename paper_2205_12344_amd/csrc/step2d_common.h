@@ -99,6 +99,45 @@ __device__ __forceinline__ void stencil2d(int kind, const Nb<T>& S, const Nb<T>&
     }
 }
 
+// ---- ragged batch: problem lookup and per-tick step kinds -----------------
+
+// Problem of a tile of the concatenated tiling (offsets ascending).
+__device__ __forceinline__ int batch_problem_of(const BProb2D* __restrict__ pr, int np, int b, bool two) {
+    int p = 0;
+    if (two) {
+        while (p + 1 < np && b >= pr[p + 1].off2) ++p;
+    } else {
+        while (p + 1 < np && b >= pr[p + 1].off) ++p;
+    }
+    return p;
+}
+
+// Step count of problem p at this tick (neff: steps done in its application)
+// and whether it takes a two-step launch.
+__host__ __device__ __forceinline__ bool batch_two_step(int neff, int nsteps, int fuse2) {
+    return fuse2 && neff >= 1 && nsteps - neff >= 2;
+}
+
+// The first two state buffers other than ic and ip (ip may be -1).
+__host__ __device__ __forceinline__ void batch_free_two(int ic, int ip, int& x1, int& x2) {
+    x1 = -1;
+    x2 = -1;
+    for (int i = 0; i < 4; ++i) {
+        if (i == ic || i == ip) continue;
+        if (x1 < 0) x1 = i;
+        else if (x2 < 0) x2 = i;
+    }
+}
+
+// Target of a single step: over u^{n-1} in place when that is a state
+// buffer, else the first free one.
+__host__ __device__ __forceinline__ int batch_single_target(int ic, int ip) {
+    if (ip >= 0) return ip;
+    int x1, x2;
+    batch_free_two(ic, ip, x1, x2);
+    return x1;
+}
+
 template <int V>
 struct Cols {
     static constexpr int W = V == 4 ? 252 : 64 * V - 2;   // computed columns per wavefront
