@@ -4,12 +4,14 @@
 // Krylov (Sec. 4.5): M A_h is symmetric, so CG runs on A_h in the M inner
 // product, A_h = I - S_h and b = Pi_h 0.  The CG scalars live on the device
 // (alpha and beta are formed by the reduction kernels), the host reads one
-// residual per iteration.  Conjugate residual (Remark of Sec. 4.5) and
-// restarted GMRES with classical Gram-Schmidt applied twice (used for
-// non-symmetric problems in Sec. 5.3) are host-driven over the same FP64
-// reductions.  The FP32 path wraps FP32-stepped inner CG solves in FP64
-// iterative refinement: r = b - A_h x with an FP64 apply, stop when
-// ||r||_M <= tol ||b||_M, else solve A_h d = r to inner_tol and x += d.
+// residual per iteration off the critical path.  Conjugate residual (Remark
+// of Sec. 4.5; also the fallback after a CG breakdown) and restarted GMRES
+// with classical Gram-Schmidt applied twice (used for non-symmetric problems
+// in Sec. 5.3) are host-driven over the same FP64 reductions.  The FP32 path
+// runs CG with FP32-stepped applications and FP64 vectors and replaces the
+// residual by b - A_h x from an FP64 application whenever it has fallen by
+// inner_tol, keeping the search direction (reliable updates); it stops on
+// that FP64 residual.
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -112,6 +114,8 @@ void free_all(elwh_ctx* c) {
     if (c->hscal) (void)hipHostFree(c->hscal);
     for (auto e : c->prof_ev) (void)hipEventDestroy(e);
     c->prof_ev.clear();
+    if (c->ev_scal) (void)hipEventDestroy(c->ev_scal);
+    c->ev_scal = nullptr;
 }
 
 // (x, y)_M into the host (synchronising).
@@ -226,6 +230,56 @@ elwh_status cg_steps(elwh_ctx* c, double* x, double* r, double* p, double* q, bo
         }
         if (record) c->betas.push_back(c->hscal[S_BETA]);
         launch_cg_update_p(c, p, r, c->stream);
+    }
+    return ELWH_OK;
+}
+
+// The same CG iterations with the host check taken off the critical path:
+// after an iteration's scalars are copied to the host (asynchronously), the
+// next direction p = r + beta p and its application q = A_h p are enqueued
+// before the host waits for and checks the copy, so the GPU never idles on
+// the host round trip.  A converged or failed iteration leaves p and q one
+// step ahead (q valid: cg_qready), which a later call continues from; the last
+// of the k iterations enqueues only the direction update.  FP64 stepping.
+elwh_status cg_steps_pipelined(elwh_ctx* c, double* x, double* r, double* p, double* q, double bb, int k, double tol,
+                               CGOut* out) {
+    if (!c->ev_scal) HIPCK(hipEventCreateWithFlags(&c->ev_scal, hipEventDisableTiming));
+    for (int it = 0; it < k; ++it) {
+        if (!c->cg_qready) apply_A(c, p, q, false);
+        c->cg_qready = false;
+        launch_dot_pq_pp_partial(c, p, q, c->stream);
+        launch_reduce_final(c, RED_PQ, 0, c->stream);
+        launch_cg_update_xr(c, x, r, p, q, c->stream);
+        launch_reduce_final(c, RED_RR, 0, c->stream);
+        HIPCK(hipMemcpyAsync(c->hscal, c->dscal, S_NSLOT * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCK(hipEventRecord(c->ev_scal, c->stream));
+        launch_cg_update_p(c, p, r, c->stream);
+        if (it + 1 < k) {
+            apply_A(c, p, q, false);
+            c->cg_qready = true;
+        }
+        HIPCK(hipEventSynchronize(c->ev_scal));
+        if (c->hscal[S_FLAG] == 2.0) {
+            c->err = "(p, A_h p)_M / (p, p)_M lies outside the spectrum of a stable step: the time step is unstable";
+            return ELWH_ERR_UNSTABLE;
+        }
+        if (c->hscal[S_FLAG] != 0.0) {
+            c->err = "CG breakdown: (p, A_h p)_M <= 0 (A_h not positive definite near resonance)";
+            return ELWH_ERR_BREAKDOWN;
+        }
+        const double rr = c->hscal[S_RR];
+        if (!std::isfinite(rr)) {
+            c->err = "non-finite residual: the time step is unstable";
+            return ELWH_ERR_UNSTABLE;
+        }
+        out->iters++;
+        out->relres = std::sqrt(rr / bb);
+        c->alphas.push_back(c->hscal[S_ALPHA]);
+        if (tol > 0 && out->relres <= tol) {
+            out->converged = true;
+            return ELWH_OK;
+        }
+        c->betas.push_back(c->hscal[S_BETA]);
     }
     return ELWH_OK;
 }
@@ -670,13 +724,14 @@ elwh_status elwh_cg_begin(elwh_ctx* c, const double* f, const double* x0) {
 
     c->cg_iters = 0;
     c->cg_active = true;
+    c->cg_qready = false;
     return ELWH_OK;
 }
 
 elwh_status elwh_cg_iterate(elwh_ctx* c, int k, double tol, double* relres) {
     if (!c || !c->cg_active || k < 0) return ELWH_ERR_ARG;
     CGOut o;
-    elwh_status st = cg_steps(c, c->vec[VX], c->vec[VR], c->vec[VP], c->vec[VQ], false, c->cg_bb, k, tol, &o, true);
+    elwh_status st = cg_steps_pipelined(c, c->vec[VX], c->vec[VR], c->vec[VP], c->vec[VQ], c->cg_bb, k, tol, &o);
     c->cg_iters += o.iters;
     if (relres) *relres = o.relres;
     return st;

@@ -157,6 +157,8 @@ struct elwh_ctx {
 
     // CG state of the stepwise interface
     bool cg_active = false;
+    bool cg_qready = false;            // q = A_h p already computed for the next CG iteration
+    hipEvent_t ev_scal = nullptr;      // marks the device-to-host copy of the CG scalars
     int cg_iters = 0;
     double cg_bb = 0;
     std::vector<double> alphas, betas;
