@@ -472,3 +472,23 @@ def test_k_period_solve_matches_oracle(E, K):
     _say("K periods", K, "iters", info["iters"], "oracle", res.iters)
     assert abs(info["iters"] - res.iters) <= 1
     assert _rel(prob.gather(v.cpu().numpy()), res.x) <= 1e-8
+
+
+def test_cr_standard_scheme_point_source_matches_oracle(E):
+    """The rectangle of the iterations-vs-omega experiment (5 x 1, standard
+    scheme, discrete point source, conjugate residual to 1e-8) at
+    omega = 8 + sqrt(2)/10: the library's CR takes the oracle's iteration
+    count (+-1) and reaches its iterate."""
+    w = 8 + math.sqrt(2) / 10
+    n = (int(4 * 5 * w + 1), int(4 * w + 1))
+    shape = (n[1] + 1, n[0] + 1)
+    rho, lam, mu = np.ones(shape), 2.0 * np.ones(shape), np.ones(shape)
+    prob, op, wh = _oracle(2, n, (5.0, 1.0), (0, 0, 0, 0), rho, lam, mu, w, scheme=S.STANDARD)
+    f = np.zeros(prob.field_shape)
+    f[0, n[1] // 2, n[0] // 10] = w * w / ((5.0 / n[0]) * (1.0 / n[1]))
+    res = krylov.cr(wh.apply_A, wh.rhs(prob.gather(f)), op.m, tol=1e-8, maxit=3000)
+    ctx = E.Context(2, n, rho, lam, mu, w, (0, 0, 0, 0), length=(5.0, 1.0), scheme=1, krylov=2)
+    v, info = ctx.solve(f, tol=1e-8, maxit=3000)
+    _say("CR point source: iters", info["iters"], "oracle", res.iters)
+    assert abs(info["iters"] - res.iters) <= 1
+    assert _rel(prob.gather(v.cpu().numpy()), res.x) <= 1e-7
