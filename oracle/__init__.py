@@ -16,6 +16,8 @@ Modules
   krylov    CG / conjugate residual / GMRES in the M inner product (Sec. 4.5)
   direct    direct solve of the discrete Helmholtz system (Sec. 4.3)
   spectral  continuous and trapezoid filter transfer functions (Sec. 3, App. B)
+  curvilinear  the stress divergence on a mapped 2-D grid (Sec. 4.1; the
+            annular sectors of Sec. 5.4), same interface as operator
 
 All arithmetic is IEEE float64.  Parity status of each function is stated in
 its docstring; the free-surface closure is a reading of the paper (the paper
@@ -23,4 +25,4 @@ defers the exact boundary stencils to another publication) and its absolute
 values are "parity unpinned" beyond the invariants listed there.
 """
 
-from . import problem, operator, stepping, krylov, direct, spectral  # noqa: F401
+from . import problem, operator, stepping, krylov, direct, spectral, curvilinear  # noqa: F401

@@ -250,3 +250,60 @@ def config5_problem(seed, n=256):
 def random_field(shape, seed):
     """Plain standard-normal test vector (for operator-level parity tests)."""
     return np.random.default_rng(seed).standard_normal(shape)
+
+
+# ---- mapped grids ------------------------------------------------------------
+
+def sector_grid(nq, nr, n_an, arc=5.0):
+    """Node coordinates (x, y), each of shape (nr + 1, nq + 1), of the annular
+    sectors of the iterations-vs-frequency experiment (Sec. 5.4): q in [0, 1]
+    runs radially from r_in to r_out = r_in + 1, r in [0, 1] along the arc,
+    the outer arc has length `arc`; n_an = 1 is the quarter annulus
+    (r_out = 2 arc / pi), n_an = 2 the half annulus (r_out = arc / pi)."""
+    if n_an not in (1, 2):
+        raise ValueError("n_an must be 1 (quarter) or 2 (half annulus)")
+    r_out = 2.0 * arc / (n_an * math.pi)
+    r_in = r_out - 1.0
+    q = np.arange(nq + 1) / nq
+    r = np.arange(nr + 1) / nr
+    Q, R = np.meshgrid(q, r)
+    rad = r_in + (r_out - r_in) * Q
+    th = n_an * 0.5 * math.pi * R - 0.5 * math.pi
+    return rad * np.cos(th), rad * np.sin(th)
+
+
+def rectangle_grid(nq, nr, lq=1.0, lr=5.0):
+    """Node coordinates of the lq x lr rectangle as a mapped grid (q along x)."""
+    Q, R = np.meshgrid(np.arange(nq + 1) / nq, np.arange(nr + 1) / nr)
+    return lq * Q, lr * R
+
+
+def warped_grid(nq, nr, amp=0.06, seed=0):
+    """A smooth, strongly non-orthogonal map of the unit square: the identity
+    plus a seeded sum of low sine modes that vanish on no side (amplitude
+    `amp`, small enough that the map stays one-to-one)."""
+    rng = np.random.default_rng(seed)
+    Q, R = np.meshgrid(np.arange(nq + 1) / nq, np.arange(nr + 1) / nr)
+    x, y = Q.copy(), R.copy()
+    for _ in range(3):
+        kq, kr = rng.integers(1, 3, size=2)
+        ph = rng.uniform(0, 2 * math.pi, size=2)
+        c = rng.uniform(-1, 1, size=2)
+        x += amp * c[0] * np.sin(math.pi * kq * Q + ph[0]) * np.cos(math.pi * kr * R + ph[1])
+        y += amp * c[1] * np.cos(math.pi * kq * Q + ph[1]) * np.sin(math.pi * kr * R + ph[0])
+    return x, y
+
+
+def media_mapped(x, y, seed):
+    """Random log-normal media (recipe above) on a mapped grid: the GRF is
+    drawn on the (q, r) index grid with the correlation length measured in
+    physical arc length along each direction's mean spacing."""
+    shape = x.shape
+    hq = float(np.mean(np.hypot(np.diff(x, axis=1), np.diff(y, axis=1))))
+    hr = float(np.mean(np.hypot(np.diff(x, axis=0), np.diff(y, axis=0))))
+    rng = np.random.default_rng(seed)
+    gs = [grf(shape, (hq, hr), ell=0.1, rng=rng) for _ in range(3)]
+    rho = np.exp(0.2 * gs[0])
+    mu = np.exp(0.2 * gs[1])
+    lam = mu * np.clip(2.0 * np.exp(0.2 * gs[2]), 1.0, 3.0)
+    return rho, lam, mu
