@@ -142,6 +142,47 @@ elwh_status elwh_create(const elwh_grid* grid, const double* rho, const double* 
                         const double* mu, double omega, const int bc[6],
                         const elwh_opts* opts, elwh_ctx** out);
 
+/*
+ * Mapped (curvilinear) 2-D grids (Sec. 4.1; the annular sectors of the
+ * iterations-vs-frequency experiment, Sec. 5.4).  The domain is the image of
+ * the unit square under a smooth one-to-one map (q, r) -> (x, y); x and y
+ * hold the physical coordinates of the (n[0]+1) x (n[1]+1) nodes of the
+ * uniform (q, r) grid, in the node layout with q along the fast axis
+ * (grid->dim must be 2; grid->len is ignored: h_q = 1/n[0], h_r = 1/n[1]).
+ *
+ * The operator is J times the stress divergence in conservation form on the
+ * square, discretised from a non-negative discrete energy: compact
+ * D+(Kbar D-) terms along q and r and central D0(K D0) cross terms, with
+ * the 2x2 blocks K^ab = J [lam g_a g_b^T + mu (g_a . g_b) I + mu g_b g_a^T],
+ * g_q = grad q, g_r = grad r.  The metric terms come from second-order
+ * differences of the node coordinates (one-sided over three nodes on the
+ * edges of the square).  The mass is rho J and the forcing J f, so the
+ * solution satisfies omega^2 rho v + div T(v) = f discretely on the mapped
+ * grid, and every other entry point (elwh_apply_filter, elwh_apply_A,
+ * elwh_dot_M with M = rho J, the solvers, K periods, FP32 stepping, the
+ * stepwise CG) works unchanged on the context.  Fields keep the node
+ * layout [2][n[1]+1][n[0]+1] with Cartesian components (u, v) along x and y.
+ *
+ * bc: the four sides of the square (-q, +q, -r, +r); all must be Dirichlet.
+ * Every time step is one launch (opts->fuse is ignored).  x, y, rho, lam, mu
+ * are DEVICE pointers, copied.  Errors: ELWH_ERR_ARG (also for a map with
+ * J <= 0 at some node, i.e. folded or left-handed, or non-finite
+ * coordinates), ELWH_ERR_ALLOC, ELWH_ERR_HIP; on error *out is NULL.  The
+ * batched solver does not take mapped grids.
+ */
+elwh_status elwh_create_mapped(const elwh_grid* grid, const double* x, const double* y,
+                               const double* rho, const double* lam, const double* mu,
+                               double omega, const int bc[4], const elwh_opts* opts,
+                               elwh_ctx** out);
+
+/* elwh_plan for a mapped grid: HOST pointers, no GPU use; G is the
+ * Gershgorin bound of (rho J)^-1 L_h over the interior rows.  Errors as
+ * elwh_create_mapped (ELWH_ERR_ARG only). */
+elwh_status elwh_plan_mapped(const elwh_grid* grid, const double* x, const double* y,
+                             const double* rho, const double* lam, const double* mu,
+                             double omega, const int bc[4], const elwh_opts* opts,
+                             elwh_info* info);
+
 /* Release every device and host resource of ctx (NULL is a no-op). */
 void elwh_destroy(elwh_ctx* ctx);
 

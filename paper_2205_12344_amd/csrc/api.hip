@@ -50,7 +50,9 @@ void prof_mark(elwh_ctx* c, int phase, int nsteps) {
 }
 
 void run_filter(elwh_ctx* c, const double* x, bool with_force, bool amode, bool fp32, double* out) {
-    if (c->L.dim == 2)
+    if (c->mapped)
+        run_filter_curv2d(c, x, with_force, amode, fp32, out);
+    else if (c->L.dim == 2)
         run_filter_2d(c, x, with_force, amode, fp32, out);
     else
         run_filter_3d(c, x, with_force, amode, fp32, out);
@@ -105,6 +107,9 @@ void free_all(elwh_ctx* c) {
     };
     f(c->ca); f(c->cl); f(c->cm); f(c->mw);
     f(c->fa); f(c->fl); f(c->fm);
+    for (auto* p : c->cg) f(p);
+    for (auto* p : c->fg) f(p);
+    f(c->jac);
     for (auto* p : c->s64) f(p);
     for (auto* p : c->s32) f(p);
     f(c->acc); f(c->acc_lo); f(c->f64); f(c->f32);
@@ -161,6 +166,13 @@ struct CGOut {
 
 // x <- alpha x, q <- alpha q with alpha = (x, b)_M / (x, q)_M (q = A_h x);
 // alpha = 0 when (x, q)_M <= 0.
+// Forcing into the internal layout (and FP32 copy); a mapped grid takes J f.
+void pack_forcing(elwh_ctx* c, const double* f, bool fp32) {
+    launch_pack(c->L, c->bc, f, c->f64, c->L.dim, c->stream);
+    if (c->mapped) launch_scale_field(c->L, c->f64, c->jac, c->L.dim, c->stream);
+    if (fp32) launch_convert_f32(c->L, c->f64, c->f32, c->L.dim, c->stream);
+}
+
 elwh_status scale_start(elwh_ctx* c, const double* b, double* x, double* q) {
     double xb, xq;
     CKST(dot_host(c, x, b, &xb));
@@ -473,6 +485,215 @@ elwh_status ctx_solve_cr(elwh_ctx* c, double tol, int maxit, int* iters, double*
 }
 }  // namespace elwh
 
+namespace {
+// Create a context; xc/yc non-null: a mapped 2-D grid with these node
+// coordinates (host copies are taken here, like the materials).
+elwh_status create_impl(const elwh_grid* grid_in, const double* xc, const double* yc, const double* rho,
+                        const double* lam, const double* mu, double omega, const int* bc_in, const elwh_opts* opts,
+                        elwh_ctx** out) {
+    if (!out) return ELWH_ERR_ARG;
+    *out = nullptr;
+    elwh_opts o;
+    elwh_default_opts(&o);
+    if (opts) o = *opts;
+    g_create_err.clear();
+    if (!grid_in || !bc_in) {
+        g_create_err = "null grid or bc";
+        return ELWH_ERR_ARG;
+    }
+    const bool mapped = xc != nullptr;
+    elwh_grid gbuf = *grid_in;
+    int bc[6] = {ELWH_BC_DIRICHLET, ELWH_BC_DIRICHLET, ELWH_BC_DIRICHLET,
+                 ELWH_BC_DIRICHLET, ELWH_BC_DIRICHLET, ELWH_BC_DIRICHLET};
+    for (int f = 0; f < (mapped ? 4 : 2 * (gbuf.dim == 3 ? 3 : 2)); ++f) bc[f] = bc_in[f];
+    if (mapped) {
+        if (gbuf.dim != 2) {
+            g_create_err = "mapped grids are two-dimensional";
+            return ELWH_ERR_ARG;
+        }
+        gbuf.len[0] = gbuf.len[1] = 1.0;   // the reference square: h_q = 1/n_q, h_r = 1/n_r
+    }
+    const elwh_grid* grid = &gbuf;
+    elwh_status st = check_config(grid, bc, &o, &g_create_err);
+    if (st != ELWH_OK) return st;
+    if (!rho || !lam || !mu) {
+        g_create_err = "null material array";
+        return ELWH_ERR_ARG;
+    }
+    elwh_ctx* c = new (std::nothrow) elwh_ctx();
+    if (!c) return ELWH_ERR_ALLOC;
+    c->grid = *grid;
+    c->mapped = mapped;
+    for (int f = 0; f < 6; ++f) c->bc[f] = f < 2 * grid->dim ? bc[f] : ELWH_BC_DIRICHLET;
+    c->omega = omega;
+    c->opts = o;
+    c->stream = reinterpret_cast<hipStream_t>(o.stream);
+    c->L = make_layout(grid);
+    c->st = make_stencil(grid);
+    c->mr = make_march(grid, c->bc);
+
+    auto fail = [&](elwh_status s) {
+        g_create_err = c->err.empty() ? g_create_err : c->err;
+        free_all(c);
+        delete c;
+        return s;
+    };
+    const int64_t nn = c->L.nodes_caller();
+    std::vector<double> hr(nn), hl(nn), hm(nn);
+    if (hipMemcpyAsync(hr.data(), rho, nn * sizeof(double), hipMemcpyDefault, c->stream) != hipSuccess ||
+        hipMemcpyAsync(hl.data(), lam, nn * sizeof(double), hipMemcpyDefault, c->stream) != hipSuccess ||
+        hipMemcpyAsync(hm.data(), mu, nn * sizeof(double), hipMemcpyDefault, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+        c->err = "copying the materials failed (device pointers expected)";
+        return fail(ELWH_ERR_HIP);
+    }
+    MappedMetric met;
+    if (mapped) {
+        std::vector<double> hx(nn), hy(nn);
+        if (hipMemcpyAsync(hx.data(), xc, nn * sizeof(double), hipMemcpyDefault, c->stream) != hipSuccess ||
+            hipMemcpyAsync(hy.data(), yc, nn * sizeof(double), hipMemcpyDefault, c->stream) != hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess) {
+            c->err = "copying the node coordinates failed (device pointers expected)";
+            return fail(ELWH_ERR_HIP);
+        }
+        st = make_plan_mapped(grid, hx.data(), hy.data(), hr.data(), hl.data(), hm.data(), omega, c->bc, &o,
+                              &c->plan, &met, &c->err);
+    } else {
+        st = make_plan(grid, hr.data(), hl.data(), hm.data(), omega, c->bc, &o, &c->plan, &c->err);
+    }
+    if (st != ELWH_OK) return fail(st);
+
+    // weights of the (K-period) trapezoid filter and the forcing factors
+    const int ntot = c->plan.nt * o.periods;
+    c->w.resize(ntot + 1);
+    c->cosn.resize(ntot + 1);
+    for (int n = 0; n <= ntot; ++n) {
+        const double cn = std::cos(2.0 * M_PI * n / c->plan.nt);
+        const double eta = (n == 0 || n == ntot) ? 0.5 : 1.0;
+        c->cosn[n] = cn;
+        c->w[n] = (2.0 / ntot) * eta * (cn - 0.25);
+    }
+
+    const Layout& L = c->L;
+    const size_t CS = (size_t)L.CS, FE = (size_t)L.field_elems();
+    if ((st = alloc_t(c, &c->ca, CS)) || (st = alloc_t(c, &c->cl, CS)) || (st = alloc_t(c, &c->cm, CS)) ||
+        (st = alloc_t(c, &c->mw, CS)) || (st = alloc_t(c, &c->s64[0], FE)) || (st = alloc_t(c, &c->s64[1], FE)) ||
+        (st = alloc_t(c, &c->acc_lo, FE)) || (st = alloc_t(c, &c->f64, FE)))
+        return fail(st);
+    for (auto& v : c->vec)
+        if ((st = alloc_t(c, &v, FE))) return fail(st);
+    if (L.dim == 2 && ((st = alloc_t(c, &c->s64[2], FE)) || (st = alloc_t(c, &c->s64[3], FE)))) return fail(st);
+    if (o.prec == ELWH_FP32_STEP) {
+        if ((st = alloc_t(c, &c->fa, CS)) || (st = alloc_t(c, &c->fl, CS)) || (st = alloc_t(c, &c->fm, CS)) ||
+            (st = alloc_t(c, &c->s32[0], FE)) || (st = alloc_t(c, &c->s32[1], FE)) ||
+            (st = alloc_t(c, &c->f32, FE)))
+            return fail(st);
+        if (L.dim == 2 && ((st = alloc_t(c, &c->s32[2], FE)) || (st = alloc_t(c, &c->s32[3], FE))))
+            return fail(st);
+    }
+    if (mapped) {
+        for (int k = 0; k < 4; ++k)
+            if ((st = alloc_t(c, &c->cg[k], CS)) ||
+                (o.prec == ELWH_FP32_STEP && (st = alloc_t(c, &c->fg[k], CS))))
+                return fail(st);
+        if ((st = alloc_t(c, &c->jac, CS))) return fail(st);
+    }
+    if ((st = alloc_t(c, &c->partials, 2 * (size_t)c->red_blocks)) || (st = alloc_t(c, &c->dscal, (size_t)S_NSLOT)))
+        return fail(st);
+    if (hipHostMalloc(reinterpret_cast<void**>(&c->hscal), S_NSLOT * sizeof(double), hipHostMallocDefault) !=
+        hipSuccess) {
+        c->err = "pinned host allocation failed";
+        return fail(ELWH_ERR_ALLOC);
+    }
+    std::memset(c->hscal, 0, S_NSLOT * sizeof(double));
+
+    // coefficient arrays in the padded layout, built on the host in FP64
+    {
+        std::vector<double> ha(CS, 0.0), hlam(CS, 0.0), hmu(CS, 0.0), hmw(CS, 0.0);
+        std::vector<double> hg[4], hj;
+        if (mapped) {
+            for (auto& v : hg) v.assign(CS, 0.0);
+            hj.assign(CS, 0.0);
+        }
+        const double cdt2 = c->plan.c * c->plan.dt * c->plan.dt;
+        const int nzn = L.dim == 3 ? L.nz + 1 : 1;
+        for (int z = 0; z < nzn; ++z)
+            for (int y = 0; y <= L.ny; ++y)
+                for (int x = 0; x <= L.nx; ++x) {
+                    const int64_t src = ((int64_t)z * (L.ny + 1) + y) * (L.nx + 1) + x;
+                    const int64_t dst = (int64_t)z * L.PS + (int64_t)y * L.P + x;
+                    const double jw = mapped ? met.J[src] : 1.0;   // mass rho J, lambda/J, mu/J
+                    ha[dst] = cdt2 / (hr[src] * jw);
+                    hlam[dst] = hl[src] / jw;
+                    hmu[dst] = hm[src] / jw;
+                    if (mapped) {
+                        for (int k = 0; k < 4; ++k) hg[k][dst] = met.g[k][src];
+                        hj[dst] = jw;
+                    }
+                    bool unknown = true;
+                    double wn = 1.0;
+                    const int coord[3] = {x, y, z};
+                    const int nmax[3] = {L.nx, L.ny, L.nz};
+                    for (int a = 0; a < L.dim; ++a) {
+                        if (coord[a] == 0) {
+                            if (c->bc[2 * a] == ELWH_BC_DIRICHLET) unknown = false; else wn *= 0.5;
+                        }
+                        if (coord[a] == nmax[a]) {
+                            if (c->bc[2 * a + 1] == ELWH_BC_DIRICHLET) unknown = false; else wn *= 0.5;
+                        }
+                    }
+                    hmw[dst] = unknown ? wn * hr[src] * jw : 0.0;
+                }
+        if (hipMemcpyAsync(c->ca, ha.data(), CS * 8, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+            hipMemcpyAsync(c->cl, hlam.data(), CS * 8, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+            hipMemcpyAsync(c->cm, hmu.data(), CS * 8, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+            hipMemcpyAsync(c->mw, hmw.data(), CS * 8, hipMemcpyHostToDevice, c->stream) != hipSuccess) {
+            c->err = "uploading coefficients failed";
+            return fail(ELWH_ERR_HIP);
+        }
+        if (mapped) {
+            bool ok = hipMemcpyAsync(c->jac, hj.data(), CS * 8, hipMemcpyHostToDevice, c->stream) == hipSuccess;
+            for (int k = 0; k < 4 && ok; ++k)
+                ok = hipMemcpyAsync(c->cg[k], hg[k].data(), CS * 8, hipMemcpyHostToDevice, c->stream) == hipSuccess;
+            if (!ok) {
+                c->err = "uploading the metric failed";
+                return fail(ELWH_ERR_HIP);
+            }
+            if (o.prec == ELWH_FP32_STEP)
+                for (int k = 0; k < 4; ++k) launch_convert_f32(L, c->cg[k], c->fg[k], 1, c->stream);
+        }
+        if (o.prec == ELWH_FP32_STEP) {
+            launch_convert_f32(L, c->ca, c->fa, 1, c->stream);
+            launch_convert_f32(L, c->cl, c->fl, 1, c->stream);
+            launch_convert_f32(L, c->cm, c->fm, 1, c->stream);
+        }
+        if (hipStreamSynchronize(c->stream) != hipSuccess) {
+            c->err = "stream synchronisation failed in create";
+            return fail(ELWH_ERR_HIP);
+        }
+    }
+    // default tiling, then (optionally) the timed choice
+    if (mapped) {
+        c->tile64 = Tile{1, 8};
+        c->tile32 = Tile{2, 8};
+    } else if (c->L.dim == 2) {
+        c->tile64 = Tile{2, 8};
+        c->tile32 = Tile{4, 8};
+    } else {
+        c->tile64 = Tile{1, 16};
+        c->tile32 = Tile{1, 16};
+    }
+    if (o.autotune) {
+        if ((st = elwh_autotune(c, ELWH_FP64, 2, nullptr)) != ELWH_OK) return fail(st);
+        if (o.prec == ELWH_FP32_STEP && (st = elwh_autotune(c, ELWH_FP32_STEP, 2, nullptr)) != ELWH_OK)
+            return fail(st);
+    }
+    *out = c;
+    return ELWH_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 void elwh_default_opts(elwh_opts* o) {
@@ -514,142 +735,41 @@ elwh_status elwh_plan(const elwh_grid* grid, const double* rho, const double* la
 
 elwh_status elwh_create(const elwh_grid* grid, const double* rho, const double* lam, const double* mu,
                         double omega, const int bc[6], const elwh_opts* opts, elwh_ctx** out) {
-    if (!out) return ELWH_ERR_ARG;
-    *out = nullptr;
+    return create_impl(grid, nullptr, nullptr, rho, lam, mu, omega, bc, opts, out);
+}
+
+elwh_status elwh_create_mapped(const elwh_grid* grid, const double* x, const double* y, const double* rho,
+                               const double* lam, const double* mu, double omega, const int bc[4],
+                               const elwh_opts* opts, elwh_ctx** out) {
+    if (!x || !y) {
+        if (out) *out = nullptr;
+        g_create_err = "null coordinate array";
+        return ELWH_ERR_ARG;
+    }
+    return create_impl(grid, x, y, rho, lam, mu, omega, bc, opts, out);
+}
+
+elwh_status elwh_plan_mapped(const elwh_grid* grid, const double* x, const double* y, const double* rho,
+                             const double* lam, const double* mu, double omega, const int bc[4],
+                             const elwh_opts* opts, elwh_info* info) {
     elwh_opts o;
     elwh_default_opts(&o);
     if (opts) o = *opts;
-    g_create_err.clear();
-    elwh_status st = check_config(grid, bc, &o, &g_create_err);
-    if (st != ELWH_OK) return st;
-    if (!rho || !lam || !mu) {
-        g_create_err = "null material array";
+    if (!bc) {
+        g_create_err = "null bc";
         return ELWH_ERR_ARG;
     }
-    elwh_ctx* c = new (std::nothrow) elwh_ctx();
-    if (!c) return ELWH_ERR_ALLOC;
-    c->grid = *grid;
-    for (int f = 0; f < 6; ++f) c->bc[f] = f < 2 * grid->dim ? bc[f] : ELWH_BC_DIRICHLET;
-    c->omega = omega;
-    c->opts = o;
-    c->stream = reinterpret_cast<hipStream_t>(o.stream);
-    c->L = make_layout(grid);
-    c->st = make_stencil(grid);
-    c->mr = make_march(grid, c->bc);
-
-    auto fail = [&](elwh_status s) {
-        g_create_err = c->err.empty() ? g_create_err : c->err;
-        free_all(c);
-        delete c;
-        return s;
-    };
-    const int64_t nn = c->L.nodes_caller();
-    std::vector<double> hr(nn), hl(nn), hm(nn);
-    if (hipMemcpyAsync(hr.data(), rho, nn * sizeof(double), hipMemcpyDefault, c->stream) != hipSuccess ||
-        hipMemcpyAsync(hl.data(), lam, nn * sizeof(double), hipMemcpyDefault, c->stream) != hipSuccess ||
-        hipMemcpyAsync(hm.data(), mu, nn * sizeof(double), hipMemcpyDefault, c->stream) != hipSuccess ||
-        hipStreamSynchronize(c->stream) != hipSuccess) {
-        c->err = "copying the materials failed (device pointers expected)";
-        return fail(ELWH_ERR_HIP);
+    int bc6[6] = {bc[0], bc[1], bc[2], bc[3], ELWH_BC_DIRICHLET, ELWH_BC_DIRICHLET};
+    Plan p;
+    elwh_status st = make_plan_mapped(grid, x, y, rho, lam, mu, omega, bc6, &o, &p, nullptr, &g_create_err);
+    if (st != ELWH_OK) return st;
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->nt = p.nt;
+        info->dt = p.dt;
+        info->c = p.c;
+        info->lambda_bound = p.lambda_bound;
     }
-    st = make_plan(grid, hr.data(), hl.data(), hm.data(), omega, c->bc, &o, &c->plan, &c->err);
-    if (st != ELWH_OK) return fail(st);
-
-    // weights of the (K-period) trapezoid filter and the forcing factors
-    const int ntot = c->plan.nt * o.periods;
-    c->w.resize(ntot + 1);
-    c->cosn.resize(ntot + 1);
-    for (int n = 0; n <= ntot; ++n) {
-        const double cn = std::cos(2.0 * M_PI * n / c->plan.nt);
-        const double eta = (n == 0 || n == ntot) ? 0.5 : 1.0;
-        c->cosn[n] = cn;
-        c->w[n] = (2.0 / ntot) * eta * (cn - 0.25);
-    }
-
-    const Layout& L = c->L;
-    const size_t CS = (size_t)L.CS, FE = (size_t)L.field_elems();
-    if ((st = alloc_t(c, &c->ca, CS)) || (st = alloc_t(c, &c->cl, CS)) || (st = alloc_t(c, &c->cm, CS)) ||
-        (st = alloc_t(c, &c->mw, CS)) || (st = alloc_t(c, &c->s64[0], FE)) || (st = alloc_t(c, &c->s64[1], FE)) ||
-        (st = alloc_t(c, &c->acc_lo, FE)) || (st = alloc_t(c, &c->f64, FE)))
-        return fail(st);
-    for (auto& v : c->vec)
-        if ((st = alloc_t(c, &v, FE))) return fail(st);
-    if (L.dim == 2 && ((st = alloc_t(c, &c->s64[2], FE)) || (st = alloc_t(c, &c->s64[3], FE)))) return fail(st);
-    if (o.prec == ELWH_FP32_STEP) {
-        if ((st = alloc_t(c, &c->fa, CS)) || (st = alloc_t(c, &c->fl, CS)) || (st = alloc_t(c, &c->fm, CS)) ||
-            (st = alloc_t(c, &c->s32[0], FE)) || (st = alloc_t(c, &c->s32[1], FE)) ||
-            (st = alloc_t(c, &c->f32, FE)))
-            return fail(st);
-        if (L.dim == 2 && ((st = alloc_t(c, &c->s32[2], FE)) || (st = alloc_t(c, &c->s32[3], FE))))
-            return fail(st);
-    }
-    if ((st = alloc_t(c, &c->partials, 2 * (size_t)c->red_blocks)) || (st = alloc_t(c, &c->dscal, (size_t)S_NSLOT)))
-        return fail(st);
-    if (hipHostMalloc(reinterpret_cast<void**>(&c->hscal), S_NSLOT * sizeof(double), hipHostMallocDefault) !=
-        hipSuccess) {
-        c->err = "pinned host allocation failed";
-        return fail(ELWH_ERR_ALLOC);
-    }
-    std::memset(c->hscal, 0, S_NSLOT * sizeof(double));
-
-    // coefficient arrays in the padded layout, built on the host in FP64
-    {
-        std::vector<double> ha(CS, 0.0), hlam(CS, 0.0), hmu(CS, 0.0), hmw(CS, 0.0);
-        const double cdt2 = c->plan.c * c->plan.dt * c->plan.dt;
-        const int nzn = L.dim == 3 ? L.nz + 1 : 1;
-        for (int z = 0; z < nzn; ++z)
-            for (int y = 0; y <= L.ny; ++y)
-                for (int x = 0; x <= L.nx; ++x) {
-                    const int64_t src = ((int64_t)z * (L.ny + 1) + y) * (L.nx + 1) + x;
-                    const int64_t dst = (int64_t)z * L.PS + (int64_t)y * L.P + x;
-                    ha[dst] = cdt2 / hr[src];
-                    hlam[dst] = hl[src];
-                    hmu[dst] = hm[src];
-                    bool unknown = true;
-                    double wn = 1.0;
-                    const int coord[3] = {x, y, z};
-                    const int nmax[3] = {L.nx, L.ny, L.nz};
-                    for (int a = 0; a < L.dim; ++a) {
-                        if (coord[a] == 0) {
-                            if (c->bc[2 * a] == ELWH_BC_DIRICHLET) unknown = false; else wn *= 0.5;
-                        }
-                        if (coord[a] == nmax[a]) {
-                            if (c->bc[2 * a + 1] == ELWH_BC_DIRICHLET) unknown = false; else wn *= 0.5;
-                        }
-                    }
-                    hmw[dst] = unknown ? wn * hr[src] : 0.0;
-                }
-        if (hipMemcpyAsync(c->ca, ha.data(), CS * 8, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
-            hipMemcpyAsync(c->cl, hlam.data(), CS * 8, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
-            hipMemcpyAsync(c->cm, hmu.data(), CS * 8, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
-            hipMemcpyAsync(c->mw, hmw.data(), CS * 8, hipMemcpyHostToDevice, c->stream) != hipSuccess) {
-            c->err = "uploading coefficients failed";
-            return fail(ELWH_ERR_HIP);
-        }
-        if (o.prec == ELWH_FP32_STEP) {
-            launch_convert_f32(L, c->ca, c->fa, 1, c->stream);
-            launch_convert_f32(L, c->cl, c->fl, 1, c->stream);
-            launch_convert_f32(L, c->cm, c->fm, 1, c->stream);
-        }
-        if (hipStreamSynchronize(c->stream) != hipSuccess) {
-            c->err = "stream synchronisation failed in create";
-            return fail(ELWH_ERR_HIP);
-        }
-    }
-    // default tiling, then (optionally) the timed choice
-    if (c->L.dim == 2) {
-        c->tile64 = Tile{2, 8};
-        c->tile32 = Tile{4, 8};
-    } else {
-        c->tile64 = Tile{1, 16};
-        c->tile32 = Tile{1, 16};
-    }
-    if (o.autotune) {
-        if ((st = elwh_autotune(c, ELWH_FP64, 2, nullptr)) != ELWH_OK) return fail(st);
-        if (o.prec == ELWH_FP32_STEP && (st = elwh_autotune(c, ELWH_FP32_STEP, 2, nullptr)) != ELWH_OK)
-            return fail(st);
-    }
-    *out = c;
     return ELWH_OK;
 }
 
@@ -678,8 +798,7 @@ elwh_status elwh_apply_filter(elwh_ctx* c, const double* u0, const double* f, do
     const bool fp32 = c->opts.prec == ELWH_FP32_STEP;
     launch_pack(c->L, c->bc, u0, c->vec[VX], c->L.dim, c->stream);
     if (f) {
-        launch_pack(c->L, c->bc, f, c->f64, c->L.dim, c->stream);
-        if (fp32) launch_convert_f32(c->L, c->f64, c->f32, c->L.dim, c->stream);
+        pack_forcing(c, f, fp32);
     }
     run_filter(c, c->vec[VX], f != nullptr, false, fp32, c->vec[VQ]);
     launch_unpack(c->L, c->bc, c->vec[VQ], out, c->L.dim, c->stream);
@@ -710,7 +829,7 @@ elwh_status elwh_cg_begin(elwh_ctx* c, const double* f, const double* x0) {
         c->err = "the stepwise CG interface is FP64 only";
         return ELWH_ERR_ARG;
     }
-    launch_pack(c->L, c->bc, f, c->f64, c->L.dim, c->stream);
+    pack_forcing(c, f, false);
     compute_rhs(c);
     if (x0)
         launch_pack(c->L, c->bc, x0, c->vec[VX], c->L.dim, c->stream);
@@ -793,7 +912,7 @@ elwh_status elwh_solve(elwh_ctx* c, const double* f, const double* x0, double to
             if (tol > 0 && !(inf.relres <= tol)) st = ELWH_ERR_NOT_CONVERGED;
         }
     } else if (c->opts.prec == ELWH_FP64) {
-        launch_pack(c->L, c->bc, f, c->f64, c->L.dim, c->stream);
+        pack_forcing(c, f, false);
         compute_rhs(c);
         if (x0)
             launch_pack(c->L, c->bc, x0, c->vec[VX], c->L.dim, c->stream);
@@ -819,7 +938,7 @@ elwh_status elwh_solve(elwh_ctx* c, const double* f, const double* x0, double to
         // (p = r + beta p with beta = (r, r)_M / (r_k, r_k)_M of the last CG
         // step).  Restarting CG at every replacement instead discards the
         // Krylov space and costs two to three times the iterations here.
-        launch_pack(c->L, c->bc, f, c->f64, c->L.dim, c->stream);
+        pack_forcing(c, f, false);
         compute_rhs(c);
         if (x0)
             launch_pack(c->L, c->bc, x0, c->vec[VX], c->L.dim, c->stream);
@@ -941,7 +1060,8 @@ elwh_status elwh_profile_read(elwh_ctx* c, double* step_ms, int* nstep, double* 
 elwh_status elwh_set_tile(elwh_ctx* c, int prec, int vec, int rows) {
     if (!c) return ELWH_ERR_ARG;
     const bool fp32 = prec == ELWH_FP32_STEP;
-    const bool ok = c->L.dim == 2 ? tile_valid_2d(fp32, vec, rows) : tile_valid_3d(fp32, vec, rows);
+    const bool ok = c->mapped ? tile_valid_curv(fp32, vec, rows)
+                              : (c->L.dim == 2 ? tile_valid_2d(fp32, vec, rows) : tile_valid_3d(fp32, vec, rows));
     if (!ok) {
         c->err = "unsupported tile";
         return ELWH_ERR_ARG;
@@ -955,7 +1075,8 @@ elwh_status elwh_set_tile(elwh_ctx* c, int prec, int vec, int rows) {
 }  // extern "C"
 
 namespace {
-// dim, prec, variant (bit 0: compensated accumulator, bit 1: 2-D step pairs), nx, ny, nz
+// dim, prec, variant (bit 0: compensated accumulator, bit 1: 2-D step pairs,
+// bit 2: mapped grid), nx, ny, nz
 using TuneKey = std::tuple<int, int, int, int, int, int>;
 std::mutex g_tune_mu;
 std::map<TuneKey, Tile> g_tune;
@@ -1015,7 +1136,8 @@ elwh_status elwh_autotune(elwh_ctx* c, int prec, int reps, double* best_step_us)
         c->err = "FP32 tiling needs an FP32 context";
         return ELWH_ERR_ARG;
     }
-    const int comp = (fp32 && c->opts.compensated ? 1 : 0) | (c->L.dim == 2 && c->opts.fuse == 2 ? 2 : 0);
+    const int comp = (fp32 && c->opts.compensated ? 1 : 0) |
+                     (c->L.dim == 2 && !c->mapped && c->opts.fuse == 2 ? 2 : 0) | (c->mapped ? 4 : 0);
     const TuneKey key(c->L.dim, fp32 ? 1 : 0, comp, c->L.nx, c->L.ny, c->L.nz);
     Tile& dst = fp32 ? c->tile32 : c->tile64;
     {
@@ -1037,7 +1159,11 @@ elwh_status elwh_autotune(elwh_ctx* c, int prec, int reps, double* best_step_us)
         return ELWH_OK;
     }
     std::vector<Tile> cands;
-    if (c->L.dim == 2) {
+    if (c->mapped) {
+        for (int V : {1, 2})
+            for (int TY : {8, 16})
+                if (tile_valid_curv(fp32, V, TY)) cands.push_back(Tile{V, TY});
+    } else if (c->L.dim == 2) {
         for (int V : {1, 2, 4})
             for (int TY : {4, 8, 16})
                 if (tile_valid_2d(fp32, V, TY)) cands.push_back(Tile{V, TY});

@@ -75,6 +75,12 @@ __global__ void convert_kernel(const double* __restrict__ src, float* __restrict
         dst[e] = (float)src[e];
 }
 
+// dst[e] *= w[e mod cs] over ncomp components of cs elements each.
+__global__ void scale_field_kernel(double* __restrict__ dst, const double* __restrict__ w, int64_t cs, int64_t n) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        dst[e] *= w[e % cs];
+}
+
 PackArgs pack_args(const Layout& L, const int bc[6], int mask) {
     PackArgs a;
     a.dim = L.dim;
@@ -258,6 +264,11 @@ void launch_unpack(const Layout& L, const int bc[6], const double* src, double* 
 void launch_convert_f32(const Layout& L, const double* src, float* dst, int ncomp, hipStream_t s) {
     const int64_t n = L.CS * ncomp;
     hipLaunchKernelGGL(convert_kernel, dim3(grid_for(n)), dim3(256), 0, s, src, dst, n);
+}
+
+void launch_scale_field(const Layout& L, double* dst, const double* w, int ncomp, hipStream_t s) {
+    const int64_t n = L.CS * ncomp;
+    hipLaunchKernelGGL(scale_field_kernel, dim3(grid_for(n)), dim3(256), 0, s, dst, w, L.CS, n);
 }
 
 void launch_dot_M_partial(const elwh_ctx* c, const double* x, const double* y, hipStream_t s) {

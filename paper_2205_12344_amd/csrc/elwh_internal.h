@@ -126,6 +126,13 @@ struct elwh_ctx {
     double* mw = nullptr;          // M weights w_node * rho (0 at Dirichlet / padding)
     // FP32 copies (FP32 path)
     float *fa = nullptr, *fl = nullptr, *fm = nullptr;
+    // mapped 2-D grids: ca = c dt^2 / (rho J), cl = lambda / J, cm = mu / J,
+    // metric arrays cg = (J grad q, J grad r) (FP32 copies fg), and J itself
+    // (the forcing enters as J f)
+    bool mapped = false;
+    double* cg[4] = {nullptr, nullptr, nullptr, nullptr};
+    float* fg[4] = {nullptr, nullptr, nullptr, nullptr};
+    double* jac = nullptr;
 
     // FP64 state buffers (2 time levels), accumulator and its compensation
     // (four for 2-D: the step-pair kernel writes two new levels beside the two it reads)
@@ -168,6 +175,16 @@ struct elwh_ctx {
 namespace elwh {
 
 // ---- host plan (plan.cpp) --------------------------------------------------
+// Metric terms of a mapped 2-D grid (Sec. 4.1) in the caller's node layout:
+// J = x_q y_r - x_r y_q and g = (J grad q, J grad r) = (y_r, -x_r, -y_q, x_q),
+// from second-order differences of the node coordinates.
+struct MappedMetric {
+    std::vector<double> J, g[4];
+};
+elwh_status mapped_metric(int nq, int nr, const double* x, const double* y, MappedMetric* m, std::string* err);
+elwh_status make_plan_mapped(const elwh_grid* g, const double* x, const double* y, const double* rho,
+                             const double* lam, const double* mu, double omega, const int bc[6], const elwh_opts* o,
+                             Plan* out, MappedMetric* met, std::string* err);
 elwh_status make_plan(const elwh_grid* g, const double* rho, const double* lam, const double* mu,
                       double omega, const int bc[6], const elwh_opts* o, Plan* out, std::string* err);
 elwh_status check_config(const elwh_grid* g, const int bc[6], const elwh_opts* o, std::string* err);
@@ -184,6 +201,11 @@ bool tile_valid_2d(bool fp32, int V, int TY);
 // right-hand side in vec[4], on the context's stream (api.hip).
 elwh_status ctx_solve_cr(elwh_ctx* c, double tol, int maxit, int* iters, double* relres);
 bool tile_valid_3d(bool fp32, int V, int TZ);
+bool tile_valid_curv(bool fp32, int V, int TY);
+// One filter application on a mapped 2-D grid (kernels2d_curv.hip).
+void run_filter_curv2d(elwh_ctx* c, const double* x, bool with_force, bool amode, bool fp32, double* out);
+// dst[comp][node] *= w[node] over the padded layout (blas.hip).
+void launch_scale_field(const Layout& L, double* dst, const double* w, int ncomp, hipStream_t s);
 
 // K = 2..4 time steps per launch (kernels2d_multi.hip): reads u^n (u) and
 // u^{n-1} (uprev), writes u^{n+K-1} (outA) and u^{n+K} (outB), four distinct

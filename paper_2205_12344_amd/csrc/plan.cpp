@@ -1,5 +1,5 @@
 // Host-side set-up of libelwh: argument checks, padded layout, stencil
-// constants and the time-step plan.
+// constants, the metric terms of mapped grids and the time-step plan.
 //
 // Time-step rule (the paper fixes only a CFL number for explicit FD runs,
 // Sec. 5.1, and a whole number of steps per period for the implicit scheme,
@@ -259,7 +259,177 @@ double gershgorin(const Geo& g) {
     return *std::max_element(part.begin(), part.end());
 }
 
+// ---- mapped 2-D grids ---------------------------------------------------------
+
+// Second-order derivative of node values along one index direction (stride
+// st, n+1 nodes, spacing h): central inside, one-sided over three nodes at
+// both ends.
+double diff1(const double* f, int64_t o, int64_t st, int k, int n, double h) {
+    if (k == 0) return (-3.0 * f[o] + 4.0 * f[o + st] - f[o + 2 * st]) / (2.0 * h);
+    if (k == n) return (3.0 * f[o] - 4.0 * f[o - st] + f[o - 2 * st]) / (2.0 * h);
+    return (f[o + st] - f[o - st]) / (2.0 * h);
+}
+
+// The 2x2 blocks K^qq, K^qr, K^rr at one node (row-major [i][k]).
+void mapped_blocks(const MappedMetric& m, const double* lam, const double* mu, int64_t o, double qq[4],
+                   double qr[4], double rr[4]) {
+    const double l = lam[o] / m.J[o], u = mu[o] / m.J[o], lu = l + u;
+    const double A0 = m.g[0][o], A1 = m.g[1][o], B0 = m.g[2][o], B1 = m.g[3][o];
+    const double AA = A0 * A0 + A1 * A1, BB = B0 * B0 + B1 * B1, AB = A0 * B0 + A1 * B1;
+    qq[0] = lu * A0 * A0 + u * AA; qq[1] = lu * A0 * A1; qq[2] = qq[1]; qq[3] = lu * A1 * A1 + u * AA;
+    rr[0] = lu * B0 * B0 + u * BB; rr[1] = lu * B0 * B1; rr[2] = rr[1]; rr[3] = lu * B1 * B1 + u * BB;
+    qr[0] = lu * A0 * B0 + u * AB; qr[1] = l * A0 * B1 + u * B0 * A1;
+    qr[2] = l * A1 * B0 + u * B1 * A0; qr[3] = lu * A1 * B1 + u * AB;
+}
+
+// Gershgorin row sums of (rho J)^-1 L_h on a mapped grid (all four sides
+// Dirichlet): the stencil entries of each interior row, summed per
+// (neighbour, component) before taking absolute values.
+double gershgorin_mapped(int nq, int nr, const MappedMetric& m, const double* rho, const double* lam,
+                         const double* mu) {
+    const double hq = 1.0 / nq, hr = 1.0 / nr;
+    const double iqq = 1.0 / (hq * hq), irr = 1.0 / (hr * hr), iqr = 1.0 / (4.0 * hq * hr);
+    const int64_t sy = nq + 1;
+    unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    nth = std::min<unsigned>(nth, (unsigned)std::max(1, nr - 1));
+    std::vector<double> part(nth, 0.0);
+    auto work = [&](unsigned t) {
+        double best = 0.0;
+        for (int j = 1 + (int)t; j <= nr - 1; j += (int)nth)
+            for (int i = 1; i <= nq - 1; ++i) {
+                const int64_t p = j * sy + i;
+                double E[3][3][2][2];   // [dj][di][row comp][col comp]
+                std::memset(E, 0, sizeof(E));
+                double qq0[4], qr0[4], rr0[4];
+                mapped_blocks(m, lam, mu, p, qq0, qr0, rr0);
+                for (int s = -1; s <= 1; s += 2) {
+                    double qq[4], qr[4], rr[4];
+                    mapped_blocks(m, lam, mu, p + s, qq, qr, rr);   // (j, i+s)
+                    for (int c = 0; c < 2; ++c)
+                        for (int e = 0; e < 2; ++e) {
+                            const double kb = 0.5 * (qq0[2 * c + e] + qq[2 * c + e]) * iqq;
+                            E[1][1 + s][c][e] += kb;
+                            E[1][1][c][e] -= kb;
+                            // D0q(K^qr D0r U): K^qr at (j, i+s)
+                            E[2][1 + s][c][e] += s * qr[2 * c + e] * iqr;
+                            E[0][1 + s][c][e] -= s * qr[2 * c + e] * iqr;
+                        }
+                    mapped_blocks(m, lam, mu, p + s * sy, qq, qr, rr);   // (j+s, i)
+                    for (int c = 0; c < 2; ++c)
+                        for (int e = 0; e < 2; ++e) {
+                            const double kb = 0.5 * (rr0[2 * c + e] + rr[2 * c + e]) * irr;
+                            E[1 + s][1][c][e] += kb;
+                            E[1][1][c][e] -= kb;
+                            // D0r(K^rq D0q U): (K^qr)^T at (j+s, i)
+                            E[1 + s][2][c][e] += s * qr[2 * e + c] * iqr;
+                            E[1 + s][0][c][e] -= s * qr[2 * e + c] * iqr;
+                        }
+                }
+                for (int c = 0; c < 2; ++c) {
+                    double sum = 0.0;
+                    for (int dj = -1; dj <= 1; ++dj)
+                        for (int di = -1; di <= 1; ++di) {
+                            const int jj = j + dj, ii = i + di;
+                            if (jj < 1 || jj > nr - 1 || ii < 1 || ii > nq - 1) continue;
+                            sum += std::fabs(E[1 + dj][1 + di][c][0]) + std::fabs(E[1 + dj][1 + di][c][1]);
+                        }
+                    best = std::max(best, sum / (rho[p] * m.J[p]));
+                }
+            }
+        part[t] = best;
+    };
+    std::vector<std::thread> th;
+    for (unsigned t = 1; t < nth; ++t) th.emplace_back(work, t);
+    work(0);
+    for (auto& x : th) x.join();
+    return *std::max_element(part.begin(), part.end());
+}
+
+// N_T, dt and c from the spectral bound G (shared by both grid kinds).
+elwh_status plan_from_bound(double G, double omega, const elwh_opts* o, Plan* out, std::string* err) {
+    const double T = 2.0 * M_PI / omega;
+    int nt;
+    if (o && o->nt > 0) {
+        nt = o->nt;
+    } else {
+        const double cfl = o ? o->cfl : 0.8;
+        const double dt_star = cfl * 2.0 / std::sqrt(G);
+        const double q = std::ceil(T / dt_star);
+        if (!(q < 1e8)) { *err = "too many steps per period"; return ELWH_ERR_ARG; }
+        nt = std::max(3, (int)q);
+    }
+    out->nt = nt;
+    out->T = T;
+    out->dt = T / nt;
+    out->lambda_bound = G;
+    const bool corrected = !o || o->scheme == ELWH_SCHEME_CORRECTED;
+    const double x = 0.5 * omega * out->dt;
+    out->c = corrected ? (std::sin(x) / x) * (std::sin(x) / x) : 1.0;
+    return ELWH_OK;
+}
+
+bool positive_materials(int64_t nn, const double* rho, const double* lam, const double* mu) {
+    for (int64_t i = 0; i < nn; ++i)
+        if (!(rho[i] > 0) || !(lam[i] > 0) || !(mu[i] > 0) || !std::isfinite(rho[i]) || !std::isfinite(lam[i]) ||
+            !std::isfinite(mu[i]))
+            return false;
+    return true;
+}
+
 }  // namespace
+
+elwh_status mapped_metric(int nq, int nr, const double* x, const double* y, MappedMetric* m, std::string* err) {
+    const int64_t sy = nq + 1, nn = sy * (nr + 1);
+    for (int64_t i = 0; i < nn; ++i)
+        if (!std::isfinite(x[i]) || !std::isfinite(y[i])) {
+            *err = "node coordinates must be finite";
+            return ELWH_ERR_ARG;
+        }
+    const double hq = 1.0 / nq, hr = 1.0 / nr;
+    m->J.assign(nn, 0.0);
+    for (auto& g : m->g) g.assign(nn, 0.0);
+    for (int j = 0; j <= nr; ++j)
+        for (int i = 0; i <= nq; ++i) {
+            const int64_t o = j * sy + i;
+            const double xq = diff1(x, o, 1, i, nq, hq), yq = diff1(y, o, 1, i, nq, hq);
+            const double xr = diff1(x, o, sy, j, nr, hr), yr = diff1(y, o, sy, j, nr, hr);
+            const double J = xq * yr - xr * yq;
+            if (!(J > 0)) {
+                *err = "the map must be one-to-one and orientation preserving (J > 0 at every node)";
+                return ELWH_ERR_ARG;
+            }
+            m->J[o] = J;
+            m->g[0][o] = yr;
+            m->g[1][o] = -xr;
+            m->g[2][o] = -yq;
+            m->g[3][o] = xq;
+        }
+    return ELWH_OK;
+}
+
+elwh_status make_plan_mapped(const elwh_grid* g, const double* x, const double* y, const double* rho,
+                             const double* lam, const double* mu, double omega, const int bc[6], const elwh_opts* o,
+                             Plan* out, MappedMetric* met, std::string* err) {
+    if (!g || !bc) { *err = "null grid or bc"; return ELWH_ERR_ARG; }
+    if (g->dim != 2) { *err = "mapped grids are two-dimensional"; return ELWH_ERR_ARG; }
+    for (int f = 0; f < 4; ++f)
+        if (bc[f] != ELWH_BC_DIRICHLET) { *err = "mapped grids support Dirichlet sides only"; return ELWH_ERR_ARG; }
+    elwh_grid unit = *g;
+    unit.len[0] = unit.len[1] = 1.0;
+    elwh_status st = check_config(&unit, bc, o, err);
+    if (st != ELWH_OK) return st;
+    if (!x || !y || !rho || !lam || !mu) { *err = "null coordinate or material array"; return ELWH_ERR_ARG; }
+    if (!(omega > 0) || !std::isfinite(omega)) { *err = "omega must be positive and finite"; return ELWH_ERR_ARG; }
+    const int nq = g->n[0], nr = g->n[1];
+    if (!positive_materials((int64_t)(nq + 1) * (nr + 1), rho, lam, mu)) {
+        *err = "materials must be positive and finite";
+        return ELWH_ERR_ARG;
+    }
+    MappedMetric local;
+    MappedMetric* m = met ? met : &local;
+    if ((st = mapped_metric(nq, nr, x, y, m, err)) != ELWH_OK) return st;
+    return plan_from_bound(gershgorin_mapped(nq, nr, *m, rho, lam, mu), omega, o, out, err);
+}
 
 elwh_status check_config(const elwh_grid* g, const int bc[6], const elwh_opts* o, std::string* err) {
     if (!g || !bc) { *err = "null grid or bc"; return ELWH_ERR_ARG; }
@@ -312,33 +482,11 @@ elwh_status make_plan(const elwh_grid* g, const double* rho, const double* lam, 
     geo.lam = lam;
     geo.mu = mu;
     const int64_t nn = geo.sz * (g->dim == 3 ? g->n[2] + 1 : 1);
-    for (int64_t i = 0; i < nn; ++i) {
-        if (!(rho[i] > 0) || !(lam[i] > 0) || !(mu[i] > 0) || !std::isfinite(rho[i]) ||
-            !std::isfinite(lam[i]) || !std::isfinite(mu[i])) {
-            *err = "materials must be positive and finite";
-            return ELWH_ERR_ARG;
-        }
+    if (!positive_materials(nn, rho, lam, mu)) {
+        *err = "materials must be positive and finite";
+        return ELWH_ERR_ARG;
     }
-    const double G = gershgorin(geo);
-    const double T = 2.0 * M_PI / omega;
-    int nt;
-    if (o && o->nt > 0) {
-        nt = o->nt;
-    } else {
-        const double cfl = o ? o->cfl : 0.8;
-        const double dt_star = cfl * 2.0 / std::sqrt(G);
-        const double q = std::ceil(T / dt_star);
-        if (!(q < 1e8)) { *err = "too many steps per period"; return ELWH_ERR_ARG; }
-        nt = std::max(3, (int)q);
-    }
-    out->nt = nt;
-    out->T = T;
-    out->dt = T / nt;
-    out->lambda_bound = G;
-    const bool corrected = !o || o->scheme == ELWH_SCHEME_CORRECTED;
-    const double x = 0.5 * omega * out->dt;
-    out->c = corrected ? (std::sin(x) / x) * (std::sin(x) / x) : 1.0;
-    return ELWH_OK;
+    return plan_from_bound(gershgorin(geo), omega, o, out, err);
 }
 
 Layout make_layout(const elwh_grid* g) {

@@ -24,7 +24,7 @@ KRYLOV_CG, KRYLOV_GMRES, KRYLOV_CR = 0, 1, 2
 SCHEME_CORRECTED, SCHEME_STANDARD = 0, 1
 
 EXPORTED = [
-    "elwh_default_opts", "elwh_plan", "elwh_create", "elwh_destroy", "elwh_query", "elwh_last_error",
+    "elwh_default_opts", "elwh_plan", "elwh_create", "elwh_plan_mapped", "elwh_create_mapped", "elwh_destroy", "elwh_query", "elwh_last_error",
     "elwh_apply_filter", "elwh_apply_A", "elwh_solve", "elwh_cg_begin", "elwh_cg_iterate",
     "elwh_cg_result", "elwh_dot_M", "elwh_profile_enable", "elwh_profile_read",
     "elwh_set_tile", "elwh_get_tile", "elwh_autotune",
@@ -77,6 +77,10 @@ def _load():
                               ctypes.POINTER(Info)]
     lib.elwh_create.argtypes = [ctypes.POINTER(Grid), P, P, P, D, ctypes.POINTER(I), ctypes.POINTER(Opts),
                                 ctypes.POINTER(P)]
+    lib.elwh_create_mapped.argtypes = [ctypes.POINTER(Grid), P, P, P, P, P, D, ctypes.POINTER(I),
+                                       ctypes.POINTER(Opts), ctypes.POINTER(P)]
+    lib.elwh_plan_mapped.argtypes = [ctypes.POINTER(Grid), P, P, P, P, P, D, ctypes.POINTER(I),
+                                     ctypes.POINTER(Opts), ctypes.POINTER(Info)]
     lib.elwh_destroy.argtypes = [P]
     lib.elwh_destroy.restype = None
     lib.elwh_query.argtypes = [P, ctypes.POINTER(Info)]
@@ -180,6 +184,23 @@ def plan(dim, n, rho, lam, mu, omega, bc, length=None, **opts):
     info = Info()
     st = lib.elwh_plan(ctypes.byref(g), r.ctypes.data, l.ctypes.data, m.ctypes.data, float(omega),
                        _bc_array(bc), ctypes.byref(o), ctypes.byref(info))
+    if st != OK:
+        raise ElwhError(st, lib.elwh_last_error(None).decode())
+    return {"nt": info.nt, "dt": info.dt, "c": info.c, "lambda_bound": info.lambda_bound}
+
+
+def plan_mapped(x, y, rho, lam, mu, omega, **opts):
+    """Time-step plan of a mapped 2-D grid on the host (no GPU); x, y, rho,
+    lam, mu node arrays of shape (n_r + 1, n_q + 1)."""
+    xs, ys = _host(x), _host(y)
+    nr, nq = xs.shape[0] - 1, xs.shape[1] - 1
+    g = make_grid(2, (nq, nr))
+    r, l, m = _host(rho), _host(lam), _host(mu)
+    o = default_opts(**opts)
+    info = Info()
+    st = lib.elwh_plan_mapped(ctypes.byref(g), xs.ctypes.data, ys.ctypes.data, r.ctypes.data, l.ctypes.data,
+                              m.ctypes.data, float(omega), _bc_array((0, 0, 0, 0)), ctypes.byref(o),
+                              ctypes.byref(info))
     if st != OK:
         raise ElwhError(st, lib.elwh_last_error(None).decode())
     return {"nt": info.nt, "dt": info.dt, "c": info.c, "lambda_bound": info.lambda_bound}
@@ -310,6 +331,40 @@ class Context:
         info = Info()
         self._check(lib.elwh_cg_result(self._h, v.data_ptr(), ctypes.byref(info)))
         return v, info.as_dict()
+
+
+class MappedContext(Context):
+    """One problem on a mapped 2-D grid (wraps elwh_create_mapped): x, y are
+    the node coordinates, shape (n_r + 1, n_q + 1), q along the last axis;
+    all four sides Dirichlet.  Every Context method applies."""
+
+    def __init__(self, x, y, rho, lam, mu, omega, stream=None, **opts):
+        if not torch.cuda.is_available():
+            raise RuntimeError("libelwh needs a GPU")
+        xs = _dev(x, "x")
+        ys = _dev(y, "y")
+        if xs.dim() != 2 or tuple(ys.shape) != tuple(xs.shape):
+            raise ValueError("x and y must be node arrays of one 2-D shape")
+        nr, nq = xs.shape[0] - 1, xs.shape[1] - 1
+        self.dim = 2
+        self.n = (nq, nr)
+        self.node_shape = (nr + 1, nq + 1)
+        self.field_shape = (2,) + self.node_shape
+        self.stream = torch.cuda.current_stream() if stream is None else stream
+        g = make_grid(2, (nq, nr))
+        o = default_opts(stream=self.stream.cuda_stream, **opts)
+        r, l, m = _dev(rho, "rho"), _dev(lam, "lam"), _dev(mu, "mu")
+        for t in (r, l, m):
+            if tuple(t.shape) != self.node_shape:
+                raise ValueError(f"material shape {tuple(t.shape)} != {self.node_shape}")
+        h = ctypes.c_void_p()
+        st = lib.elwh_create_mapped(ctypes.byref(g), xs.data_ptr(), ys.data_ptr(), r.data_ptr(), l.data_ptr(),
+                                    m.data_ptr(), float(omega), _bc_array((0, 0, 0, 0)), ctypes.byref(o),
+                                    ctypes.byref(h))
+        if st != OK:
+            raise ElwhError(st, lib.elwh_last_error(None).decode())
+        self._h = h
+        self.opts = o
 
 
 def context_from_case(case, **opts):

@@ -307,3 +307,27 @@ def media_mapped(x, y, seed):
     mu = np.exp(0.2 * gs[1])
     lam = mu * np.clip(2.0 * np.exp(0.2 * gs[2]), 1.0, 3.0)
     return rho, lam, mu
+
+
+def sector_case(k, n_an=1, seed=None, arc=5.0):
+    """The iterations-vs-frequency setup of Sec. 5.4 on an annular sector:
+    omega = k + sqrt(2)/10, n_q = int(4 omega + 1) radial and
+    n_r = int(4 arc omega + 1) arc-wise cells (about 20 points per shear
+    wavelength), a discrete point source in u of amplitude omega^2 (divided
+    by the cell's polar area) at node i = j = (n_q + 1) // 2.  Media:
+    lambda = 2, mu = rho = 1 as in the paper, or (seed given) the random
+    log-normal media above.  Returns (x, y, rho, lam, mu, omega, f)."""
+    w = k + math.sqrt(2) / 10
+    nq, nr = int(4 * w + 1), int(4 * arc * w + 1)
+    x, y = sector_grid(nq, nr, n_an, arc)
+    if seed is None:
+        rho, lam, mu = np.ones(x.shape), 2.0 * np.ones(x.shape), np.ones(x.shape)
+    else:
+        rho, lam, mu = media_mapped(x, y, seed)
+    r_out = 2.0 * arc / (n_an * math.pi)
+    r_in = r_out - 1.0
+    i = (nq + 1) // 2
+    area = math.hypot(x[i, i], y[i, i]) * ((r_out - r_in) / nq) * (n_an * 0.5 * math.pi / nr)
+    f = np.zeros((2,) + x.shape)
+    f[0, i, i] = w * w / area
+    return x, y, rho, lam, mu, w, f

@@ -113,3 +113,47 @@ def test_plan_nt_override_and_standard(elwh):
     ok = np.ones((9, 9))
     p = elwh.plan(2, (8, 8), ok, ok, ok, 3.0, (0, 0, 0, 0), nt=17, scheme=1)
     assert p["nt"] == 17 and p["c"] == 1.0
+
+
+MAPPED_CASES = [("quarter", 9, 40), ("half", 7, 33), ("warped", 13, 11), ("rectangle", 6, 21)]
+
+
+@pytest.mark.parametrize("kind,nq,nr", MAPPED_CASES)
+def test_plan_mapped_matches_oracle(elwh, kind, nq, nr):
+    from oracle.curvilinear import MappedOperator
+    from paper_2205_12344_amd import inputs
+    if kind == "quarter":
+        x, y = inputs.sector_grid(nq, nr, 1)
+    elif kind == "half":
+        x, y = inputs.sector_grid(nq, nr, 2)
+    elif kind == "warped":
+        x, y = inputs.warped_grid(nq, nr, seed=nq)
+    else:
+        x, y = inputs.rectangle_grid(nq, nr, 1.0, 5.0)
+    rho, lam, mu = inputs.media_mapped(x, y, seed=nq + nr)
+    om = 5.3
+    G = MappedOperator(x, y, rho, lam, mu).gershgorin()
+    p = elwh.plan_mapped(x, y, rho, lam, mu, om)
+    assert p["lambda_bound"] == pytest.approx(G, rel=1e-13)
+    assert p["nt"] == steps_per_period(G, om)
+
+
+def test_plan_mapped_rejects_bad_input(elwh):
+    from paper_2205_12344_amd import inputs
+    x, y = inputs.sector_grid(6, 20, 1)
+    ok = np.ones(x.shape)
+    with pytest.raises(elwh.ElwhError, match="J > 0"):
+        elwh.plan_mapped(x[:, ::-1], y[:, ::-1], ok, ok, ok, 3.0)      # left-handed
+    xb = x.copy()
+    xb[3, 3] = np.inf
+    with pytest.raises(elwh.ElwhError, match="finite"):
+        elwh.plan_mapped(xb, y, ok, ok, ok, 3.0)
+    with pytest.raises(elwh.ElwhError, match="ERR_ARG"):
+        elwh.plan_mapped(x, y, ok, 0 * ok, ok, 3.0)
+    g = elwh.make_grid(2, (6, 20))
+    o = elwh.default_opts()
+    info = elwh.Info()
+    st = elwh.lib.elwh_plan_mapped(ctypes.byref(g), x.ctypes.data, y.ctypes.data, ok.ctypes.data, ok.ctypes.data,
+                                   ok.ctypes.data, 3.0, elwh._bc_array((0, 0, 0, 1)), ctypes.byref(o),
+                                   ctypes.byref(info))
+    assert st == elwh.ERR_ARG and b"Dirichlet" in elwh.lib.elwh_last_error(None)
