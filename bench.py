@@ -11,10 +11,11 @@ accumulation.
 
 The JSON line also carries the roofline of the fused step-pair kernel
 (HIP-event durations of the step launches over a profiled repeat of the
-timed steps), the FP32-stepping and single-step variants, and the CPU
-oracle's rate on a bounded sample.
+timed steps), the FP32-stepping and single-step variants, the step kernel
+of mapped (curvilinear) grids on an annular sector, and the CPU oracle's
+rate on a bounded sample.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--all]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--all] [--mapped-only]
 """
 
 import argparse
@@ -51,6 +52,15 @@ BYTES_PER_LUP = {
     (3, "f64", 1): 144, (3, "f32c", 1): 144, (3, "f32", 1): 96,
 }
 BYTES_PER_MULTI_LAUNCH = {"f64": 120, "f32c": 108, "f32": 76}
+# Mapped (curvilinear) 2-D grids, single-step kernel: the three coefficient
+# arrays become seven (a = c dt^2/(rho J), lambda/J, mu/J and the metric
+# vectors J grad q, J grad r):
+#   FP64: state 3x2x8 + 7x8 + acc 2x2x8 = 136; FP32 compensated:
+#   24 + 28 + 64 = 116; FP32 plain accumulator: 24 + 28 + 32 = 84
+BYTES_PER_LUP_MAPPED = {"f64": 136, "f32c": 116, "f32": 84}
+MAPPED_WORKLOAD = ("quarter annulus of the iterations-vs-frequency experiment at omega = 200 + sqrt(2)/10 "
+                   "(801 x 4003 cells, 20 points per shear wavelength at c_s = 1), random log-normal medium "
+                   "(seed 14), Dirichlet sides")
 
 
 def step_launches(nt, fuse):
@@ -145,6 +155,27 @@ def kernel_rate(ctx, napply):
     return prof
 
 
+def mapped_rates(elwh, inputs, napply=3):
+    """Step-kernel rate on the mapped workload (FP64 and FP32 compensated)."""
+    x, y, rho, lam, mu, om, _ = inputs.sector_case(200, 1, seed=14)
+    nodes = (x.shape[0] - 2) * (x.shape[1] - 2)
+    out = {}
+    for tag, kw in (("f64", {}), ("f32c", {"prec": elwh.FP32_STEP, "compensated": 1})):
+        ctx = elwh.MappedContext(x, y, rho, lam, mu, om, **kw)
+        p = kernel_rate(ctx, napply)
+        avg_s = p["step_ms"] * 1e-3 / max(p["nstep"], 1)
+        bb = BYTES_PER_LUP_MAPPED[tag]
+        t = ctx.get_tile(elwh.FP64 if tag == "f64" else elwh.FP32_STEP)
+        out[tag] = {"workload": MAPPED_WORKLOAD, "cells": [x.shape[1] - 1, x.shape[0] - 1], "omega": om,
+                    "nt": ctx.info()["nt"], "tile": list(t), "kernel": "curv2d_kernel",
+                    "step_kernel_us": round(1e6 * avg_s, 3), "glup_s_kernel": round(nodes / avg_s / 1e9, 3),
+                    "bytes_per_lup": bb, "achieved_GBs": round(bb * nodes / avg_s / 1e9, 1),
+                    "frac": round(bb * nodes / avg_s / 1e9 / HBM_PEAK_GBS, 4)}
+        log(f"mapped {tag}: {out[tag]}")
+        ctx.close()
+    return out
+
+
 def cpu_baseline(case, budget_s=12.0):
     """The oracle as it stands, timed on the host: A_h applications on the
     benchmark workload until the budget is spent (single-threaded sparse
@@ -216,10 +247,11 @@ def time_to_tol(elwh, nprob=24, first_seed=4096):
     return r
 
 
-def counters_pass(tile):
+def counters_pass(tile, mapped=False):
     """Dispatches for the HBM-traffic counters: a plain copy of 256 MiB (the
     scale reference: 262144 KiB read, 262144 KiB written) and three A_h
-    applications of the benchmark workload with a fixed tiling."""
+    applications of the benchmark workload (or of the mapped workload) with
+    a fixed FP64 tiling."""
     import torch
     from paper_2205_12344_amd import elwh, inputs
     v, ty = (int(t) for t in tile.split(","))
@@ -227,8 +259,11 @@ def counters_pass(tile):
     y = torch.empty_like(x)
     y.copy_(x)
     torch.cuda.synchronize()
-    case = inputs.config2()
-    ctx = elwh.context_from_case(case, autotune=0)
+    if mapped:
+        xs, ys, rho, lam, mu, om, _ = inputs.sector_case(200, 1, seed=14)
+        ctx = elwh.MappedContext(xs, ys, rho, lam, mu, om, autotune=0)
+    else:
+        ctx = elwh.context_from_case(inputs.config2(), autotune=0)
     ctx.set_tile(elwh.FP64, v, ty)
     z = torch.zeros(ctx.field_shape, dtype=torch.float64, device="cuda")
     for _ in range(3):
@@ -250,6 +285,10 @@ def main():
     ap.add_argument("--counters", default=None, metavar="V,TY",
                     help="counter-collection pass for rocprofv3 --pmc: a 256 MiB calibration copy, then 3 "
                          "A_h applications of the benchmark workload with the fixed FP64 tiling V,TY")
+    ap.add_argument("--counters-mapped", default=None, metavar="V,TY",
+                    help="the same counter pass on the mapped workload (curvilinear step kernel)")
+    ap.add_argument("--mapped-only", action="store_true",
+                    help="only the mapped-grid step-kernel measurement (for kernel traces and counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the hot path runs on a single MI355X "
@@ -262,6 +301,12 @@ def main():
     torch.cuda.set_device(0)
     if args.counters:
         counters_pass(args.counters)
+        return
+    if args.counters_mapped:
+        counters_pass(args.counters_mapped, mapped=True)
+        return
+    if args.mapped_only:
+        print(json.dumps(mapped_rates(elwh, inputs)))
         return
     t0 = time.perf_counter()
     case = inputs.config2()
@@ -318,6 +363,9 @@ def main():
                          "frac": round(gbs / HBM_PEAK_GBS, 4)}
         log(f"{tag}: {variants[tag]}")
         c2.close()
+
+    for tag, v in mapped_rates(elwh, inputs).items():
+        variants["mapped_" + tag] = v
 
     if args.all:
         c3 = inputs.config3()

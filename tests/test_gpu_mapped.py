@@ -175,7 +175,7 @@ def test_mapped_cr_point_source_matches_oracle(E, geometry):
 
 def test_mapped_full_size_fixed_point(E):
     """The benchmark's mapped workload (quarter annulus of Sec. 5.4 at
-    omega = 200 + sqrt(2)/10: 801 x 4001 cells, random media) in the launch
+    omega = 200 + sqrt(2)/10: 801 x 4003 cells, random media) in the launch
     configuration it times: with the forcing of a discrete manufactured v*
     (f = omega^2 rho v* + J^-1 L_h v*, from the oracle's stencil form) the
     filter returns v* (a property of the exact operator at any size), in FP64
