@@ -338,7 +338,14 @@ def main():
                 "kernel": f"multi2d_kernel<double,V={tv},TY={tr},K={fuse},FORCE=0,COMP=0>",
                 "bytes_per_lup": BYTES_PER_MULTI_LAUNCH["f64"] / fuse, "lup_per_launch": fuse * nodes,
                 "bytes_per_launch": BYTES_PER_MULTI_LAUNCH["f64"] * nodes,
-                "avg_launch_us": round(1e3 * step_avg_ms, 3)}
+                "avg_launch_us": round(1e3 * step_avg_ms, 3),
+                # effective fraction: lattice updates per second times the
+                # single-step algorithmic bytes (104 B/LUP), the measure under
+                # which temporal blocking can exceed 1 (the K-step kernel
+                # needs 120/K B/LUP, frac above)
+                "effective_frac_kernel": round(fuse * nodes / (step_avg_ms * 1e-3) * BYTES_PER_LUP[(2, "f64", 1)]
+                                               / (HBM_PEAK_GBS * 1e9), 4),
+                "effective_frac_end_to_end": round(value * BYTES_PER_LUP[(2, "f64", 1)] / (HBM_PEAK_GBS * 1e9), 4)}
     ctx.close()
 
     variants = {}

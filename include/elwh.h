@@ -183,6 +183,37 @@ elwh_status elwh_plan_mapped(const elwh_grid* grid, const double* x, const doubl
                              double omega, const int bc[4], const elwh_opts* opts,
                              elwh_info* info);
 
+/*
+ * Accuracy of the discrete filter (App. B), host only, no GPU use.  For N_T
+ * steps per period and K = periods, the trapezoid filter multiplies a mode
+ * cos(n theta) of the time stepping by beta_h(theta) = sum_n w_n cos(n theta)
+ * (w_n the weights of elwh_apply_filter); A_h = I - S_h has the eigenvalue
+ * 1 - beta_h, which is negative where beta_h > 1.  With the rescaled
+ * frequency r = theta / (omega dt) (r = 1 at resonance, where beta_h = 1):
+ *   r_star     the leftmost r < 1 with beta_h(r) = 1 (bisection); beta_h >= 1
+ *              on [r_star, 1]; r_star = 1 when double precision resolves no
+ *              such band
+ *   gap        1 - r_star (App. B bounds it by 0.022 dt^2 in the time unit
+ *              T = 2 pi, i.e. dt = 2 pi / N_T, for one period)
+ *   beta_max, r_max   the largest beta_h on [r_star, 1] and where it occurs
+ *   lambda_lo, lambda_hi   the band of spatial frequencies lambda (modes
+ *              with -L_h phi = lambda^2 M phi) that land in [r_star, 1]:
+ *              sin(theta/2) = sin(omega dt/2) lambda / omega for the
+ *              corrected scheme (lambda_hi = omega), sin(theta/2) =
+ *              lambda dt / 2 for the standard one (scheme: ELWH_SCHEME_*).
+ * An eigenvalue lambda_j of the medium inside [lambda_lo, lambda_hi] makes
+ * A_h indefinite: CG may break down there and the conjugate residual method
+ * (opts.krylov, or the cr_fallback of elwh_solve) is the remedy of the
+ * remark in Sec. 4.4.  Errors: ELWH_ERR_ARG (nt < 3, periods outside
+ * [1, 1000], omega <= 0, unknown scheme).
+ */
+typedef struct {
+    double r_star, gap, beta_max, r_max, lambda_lo, lambda_hi;
+} elwh_filter_diag;
+
+elwh_status elwh_filter_diagnostics(int nt, int periods, double omega, int scheme,
+                                    elwh_filter_diag* out);
+
 /* Release every device and host resource of ctx (NULL is a no-op). */
 void elwh_destroy(elwh_ctx* ctx);
 

@@ -749,6 +749,10 @@ elwh_status elwh_create_mapped(const elwh_grid* grid, const double* x, const dou
     return create_impl(grid, x, y, rho, lam, mu, omega, bc, opts, out);
 }
 
+elwh_status elwh_filter_diagnostics(int nt, int periods, double omega, int scheme, elwh_filter_diag* out) {
+    return filter_diagnostics(nt, periods, omega, scheme, out, &g_create_err);
+}
+
 elwh_status elwh_plan_mapped(const elwh_grid* grid, const double* x, const double* y, const double* rho,
                              const double* lam, const double* mu, double omega, const int bc[4],
                              const elwh_opts* opts, elwh_info* info) {

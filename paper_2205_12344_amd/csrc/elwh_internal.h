@@ -185,6 +185,8 @@ elwh_status mapped_metric(int nq, int nr, const double* x, const double* y, Mapp
 elwh_status make_plan_mapped(const elwh_grid* g, const double* x, const double* y, const double* rho,
                              const double* lam, const double* mu, double omega, const int bc[6], const elwh_opts* o,
                              Plan* out, MappedMetric* met, std::string* err);
+elwh_status filter_diagnostics(int nt, int periods, double omega, int scheme, elwh_filter_diag* out,
+                               std::string* err);
 elwh_status make_plan(const elwh_grid* g, const double* rho, const double* lam, const double* mu,
                       double omega, const int bc[6], const elwh_opts* o, Plan* out, std::string* err);
 elwh_status check_config(const elwh_grid* g, const int bc[6], const elwh_opts* o, std::string* err);

@@ -378,6 +378,86 @@ bool positive_materials(int64_t nn, const double* rho, const double* lam, const 
 
 }  // namespace
 
+// ---- discrete filter transfer function (App. B) --------------------------------
+
+namespace {
+
+// sum_{n=0}^{M} eta_n cos(n x), eta = 1/2 at both ends: sin(M x) / (2 tan(x / 2)),
+// M at x = 0.
+double trapezoid_cos_sum(int M, double x) {
+    const double s = std::sin(0.5 * x);
+    if (s == 0.0) return (double)M;
+    return std::sin(M * x) * std::cos(0.5 * x) / (2.0 * s);
+}
+
+// beta_h at the rescaled frequency r (a mode cos(n theta), theta = r * 2 pi / N_T):
+// sum_n w_n cos(n theta) with w_n = (2 / M) eta_n (cos(n phi) - 1/4), phi = 2 pi / N_T,
+// M = K N_T, written with cos a cos b = (cos(a - b) + cos(a + b)) / 2.
+double beta_rescaled(int nt, int periods, double r) {
+    const int M = nt * periods;
+    const double phi = 2.0 * M_PI / nt, th = r * phi;
+    return (2.0 / M) * (0.5 * trapezoid_cos_sum(M, th - phi) + 0.5 * trapezoid_cos_sum(M, th + phi) -
+                        0.25 * trapezoid_cos_sum(M, th));
+}
+
+}  // namespace
+
+elwh_status filter_diagnostics(int nt, int periods, double omega, int scheme, elwh_filter_diag* out,
+                               std::string* err) {
+    if (!out) { *err = "null output"; return ELWH_ERR_ARG; }
+    if (nt < 3) { *err = "nt must be >= 3"; return ELWH_ERR_ARG; }
+    if (periods < 1 || periods > 1000) { *err = "periods must be in [1, 1000]"; return ELWH_ERR_ARG; }
+    if (!(omega > 0) || !std::isfinite(omega)) { *err = "omega must be positive and finite"; return ELWH_ERR_ARG; }
+    if (scheme != ELWH_SCHEME_CORRECTED && scheme != ELWH_SCHEME_STANDARD) { *err = "bad scheme"; return ELWH_ERR_ARG; }
+    auto above = [&](double r) { return beta_rescaled(nt, periods, r) >= 1.0; };
+    // increasing r: a linear scan of [1/2, 1 - 1e-3] and a logarithmic one of
+    // 1 - 10^-3 .. 1 - 10^-15 (the band shrinks like dt^2); r = 1 itself, where
+    // beta_h = 1 exactly, is left out.  The first sample at or above one and
+    // the one before it bracket r*.
+    std::vector<double> rs;
+    for (int i = 0; i <= 20000; ++i) rs.push_back(0.5 + (0.5 - 1e-3) * i / 20000.0);
+    for (int i = 1; i <= 1200; ++i) rs.push_back(1.0 - std::pow(10.0, -3.0 - 12.0 * i / 1200.0));
+    double lo = -1, hi = -1;
+    for (size_t i = 1; i < rs.size(); ++i)
+        if (above(rs[i])) {
+            if (above(rs[i - 1])) { *err = "transfer function at or above one below r = 1/2"; return ELWH_ERR_ARG; }
+            lo = rs[i - 1];
+            hi = rs[i];
+            break;
+        }
+    if (hi < 0) {
+        lo = hi = 1.0;   // no band above one that double precision resolves
+    } else {
+        for (int it = 0; it < 200 && hi - lo > 1e-16; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            (above(mid) ? hi : lo) = mid;
+        }
+    }
+    out->r_star = hi;
+    out->gap = 1.0 - hi;
+    // maximum of beta_h over [r*, 1]: golden-section search (one peak)
+    double a = hi, b = 1.0;
+    const double g = 0.5 * (std::sqrt(5.0) - 1.0);
+    for (int it = 0; it < 200 && b - a > 1e-16; ++it) {
+        const double c = b - g * (b - a), d = a + g * (b - a);
+        if (beta_rescaled(nt, periods, c) >= beta_rescaled(nt, periods, d)) b = d; else a = c;
+    }
+    out->r_max = 0.5 * (a + b);
+    out->beta_max = std::max(1.0, beta_rescaled(nt, periods, out->r_max));
+    // spatial frequencies whose modes land in the band: theta = r omega dt with
+    // sin(theta/2) = sin(omega dt/2) lambda / omega (corrected scheme) or
+    // sin(theta/2) = lambda dt / 2 (standard scheme)
+    const double dt = 2.0 * M_PI / omega / nt;
+    auto lam = [&](double r) {
+        const double th = r * omega * dt;
+        return scheme == ELWH_SCHEME_CORRECTED ? omega * std::sin(0.5 * th) / std::sin(0.5 * omega * dt)
+                                               : 2.0 * std::sin(0.5 * th) / dt;
+    };
+    out->lambda_lo = lam(out->r_star);
+    out->lambda_hi = lam(1.0);
+    return ELWH_OK;
+}
+
 elwh_status mapped_metric(int nq, int nr, const double* x, const double* y, MappedMetric* m, std::string* err) {
     const int64_t sy = nq + 1, nn = sy * (nr + 1);
     for (int64_t i = 0; i < nn; ++i)

@@ -24,7 +24,8 @@ KRYLOV_CG, KRYLOV_GMRES, KRYLOV_CR = 0, 1, 2
 SCHEME_CORRECTED, SCHEME_STANDARD = 0, 1
 
 EXPORTED = [
-    "elwh_default_opts", "elwh_plan", "elwh_create", "elwh_plan_mapped", "elwh_create_mapped", "elwh_destroy", "elwh_query", "elwh_last_error",
+    "elwh_default_opts", "elwh_plan", "elwh_create", "elwh_plan_mapped", "elwh_create_mapped",
+    "elwh_filter_diagnostics", "elwh_destroy", "elwh_query", "elwh_last_error",
     "elwh_apply_filter", "elwh_apply_A", "elwh_solve", "elwh_cg_begin", "elwh_cg_iterate",
     "elwh_cg_result", "elwh_dot_M", "elwh_profile_enable", "elwh_profile_read",
     "elwh_set_tile", "elwh_get_tile", "elwh_autotune",
@@ -58,6 +59,11 @@ class Info(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class FilterDiag(ctypes.Structure):
+    _fields_ = [("r_star", ctypes.c_double), ("gap", ctypes.c_double), ("beta_max", ctypes.c_double),
+                ("r_max", ctypes.c_double), ("lambda_lo", ctypes.c_double), ("lambda_hi", ctypes.c_double)]
+
+
 class ElwhError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS_NAMES[status] if 0 <= status < 7 else status}: {msg}")
@@ -81,6 +87,7 @@ def _load():
                                        ctypes.POINTER(Opts), ctypes.POINTER(P)]
     lib.elwh_plan_mapped.argtypes = [ctypes.POINTER(Grid), P, P, P, P, P, D, ctypes.POINTER(I),
                                      ctypes.POINTER(Opts), ctypes.POINTER(Info)]
+    lib.elwh_filter_diagnostics.argtypes = [I, I, D, I, ctypes.POINTER(FilterDiag)]
     lib.elwh_destroy.argtypes = [P]
     lib.elwh_destroy.restype = None
     lib.elwh_query.argtypes = [P, ctypes.POINTER(Info)]
@@ -187,6 +194,16 @@ def plan(dim, n, rho, lam, mu, omega, bc, length=None, **opts):
     if st != OK:
         raise ElwhError(st, lib.elwh_last_error(None).decode())
     return {"nt": info.nt, "dt": info.dt, "c": info.c, "lambda_bound": info.lambda_bound}
+
+
+def filter_diagnostics(nt, periods=1, omega=1.0, scheme=0):
+    """Discrete-filter accuracy of App. B (host only): dict with r_star, gap,
+    beta_max, r_max, lambda_lo, lambda_hi (see elwh_filter_diagnostics)."""
+    d = FilterDiag()
+    st = lib.elwh_filter_diagnostics(int(nt), int(periods), float(omega), int(scheme), ctypes.byref(d))
+    if st != OK:
+        raise ElwhError(st, lib.elwh_last_error(None).decode())
+    return {k: getattr(d, k) for k, _ in FilterDiag._fields_}
 
 
 def plan_mapped(x, y, rho, lam, mu, omega, **opts):

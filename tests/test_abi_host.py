@@ -157,3 +157,53 @@ def test_plan_mapped_rejects_bad_input(elwh):
                                    ok.ctypes.data, 3.0, elwh._bc_array((0, 0, 0, 1)), ctypes.byref(o),
                                    ctypes.byref(info))
     assert st == elwh.ERR_ARG and b"Dirichlet" in elwh.lib.elwh_last_error(None)
+
+
+def test_filter_diagnostics_match_the_oracle_gap(elwh, golden_dir):
+    """App. B: the library's closed-form transfer function and bisection give
+    the oracle's resonance gap (direct trapezoid sums) for every N_T = 5..100,
+    within the printed bound 0.022 dt^2."""
+    import json
+    import math
+    from oracle import spectral
+    g = json.load(open(os.path.join(golden_dir, "appendix_b_gap.json")))
+    for k in range(g["k_min"], g["k_max"] + 1):
+        d = elwh.filter_diagnostics(k)
+        gap_o = 1.0 - spectral.resonance_gap(k)
+        # both sides bisect beta_h(r) = 1, where beta_h - 1 has slope ~1e-3:
+        # rounding of beta_h (~1e-16) places r* to ~1e-13
+        assert abs(d["gap"] - gap_o) <= 1e-12, k
+        assert 0 < d["gap"] <= g["constant"] * (2 * math.pi / k) ** 2
+        assert d["beta_max"] > 1.0 and d["r_star"] < d["r_max"] < 1.0
+
+
+@pytest.mark.parametrize("nt,periods", [(7, 2), (20, 3), (63, 1), (63, 2), (150, 1)])
+def test_filter_diagnostics_band_against_oracle_weights(elwh, nt, periods):
+    import math
+    from oracle import spectral
+    from oracle.stepping import filter_weights
+    w, _ = filter_weights(nt, periods)
+    d = elwh.filter_diagnostics(nt, periods, 7.0, 0)
+    th = lambda r: np.asarray(r) * 2 * math.pi / nt     # noqa: E731
+    assert spectral.beta_h(th(d["r_star"]), w)[0] == pytest.approx(1.0, abs=1e-12)
+    left = np.linspace(0.5, d["r_star"] - 1e-3 * d["gap"], 4001)
+    assert np.all(spectral.beta_h(th(left), w) < 1.0)
+    inside = np.linspace(d["r_star"], 1.0, 2001)
+    vals = spectral.beta_h(th(inside), w)
+    assert np.all(vals >= 1.0 - 1e-13)
+    assert vals.max() <= d["beta_max"] + 1e-13
+    assert spectral.beta_h(th(d["r_max"]), w)[0] == pytest.approx(d["beta_max"], abs=1e-13)
+    # the band of spatial frequencies: corrected scheme theta = 2 arcsin(sin(w dt/2) lambda / w)
+    om = 7.0
+    dt = 2 * math.pi / om / nt
+    assert spectral.mode_angle(d["lambda_lo"], om, dt) == pytest.approx(d["r_star"] * om * dt, rel=1e-12)
+    assert d["lambda_hi"] == pytest.approx(om, rel=1e-14)
+    s = elwh.filter_diagnostics(nt, periods, om, 1)
+    assert 2 * math.asin(s["lambda_lo"] * dt / 2) == pytest.approx(s["r_star"] * om * dt, rel=1e-12)
+    assert s["lambda_hi"] == pytest.approx(2 * math.sin(om * dt / 2) / dt, rel=1e-14)
+
+
+def test_filter_diagnostics_reject_bad_input(elwh):
+    for args in ((2, 1, 1.0, 0), (10, 0, 1.0, 0), (10, 1, -1.0, 0), (10, 1, 1.0, 7)):
+        with pytest.raises(elwh.ElwhError, match="ERR_ARG"):
+            elwh.filter_diagnostics(*args)
