@@ -30,10 +30,15 @@ Reading taken here (the Cartesian reading of operator.py carried over):
   the square); J g_q = (y_r, -x_r), J g_r = (-y_q, x_q).
 * Mass rho J, forcing J f:  rho J u'' = L_h u - J f cos(omega t).  In the
   Operator convention of operator.py (rho u'' = Ltilde u - f cos) this is
-  Ltilde = J^-1 L_h with node weight W = J and M = W rho.
-* Boundary: homogeneous Dirichlet on all four sides of the square (the
-  annular-sector experiments of Sec. 5.4 state no boundary condition; the
-  rectangle beside them is Dirichlet).
+  Ltilde = W^-1 L_h with node weight W = J w_p and M = W rho.
+* Boundary: homogeneous Dirichlet on the q sides; Dirichlet (default; the
+  annular-sector experiments of Sec. 5.4 state no boundary condition and
+  the rectangle beside them is Dirichlet) or traction-free on each r side
+  (the free curved surfaces of the toroidal shell of Sec. 5.9, in 2-D).  A
+  free side is closed from the same energy as on Cartesian grids (reading of
+  operator.py): trapezoid weight w_p = 1/2 for its nodes and for the q-edges
+  lying in it, and the one-sided r difference into the domain in place of
+  D0r in its cross terms; traction-free is the natural boundary condition.
 
 Parity: pinned by the reduction to the Cartesian operator for a scaled
 identity map, exact rotation equivariance, symmetry and semi-definiteness,
@@ -48,7 +53,8 @@ numbers for these grids, so absolute values are otherwise "parity unpinned".
 import numpy as np
 import scipy.sparse as sp
 
-from .problem import DIRICHLET, Problem
+from .operator import _edges, forward_difference, node_difference
+from .problem import DIRICHLET, FREE, Problem  # noqa: F401
 
 
 def _diff(f, h, axis):
@@ -94,13 +100,16 @@ class MappedOperator:
     unknown (interior) dofs; the same interface as operator.Operator, so the
     filter, the Krylov solvers and the direct solve apply unchanged.
 
-    x, y, rho, lam, mu: node arrays of shape (n_r + 1, n_q + 1)."""
+    x, y, rho, lam, mu: node arrays of shape (n_r + 1, n_q + 1); bc: the
+    sides (-q, +q, -r, +r), q sides Dirichlet, r sides DIRICHLET or FREE."""
 
-    def __init__(self, x, y, rho, lam, mu):
+    def __init__(self, x, y, rho, lam, mu, bc=(DIRICHLET,) * 4):
         x = np.asarray(x, np.float64)
         shape = x.shape
         nr, nq = shape[0] - 1, shape[1] - 1
-        self.prob = Problem(2, (nq, nr), length=(1.0, 1.0), bc=(DIRICHLET,) * 4)
+        if bc[0] != DIRICHLET or bc[1] != DIRICHLET:
+            raise ValueError("the q sides must be Dirichlet")
+        self.prob = Problem(2, (nq, nr), length=(1.0, 1.0), bc=tuple(bc))
         self.hq, self.hr = 1.0 / nq, 1.0 / nr
         self.rho = np.broadcast_to(np.asarray(rho, np.float64), shape).copy()
         self.lam = np.broadcast_to(np.asarray(lam, np.float64), shape).copy()
@@ -113,75 +122,55 @@ class MappedOperator:
         keep = prob.dof_mask().ravel()
         Kfull = self.stiffness()
         self.Lh = (-Kfull[keep][:, keep]).tocsr()
-        self.w = prob.gather(np.broadcast_to(self.J, prob.field_shape))
+        self.w = prob.gather(np.broadcast_to(self.J * prob.node_weight(), prob.field_shape))
         self.rho_dof = prob.gather(np.broadcast_to(self.rho, prob.field_shape))
         self.m = self.w * self.rho_dof
         self.Lt = (sp.diags(1.0 / self.w) @ self.Lh).tocsr()
         self.ndof = int(keep.sum())
 
     # ---- assembly from the energy -------------------------------------------
-    def _edge_diff(self, axis):
-        """D+ along q (axis 0) or r (axis 1): node values -> edge values, and
-        the edge endpoints."""
-        nr1, nq1 = self.J.shape
-        ni = np.arange(nr1 * nq1).reshape(nr1, nq1)
-        if axis == 0:
-            lo, hi, h = ni[:, :-1].ravel(), ni[:, 1:].ravel(), self.hq
-        else:
-            lo, hi, h = ni[:-1, :].ravel(), ni[1:, :].ravel(), self.hr
-        ne = lo.size
-        rows = np.concatenate([np.arange(ne), np.arange(ne)])
-        D = sp.csr_matrix((np.concatenate([-np.ones(ne), np.ones(ne)]) / h, (rows, np.concatenate([lo, hi]))),
-                          shape=(ne, nr1 * nq1))
-        return D, lo, hi
-
-    def _central(self, axis):
-        """D0 along q or r at interior nodes (rows of boundary nodes empty)."""
-        nr1, nq1 = self.J.shape
-        ni = np.arange(nr1 * nq1).reshape(nr1, nq1)
-        mid = ni[1:-1, 1:-1].ravel()
-        if axis == 0:
-            plus, minus, h = ni[1:-1, 2:].ravel(), ni[1:-1, :-2].ravel(), self.hq
-        else:
-            plus, minus, h = ni[2:, 1:-1].ravel(), ni[:-2, 1:-1].ravel(), self.hr
-        n = nr1 * nq1
-        return sp.csr_matrix((np.concatenate([np.full(mid.size, 0.5 / h), np.full(mid.size, -0.5 / h)]),
-                              (np.concatenate([mid, mid]), np.concatenate([plus, minus]))), shape=(n, n))
-
     def stiffness(self):
         """Hessian of E_h over all node dofs (component-major), Dirichlet
         nodes included."""
+        prob = self.prob
         n = self.J.size
         B = [[sp.csr_matrix((n, n)) for _ in range(2)] for _ in range(2)]
         for axis, Kn in ((0, self.Kqq), (1, self.Krr)):
-            D, lo, hi = self._edge_diff(axis)
+            lo, hi, we = _edges(prob, axis)
+            D = forward_difference(prob, axis)
             for c in range(2):
                 for e in range(2):
                     k = Kn[c, e].ravel()
-                    B[c][e] = B[c][e] + D.T @ sp.diags(0.5 * (k[lo] + k[hi])) @ D
-        Dq, Dr = self._central(0), self._central(1)
+                    B[c][e] = B[c][e] + D.T @ sp.diags(we * 0.5 * (k[lo] + k[hi])) @ D
+        wn = (prob.node_weight() * prob.unknown_mask()).ravel()
+        Dq, Dr = node_difference(prob, 0), node_difference(prob, 1)     # D0q, Dhat_r
         for c in range(2):
             for e in range(2):
-                C = Dq.T @ sp.diags(self.Kqr[c, e].ravel()) @ Dr     # (D0q u_c) K_ce (D0r u_e)
+                C = Dq.T @ sp.diags(wn * self.Kqr[c, e].ravel()) @ Dr     # w (D0q u_c) K_ce (Dhat_r u_e)
                 B[c][e] = B[c][e] + C
                 B[e][c] = B[e][c] + C.T
         return sp.bmat(B, format="csr")
 
     def energy(self, full):
         """E_h of a full node field (2, n_r + 1, n_q + 1), term by term."""
-        U = np.asarray(full, np.float64)
+        prob = self.prob
+        U = [np.asarray(full[c], np.float64).ravel() for c in range(2)]
         E = 0.0
-        for ax, Kn, h in ((1, self.Kqq, self.hq), (0, self.Krr, self.hr)):
-            lo = [slice(None)] * 2
-            hi = [slice(None)] * 2
-            lo[ax], hi[ax] = slice(0, -1), slice(1, None)
-            g = (U[(slice(None),) + tuple(hi)] - U[(slice(None),) + tuple(lo)]) / h
-            Kb = 0.5 * (Kn[(slice(None), slice(None)) + tuple(lo)] + Kn[(slice(None), slice(None)) + tuple(hi)])
-            E += 0.5 * sum(float(np.sum(g[i] * Kb[i, k] * g[k])) for i in range(2) for k in range(2))
-        dq = (U[:, 1:-1, 2:] - U[:, 1:-1, :-2]) / (2 * self.hq)
-        dr = (U[:, 2:, 1:-1] - U[:, :-2, 1:-1]) / (2 * self.hr)
-        Kc = self.Kqr[:, :, 1:-1, 1:-1]
-        E += sum(float(np.sum(dq[i] * Kc[i, k] * dr[k])) for i in range(2) for k in range(2))
+        for axis, Kn in ((0, self.Kqq), (1, self.Krr)):
+            lo, hi, we = _edges(prob, axis)
+            h = prob.h[axis]
+            g = [(U[c][hi] - U[c][lo]) / h for c in range(2)]
+            for c in range(2):
+                for e in range(2):
+                    k = Kn[c, e].ravel()
+                    E += 0.5 * float(np.sum(we * 0.5 * (k[lo] + k[hi]) * g[c] * g[e]))
+        wn = (prob.node_weight() * prob.unknown_mask()).ravel()
+        Dq, Dr = node_difference(prob, 0), node_difference(prob, 1)
+        dq = [Dq @ U[c] for c in range(2)]
+        dr = [Dr @ U[c] for c in range(2)]
+        for c in range(2):
+            for e in range(2):
+                E += float(np.sum(wn * self.Kqr[c, e].ravel() * dq[c] * dr[e]))
         return E
 
     # ---- interface shared with operator.Operator ------------------------------
@@ -197,8 +186,8 @@ class MappedOperator:
 def lh_stencil(x, y, lam, mu, U):
     """L_h U at the interior nodes written out as the stencil (zeros on the
     boundary), with U = (u, v) of shape (2, n_r + 1, n_q + 1) and zero
-    boundary values: a second statement of the operator that needs no matrix
-    (it reaches the largest grids)."""
+    boundary values (all sides Dirichlet): a second statement of the operator
+    that needs no matrix (it reaches the largest grids)."""
     x = np.asarray(x, np.float64)
     nr, nq = x.shape[0] - 1, x.shape[1] - 1
     hq, hr = 1.0 / nq, 1.0 / nr

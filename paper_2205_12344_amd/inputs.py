@@ -331,3 +331,15 @@ def sector_case(k, n_an=1, seed=None, arc=5.0):
     f = np.zeros((2,) + x.shape)
     f[0, i, i] = w * w / area
     return x, y, rho, lam, mu, w, f
+
+
+def ring_grid(nq, nr, r_in=1.0, r_out=2.0, angle=math.pi):
+    """Node coordinates of a ring sector with q along the arc and r radial
+    (r = 0 the inner arc of radius r_in, r = 1 the outer arc of radius
+    r_out; the angle decreases with q so the map is right-handed): the
+    cross-section of the partial toroidal shell of Sec. 5.9 (1 <= r <= 2,
+    0 <= theta <= pi), whose curved surfaces are traction-free."""
+    Q, R = np.meshgrid(np.arange(nq + 1) / nq, np.arange(nr + 1) / nr)
+    rad = r_in + (r_out - r_in) * R
+    th = angle * (1.0 - Q)
+    return rad * np.cos(th), rad * np.sin(th)

@@ -27,7 +27,7 @@ from oracle.curvilinear import MappedOperator, lh_stencil, metric
 from oracle.operator import Operator
 from oracle.problem import Problem
 from oracle.stepping import STANDARD, WaveHoltz
-from paper_2205_12344_amd.inputs import media_mapped, rectangle_grid, sector_grid, warped_grid
+from paper_2205_12344_amd.inputs import media_mapped, rectangle_grid, ring_grid, sector_grid, warped_grid
 
 
 def rel(a, b):
@@ -242,3 +242,69 @@ def test_sector_iterations_match_the_rectangle():
     for g in ("quarter", "half"):
         ratio = np.array(its[g]) / np.array(its["rectangle"])
         assert np.all(ratio > 0.6) and np.all(ratio < 1.4), (its, ratio)
+
+
+# ---- traction-free r sides (the free curved surfaces of Sec. 5.9, in 2-D) ----------
+
+@pytest.mark.parametrize("bc", [(0, 0, 1, 1), (0, 0, 0, 1), (0, 0, 1, 0)])
+def test_free_sides_of_a_scaled_identity_map_are_the_cartesian_closure(bc):
+    nq, nr, lq, lr = 8, 11, 0.9, 1.7
+    x, y = rectangle_grid(nq, nr, lq, lr)
+    rho, lam, mu = media_mapped(x, y, seed=21)
+    m = MappedOperator(x, y, rho, lam, mu, bc=bc)
+    c = Operator(Problem(2, (nq, nr), length=(lq, lr), bc=bc), rho, lam, mu)
+    assert m.ndof == c.ndof
+    d = (m.Lt - c.Lt).toarray()
+    assert np.max(np.abs(d)) <= 1e-12 * np.max(np.abs(c.Lt.toarray()))
+    assert np.allclose(m.m, c.m * lq * lr, rtol=1e-14)
+
+
+def test_free_sides_structure_on_a_ring_sector():
+    x, y = ring_grid(18, 7)
+    rho, lam, mu = media_mapped(x, y, seed=22)
+    bc = (0, 0, 1, 1)
+    op = MappedOperator(x, y, rho, lam, mu, bc=bc)
+    L = op.Lh.toarray()
+    assert np.max(np.abs(L - L.T)) <= 1e-14 * np.max(np.abs(L))
+    assert np.linalg.eigvalsh(-L)[0] > 0
+    prob = op.prob
+    U = np.random.default_rng(23).standard_normal(prob.field_shape) * prob.unknown_mask()
+    xv = prob.gather(U)
+    assert abs(op.energy(U) - 0.5 * xv @ (-op.Lh @ xv)) <= 1e-12 * abs(op.energy(U))
+    K = op.stiffness()
+    for c in range(2):
+        T = np.zeros(2 * x.size)
+        T[c * x.size:(c + 1) * x.size] = 1.0
+        assert np.max(np.abs(K @ T)) <= 1e-12 * np.max(np.abs(K.diagonal()))
+    # rotation equivariance with free sides
+    phi = -1.1
+    cs, sn = math.cos(phi), math.sin(phi)
+    b = MappedOperator(cs * x - sn * y, sn * x + cs * y, rho, lam, mu, bc=bc)
+    RU = np.stack([cs * U[0] - sn * U[1], sn * U[0] + cs * U[1]])
+    LU = prob.scatter(op.Lh @ xv)
+    expect = np.stack([cs * LU[0] - sn * LU[1], sn * LU[0] + cs * LU[1]])
+    assert rel(prob.scatter(b.Lh @ prob.gather(RU)), expect) <= 1e-12
+
+
+def test_free_sides_converge_at_second_order():
+    """Self-convergence of the Helmholtz solution on the ring sector with
+    traction-free inner and outer arcs (no closed-form solution satisfies the
+    free condition on the curved sides with variable media): differences
+    between successive refinements, at the coarse nodes, fall like h^2."""
+    sols = []
+    omega = 1.7
+    for k in (1, 2, 4):
+        nq, nr = 24 * k, 8 * k
+        x, y = ring_grid(nq, nr)
+        rho = 1.0 + 0.2 * np.sin(x + 0.5 * y)
+        mu = 1.0 + 0.3 * np.cos(0.7 * x - y)
+        lam = 2.0 + 0.5 * np.sin(x * y)
+        op = MappedOperator(x, y, rho, lam, mu, bc=(0, 0, 1, 1))
+        f = np.stack([np.exp(-((x + 0.8) ** 2 + (y - 1.1) ** 2) / 0.18),
+                      0.5 * np.exp(-((x - 1.0) ** 2 + (y - 1.2) ** 2) / 0.2)])
+        sol = op.prob.scatter(direct.solve(op, omega, op.prob.gather(f)))
+        sols.append(sol[:, ::k, ::k])
+    scale = np.max(np.abs(sols[-1]))
+    d1 = np.max(np.abs(sols[0] - sols[1])) / scale
+    d2 = np.max(np.abs(sols[1] - sols[2])) / scale
+    assert np.log2(d1 / d2) > 1.8, (d1, d2)
