@@ -163,7 +163,10 @@ elwh_status elwh_create(const elwh_grid* grid, const double* rho, const double* 
  * stepwise CG) works unchanged on the context.  Fields keep the node
  * layout [2][n[1]+1][n[0]+1] with Cartesian components (u, v) along x and y.
  *
- * bc: the four sides of the square (-q, +q, -r, +r); all must be Dirichlet.
+ * bc: the four sides of the square (-q, +q, -r, +r).  The q sides must be
+ * Dirichlet; each r side is Dirichlet or traction-free, closed from the same
+ * energy with trapezoid weight 1/2 on its nodes and q-edges and the
+ * one-sided r difference in its cross terms (M weights rho J / 2 there).
  * Every time step is one launch (opts->fuse is ignored).  x, y, rho, lam, mu
  * are DEVICE pointers, copied.  Errors: ELWH_ERR_ARG (also for a map with
  * J <= 0 at some node, i.e. folded or left-handed, or non-finite

@@ -25,8 +25,16 @@
 // term D0r(K^rq D0q U) of the centre row is (Q_N - Q_S) / (4 h_q h_r).  The
 // other cross term needs P = K^qr (U_N - U_S) at the q neighbours: P is
 // formed per lane and moved across lanes by DPP shifts, like K^qq and the
-// neighbour displacements.  Boundary nodes hold zero displacement and the
-// padding zero coefficients, so no node needs a special case.
+// neighbour displacements.  Dirichlet nodes hold zero displacement and the
+// padding zero coefficients, so interior nodes need no special case.
+//
+// Traction-free r sides (rows r = 0 / r = 1) are closed from the same
+// energy with trapezoid weight 1/2 on the side's nodes and q-edges and the
+// one-sided r difference in its cross terms; divided by the weight, the row
+// of the top side reads
+//     D+q(Kbar^qq D-q U) - (K^rr_C + K^rr_S)(U_C - U_S) / h_r^2
+//     + [P'_{i+1} - P'_{i-1} - (Q_C + Q_S)] / (2 h_q h_r),
+// P' = K^qr (U_C - U_S), and the bottom side mirrors it.
 #include "step2d_common.h"
 
 namespace elwh {
@@ -86,6 +94,7 @@ __device__ __forceinline__ void curv2d_body(int bx, int by, const U* __restrict_
     const int P = (int)A.P;
     const int64_t CS = A.CS;
     const T cqq2 = (T)A.cxx2, crr2 = (T)A.cyy2, cqr = (T)A.cxy;
+    const T crrf = (T)A.cyyf, cqrf = (T)A.cfx;   // free rows: 1/h_r^2, 1/(2 h_q h_r)
     const T two = (T)2;
     const int ilo = max(c0 + 1, 1), ihi = min(c0 + W, A.nx - 1);
 
@@ -194,11 +203,14 @@ __device__ __forceinline__ void curv2d_body(int bx, int by, const U* __restrict_
             load_ctr(j + 1, ctrN);
         }
         finish(rawN, N);
-        // K^qq of the q neighbours and P = K^qr (U_N - U_S), across the lane edges
+        // K^qq of the q neighbours and P = K^qr (U_N - U_S) (one-sided on a
+        // free row), across the lane edges
+        const int kind = (A.free_hi && j == A.ny) ? 1 : ((A.free_lo && j == 0) ? 2 : 0);
         T P0[V], P1[V];
 #pragma unroll
         for (int k = 0; k < V; ++k) {
-            const T du = N.u[k] - S.u[k], dv = N.v[k] - S.v[k];
+            const T du = (kind == 1 ? C.u[k] : N.u[k]) - (kind == 2 ? C.u[k] : S.u[k]);
+            const T dv = (kind == 1 ? C.v[k] : N.v[k]) - (kind == 2 ? C.v[k] : S.v[k]);
             P0[k] = C.qr0[k] * du + C.qr1[k] * dv;
             P1[k] = C.qr2[k] * du + C.qr3[k] * dv;
         }
@@ -234,11 +246,25 @@ __device__ __forceinline__ void curv2d_body(int bx, int by, const U* __restrict_
             dpv = N.v[k] - vc;
             dmu = uc - S.u[k];
             dmv = vc - S.v[k];
-            Lu += crr2 * ((kp0 * dpu + kp1 * dpv) - (km0 * dmu + km1 * dmv));
-            Lv += crr2 * ((kp1 * dpu + kp2 * dpv) - (km1 * dmu + km2 * dmv));
-            // cross terms D0q(K^qr D0r U) + D0r(K^rq D0q U)
-            Lu += cqr * ((at_right<T, V>(P0, k, P0R) - at_left<T, V>(P0, k, P0L)) + (N.Q0[k] - S.Q0[k]));
-            Lv += cqr * ((at_right<T, V>(P1, k, P1R) - at_left<T, V>(P1, k, P1L)) + (N.Q1[k] - S.Q1[k]));
+            const T dP0 = at_right<T, V>(P0, k, P0R) - at_left<T, V>(P0, k, P0L);
+            const T dP1 = at_right<T, V>(P1, k, P1R) - at_left<T, V>(P1, k, P1L);
+            if (kind == 0) {
+                Lu += crr2 * ((kp0 * dpu + kp1 * dpv) - (km0 * dmu + km1 * dmv));
+                Lv += crr2 * ((kp1 * dpu + kp2 * dpv) - (km1 * dmu + km2 * dmv));
+                // cross terms D0q(K^qr D0r U) + D0r(K^rq D0q U)
+                Lu += cqr * (dP0 + (N.Q0[k] - S.Q0[k]));
+                Lv += cqr * (dP1 + (N.Q1[k] - S.Q1[k]));
+            } else if (kind == 1) {
+                Lu -= crrf * (km0 * dmu + km1 * dmv);
+                Lv -= crrf * (km1 * dmu + km2 * dmv);
+                Lu += cqrf * (dP0 - (C.Q0[k] + S.Q0[k]));
+                Lv += cqrf * (dP1 - (C.Q1[k] + S.Q1[k]));
+            } else {
+                Lu += crrf * (kp0 * dpu + kp1 * dpv);
+                Lv += crrf * (kp1 * dpu + kp2 * dpv);
+                Lu += cqrf * (dP0 + (C.Q0[k] + N.Q0[k]));
+                Lv += cqrf * (dP1 + (C.Q1[k] + N.Q1[k]));
+            }
             if constexpr (FORCE) {
                 const T fc = (T)A.fc;
                 Lu -= fc * ctr.fu[k];

@@ -282,27 +282,71 @@ void mapped_blocks(const MappedMetric& m, const double* lam, const double* mu, i
     qr[2] = l * A1 * B0 + u * B1 * A0; qr[3] = lu * A1 * B1 + u * AB;
 }
 
-// Gershgorin row sums of (rho J)^-1 L_h on a mapped grid (all four sides
-// Dirichlet): the stencil entries of each interior row, summed per
-// (neighbour, component) before taking absolute values.
+// Gershgorin row sums of (w_p rho J)^-1 L_h on a mapped grid (q sides
+// Dirichlet, r sides Dirichlet or traction-free): the stencil entries of
+// each unknown row, summed per (neighbour, component) before taking absolute
+// values.  A traction-free row (weight 1/2) is the Hessian row of the
+// energy with the one-sided r difference in its cross terms, times 2.
 double gershgorin_mapped(int nq, int nr, const MappedMetric& m, const double* rho, const double* lam,
-                         const double* mu) {
+                         const double* mu, bool free_lo, bool free_hi) {
     const double hq = 1.0 / nq, hr = 1.0 / nr;
     const double iqq = 1.0 / (hq * hq), irr = 1.0 / (hr * hr), iqr = 1.0 / (4.0 * hq * hr);
     const int64_t sy = nq + 1;
     unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    nth = std::min<unsigned>(nth, (unsigned)std::max(1, nr - 1));
+    const int jlo = free_lo ? 0 : 1, jhi = free_hi ? nr : nr - 1;
+    nth = std::min<unsigned>(nth, (unsigned)std::max(1, jhi - jlo + 1));
     std::vector<double> part(nth, 0.0);
     auto work = [&](unsigned t) {
         double best = 0.0;
-        for (int j = 1 + (int)t; j <= nr - 1; j += (int)nth)
+        for (int j = jlo + (int)t; j <= jhi; j += (int)nth)
             for (int i = 1; i <= nq - 1; ++i) {
                 const int64_t p = j * sy + i;
                 double E[3][3][2][2];   // [dj][di][row comp][col comp]
                 std::memset(E, 0, sizeof(E));
                 double qq0[4], qr0[4], rr0[4];
                 mapped_blocks(m, lam, mu, p, qq0, qr0, rr0);
-                for (int s = -1; s <= 1; s += 2) {
+                const int kind = (free_hi && j == nr) ? 1 : ((free_lo && j == 0) ? 2 : 0);
+                if (kind != 0) {
+                    // free row: q-compact as inside (weight 1/2, times 2); the
+                    // r-edge into the domain; cross terms with the one-sided
+                    // r difference (d = -1 top, +1 bottom)
+                    const int d = kind == 1 ? -1 : 1;
+                    for (int s = -1; s <= 1; s += 2) {
+                        double qq[4], qr[4], rr[4];
+                        mapped_blocks(m, lam, mu, p + s, qq, qr, rr);
+                        for (int c = 0; c < 2; ++c)
+                            for (int e = 0; e < 2; ++e) {
+                                const double kb = 0.5 * (qq0[2 * c + e] + qq[2 * c + e]) * iqq;
+                                E[1][1 + s][c][e] += kb;
+                                E[1][1][c][e] -= kb;
+                                // 2 x (1/2) D0q(K^qr Dhat_r U): K^qr at (j, i+s)
+                                // times the one-sided r difference there
+                                const double v = 2.0 * s * qr[2 * c + e] * iqr;
+                                if (kind == 1) {   // (U_j - U_{j-1}) at i+s
+                                    E[1][1 + s][c][e] += v;
+                                    E[0][1 + s][c][e] -= v;
+                                } else {           // (U_{j+1} - U_j) at i+s
+                                    E[2][1 + s][c][e] += v;
+                                    E[1][1 + s][c][e] -= v;
+                                }
+                            }
+                    }
+                    double qq[4], qr[4], rr[4];
+                    mapped_blocks(m, lam, mu, p + d * sy, qq, qr, rr);   // the row inside
+                    for (int c = 0; c < 2; ++c)
+                        for (int e = 0; e < 2; ++e) {
+                            const double kb = (rr0[2 * c + e] + rr[2 * c + e]) * irr;   // 2 x mean
+                            E[1 + d][1][c][e] += kb;
+                            E[1][1][c][e] -= kb;
+                            // -/+ 2 (Q_row + Q_in) / (4 h_q h_r), Q = (K^qr)^T (U_{i+1} - U_{i-1})
+                            const double sg = kind == 1 ? -2.0 * iqr : 2.0 * iqr;
+                            E[1][2][c][e] += sg * qr0[2 * e + c];
+                            E[1][0][c][e] -= sg * qr0[2 * e + c];
+                            E[1 + d][2][c][e] += sg * qr[2 * e + c];
+                            E[1 + d][0][c][e] -= sg * qr[2 * e + c];
+                        }
+                }
+                for (int s = -1; s <= 1 && kind == 0; s += 2) {
                     double qq[4], qr[4], rr[4];
                     mapped_blocks(m, lam, mu, p + s, qq, qr, rr);   // (j, i+s)
                     for (int c = 0; c < 2; ++c)
@@ -330,10 +374,10 @@ double gershgorin_mapped(int nq, int nr, const MappedMetric& m, const double* rh
                     for (int dj = -1; dj <= 1; ++dj)
                         for (int di = -1; di <= 1; ++di) {
                             const int jj = j + dj, ii = i + di;
-                            if (jj < 1 || jj > nr - 1 || ii < 1 || ii > nq - 1) continue;
+                            if (jj < jlo || jj > jhi || ii < 1 || ii > nq - 1) continue;
                             sum += std::fabs(E[1 + dj][1 + di][c][0]) + std::fabs(E[1 + dj][1 + di][c][1]);
                         }
-                    best = std::max(best, sum / (rho[p] * m.J[p]));
+                    best = std::max(best, sum / (rho[p] * m.J[p]));   // free rows: entries carry the 2
                 }
             }
         part[t] = best;
@@ -492,8 +536,10 @@ elwh_status make_plan_mapped(const elwh_grid* g, const double* x, const double* 
                              Plan* out, MappedMetric* met, std::string* err) {
     if (!g || !bc) { *err = "null grid or bc"; return ELWH_ERR_ARG; }
     if (g->dim != 2) { *err = "mapped grids are two-dimensional"; return ELWH_ERR_ARG; }
-    for (int f = 0; f < 4; ++f)
-        if (bc[f] != ELWH_BC_DIRICHLET) { *err = "mapped grids support Dirichlet sides only"; return ELWH_ERR_ARG; }
+    if (bc[0] != ELWH_BC_DIRICHLET || bc[1] != ELWH_BC_DIRICHLET) {
+        *err = "mapped grids need Dirichlet q sides (traction-free is supported on the r sides)";
+        return ELWH_ERR_ARG;
+    }
     elwh_grid unit = *g;
     unit.len[0] = unit.len[1] = 1.0;
     elwh_status st = check_config(&unit, bc, o, err);
@@ -508,7 +554,9 @@ elwh_status make_plan_mapped(const elwh_grid* g, const double* x, const double* 
     MappedMetric local;
     MappedMetric* m = met ? met : &local;
     if ((st = mapped_metric(nq, nr, x, y, m, err)) != ELWH_OK) return st;
-    return plan_from_bound(gershgorin_mapped(nq, nr, *m, rho, lam, mu), omega, o, out, err);
+    const double G = gershgorin_mapped(nq, nr, *m, rho, lam, mu, bc[2] == ELWH_BC_TRACTION_FREE,
+                                       bc[3] == ELWH_BC_TRACTION_FREE);
+    return plan_from_bound(G, omega, o, out, err);
 }
 
 elwh_status check_config(const elwh_grid* g, const int bc[6], const elwh_opts* o, std::string* err) {

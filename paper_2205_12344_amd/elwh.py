@@ -206,9 +206,10 @@ def filter_diagnostics(nt, periods=1, omega=1.0, scheme=0):
     return {k: getattr(d, k) for k, _ in FilterDiag._fields_}
 
 
-def plan_mapped(x, y, rho, lam, mu, omega, **opts):
+def plan_mapped(x, y, rho, lam, mu, omega, bc=(0, 0, 0, 0), **opts):
     """Time-step plan of a mapped 2-D grid on the host (no GPU); x, y, rho,
-    lam, mu node arrays of shape (n_r + 1, n_q + 1)."""
+    lam, mu node arrays of shape (n_r + 1, n_q + 1); bc the sides
+    (-q, +q, -r, +r)."""
     xs, ys = _host(x), _host(y)
     nr, nq = xs.shape[0] - 1, xs.shape[1] - 1
     g = make_grid(2, (nq, nr))
@@ -216,7 +217,7 @@ def plan_mapped(x, y, rho, lam, mu, omega, **opts):
     o = default_opts(**opts)
     info = Info()
     st = lib.elwh_plan_mapped(ctypes.byref(g), xs.ctypes.data, ys.ctypes.data, r.ctypes.data, l.ctypes.data,
-                              m.ctypes.data, float(omega), _bc_array((0, 0, 0, 0)), ctypes.byref(o),
+                              m.ctypes.data, float(omega), _bc_array(bc), ctypes.byref(o),
                               ctypes.byref(info))
     if st != OK:
         raise ElwhError(st, lib.elwh_last_error(None).decode())
@@ -353,9 +354,10 @@ class Context:
 class MappedContext(Context):
     """One problem on a mapped 2-D grid (wraps elwh_create_mapped): x, y are
     the node coordinates, shape (n_r + 1, n_q + 1), q along the last axis;
-    all four sides Dirichlet.  Every Context method applies."""
+    bc = (-q, +q, -r, +r) sides, q sides Dirichlet, r sides Dirichlet (0) or
+    traction-free (1).  Every Context method applies."""
 
-    def __init__(self, x, y, rho, lam, mu, omega, stream=None, **opts):
+    def __init__(self, x, y, rho, lam, mu, omega, bc=(0, 0, 0, 0), stream=None, **opts):
         if not torch.cuda.is_available():
             raise RuntimeError("libelwh needs a GPU")
         xs = _dev(x, "x")
@@ -376,7 +378,7 @@ class MappedContext(Context):
                 raise ValueError(f"material shape {tuple(t.shape)} != {self.node_shape}")
         h = ctypes.c_void_p()
         st = lib.elwh_create_mapped(ctypes.byref(g), xs.data_ptr(), ys.data_ptr(), r.data_ptr(), l.data_ptr(),
-                                    m.data_ptr(), float(omega), _bc_array((0, 0, 0, 0)), ctypes.byref(o),
+                                    m.data_ptr(), float(omega), _bc_array(bc), ctypes.byref(o),
                                     ctypes.byref(h))
         if st != OK:
             raise ElwhError(st, lib.elwh_last_error(None).decode())

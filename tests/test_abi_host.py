@@ -154,9 +154,38 @@ def test_plan_mapped_rejects_bad_input(elwh):
     o = elwh.default_opts()
     info = elwh.Info()
     st = elwh.lib.elwh_plan_mapped(ctypes.byref(g), x.ctypes.data, y.ctypes.data, ok.ctypes.data, ok.ctypes.data,
-                                   ok.ctypes.data, 3.0, elwh._bc_array((0, 0, 0, 1)), ctypes.byref(o),
+                                   ok.ctypes.data, 3.0, elwh._bc_array((1, 0, 0, 0)), ctypes.byref(o),
                                    ctypes.byref(info))
-    assert st == elwh.ERR_ARG and b"Dirichlet" in elwh.lib.elwh_last_error(None)
+    assert st == elwh.ERR_ARG and b"Dirichlet q sides" in elwh.lib.elwh_last_error(None)
+
+
+@pytest.mark.parametrize("kind", ["ring", "warped", "quarter"])
+@pytest.mark.parametrize("bc", [(0, 0, 1, 1), (0, 0, 0, 1), (0, 0, 1, 0)])
+def test_plan_mapped_free_sides_match_oracle(elwh, kind, bc):
+    """Traction-free r sides: the media are stiffened eightfold on the two r
+    sides so that the largest Gershgorin row is a free (or Dirichlet-side)
+    row, which the plan must then reproduce."""
+    from oracle.curvilinear import MappedOperator
+    from paper_2205_12344_amd import inputs
+    if kind == "ring":
+        x, y = inputs.ring_grid(18, 7)
+    elif kind == "warped":
+        x, y = inputs.warped_grid(11, 13, seed=2)
+    else:
+        x, y = inputs.sector_grid(9, 30, 1)
+    rho, lam, mu = inputs.media_mapped(x, y, seed=x.shape[1])
+    for a in (lam, mu):
+        a[0, :] *= 8
+        a[-1, :] *= 8
+    op = MappedOperator(x, y, rho, lam, mu, bc=bc)
+    rows = np.asarray(abs(op.Lt).sum(axis=1)).ravel() / op.rho_dof
+    full = np.zeros(op.prob.field_shape)
+    full[op.prob.dof_mask()] = rows
+    jmax = np.unravel_index(np.argmax(full), full.shape)[1]
+    free_rows = [j for j, f in ((0, bc[2]), (x.shape[0] - 1, bc[3])) if f]
+    assert jmax in free_rows
+    p = elwh.plan_mapped(x, y, rho, lam, mu, 4.0, bc=bc)
+    assert p["lambda_bound"] == pytest.approx(op.gershgorin(), rel=1e-13)
 
 
 def test_filter_diagnostics_match_the_oracle_gap(elwh, golden_dir):

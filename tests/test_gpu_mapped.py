@@ -216,3 +216,94 @@ def test_mapped_rejects_bad_arguments(E):
     ctx = E.MappedContext(x, y, one, one, one, 3.0)
     with pytest.raises(E.ElwhError, match="ERR_ARG"):
         ctx.set_tile(0, 4, 8)
+
+
+# ---- traction-free r sides ------------------------------------------------------
+
+FREE_CASES = [("ring", 70, 21, (0, 0, 1, 1)), ("ring", 130, 16, (0, 0, 0, 1)), ("warped", 63, 17, (0, 0, 1, 0)),
+              ("quarter", 40, 33, (0, 0, 1, 1)), ("ring", 5, 2, (0, 0, 1, 1))]
+
+
+def _grid_bc(kind, nq, nr, seed=0):
+    if kind == "ring":
+        return inputs.ring_grid(nq, nr)
+    return _grid(kind, nq, nr, seed)
+
+
+@pytest.mark.parametrize("kind,nq,nr,bc", FREE_CASES)
+@pytest.mark.parametrize("force", [False, True])
+def test_mapped_free_sides_filter_fp64(E, kind, nq, nr, bc, force):
+    _say("mapped free filter fp64", kind, nq, nr, bc, force)
+    x, y = _grid_bc(kind, nq, nr, seed=nq)
+    rho, lam, mu = inputs.media_mapped(x, y, seed=nq + 2 * nr)
+    om = 6.3
+    op = MappedOperator(x, y, rho, lam, mu, bc=bc)
+    wh = S.WaveHoltz(op, om)
+    prob = op.prob
+    rng = np.random.default_rng(17)
+    mask = prob.unknown_mask()
+    u0 = rng.standard_normal(prob.field_shape) * mask
+    f = rng.standard_normal(prob.field_shape) * mask if force else None
+    ref = prob.scatter(wh.apply_filter(prob.gather(u0), prob.gather(f) if force else None))
+    refA = prob.scatter(wh.apply_A(prob.gather(u0)))
+    ctx = E.MappedContext(x, y, rho, lam, mu, om, bc=bc)
+    assert ctx.info()["nt"] == wh.nt
+    for V, TY in ((1, 8), (1, 16), (2, 8), (2, 16)):
+        ctx.set_tile(0, V, TY)
+        got = ctx.apply_filter(u0, f).cpu().numpy()
+        assert _rel(got, ref) <= FP64_TOL, (V, TY)
+        assert _rel(ctx.apply_A(u0).cpu().numpy(), refA) <= FP64_TOL, (V, TY)
+    a = rng.standard_normal(prob.field_shape) * mask
+    assert ctx.dot_M(a, u0) == pytest.approx(float(np.dot(op.m * prob.gather(a), prob.gather(u0))), rel=1e-13)
+
+
+def test_mapped_free_sides_fp32(E):
+    x, y = inputs.ring_grid(150, 50)
+    rho, lam, mu = inputs.media_mapped(x, y, seed=31)
+    bc = (0, 0, 1, 1)
+    om = 8.0
+    op = MappedOperator(x, y, rho, lam, mu, bc=bc)
+    wh = S.WaveHoltz(op, om)
+    prob = op.prob
+    rng = np.random.default_rng(32)
+    u0 = rng.standard_normal(prob.field_shape) * prob.unknown_mask()
+    f = rng.standard_normal(prob.field_shape) * prob.unknown_mask()
+    ref = prob.scatter(wh.apply_filter(prob.gather(u0), prob.gather(f)))
+    for comp in (1, 0):
+        ctx = E.MappedContext(x, y, rho, lam, mu, om, bc=bc, prec=E.FP32_STEP, compensated=comp)
+        err = _rel(ctx.apply_filter(u0, f).cpu().numpy(), ref)
+        _say("mapped free fp32 compensated", comp, "nt", wh.nt, "err", err, "bound", fp32_bound(wh.nt))
+        assert err <= fp32_bound(wh.nt)
+
+
+def test_ring_sector_with_free_arcs_cr_matches_oracle(E):
+    """A 2-D analogue of the toroidal shell of Sec. 5.9: the ring sector
+    1 <= radius <= 2, 0 <= angle <= pi with traction-free inner and outer arcs
+    and Dirichlet cuts, the paper's forcing form (sqrt(sigma^3)/20) (1, 1)
+    exp(-zeta^2), sigma = 100 omega, at omega = 5.1234, conjugate residual to
+    1e-5 as in that experiment: the library's count equals the oracle's (+-1)
+    and its iterate matches."""
+    w = 5.1234
+    x, y = inputs.ring_grid(120, 40)
+    one = np.ones(x.shape)
+    rho, lam, mu = one, 2 * one, one
+    bc = (0, 0, 1, 1)
+    op = MappedOperator(x, y, rho, lam, mu, bc=bc)
+    wh = S.WaveHoltz(op, w)
+    prob = op.prob
+    sigma = 100 * w
+    zeta2 = 0.5 * sigma * ((x + 0.4) ** 2 + (y - 1.3) ** 2)
+    amp = math.sqrt(sigma ** 3) / 20 * np.exp(-zeta2)
+    f = np.stack([amp, amp]) * prob.unknown_mask()
+    res = krylov.cr(wh.apply_A, wh.rhs(prob.gather(f)), op.m, tol=1e-5, maxit=5000)
+    ctx = E.MappedContext(x, y, rho, lam, mu, w, bc=bc, krylov=2)
+    v, info = ctx.solve(f, tol=1e-5, maxit=5000)
+    _say("ring with free arcs, CR: iters", info["iters"], "oracle", res.iters, "nt", wh.nt)
+    assert res.converged and abs(info["iters"] - res.iters) <= 1
+    assert _rel(prob.gather(v.cpu().numpy()), res.x) <= 1e-4
+    # CG to 1e-10 reaches the direct solution
+    ctx_cg = E.MappedContext(x, y, rho, lam, mu, w, bc=bc)
+    v2, info2 = ctx_cg.solve(f, tol=1e-10, maxit=5000)
+    vstar = direct.solve(op, w, prob.gather(f))
+    _say("ring with free arcs, CG: iters", info2["iters"], "cr", info2.get("cr_iters"))
+    assert _rel(prob.gather(v2.cpu().numpy()), vstar) <= 1e-7
