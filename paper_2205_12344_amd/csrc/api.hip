@@ -1079,8 +1079,8 @@ elwh_status elwh_set_tile(elwh_ctx* c, int prec, int vec, int rows) {
 }  // extern "C"
 
 namespace {
-// dim, prec, variant (bit 0: compensated accumulator, bit 1: 2-D step pairs,
-// bit 2: mapped grid), nx, ny, nz
+// dim, prec, variant (bit 0: compensated accumulator, bits 1-2: steps per
+// 2-D launch minus one, bit 3: mapped grid), nx, ny, nz
 using TuneKey = std::tuple<int, int, int, int, int, int>;
 std::mutex g_tune_mu;
 std::map<TuneKey, Tile> g_tune;
@@ -1104,7 +1104,7 @@ bool file_lookup(const TuneKey& k, const std::string& arch, Tile* t) {
     while (std::fgets(line, sizeof line, fp)) {
         int dim, prec, comp, nx, ny, nz, V, rows;
         double us;
-        if (std::sscanf(line, "{\"arch\": \"%63[^\"]\", \"dim\": %d, \"prec\": %d, \"comp\": %d, \"n\": [%d, %d, %d], "
+        if (std::sscanf(line, "{\"arch\": \"%63[^\"]\", \"dim\": %d, \"prec\": %d, \"variant\": %d, \"n\": [%d, %d, %d], "
                               "\"V\": %d, \"rows\": %d, \"us\": %lf}",
                         a, &dim, &prec, &comp, &nx, &ny, &nz, &V, &rows, &us) == 10 &&
             arch == a && k == TuneKey(dim, prec, comp, nx, ny, nz)) {
@@ -1123,7 +1123,7 @@ void file_store(const TuneKey& k, const std::string& arch, const Tile& t, double
     FILE* fp = std::fopen(path, "a");
     if (!fp) return;
     std::fprintf(fp,
-                 "{\"arch\": \"%s\", \"dim\": %d, \"prec\": %d, \"comp\": %d, \"n\": [%d, %d, %d], \"V\": %d, "
+                 "{\"arch\": \"%s\", \"dim\": %d, \"prec\": %d, \"variant\": %d, \"n\": [%d, %d, %d], \"V\": %d, "
                  "\"rows\": %d, \"us\": %.3f}\n",
                  arch.c_str(), std::get<0>(k), std::get<1>(k), std::get<2>(k), std::get<3>(k), std::get<4>(k),
                  std::get<5>(k), t.V, t.TY, us);
@@ -1140,8 +1140,8 @@ elwh_status elwh_autotune(elwh_ctx* c, int prec, int reps, double* best_step_us)
         c->err = "FP32 tiling needs an FP32 context";
         return ELWH_ERR_ARG;
     }
-    const int comp = (fp32 && c->opts.compensated ? 1 : 0) |
-                     (c->L.dim == 2 && !c->mapped && c->opts.fuse == 2 ? 2 : 0) | (c->mapped ? 4 : 0);
+    const int steps = c->L.dim == 2 && !c->mapped ? c->opts.fuse : 1;
+    const int comp = (fp32 && c->opts.compensated ? 1 : 0) | ((steps - 1) << 1) | (c->mapped ? 8 : 0);
     const TuneKey key(c->L.dim, fp32 ? 1 : 0, comp, c->L.nx, c->L.ny, c->L.nz);
     Tile& dst = fp32 ? c->tile32 : c->tile64;
     {

@@ -456,6 +456,16 @@ def test_autotune_choice_is_valid_and_cached(E):
     assert ctx.autotune(0) == -1.0          # cached per process
 
 
+def test_autotune_cache_keeps_steps_per_launch_apart(E):
+    """The tile cache is keyed by the steps per launch: a K = 3 context does
+    not inherit the tile timed for single-step launches of the same grid."""
+    c = inputs.random_problem_2d(200, 30.0, seed=41)
+    E.context_from_case(c, fuse=1)                 # tunes and caches the K = 1 tile
+    ctx3 = E.context_from_case(c, fuse=3, autotune=0)
+    assert ctx3.autotune(0, reps=1) > 0.0           # not a cache hit: timed afresh
+    assert ctx3.autotune(0) == -1.0
+
+
 @pytest.mark.parametrize("K", [1, 2, 5])
 def test_k_period_solve_matches_oracle(E, K):
     """K-period filter (eq. many_periods_filter) inside CG on the FD bar of
