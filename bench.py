@@ -15,7 +15,7 @@ timed steps), the FP32-stepping and single-step variants, the step kernel
 of mapped (curvilinear) grids on an annular sector, and the CPU oracle's
 rate on a bounded sample.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--all] [--mapped-only]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-3d] [--mapped-only]
 """
 
 import argparse
@@ -278,7 +278,7 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--all", action="store_true", help="also measure the 3-D 256^3 workload")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3-D 256^3 (config 3) step-kernel measurement")
     ap.add_argument("--no-extra", action="store_true", help="skip the time-to-1e-8 (config 5) measurement")
     ap.add_argument("--batch", action="store_true",
                     help="also solve the config-4 batch (48 problems) in FP32 and FP64 (several minutes)")
@@ -374,7 +374,7 @@ def main():
     for tag, v in mapped_rates(elwh, inputs).items():
         variants["mapped_" + tag] = v
 
-    if args.all:
+    if not args.no_3d:
         c3 = inputs.config3()
         n3 = unknown_nodes(c3)
         for tag, kw in (("f64", {}), ("f32c", {"prec": elwh.FP32_STEP, "compensated": 1})):
