@@ -236,3 +236,32 @@ def test_filter_diagnostics_reject_bad_input(elwh):
     for args in ((2, 1, 1.0, 0), (10, 0, 1.0, 0), (10, 1, -1.0, 0), (10, 1, 1.0, 7)):
         with pytest.raises(elwh.ElwhError, match="ERR_ARG"):
             elwh.filter_diagnostics(*args)
+
+
+@pytest.mark.parametrize("seed,indefinite", [(4115, True), (4099, False), (4096, False)])
+def test_filter_diagnostics_explain_the_cg_breakdown(elwh, seed, indefinite):
+    """The band the diagnostics report holds a medium eigenvalue exactly when
+    A_h is indefinite: on the config-5 problem (64^2) where CG breaks down
+    (seed 4115, tests/test_oracle_krylov_limits.py) one eigenvalue lambda_j
+    of -L_h phi = lambda^2 M phi (shift-invert near omega^2) lies in
+    [lambda_lo, lambda_hi] and the oracle's 1 - beta_h(theta_j) is negative
+    there; on two problems where CG converges none does and every nearby
+    eigenvalue of A_h is positive."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spl
+    from oracle import spectral
+    from oracle.stepping import WaveHoltz, filter_weights
+    from paper_2205_12344_amd import inputs
+    c = inputs.config5_problem(seed, n=64)
+    prob = Problem(2, c.n, bc=c.bc)
+    op = Operator(prob, c.rho, c.lam, c.mu)
+    wh = WaveHoltz(op, c.omega)
+    vals = spl.eigsh(-op.Lh.tocsc(), k=8, M=sp.diags(op.m).tocsc(), sigma=c.omega ** 2, which="LM",
+                     return_eigenvectors=False)
+    lam = np.sqrt(np.sort(vals))
+    d = elwh.filter_diagnostics(wh.nt, 1, c.omega, 0)
+    w, _ = filter_weights(wh.nt)
+    eig_A = 1.0 - spectral.beta_h(spectral.mode_angle(lam, c.omega, wh.dt), w)
+    inband = (lam >= d["lambda_lo"]) & (lam <= d["lambda_hi"])
+    assert np.all((eig_A < 0) == inband)
+    assert bool(inband.any()) == indefinite
