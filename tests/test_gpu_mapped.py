@@ -307,3 +307,44 @@ def test_ring_sector_with_free_arcs_cr_matches_oracle(E):
     vstar = direct.solve(op, w, prob.gather(f))
     _say("ring with free arcs, CG: iters", info2["iters"], "cr", info2.get("cr_iters"))
     assert _rel(prob.gather(v2.cpu().numpy()), vstar) <= 1e-7
+
+
+def test_mapped_fp32_solve_reaches_fp64_residual(E):
+    """FP32 stepping on a mapped grid: CG with FP32 applications and FP64
+    residual replacement reaches an FP64-recomputed residual of 1e-10 and the
+    direct solution."""
+    x, y = inputs.ring_grid(90, 30)
+    rho, lam, mu = inputs.media_mapped(x, y, seed=51)
+    bc = (0, 0, 1, 1)
+    om = 4.3
+    op = MappedOperator(x, y, rho, lam, mu, bc=bc)
+    prob = op.prob
+    f = np.zeros(prob.field_shape)
+    f[0, 15, 40] = 1.0 / (op.J[15, 40] / (90 * 30))
+    vstar = direct.solve(op, om, prob.gather(f))
+    ctx64 = E.MappedContext(x, y, rho, lam, mu, om, bc=bc)
+    _, i64 = ctx64.solve(f, tol=1e-10, maxit=4000)
+    ctx = E.MappedContext(x, y, rho, lam, mu, om, bc=bc, prec=E.FP32_STEP)
+    v, info = ctx.solve(f, tol=1e-10, maxit=4000)
+    _say("mapped fp32 solve", info, "fp64 iters", i64["iters"])
+    assert info["relres_fp64"] <= 1.1e-10
+    assert _rel(prob.gather(v.cpu().numpy()), vstar) <= 1e-7
+    assert info["iters"] <= 3.5 * i64["iters"] + 10
+
+
+@pytest.mark.parametrize("K", [1, 3])
+def test_mapped_k_period_cg_matches_oracle(E, K):
+    x, y = _grid("half", 20, 60)
+    rho, lam, mu = inputs.media_mapped(x, y, seed=52)
+    om = 3.7
+    op = MappedOperator(x, y, rho, lam, mu)
+    wh = S.WaveHoltz(op, om, periods=K)
+    prob = op.prob
+    f = np.zeros(prob.field_shape)
+    f[1, 30, 10] = 1.0 / (op.J[30, 10] / (20 * 60))
+    res = krylov.cg(wh.apply_A, wh.rhs(prob.gather(f)), op.m, tol=1e-10, maxit=3000)
+    ctx = E.MappedContext(x, y, rho, lam, mu, om, periods=K)
+    v, info = ctx.solve(f, tol=1e-10, maxit=3000)
+    _say("mapped K-period CG", K, "iters", info["iters"], "oracle", res.iters)
+    assert abs(info["iters"] - res.iters) <= 1
+    assert _rel(prob.gather(v.cpu().numpy()), res.x) <= 1e-8
