@@ -42,10 +42,14 @@ struct elwh_batch {
     bool use_graph = true;
     Tile tile[2];                   // [0] FP64, [1] FP32
     std::vector<BProb2D> h_pr;
+    std::vector<int> full_blk, full_blk2;   // tiles of each problem in the two tilings of the phase
     BProb2D* d_pr = nullptr;
     std::vector<BState> h_st;
     BState* d_st = nullptr;
     int* d_mask = nullptr;
+    int* d_plist = nullptr;         // problems the CG kernels of a tick visit (the live ones)
+    int nplist = 0;
+    int gnplist[2] = {0, 0};
     int* d_active = nullptr;
     int* h_active = nullptr;        // pinned
     double* d_partials = nullptr;
@@ -126,8 +130,48 @@ elwh_status set_phase(elwh_batch* b, bool fp32, int isrc, int iout, int ix, int 
     }
     *nblocks = off;
     if (nblocks2) *nblocks2 = off2;
+    b->full_blk.resize(b->np);
+    b->full_blk2.resize(b->np);
+    for (int p = 0; p < b->np; ++p) {
+        b->full_blk[p] = b->h_pr[p].nblk;
+        b->full_blk2[p] = b->h_pr[p].nblk2;
+    }
     BCK(hipMemcpyAsync(b->d_pr, b->h_pr.data(), sizeof(BProb2D) * b->np, hipMemcpyHostToDevice, b->stream));
     BCK(hipStreamSynchronize(b->stream));   // h_pr is rewritten by the next phase
+    return ELWH_OK;
+}
+
+// The problems still active (h_st) as the device list the CG kernels visit.
+elwh_status list_active(elwh_batch* b) {
+    std::vector<int> pl;
+    for (int p = 0; p < b->np; ++p)
+        if (b->h_st[p].active) pl.push_back(p);
+    b->nplist = (int)pl.size();
+    if (!pl.empty())
+        BCK(hipMemcpyAsync(b->d_plist, pl.data(), sizeof(int) * pl.size(), hipMemcpyHostToDevice, b->stream));
+    BCK(hipStreamSynchronize(b->stream));
+    return ELWH_OK;
+}
+
+// Keep the tiles of the problems still active (h_st) and give the others
+// none, so the step launches of the remaining ticks cover only live
+// problems; the launch sizes shrink with the active set.
+elwh_status retile_active(elwh_batch* b, int* nblocks, int* nblocks2) {
+    int off = 0, off2 = 0;
+    for (int p = 0; p < b->np; ++p) {
+        BProb2D& q = b->h_pr[p];
+        const bool live = b->h_st[p].active != 0;
+        q.off = off;
+        q.nblk = live ? b->full_blk[p] : 0;
+        off += q.nblk;
+        q.off2 = off2;
+        q.nblk2 = live ? b->full_blk2[p] : 0;
+        off2 += q.nblk2;
+    }
+    *nblocks = off;
+    *nblocks2 = off2;
+    BCK(hipMemcpyAsync(b->d_pr, b->h_pr.data(), sizeof(BProb2D) * b->np, hipMemcpyHostToDevice, b->stream));
+    BCK(hipStreamSynchronize(b->stream));
     return ELWH_OK;
 }
 
@@ -271,15 +315,16 @@ void enqueue_ticks(elwh_batch* b, bool fp32, int nblocks, int nblocks2, int ntic
         if (fuse2)
             launch_batch_multi(fp32, t.V, t.TY, false, comp, nblocks2, b->stream, b->d_pr, b->d_st, b->np, -1.0, 1);
         launch_batch_advance(b->stream, b->d_pr, b->d_st, b->np, 0, fuse2, fp32 ? 1 : 0);
-        launch_batch_cg(b->stream, 0, b->d_pr, b->d_st, b->np, b->d_partials, b->d_active);
-        launch_batch_cg(b->stream, 1, b->d_pr, b->d_st, b->np, b->d_partials, b->d_active);
-        launch_batch_cg(b->stream, 2, b->d_pr, b->d_st, b->np, b->d_partials, b->d_active);
+        for (int mode = 0; mode < 3; ++mode)
+            launch_batch_cg(b->stream, mode, b->d_pr, b->d_st, b->np, b->d_plist, b->nplist, b->d_partials,
+                            b->d_active);
     }
 }
 
 elwh_status graph_for(elwh_batch* b, bool fp32, int nblocks, int nblocks2) {
     const int k = fp32 ? 1 : 0;
-    if (b->gexec[k] && b->gblocks[k] == nblocks && b->gblocks2[k] == nblocks2) return ELWH_OK;
+    if (b->gexec[k] && b->gblocks[k] == nblocks && b->gblocks2[k] == nblocks2 && b->gnplist[k] == b->nplist)
+        return ELWH_OK;
     if (b->gexec[k]) {
         (void)hipGraphExecDestroy(b->gexec[k]);
         b->gexec[k] = nullptr;
@@ -297,6 +342,7 @@ elwh_status graph_for(elwh_batch* b, bool fp32, int nblocks, int nblocks2) {
     }
     b->gblocks[k] = nblocks;
     b->gblocks2[k] = nblocks2;
+    b->gnplist[k] = b->nplist;
     return ELWH_OK;
 }
 
@@ -312,6 +358,7 @@ elwh_status run_cg(elwh_batch* b, bool fp32, int ix, int ir, int ip, int iq, lon
         nact += s.active;
     }
     BST(upload_states(b));
+    BST(list_active(b));
     *b->h_active = nact;
     BCK(hipMemcpyAsync(b->d_active, b->h_active, sizeof(int), hipMemcpyHostToDevice, b->stream));
     BCK(hipStreamSynchronize(b->stream));
@@ -324,6 +371,7 @@ elwh_status run_cg(elwh_batch* b, bool fp32, int ix, int ir, int ip, int iq, lon
         return e && e[0] == '1';
     }();
     auto last = std::chrono::steady_clock::now();
+    int live = nact;
     while (true) {
         if (b->use_graph) {
             BCK(hipGraphLaunch(b->gexec[fp32 ? 1 : 0], b->stream));
@@ -335,6 +383,15 @@ elwh_status run_cg(elwh_batch* b, bool fp32, int ix, int ir, int ip, int iq, lon
         BCK(hipMemcpyAsync(b->h_active, b->d_active, sizeof(int), hipMemcpyDeviceToHost, b->stream));
         BCK(hipStreamSynchronize(b->stream));
         if (*b->h_active <= 0) break;
+        if (*b->h_active < live) {
+            // problems finished: drop their tiles from the launches (and
+            // re-capture the graph for the smaller grids)
+            live = *b->h_active;
+            BST(download_states(b));
+            BST(retile_active(b, &nblocks, &nblocks2));
+            BST(list_active(b));
+            if (b->use_graph) BST(graph_for(b, fp32, nblocks, nblocks2));
+        }
         if (progress && std::chrono::steady_clock::now() - last > std::chrono::seconds(10)) {
             last = std::chrono::steady_clock::now();
             std::fprintf(stderr, "[elwh batch] %s CG: %lld ticks, %d of %d problems active\n", fp32 ? "FP32" : "FP64",
@@ -356,7 +413,7 @@ void free_batch(elwh_batch* b) {
     auto f = [](void* p) {
         if (p) (void)hipFree(p);
     };
-    f(b->d_pr); f(b->d_st); f(b->d_mask); f(b->d_active); f(b->d_partials); f(b->d_dots);
+    f(b->d_pr); f(b->d_st); f(b->d_mask); f(b->d_plist); f(b->d_active); f(b->d_partials); f(b->d_dots);
     if (b->h_active) (void)hipHostFree(b->h_active);
     if (b->h_dots) (void)hipHostFree(b->h_dots);
     for (auto& g : b->gexec)
@@ -441,6 +498,7 @@ elwh_status elwh_batch_create(int nprob, const elwh_grid* grids, const double* c
     bool ok = dalloc(reinterpret_cast<void**>(&b->d_pr), sizeof(BProb2D) * nprob) &&
               dalloc(reinterpret_cast<void**>(&b->d_st), sizeof(BState) * nprob) &&
               dalloc(reinterpret_cast<void**>(&b->d_mask), sizeof(int) * nprob) &&
+              dalloc(reinterpret_cast<void**>(&b->d_plist), sizeof(int) * nprob) &&
               dalloc(reinterpret_cast<void**>(&b->d_active), sizeof(int)) &&
               dalloc(reinterpret_cast<void**>(&b->d_partials), 2 * sizeof(double) * nprob * BATCH_RED_BLOCKS) &&
               dalloc(reinterpret_cast<void**>(&b->d_dots), sizeof(double) * nprob) &&

@@ -375,12 +375,17 @@ constexpr int BRB = 64;   // reduction blocks per problem
 
 // mode 0: partials (p, q)_M (partials[p BRB + k]) and (p, p)_M (partials[(np + p) BRB + k]);
 // mode 1: x += alpha p, r -= alpha q, partial (r, r)_M; mode 2: p = r + beta p.
-// Only problems that finished an application this tick.
+// Only problems that finished an application this tick.  BRB blocks per
+// listed problem: block b works for problem plist[b / BRB] (the problems
+// still active when the launch was set up; nplist of them).
 template <int MODE>
 __global__ __launch_bounds__(256) void batch_cg_kernel(const BProb2D* __restrict__ pr, const BState* __restrict__ st,
-                                                       int np, double* __restrict__ partials) {
-    const int p = (int)blockIdx.x / BRB, k = (int)blockIdx.x % BRB;
-    if (p >= np || !st[p].active || !st[p].end) return;
+                                                       int np, const int* __restrict__ plist, int nplist,
+                                                       double* __restrict__ partials) {
+    const int slot = (int)blockIdx.x / BRB, k = (int)blockIdx.x % BRB;
+    if (slot >= nplist) return;
+    const int p = plist[slot];
+    if (p < 0 || p >= np || !st[p].active || !st[p].end) return;
     const BProb2D& q = pr[p];
     const int64_t CS = q.A.CS;
     double s = 0.0, s2 = 0.0;
@@ -430,10 +435,12 @@ __global__ __launch_bounds__(256) void batch_cg_kernel(const BProb2D* __restrict
 // mode 1: rr, beta, iteration count and the stopping tests.
 template <int MODE>
 __global__ __launch_bounds__(64) void batch_cg_final_kernel(BState* __restrict__ st, int np,
+                                                            const int* __restrict__ plist, int nplist,
                                                             const double* __restrict__ partials,
                                                             int* __restrict__ n_active) {
-    const int p = (int)blockIdx.x;
-    if (p >= np || !st[p].active || !st[p].end) return;
+    if ((int)blockIdx.x >= nplist) return;
+    const int p = plist[blockIdx.x];
+    if (p < 0 || p >= np || !st[p].active || !st[p].end) return;
     double s = partials[p * BRB + threadIdx.x];   // BRB == 64 == blockDim
     double s2 = MODE == 0 ? partials[(np + p) * BRB + threadIdx.x] : 0.0;
 #pragma unroll
@@ -568,17 +575,20 @@ void launch_batch_advance(hipStream_t s, const BProb2D* pr, BState* st, int np, 
     hipLaunchKernelGGL(batch_advance_kernel, dim3((np + 63) / 64), dim3(64), 0, s, pr, st, np, single, fuse2, fp32);
 }
 
-void launch_batch_cg(hipStream_t s, int mode, const BProb2D* pr, BState* st, int np, double* partials,
-                     int* n_active) {
-    const dim3 g((unsigned)(np * BRB));
+void launch_batch_cg(hipStream_t s, int mode, const BProb2D* pr, BState* st, int np, const int* plist, int nplist,
+                     double* partials, int* n_active) {
+    if (nplist < 1) return;
+    const dim3 g((unsigned)(nplist * BRB));
     if (mode == 0) {
-        hipLaunchKernelGGL(batch_cg_kernel<0>, g, dim3(256), 0, s, pr, st, np, partials);
-        hipLaunchKernelGGL(batch_cg_final_kernel<0>, dim3(np), dim3(64), 0, s, st, np, partials, n_active);
+        hipLaunchKernelGGL(batch_cg_kernel<0>, g, dim3(256), 0, s, pr, st, np, plist, nplist, partials);
+        hipLaunchKernelGGL(batch_cg_final_kernel<0>, dim3(nplist), dim3(64), 0, s, st, np, plist, nplist, partials,
+                           n_active);
     } else if (mode == 1) {
-        hipLaunchKernelGGL(batch_cg_kernel<1>, g, dim3(256), 0, s, pr, st, np, partials);
-        hipLaunchKernelGGL(batch_cg_final_kernel<1>, dim3(np), dim3(64), 0, s, st, np, partials, n_active);
+        hipLaunchKernelGGL(batch_cg_kernel<1>, g, dim3(256), 0, s, pr, st, np, plist, nplist, partials);
+        hipLaunchKernelGGL(batch_cg_final_kernel<1>, dim3(nplist), dim3(64), 0, s, st, np, plist, nplist, partials,
+                           n_active);
     } else {
-        hipLaunchKernelGGL(batch_cg_kernel<2>, g, dim3(256), 0, s, pr, st, np, partials);
+        hipLaunchKernelGGL(batch_cg_kernel<2>, g, dim3(256), 0, s, pr, st, np, plist, nplist, partials);
     }
 }
 
