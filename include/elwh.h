@@ -99,6 +99,11 @@ typedef struct {
                           with the conjugate residual method in FP64 (the
                           MINRES-type remedy the remark recommends); 0 = return
                           ELWH_ERR_BREAKDOWN */
+    int fp64_fallback; /* FP32 path: 1 (default) = when the FP64-recomputed
+                          residual has not halved over the last two segments
+                          (FP32 applications no longer improve x), finish with
+                          FP64 CG from the current iterate (info.fp64_iters);
+                          0 = stay with FP32 applications until maxit */
 } elwh_opts;
 
 typedef struct {
@@ -113,6 +118,8 @@ typedef struct {
     double relres_fp64; /* final ||b - A_h v||_M / ||b||_M recomputed with an FP64 apply */
     double cond_est;    /* Lanczos condition estimate from the CG coefficients (CG only) */
     int cr_iters;       /* conjugate-residual iterations after a CG breakdown (cr_fallback), else 0 */
+    int fp64_iters;     /* FP32 path: FP64 CG iterations after a stagnation (fp64_fallback), else 0;
+                           included in iters */
 } elwh_info;
 
 /* Fill *opts with the defaults listed above.  Never fails. */

@@ -713,6 +713,7 @@ void elwh_default_opts(elwh_opts* o) {
     o->fuse = 2;
     o->scale_x0 = 0;
     o->cr_fallback = 1;
+    o->fp64_fallback = 1;
 }
 
 elwh_status elwh_plan(const elwh_grid* grid, const double* rho, const double* lam, const double* mu, double omega,
@@ -978,6 +979,9 @@ elwh_status elwh_solve(elwh_ctx* c, const double* f, const double* x0, double to
         double relfp64 = std::sqrt(rr / bb), seg = rr;
         inf.relres = relfp64;
         int outer = 0, iters = 0;
+        std::vector<double> hist{relfp64};   // FP64 residual after each segment
+        bool stagnated = false;
+        int longest = 0;                      // iterations of the longest segment so far
         st = ELWH_ERR_NOT_CONVERGED;
         while (true) {
             if (tol > 0 && relfp64 <= tol) {
@@ -990,8 +994,13 @@ elwh_status elwh_solve(elwh_ctx* c, const double* f, const double* x0, double to
             }
             // stop the segment at rr <= max(inner_tol^2 seg, (tol/2)^2 bb)
             const double tseg = std::max(c->opts.inner_tol, tol > 0 ? 0.5 * tol * std::sqrt(bb / seg) : 0.0);
+            // with the fallback on, a segment may take at most twice the
+            // iterations of the longest earlier one (at least 64)
+            int budget = maxit - iters;
+            const bool capped = c->opts.fp64_fallback && tol > 0 && outer > 0 && budget > std::max(64, 2 * longest);
+            if (capped) budget = std::max(64, 2 * longest);
             CGOut o;
-            elwh_status si = cg_steps(c, c->vec[VX], c->vec[VR], c->vec[VP], c->vec[VQ], true, seg, maxit - iters,
+            elwh_status si = cg_steps(c, c->vec[VX], c->vec[VR], c->vec[VP], c->vec[VQ], true, seg, budget,
                                       tseg, &o, false);
             if (si == ELWH_ERR_BREAKDOWN && c->opts.cr_fallback) {
                 // conjugate residual in FP64 from the current iterate
@@ -1009,16 +1018,49 @@ elwh_status elwh_solve(elwh_ctx* c, const double* f, const double* x0, double to
             if (si != ELWH_OK) return si;
             iters += o.iters;
             ++outer;
+            longest = std::max(longest, o.iters);
             const double rr_new = c->hscal[S_RR], beta_k = c->hscal[S_BETA];
             inf.relres = std::sqrt(rr_new / bb);
             const double rr_k = beta_k > 0 ? rr_new / beta_k : 0.0;
             CKST(true_residual(false, &rr, false));
             relfp64 = std::sqrt(rr / bb);
             seg = rr;
+            hist.push_back(relfp64);
+            if (c->opts.fp64_fallback && tol > 0 && relfp64 > tol && iters < maxit &&
+                ((capped && !o.converged) || (hist.size() >= 3 && relfp64 > 0.5 * hist[hist.size() - 3]))) {
+                stagnated = true;   // a segment over its cap, or less than a halving over two segments
+                break;
+            }
             if (!o.converged) continue;   // out of iterations: the loop head ends it
             CKST(set_scalar(c, S_BETA, rr_k > 0 ? rr / rr_k : 0.0));
             CKST(set_scalar(c, S_RR, rr));
             launch_cg_update_p(c, c->vec[VP], c->vec[VR], c->stream);
+        }
+        if (stagnated) {
+            // FP32 applications no longer improve x: FP64 CG from x (r = b - A_h x)
+            const int keep = c->opts.scale_x0;
+            c->opts.scale_x0 = 0;
+            double bb2 = 0, rr2 = 0;
+            const elwh_status s0 = cg_start(c, c->vec[VB], c->vec[VX], false, c->vec[VR], c->vec[VP], c->vec[VQ],
+                                            false, &bb2, &rr2);
+            c->opts.scale_x0 = keep;
+            CKST(s0);
+            c->cg_qready = false;
+            CGOut o2;
+            st = cg_steps_pipelined(c, c->vec[VX], c->vec[VR], c->vec[VP], c->vec[VQ], bb2, maxit - iters, tol, &o2);
+            inf.fp64_iters = o2.iters;
+            iters += o2.iters;
+            inf.relres = o2.relres;
+            if (st == ELWH_ERR_BREAKDOWN && c->opts.cr_fallback) {
+                int it = 0;
+                double relcr = 1.0;
+                st = solve_cr(c, false, tol, std::max(1, maxit - iters), &it, &relcr);
+                inf.cr_iters = it;
+                inf.relres = relcr;
+            }
+            if (st != ELWH_OK && st != ELWH_ERR_NOT_CONVERGED) return st;
+            CKST(final_residual(c, c->vec[VX], bb, &relfp64));
+            st = relfp64 <= tol ? ELWH_OK : ELWH_ERR_NOT_CONVERGED;
         }
         inf.iters = iters;
         inf.outer = outer;

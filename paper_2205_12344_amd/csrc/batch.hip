@@ -601,7 +601,8 @@ elwh_status elwh_batch_solve(elwh_batch* b, const double* const* f, const double
     BST(run_apply(b, false, true, false, VT, VB, all));
     std::vector<double> bb, rr;
     BST(dots(b, all, VB, VB, bb));
-    std::vector<int> iters(np, 0), outer(np, 0), status(np, ELWH_ERR_NOT_CONVERGED), cr_iters(np, 0);
+    std::vector<int> iters(np, 0), outer(np, 0), status(np, ELWH_ERR_NOT_CONVERGED), cr_iters(np, 0),
+        fp64_iters(np, 0);
     std::vector<double> relres(np, 1.0), relfp64(np, 1.0);
     std::vector<int> has_x(np, 0);
     for (int p = 0; p < np; ++p) has_x[p] = (x0 && x0[p]) ? 1 : 0;
@@ -667,10 +668,12 @@ elwh_status elwh_batch_solve(elwh_batch* b, const double* const* f, const double
         BST(lincomb(b, all, VP, VR, 1.0, -1, 0.0));
         BST(dots(b, all, VR, VR, rr));
         std::vector<double> seg = rr, rr_k(np, 0.0), beta(np, 0.0);
-        std::vector<int> done_p(np, 0);
+        std::vector<int> done_p(np, 0), stag(np, 0), longest(np, 0), capped(np, 0);
+        std::vector<std::vector<double>> hist(np);   // FP64 residual after each segment
         for (int p = 0; p < np; ++p) {
             relfp64[p] = bb[p] > 0 ? std::sqrt(rr[p] / bb[p]) : 0.0;
             relres[p] = relfp64[p];
+            hist[p].push_back(relfp64[p]);
         }
         for (int o = 0;; ++o) {
             std::vector<int> pending(np, 0);
@@ -683,6 +686,10 @@ elwh_status elwh_batch_solve(elwh_batch* b, const double* const* f, const double
                     status[p] = ELWH_ERR_UNSTABLE;
                 } else if (iters[p] >= maxit || o > b->opts.max_outer) {
                     status[p] = tol > 0 ? ELWH_ERR_NOT_CONVERGED : ELWH_OK;
+                    done_p[p] = 1;
+                } else if (b->opts.fp64_fallback && tol > 0 &&
+                           (stag[p] == 2 || (hist[p].size() >= 3 && relfp64[p] > 0.5 * hist[p][hist[p].size() - 3]))) {
+                    stag[p] = 1;   // a segment over its cap, or less than a halving over two segments: FP64 below
                     done_p[p] = 1;
                 } else {
                     pending[p] = 1;
@@ -699,6 +706,11 @@ elwh_status elwh_batch_solve(elwh_batch* b, const double* const* f, const double
                 const double stop = tol > 0 ? 0.25 * tol * tol * bb[p] : 0.0;
                 s.tol2 = std::max(b->opts.inner_tol * b->opts.inner_tol * seg[p], stop);
                 s.maxit = std::max(1, maxit - iters[p]);
+                // with the fallback on, a segment may take at most twice the
+                // iterations of the longest earlier one (at least 64)
+                const int cap = std::max(64, 2 * longest[p]);
+                capped[p] = b->opts.fp64_fallback && tol > 0 && o > 0 && s.maxit > cap;
+                if (capped[p]) s.maxit = cap;
                 s.status = ELWH_ERR_NOT_CONVERGED;
             }
             BST(run_cg(b, true, VX, VR, VP, VQ, tick_budget));
@@ -707,6 +719,8 @@ elwh_status elwh_batch_solve(elwh_batch* b, const double* const* f, const double
                 const BState& s = b->h_st[p];
                 iters[p] += s.iters;
                 outer[p] = o + 1;
+                longest[p] = std::max(longest[p], s.iters);
+                if (capped[p] && s.status == ELWH_ERR_NOT_CONVERGED) stag[p] = 2;   // segment over its cap
                 relres[p] = std::sqrt(s.rr / bb[p]);
                 rr_k[p] = s.beta > 0 ? s.rr / s.beta : 0.0;
                 if (s.status == ELWH_ERR_BREAKDOWN || s.status == ELWH_ERR_UNSTABLE) {
@@ -723,8 +737,46 @@ elwh_status elwh_batch_solve(elwh_batch* b, const double* const* f, const double
                 relfp64[p] = std::sqrt(rr[p] / bb[p]);
                 seg[p] = rr[p];
                 beta[p] = rr_k[p] > 0 ? rr[p] / rr_k[p] : 0.0;
+                hist[p].push_back(relfp64[p]);
             }
             BST(lincomb(b, pending, VP, VR, 1.0, VP, 0.0, &beta));
+        }
+        // problems whose FP32 segments stopped improving x: FP64 CG from x
+        bool anystag = false;
+        for (int p = 0; p < np; ++p) {
+            if (stag[p] != 1) stag[p] = 0;   // over a cap but finished otherwise
+            anystag |= stag[p] != 0;
+        }
+        if (anystag) {
+            BST(run_apply(b, false, false, true, VX, VQ, stag));
+            BST(lincomb(b, stag, VR, VB, 1.0, VQ, -1.0));
+            BST(lincomb(b, stag, VP, VR, 1.0, -1, 0.0));
+            BST(dots(b, stag, VR, VR, rr));
+            for (int p = 0; p < np; ++p) {
+                BState& s = b->h_st[p];
+                std::memset(&s, 0, sizeof(s));
+                if (!stag[p]) continue;
+                s.rr = rr[p];
+                s.bb = bb[p];
+                s.tol2 = tol * tol;
+                s.maxit = std::max(1, maxit - iters[p]);
+                s.status = ELWH_ERR_NOT_CONVERGED;
+                s.active = rr[p] <= s.tol2 * bb[p] ? 0 : 1;
+                if (!s.active) s.status = ELWH_OK;
+            }
+            BST(run_cg(b, false, VX, VR, VP, VQ, tick_budget));
+            for (int p = 0; p < np; ++p) {
+                if (!stag[p]) continue;
+                fp64_iters[p] = b->h_st[p].iters;
+                iters[p] += b->h_st[p].iters;
+                status[p] = b->h_st[p].status;
+                relres[p] = std::sqrt(b->h_st[p].rr / bb[p]);
+            }
+            BST(run_apply(b, false, false, true, VX, VQ, stag));
+            BST(lincomb(b, stag, VT, VB, 1.0, VQ, -1.0));
+            BST(dots(b, stag, VT, VT, rr));
+            for (int p = 0; p < np; ++p)
+                if (stag[p]) relfp64[p] = std::sqrt(rr[p] / bb[p]);
         }
         if (b->opts.cr_fallback) BST(cr_fallback(b, status, iters, cr_iters, relres, relfp64, bb, tol, maxit));
     }
@@ -749,6 +801,7 @@ elwh_status elwh_batch_solve(elwh_batch* b, const double* const* f, const double
         in.relres_fp64 = relfp64[p];
         in.cond_est = NAN;
         in.cr_iters = cr_iters[p];
+        in.fp64_iters = fp64_iters[p];
         if (infos) infos[p] = in;
         if (status[p] != ELWH_OK && worst == ELWH_OK) worst = (elwh_status)status[p];
         if (status[p] == ELWH_ERR_BREAKDOWN || status[p] == ELWH_ERR_UNSTABLE) worst = (elwh_status)status[p];

@@ -46,14 +46,15 @@ class Opts(ctypes.Structure):
                 ("prec", ctypes.c_int), ("krylov", ctypes.c_int), ("gmres_m", ctypes.c_int),
                 ("scheme", ctypes.c_int), ("compensated", ctypes.c_int), ("inner_tol", ctypes.c_double),
                 ("max_outer", ctypes.c_int), ("stream", ctypes.c_void_p), ("autotune", ctypes.c_int),
-                ("fuse", ctypes.c_int), ("scale_x0", ctypes.c_int), ("cr_fallback", ctypes.c_int)]
+                ("fuse", ctypes.c_int), ("scale_x0", ctypes.c_int), ("cr_fallback", ctypes.c_int),
+                ("fp64_fallback", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("outer", ctypes.c_int), ("nt", ctypes.c_int), ("napply", ctypes.c_int),
                 ("dt", ctypes.c_double), ("c", ctypes.c_double), ("lambda_bound", ctypes.c_double),
                 ("relres", ctypes.c_double), ("relres_fp64", ctypes.c_double), ("cond_est", ctypes.c_double),
-                ("cr_iters", ctypes.c_int)]
+                ("cr_iters", ctypes.c_int), ("fp64_iters", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -190,3 +190,33 @@ def test_cr_fallback_after_cg_breakdown(E, prec):
         prob, op, vs_ = _direct(x)
         assert info["relres_fp64"] <= 2e-8
         assert _rel(prob.gather(vv.cpu().numpy()), vs_) <= 1e-3
+
+
+def test_fp32_stagnation_falls_back_to_fp64(E):
+    """Config-5 problems (256^2, seeds 4096 and 4112) on which CG with FP32
+    applications stalls: with the guard off the FP32 batch stops short of
+    1e-8 at the iteration cap; with it (default) each problem switches to
+    FP64 CG from its iterate and reaches 1e-8, alone and batched, and the
+    solution equals the FP64 one."""
+    cases = [inputs.config5_problem(s) for s in (4096, 4112)]
+    fs = [c.f for c in cases]
+    ref = E.Batch(cases)
+    v64, i64, st64 = ref.solve(fs, tol=1e-8, maxit=3000)
+    assert st64 == "OK"
+    off = E.Batch(cases, prec=E.FP32_STEP, fp64_fallback=0)
+    _, ioff, stoff = off.solve(fs, tol=1e-8, maxit=1500)
+    _say("fp32 without fallback", stoff, [(i["iters"], i["relres_fp64"]) for i in ioff])
+    assert stoff == "ERR_NOT_CONVERGED"
+    on = E.Batch(cases, prec=E.FP32_STEP)
+    v, infos, st = on.solve(fs, tol=1e-8, maxit=3000)
+    _say("fp32 with fallback", st, [(i["iters"], i["fp64_iters"], i["relres_fp64"]) for i in infos])
+    assert st == "OK"
+    for a, b, info in zip(v, v64, infos):
+        assert info["fp64_iters"] > 0 and info["relres_fp64"] <= 1e-8
+        assert _rel(a.cpu().numpy(), b.cpu().numpy()) <= 1e-6
+    c = cases[0]
+    ctx = E.context_from_case(c, prec=E.FP32_STEP)
+    vs, info = ctx.solve(c.f, tol=1e-8, maxit=3000)
+    _say("single context fp32 with fallback", info)
+    assert info["fp64_iters"] > 0 and info["relres_fp64"] <= 1e-8
+    assert _rel(vs.cpu().numpy(), v64[0].cpu().numpy()) <= 1e-6
