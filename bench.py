@@ -247,6 +247,26 @@ def time_to_tol(elwh, nprob=24, first_seed=4096):
     return r
 
 
+def counters_pass_3d(tz, prec):
+    """Dispatches for the HBM-traffic counters of the 3-D step kernel: the
+    256 MiB calibration copy, then two A_h applications of the 256^3
+    workload (config 3) with the fixed tiling TZ, FP64 or FP32 compensated."""
+    import torch
+    from paper_2205_12344_amd import elwh, inputs
+    x = torch.ones(2 ** 25, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    kw = {} if prec == "f64" else {"prec": elwh.FP32_STEP, "compensated": 1}
+    ctx = elwh.context_from_case(inputs.config3(), autotune=0, **kw)
+    ctx.set_tile(elwh.FP64 if prec == "f64" else elwh.FP32_STEP, 1, int(tz))
+    z = torch.zeros(ctx.field_shape, dtype=torch.float64, device="cuda")
+    for _ in range(2):
+        ctx.apply_A(z)
+    torch.cuda.synchronize()
+    log(f"3-D counters pass done (TZ={tz}, {prec})")
+
+
 def counters_pass(tile, mapped=False):
     """Dispatches for the HBM-traffic counters: a plain copy of 256 MiB (the
     scale reference: 262144 KiB read, 262144 KiB written) and three A_h
@@ -287,6 +307,8 @@ def main():
                          "A_h applications of the benchmark workload with the fixed FP64 tiling V,TY")
     ap.add_argument("--counters-mapped", default=None, metavar="V,TY",
                     help="the same counter pass on the mapped workload (curvilinear step kernel)")
+    ap.add_argument("--counters-3d", default=None, metavar="TZ,PREC",
+                    help="counter pass on the 3-D 256^3 workload (PREC f64 or f32c)")
     ap.add_argument("--mapped-only", action="store_true",
                     help="only the mapped-grid step-kernel measurement (for kernel traces and counters)")
     args = ap.parse_args()
@@ -304,6 +326,10 @@ def main():
         return
     if args.counters_mapped:
         counters_pass(args.counters_mapped, mapped=True)
+        return
+    if args.counters_3d:
+        tz, prec = args.counters_3d.split(",")
+        counters_pass_3d(tz, prec)
         return
     if args.mapped_only:
         print(json.dumps(mapped_rates(elwh, inputs)))
