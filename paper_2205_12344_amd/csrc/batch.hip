@@ -29,7 +29,7 @@ using namespace elwh;
 
 namespace {
 enum { VX = 0, VR, VP, VQ, VB, VT, VD, VRI };
-constexpr int GRAPH_TICKS = 8;
+constexpr int GRAPH_TICKS = 32;   // ticks per graph replay (one host check of the active count each)
 }  // namespace
 
 struct elwh_batch {
