@@ -205,16 +205,16 @@ def cpu_baseline(case, budget_s=12.0):
                       f"workload, {el:.1f} s; operator assembly {t_setup:.1f} s excluded"}
 
 
-def batch_cfg4(elwh, inputs):
-    """Config 4: 48 problems (256^2..1024^2 cells, omega in [10, 80], 1-4
+def ragged_batch_solve(elwh, inputs):
+    """The ragged batch: 48 problems (256^2..1024^2 cells, omega in [10, 80], 1-4
     sources) solved to 1e-8 as one batch (one launch per tick for all
     problems, CG phase replayed as a hipGraph), FP32 stepping and FP64."""
     import torch
-    cases = inputs.config4()
-    out = {"workload": "config 4: 48 problems, n ~ U{256..1024}, omega ~ U[10, 80], 1-4 Gaussian sources, "
+    cases = inputs.ragged_batch()
+    out = {"workload": "ragged batch: 48 problems, n ~ U{256..1024}, omega ~ U[10, 80], 1-4 Gaussian sources, "
                        "random log-normal media, free top", "tol": 1e-8}
     for tag, kw in (("fp64", {}), ("fp32", {"prec": elwh.FP32_STEP})):
-        log(f"config 4 {tag}: solving")
+        log(f"ragged batch {tag}: solving")
         bt = elwh.Batch(cases, **kw)
         fs = [c.f for c in cases]
         torch.cuda.synchronize()
@@ -226,14 +226,14 @@ def batch_cfg4(elwh, inputs):
                     "iters_mean": round(sum(i["iters"] for i in infos) / len(infos), 1),
                     "max_relres_fp64": max(i["relres_fp64"] for i in infos),
                     "aggregate_glup_s": round(lup / s["seconds"] / 1e9, 2)}
-        log(f"config 4 {tag}: {out[tag]}")
+        log(f"ragged batch {tag}: {out[tag]}")
         bt.close()
     return out
 
 
 def time_to_tol(elwh, nprob=24, first_seed=4096):
     """Wall time to relative residual 1e-8 on held-out warm-start problems
-    (config 5, seeds first_seed..): plain FP64 from zero against the learned
+    (warm-start workload, seeds first_seed..): plain FP64 from zero against the learned
     start with FP32 stepping (and with FP64), one batch each."""
     from paper_2205_12344_amd import warmstart
     net = elwh.WarmStartNet(max_batch=nprob, H=warmstart.N_CELLS, seed=0)
@@ -241,7 +241,7 @@ def time_to_tol(elwh, nprob=24, first_seed=4096):
     r = warmstart.evaluate(net, list(range(first_seed, first_seed + nprob)), batch=nprob, tol=1e-8,
                            zero_fp32=False)
     net.close()
-    r["workload"] = (f"config 5: {nprob} held-out problems (seeds {first_seed}..{first_seed + nprob - 1}), 256^2 "
+    r["workload"] = (f"warm-start workload: {nprob} held-out problems (seeds {first_seed}..{first_seed + nprob - 1}), 256^2 "
                      f"cells, omega ~ U[20, 60], 1-4 Gaussian sources of width U[2h, 6h]")
     r["weights"] = {k: meta.get(k) for k in ("n_train", "epochs", "val_loss_after")}
     return r
@@ -250,7 +250,7 @@ def time_to_tol(elwh, nprob=24, first_seed=4096):
 def counters_pass_3d(tz, prec):
     """Dispatches for the HBM-traffic counters of the 3-D step kernel: the
     256 MiB calibration copy, then two A_h applications of the 256^3
-    workload (config 3) with the fixed tiling TZ, FP64 or FP32 compensated."""
+    layered-cube workload with the fixed tiling TZ, FP64 or FP32 compensated."""
     import torch
     from paper_2205_12344_amd import elwh, inputs
     x = torch.ones(2 ** 25, dtype=torch.float64, device="cuda")
@@ -258,7 +258,7 @@ def counters_pass_3d(tz, prec):
     y.copy_(x)
     torch.cuda.synchronize()
     kw = {} if prec == "f64" else {"prec": elwh.FP32_STEP, "compensated": 1}
-    ctx = elwh.context_from_case(inputs.config3(), autotune=0, **kw)
+    ctx = elwh.context_from_case(inputs.layered_cube(), autotune=0, **kw)
     ctx.set_tile(elwh.FP64 if prec == "f64" else elwh.FP32_STEP, 1, int(tz))
     z = torch.zeros(ctx.field_shape, dtype=torch.float64, device="cuda")
     for _ in range(2):
@@ -283,7 +283,7 @@ def counters_pass(tile, mapped=False):
         xs, ys, rho, lam, mu, om, _ = inputs.sector_case(200, 1, seed=14)
         ctx = elwh.MappedContext(xs, ys, rho, lam, mu, om, autotune=0)
     else:
-        ctx = elwh.context_from_case(inputs.config2(), autotune=0)
+        ctx = elwh.context_from_case(inputs.random_square(), autotune=0)
     ctx.set_tile(elwh.FP64, v, ty)
     z = torch.zeros(ctx.field_shape, dtype=torch.float64, device="cuda")
     for _ in range(3):
@@ -298,10 +298,10 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-3d", action="store_true", help="skip the 3-D 256^3 (config 3) step-kernel measurement")
-    ap.add_argument("--no-extra", action="store_true", help="skip the time-to-1e-8 (config 5) measurement")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3-D 256^3 layered-cube step-kernel measurement")
+    ap.add_argument("--no-extra", action="store_true", help="skip the time-to-1e-8 (warm-start workload) measurement")
     ap.add_argument("--batch", action="store_true",
-                    help="also solve the config-4 batch (48 problems) in FP32 and FP64 (several minutes)")
+                    help="also solve the ragged batch (48 problems) in FP32 and FP64 (several minutes)")
     ap.add_argument("--counters", default=None, metavar="V,TY",
                     help="counter-collection pass for rocprofv3 --pmc: a 256 MiB calibration copy, then 3 "
                          "A_h applications of the benchmark workload with the fixed FP64 tiling V,TY")
@@ -314,7 +314,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the hot path runs on a single MI355X "
-              "(multi-GPU sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
+              "(sharding across GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -335,7 +335,7 @@ def main():
         print(json.dumps(mapped_rates(elwh, inputs)))
         return
     t0 = time.perf_counter()
-    case = inputs.config2()
+    case = inputs.random_square()
     log(f"workload {case.name}: omega {case.omega:.3f}, inputs {time.perf_counter() - t0:.1f} s")
     nodes = unknown_nodes(case)
 
@@ -354,7 +354,7 @@ def main():
     bytes_app, launches_app = phase_bytes(2, "f64", fuse, nt, nodes)
     step_avg_ms = prof["step_ms"] / max(napp * launches_app, 1)
     achieved = bytes_app * napp / (prof["step_ms"] * 1e-3) / 1e9
-    traffic = read_traffic(f"multi2d_k{fuse}_f64_cfg2_1024", (tv, tr))
+    traffic = read_traffic(f"multi2d_k{fuse}_f64_square1024", (tv, tr))
     log(f"tile V={tv} TY={tr}")
     log(f"fp64: {ms_per_step:.3f} ms/step, {value / 1e9:.2f} GLUP/s, {fuse}-step kernel {1e3 * step_avg_ms:.1f} us "
         f"({napp * launches_app} launches), {achieved:.0f} GB/s")
@@ -401,7 +401,7 @@ def main():
         variants["mapped_" + tag] = v
 
     if not args.no_3d:
-        c3 = inputs.config3()
+        c3 = inputs.layered_cube()
         n3 = unknown_nodes(c3)
         for tag, kw in (("f64", {}), ("f32c", {"prec": elwh.FP32_STEP, "compensated": 1})):
             ctx3 = elwh.context_from_case(c3, **kw)
@@ -422,7 +422,7 @@ def main():
         extra["time_to_1e-8"] = time_to_tol(elwh)
         log(f"time to 1e-8: {json.dumps(extra['time_to_1e-8'])}")
     if args.batch:
-        extra["batch_config4"] = batch_cfg4(elwh, inputs)
+        extra["ragged_batch48"] = ragged_batch_solve(elwh, inputs)
 
     # practical HBM ceiling: a plain device-to-device copy of 2 GiB (beyond
     # the 256 MB last-level cache)

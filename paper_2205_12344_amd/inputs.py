@@ -167,18 +167,18 @@ def min_shear_speed(rho, mu):
 # presets, shaped like the paper's experiments
 # --------------------------------------------------------------------------
 
-def config1():
+def constant_square64():
     """2-D unit square, 64 x 64 cells, rho = 1, lambda = 2, mu = 1, omega = 10,
     all Dirichlet; Gaussian of width 0.05 in x-displacement at (0.5, 0.5);
     CG to 1e-10."""
     n = (64, 64)
     shape = (65, 65)
     f = gaussian_sources(2, n, (1.0, 1.0), [(0.5, 0.5)], [0.05], [(1.0, 0.0)])
-    return Case("cfg1_square64_const", 2, n, 10.0, np.ones(shape), np.full(shape, 2.0),
+    return Case("square64_const", 2, n, 10.0, np.ones(shape), np.full(shape, 2.0),
                 np.ones(shape), f, BC_ALL_DIRICHLET_2D, tol=1e-10)
 
 
-def config2(n=1024, seed=2, ppw=10.0):
+def random_square(n=1024, seed=2, ppw=10.0):
     """2-D n x n cells, random log-normal media, omega for ~ppw points per
     shear wavelength at the slowest shear speed; Dirichlet sides and bottom,
     traction-free top; one seeded Gaussian of width 3.2 h."""
@@ -190,11 +190,11 @@ def config2(n=1024, seed=2, ppw=10.0):
     e = unit_vector(rng, 2)
     f = gaussian_sources(2, (n, n), (1.0, 1.0), [x0], [3.2 * h], [e])
     omega = 2 * math.pi * min_shear_speed(rho, mu) / (ppw * h)
-    return Case(f"cfg2_square{n}_random", 2, (n, n), omega, rho, lam, mu, f, BC_FREE_TOP_2D,
+    return Case(f"square{n}_random", 2, (n, n), omega, rho, lam, mu, f, BC_FREE_TOP_2D,
                 tol=1e-8, meta={"seed": seed, "center": x0.tolist(), "direction": e.tolist()})
 
 
-def config3(n=256, seed=3, ppw=8.0):
+def layered_cube(n=256, seed=3, ppw=8.0):
     """3-D n^3 cells, three-layer medium with 5% perturbations, all
     Dirichlet; omega for ~ppw points per shear wavelength; one Gaussian."""
     h = 1.0 / n
@@ -204,12 +204,12 @@ def config3(n=256, seed=3, ppw=8.0):
     e = unit_vector(rng, 3)
     f = gaussian_sources(3, (n, n, n), (1.0, 1.0, 1.0), [x0], [3.2 * h], [e])
     omega = 2 * math.pi * min_shear_speed(rho, mu) / (ppw * h)
-    return Case(f"cfg3_cube{n}_layered", 3, (n, n, n), omega, rho, lam, mu, f, BC_ALL_DIRICHLET_3D,
+    return Case(f"cube{n}_layered", 3, (n, n, n), omega, rho, lam, mu, f, BC_ALL_DIRICHLET_3D,
                 tol=1e-8, meta={"seed": seed, "center": x0.tolist(), "direction": e.tolist()})
 
 
 def random_problem_2d(n, omega, seed, nsrc=None, width_h=(3.2, 3.2), rng=None):
-    """One random 2-D problem: config-2 media, 1-4 Gaussians in [0.2,0.8]^2."""
+    """One random 2-D problem: random log-normal media, 1-4 Gaussians in [0.2,0.8]^2."""
     h = 1.0 / n
     shape = (n + 1, n + 1)
     rho, lam, mu = media_random(shape, (h, h), seed)
@@ -223,7 +223,7 @@ def random_problem_2d(n, omega, seed, nsrc=None, width_h=(3.2, 3.2), rng=None):
                 tol=1e-8, meta={"seed": seed, "nsrc": k})
 
 
-def config4(nprob=48, seed=4, nmin=256, nmax=1024, wmin=10.0, wmax=80.0):
+def ragged_batch(nprob=48, seed=4, nmin=256, nmax=1024, wmin=10.0, wmax=80.0):
     """Batch of problems with n ~ U{nmin..nmax}, omega ~ U[wmin, wmax]."""
     rng = np.random.default_rng(seed)
     cases = []
@@ -234,14 +234,14 @@ def config4(nprob=48, seed=4, nmin=256, nmax=1024, wmin=10.0, wmax=80.0):
     return cases
 
 
-def config5_omega(seed):
-    """The omega that config5_problem(seed) draws (its first draw)."""
+def warmstart_omega(seed):
+    """The omega that warmstart_problem(seed) draws (its first draw)."""
     return float(np.random.default_rng(50_000 + seed).uniform(20.0, 60.0))
 
 
-def config5_problem(seed, n=256):
+def warmstart_problem(seed, n=256):
     """Warm-start training/evaluation problem: n = 256, omega ~ U[20, 60],
-    config-2 media, 1-4 Gaussians of width U[2h, 6h]."""
+    random log-normal media, 1-4 Gaussians of width U[2h, 6h]."""
     rng = np.random.default_rng(50_000 + seed)
     om = float(rng.uniform(20.0, 60.0))
     return random_problem_2d(n, om, seed=seed, width_h=(2.0, 6.0), rng=rng)

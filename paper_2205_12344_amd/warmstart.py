@@ -46,7 +46,7 @@ def make_dataset(seeds, net, batch=48, tol=1e-10, maxit=4000, time_budget=None):
     by omega so the problems of one batch need similar work.  Stops early
     (keeping what is done) past time_budget s."""
     n = net.H
-    seeds = sorted(seeds, key=inputs.config5_omega)
+    seeds = sorted(seeds, key=inputs.warmstart_omega)
     N = len(seeds)
     x = torch.empty((N, n, n, 7), dtype=torch.float32, device="cuda")
     y = torch.empty((N, n, n, 2), dtype=torch.float32, device="cuda")
@@ -56,7 +56,7 @@ def make_dataset(seeds, net, batch=48, tol=1e-10, maxit=4000, time_budget=None):
     t0 = time.time()
     for k in range(0, N, batch):
         chunk = seeds[k:k + batch]
-        cases = [inputs.config5_problem(s, n=n) for s in chunk]
+        cases = [inputs.warmstart_problem(s, n=n) for s in chunk]
         bt = elwh.Batch(cases)
         vs, infos, status = bt.solve([c.f for c in cases], tol=tol, maxit=maxit)
         bt.close()
@@ -180,7 +180,7 @@ def evaluate(net, seeds, batch=48, tol=1e-8, maxit=4000, fp32_batches=None, zero
 
     for k in range(0, len(seeds), batch):
         chunk = seeds[k:k + batch]
-        cases = [inputs.config5_problem(s, n=net.H) for s in chunk]
+        cases = [inputs.warmstart_problem(s, n=net.H) for s in chunk]
         f = [c.f for c in cases]
         # scale_x0 acts on given starts only: the zero-start runs are unchanged
         b64 = elwh.Batch(cases, scale_x0=1)

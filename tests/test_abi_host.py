@@ -81,9 +81,9 @@ def test_plan_matches_oracle(elwh, dim, n, bc):
     assert p["c"] == pytest.approx(correction_factor(om, 2 * np.pi / om / p["nt"]), rel=1e-14)
 
 
-def test_plan_config1(elwh):
+def test_plan_square64(elwh):
     from paper_2205_12344_amd import inputs
-    c = inputs.config1()
+    c = inputs.constant_square64()
     p = elwh.plan(2, c.n, c.rho, c.lam, c.mu, c.omega, c.bc)
     assert p["nt"] == 121
     assert p["lambda_bound"] == pytest.approx((5 * 2 + 13 * 1) * 64 ** 2, rel=1e-14)
@@ -241,7 +241,7 @@ def test_filter_diagnostics_reject_bad_input(elwh):
 @pytest.mark.parametrize("seed,indefinite", [(4115, True), (4099, False), (4096, False)])
 def test_filter_diagnostics_explain_the_cg_breakdown(elwh, seed, indefinite):
     """The band the diagnostics report holds a medium eigenvalue exactly when
-    A_h is indefinite: on the config-5 problem (64^2) where CG breaks down
+    A_h is indefinite: on the warm-start problem (64^2) where CG breaks down
     (seed 4115, tests/test_oracle_krylov_limits.py) one eigenvalue lambda_j
     of -L_h phi = lambda^2 M phi (shift-invert near omega^2) lies in
     [lambda_lo, lambda_hi] and the oracle's 1 - beta_h(theta_j) is negative
@@ -252,7 +252,7 @@ def test_filter_diagnostics_explain_the_cg_breakdown(elwh, seed, indefinite):
     from oracle import spectral
     from oracle.stepping import WaveHoltz, filter_weights
     from paper_2205_12344_amd import inputs
-    c = inputs.config5_problem(seed, n=64)
+    c = inputs.warmstart_problem(seed, n=64)
     prob = Problem(2, c.n, bc=c.bc)
     op = Operator(prob, c.rho, c.lam, c.mu)
     wh = WaveHoltz(op, c.omega)

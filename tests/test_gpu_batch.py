@@ -139,14 +139,14 @@ def test_scaled_warm_start(E, prec):
         assert _rel(prob.gather(x.cpu().numpy()), vs) <= 1e-6
 
 
-def test_config4_full_size_matches_single_contexts(E):
-    """Config 4 at full size (48 problems, 256^2..1024^2 cells, omega in
+def test_ragged_batch48_full_size_matches_single_contexts(E):
+    """The ragged batch at full size (48 problems, 256^2..1024^2 cells, omega in
     [10, 80], N_T up to ~3000) in one batch: two CG iterations of every
     problem equal those of the single-problem path (itself pinned to the
     oracle), which runs other kernels (K-step launches)."""
-    cases = inputs.config4()
+    cases = inputs.ragged_batch()
     bt = E.Batch(cases)
-    _say("config 4 batch tiles", bt.stats())
+    _say("ragged batch tiles", bt.stats())
     vs, infos, st = bt.solve([c.f for c in cases], tol=0.0, maxit=2)
     assert st == "OK"
     worst = 0.0
@@ -158,13 +158,13 @@ def test_config4_full_size_matches_single_contexts(E):
         v1, _ = ctx.cg_result()
         worst = max(worst, _rel(v.cpu().numpy(), v1.cpu().numpy()))
         ctx.close()
-    _say("config 4: worst rel diff batch vs single", worst)
+    _say("ragged batch: worst rel diff batch vs single", worst)
     assert worst <= 1e-12
 
 
 @pytest.mark.parametrize("prec", [0, 1])
 def test_cr_fallback_after_cg_breakdown(E, prec):
-    """A near-resonant warm-start problem (config 5, seed 4115, coarsened to
+    """A near-resonant warm-start problem (seed 4115, coarsened to
     64^2: omega = 59.0, N_T = 31) makes A_h slightly indefinite and CG break
     down (the oracle's CG does too); with cr_fallback the solve continues with
     conjugate residual in FP64 and reaches the residual target, alone and in
@@ -172,7 +172,7 @@ def test_cr_fallback_after_cg_breakdown(E, prec):
     within ~1e-5 of resonance), so a residual of 1e-8 bounds the error only
     to ~1e-4 (the oracle's CR from zero happens to land at 2e-7); the check
     on the solution is accordingly |v - v*| / |v*| <= 1e-3."""
-    c = inputs.config5_problem(4115, n=64)
+    c = inputs.warmstart_problem(4115, n=64)
     prob, op, vstar = _direct(c)
     with pytest.raises(E.ElwhError, match="BREAKDOWN"):
         E.context_from_case(c, prec=prec, cr_fallback=0).solve(c.f, tol=1e-8, maxit=3000)
@@ -180,7 +180,7 @@ def test_cr_fallback_after_cg_breakdown(E, prec):
     _say("single: cg iters", info["iters"], "cr iters", info["cr_iters"], "relres", info["relres_fp64"])
     assert info["cr_iters"] > 0 and info["relres_fp64"] <= 2e-8
     assert _rel(prob.gather(v.cpu().numpy()), vstar) <= 1e-3
-    cases = [c] + [inputs.config5_problem(s, n=64) for s in (4099, 4096)]
+    cases = [c] + [inputs.warmstart_problem(s, n=64) for s in (4099, 4096)]
     bt = E.Batch(cases, prec=prec)
     vs, infos, st = bt.solve([x.f for x in cases], tol=1e-8, maxit=3000)
     _say("batch:", st, [(i["iters"], i["cr_iters"], i["relres_fp64"]) for i in infos])
@@ -193,12 +193,12 @@ def test_cr_fallback_after_cg_breakdown(E, prec):
 
 
 def test_fp32_stagnation_falls_back_to_fp64(E):
-    """Config-5 problems (256^2, seeds 4096 and 4112) on which CG with FP32
+    """Warm-start problems (256^2, seeds 4096 and 4112) on which CG with FP32
     applications stalls: with the guard off the FP32 batch stops short of
     1e-8 at the iteration cap; with it (default) each problem switches to
     FP64 CG from its iterate and reaches 1e-8, alone and batched, and the
     solution equals the FP64 one."""
-    cases = [inputs.config5_problem(s) for s in (4096, 4112)]
+    cases = [inputs.warmstart_problem(s) for s in (4096, 4112)]
     fs = [c.f for c in cases]
     ref = E.Batch(cases)
     v64, i64, st64 = ref.solve(fs, tol=1e-8, maxit=3000)

@@ -214,9 +214,9 @@ def test_dot_M(E):
     assert got == pytest.approx(ref, rel=1e-13)
 
 
-def test_fixed_point_config1(E):
+def test_fixed_point_square64(E):
     """Sec. 1.1 / 4.3: Pi_h v* = v* with v* the direct Helmholtz solve."""
-    c = inputs.config1()
+    c = inputs.constant_square64()
     prob, op, wh = _oracle(2, c.n, None, c.bc, c.rho, c.lam, c.mu, c.omega)
     v = prob.scatter(direct.solve(op, c.omega, prob.gather(c.f)))
     ctx = E.context_from_case(c)
@@ -224,16 +224,16 @@ def test_fixed_point_config1(E):
     assert _rel(got, v) <= FP64_TOL
 
 
-def test_solve_config1_matches_direct_and_oracle_cg(E):
-    """Config 1: CG to 1e-10 matches the direct solve (<= 1e-10) and the
+def test_solve_square64_matches_direct_and_oracle_cg(E):
+    """64^2 constant medium: CG to 1e-10 matches the direct solve (<= 1e-10) and the
     oracle's CG iterate after the same number of iterations (<= 1e-12)."""
-    c = inputs.config1()
+    c = inputs.constant_square64()
     prob, op, wh = _oracle(2, c.n, None, c.bc, c.rho, c.lam, c.mu, c.omega)
     fv = prob.gather(c.f)
     vstar = direct.solve(op, c.omega, fv)
     ctx = E.context_from_case(c)
     v, info = ctx.solve(c.f, tol=1e-10, maxit=200)
-    _say("config1 solve", info)
+    _say("square64 solve", info)
     v = v.cpu().numpy()
     assert info["iters"] <= 20
     assert info["relres_fp64"] <= 1.1e-10
@@ -251,7 +251,7 @@ def test_solve_config1_matches_direct_and_oracle_cg(E):
 def test_scaled_start_single_context(E, prec):
     """scale_x0 on elwh_solve: 3 v* as the start is rescaled to v* (no
     iteration needed); the unscaled 3 v* start needs several."""
-    c = inputs.config1()
+    c = inputs.constant_square64()
     prob, op, wh = _oracle(2, c.n, None, c.bc, c.rho, c.lam, c.mu, c.omega)
     vstar = direct.solve(op, c.omega, prob.gather(c.f))
     x0 = 3.0 * prob.scatter(vstar)
@@ -265,7 +265,7 @@ def test_scaled_start_single_context(E, prec):
 
 
 def test_stepwise_cg_and_warm_start(E):
-    c = inputs.config1()
+    c = inputs.constant_square64()
     prob, op, wh = _oracle(2, c.n, None, c.bc, c.rho, c.lam, c.mu, c.omega)
     fv = prob.gather(c.f)
     ctx = E.context_from_case(c)
@@ -341,22 +341,22 @@ def test_unstable_step_is_reported(E, prec):
     first Rayleigh quotient (b, A_h b)_M / (b, b)_M then exceeds 4, which no
     stable step allows (|beta_h| <= 5/2), and the solver reports
     ELWH_ERR_UNSTABLE, alone and in a batch, instead of returning garbage."""
-    c = inputs.config1()
+    c = inputs.constant_square64()
     ctx = E.Context(2, c.n, c.rho, c.lam, c.mu, c.omega, c.bc, nt=6, prec=prec)
     v, info = ctx.solve(c.f, tol=1e-10, maxit=50, raise_on_fail=False)
     assert info["status"] == "ERR_UNSTABLE"
-    bt = E.Batch([c, inputs.config1()], nt=6, prec=prec)
+    bt = E.Batch([c, inputs.constant_square64()], nt=6, prec=prec)
     _, infos, st = bt.solve([c.f, c.f], tol=1e-10, maxit=50)
     assert st == "ERR_UNSTABLE"
 
 
 # ---------------------------------------------------------------- full size --
 
-def test_config2_full_size_fp64_and_fp32(E):
-    """Config 2 (1024^2, random media, free top) element by element against
+def test_square1024_full_size_fp64_and_fp32(E):
+    """The 1024^2 random medium with a free top element by element against
     the oracle, in the launch configuration the benchmark times."""
-    c = inputs.config2()
-    _say("config2 full size, omega", c.omega)
+    c = inputs.random_square()
+    _say("1024^2 random medium, omega", c.omega)
     prob, op, wh = _oracle(2, c.n, None, c.bc, c.rho, c.lam, c.mu, c.omega)
     fv = prob.gather(c.f)
     u0 = inputs.gaussian_sources(2, c.n, (1.0, 1.0), [(0.3, 0.4), (0.7, 0.6)], [0.05, 0.03],
@@ -368,12 +368,12 @@ def test_config2_full_size_fp64_and_fp32(E):
     assert _rel(got, ref) <= FP64_TOL
     ctx32 = E.context_from_case(c, prec=E.FP32_STEP)
     err32 = _rel(ctx32.apply_filter(u0, c.f).cpu().numpy(), ref)
-    _say("config2 fp32 rel err", err32, "bound", fp32_bound(wh.nt))
+    _say("1024^2 fp32 rel err", err32, "bound", fp32_bound(wh.nt))
     assert err32 <= fp32_bound(wh.nt)
 
 
-def test_config3_full_size_fixed_point():
-    """Config 3 (256^3 layered medium): the manufactured fixed point
+def test_cube256_full_size_fixed_point():
+    """The 256^3 layered medium: the manufactured fixed point
     Pi_h v* = v* with f = omega^2 rho v* + Ltilde v* from the oracle's slice
     stencil, FP64 (<= 1e-12) and FP32 stepping (<= fp32_bound(N_T))."""
     import torch
@@ -381,8 +381,8 @@ def test_config3_full_size_fixed_point():
         pytest.skip("no GPU")
     from paper_2205_12344_amd import elwh as E
     from oracle.stencil import ltilde_dirichlet
-    c = inputs.config3()
-    _say("config3 full size, omega", c.omega)
+    c = inputs.layered_cube()
+    _say("256^3 layered medium, omega", c.omega)
     n = c.n[0]
     x = np.arange(n + 1) / n
     Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
@@ -393,13 +393,13 @@ def test_config3_full_size_fixed_point():
     ctx = E.context_from_case(c)
     got = ctx.apply_filter(v, f).cpu().numpy()
     err = _rel(got, v)
-    _say("config3 fp64 fixed point err", err)
+    _say("256^3 fp64 fixed point err", err)
     assert err <= FP64_TOL
     del ctx
     ctx32 = E.context_from_case(c, prec=E.FP32_STEP)
     err32 = _rel(ctx32.apply_filter(v, f).cpu().numpy(), v)
     nt = ctx32.info()["nt"]
-    _say("config3 fp32 fixed point err", err32, "bound", fp32_bound(nt))
+    _say("256^3 fp32 fixed point err", err32, "bound", fp32_bound(nt))
     assert err32 <= fp32_bound(nt)
 
 
@@ -448,7 +448,7 @@ def test_every_tiling_matches_oracle(E, dim, prec):
 
 
 def test_autotune_choice_is_valid_and_cached(E):
-    c = inputs.config1()
+    c = inputs.constant_square64()
     ctx = E.context_from_case(c, prec=E.FP32_STEP)
     v64, r64 = ctx.get_tile(0)
     v32, r32 = ctx.get_tile(1)

@@ -149,7 +149,7 @@ def test_trained_network_start_vs_zero_start(E):
     net = E.WarmStartNet(max_batch=8, H=warmstart.N_CELLS, seed=0)
     meta = warmstart.load_weights(net)
     assert meta.get("n_train", 0) >= 2000
-    cases = [inputs.config5_problem(s) for s in range(4096, 4102)]
+    cases = [inputs.warmstart_problem(s) for s in range(4096, 4102)]
     x0 = warmstart.predict_x0(net, cases)
     assert all(bool(torch.isfinite(x).all()) for x in x0)
     bt = E.Batch(cases, scale_x0=1)

@@ -72,11 +72,11 @@ def _case_free_top(seed=11):
     return prob, op
 
 
-def test_fixed_point_config1():
+def test_fixed_point_square64():
     """Sec. 1.1 / 4.3: with the corrected scheme the discrete WaveHoltz fixed
     point is the direct discretisation of the Helmholtz equation:
     Pi_h v* = v*, v* = (w^2 M + L_h)^-1 W f."""
-    c = inputs.config1()
+    c = inputs.constant_square64()
     prob = Problem(2, c.n, bc=c.bc)
     op = Operator(prob, c.rho, c.lam, c.mu)
     wh = S.WaveHoltz(op, c.omega)
@@ -347,10 +347,10 @@ def test_manufactured_free_surface_converges():
 
 # --------------------------------------------------------------- Krylov -----
 
-def test_cg_config1_matches_direct():
-    """Config 1: CG in the M inner product to 1e-10 reproduces the direct
-    solve (the survey measured 14 iterations and 3e-12)."""
-    c = inputs.config1()
+def test_cg_square64_matches_direct():
+    """64^2 constant medium: CG in the M inner product to 1e-10 reproduces the direct
+    solve (14 iterations, error about 3e-12)."""
+    c = inputs.constant_square64()
     prob = Problem(2, c.n, bc=c.bc)
     op = Operator(prob, c.rho, c.lam, c.mu)
     wh = S.WaveHoltz(op, c.omega)

@@ -1,4 +1,4 @@
-"""Two properties of the warm-start workload (config-5 problems, coarsened
+"""Two properties of the warm-start workload (its problems coarsened
 to 64^2 cells so the CPU oracle runs in seconds) that bound what any solver
 option can gain there.
 
@@ -24,7 +24,7 @@ from paper_2205_12344_amd import inputs
 
 
 def _setup(seed):
-    c = inputs.config5_problem(seed, n=64)
+    c = inputs.warmstart_problem(seed, n=64)
     prob = Problem(2, c.n, bc=c.bc)
     op = Operator(prob, c.rho, c.lam, c.mu)
     wh = WaveHoltz(op, c.omega)

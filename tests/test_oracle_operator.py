@@ -227,9 +227,9 @@ def test_gershgorin_constant_medium(dim, closed):
 
 
 def test_inputs_are_sane():
-    c1 = inputs.config1()
+    c1 = inputs.constant_square64()
     assert c1.f.shape == (2, 65, 65) and c1.f[1].max() == 0
-    c2 = inputs.config2(n=64)
+    c2 = inputs.random_square(n=64)
     assert c2.rho.shape == (65, 65) and np.all(c2.lam >= c2.mu * 0.999999) and np.all(c2.lam <= 3 * c2.mu * 1.000001)
     assert c2.omega > 0
 
