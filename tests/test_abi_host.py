@@ -265,3 +265,28 @@ def test_filter_diagnostics_explain_the_cg_breakdown(elwh, seed, indefinite):
     inband = (lam >= d["lambda_lo"]) & (lam <= d["lambda_hi"])
     assert np.all((eig_A < 0) == inband)
     assert bool(inband.any()) == indefinite
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path):
+    """The product path has no CPU fallback: the binding, loaded from a
+    directory that holds no libelwh.so, refuses to import."""
+    import importlib.util
+    import shutil
+    src = os.path.join(ROOT, "paper_2205_12344_amd", "elwh.py")
+    shutil.copy(src, tmp_path / "elwh.py")
+    spec = importlib.util.spec_from_file_location("elwh_without_library", tmp_path / "elwh.py")
+    mod = importlib.util.module_from_spec(spec)
+    with pytest.raises(ImportError, match="not built"):
+        spec.loader.exec_module(mod)
+
+
+def test_product_code_never_touches_the_oracle():
+    """Only the tests, the smoke check and the CPU-baseline leg of the
+    benchmark may use oracle/; the package itself never imports it."""
+    pkg = os.path.join(ROOT, "paper_2205_12344_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".cpp", ".h")):
+                txt = open(os.path.join(dirpath, f), errors="replace").read()
+                assert not re.search(r"^\s*(from|import)\s+oracle\b", txt, flags=re.M), f
+                assert "oracle/" not in txt, f
