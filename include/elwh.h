@@ -76,7 +76,8 @@ typedef struct {
     int prec;          /* ELWH_FP64, or ELWH_FP32_STEP: FP32 state and stencil,
                           FP64 accumulator, FP64 Krylov vectors and inner
                           products, FP64 residual replacements */
-    int krylov;        /* ELWH_KRYLOV_CG (default), _GMRES, _CR */
+    int krylov;        /* ELWH_KRYLOV_CG (default), _GMRES, _CR; with
+                          ELWH_FP32_STEP only CG (else ELWH_ERR_ARG) */
     int gmres_m;       /* GMRES restart length (default 30) */
     int scheme;        /* ELWH_SCHEME_CORRECTED (default, Sec. 4.3) or _STANDARD */
     int compensated;   /* FP32 path: Neumaier-compensated FP64 accumulator (default 1) */

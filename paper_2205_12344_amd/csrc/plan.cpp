@@ -583,6 +583,10 @@ elwh_status check_config(const elwh_grid* g, const int bc[6], const elwh_opts* o
         if (o->periods < 1 || o->periods > 1000) { *err = "periods must be in [1, 1000]"; return ELWH_ERR_ARG; }
         if (o->prec != ELWH_FP64 && o->prec != ELWH_FP32_STEP) { *err = "bad precision"; return ELWH_ERR_ARG; }
         if (o->krylov < 0 || o->krylov > 2) { *err = "bad krylov method"; return ELWH_ERR_ARG; }
+        if (o->prec == ELWH_FP32_STEP && o->krylov != ELWH_KRYLOV_CG) {
+            *err = "FP32 stepping solves with CG (residual-replacement segments); GMRES and CR need FP64";
+            return ELWH_ERR_ARG;
+        }
         if (o->gmres_m < 1 || o->gmres_m > 200) { *err = "gmres_m must be in [1, 200]"; return ELWH_ERR_ARG; }
         if (o->scheme != ELWH_SCHEME_CORRECTED && o->scheme != ELWH_SCHEME_STANDARD) { *err = "bad scheme"; return ELWH_ERR_ARG; }
         if (o->fuse < 1 || o->fuse > 4) { *err = "fuse must be in [1, 4]"; return ELWH_ERR_ARG; }

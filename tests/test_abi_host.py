@@ -107,6 +107,9 @@ def test_plan_rejects_bad_input(elwh):
     for fuse in (0, 5):
         with pytest.raises(elwh.ElwhError, match="ERR_ARG"):
             elwh.plan(2, (8, 8), ok, ok, ok, 3.0, (0, 0, 0, 0), fuse=fuse)
+    for krylov in (1, 2):   # FP32 stepping runs CG only
+        with pytest.raises(elwh.ElwhError, match="need FP64"):
+            elwh.plan(2, (8, 8), ok, ok, ok, 3.0, (0, 0, 0, 0), prec=1, krylov=krylov)
 
 
 def test_plan_nt_override_and_standard(elwh):
