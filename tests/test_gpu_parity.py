@@ -403,6 +403,48 @@ def test_cube256_full_size_fixed_point():
     assert err32 <= fp32_bound(nt)
 
 
+def test_large_sizes_fixed_point():
+    """Sizes well beyond the benchmark's (4096^2 cells in 2-D, 16.8 M nodes;
+    384^3 in 3-D, 57 M nodes): the manufactured fixed point Pi_h v* = v* of
+    random and layered media with all faces Dirichlet, forcing from the
+    oracle's slice stencil, in FP64 (<= 1e-11)."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2205_12344_amd import elwh as E
+    from oracle.stencil import ltilde_dirichlet
+    n = 4096
+    h = 1.0 / n
+    rho, lam, mu = inputs.media_random((n + 1, n + 1), (h, h), seed=21)
+    om = 2 * math.pi * inputs.min_shear_speed(rho, mu) / (10 * h)
+    x = np.arange(n + 1) / n
+    Y, X = np.meshgrid(x, x, indexing="ij")
+    bump = np.sin(np.pi * X) * np.sin(np.pi * Y)
+    v = np.array([bump * np.sin(7 * np.pi * X + Y), bump * np.cos(5 * np.pi * Y)])
+    del X, Y, bump
+    f = om ** 2 * rho[None] * v + ltilde_dirichlet((h, h), lam, mu, v)
+    _say("4096^2 fixed point, omega", om)
+    ctx = E.Context(2, (n, n), rho, lam, mu, om, (0, 0, 0, 0))
+    err = _rel(ctx.apply_filter(v, f).cpu().numpy(), v)
+    _say("4096^2 fp64 fixed point err", err, "nt", ctx.info()["nt"])
+    assert err <= 1e-11
+    ctx.close()
+    del ctx, v, f, rho, lam, mu
+    c = inputs.layered_cube(n=384)
+    m = c.n[0]
+    x = np.arange(m + 1) / m
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    bump = np.sin(np.pi * X) * np.sin(np.pi * Y) * np.sin(np.pi * Z)
+    v = np.array([bump * np.sin(3 * np.pi * X), bump * np.cos(2 * np.pi * Y), bump * np.sin(5 * np.pi * Z)])
+    del X, Y, Z, bump
+    f = c.omega ** 2 * c.rho[None] * v + ltilde_dirichlet(tuple(1.0 / k for k in c.n), c.lam, c.mu, v)
+    _say("384^3 fixed point, omega", c.omega)
+    ctx3 = E.context_from_case(c)
+    err3 = _rel(ctx3.apply_filter(v, f).cpu().numpy(), v)
+    _say("384^3 fp64 fixed point err", err3, "nt", ctx3.info()["nt"])
+    assert err3 <= 1e-11
+
+
 # ------------------------------------------------------------- tilings --------
 
 def _tiles(dim, fp32):
