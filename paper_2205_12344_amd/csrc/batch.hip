@@ -48,6 +48,7 @@ struct elwh_batch {
     BState* d_st = nullptr;
     int* d_mask = nullptr;
     int* d_plist = nullptr;         // problems the CG kernels of a tick visit (the live ones)
+    int* d_arrive = nullptr;        // per-problem block counters of the CG reductions (kept zero)
     int nplist = 0;
     int gnplist[2] = {0, 0};
     int* d_active = nullptr;
@@ -317,7 +318,7 @@ void enqueue_ticks(elwh_batch* b, bool fp32, int nblocks, int nblocks2, int ntic
         launch_batch_advance(b->stream, b->d_pr, b->d_st, b->np, 0, fuse2, fp32 ? 1 : 0);
         for (int mode = 0; mode < 3; ++mode)
             launch_batch_cg(b->stream, mode, b->d_pr, b->d_st, b->np, b->d_plist, b->nplist, b->d_partials,
-                            b->d_active);
+                            b->d_arrive, b->d_active);
     }
 }
 
@@ -413,7 +414,8 @@ void free_batch(elwh_batch* b) {
     auto f = [](void* p) {
         if (p) (void)hipFree(p);
     };
-    f(b->d_pr); f(b->d_st); f(b->d_mask); f(b->d_plist); f(b->d_active); f(b->d_partials); f(b->d_dots);
+    f(b->d_pr); f(b->d_st); f(b->d_mask); f(b->d_plist); f(b->d_arrive); f(b->d_active); f(b->d_partials);
+    f(b->d_dots);
     if (b->h_active) (void)hipHostFree(b->h_active);
     if (b->h_dots) (void)hipHostFree(b->h_dots);
     for (auto& g : b->gexec)
@@ -499,6 +501,7 @@ elwh_status elwh_batch_create(int nprob, const elwh_grid* grids, const double* c
               dalloc(reinterpret_cast<void**>(&b->d_st), sizeof(BState) * nprob) &&
               dalloc(reinterpret_cast<void**>(&b->d_mask), sizeof(int) * nprob) &&
               dalloc(reinterpret_cast<void**>(&b->d_plist), sizeof(int) * nprob) &&
+              dalloc(reinterpret_cast<void**>(&b->d_arrive), sizeof(int) * nprob) &&
               dalloc(reinterpret_cast<void**>(&b->d_active), sizeof(int)) &&
               dalloc(reinterpret_cast<void**>(&b->d_partials), 2 * sizeof(double) * nprob * BATCH_RED_BLOCKS) &&
               dalloc(reinterpret_cast<void**>(&b->d_dots), sizeof(double) * nprob) &&
@@ -506,6 +509,8 @@ elwh_status elwh_batch_create(int nprob, const elwh_grid* grids, const double* c
               hipHostMalloc(reinterpret_cast<void**>(&b->h_dots), sizeof(double) * nprob, hipHostMallocDefault) ==
                   hipSuccess;
     if (!ok) return fail(ELWH_ERR_ALLOC, "batch allocation failed");
+    if (hipMemsetAsync(b->d_arrive, 0, sizeof(int) * nprob, b->stream) != hipSuccess)
+        return fail(ELWH_ERR_HIP, "clearing the reduction counters failed");
     for (int p = 0; p < nprob; ++p) {
         elwh_ctx* c = b->ctx[p];
         double *w = nullptr, *cs = nullptr;

@@ -263,9 +263,10 @@ int batch_cols2(int V);
 void launch_batch_multi(bool fp32, int V, int TY, bool force, bool comp, int nblocks2, hipStream_t s,
                         const BProb2D* pr, const BState* st, int np, double sgn, int amode);
 // CG update kernels of the ragged batch for the nplist problems listed in
-// plist (device array of problem indices).
+// plist (device array of problem indices); arrive: one zeroed counter per
+// problem (left zero by every launch).
 void launch_batch_cg(hipStream_t s, int mode, const BProb2D* pr, BState* st, int np, const int* plist, int nplist,
-                     double* partials, int* n_active);
+                     double* partials, int* arrive, int* n_active);
 void launch_batch_lincomb(hipStream_t s, const BProb2D* pr, int np, const int* mask, int idst, int ia,
                           double alpha, int ib, double beta, const double* betav = nullptr);
 void launch_batch_dot(hipStream_t s, const BProb2D* pr, int np, const int* mask, int ia, int ib,
