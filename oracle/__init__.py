@@ -18,6 +18,8 @@ Modules
   spectral  continuous and trapezoid filter transfer functions (Sec. 3, App. B)
   curvilinear  the stress divergence on a mapped 2-D grid (Sec. 4.1; the
             annular sectors of Sec. 5.4), same interface as operator
+  twofield  the two-field (displacement, velocity) filter for impedance faces
+            (the remark of Sec. 3), damped corrected leapfrog, GMRES
 
 All arithmetic is IEEE float64.  Parity status of each function is stated in
 its docstring; the free-surface closure is a reading of the paper (the paper
@@ -25,4 +27,4 @@ defers the exact boundary stencils to another publication) and its absolute
 values are "parity unpinned" beyond the invariants listed there.
 """
 
-from . import problem, operator, stepping, krylov, direct, spectral, curvilinear  # noqa: F401
+from . import problem, operator, stepping, krylov, direct, spectral, curvilinear, twofield  # noqa: F401

@@ -1,0 +1,163 @@
+"""Pins of the two-field oracle for impedance faces (oracle/twofield.py).
+
+* The GMRES fixed point of the two-field filter equals the complex direct
+  solve of the damped Helmholtz system (w^2 M + L_h - i w D) v = W f: the
+  corrected scheme reaches the time-harmonic solution with no time error
+  (Sec. 4.3, extended to the centred damping term), one and two periods.
+* The damped leapfrog dissipates exactly what its centred damping term
+  takes out: E^{n+1/2} - E^{n-1/2} = -sum g m (u^{n+1} - u^{n-1})^2 / (c dt^2).
+* Without impedance faces the displacement half of the two-field filter at
+  zero initial velocity is the one-field filter Pi_h (Sec. 3).
+* The damped discrete Helmholtz solution converges at second order to a
+  manufactured complex solution of w^2 rho v + div T(v) = F with
+  T(v) n + i w Z v = g on the impedance faces (Z = rho c_p normal, rho c_s
+  tangential), which pins the damping coefficients B = 2 c / h.
+* The remark of Sec. 3: with absorbing boundaries the iteration count grows
+  like omega (all four faces absorbing), against a markedly faster growth
+  for energy-conserving faces.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import jets
+from oracle.operator import Operator
+from oracle.problem import DIRICHLET, FREE, Problem
+from oracle.stepping import WaveHoltz
+from oracle.twofield import TwoField
+
+
+def random_case(seed, n=(12, 10), bc=(DIRICHLET, DIRICHLET, FREE, FREE)):
+    rng = np.random.default_rng(seed)
+    prob = Problem(2, n, length=(1.2, 1.0), bc=bc)
+    sh = prob.node_shape
+    op = Operator(prob, 1 + 0.3 * rng.random(sh), 2 + rng.random(sh), 1 + 0.5 * rng.random(sh))
+    return op, rng.standard_normal(op.ndof), rng
+
+
+@pytest.mark.parametrize("faces,periods", [([(1, 0), (1, 1)], 1), ([(1, 1)], 1), ([(1, 0), (1, 1)], 2)])
+def test_fixed_point_is_the_damped_helmholtz_solution(faces, periods):
+    op, f, _ = random_case(3)
+    tf = TwoField(op, 7.3, faces, periods=periods)
+    u0, u1, res = tf.solve(f, tol=1e-13, maxit=3000)
+    assert res.converged
+    a, b = tf.fixed_point_of(tf.helmholtz_direct(f))
+    assert np.abs(u0 - a).max() <= 1e-10 * np.abs(a).max()
+    assert np.abs(u1 - b).max() <= 1e-10 * np.abs(b).max()
+    assert np.abs(b).max() > 1e-2 * np.abs(a).max() * tf.omega     # the velocity field is not trivial
+
+
+def test_damped_energy_identity():
+    op, _, rng = random_case(5)
+    tf = TwoField(op, 9.1, [(1, 0), (1, 1)])
+    u0, u1 = rng.standard_normal(op.ndof), rng.standard_normal(op.ndof)
+    traj = list(tf.trajectory(u0, u1, None, 60))
+    E = tf.energies(u0, u1, 60)
+    cdt2 = tf.wh.c * tf.dt ** 2
+    for n in range(1, 60):
+        d = traj[n + 1] - traj[n - 1]
+        loss = float(np.sum(tf.g * op.m * d * d)) / cdt2
+        assert abs((E[n] - E[n - 1]) + loss) <= 1e-11 * abs(E[0])
+        assert loss >= 0.0
+    assert E[-1] < 0.9 * E[0]
+
+
+def test_reduces_to_one_field_without_impedance():
+    op, f, rng = random_case(7)
+    u0 = rng.standard_normal(op.ndof)
+    tf = TwoField(op, 6.2, [])
+    wh = WaveHoltz(op, 6.2)
+    assert tf.nt == wh.nt
+    for forcing in (None, f):
+        got = tf.apply_filter(u0, np.zeros(op.ndof), forcing)[0]
+        ref = wh.apply_filter(u0, forcing)
+        assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_impedance_face_must_be_traction_type():
+    op, _, _ = random_case(1)
+    with pytest.raises(ValueError):
+        TwoField(op, 5.0, [(0, 0)])
+
+
+# ---- manufactured damped Helmholtz solution ----------------------------------
+
+def _fields(X, Y):
+    x, y = jets.Jet.var_x(X), jets.Jet.var_y(Y)
+    sx = jets.sin(math.pi * x)
+    rho = 1.0 + 0.2 * jets.sin(1.3 * x + 0.7 * y)
+    lam = 2.0 + 0.3 * jets.cos(0.9 * x - 1.1 * y)
+    mu = 1.0 + 0.2 * jets.sin(0.8 * x + 1.4 * y)
+    # v = (ur + i ui, vr + i vi), zero on the x faces
+    ur = sx * jets.cos(2.1 * y + 0.3)
+    ui = sx * jets.sin(1.7 * y - 0.4)
+    vr = sx * jets.exp(0.5 * y)
+    vi = sx * jets.cos(1.3 * y + 0.9)
+    return rho, lam, mu, (ur, ui), (vr, vi)
+
+
+def manufactured_error(n, omega):
+    prob = Problem(2, (n, n), bc=(DIRICHLET, DIRICHLET, FREE, FREE))
+    X, Y = prob.mesh()
+    rho, lam, mu, (ur, ui), (vr, vi) = _fields(X, Y)
+    op = Operator(prob, rho.v, lam.v, mu.v)
+    tf = TwoField(op, omega, [(1, 0), (1, 1)])
+    cp = np.sqrt((lam.v + 2 * mu.v) / rho.v)
+    cs = np.sqrt(mu.v / rho.v)
+    F = np.zeros(prob.field_shape, complex)
+    V = np.zeros(prob.field_shape, complex)
+    for u, v, unit in ((ur, vr, 1.0), (ui, vi, 1j)):
+        fx, fy = jets.stress_divergence(u, v, lam, mu)
+        F[0] += unit * (omega ** 2 * rho.v * u.v + fx)
+        F[1] += unit * (omega ** 2 * rho.v * v.v + fy)
+        V[0] += unit * u.v
+        V[1] += unit * v.v
+    # boundary data g = T(v) n + i omega Z v on y = 0 (n = -e_y) and y = 1 (n = +e_y)
+    sxy = np.zeros(prob.node_shape, complex)
+    syy = np.zeros(prob.node_shape, complex)
+    for u, v, unit in ((ur, vr, 1.0), (ui, vi, 1j)):
+        sxy += unit * mu.v * (u.gy + v.gx)
+        syy += unit * (lam.v * (u.gx + v.gy) + 2 * mu.v * v.gy)
+    h = prob.h[1]
+    for side, j, ny in ((0, 0, -1.0), (1, -1, 1.0)):
+        gx = ny * sxy[j] + 1j * omega * rho.v[j] * cs[j] * V[0, j]
+        gy = ny * syy[j] + 1j * omega * rho.v[j] * cp[j] * V[1, j]
+        F[0, j] -= 2.0 * gx / h
+        F[1, j] -= 2.0 * gy / h
+    v_h = tf.helmholtz_direct(prob.gather(F.real) + 1j * prob.gather(F.imag))
+    exact = prob.gather(V.real) + 1j * prob.gather(V.imag)
+    return np.abs(v_h - exact).max() / np.abs(exact).max()
+
+
+def test_manufactured_damped_helmholtz_converges_second_order():
+    errs = [manufactured_error(n, 3.3) for n in (16, 32, 64)]
+    rates = [math.log2(a / b) for a, b in zip(errs, errs[1:])]
+    assert errs[-1] < 5e-4, errs
+    assert all(r > 1.8 for r in rates), (errs, rates)
+
+
+# ---- iterations against frequency --------------------------------------------
+
+def gmres_iterations(k, bc, faces):
+    w = k + math.sqrt(2) / 10
+    n = int(4 * w + 1)
+    prob = Problem(2, (n, n), bc=bc)
+    sh = prob.node_shape
+    op = Operator(prob, np.ones(sh), 2 * np.ones(sh), np.ones(sh))
+    f = np.zeros(prob.field_shape)
+    f[0, n // 2, n // 2] = w * w * n * n
+    tf = TwoField(op, w, faces)
+    _, _, res = tf.solve(prob.gather(f), tol=1e-8, maxit=3000, restart=400)
+    assert res.converged
+    return w, res.iters
+
+
+def test_absorbing_iterations_grow_like_omega():
+    data = [gmres_iterations(k, (FREE,) * 4, [(0, 0), (0, 1), (1, 0), (1, 1)]) for k in (4, 8, 16, 24)]
+    slope = np.polyfit(np.log([w for w, _ in data]), np.log([i for _, i in data]), 1)[0]
+    assert 0.6 <= slope <= 1.2, (data, slope)
+    _, closed = gmres_iterations(16, (DIRICHLET, DIRICHLET, FREE, FREE), [])
+    _, open_ = gmres_iterations(16, (DIRICHLET, DIRICHLET, FREE, FREE), [(1, 0), (1, 1)])
+    assert 2 * open_ < closed, (open_, closed)
