@@ -58,6 +58,12 @@ BYTES_PER_MULTI_LAUNCH = {"f64": 120, "f32c": 108, "f32": 76}
 #   FP64: state 3x2x8 + 7x8 + acc 2x2x8 = 136; FP32 compensated:
 #   24 + 28 + 64 = 116; FP32 plain accumulator: 24 + 28 + 32 = 84
 BYTES_PER_LUP_MAPPED = {"f64": 136, "f32c": 116, "f32": 84}
+# Two-field step with impedance faces (FP64, one step per launch): state u^n,
+# u^{n-1} read and u^{n+1} written (3 x 2 x 8), a, lambda, mu (3 x 8), the
+# displacement and velocity accumulators read and written (2 x 2 x 2 x 8)
+BYTES_PER_LUP_TWOFIELD = 136
+TWOFIELD_WORKLOAD = ("the 1024^2 random-medium benchmark workload with both y faces absorbing (impedance "
+                     "Z = rho c_p normal, rho c_s tangential), Dirichlet x faces")
 MAPPED_WORKLOAD = ("quarter annulus of the iterations-vs-frequency experiment at omega = 200 + sqrt(2)/10 "
                    "(801 x 4003 cells, 20 points per shear wavelength at c_s = 1), random log-normal medium "
                    "(seed 14), Dirichlet sides")
@@ -176,6 +182,49 @@ def mapped_rates(elwh, inputs, napply=3):
     return out
 
 
+def twofield_rates(elwh, inputs, napply=3, solve=True):
+    """Two-field (impedance) step-kernel rate on the 1024^2 absorbing workload,
+    and optionally the GMRES solve of its fixed point to 1e-8."""
+    import torch
+    case = inputs.absorbing_square()
+    nodes = unknown_nodes(case)
+    ctx = elwh.context_from_case(case)
+    x = torch.zeros(ctx.field_shape, dtype=torch.float64, device="cuda")
+    ctx.apply_A2(x, x)
+    ctx.profile_enable(True)
+    for _ in range(napply):
+        ctx.apply_A2(x, x)
+    p = ctx.profile_read()
+    ctx.profile_enable(False)
+    avg_s = p["step_ms"] * 1e-3 / max(p["nstep"], 1)
+    bb = BYTES_PER_LUP_TWOFIELD
+    out = {"workload": TWOFIELD_WORKLOAD, "nt": ctx.info()["nt"], "tile": list(ctx.get_tile(elwh.FP64)),
+           "kernel": "damped2d_kernel", "step_kernel_us": round(1e6 * avg_s, 3),
+           "glup_s_kernel": round(nodes / avg_s / 1e9, 3), "bytes_per_lup": bb,
+           "achieved_GBs": round(bb * nodes / avg_s / 1e9, 1),
+           "frac": round(bb * nodes / avg_s / 1e9 / HBM_PEAK_GBS, 4)}
+    ctx.close()
+    if solve:
+        # GMRES to 1e-8 on the 256^2 version (omega = 116.5): with reflecting
+        # x faces the count grows faster than omega, and the 1024^2 one
+        # (omega = 470) needs far more than its time budget
+        small = inputs.absorbing_square(256)
+        cs = elwh.context_from_case(small)
+        f = torch.tensor(small.f, device="cuda")
+        cs.solve2(f, tol=1e-2, maxit=5, raise_on_fail=False)      # allocate the basis
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, info = cs.solve2(f, tol=1e-8, maxit=4000, raise_on_fail=False)
+        el = time.perf_counter() - t0
+        out["gmres_to_1e-8"] = {"workload": "the same construction at 256^2 cells", "omega": small.omega,
+                                "nt": info["nt"], "seconds": round(el, 3), "iters": info["iters"],
+                                "napply": info["napply"], "status": info["status"],
+                                "relres_fp64": info["relres_fp64"], "gmres_m": 30}
+        cs.close()
+    log(f"two-field: {out}")
+    return out
+
+
 def cpu_baseline(case, budget_s=12.0):
     """The oracle as it stands, timed on the host: A_h applications on the
     benchmark workload until the budget is spent (single-threaded sparse
@@ -267,6 +316,26 @@ def counters_pass_3d(tz, prec):
     log(f"3-D counters pass done (TZ={tz}, {prec})")
 
 
+def counters_pass_twofield(tile):
+    """The counter pass of the two-field step kernel: the 256 MiB calibration
+    copy, then three A_h applications of the 1024^2 absorbing workload with a
+    fixed tiling."""
+    import torch
+    from paper_2205_12344_amd import elwh, inputs
+    v, ty = (int(t) for t in tile.split(","))
+    x = torch.ones(2 ** 25, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    ctx = elwh.context_from_case(inputs.absorbing_square(), autotune=0)
+    ctx.set_tile(elwh.FP64, v, ty)
+    z = torch.zeros(ctx.field_shape, dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        ctx.apply_A2(z, z)
+    torch.cuda.synchronize()
+    log(f"two-field counters pass done (tile V={v} TY={ty})")
+
+
 def counters_pass(tile, mapped=False):
     """Dispatches for the HBM-traffic counters: a plain copy of 256 MiB (the
     scale reference: 262144 KiB read, 262144 KiB written) and three A_h
@@ -309,6 +378,10 @@ def main():
                     help="the same counter pass on the mapped workload (curvilinear step kernel)")
     ap.add_argument("--counters-3d", default=None, metavar="TZ,PREC",
                     help="counter pass on the 3-D 256^3 workload (PREC f64 or f32c)")
+    ap.add_argument("--counters-twofield", default=None, metavar="V,TY",
+                    help="counter pass of the two-field (impedance) step kernel on the 1024^2 absorbing workload")
+    ap.add_argument("--twofield-only", action="store_true",
+                    help="only the two-field (impedance) step-kernel measurement and its GMRES solve")
     ap.add_argument("--mapped-only", action="store_true",
                     help="only the mapped-grid step-kernel measurement (for kernel traces and counters)")
     args = ap.parse_args()
@@ -327,12 +400,18 @@ def main():
     if args.counters_mapped:
         counters_pass(args.counters_mapped, mapped=True)
         return
+    if args.counters_twofield:
+        counters_pass_twofield(args.counters_twofield)
+        return
     if args.counters_3d:
         tz, prec = args.counters_3d.split(",")
         counters_pass_3d(tz, prec)
         return
     if args.mapped_only:
         print(json.dumps(mapped_rates(elwh, inputs)))
+        return
+    if args.twofield_only:
+        print(json.dumps(twofield_rates(elwh, inputs, solve=True)))
         return
     t0 = time.perf_counter()
     case = inputs.random_square()
@@ -399,6 +478,7 @@ def main():
 
     for tag, v in mapped_rates(elwh, inputs).items():
         variants["mapped_" + tag] = v
+    variants["twofield_f64"] = twofield_rates(elwh, inputs, solve=not args.no_extra)
 
     if not args.no_3d:
         c3 = inputs.layered_cube()

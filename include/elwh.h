@@ -30,7 +30,8 @@
  *    Dirichlet-face nodes hold 0: inputs there are ignored, outputs there
  *    are written as 0.  Traction-free faces are supported on the +-y faces in
  *    2-D and the +-z faces in 3-D; the x faces (and y faces in 3-D) must be
- *    Dirichlet.
+ *    Dirichlet.  Impedance (absorbing) faces: +-y in 2-D, two-field entry
+ *    points only.
  *  - Calls are asynchronous on the context's stream unless stated otherwise.
  *    One context must not be used from two threads at once.
  *  - Errors are returned as elwh_status; nothing aborts or throws across the
@@ -55,7 +56,12 @@ typedef enum {
     ELWH_ERR_BREAKDOWN = 6       /* (p, A p)_M <= 0: A_h indefinite near resonance (Sec. 4.4 Remark) */
 } elwh_status;
 
-enum { ELWH_BC_DIRICHLET = 0, ELWH_BC_TRACTION_FREE = 1 };
+/* ELWH_BC_IMPEDANCE: an absorbing face T(u) n = -Z u_t (Z = rho c_p on the
+ * normal, rho c_s on the tangential component); only on the -y and +y faces
+ * of 2-D Cartesian grids with FP64 stepping, and only through the two-field
+ * entry points elwh_apply_filter2 / elwh_apply_A2 / elwh_solve2 (the
+ * one-field ones return ELWH_ERR_ARG on such a context). */
+enum { ELWH_BC_DIRICHLET = 0, ELWH_BC_TRACTION_FREE = 1, ELWH_BC_IMPEDANCE = 2 };
 enum { ELWH_FP64 = 0, ELWH_FP32_STEP = 1 };
 enum { ELWH_KRYLOV_CG = 0, ELWH_KRYLOV_GMRES = 1, ELWH_KRYLOV_CR = 2 };
 enum { ELWH_SCHEME_CORRECTED = 0, ELWH_SCHEME_STANDARD = 1 };
@@ -224,6 +230,51 @@ typedef struct {
 
 elwh_status elwh_filter_diagnostics(int nt, int periods, double omega, int scheme,
                                     elwh_filter_diag* out);
+
+/*
+ * Two-field operator for impedance faces (the remark after eq.
+ * many_periods_filter in Sec. 3; the paper leaves such boundaries to future
+ * work).  With an absorbing face the initial velocity of the time-harmonic
+ * solution is not zero and the filter acts on the pair
+ *     Pi_h [u0; u1] = [sum_n w_n u^n; sum_n w_n v^n],
+ * u^n the corrected leapfrog (Sec. 4.3) started from displacement u0 and
+ * velocity u1, v^n = (u^{n+1} - u^{n-1}) / (2 dt) its centred velocity
+ * (v^0 = u1; one step past the window gives v^{K N_T}), w_n the trapezoid
+ * weights of elwh_apply_filter.  An impedance face is a traction-type face of
+ * the discrete energy (Sec. 4.1) whose rows carry the damping B = 2 c / h_y
+ * (c = c_p for the normal, c_s for the tangential component), stepped as
+ *     (1 + g) u^{n+1} = 2 u^n - (1 - g) u^{n-1} + a (Ltilde u^n - f cos(omega t_n)),
+ * g = c dt Bt / 2 with Bt = B omega dt / sin(omega dt) for the corrected
+ * scheme (Bt = B for the standard one), so that the fixed point reproduces
+ * the time-harmonic solution without time error: with the corrected scheme
+ *     u0 = Re v,   u1 = -(sin(omega dt) / dt) Im v,
+ * v the complex solution of (omega^2 M + L_h - i omega D) v = W f, D = M B
+ * (the direct discretisation of omega^2 rho v + div T(v) = f with the
+ * impedance condition T(v) n + i omega Z v = 0).  Without impedance faces
+ * these entry points apply the same operator (the fixed point has u1 = 0).
+ * FP64, 2-D Cartesian contexts only.  All arrays are DEVICE fields in the
+ * layout above.
+ *
+ * elwh_apply_filter2  out0, out1 = Pi_h [u0; u1] with forcing f (NULL: S_h).
+ * elwh_apply_A2       [y0; y1] = [x0; x1] - S_h [x0; x1]; no aliasing of
+ *                     inputs with outputs of the other field.
+ * elwh_solve2         the fixed point by restarted GMRES (opts.gmres_m, CGS2)
+ *                     on A_h z = Pi_h [0; 0] for the stacked z = [u0; u1 /
+ *                     omega] in the M inner product of each half, from
+ *                     [x0; x1] (NULL: zero), until the recurrence residual is
+ *                     <= tol times ||b|| or maxit applications; writes the
+ *                     displacement v0 and the velocity v1, info->iters,
+ *                     relres and relres_fp64 (the true residual recomputed
+ *                     with one more application).  Synchronises the stream.
+ * Errors: ELWH_ERR_ARG (NULL pointer, mapped, 3-D or FP32 context),
+ * ELWH_ERR_NOT_CONVERGED (v0, v1 hold the last iterate), ELWH_ERR_UNSTABLE,
+ * ELWH_ERR_ALLOC, ELWH_ERR_HIP.
+ */
+elwh_status elwh_apply_filter2(elwh_ctx* ctx, const double* u0, const double* u1, const double* f, double* out0,
+                               double* out1);
+elwh_status elwh_apply_A2(elwh_ctx* ctx, const double* x0, const double* x1, double* y0, double* y1);
+elwh_status elwh_solve2(elwh_ctx* ctx, const double* f, const double* x0, const double* x1, double tol, int maxit,
+                        double* v0, double* v1, elwh_info* info);
 
 /* Release every device and host resource of ctx (NULL is a no-op). */
 void elwh_destroy(elwh_ctx* ctx);

@@ -115,6 +115,9 @@ void free_all(elwh_ctx* c) {
     f(c->acc); f(c->acc_lo); f(c->f64); f(c->f32);
     for (auto* v : c->vec) f(v);
     for (auto* v : c->basis) f(v);
+    f(c->dmp); f(c->acc1); f(c->x1);
+    for (auto* v : c->basis2) f(v);
+    f(c->gm_ptrs); f(c->gm_part); f(c->gm_h);
     f(c->partials); f(c->dscal);
     if (c->hscal) (void)hipHostFree(c->hscal);
     for (auto e : c->prof_ev) (void)hipEventDestroy(e);
@@ -513,6 +516,21 @@ elwh_status create_impl(const elwh_grid* grid_in, const double* xc, const double
         }
         gbuf.len[0] = gbuf.len[1] = 1.0;   // the reference square: h_q = 1/n_q, h_r = 1/n_r
     }
+    // impedance faces: traction-type faces of the energy plus boundary damping
+    int imp[2] = {0, 0};
+    for (int f = 0; f < 6; ++f) {
+        if (bc[f] != ELWH_BC_IMPEDANCE) continue;
+        if (mapped || gbuf.dim != 2 || f < 2 || f > 3) {
+            g_create_err = "impedance faces are supported on the -y and +y faces of 2-D Cartesian grids";
+            return ELWH_ERR_ARG;
+        }
+        if (o.prec != ELWH_FP64) {
+            g_create_err = "impedance faces need FP64 stepping";
+            return ELWH_ERR_ARG;
+        }
+        imp[f - 2] = 1;
+        bc[f] = ELWH_BC_TRACTION_FREE;
+    }
     const elwh_grid* grid = &gbuf;
     elwh_status st = check_config(grid, bc, &o, &g_create_err);
     if (st != ELWH_OK) return st;
@@ -524,6 +542,8 @@ elwh_status create_impl(const elwh_grid* grid_in, const double* xc, const double
     if (!c) return ELWH_ERR_ALLOC;
     c->grid = *grid;
     c->mapped = mapped;
+    c->imp[0] = imp[0];
+    c->imp[1] = imp[1];
     for (int f = 0; f < 6; ++f) c->bc[f] = f < 2 * grid->dim ? bc[f] : ELWH_BC_DIRICHLET;
     c->omega = omega;
     c->opts = o;
@@ -672,6 +692,33 @@ elwh_status create_impl(const elwh_grid* grid_in, const double* xc, const double
             return fail(ELWH_ERR_HIP);
         }
     }
+    if (imp[0] || imp[1]) {
+        // damping g = c dt Bt / 2 of the two face rows, B = 2 c_s / h_y (u, tangential)
+        // and 2 c_p / h_y (v, normal), Bt = B omega dt / sin(omega dt) for the
+        // corrected scheme; the velocity accumulator and the second input field
+        const size_t P = (size_t)L.P;
+        if ((st = alloc_t(c, &c->dmp, 4 * P)) || (st = alloc_t(c, &c->acc1, FE)) || (st = alloc_t(c, &c->x1, FE)))
+            return fail(st);
+        std::vector<double> hd(4 * P, 0.0);
+        const double hy = grid->len[1] / grid->n[1];
+        const double wdt = omega * c->plan.dt;
+        const double rescale = o.scheme == ELWH_SCHEME_CORRECTED ? wdt / std::sin(wdt) : 1.0;
+        const double gfac = 0.5 * c->plan.c * c->plan.dt * rescale * 2.0 / hy;
+        for (int side = 0; side < 2; ++side) {
+            if (!imp[side]) continue;
+            const int j = side ? L.ny : 0;
+            for (int x = 0; x <= L.nx; ++x) {
+                const int64_t src = (int64_t)j * (L.nx + 1) + x;
+                hd[(2 * side) * P + x] = gfac * std::sqrt(hm[src] / hr[src]);
+                hd[(2 * side + 1) * P + x] = gfac * std::sqrt((hl[src] + 2.0 * hm[src]) / hr[src]);
+            }
+        }
+        if (hipMemcpyAsync(c->dmp, hd.data(), 4 * P * 8, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess) {
+            c->err = "uploading the damping rows failed";
+            return fail(ELWH_ERR_HIP);
+        }
+    }
     // default tiling, then (optionally) the timed choice
     if (mapped) {
         c->tile64 = Tile{1, 8};
@@ -721,8 +768,14 @@ elwh_status elwh_plan(const elwh_grid* grid, const double* rho, const double* la
     elwh_opts o;
     elwh_default_opts(&o);
     if (opts) o = *opts;
+    if (!bc) {
+        g_create_err = "null bc";
+        return ELWH_ERR_ARG;
+    }
+    int bcp[6];
+    for (int f = 0; f < 6; ++f) bcp[f] = bc[f] == ELWH_BC_IMPEDANCE ? ELWH_BC_TRACTION_FREE : bc[f];
     Plan p;
-    elwh_status st = make_plan(grid, rho, lam, mu, omega, bc, &o, &p, &g_create_err);
+    elwh_status st = make_plan(grid, rho, lam, mu, omega, bcp, &o, &p, &g_create_err);
     if (st != ELWH_OK) return st;
     if (info) {
         std::memset(info, 0, sizeof(*info));
@@ -800,6 +853,11 @@ const char* elwh_last_error(const elwh_ctx* c) { return c ? c->err.c_str() : g_c
 
 elwh_status elwh_apply_filter(elwh_ctx* c, const double* u0, const double* f, double* out) {
     if (!c || !u0 || !out) return ELWH_ERR_ARG;
+    if (c->imp[0] || c->imp[1]) {
+        c->err = "a context with impedance faces takes the two-field entry points (elwh_apply_filter2, "
+                 "elwh_apply_A2, elwh_solve2)";
+        return ELWH_ERR_ARG;
+    }
     const bool fp32 = c->opts.prec == ELWH_FP32_STEP;
     launch_pack(c->L, c->bc, u0, c->vec[VX], c->L.dim, c->stream);
     if (f) {
@@ -813,6 +871,11 @@ elwh_status elwh_apply_filter(elwh_ctx* c, const double* u0, const double* f, do
 
 elwh_status elwh_apply_A(elwh_ctx* c, const double* x, double* y) {
     if (!c || !x || !y) return ELWH_ERR_ARG;
+    if (c->imp[0] || c->imp[1]) {
+        c->err = "a context with impedance faces takes the two-field entry points (elwh_apply_filter2, "
+                 "elwh_apply_A2, elwh_solve2)";
+        return ELWH_ERR_ARG;
+    }
     const bool fp32 = c->opts.prec == ELWH_FP32_STEP;
     launch_pack(c->L, c->bc, x, c->vec[VX], c->L.dim, c->stream);
     apply_A(c, c->vec[VX], c->vec[VQ], fp32);
@@ -830,6 +893,11 @@ elwh_status elwh_dot_M(elwh_ctx* c, const double* x, const double* y, double* ou
 
 elwh_status elwh_cg_begin(elwh_ctx* c, const double* f, const double* x0) {
     if (!c || !f) return ELWH_ERR_ARG;
+    if (c->imp[0] || c->imp[1]) {
+        c->err = "a context with impedance faces takes the two-field entry points (elwh_apply_filter2, "
+                 "elwh_apply_A2, elwh_solve2)";
+        return ELWH_ERR_ARG;
+    }
     if (c->opts.prec != ELWH_FP64) {
         c->err = "the stepwise CG interface is FP64 only";
         return ELWH_ERR_ARG;
@@ -885,6 +953,11 @@ elwh_status elwh_cg_result(elwh_ctx* c, double* v, elwh_info* info) {
 elwh_status elwh_solve(elwh_ctx* c, const double* f, const double* x0, double tol, int maxit, double* v,
                        elwh_info* info) {
     if (!c || !f || !v || maxit < 0) return ELWH_ERR_ARG;
+    if (c->imp[0] || c->imp[1]) {
+        c->err = "a context with impedance faces takes the two-field entry points (elwh_apply_filter2, "
+                 "elwh_apply_A2, elwh_solve2)";
+        return ELWH_ERR_ARG;
+    }
     c->napply = 0;
     elwh_info inf;
     std::memset(&inf, 0, sizeof(inf));
@@ -1263,6 +1336,298 @@ elwh_status elwh_get_tile(const elwh_ctx* c, int prec, int* vec, int* rows) {
     *vec = t.V;
     *rows = t.TY;
     return ELWH_OK;
+}
+
+}  // extern "C"
+
+// ============================================================================
+// Two-field operator for impedance y faces (the remark of Sec. 3): the filter
+// acts on the pair (u0, u1) of initial displacement and velocity; GMRES on
+// A_h = I - S_h of the stacked unknown z = [u0; u1 / omega] in the M inner
+// product of each half.
+
+namespace {
+
+bool twofield_ok(elwh_ctx* c) {
+    if (c->mapped || c->L.dim != 2 || c->opts.prec != ELWH_FP64) {
+        c->err = "the two-field operator runs on 2-D Cartesian grids in FP64";
+        return false;
+    }
+    if (!c->acc1) {
+        // a context without impedance faces: allocate the two-field buffers now
+        const size_t P = (size_t)c->L.P, FE = (size_t)c->L.field_elems();
+        if (alloc_t(c, &c->dmp, 4 * P) != ELWH_OK || alloc_t(c, &c->acc1, FE) != ELWH_OK ||
+            alloc_t(c, &c->x1, FE) != ELWH_OK)
+            return false;
+    }
+    return true;
+}
+
+// out0 = sum w_n u^n, out1 = s_out sum w_n v^n for u^0 = x0 and the second
+// field u1 = s_in z1 (amode: x0 - ..., z1 - ...), v^n the centred velocity.
+void run_filter_twofield(elwh_ctx* c, const double* x0, const double* z1, bool with_force, bool amode, double s_in,
+                         double s_out, double* out0, double* out1) {
+    hipStream_t s = c->stream;
+    Damp2D D;
+    D.A = make_args2d(c);
+    D.imp_lo = c->imp[0];
+    D.imp_hi = c->imp[1];
+    const Tile t = tile_valid_damped(c->tile64.V, c->tile64.TY) ? c->tile64 : Tile{2, 8};
+    const int N = c->plan.nt * c->opts.periods;
+    const double sgn = amode ? -1.0 : 1.0, dt = c->plan.dt;
+    D.A.w0 = sgn * c->w[0];
+    D.A.w = sgn * c->w[1];
+    D.A.fc = c->cosn[0];
+    D.w0v = sgn * c->w[0] * s_in * s_out;
+    D.dtw = dt * s_in;
+    D.wv = 0.0;
+    prof_mark(c, 0);
+    launch_damped2d(t.V, t.TY, 1, with_force, s, x0, z1, c->s64[1], amode ? x0 : nullptr, amode ? z1 : nullptr,
+                    out0, out1, c->dmp, c->ca, c->cl, c->cm, c->f64, D);
+    prof_mark(c, 1);
+    const double* prev = x0;
+    double* cur = c->s64[1];
+    for (int n = 1; n <= N; ++n) {
+        // u^{n+1} over u^{n-1} when that is a state buffer, else a free one
+        double* nxt = nullptr;
+        for (double* b : c->s64)
+            if (b == prev) nxt = b;
+        if (!nxt)
+            for (double* b : c->s64)
+                if (b != cur && b != prev) {
+                    nxt = b;
+                    break;
+                }
+        D.A.w = n < N ? sgn * c->w[n + 1] : 0.0;   // the step past the window adds velocity only
+        D.A.fc = c->cosn[n];
+        D.wv = sgn * c->w[n] * s_out / (2.0 * dt);
+        launch_damped2d(t.V, t.TY, 0, with_force, s, cur, prev, nxt, nullptr, nullptr, out0, out1, c->dmp, c->ca,
+                        c->cl, c->cm, c->f64, D);
+        prev = cur;
+        cur = nxt;
+    }
+    prof_mark(c, 2, N);
+    c->napply++;
+}
+
+// Pair helpers: a two-field vector is two field vectors in the internal layout.
+struct Pair {
+    double* a;
+    double* b;
+};
+
+elwh_status dot2(elwh_ctx* c, Pair x, Pair y, double* out) {
+    double d0, d1;
+    CKST(dot_host(c, x.a, y.a, &d0));
+    CKST(dot_host(c, x.b, y.b, &d1));
+    *out = d0 + d1;
+    return ELWH_OK;
+}
+
+void axpby2(elwh_ctx* c, double a, Pair x, double b, Pair y) {
+    launch_axpby(c, a, x.a, b, y.a, c->stream);
+    launch_axpby(c, a, x.b, b, y.b, c->stream);
+}
+
+void copy2(elwh_ctx* c, Pair x, Pair y) {
+    launch_copy(c, x.a, y.a, c->stream);
+    launch_copy(c, x.b, y.b, c->stream);
+}
+
+void apply_A2(elwh_ctx* c, Pair x, Pair y) {
+    run_filter_twofield(c, x.a, x.b, false, true, c->omega, 1.0 / c->omega, y.a, y.b);
+}
+
+// Restarted GMRES with classical Gram-Schmidt twice on the stacked system
+// A_h z = b (z in x, b in b; x holds the start, x_zero: it is zero).
+elwh_status solve_gmres2(elwh_ctx* c, Pair x, Pair b, Pair w, bool x_zero, double tol, int maxit, int* iters,
+                         double* relres) {
+    const int m = c->opts.gmres_m;
+    const size_t FE = (size_t)c->L.field_elems();
+    while ((int)c->basis2.size() < 2 * (m + 1)) {
+        double* v = nullptr;
+        CKST(alloc_t(c, &v, FE));
+        c->basis2.push_back(v);
+    }
+    if (c->gm_cap < m + 1) {
+        // device pointer table (basis pairs, then w), multidot partials, coefficients
+        for (void* q : {(void*)c->gm_ptrs, (void*)c->gm_part, (void*)c->gm_h})
+            if (q) (void)hipFree(q);
+        c->gm_ptrs = nullptr;
+        c->gm_part = c->gm_h = nullptr;
+        c->gm_cap = 0;
+        CKST(alloc_t(c, &c->gm_ptrs, (size_t)(2 * (m + 1) + 2)));
+        CKST(alloc_t(c, &c->gm_part, (size_t)(m + 1) * multidot2_blocks(c)));
+        CKST(alloc_t(c, &c->gm_h, (size_t)(2 * (m + 1) + 1)));
+        c->gm_cap = m + 1;
+    }
+    {
+        std::vector<double*> tab(c->basis2.begin(), c->basis2.begin() + 2 * (m + 1));
+        tab.push_back(w.a);
+        tab.push_back(w.b);
+        HIPCK(hipMemcpyAsync(c->gm_ptrs, tab.data(), tab.size() * sizeof(double*), hipMemcpyHostToDevice,
+                             c->stream));
+        HIPCK(hipStreamSynchronize(c->stream));   // tab is a host temporary
+    }
+    const double* const* ptrs = c->gm_ptrs;
+    std::vector<double> hh(2 * (m + 1) + 1);
+    auto V = [&](int j) { return Pair{c->basis2[2 * j], c->basis2[2 * j + 1]}; };
+    double bb;
+    CKST(dot2(c, b, b, &bb));
+    const double bn = std::sqrt(bb);
+    int total = 0;
+    bool first = true;
+    std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+    while (true) {
+        const Pair r = V(0);
+        if (first && x_zero) {
+            copy2(c, b, r);
+        } else {
+            apply_A2(c, x, w);
+            copy2(c, b, r);
+            axpby2(c, -1.0, w, 1.0, r);
+        }
+        first = false;
+        double rr;
+        CKST(dot2(c, r, r, &rr));
+        const double beta = std::sqrt(rr);
+        if (!std::isfinite(beta)) {
+            c->err = "non-finite residual: the time step is unstable";
+            return ELWH_ERR_UNSTABLE;
+        }
+        *relres = bn > 0 ? beta / bn : 0.0;
+        *iters = total;
+        if (bn == 0 || (tol > 0 && *relres <= tol) || total >= maxit) break;
+        axpby2(c, 0.0, r, 1.0 / beta, r);
+        std::fill(H.begin(), H.end(), 0.0);
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int jdone = 0;
+        for (int j = 0; j < m; ++j) {
+            apply_A2(c, V(j), w);
+            total++;
+            // classical Gram-Schmidt twice, coefficients kept on the device;
+            // one host synchronisation per iteration
+            for (int pass = 0; pass < 2; ++pass) {
+                double* hp = c->gm_h + pass * (m + 1);
+                launch_multidot2(c, ptrs, j + 1, w.a, w.b, c->gm_part, hp, c->stream);
+                launch_multiaxpy2(c, ptrs, j + 1, hp, w.a, w.b, c->stream);
+            }
+            launch_multidot2(c, ptrs + 2 * (m + 1), 1, w.a, w.b, c->gm_part, c->gm_h + 2 * (m + 1), c->stream);
+            HIPCK(hipMemcpyAsync(hh.data(), c->gm_h, hh.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+            HIPCK(hipStreamSynchronize(c->stream));
+            for (int i = 0; i <= j; ++i) H[i * m + j] += hh[i] + hh[m + 1 + i];
+            const double ww = hh[2 * (m + 1)];
+            const double hn = std::sqrt(ww);
+            H[(j + 1) * m + j] = hn;
+            for (int i = 0; i < j; ++i) {
+                const double tt = cs[i] * H[i * m + j] + sn[i] * H[(i + 1) * m + j];
+                H[(i + 1) * m + j] = -sn[i] * H[i * m + j] + cs[i] * H[(i + 1) * m + j];
+                H[i * m + j] = tt;
+            }
+            const double rho = std::hypot(H[j * m + j], H[(j + 1) * m + j]);
+            cs[j] = H[j * m + j] / rho;
+            sn[j] = H[(j + 1) * m + j] / rho;
+            H[j * m + j] = rho;
+            H[(j + 1) * m + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            jdone = j + 1;
+            *relres = std::fabs(g[j + 1]) / bn;
+            if ((tol > 0 && *relres <= tol) || total >= maxit || hn == 0.0) break;
+            copy2(c, w, V(j + 1));
+            axpby2(c, 0.0, w, 1.0 / hn, V(j + 1));
+        }
+        for (int i = jdone - 1; i >= 0; --i) {
+            double sum = g[i];
+            for (int k = i + 1; k < jdone; ++k) sum -= H[i * m + k] * y[k];
+            y[i] = sum / H[i * m + i];
+        }
+        for (int i = 0; i < jdone; ++i) axpby2(c, y[i], V(i), 1.0, x);
+    }
+    *iters = total;
+    return (tol > 0 && *relres > tol) ? ELWH_ERR_NOT_CONVERGED : ELWH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+elwh_status elwh_apply_filter2(elwh_ctx* c, const double* u0, const double* u1, const double* f, double* out0,
+                               double* out1) {
+    if (!c || !u0 || !u1 || !out0 || !out1) return ELWH_ERR_ARG;
+    if (!twofield_ok(c)) return ELWH_ERR_ARG;
+    launch_pack(c->L, c->bc, u0, c->vec[VX], c->L.dim, c->stream);
+    launch_pack(c->L, c->bc, u1, c->x1, c->L.dim, c->stream);
+    if (f) pack_forcing(c, f, false);
+    run_filter_twofield(c, c->vec[VX], c->x1, f != nullptr, false, 1.0, 1.0, c->vec[VQ], c->acc1);
+    launch_unpack(c->L, c->bc, c->vec[VQ], out0, c->L.dim, c->stream);
+    launch_unpack(c->L, c->bc, c->acc1, out1, c->L.dim, c->stream);
+    HIPCK(hipGetLastError());
+    return ELWH_OK;
+}
+
+elwh_status elwh_apply_A2(elwh_ctx* c, const double* x0, const double* x1, double* y0, double* y1) {
+    if (!c || !x0 || !x1 || !y0 || !y1) return ELWH_ERR_ARG;
+    if (!twofield_ok(c)) return ELWH_ERR_ARG;
+    launch_pack(c->L, c->bc, x0, c->vec[VX], c->L.dim, c->stream);
+    launch_pack(c->L, c->bc, x1, c->x1, c->L.dim, c->stream);
+    run_filter_twofield(c, c->vec[VX], c->x1, false, true, 1.0, 1.0, c->vec[VQ], c->acc1);
+    launch_unpack(c->L, c->bc, c->vec[VQ], y0, c->L.dim, c->stream);
+    launch_unpack(c->L, c->bc, c->acc1, y1, c->L.dim, c->stream);
+    HIPCK(hipGetLastError());
+    return ELWH_OK;
+}
+
+elwh_status elwh_solve2(elwh_ctx* c, const double* f, const double* x0, const double* x1, double tol, int maxit,
+                        double* v0, double* v1, elwh_info* info) {
+    if (!c || !f || !v0 || !v1 || maxit < 0) return ELWH_ERR_ARG;
+    if (!twofield_ok(c)) return ELWH_ERR_ARG;
+    c->napply = 0;
+    const size_t FE = (size_t)c->L.field_elems();
+    const Pair x{c->vec[VX], c->vec[VP]}, b{c->vec[VB], c->vec[VD]}, w{c->vec[VQ], c->vec[VR]};
+    double* zero = c->vec[VT];
+    HIPCK(hipMemsetAsync(zero, 0, FE * sizeof(double), c->stream));
+    pack_forcing(c, f, false);
+    run_filter_twofield(c, zero, zero, true, false, c->omega, 1.0 / c->omega, b.a, b.b);   // b = Pi_h [0; 0]
+    const bool xz = x0 == nullptr && x1 == nullptr;
+    if (x0)
+        launch_pack(c->L, c->bc, x0, x.a, c->L.dim, c->stream);
+    else
+        HIPCK(hipMemsetAsync(x.a, 0, FE * sizeof(double), c->stream));
+    if (x1) {
+        launch_pack(c->L, c->bc, x1, x.b, c->L.dim, c->stream);
+        launch_axpby(c, 0.0, x.b, 1.0 / c->omega, x.b, c->stream);
+    } else {
+        HIPCK(hipMemsetAsync(x.b, 0, FE * sizeof(double), c->stream));
+    }
+    int it = 0;
+    double rel = 1.0;
+    elwh_status st = solve_gmres2(c, x, b, w, xz, tol, maxit, &it, &rel);
+    if (st != ELWH_OK && st != ELWH_ERR_NOT_CONVERGED) return st;
+    // the true residual with one more application
+    double bb, rr;
+    CKST(dot2(c, b, b, &bb));
+    apply_A2(c, x, w);
+    axpby2(c, 1.0, b, -1.0, w);
+    CKST(dot2(c, w, w, &rr));
+    launch_unpack(c->L, c->bc, x.a, v0, c->L.dim, c->stream);
+    launch_axpby(c, 0.0, x.b, c->omega, x.b, c->stream);
+    launch_unpack(c->L, c->bc, x.b, v1, c->L.dim, c->stream);
+    HIPCK(hipStreamSynchronize(c->stream));
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->iters = it;
+        info->nt = c->plan.nt;
+        info->napply = c->napply;
+        info->dt = c->plan.dt;
+        info->c = c->plan.c;
+        info->lambda_bound = c->plan.lambda_bound;
+        info->relres = rel;
+        info->relres_fp64 = bb > 0 ? std::sqrt(rr / bb) : 0.0;
+        info->cond_est = NAN;
+    }
+    return st;
 }
 
 }  // extern "C"

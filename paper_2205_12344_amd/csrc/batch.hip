@@ -491,6 +491,9 @@ elwh_status elwh_batch_create(int nprob, const elwh_grid* grids, const double* c
     co.autotune = 0;
     for (int p = 0; p < nprob; ++p) {
         if (grids[p].dim != 2) return fail(ELWH_ERR_ARG, "batches hold 2-D problems");
+        for (int f = 0; f < 6; ++f)
+            if (bc[6 * p + f] == ELWH_BC_IMPEDANCE)
+                return fail(ELWH_ERR_ARG, "impedance faces need the two-field solve (elwh_solve2), not the batch");
         elwh_ctx* c = nullptr;
         const elwh_status st = elwh_create(&grids[p], rho[p], lam[p], mu[p], omega[p], bc + 6 * p, &co, &c);
         if (st != ELWH_OK) return fail(st, "problem " + std::to_string(p) + ": " + elwh_last_error(nullptr));

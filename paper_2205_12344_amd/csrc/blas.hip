@@ -239,6 +239,55 @@ __global__ void axpby_kernel(double a, const double* __restrict__ x, double b, d
         y[e] = a * x[e] + b * y[e];
 }
 
+// Orthogonalisation of the two-field GMRES: a vector is a pair of fields
+// (V[2i], V[2i+1]).  Block (b, i) of multidot2 adds the M-weighted products
+// of pair i with (wa, wb) over its grid-stride share into partials[i nb + b];
+// multireduce sums the nb partials of each i in a fixed order.
+__global__ __launch_bounds__(RB) void multidot2_kernel(const double* const* __restrict__ V,
+                                                       const double* __restrict__ wa,
+                                                       const double* __restrict__ wb,
+                                                       const double* __restrict__ m, int ncomp, int64_t CS,
+                                                       double* __restrict__ partials) {
+    const int i = blockIdx.y, nb = gridDim.x;
+    const double* __restrict__ va = V[2 * i];
+    const double* __restrict__ vb = V[2 * i + 1];
+    double s = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * RB + threadIdx.x; e < CS; e += (int64_t)nb * RB) {
+        double t = 0.0;
+        for (int c = 0; c < ncomp; ++c) {
+            const int64_t o = e + c * CS;
+            t += va[o] * wa[o] + vb[o] * wb[o];
+        }
+        s += m[e] * t;
+    }
+    s = block_sum(s);
+    if (threadIdx.x == 0) partials[(int64_t)i * nb + blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(RB) void multireduce_kernel(const double* __restrict__ partials, int nb,
+                                                         double* __restrict__ out) {
+    double v = 0.0;
+    for (int k = threadIdx.x; k < nb; k += RB) v += partials[(int64_t)blockIdx.x * nb + k];
+    v = block_sum(v);
+    if (threadIdx.x == 0) out[blockIdx.x] = v;
+}
+
+// (wa, wb) -= sum_i h[i] (V[2i], V[2i+1]) over n elements of each field.
+__global__ __launch_bounds__(RB) void multiaxpy2_kernel(const double* const* __restrict__ V, int k,
+                                                        const double* __restrict__ h, double* __restrict__ wa,
+                                                        double* __restrict__ wb, int64_t n) {
+    for (int64_t e = (int64_t)blockIdx.x * RB + threadIdx.x; e < n; e += (int64_t)gridDim.x * RB) {
+        double a = wa[e], b = wb[e];
+        for (int i = 0; i < k; ++i) {
+            const double hi = h[i];
+            a -= hi * V[2 * i][e];
+            b -= hi * V[2 * i + 1][e];
+        }
+        wa[e] = a;
+        wb[e] = b;
+    }
+}
+
 __global__ void copy_kernel(const double* __restrict__ x, double* __restrict__ y, int64_t n) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
         y[e] = x[e];
@@ -300,6 +349,22 @@ void launch_cg_update_p(const elwh_ctx* c, double* p, const double* r, hipStream
 void launch_axpby(const elwh_ctx* c, double a, const double* x, double b, double* y, hipStream_t s) {
     const int64_t n = c->L.field_elems();
     hipLaunchKernelGGL(axpby_kernel, dim3(grid_for(n)), dim3(256), 0, s, a, x, b, y, n);
+}
+
+int multidot2_blocks(const elwh_ctx* c) { return (int)std::min<int64_t>(256, grid_for(c->L.CS, RB)); }
+
+void launch_multidot2(const elwh_ctx* c, const double* const* V, int k, const double* wa, const double* wb,
+                      double* partials, double* out, hipStream_t s) {
+    const int nb = multidot2_blocks(c);
+    hipLaunchKernelGGL(multidot2_kernel, dim3(nb, k), dim3(RB), 0, s, V, wa, wb, c->mw, c->L.dim, c->L.CS,
+                       partials);
+    hipLaunchKernelGGL(multireduce_kernel, dim3(k), dim3(RB), 0, s, partials, nb, out);
+}
+
+void launch_multiaxpy2(const elwh_ctx* c, const double* const* V, int k, const double* h, double* wa, double* wb,
+                       hipStream_t s) {
+    const int64_t n = c->L.field_elems();
+    hipLaunchKernelGGL(multiaxpy2_kernel, dim3(grid_for(n, RB)), dim3(RB), 0, s, V, k, h, wa, wb, n);
 }
 
 void launch_copy(const elwh_ctx* c, const double* x, double* y, hipStream_t s) {

@@ -68,6 +68,15 @@ struct Args2D {
     int final_;
 };
 
+// Two-field step on a 2-D grid with impedance y faces (kernels2d_damped.hip).
+struct Damp2D {
+    Args2D A;                 // geometry, stencil constants, w (of u^{n+1}), w0 (of u^0), fc
+    double wv;                // weight of the centred velocity of level n (step launch)
+    double w0v;               // weight of the second field (start launch)
+    double dtw;               // dt times the scale of the second field (start launch)
+    int imp_lo, imp_hi;       // the -y / +y face is an impedance face
+};
+
 // Batched problem descriptor (device copy built by the host per phase).
 struct BProb2D {
     Args2D A;                 // geometry and stencil constants
@@ -162,6 +171,19 @@ struct elwh_ctx {
     std::vector<int> prof_nsteps;      // step launches per recorded application
     size_t prof_used = 0;              // applications recorded since the last read
 
+    // impedance y faces (two-field path): flags, damping rows g (4 x P: u and v
+    // of the -y face, then of the +y face), the velocity accumulator and the
+    // second field of the input, GMRES basis of the two-field solve
+    int imp[2] = {0, 0};
+    double* dmp = nullptr;
+    double* acc1 = nullptr;
+    double* x1 = nullptr;
+    std::vector<double*> basis2;
+    double** gm_ptrs = nullptr;        // device copy of the basis2 pointers, then the pair w
+    double* gm_part = nullptr;         // multidot partials
+    double* gm_h = nullptr;            // device Gram-Schmidt coefficients and ||w||^2
+    int gm_cap = 0;                    // pairs the three buffers above hold
+
     // CG state of the stepwise interface
     bool cg_active = false;
     bool cg_qready = false;            // q = A_h p already computed for the next CG iteration
@@ -206,6 +228,16 @@ bool tile_valid_3d(bool fp32, int V, int TZ);
 bool tile_valid_curv(bool fp32, int V, int TY);
 // One filter application on a mapped 2-D grid (kernels2d_curv.hip).
 void run_filter_curv2d(elwh_ctx* c, const double* x, bool with_force, bool amode, bool fp32, double* out);
+// Two-field step of the impedance path (kernels2d_damped.hip).  mode 1 (start):
+// u = u^0, uprev = the second field, base0/base1 the A_h bases or null;
+// mode 0: u = u^n, uprev = u^{n-1} (unext may alias it), acc0/acc1 updated.
+// dmp: four rows of P values, the damping g of (u, v) on the -y, then +y face.
+bool tile_valid_damped(int V, int TY);
+void launch_damped2d(int V, int TY, int mode, bool force, hipStream_t s, const double* u, const double* uprev,
+                     double* unext, const double* base0, const double* base1, double* acc0, double* acc1,
+                     const double* dmp, const double* ca, const double* cl, const double* cm, const double* f,
+                     const Damp2D& D);
+Args2D make_args2d(const elwh_ctx* c);
 // dst[comp][node] *= w[node] over the padded layout (blas.hip).
 void launch_scale_field(const Layout& L, double* dst, const double* w, int ncomp, hipStream_t s);
 
@@ -246,6 +278,15 @@ void launch_cg_update_xr(const elwh_ctx* c, double* x, double* r, const double* 
 void launch_cg_update_p(const elwh_ctx* c, double* p, const double* r, hipStream_t s);
 void launch_axpby(const elwh_ctx* c, double a, const double* x, double b, double* y, hipStream_t s);
 void launch_copy(const elwh_ctx* c, const double* x, double* y, hipStream_t s);
+// Two-field GMRES orthogonalisation (blas.hip).  V: device array of 2k field
+// pointers, pair i = (V[2i], V[2i+1]).  launch_multidot2: out[i] = (pair i,
+// (wa, wb))_M for i < k (partials: k * multidot2_blocks(c) doubles);
+// launch_multiaxpy2: (wa, wb) -= sum_i h[i] pair i, h on the device.
+int multidot2_blocks(const elwh_ctx* c);
+void launch_multidot2(const elwh_ctx* c, const double* const* V, int k, const double* wa, const double* wb,
+                      double* partials, double* out, hipStream_t s);
+void launch_multiaxpy2(const elwh_ctx* c, const double* const* V, int k, const double* h, double* wa, double* wb,
+                       hipStream_t s);
 
 enum { RED_SUM = 0, RED_PQ = 1, RED_RR = 2 };
 

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libelwh.so")
 
 OK, ERR_ARG, ERR_ALLOC, ERR_HIP, ERR_UNSTABLE, ERR_NOT_CONVERGED, ERR_BREAKDOWN = range(7)
 STATUS_NAMES = ["OK", "ERR_ARG", "ERR_ALLOC", "ERR_HIP", "ERR_UNSTABLE", "ERR_NOT_CONVERGED", "ERR_BREAKDOWN"]
-BC_DIRICHLET, BC_TRACTION_FREE = 0, 1
+BC_DIRICHLET, BC_TRACTION_FREE, BC_IMPEDANCE = 0, 1, 2
 FP64, FP32_STEP = 0, 1
 KRYLOV_CG, KRYLOV_GMRES, KRYLOV_CR = 0, 1, 2
 SCHEME_CORRECTED, SCHEME_STANDARD = 0, 1
@@ -27,6 +27,7 @@ EXPORTED = [
     "elwh_default_opts", "elwh_plan", "elwh_create", "elwh_plan_mapped", "elwh_create_mapped",
     "elwh_filter_diagnostics", "elwh_destroy", "elwh_query", "elwh_last_error",
     "elwh_apply_filter", "elwh_apply_A", "elwh_solve", "elwh_cg_begin", "elwh_cg_iterate",
+    "elwh_apply_filter2", "elwh_apply_A2", "elwh_solve2",
     "elwh_cg_result", "elwh_dot_M", "elwh_profile_enable", "elwh_profile_read",
     "elwh_set_tile", "elwh_get_tile", "elwh_autotune",
     "elwh_batch_create", "elwh_batch_solve", "elwh_batch_set_graph", "elwh_batch_info", "elwh_batch_stats",
@@ -97,6 +98,9 @@ def _load():
     lib.elwh_apply_filter.argtypes = [P, P, P, P]
     lib.elwh_apply_A.argtypes = [P, P, P]
     lib.elwh_solve.argtypes = [P, P, P, D, I, P, ctypes.POINTER(Info)]
+    lib.elwh_apply_filter2.argtypes = [P, P, P, P, P, P]
+    lib.elwh_apply_A2.argtypes = [P, P, P, P, P]
+    lib.elwh_solve2.argtypes = [P, P, P, P, D, I, P, P, ctypes.POINTER(Info)]
     lib.elwh_cg_begin.argtypes = [P, P, P]
     lib.elwh_cg_iterate.argtypes = [P, I, D, ctypes.POINTER(D)]
     lib.elwh_cg_result.argtypes = [P, P, ctypes.POINTER(Info)]
@@ -309,6 +313,41 @@ class Context:
         if st != OK and raise_on_fail:
             self._check(st)
         return v, d
+
+    # two-field operator (impedance faces)
+    def apply_filter2(self, u0, u1, f=None):
+        """(out0, out1) = Pi_h [u0; u1]: filtered displacement and velocity."""
+        u0, u1 = self._field(u0, "u0"), self._field(u1, "u1")
+        ft = self._field(f, "f") if f is not None else None
+        o0 = torch.empty(self.field_shape, dtype=torch.float64, device="cuda")
+        o1 = torch.empty(self.field_shape, dtype=torch.float64, device="cuda")
+        self._check(lib.elwh_apply_filter2(self._h, u0.data_ptr(), u1.data_ptr(),
+                                           ft.data_ptr() if ft is not None else None, o0.data_ptr(), o1.data_ptr()))
+        return o0, o1
+
+    def apply_A2(self, x0, x1):
+        x0, x1 = self._field(x0, "x0"), self._field(x1, "x1")
+        y0 = torch.empty(self.field_shape, dtype=torch.float64, device="cuda")
+        y1 = torch.empty(self.field_shape, dtype=torch.float64, device="cuda")
+        self._check(lib.elwh_apply_A2(self._h, x0.data_ptr(), x1.data_ptr(), y0.data_ptr(), y1.data_ptr()))
+        return y0, y1
+
+    def solve2(self, f, x0=None, x1=None, tol=1e-10, maxit=1000, raise_on_fail=True):
+        """GMRES for the two-field fixed point: (u0, u1, info)."""
+        f = self._field(f, "f")
+        a = self._field(x0, "x0") if x0 is not None else None
+        b = self._field(x1, "x1") if x1 is not None else None
+        v0 = torch.empty(self.field_shape, dtype=torch.float64, device="cuda")
+        v1 = torch.empty(self.field_shape, dtype=torch.float64, device="cuda")
+        info = Info()
+        st = lib.elwh_solve2(self._h, f.data_ptr(), a.data_ptr() if a is not None else None,
+                             b.data_ptr() if b is not None else None, float(tol), int(maxit), v0.data_ptr(),
+                             v1.data_ptr(), ctypes.byref(info))
+        d = info.as_dict()
+        d["status"] = STATUS_NAMES[st]
+        if st != OK and raise_on_fail:
+            self._check(st)
+        return v0, v1, d
 
     # stepwise CG
     def cg_begin(self, f, x0=None):

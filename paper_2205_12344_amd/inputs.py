@@ -36,6 +36,7 @@ DIRICHLET = 0
 FREE = 1
 BC_ALL_DIRICHLET_2D = (0, 0, 0, 0)
 BC_FREE_TOP_2D = (0, 0, 0, 1)        # Dirichlet sides and bottom, free top
+BC_ABSORBING_Y_2D = (0, 0, 2, 2)     # Dirichlet sides, impedance bottom and top
 BC_ALL_DIRICHLET_3D = (0, 0, 0, 0, 0, 0)
 
 
@@ -192,6 +193,15 @@ def random_square(n=1024, seed=2, ppw=10.0):
     omega = 2 * math.pi * min_shear_speed(rho, mu) / (ppw * h)
     return Case(f"square{n}_random", 2, (n, n), omega, rho, lam, mu, f, BC_FREE_TOP_2D,
                 tol=1e-8, meta={"seed": seed, "center": x0.tolist(), "direction": e.tolist()})
+
+
+def absorbing_square(n=1024, seed=2, ppw=10.0):
+    """The random_square medium, source and omega with both y faces absorbing
+    (impedance), Dirichlet x faces: the input of the two-field solve."""
+    c = random_square(n, seed, ppw)
+    c.name = f"square{n}_absorbing"
+    c.bc = BC_ABSORBING_Y_2D
+    return c
 
 
 def layered_cube(n=256, seed=3, ppw=8.0):

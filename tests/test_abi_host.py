@@ -293,3 +293,15 @@ def test_product_code_never_touches_the_oracle():
                 txt = open(os.path.join(dirpath, f), errors="replace").read()
                 assert not re.search(r"^\s*(from|import)\s+oracle\b", txt, flags=re.M), f
                 assert "oracle/" not in txt, f
+
+
+def test_plan_treats_impedance_faces_as_traction_type(elwh):
+    """The time-step plan of impedance faces is that of traction-free faces
+    (the damping does not enter the Gershgorin bound)."""
+    import numpy as np
+    rng = np.random.default_rng(5)
+    shape = (31, 41)
+    rho, lam, mu = 1 + rng.random(shape), 2 + rng.random(shape), 1 + rng.random(shape)
+    a = elwh.plan(2, (40, 30), rho, lam, mu, 9.0, (0, 0, 2, 2))
+    b = elwh.plan(2, (40, 30), rho, lam, mu, 9.0, (0, 0, 1, 1))
+    assert a == b
