@@ -30,8 +30,8 @@
  *    Dirichlet-face nodes hold 0: inputs there are ignored, outputs there
  *    are written as 0.  Traction-free faces are supported on the +-y faces in
  *    2-D and the +-z faces in 3-D; the x faces (and y faces in 3-D) must be
- *    Dirichlet.  Impedance (absorbing) faces: +-y in 2-D, two-field entry
- *    points only.
+ *    Dirichlet.  Impedance (absorbing) faces: any face in 2-D, two-field
+ *    entry points only.
  *  - Calls are asynchronous on the context's stream unless stated otherwise.
  *    One context must not be used from two threads at once.
  *  - Errors are returned as elwh_status; nothing aborts or throws across the
@@ -57,10 +57,10 @@ typedef enum {
 } elwh_status;
 
 /* ELWH_BC_IMPEDANCE: an absorbing face T(u) n = -Z u_t (Z = rho c_p on the
- * normal, rho c_s on the tangential component); only on the -y and +y faces
- * of 2-D Cartesian grids with FP64 stepping, and only through the two-field
- * entry points elwh_apply_filter2 / elwh_apply_A2 / elwh_solve2 (the
- * one-field ones return ELWH_ERR_ARG on such a context). */
+ * normal, rho c_s on the tangential component); on any face of 2-D
+ * Cartesian grids with FP64 stepping, and only through the two-field entry
+ * points elwh_apply_filter2 / elwh_apply_A2 / elwh_solve2 (the one-field
+ * ones return ELWH_ERR_ARG on such a context). */
 enum { ELWH_BC_DIRICHLET = 0, ELWH_BC_TRACTION_FREE = 1, ELWH_BC_IMPEDANCE = 2 };
 enum { ELWH_FP64 = 0, ELWH_FP32_STEP = 1 };
 enum { ELWH_KRYLOV_CG = 0, ELWH_KRYLOV_GMRES = 1, ELWH_KRYLOV_CR = 2 };
@@ -241,8 +241,9 @@ elwh_status elwh_filter_diagnostics(int nt, int periods, double omega, int schem
  * velocity u1, v^n = (u^{n+1} - u^{n-1}) / (2 dt) its centred velocity
  * (v^0 = u1; one step past the window gives v^{K N_T}), w_n the trapezoid
  * weights of elwh_apply_filter.  An impedance face is a traction-type face of
- * the discrete energy (Sec. 4.1) whose rows carry the damping B = 2 c / h_y
- * (c = c_p for the normal, c_s for the tangential component), stepped as
+ * the discrete energy (Sec. 4.1) whose rows carry the damping B = 2 c / h
+ * (c = c_p for the normal, c_s for the tangential component, h the spacing
+ * normal to the face; the two faces' terms add at a corner), stepped as
  *     (1 + g) u^{n+1} = 2 u^n - (1 - g) u^{n-1} + a (Ltilde u^n - f cos(omega t_n)),
  * g = c dt Bt / 2 with Bt = B omega dt / sin(omega dt) for the corrected
  * scheme (Bt = B for the standard one), so that the fixed point reproduces

@@ -115,7 +115,7 @@ void free_all(elwh_ctx* c) {
     f(c->acc); f(c->acc_lo); f(c->f64); f(c->f32);
     for (auto* v : c->vec) f(v);
     for (auto* v : c->basis) f(v);
-    f(c->dmp); f(c->acc1); f(c->x1);
+    f(c->dmp); f(c->dmpx); f(c->acc1); f(c->x1);
     for (auto* v : c->basis2) f(v);
     f(c->gm_ptrs); f(c->gm_part); f(c->gm_h);
     f(c->partials); f(c->dscal);
@@ -517,22 +517,23 @@ elwh_status create_impl(const elwh_grid* grid_in, const double* xc, const double
         gbuf.len[0] = gbuf.len[1] = 1.0;   // the reference square: h_q = 1/n_q, h_r = 1/n_r
     }
     // impedance faces: traction-type faces of the energy plus boundary damping
-    int imp[2] = {0, 0};
+    int imp[2] = {0, 0}, ximp[2] = {0, 0};
     for (int f = 0; f < 6; ++f) {
         if (bc[f] != ELWH_BC_IMPEDANCE) continue;
-        if (mapped || gbuf.dim != 2 || f < 2 || f > 3) {
-            g_create_err = "impedance faces are supported on the -y and +y faces of 2-D Cartesian grids";
+        if (mapped || gbuf.dim != 2 || f > 3) {
+            g_create_err = "impedance faces are supported on the faces of 2-D Cartesian grids";
             return ELWH_ERR_ARG;
         }
         if (o.prec != ELWH_FP64) {
             g_create_err = "impedance faces need FP64 stepping";
             return ELWH_ERR_ARG;
         }
-        imp[f - 2] = 1;
+        (f < 2 ? ximp[f] : imp[f - 2]) = 1;
         bc[f] = ELWH_BC_TRACTION_FREE;
     }
+    const bool x_free_ok = ximp[0] || ximp[1];
     const elwh_grid* grid = &gbuf;
-    elwh_status st = check_config(grid, bc, &o, &g_create_err);
+    elwh_status st = check_config(grid, bc, &o, &g_create_err, x_free_ok);
     if (st != ELWH_OK) return st;
     if (!rho || !lam || !mu) {
         g_create_err = "null material array";
@@ -544,6 +545,8 @@ elwh_status create_impl(const elwh_grid* grid_in, const double* xc, const double
     c->mapped = mapped;
     c->imp[0] = imp[0];
     c->imp[1] = imp[1];
+    c->ximp[0] = ximp[0];
+    c->ximp[1] = ximp[1];
     for (int f = 0; f < 6; ++f) c->bc[f] = f < 2 * grid->dim ? bc[f] : ELWH_BC_DIRICHLET;
     c->omega = omega;
     c->opts = o;
@@ -579,7 +582,7 @@ elwh_status create_impl(const elwh_grid* grid_in, const double* xc, const double
         st = make_plan_mapped(grid, hx.data(), hy.data(), hr.data(), hl.data(), hm.data(), omega, c->bc, &o,
                               &c->plan, &met, &c->err);
     } else {
-        st = make_plan(grid, hr.data(), hl.data(), hm.data(), omega, c->bc, &o, &c->plan, &c->err);
+        st = make_plan(grid, hr.data(), hl.data(), hm.data(), omega, c->bc, &o, &c->plan, &c->err, x_free_ok);
     }
     if (st != ELWH_OK) return fail(st);
 
@@ -692,28 +695,42 @@ elwh_status create_impl(const elwh_grid* grid_in, const double* xc, const double
             return fail(ELWH_ERR_HIP);
         }
     }
-    if (imp[0] || imp[1]) {
-        // damping g = c dt Bt / 2 of the two face rows, B = 2 c_s / h_y (u, tangential)
-        // and 2 c_p / h_y (v, normal), Bt = B omega dt / sin(omega dt) for the
+    if (imp[0] || imp[1] || ximp[0] || ximp[1]) {
+        // damping g = c dt Bt / 2 of the face rows and columns, B = 2 c / h
+        // (c = c_p for the normal, c_s for the tangential component, h the
+        // spacing normal to the face), Bt = B omega dt / sin(omega dt) for the
         // corrected scheme; the velocity accumulator and the second input field
-        const size_t P = (size_t)L.P;
-        if ((st = alloc_t(c, &c->dmp, 4 * P)) || (st = alloc_t(c, &c->acc1, FE)) || (st = alloc_t(c, &c->x1, FE)))
+        const size_t P = (size_t)L.P, NY = (size_t)L.ny + 1;
+        if ((st = alloc_t(c, &c->dmp, 4 * P)) || (st = alloc_t(c, &c->dmpx, 4 * NY)) ||
+            (st = alloc_t(c, &c->acc1, FE)) || (st = alloc_t(c, &c->x1, FE)))
             return fail(st);
-        std::vector<double> hd(4 * P, 0.0);
-        const double hy = grid->len[1] / grid->n[1];
+        std::vector<double> hd(4 * P, 0.0), hdx(4 * NY, 0.0);
+        const double hx = grid->len[0] / grid->n[0], hy = grid->len[1] / grid->n[1];
         const double wdt = omega * c->plan.dt;
         const double rescale = o.scheme == ELWH_SCHEME_CORRECTED ? wdt / std::sin(wdt) : 1.0;
-        const double gfac = 0.5 * c->plan.c * c->plan.dt * rescale * 2.0 / hy;
+        const double gfac = 0.5 * c->plan.c * c->plan.dt * rescale * 2.0;
+        auto cs_at = [&](int64_t k) { return std::sqrt(hm[k] / hr[k]); };
+        auto cp_at = [&](int64_t k) { return std::sqrt((hl[k] + 2.0 * hm[k]) / hr[k]); };
         for (int side = 0; side < 2; ++side) {
-            if (!imp[side]) continue;
-            const int j = side ? L.ny : 0;
-            for (int x = 0; x <= L.nx; ++x) {
-                const int64_t src = (int64_t)j * (L.nx + 1) + x;
-                hd[(2 * side) * P + x] = gfac * std::sqrt(hm[src] / hr[src]);
-                hd[(2 * side + 1) * P + x] = gfac * std::sqrt((hl[src] + 2.0 * hm[src]) / hr[src]);
+            if (imp[side]) {
+                const int j = side ? L.ny : 0;
+                for (int x = 0; x <= L.nx; ++x) {
+                    const int64_t src = (int64_t)j * (L.nx + 1) + x;
+                    hd[(2 * side) * P + x] = gfac / hy * cs_at(src);       // u tangential
+                    hd[(2 * side + 1) * P + x] = gfac / hy * cp_at(src);   // v normal
+                }
+            }
+            if (ximp[side]) {
+                const int x = side ? L.nx : 0;
+                for (int j = 0; j <= L.ny; ++j) {
+                    const int64_t src = (int64_t)j * (L.nx + 1) + x;
+                    hdx[(2 * side) * NY + j] = gfac / hx * cp_at(src);     // u normal
+                    hdx[(2 * side + 1) * NY + j] = gfac / hx * cs_at(src); // v tangential
+                }
             }
         }
         if (hipMemcpyAsync(c->dmp, hd.data(), 4 * P * 8, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+            hipMemcpyAsync(c->dmpx, hdx.data(), 4 * NY * 8, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
             hipStreamSynchronize(c->stream) != hipSuccess) {
             c->err = "uploading the damping rows failed";
             return fail(ELWH_ERR_HIP);
@@ -723,6 +740,9 @@ elwh_status create_impl(const elwh_grid* grid_in, const double* xc, const double
     if (mapped) {
         c->tile64 = Tile{1, 8};
         c->tile32 = Tile{2, 8};
+    } else if (imp[0] || imp[1] || ximp[0] || ximp[1]) {
+        c->tile64 = Tile{1, 8};   // the two-field step kernel (fewer registers at V = 1)
+        c->tile32 = Tile{4, 8};
     } else if (c->L.dim == 2) {
         c->tile64 = Tile{2, 8};
         c->tile32 = Tile{4, 8};
@@ -774,8 +794,9 @@ elwh_status elwh_plan(const elwh_grid* grid, const double* rho, const double* la
     }
     int bcp[6];
     for (int f = 0; f < 6; ++f) bcp[f] = bc[f] == ELWH_BC_IMPEDANCE ? ELWH_BC_TRACTION_FREE : bc[f];
+    const bool x_free_ok = grid && grid->dim == 2 && (bc[0] == ELWH_BC_IMPEDANCE || bc[1] == ELWH_BC_IMPEDANCE);
     Plan p;
-    elwh_status st = make_plan(grid, rho, lam, mu, omega, bcp, &o, &p, &g_create_err);
+    elwh_status st = make_plan(grid, rho, lam, mu, omega, bcp, &o, &p, &g_create_err, x_free_ok);
     if (st != ELWH_OK) return st;
     if (info) {
         std::memset(info, 0, sizeof(*info));
@@ -853,7 +874,7 @@ const char* elwh_last_error(const elwh_ctx* c) { return c ? c->err.c_str() : g_c
 
 elwh_status elwh_apply_filter(elwh_ctx* c, const double* u0, const double* f, double* out) {
     if (!c || !u0 || !out) return ELWH_ERR_ARG;
-    if (c->imp[0] || c->imp[1]) {
+    if (c->imp[0] || c->imp[1] || c->ximp[0] || c->ximp[1]) {
         c->err = "a context with impedance faces takes the two-field entry points (elwh_apply_filter2, "
                  "elwh_apply_A2, elwh_solve2)";
         return ELWH_ERR_ARG;
@@ -1194,8 +1215,10 @@ elwh_status elwh_set_tile(elwh_ctx* c, int prec, int vec, int rows) {
 }  // extern "C"
 
 namespace {
+void run_filter_twofield(elwh_ctx* c, const double* x0, const double* z1, bool with_force, bool amode, double s_in,
+                         double s_out, double* out0, double* out1);
 // dim, prec, variant (bit 0: compensated accumulator, bits 1-2: steps per
-// 2-D launch minus one, bit 3: mapped grid), nx, ny, nz
+// 2-D launch minus one, bit 3: mapped grid, bit 4: two-field step), nx, ny, nz
 using TuneKey = std::tuple<int, int, int, int, int, int>;
 std::mutex g_tune_mu;
 std::map<TuneKey, Tile> g_tune;
@@ -1255,8 +1278,11 @@ elwh_status elwh_autotune(elwh_ctx* c, int prec, int reps, double* best_step_us)
         c->err = "FP32 tiling needs an FP32 context";
         return ELWH_ERR_ARG;
     }
-    const int steps = c->L.dim == 2 && !c->mapped ? c->opts.fuse : 1;
-    const int comp = (fp32 && c->opts.compensated ? 1 : 0) | ((steps - 1) << 1) | (c->mapped ? 8 : 0);
+    // a context with impedance faces runs the two-field step kernel: tune that
+    const bool twofield = !fp32 && (c->imp[0] || c->imp[1] || c->ximp[0] || c->ximp[1]);
+    const int steps = c->L.dim == 2 && !c->mapped && !twofield ? c->opts.fuse : 1;
+    const int comp = (fp32 && c->opts.compensated ? 1 : 0) | ((steps - 1) << 1) | (c->mapped ? 8 : 0) |
+                     (twofield ? 16 : 0);
     const TuneKey key(c->L.dim, fp32 ? 1 : 0, comp, c->L.nx, c->L.ny, c->L.nz);
     Tile& dst = fp32 ? c->tile32 : c->tile64;
     {
@@ -1278,7 +1304,11 @@ elwh_status elwh_autotune(elwh_ctx* c, int prec, int reps, double* best_step_us)
         return ELWH_OK;
     }
     std::vector<Tile> cands;
-    if (c->mapped) {
+    if (twofield) {
+        for (int V : {1, 2})
+            for (int TY : {4, 8, 16})
+                if (tile_valid_damped(V, TY)) cands.push_back(Tile{V, TY});
+    } else if (c->mapped) {
         for (int V : {1, 2})
             for (int TY : {8, 16})
                 if (tile_valid_curv(fp32, V, TY)) cands.push_back(Tile{V, TY});
@@ -1302,9 +1332,15 @@ elwh_status elwh_autotune(elwh_ctx* c, int prec, int reps, double* best_step_us)
     Tile bt = dst;
     for (const Tile& t : cands) {
         dst = t;
-        apply_A(c, in, out, fp32);   // warm-up (first launch of this instantiation)
+        auto once = [&]() {
+            if (twofield)
+                run_filter_twofield(c, in, in, false, true, 1.0, 1.0, out, c->acc1);
+            else
+                apply_A(c, in, out, fp32);
+        };
+        once();   // warm-up (first launch of this instantiation)
         (void)hipEventRecord(e0, c->stream);
-        for (int r = 0; r < reps; ++r) apply_A(c, in, out, fp32);
+        for (int r = 0; r < reps; ++r) once();
         (void)hipEventRecord(e1, c->stream);
         if (hipEventSynchronize(e1) != hipSuccess) break;
         float ms = 0.f;
@@ -1356,8 +1392,8 @@ bool twofield_ok(elwh_ctx* c) {
     if (!c->acc1) {
         // a context without impedance faces: allocate the two-field buffers now
         const size_t P = (size_t)c->L.P, FE = (size_t)c->L.field_elems();
-        if (alloc_t(c, &c->dmp, 4 * P) != ELWH_OK || alloc_t(c, &c->acc1, FE) != ELWH_OK ||
-            alloc_t(c, &c->x1, FE) != ELWH_OK)
+        if (alloc_t(c, &c->dmp, 4 * P) != ELWH_OK || alloc_t(c, &c->dmpx, 4 * ((size_t)c->L.ny + 1)) != ELWH_OK ||
+            alloc_t(c, &c->acc1, FE) != ELWH_OK || alloc_t(c, &c->x1, FE) != ELWH_OK)
             return false;
     }
     return true;
@@ -1372,6 +1408,10 @@ void run_filter_twofield(elwh_ctx* c, const double* x0, const double* z1, bool w
     D.A = make_args2d(c);
     D.imp_lo = c->imp[0];
     D.imp_hi = c->imp[1];
+    D.ximp_lo = c->ximp[0];
+    D.ximp_hi = c->ximp[1];
+    D.hx = c->grid.len[0] / c->grid.n[0];
+    D.hy = c->grid.len[1] / c->grid.n[1];
     const Tile t = tile_valid_damped(c->tile64.V, c->tile64.TY) ? c->tile64 : Tile{2, 8};
     const int N = c->plan.nt * c->opts.periods;
     const double sgn = amode ? -1.0 : 1.0, dt = c->plan.dt;
@@ -1383,7 +1423,7 @@ void run_filter_twofield(elwh_ctx* c, const double* x0, const double* z1, bool w
     D.wv = 0.0;
     prof_mark(c, 0);
     launch_damped2d(t.V, t.TY, 1, with_force, s, x0, z1, c->s64[1], amode ? x0 : nullptr, amode ? z1 : nullptr,
-                    out0, out1, c->dmp, c->ca, c->cl, c->cm, c->f64, D);
+                    out0, out1, c->dmp, c->dmpx, c->ca, c->cl, c->cm, c->f64, D);
     prof_mark(c, 1);
     const double* prev = x0;
     double* cur = c->s64[1];
@@ -1401,8 +1441,8 @@ void run_filter_twofield(elwh_ctx* c, const double* x0, const double* z1, bool w
         D.A.w = n < N ? sgn * c->w[n + 1] : 0.0;   // the step past the window adds velocity only
         D.A.fc = c->cosn[n];
         D.wv = sgn * c->w[n] * s_out / (2.0 * dt);
-        launch_damped2d(t.V, t.TY, 0, with_force, s, cur, prev, nxt, nullptr, nullptr, out0, out1, c->dmp, c->ca,
-                        c->cl, c->cm, c->f64, D);
+        launch_damped2d(t.V, t.TY, 0, with_force, s, cur, prev, nxt, nullptr, nullptr, out0, out1, c->dmp, c->dmpx,
+                        c->ca, c->cl, c->cm, c->f64, D);
         prev = cur;
         cur = nxt;
     }

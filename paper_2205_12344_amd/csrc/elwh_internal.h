@@ -75,6 +75,9 @@ struct Damp2D {
     double w0v;               // weight of the second field (start launch)
     double dtw;               // dt times the scale of the second field (start launch)
     int imp_lo, imp_hi;       // the -y / +y face is an impedance face
+    int ximp_lo, ximp_hi;     // the -x / +x face is an impedance face (its column is computed)
+    double hx, hy;            // grid spacings (the x-face rows)
+    int nmain;                // blocks of the strip march; face-column blocks follow (set at launch)
 };
 
 // Batched problem descriptor (device copy built by the host per phase).
@@ -175,7 +178,9 @@ struct elwh_ctx {
     // of the -y face, then of the +y face), the velocity accumulator and the
     // second field of the input, GMRES basis of the two-field solve
     int imp[2] = {0, 0};
+    int ximp[2] = {0, 0};              // impedance -x / +x faces
     double* dmp = nullptr;
+    double* dmpx = nullptr;
     double* acc1 = nullptr;
     double* x1 = nullptr;
     std::vector<double*> basis2;
@@ -210,8 +215,12 @@ elwh_status make_plan_mapped(const elwh_grid* g, const double* x, const double* 
 elwh_status filter_diagnostics(int nt, int periods, double omega, int scheme, elwh_filter_diag* out,
                                std::string* err);
 elwh_status make_plan(const elwh_grid* g, const double* rho, const double* lam, const double* mu,
-                      double omega, const int bc[6], const elwh_opts* o, Plan* out, std::string* err);
-elwh_status check_config(const elwh_grid* g, const int bc[6], const elwh_opts* o, std::string* err);
+                      double omega, const int bc[6], const elwh_opts* o, Plan* out, std::string* err,
+                      bool x_free_ok = false);
+// x_free_ok: traction-type x faces are allowed (2-D impedance x faces of the
+// two-field path); otherwise only the marching axis takes them.
+elwh_status check_config(const elwh_grid* g, const int bc[6], const elwh_opts* o, std::string* err,
+                         bool x_free_ok = false);
 Layout make_layout(const elwh_grid* g);
 Stencil make_stencil(const elwh_grid* g);
 March make_march(const elwh_grid* g, const int bc[6]);
@@ -231,12 +240,13 @@ void run_filter_curv2d(elwh_ctx* c, const double* x, bool with_force, bool amode
 // Two-field step of the impedance path (kernels2d_damped.hip).  mode 1 (start):
 // u = u^0, uprev = the second field, base0/base1 the A_h bases or null;
 // mode 0: u = u^n, uprev = u^{n-1} (unext may alias it), acc0/acc1 updated.
-// dmp: four rows of P values, the damping g of (u, v) on the -y, then +y face.
+// dmp: four rows of P values, the damping g of (u, v) on the -y, then +y face;
+// dmpx: four columns of ny + 1 values, the same on the -x, then +x face.
 bool tile_valid_damped(int V, int TY);
 void launch_damped2d(int V, int TY, int mode, bool force, hipStream_t s, const double* u, const double* uprev,
                      double* unext, const double* base0, const double* base1, double* acc0, double* acc1,
-                     const double* dmp, const double* ca, const double* cl, const double* cm, const double* f,
-                     const Damp2D& D);
+                     const double* dmp, const double* dmpx, const double* ca, const double* cl, const double* cm,
+                     const double* f, const Damp2D& D);
 Args2D make_args2d(const elwh_ctx* c);
 // dst[comp][node] *= w[node] over the padded layout (blas.hip).
 void launch_scale_field(const Layout& L, double* dst, const double* w, int ncomp, hipStream_t s);

@@ -1,4 +1,4 @@
-// 2-D two-field El-WaveHoltz step for impedance (absorbing) y faces, FP64.
+// 2-D two-field El-WaveHoltz step for impedance (absorbing) faces, FP64.
 //
 // The filter of the remark in Sec. 3 acts on the initial displacement and
 // velocity together, Pi [u0; u1] = (2/T) int (cos(omega t) - 1/4) [u; u_t] dt.
@@ -15,8 +15,14 @@
 // step beyond the window supplies the velocity of the last level.
 //
 // The impedance face is a traction-type face of the discrete energy
-// (Sec. 4.1), so the stencil rows are the traction-free closure of the
-// one-field kernels; the damping values are per x node of the two face rows.
+// (Sec. 4.1): on the y faces the stencil rows are the traction-free closure
+// of the one-field kernels; on an impedance x face the face column's rows
+// (corners included) are the energy gradient evaluated directly, by extra
+// blocks of the same launch (one row per lane) so that the strip march keeps
+// its registers, while the rows one column inside keep the interior stencil
+// (the x face's half weight and its one-sided difference cancel there).  The
+// damping values are per node of the face rows and columns; at a corner the
+// two faces' terms add.
 // Mapping and loads are those of the one-field single-step kernel: one
 // 64-lane wavefront per x-strip of 64 V columns, TY rows marched upward with
 // the three stencil rows in registers and the next row's loads issued one
@@ -26,6 +32,64 @@
 namespace elwh {
 
 namespace {
+
+// Ltilde at a node of an impedance (traction-type) x face, column i with
+// inward neighbour column i + d (d = +1 on the -x face, -1 on the +x face),
+// from the discrete energy: compact terms with the edge-to-node weight
+// ratio (2 across the x face, and 2 along y on a free y face), and the cross
+// terms lambda X(u) Y(v) + mu Y(u) X(v) of the nodes whose differences
+// involve this one -- the node itself, its inward neighbour and its
+// neighbours along the face -- each with its trapezoid weight, X one-sided
+// on the face column and central inside, Y one-sided on free y faces.
+// S, C, N: rows j-1, j, j+1 at column i; Si, Ci, Ni: the same at column
+// i + d (lI, mI the inward node's lambda, mu).
+__device__ __forceinline__ void xface_rows(double d, int j, int ny, bool free_lo, bool free_hi, double cxx2,
+                                           double cyy2, double hx, double hy, double uS, double uC, double uN,
+                                           double vS, double vC, double vN, double uSi, double uCi, double uNi,
+                                           double vSi, double vCi, double vNi, double lS, double lC, double lN,
+                                           double mS, double mC, double mN, double lI, double mI, double& Lu,
+                                           double& Lv) {
+    const bool onlo = free_lo && j == 0, onhi = free_hi && j == ny, onface = onlo || onhi;
+    const bool hasS = j > 0, hasN = j < ny;
+    const double fy = onface ? 2.0 : 1.0;
+    const double AC = lC + 2.0 * mC, AI = lI + 2.0 * mI, AS = lS + 2.0 * mS, AN = lN + 2.0 * mN;
+    double cu = 2.0 * cxx2 * (AI + AC) * (uCi - uC);
+    double cv = 2.0 * cxx2 * (mI + mC) * (vCi - vC);
+    if (hasN) {
+        cu += fy * cyy2 * (mN + mC) * (uN - uC);
+        cv += fy * cyy2 * (AN + AC) * (vN - vC);
+    }
+    if (hasS) {
+        cu -= fy * cyy2 * (mC + mS) * (uC - uS);
+        cv -= fy * cyy2 * (AC + AS) * (vC - vS);
+    }
+    auto ydiff = [&](double fs, double fc, double fn, int jj) {
+        if (free_lo && jj == 0) return (fn - fc) / hy;
+        if (free_hi && jj == ny) return (fc - fs) / hy;
+        return (fn - fs) / (2.0 * hy);
+    };
+    const double wp = onface ? 0.25 : 0.5, wI = onface ? 0.5 : 1.0;
+    const double cXp = -d / hx, cXi = -d / (2.0 * hx);
+    const double cYp = onlo ? -1.0 / hy : (onhi ? 1.0 / hy : 0.0);
+    double xu = wp * (lC * cXp * ydiff(vS, vC, vN, j) + mC * cYp * d * (vCi - vC) / hx);
+    double xv = wp * (lC * d * (uCi - uC) / hx * cYp + mC * ydiff(uS, uC, uN, j) * cXp);
+    xu += wI * lI * cXi * ydiff(vSi, vCi, vNi, j);
+    xv += wI * mI * ydiff(uSi, uCi, uNi, j) * cXi;
+    if (hasN && !(j + 1 == ny && !free_hi)) {
+        const bool on = free_hi && j + 1 == ny;
+        const double wN = on ? 0.25 : 0.5, cY = on ? -1.0 / hy : -0.5 / hy;
+        xu += wN * mN * cY * d * (vNi - vN) / hx;
+        xv += wN * lN * d * (uNi - uN) / hx * cY;
+    }
+    if (hasS && !(j - 1 == 0 && !free_lo)) {
+        const bool on = free_lo && j - 1 == 0;
+        const double wS = on ? 0.25 : 0.5, cY = on ? 1.0 / hy : 0.5 / hy;
+        xu += wS * mS * cY * d * (vSi - vS) / hx;
+        xv += wS * lS * d * (uSi - uS) / hx * cY;
+    }
+    Lu = cu - xu / wp;
+    Lv = cv - xv / wp;
+}
 
 template <int V, int MODE, bool FORCE>
 struct DCentre {
@@ -41,9 +105,9 @@ __device__ __forceinline__ void damped2d_body(int bx, int by, const double* __re
                                               double* unext, const double* __restrict__ base0,
                                               const double* __restrict__ base1, double* __restrict__ acc0,
                                               double* __restrict__ acc1, const double* __restrict__ dmp,
-                                              const double* __restrict__ ca, const double* __restrict__ cl,
-                                              const double* __restrict__ cm, const double* __restrict__ f,
-                                              const Damp2D& D) {
+                                              const double* __restrict__ dmpx, const double* __restrict__ ca,
+                                              const double* __restrict__ cl, const double* __restrict__ cm,
+                                              const double* __restrict__ f, const Damp2D& D) {
     using T = double;
     const Args2D& A = D.A;
     constexpr int W = Cols<V>::W;
@@ -57,7 +121,7 @@ __device__ __forceinline__ void damped2d_body(int bx, int by, const double* __re
     const int P = (int)A.P;
     const int64_t CS = A.CS;
     const T cxx2 = A.cxx2, cyy2 = A.cyy2, cxy = A.cxy, cyyf = A.cyyf, cfx = A.cfx;
-    const int ilo = max(c0 + 1, 1), ihi = min(c0 + W, A.nx - 1);
+    const int ilo = max(c0 + 1, 1), ihi = min(c0 + W, A.nx - 1);   // columns 1..nx-1
 
     auto load_raw = [&](int j, RawRow<T, V>& r) {
         if (colv && j >= 0 && j <= A.ny) {
@@ -200,31 +264,106 @@ __device__ __forceinline__ void damped2d_body(int bx, int by, const double* __re
     }
 }
 
+// The face column of an impedance x face, one row per lane: block fb of the
+// face blocks takes 64 rows of the -x face column (fb < nchunk when that
+// face is an impedance face) or of the +x face column.  Same update and
+// accumulation as the strip march; strided loads (two columns only).
+template <int MODE, bool FORCE>
+__device__ __forceinline__ void damped2d_face(int fb, const double* __restrict__ u, const double* uprev,
+                                              double* unext, const double* __restrict__ base0,
+                                              const double* __restrict__ base1, double* __restrict__ acc0,
+                                              double* __restrict__ acc1, const double* __restrict__ dmp,
+                                              const double* __restrict__ dmpx, const double* __restrict__ ca,
+                                              const double* __restrict__ cl, const double* __restrict__ cm,
+                                              const double* __restrict__ f, const Damp2D& D) {
+    const Args2D& A = D.A;
+    const int nchunk = (A.jhi - A.jlo + 1 + 63) / 64;
+    const bool lo = D.ximp_lo && fb < nchunk;
+    const int j = A.jlo + (fb % nchunk) * 64 + (int)threadIdx.x;
+    if (j > A.jhi) return;
+    const int i = lo ? 0 : A.nx, in = lo ? 1 : A.nx - 1;
+    const int64_t P = A.P, CS = A.CS, o = (int64_t)j * P + i;
+    auto at = [&](const double* b, int ii, int jj) { return (jj >= 0 && jj <= A.ny) ? b[jj * P + ii] : 0.0; };
+    const double* v = u + CS;
+    double Lu, Lv;
+    xface_rows(lo ? 1.0 : -1.0, j, A.ny, A.free_lo, A.free_hi, A.cxx2, A.cyy2, D.hx, D.hy, at(u, i, j - 1),
+               at(u, i, j), at(u, i, j + 1), at(v, i, j - 1), at(v, i, j), at(v, i, j + 1), at(u, in, j - 1),
+               at(u, in, j), at(u, in, j + 1), at(v, in, j - 1), at(v, in, j), at(v, in, j + 1), at(cl, i, j - 1),
+               at(cl, i, j), at(cl, i, j + 1), at(cm, i, j - 1), at(cm, i, j), at(cm, i, j + 1), at(cl, in, j),
+               at(cm, in, j), Lu, Lv);
+    if constexpr (FORCE) {
+        Lu -= A.fc * f[o];
+        Lv -= A.fc * f[o + CS];
+    }
+    // damping of this face column, plus that of an impedance y face at the corners
+    const double* gx = dmpx + (int64_t)(lo ? 0 : 2) * (A.ny + 1);
+    double gu = gx[j], gv = gx[A.ny + 1 + j];
+    if ((j == 0 && D.imp_lo) || (j == A.ny && D.imp_hi)) {
+        const double* gy = dmp + (int64_t)(j == 0 ? 0 : 2) * P;
+        gu += gy[i];
+        gv += gy[P + i];
+    }
+    const double a = ca[o], uc = u[o], vc = v[o], up = uprev[o], vp = uprev[o + CS];
+    double nu, nv, h0u, h0v, h1u, h1v;
+    if constexpr (MODE == 0) {
+        nu = (2.0 * uc - up + a * Lu + gu * up) / (1.0 + gu);
+        nv = (2.0 * vc - vp + a * Lv + gv * vp) / (1.0 + gv);
+        h0u = acc0[o] + A.w * nu;
+        h0v = acc0[o + CS] + A.w * nv;
+        h1u = acc1[o] + D.wv * (nu - up);
+        h1v = acc1[o + CS] + D.wv * (nv - vp);
+    } else {
+        // up / vp hold the second field u1 here
+        nu = uc + D.dtw * (1.0 - gu) * up + 0.5 * a * Lu;
+        nv = vc + D.dtw * (1.0 - gv) * vp + 0.5 * a * Lv;
+        h0u = (base0 ? base0[o] : 0.0) + A.w0 * uc + A.w * nu;
+        h0v = (base0 ? base0[o + CS] : 0.0) + A.w0 * vc + A.w * nv;
+        h1u = (base1 ? base1[o] : 0.0) + D.w0v * up;
+        h1v = (base1 ? base1[o + CS] : 0.0) + D.w0v * vp;
+    }
+    unext[o] = nu;
+    unext[o + CS] = nv;
+    acc0[o] = h0u;
+    acc0[o + CS] = h0v;
+    acc1[o] = h1u;
+    acc1[o + CS] = h1v;
+}
+
 template <int V, int TY, int MODE, bool FORCE>
 __global__ __launch_bounds__(64) void damped2d_kernel(const double* __restrict__ u, const double* uprev,
                                                      double* unext, const double* __restrict__ base0,
                                                      const double* __restrict__ base1, double* __restrict__ acc0,
                                                      double* __restrict__ acc1, const double* __restrict__ dmp,
-                                                     const double* __restrict__ ca, const double* __restrict__ cl,
-                                                     const double* __restrict__ cm, const double* __restrict__ f,
-                                                     Damp2D D) {
+                                                     const double* __restrict__ dmpx, const double* __restrict__ ca,
+                                                     const double* __restrict__ cl, const double* __restrict__ cm,
+                                                     const double* __restrict__ f, Damp2D D) {
+    if ((int)blockIdx.x >= D.nmain) {   // the face-column blocks follow the strip tiles
+        damped2d_face<MODE, FORCE>((int)blockIdx.x - D.nmain, u, uprev, unext, base0, base1, acc0, acc1, dmp, dmpx,
+                                   ca, cl, cm, f, D);
+        return;
+    }
     const int nbx = (D.A.nx - 1 + Cols<V>::W - 1) / Cols<V>::W;
     const int nby = (D.A.jhi - D.A.jlo + 1 + TY - 1) / TY;
     int t;
     if (!xcd_tile((int)blockIdx.x, nbx * nby, t)) return;
-    damped2d_body<V, TY, MODE, FORCE>(t % nbx, t / nbx, u, uprev, unext, base0, base1, acc0, acc1, dmp, ca, cl, cm,
-                                      f, D);
+    damped2d_body<V, TY, MODE, FORCE>(t % nbx, t / nbx, u, uprev, unext, base0, base1, acc0, acc1, dmp, dmpx, ca,
+                                      cl, cm, f, D);
 }
 
 template <int V, int TY>
 void damped_launch_vt(int mode, bool force, hipStream_t s, const double* u, const double* uprev, double* unext,
                       const double* base0, const double* base1, double* acc0, double* acc1, const double* dmp,
-                      const double* ca, const double* cl, const double* cm, const double* f, const Damp2D& D) {
+                      const double* dmpx, const double* ca, const double* cl, const double* cm, const double* f,
+                      const Damp2D& Din) {
+    Damp2D D = Din;
     const int nrows = D.A.jhi - D.A.jlo + 1;
-    const dim3 grid((unsigned)xcd_grid(((D.A.nx - 1 + Cols<V>::W - 1) / Cols<V>::W) * ((nrows + TY - 1) / TY)));
+    const int nbx = (D.A.nx - 1 + Cols<V>::W - 1) / Cols<V>::W;
+    D.nmain = xcd_grid(nbx * ((nrows + TY - 1) / TY));
+    const int nface = (D.ximp_lo + D.ximp_hi) * ((nrows + 63) / 64);
+    const dim3 grid((unsigned)(D.nmain + nface));
 #define ELWH_DL(M, F)                                                                                         \
     hipLaunchKernelGGL((damped2d_kernel<V, TY, M, F>), grid, dim3(64), 0, s, u, uprev, unext, base0, base1,  \
-                       acc0, acc1, dmp, ca, cl, cm, f, D)
+                       acc0, acc1, dmp, dmpx, ca, cl, cm, f, D)
     if (mode == 0) {
         if (force) ELWH_DL(0, true); else ELWH_DL(0, false);
     } else {
@@ -239,17 +378,17 @@ bool tile_valid_damped(int V, int TY) { return (V == 1 || V == 2) && (TY == 4 ||
 
 void launch_damped2d(int V, int TY, int mode, bool force, hipStream_t s, const double* u, const double* uprev,
                      double* unext, const double* base0, const double* base1, double* acc0, double* acc1,
-                     const double* dmp, const double* ca, const double* cl, const double* cm, const double* f,
-                     const Damp2D& D) {
+                     const double* dmp, const double* dmpx, const double* ca, const double* cl, const double* cm,
+                     const double* f, const Damp2D& D) {
 #define ELWH_DV(VV, TT)                                                                                       \
     if (V == VV && TY == TT) {                                                                                \
-        damped_launch_vt<VV, TT>(mode, force, s, u, uprev, unext, base0, base1, acc0, acc1, dmp, ca, cl, cm, f, \
-                                 D);                                                                          \
+        damped_launch_vt<VV, TT>(mode, force, s, u, uprev, unext, base0, base1, acc0, acc1, dmp, dmpx, ca, cl, \
+                                 cm, f, D);                                                                   \
         return;                                                                                               \
     }
     ELWH_DV(1, 4) ELWH_DV(1, 8) ELWH_DV(1, 16) ELWH_DV(2, 4) ELWH_DV(2, 8) ELWH_DV(2, 16)
 #undef ELWH_DV
-    damped_launch_vt<1, 8>(mode, force, s, u, uprev, unext, base0, base1, acc0, acc1, dmp, ca, cl, cm, f, D);
+    damped_launch_vt<1, 8>(mode, force, s, u, uprev, unext, base0, base1, acc0, acc1, dmp, dmpx, ca, cl, cm, f, D);
 }
 
 }  // namespace elwh

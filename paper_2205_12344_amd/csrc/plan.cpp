@@ -559,7 +559,8 @@ elwh_status make_plan_mapped(const elwh_grid* g, const double* x, const double* 
     return plan_from_bound(G, omega, o, out, err);
 }
 
-elwh_status check_config(const elwh_grid* g, const int bc[6], const elwh_opts* o, std::string* err) {
+elwh_status check_config(const elwh_grid* g, const int bc[6], const elwh_opts* o, std::string* err,
+                         bool x_free_ok) {
     if (!g || !bc) { *err = "null grid or bc"; return ELWH_ERR_ARG; }
     if (g->dim != 2 && g->dim != 3) { *err = "dim must be 2 or 3"; return ELWH_ERR_ARG; }
     for (int a = 0; a < g->dim; ++a) {
@@ -572,7 +573,8 @@ elwh_status check_config(const elwh_grid* g, const int bc[6], const elwh_opts* o
     // traction-free faces only on the marching axis (y in 2-D, z in 3-D)
     const int march = g->dim - 1;
     for (int a = 0; a < g->dim; ++a)
-        if (a != march && (bc[2 * a] != ELWH_BC_DIRICHLET || bc[2 * a + 1] != ELWH_BC_DIRICHLET)) {
+        if (a != march && !(x_free_ok && g->dim == 2 && a == 0) &&
+            (bc[2 * a] != ELWH_BC_DIRICHLET || bc[2 * a + 1] != ELWH_BC_DIRICHLET)) {
             *err = g->dim == 2 ? "traction-free faces are supported on the y faces only"
                                : "traction-free faces are supported on the z faces only";
             return ELWH_ERR_ARG;
@@ -595,8 +597,9 @@ elwh_status check_config(const elwh_grid* g, const int bc[6], const elwh_opts* o
 }
 
 elwh_status make_plan(const elwh_grid* g, const double* rho, const double* lam, const double* mu,
-                      double omega, const int bc[6], const elwh_opts* o, Plan* out, std::string* err) {
-    elwh_status st = check_config(g, bc, o, err);
+                      double omega, const int bc[6], const elwh_opts* o, Plan* out, std::string* err,
+                      bool x_free_ok) {
+    elwh_status st = check_config(g, bc, o, err, x_free_ok);
     if (st != ELWH_OK) return st;
     if (!rho || !lam || !mu) { *err = "null material array"; return ELWH_ERR_ARG; }
     if (!(omega > 0) || !std::isfinite(omega)) { *err = "omega must be positive and finite"; return ELWH_ERR_ARG; }

@@ -37,6 +37,7 @@ FREE = 1
 BC_ALL_DIRICHLET_2D = (0, 0, 0, 0)
 BC_FREE_TOP_2D = (0, 0, 0, 1)        # Dirichlet sides and bottom, free top
 BC_ABSORBING_Y_2D = (0, 0, 2, 2)     # Dirichlet sides, impedance bottom and top
+BC_ABSORBING_2D = (2, 2, 2, 2)       # impedance on every face (an open box)
 BC_ALL_DIRICHLET_3D = (0, 0, 0, 0, 0, 0)
 
 
@@ -196,11 +197,11 @@ def random_square(n=1024, seed=2, ppw=10.0):
 
 
 def absorbing_square(n=1024, seed=2, ppw=10.0):
-    """The random_square medium, source and omega with both y faces absorbing
-    (impedance), Dirichlet x faces: the input of the two-field solve."""
+    """The random_square medium, source and omega with every face absorbing
+    (impedance): an open box, the input of the two-field solve."""
     c = random_square(n, seed, ppw)
     c.name = f"square{n}_absorbing"
-    c.bc = BC_ABSORBING_Y_2D
+    c.bc = BC_ABSORBING_2D
     return c
 
 

@@ -305,3 +305,17 @@ def test_plan_treats_impedance_faces_as_traction_type(elwh):
     a = elwh.plan(2, (40, 30), rho, lam, mu, 9.0, (0, 0, 2, 2))
     b = elwh.plan(2, (40, 30), rho, lam, mu, 9.0, (0, 0, 1, 1))
     assert a == b
+
+
+@pytest.mark.parametrize("bc", [(2, 2, 2, 2), (2, 0, 1, 2), (0, 2, 0, 0)])
+def test_plan_with_impedance_x_faces_matches_oracle(elwh, bc):
+    """Impedance x faces are traction-type faces for the time-step plan: the
+    bound equals the oracle's Gershgorin bound with those faces free."""
+    n = (23, 17)
+    prob = Problem(2, n, length=(1.0, 0.7), bc=tuple(1 if b == 2 else b for b in bc))
+    rho, lam, mu = _media(prob.node_shape, 40)
+    G = Operator(prob, rho, lam, mu).gershgorin()
+    p = elwh.plan(2, n, rho, lam, mu, 6.1, bc, length=(1.0, 0.7))
+    assert p["lambda_bound"] == pytest.approx(G, rel=1e-13)
+    with pytest.raises(elwh.ElwhError, match="ERR_ARG"):      # traction-free x faces stay one-field-only
+        elwh.plan(2, n, rho, lam, mu, 6.1, (1, 0, 0, 0), length=(1.0, 0.7))
