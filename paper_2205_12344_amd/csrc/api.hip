@@ -1384,19 +1384,19 @@ elwh_status elwh_get_tile(const elwh_ctx* c, int prec, int* vec, int* rows) {
 
 namespace {
 
-bool twofield_ok(elwh_ctx* c) {
+elwh_status twofield_ready(elwh_ctx* c) {
     if (c->mapped || c->L.dim != 2 || c->opts.prec != ELWH_FP64) {
         c->err = "the two-field operator runs on 2-D Cartesian grids in FP64";
-        return false;
+        return ELWH_ERR_ARG;
     }
-    if (!c->acc1) {
-        // a context without impedance faces: allocate the two-field buffers now
-        const size_t P = (size_t)c->L.P, FE = (size_t)c->L.field_elems();
-        if (alloc_t(c, &c->dmp, 4 * P) != ELWH_OK || alloc_t(c, &c->dmpx, 4 * ((size_t)c->L.ny + 1)) != ELWH_OK ||
-            alloc_t(c, &c->acc1, FE) != ELWH_OK || alloc_t(c, &c->x1, FE) != ELWH_OK)
-            return false;
-    }
-    return true;
+    // a context without impedance faces: allocate the two-field buffers (zero
+    // damping tables) at the first two-field call
+    const size_t P = (size_t)c->L.P, FE = (size_t)c->L.field_elems();
+    if (!c->dmp) CKST(alloc_t(c, &c->dmp, 4 * P));
+    if (!c->dmpx) CKST(alloc_t(c, &c->dmpx, 4 * ((size_t)c->L.ny + 1)));
+    if (!c->acc1) CKST(alloc_t(c, &c->acc1, FE));
+    if (!c->x1) CKST(alloc_t(c, &c->x1, FE));
+    return ELWH_OK;
 }
 
 // out0 = sum w_n u^n, out1 = s_out sum w_n v^n for u^0 = x0 and the second
@@ -1596,7 +1596,7 @@ extern "C" {
 elwh_status elwh_apply_filter2(elwh_ctx* c, const double* u0, const double* u1, const double* f, double* out0,
                                double* out1) {
     if (!c || !u0 || !u1 || !out0 || !out1) return ELWH_ERR_ARG;
-    if (!twofield_ok(c)) return ELWH_ERR_ARG;
+    CKST(twofield_ready(c));
     launch_pack(c->L, c->bc, u0, c->vec[VX], c->L.dim, c->stream);
     launch_pack(c->L, c->bc, u1, c->x1, c->L.dim, c->stream);
     if (f) pack_forcing(c, f, false);
@@ -1609,7 +1609,7 @@ elwh_status elwh_apply_filter2(elwh_ctx* c, const double* u0, const double* u1, 
 
 elwh_status elwh_apply_A2(elwh_ctx* c, const double* x0, const double* x1, double* y0, double* y1) {
     if (!c || !x0 || !x1 || !y0 || !y1) return ELWH_ERR_ARG;
-    if (!twofield_ok(c)) return ELWH_ERR_ARG;
+    CKST(twofield_ready(c));
     launch_pack(c->L, c->bc, x0, c->vec[VX], c->L.dim, c->stream);
     launch_pack(c->L, c->bc, x1, c->x1, c->L.dim, c->stream);
     run_filter_twofield(c, c->vec[VX], c->x1, false, true, 1.0, 1.0, c->vec[VQ], c->acc1);
@@ -1622,7 +1622,7 @@ elwh_status elwh_apply_A2(elwh_ctx* c, const double* x0, const double* x1, doubl
 elwh_status elwh_solve2(elwh_ctx* c, const double* f, const double* x0, const double* x1, double tol, int maxit,
                         double* v0, double* v1, elwh_info* info) {
     if (!c || !f || !v0 || !v1 || maxit < 0) return ELWH_ERR_ARG;
-    if (!twofield_ok(c)) return ELWH_ERR_ARG;
+    CKST(twofield_ready(c));
     c->napply = 0;
     const size_t FE = (size_t)c->L.field_elems();
     const Pair x{c->vec[VX], c->vec[VP]}, b{c->vec[VB], c->vec[VD]}, w{c->vec[VQ], c->vec[VR]};
