@@ -257,8 +257,9 @@ elwh_status elwh_filter_diagnostics(int nt, int periods, double omega, int schem
  * layout above.
  *
  * elwh_apply_filter2  out0, out1 = Pi_h [u0; u1] with forcing f (NULL: S_h).
- * elwh_apply_A2       [y0; y1] = [x0; x1] - S_h [x0; x1]; no aliasing of
- *                     inputs with outputs of the other field.
+ * elwh_apply_A2       [y0; y1] = [x0; x1] - S_h [x0; x1].  In both calls the
+ *                     inputs are copied before any output is written, so
+ *                     inputs and outputs may alias.
  * elwh_solve2         the fixed point by restarted GMRES (opts.gmres_m, CGS2)
  *                     on A_h z = Pi_h [0; 0] for the stacked z = [u0; u1 /
  *                     omega] in the M inner product of each half, from

@@ -391,6 +391,24 @@ elwh_status solve_cr(elwh_ctx* c, bool x_zero, double tol, int maxit, int* iters
     return tol > 0 ? ELWH_ERR_NOT_CONVERGED : ELWH_OK;
 }
 
+// Device buffers of the GMRES orthogonalisation for restart length m: the
+// pointer table (up to 2 (m + 1) basis fields, then the two fields of w),
+// the multi-dot partials and the coefficients of the two CGS passes plus
+// ||w||^2.
+elwh_status ensure_gm(elwh_ctx* c, int m) {
+    if (c->gm_cap >= m + 1) return ELWH_OK;
+    for (void* q : {(void*)c->gm_ptrs, (void*)c->gm_part, (void*)c->gm_h})
+        if (q) (void)hipFree(q);
+    c->gm_ptrs = nullptr;
+    c->gm_part = c->gm_h = nullptr;
+    c->gm_cap = 0;
+    CKST(alloc_t(c, &c->gm_ptrs, (size_t)(2 * (m + 1) + 2)));
+    CKST(alloc_t(c, &c->gm_part, (size_t)(m + 1) * multidot2_blocks(c)));
+    CKST(alloc_t(c, &c->gm_h, (size_t)(2 * (m + 1) + 1)));
+    c->gm_cap = m + 1;
+    return ELWH_OK;
+}
+
 elwh_status solve_gmres(elwh_ctx* c, bool x_zero, double tol, int maxit, int* iters, double* relres) {
     const int m = c->opts.gmres_m;
     while ((int)c->basis.size() < m + 1) {
@@ -401,6 +419,16 @@ elwh_status solve_gmres(elwh_ctx* c, bool x_zero, double tol, int maxit, int* it
     double* x = c->vec[VX];
     double* w = c->vec[VQ];
     const double* b = c->vec[VB];
+    CKST(ensure_gm(c, m));
+    {
+        std::vector<double*> tab(c->basis.begin(), c->basis.begin() + (m + 1));
+        tab.push_back(w);
+        HIPCK(hipMemcpyAsync(c->gm_ptrs, tab.data(), tab.size() * sizeof(double*), hipMemcpyHostToDevice,
+                             c->stream));
+        HIPCK(hipStreamSynchronize(c->stream));   // tab is a host temporary
+    }
+    const double* const* ptrs = c->gm_ptrs;
+    std::vector<double> hh(2 * (m + 1) + 1);
     double bb;
     CKST(dot_host(c, b, b, &bb));
     const double bn = std::sqrt(bb);
@@ -435,16 +463,18 @@ elwh_status solve_gmres(elwh_ctx* c, bool x_zero, double tol, int maxit, int* it
         for (int j = 0; j < m; ++j) {
             apply_A(c, c->basis[j], w, false);
             total++;
-            for (int pass = 0; pass < 2; ++pass) {  // classical Gram-Schmidt, twice
-                std::vector<double> h(j + 1);
-                for (int i = 0; i <= j; ++i) CKST(dot_host(c, c->basis[i], w, &h[i]));
-                for (int i = 0; i <= j; ++i) {
-                    launch_axpby(c, -h[i], c->basis[i], 1.0, w, c->stream);
-                    H[i * m + j] += h[i];
-                }
+            // classical Gram-Schmidt twice, coefficients on the device, one
+            // host synchronisation per iteration
+            for (int pass = 0; pass < 2; ++pass) {
+                double* hp = c->gm_h + pass * (m + 1);
+                launch_multidot2(c, ptrs, j + 1, w, nullptr, c->gm_part, hp, c->stream);
+                launch_multiaxpy2(c, ptrs, j + 1, hp, w, nullptr, c->stream);
             }
-            double ww;
-            CKST(dot_host(c, w, w, &ww));
+            launch_multidot2(c, ptrs + (m + 1), 1, w, nullptr, c->gm_part, c->gm_h + 2 * (m + 1), c->stream);
+            HIPCK(hipMemcpyAsync(hh.data(), c->gm_h, hh.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+            HIPCK(hipStreamSynchronize(c->stream));
+            for (int i = 0; i <= j; ++i) H[i * m + j] += hh[i] + hh[m + 1 + i];
+            const double ww = hh[2 * (m + 1)];
             const double hn = std::sqrt(ww);
             H[(j + 1) * m + j] = hn;
             for (int i = 0; i < j; ++i) {
@@ -1489,18 +1519,7 @@ elwh_status solve_gmres2(elwh_ctx* c, Pair x, Pair b, Pair w, bool x_zero, doubl
         CKST(alloc_t(c, &v, FE));
         c->basis2.push_back(v);
     }
-    if (c->gm_cap < m + 1) {
-        // device pointer table (basis pairs, then w), multidot partials, coefficients
-        for (void* q : {(void*)c->gm_ptrs, (void*)c->gm_part, (void*)c->gm_h})
-            if (q) (void)hipFree(q);
-        c->gm_ptrs = nullptr;
-        c->gm_part = c->gm_h = nullptr;
-        c->gm_cap = 0;
-        CKST(alloc_t(c, &c->gm_ptrs, (size_t)(2 * (m + 1) + 2)));
-        CKST(alloc_t(c, &c->gm_part, (size_t)(m + 1) * multidot2_blocks(c)));
-        CKST(alloc_t(c, &c->gm_h, (size_t)(2 * (m + 1) + 1)));
-        c->gm_cap = m + 1;
-    }
+    CKST(ensure_gm(c, m));
     {
         std::vector<double*> tab(c->basis2.begin(), c->basis2.begin() + 2 * (m + 1));
         tab.push_back(w.a);
@@ -1515,6 +1534,16 @@ elwh_status solve_gmres2(elwh_ctx* c, Pair x, Pair b, Pair w, bool x_zero, doubl
     double bb;
     CKST(dot2(c, b, b, &bb));
     const double bn = std::sqrt(bb);
+    if (!(bn > 0)) {
+        // b = 0: the solution is zero whatever the start
+        HIPCK(hipMemsetAsync(x.a, 0, FE * sizeof(double), c->stream));
+        HIPCK(hipMemsetAsync(x.b, 0, FE * sizeof(double), c->stream));
+        *iters = 0;
+        *relres = 0.0;
+        if (std::isfinite(bb)) return ELWH_OK;
+        c->err = "non-finite right-hand side: the time step is unstable";
+        return ELWH_ERR_UNSTABLE;
+    }
     int total = 0;
     bool first = true;
     std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
@@ -1535,9 +1564,9 @@ elwh_status solve_gmres2(elwh_ctx* c, Pair x, Pair b, Pair w, bool x_zero, doubl
             c->err = "non-finite residual: the time step is unstable";
             return ELWH_ERR_UNSTABLE;
         }
-        *relres = bn > 0 ? beta / bn : 0.0;
+        *relres = beta / bn;
         *iters = total;
-        if (bn == 0 || (tol > 0 && *relres <= tol) || total >= maxit) break;
+        if ((tol > 0 && *relres <= tol) || total >= maxit) break;
         axpby2(c, 0.0, r, 1.0 / beta, r);
         std::fill(H.begin(), H.end(), 0.0);
         std::fill(g.begin(), g.end(), 0.0);

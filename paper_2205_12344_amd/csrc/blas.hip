@@ -239,24 +239,28 @@ __global__ void axpby_kernel(double a, const double* __restrict__ x, double b, d
         y[e] = a * x[e] + b * y[e];
 }
 
-// Orthogonalisation of the two-field GMRES: a vector is a pair of fields
-// (V[2i], V[2i+1]).  Block (b, i) of multidot2 adds the M-weighted products
-// of pair i with (wa, wb) over its grid-stride share into partials[i nb + b];
-// multireduce sums the nb partials of each i in a fixed order.
-__global__ __launch_bounds__(RB) void multidot2_kernel(const double* const* __restrict__ V,
-                                                       const double* __restrict__ wa,
-                                                       const double* __restrict__ wb,
-                                                       const double* __restrict__ m, int ncomp, int64_t CS,
-                                                       double* __restrict__ partials) {
+// Orthogonalisation of GMRES with the coefficients on the device: a Krylov
+// vector is H fields, V[H i .. H i + H - 1] (H = 2 for the two-field
+// operator, 1 otherwise).  Block (b, i) of multidot adds the M-weighted
+// products of vector i with w over its grid-stride share into
+// partials[i nb + b]; multireduce sums the nb partials of each i in a fixed
+// order.
+template <int H>
+__global__ __launch_bounds__(RB) void multidot_kernel(const double* const* __restrict__ V,
+                                                      const double* __restrict__ wa,
+                                                      const double* __restrict__ wb,
+                                                      const double* __restrict__ m, int ncomp, int64_t CS,
+                                                      double* __restrict__ partials) {
     const int i = blockIdx.y, nb = gridDim.x;
-    const double* __restrict__ va = V[2 * i];
-    const double* __restrict__ vb = V[2 * i + 1];
+    const double* __restrict__ va = V[H * i];
+    const double* __restrict__ vb = V[H * i + H - 1];
     double s = 0.0;
     for (int64_t e = (int64_t)blockIdx.x * RB + threadIdx.x; e < CS; e += (int64_t)nb * RB) {
         double t = 0.0;
         for (int c = 0; c < ncomp; ++c) {
             const int64_t o = e + c * CS;
-            t += va[o] * wa[o] + vb[o] * wb[o];
+            t += va[o] * wa[o];
+            if (H == 2) t += vb[o] * wb[o];
         }
         s += m[e] * t;
     }
@@ -272,19 +276,20 @@ __global__ __launch_bounds__(RB) void multireduce_kernel(const double* __restric
     if (threadIdx.x == 0) out[blockIdx.x] = v;
 }
 
-// (wa, wb) -= sum_i h[i] (V[2i], V[2i+1]) over n elements of each field.
-__global__ __launch_bounds__(RB) void multiaxpy2_kernel(const double* const* __restrict__ V, int k,
-                                                        const double* __restrict__ h, double* __restrict__ wa,
-                                                        double* __restrict__ wb, int64_t n) {
+// w -= sum_i h[i] V_i over n elements of each field.
+template <int H>
+__global__ __launch_bounds__(RB) void multiaxpy_kernel(const double* const* __restrict__ V, int k,
+                                                       const double* __restrict__ h, double* __restrict__ wa,
+                                                       double* __restrict__ wb, int64_t n) {
     for (int64_t e = (int64_t)blockIdx.x * RB + threadIdx.x; e < n; e += (int64_t)gridDim.x * RB) {
-        double a = wa[e], b = wb[e];
+        double a = wa[e], b = H == 2 ? wb[e] : 0.0;
         for (int i = 0; i < k; ++i) {
             const double hi = h[i];
-            a -= hi * V[2 * i][e];
-            b -= hi * V[2 * i + 1][e];
+            a -= hi * V[H * i][e];
+            if (H == 2) b -= hi * V[H * i + 1][e];
         }
         wa[e] = a;
-        wb[e] = b;
+        if (H == 2) wb[e] = b;
     }
 }
 
@@ -356,15 +361,22 @@ int multidot2_blocks(const elwh_ctx* c) { return (int)std::min<int64_t>(256, gri
 void launch_multidot2(const elwh_ctx* c, const double* const* V, int k, const double* wa, const double* wb,
                       double* partials, double* out, hipStream_t s) {
     const int nb = multidot2_blocks(c);
-    hipLaunchKernelGGL(multidot2_kernel, dim3(nb, k), dim3(RB), 0, s, V, wa, wb, c->mw, c->L.dim, c->L.CS,
-                       partials);
+    if (wb)
+        hipLaunchKernelGGL(multidot_kernel<2>, dim3(nb, k), dim3(RB), 0, s, V, wa, wb, c->mw, c->L.dim, c->L.CS,
+                           partials);
+    else
+        hipLaunchKernelGGL(multidot_kernel<1>, dim3(nb, k), dim3(RB), 0, s, V, wa, wa, c->mw, c->L.dim, c->L.CS,
+                           partials);
     hipLaunchKernelGGL(multireduce_kernel, dim3(k), dim3(RB), 0, s, partials, nb, out);
 }
 
 void launch_multiaxpy2(const elwh_ctx* c, const double* const* V, int k, const double* h, double* wa, double* wb,
                        hipStream_t s) {
     const int64_t n = c->L.field_elems();
-    hipLaunchKernelGGL(multiaxpy2_kernel, dim3(grid_for(n, RB)), dim3(RB), 0, s, V, k, h, wa, wb, n);
+    if (wb)
+        hipLaunchKernelGGL(multiaxpy_kernel<2>, dim3(grid_for(n, RB)), dim3(RB), 0, s, V, k, h, wa, wb, n);
+    else
+        hipLaunchKernelGGL(multiaxpy_kernel<1>, dim3(grid_for(n, RB)), dim3(RB), 0, s, V, k, h, wa, wa, n);
 }
 
 void launch_copy(const elwh_ctx* c, const double* x, double* y, hipStream_t s) {

@@ -288,10 +288,12 @@ void launch_cg_update_xr(const elwh_ctx* c, double* x, double* r, const double* 
 void launch_cg_update_p(const elwh_ctx* c, double* p, const double* r, hipStream_t s);
 void launch_axpby(const elwh_ctx* c, double a, const double* x, double b, double* y, hipStream_t s);
 void launch_copy(const elwh_ctx* c, const double* x, double* y, hipStream_t s);
-// Two-field GMRES orthogonalisation (blas.hip).  V: device array of 2k field
-// pointers, pair i = (V[2i], V[2i+1]).  launch_multidot2: out[i] = (pair i,
-// (wa, wb))_M for i < k (partials: k * multidot2_blocks(c) doubles);
-// launch_multiaxpy2: (wa, wb) -= sum_i h[i] pair i, h on the device.
+// GMRES orthogonalisation with device coefficients (blas.hip).  Two-field
+// (wb != null): V is a device array of 2k field pointers, vector i = (V[2i],
+// V[2i+1]); one-field (wb == null): k pointers, vector i = V[i].
+// launch_multidot2: out[i] = (vector i, w)_M for i < k (partials:
+// k * multidot2_blocks(c) doubles); launch_multiaxpy2: w -= sum_i h[i]
+// vector i, h on the device.
 int multidot2_blocks(const elwh_ctx* c);
 void launch_multidot2(const elwh_ctx* c, const double* const* V, int k, const double* wa, const double* wb,
                       double* partials, double* out, hipStream_t s);

@@ -297,6 +297,25 @@ def test_gmres_and_cr_match_direct(E, krylov_id):
     assert _rel(prob.gather(v.cpu().numpy()), vstar) <= 1e-9
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_gmres_iterations_match_oracle(E, dim):
+    """GMRES(20) with the Gram-Schmidt coefficients on the device takes the
+    oracle's GMRES(20) iteration count (CGS2 in the M inner product)."""
+    n = (40, 30) if dim == 2 else (14, 12, 10)
+    bc = (0, 0, 0, 1) if dim == 2 else (0, 0, 0, 0, 0, 1)
+    rho, lam, mu = _media(tuple(k + 1 for k in reversed(n)), 62)
+    om = 6.3 if dim == 2 else 4.1
+    prob, op, wh = _oracle(dim, n, None, bc, rho, lam, mu, om)
+    rng = np.random.default_rng(14)
+    f = rng.standard_normal(prob.field_shape) * prob.unknown_mask()
+    ctx = E.Context(dim, n, rho, lam, mu, om, bc, krylov=1, gmres_m=20)
+    v, info = ctx.solve(f, tol=1e-10, maxit=500)
+    res = krylov.gmres(wh.apply_A, wh.rhs(prob.gather(f)), op.m, tol=1e-10, maxit=500, restart=20)
+    _say("gmres", dim, info["iters"], res.iters)
+    assert res.converged and abs(info["iters"] - res.iters) <= 2, (info["iters"], res.iters)
+    assert _rel(prob.gather(v.cpu().numpy()), res.x) <= 1e-8
+
+
 def test_fp32_refinement_reaches_fp64_residual(E):
     """FP32 stepping + FP64 iterative refinement: the FP64-recomputed residual
     reaches 1e-8 and the solution matches the direct solve."""

@@ -236,3 +236,25 @@ def test_open_box_iterations_match_oracle_and_grow_like_omega(E):
         counts.append((w, info["iters"]))
     slope = np.polyfit(np.log([c[0] for c in counts]), np.log([c[1] for c in counts]), 1)[0]
     assert 0.6 <= slope <= 1.2, (counts, slope)
+
+
+def test_zero_forcing_and_aliasing(E):
+    """f = 0 gives the zero solution from any start; inputs and outputs of
+    apply_filter2 / apply_A2 may alias."""
+    import torch
+    ctx, prob, tf, (u0, u1, f), (du0, du1, df) = _setup(E, (70, 52), (2, 2, 2, 1), 51, 6.6)
+    v0, v1, info = ctx.solve2(torch.zeros_like(df), x0=du0, x1=du1, tol=1e-10, maxit=10)
+    assert info["iters"] == 0 and float(v0.abs().max()) == 0.0 and float(v1.abs().max()) == 0.0
+    r0, r1 = tf.apply_filter(prob.gather(u0), prob.gather(u1), prob.gather(f))
+    a0, a1 = du0.clone(), du1.clone()
+    lib = E.lib
+    st = lib.elwh_apply_filter2(ctx._h, a0.data_ptr(), a1.data_ptr(), df.data_ptr(), a0.data_ptr(), a1.data_ptr())
+    assert st == E.OK
+    assert _rel(prob.gather(a0.cpu().numpy()), r0) <= FP64_TOL
+    assert _rel(prob.gather(a1.cpu().numpy()), r1) <= FP64_TOL
+    b0, b1 = du0.clone(), du1.clone()
+    st = lib.elwh_apply_A2(ctx._h, b0.data_ptr(), b1.data_ptr(), b1.data_ptr(), b0.data_ptr())   # swapped outputs
+    assert st == E.OK
+    s0, s1 = tf.apply_filter(prob.gather(u0), prob.gather(u1))
+    assert _rel(prob.gather(b1.cpu().numpy()), prob.gather(u0) - s0) <= FP64_TOL
+    assert _rel(prob.gather(b0.cpu().numpy()), prob.gather(u1) - s1) <= FP64_TOL
