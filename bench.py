@@ -214,6 +214,16 @@ def twofield_rates(elwh, inputs, napply=3, solve=True):
         out["gmres_to_1e-8"] = {"seconds": round(el, 3), "iters": info["iters"], "napply": info["napply"],
                                 "status": info["status"], "relres_fp64": info["relres_fp64"], "gmres_m": 30,
                                 "step_share": round(info["napply"] * (info["nt"] + 1) * avg_s / el, 3)}
+        # the same solve with two periods per application (eq. many_periods_filter)
+        c2 = elwh.context_from_case(case, periods=2)
+        c2.solve2(f, tol=1e-2, maxit=3, raise_on_fail=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, i2 = c2.solve2(f, tol=1e-8, maxit=4000, raise_on_fail=False)
+        el2 = time.perf_counter() - t0
+        out["gmres_to_1e-8_two_periods"] = {"seconds": round(el2, 3), "iters": i2["iters"], "status": i2["status"],
+                                            "relres_fp64": i2["relres_fp64"], "gmres_m": 30}
+        c2.close()
     ctx.close()
     log(f"two-field: {out}")
     return out

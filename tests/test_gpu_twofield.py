@@ -258,3 +258,28 @@ def test_zero_forcing_and_aliasing(E):
     s0, s1 = tf.apply_filter(prob.gather(u0), prob.gather(u1))
     assert _rel(prob.gather(b1.cpu().numpy()), prob.gather(u0) - s0) <= FP64_TOL
     assert _rel(prob.gather(b0.cpu().numpy()), prob.gather(u1) - s1) <= FP64_TOL
+
+
+def test_open_box_k_periods_match_oracle(E):
+    """Two periods per application (eq. many_periods_filter) on the open box:
+    GPU GMRES = oracle GMRES iterations (+-2) and fewer than with one period."""
+    import torch
+    from oracle.problem import FREE as FR
+    w = 16 + math.sqrt(2) / 10
+    n = int(4 * w + 1)
+    shape = (n + 1, n + 1)
+    one = np.ones(shape)
+    f = np.zeros((2,) + shape)
+    f[0, n // 2, n // 2] = w * w * n * n
+    prob = Problem(2, (n, n), bc=(FR,) * 4)
+    op = Operator(prob, one, 2 * one, one)
+    its = {}
+    for K in (1, 2):
+        ctx = E.Context(2, (n, n), one, 2 * one, one, w, (2, 2, 2, 2), gmres_m=100, periods=K)
+        _, _, info = ctx.solve2(torch.tensor(f, device="cuda"), tol=1e-8, maxit=1000)
+        tf = TwoField(op, w, [(0, 0), (0, 1), (1, 0), (1, 1)], nt=info["nt"], periods=K)
+        _, _, res = tf.solve(prob.gather(f), tol=1e-8, maxit=1000, restart=100)
+        _say("open box K", K, info["iters"], res.iters)
+        assert abs(info["iters"] - res.iters) <= 2
+        its[K] = info["iters"]
+    assert its[2] < 0.7 * its[1], its
