@@ -319,3 +319,28 @@ def test_plan_with_impedance_x_faces_matches_oracle(elwh, bc):
     assert p["lambda_bound"] == pytest.approx(G, rel=1e-13)
     with pytest.raises(elwh.ElwhError, match="ERR_ARG"):      # traction-free x faces stay one-field-only
         elwh.plan(2, n, rho, lam, mu, 6.1, (1, 0, 0, 0), length=(1.0, 0.7))
+
+
+def test_plain_c_client(elwh, tmp_path):
+    """The header is plain C99 and the library links into a C program: the
+    host-only plan of the 64^2 constant square from C equals the known values
+    (N_T = 121, G = (5 lambda + 13 mu) 64^2), and an argument error comes
+    back as ELWH_ERR_ARG."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    here = os.path.dirname(os.path.abspath(__file__))
+    root = os.path.dirname(here)
+    lib_dir = os.path.join(root, "paper_2205_12344_amd")
+    exe = str(tmp_path / "plan_check")
+    subprocess.run([gcc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror",
+                    "-I", os.path.join(root, "include"), os.path.join(here, "c_abi", "plan_check.c"),
+                    "-o", exe, "-L", lib_dir, "-lelwh", "-Wl,-rpath," + lib_dir], check=True)
+    out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout.split("\n")
+    f = out[0].split()
+    assert int(f[1]) == 121
+    assert float(f[7]) == pytest.approx((5 * 2 + 13 * 1) * 64 ** 2, rel=1e-14)
+    assert float(out[1].split()[1]) > 0
+    assert out[2].startswith("bad omega -> 1")
