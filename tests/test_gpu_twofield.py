@@ -167,19 +167,21 @@ def test_rejections(E):
         E.Batch([c])
 
 
-def test_full_size_sampled_against_oracle_windows(E):
+@pytest.mark.parametrize("size", [1024, 4096])
+def test_full_size_sampled_against_oracle_windows(E, size):
     """1024^2 absorbing_square (every face absorbing), the launch
-    configuration the benchmark times:
+    configuration the benchmark times, and 4096^2 (16.8 M nodes):
     Pi_h [u0; u1] with forcing at sampled nodes, each recomputed by the
     oracle on the window of radius N + 2 around it."""
     import torch
-    case = inputs.absorbing_square(1024)
+    case = inputs.absorbing_square(size)
     ctx = E.context_from_case(case)
     info = ctx.info()
     nt = info["nt"]
     N = nt
     rng = np.random.default_rng(77)
-    shape = (2, 1025, 1025)
+    M = size
+    shape = (2, M + 1, M + 1)
     u0 = np.zeros(shape)
     u1 = np.zeros(shape)
     u0[:] = rng.standard_normal(shape)
@@ -190,13 +192,13 @@ def test_full_size_sampled_against_oracle_windows(E):
     o0, o1 = o0.cpu().numpy(), o1.cpu().numpy()
     _say("full size: nt", nt, "tile", ctx.get_tile(E.FP64))
     R = N + 2
-    h = 1.0 / 1024
-    samples = [(512, 512), (300, 0), (700, 1024), (0, 3), (1024, 1021), (5, 600), (1024, 0), (0, 1024)]
+    h = 1.0 / M
+    samples = [(M // 2, M // 2), (300, 0), (700, M), (0, 3), (M, M - 3), (5, 600), (M, 0), (0, M), (M - 1, M // 3)]
     for (i, j) in samples:
-        i0, i1 = max(0, i - R), min(1024, i + R)
-        j0, j1 = max(0, j - R), min(1024, j + R)
+        i0, i1 = max(0, i - R), min(M, i + R)
+        j0, j1 = max(0, j - R), min(M, j + R)
         # real faces of the window are absorbing, artificial ones Dirichlet
-        touch = (i0 == 0, i1 == 1024, j0 == 0, j1 == 1024)
+        touch = (i0 == 0, i1 == M, j0 == 0, j1 == M)
         bc = tuple(FREE if t else DIRICHLET for t in touch)
         faces = [(f // 2, f % 2) for f in range(4) if touch[f]]
         prob = Problem(2, (i1 - i0, j1 - j0), length=((i1 - i0) * h, (j1 - j0) * h), bc=bc)
