@@ -344,3 +344,28 @@ def test_plain_c_client(elwh, tmp_path):
     assert float(f[7]) == pytest.approx((5 * 2 + 13 * 1) * 64 ** 2, rel=1e-14)
     assert float(out[1].split()[1]) > 0
     assert out[2].startswith("bad omega -> 1")
+
+
+def test_plan_property_random_grids(elwh):
+    """Property: for random small 2-D grids, spacings, media and faces
+    (Dirichlet or traction-free y faces, Dirichlet or impedance faces
+    anywhere), the plan's bound is the oracle's Gershgorin bound and N_T
+    follows the time-step rule."""
+    hyp = pytest.importorskip("hypothesis")
+    st = hyp.strategies
+
+    @hyp.settings(max_examples=40, deadline=None, derandomize=True)
+    @hyp.given(nx=st.integers(2, 11), ny=st.integers(2, 11), lx=st.floats(0.3, 2.0), ly=st.floats(0.3, 2.0),
+               xf=st.tuples(st.sampled_from([0, 2]), st.sampled_from([0, 2])),
+               yf=st.tuples(st.sampled_from([0, 1, 2]), st.sampled_from([0, 1, 2])),
+               seed=st.integers(0, 10 ** 6), omega=st.floats(0.5, 30.0))
+    def check(nx, ny, lx, ly, xf, yf, seed, omega):
+        bc = xf + yf
+        prob = Problem(2, (nx, ny), length=(lx, ly), bc=tuple(1 if b == 2 else b for b in bc))
+        rho, lam, mu = _media(prob.node_shape, seed)
+        G = Operator(prob, rho, lam, mu).gershgorin()
+        p = elwh.plan(2, (nx, ny), rho, lam, mu, omega, bc, length=(lx, ly))
+        assert p["lambda_bound"] == pytest.approx(G, rel=1e-12)
+        assert p["nt"] == steps_per_period(G, omega)
+
+    check()
