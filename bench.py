@@ -258,15 +258,18 @@ def cpu_baseline(case, budget_s=12.0):
                       f"workload, {el:.1f} s; operator assembly {t_setup:.1f} s excluded"}
 
 
-def ragged_batch_solve(elwh, inputs):
+def ragged_batch_solve(elwh, inputs, nprob=48, precisions=("fp64", "fp32")):
     """The ragged batch: 48 problems (256^2..1024^2 cells, omega in [10, 80], 1-4
     sources) solved to 1e-8 as one batch (one launch per tick for all
-    problems, CG phase replayed as a hipGraph), FP32 stepping and FP64."""
+    problems, CG phase replayed as a hipGraph), FP32 stepping and FP64; nprob
+    takes the first problems of the same draw."""
     import torch
-    cases = inputs.ragged_batch()
-    out = {"workload": "ragged batch: 48 problems, n ~ U{256..1024}, omega ~ U[10, 80], 1-4 Gaussian sources, "
-                       "random log-normal media, free top", "tol": 1e-8}
+    cases = inputs.ragged_batch()[:nprob]
+    out = {"workload": f"ragged batch: {nprob} problems, n ~ U{{256..1024}}, omega ~ U[10, 80], 1-4 Gaussian "
+                       "sources, random log-normal media, free top", "tol": 1e-8}
     for tag, kw in (("fp64", {}), ("fp32", {"prec": elwh.FP32_STEP})):
+        if tag not in precisions:
+            continue
         log(f"ragged batch {tag}: solving")
         bt = elwh.Batch(cases, **kw)
         fs = [c.f for c in cases]
@@ -375,6 +378,10 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the time-to-1e-8 (warm-start workload) measurement")
     ap.add_argument("--batch", action="store_true",
                     help="also solve the ragged batch (48 problems) in FP32 and FP64 (several minutes)")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only the ragged-batch solve, FP64 (for kernel traces; see --batch-problems)")
+    ap.add_argument("--batch-problems", type=int, default=48,
+                    help="with --batch-only: solve the first N problems of the ragged batch")
     ap.add_argument("--counters", default=None, metavar="V,TY",
                     help="counter-collection pass for rocprofv3 --pmc: a 256 MiB calibration copy, then 3 "
                          "A_h applications of the benchmark workload with the fixed FP64 tiling V,TY")
@@ -413,6 +420,9 @@ def main():
         return
     if args.mapped_only:
         print(json.dumps(mapped_rates(elwh, inputs)))
+        return
+    if args.batch_only:
+        print(json.dumps(ragged_batch_solve(elwh, inputs, nprob=args.batch_problems, precisions=("fp64",))))
         return
     if args.twofield_only:
         print(json.dumps(twofield_rates(elwh, inputs, solve=True)))

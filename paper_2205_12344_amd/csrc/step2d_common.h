@@ -101,15 +101,19 @@ __device__ __forceinline__ void stencil2d(int kind, const Nb<T>& S, const Nb<T>&
 
 // ---- ragged batch: problem lookup and per-tick step kinds -----------------
 
-// Problem of a tile of the concatenated tiling (offsets ascending).
+// Problem of tile b of the concatenated tiling: binary search for the last
+// problem whose first tile is at or before b (offsets ascend; a problem with
+// no tiles shares its successor's offset).
 __device__ __forceinline__ int batch_problem_of(const BProb2D* __restrict__ pr, int np, int b, bool two) {
-    int p = 0;
-    if (two) {
-        while (p + 1 < np && b >= pr[p + 1].off2) ++p;
-    } else {
-        while (p + 1 < np && b >= pr[p + 1].off) ++p;
+    int lo = 0, hi = np - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if ((two ? pr[mid].off2 : pr[mid].off) <= b)
+            lo = mid;
+        else
+            hi = mid - 1;
     }
-    return p;
+    return lo;
 }
 
 // Step count of problem p at this tick (neff: steps done in its application)
