@@ -358,7 +358,9 @@ elwh_status elwh_profile_read(elwh_ctx* ctx, double* step_ms, int* nstep, double
  * 3-D: 1) and rows (2-D: 4, 8, 16 rows; 3-D: 4, 8, 16, 32 planes) marched
  * per wavefront.  The tiling changes speed only, never results.
  * elwh_autotune times every supported tiling on reps operator applications
- * (HIP events) and keeps the fastest; results are cached per process by
+ * (HIP events), in three round-robin passes, and keeps the tiling with the
+ * fastest pass (contexts with impedance faces time the two-field step);
+ * results are cached per process by
  * (dim, precision, accumulator, grid size) and, when the environment
  * variable ELWH_TUNE_CACHE names a file, in that file as JSON lines keyed by
  * (arch, dim, precision, accumulator, grid size).  Synchronous.
