@@ -158,7 +158,7 @@ elwh_status elwh_create(const elwh_grid* grid, const double* rho, const double* 
 
 /*
  * Mapped (curvilinear) 2-D grids (Sec. 4.1; the annular sectors of the
- * iterations-vs-frequency experiment, Sec. 5.4).  The domain is the image of
+ * iterations-vs-frequency experiment, Sec. 5.5).  The domain is the image of
  * the unit square under a smooth one-to-one map (q, r) -> (x, y); x and y
  * hold the physical coordinates of the (n[0]+1) x (n[1]+1) nodes of the
  * uniform (q, r) grid, in the node layout with q along the fast axis

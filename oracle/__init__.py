@@ -12,12 +12,14 @@ Modules
             elastic energy (Sec. 4.1, eq. (symmetric FD); reading of Sec. 4.1
             for the Cartesian specialisation and the free-surface closure)
   stepping  time-step rule, corrected leapfrog, filter weights, the filter
-            Pi_h, the affine split A_h = I - S_h, b = Pi_h 0 (Sec. 3, 4.3, 4.5)
-  krylov    CG / conjugate residual / GMRES in the M inner product (Sec. 4.5)
+            Pi_h, the affine split A_h = I - S_h, b = Pi_h 0 (Sec. 3, 4.3, 4.5);
+            the modified trapezoid weights of the remark closing Sec. 4.4
+  krylov    CG / conjugate residual / MINRES / GMRES in the M inner product
+            (Sec. 4.5; MINRES: the remark in Sec. 4.4)
   direct    direct solve of the discrete Helmholtz system (Sec. 4.3)
   spectral  continuous and trapezoid filter transfer functions (Sec. 3, App. B)
   curvilinear  the stress divergence on a mapped 2-D grid (Sec. 4.1; the
-            annular sectors of Sec. 5.4), same interface as operator
+            annular sectors of Sec. 5.5), same interface as operator
   twofield  the two-field (displacement, velocity) filter for impedance faces
             (the remark of Sec. 3), damped corrected leapfrog, GMRES
 

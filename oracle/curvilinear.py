@@ -32,9 +32,9 @@ Reading taken here (the Cartesian reading of operator.py carried over):
   Operator convention of operator.py (rho u'' = Ltilde u - f cos) this is
   Ltilde = W^-1 L_h with node weight W = J w_p and M = W rho.
 * Boundary: homogeneous Dirichlet on the q sides; Dirichlet (default; the
-  annular-sector experiments of Sec. 5.4 state no boundary condition and
+  annular-sector experiments of Sec. 5.5 state no boundary condition and
   the rectangle beside them is Dirichlet) or traction-free on each r side
-  (the free curved surfaces of the toroidal shell of Sec. 5.9, in 2-D).  A
+  (the free curved surfaces of the toroidal shell of Sec. 5.11, in 2-D).  A
   free side is closed from the same energy as on Cartesian grids (reading of
   operator.py): trapezoid weight w_p = 1/2 for its nodes and for the q-edges
   lying in it, and the one-sided r difference into the domain in place of
@@ -46,7 +46,7 @@ the agreement of the energy Hessian with the stencil form, second-order
 convergence of the truncation error and of the Helmholtz solution against a
 continuous manufactured solution on the quarter annulus, and the paper's
 observation that the iteration count on the annular sectors matches the
-rectangle's (Sec. 5.4).  The paper's own closure differs and prints no
+rectangle's (Sec. 5.5).  The paper's own closure differs and prints no
 numbers for these grids, so absolute values are otherwise "parity unpinned".
 """
 

@@ -12,9 +12,10 @@ identity (constant rho, all-Dirichlet).  The stopping test is
 ||r||_M <= tol ||b||_M; the paper measures residuals relative to the
 zero-guess residual, which is b.
 
-Conjugate residual (the Remark at the end of Sec. 4.5) and restarted GMRES
-(used for non-symmetric problems in Sec. 5.3) are provided in the same inner
-product.
+Conjugate residual (the Remark at the end of Sec. 4.5), MINRES (the remedy
+the remark in Sec. 4.4 recommends when A_h is slightly indefinite near
+resonance) and restarted GMRES (used for non-symmetric problems in Sec. 5.4)
+are provided in the same inner product.
 """
 
 import math
@@ -155,3 +156,64 @@ def gmres(apply_A, b, m, x0=None, tol=1e-10, maxit=1000, restart=30):
             V.append(w / hn)
         y = np.linalg.solve(np.triu(H[:j_done, :j_done]), g[:j_done])
         x = x + np.array(V[:j_done]).T @ y
+
+
+def minres(apply_A, b, m, x0=None, tol=1e-10, maxit=1000):
+    """MINRES on an M-self-adjoint A in the M inner product (the remark in
+    Sec. 4.4 recommends it when A_h is indefinite near resonance).
+
+    Written from its definition (Paige and Saunders, 1975): x_k minimises
+    ||b - A x||_M over x0 + K_k(A, r0).  The Lanczos process in the M inner
+    product gives A V_k = V_{k+1} Tbar_k with M-orthonormal V and the
+    (k+1) x k tridiagonal Tbar_k (diagonal alpha_j, off-diagonals beta_{j+1}),
+    so ||r_k||_M = min_y ||beta_1 e_1 - Tbar_k y||_2.  That small least-squares
+    problem is solved by a QR factorisation of Tbar_k built one Givens rotation
+    per column; x_k = x_0 + V_k R_k^{-1} t_k is updated through the direction
+    vectors D_k = V_k R_k^{-1}, and |last entry of the rotated right-hand side|
+    is ||r_k||_M.
+    """
+    x = np.zeros_like(b) if x0 is None else np.asarray(x0, np.float64).copy()
+    r = b - apply_A(x) if x0 is not None else b.copy()
+    bn = math.sqrt(_mdot(m, b, b))
+    beta = math.sqrt(_mdot(m, r, r))          # beta_1
+    hist = [beta / bn]
+    if hist[-1] <= tol:
+        return KrylovResult(x, 0, True, hist)
+    v_prev = np.zeros_like(b)
+    v = r / beta
+    d_prev2 = np.zeros_like(b)                # d_{j-2}
+    d_prev = np.zeros_like(b)                 # d_{j-1}
+    c2, s2 = 1.0, 0.0                         # rotation G_{j-2}
+    c1, s1 = 1.0, 0.0                         # rotation G_{j-1}
+    g = beta                                  # j-th entry of the rotated rhs, before G_j
+    for k in range(1, maxit + 1):
+        # Lanczos: beta_{j+1} v_{j+1} = A v_j - alpha_j v_j - beta_j v_{j-1}
+        q = apply_A(v)
+        alpha = _mdot(m, v, q)
+        q = q - alpha * v - beta * v_prev
+        beta_next = math.sqrt(_mdot(m, q, q))
+        # column j of Tbar: (beta_j, alpha_j, beta_{j+1}) in rows j-1, j, j+1;
+        # apply G_{j-2} (rows j-2, j-1) then G_{j-1} (rows j-1, j)
+        b_j = beta if k > 1 else 0.0          # Tbar has no entry above its first diagonal
+        eps = s2 * b_j
+        t = c2 * b_j
+        delta = c1 * t + s1 * alpha
+        gbar = -s1 * t + c1 * alpha
+        # new rotation G_j zeroes beta_{j+1}
+        gamma = math.hypot(gbar, beta_next)
+        if gamma == 0.0:
+            raise ArithmeticError("MINRES breakdown: singular tridiagonal")
+        c, s = gbar / gamma, beta_next / gamma
+        tau = c * g
+        g = -s * g
+        # d_j = (v_j - delta d_{j-1} - eps d_{j-2}) / gamma;  x_j = x_{j-1} + tau d_j
+        d = (v - delta * d_prev - eps * d_prev2) / gamma
+        x += tau * d
+        hist.append(abs(g) / bn)
+        if hist[-1] <= tol or beta_next == 0.0:
+            return KrylovResult(x, k, True, hist)
+        d_prev2, d_prev = d_prev, d
+        c2, s2, c1, s1 = c1, s1, c, s
+        v_prev, v = v, q / beta_next
+        beta = beta_next
+    return KrylovResult(x, maxit, False, hist)

@@ -1,7 +1,7 @@
 """Grid, boundary faces and trapezoid weights (oracle; test infrastructure only).
 
 The paper discretises the mapped unit square/cube on a uniform grid
-q_i = i h_q, i = 0..n_q (Sec. 4.1 and the grid description of Sec. 5.4).
+q_i = i h_q, i = 0..n_q (Sec. 4.1 and the grid description of Sec. 5.5).
 Here the mapping is the identity scaled by the box lengths, so the grid is
 Cartesian with h_a = len_a / n_a and n_a + 1 nodes per axis a.
 

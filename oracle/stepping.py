@@ -24,6 +24,18 @@ Test infrastructure only.  Passages followed:
   rho^-1 Ltilde;  N_T = max(3, ceil(T / dt*)),  dt = T / N_T exactly (a whole
   number of steps per period is what makes the trapezoid rule reproduce the
   fixed point exactly; N_T >= 3 makes sum cos^2 = N_T / 2).
+* Modified trapezoid weights (the remark closing Sec. 4.4, after Peng et al.):
+  the standard scheme keeps its time error out of the fixed point when the
+  weights are multiplied by cos(w t_n) / cos(wbar t_n).  The printed formula
+  names the ratio but not the frequency the discrete solution oscillates at.
+  Reading: the standard leapfrog is forced at wbar = (2 / dt) asin(w dt / 2),
+  the frequency whose discrete dispersion relation gives w, so its
+  time-harmonic solution is v cos(wbar t_n) with (w^2 M + L_h) v = W f exactly
+  (2 sin(wbar dt / 2) / dt = w), and the weights
+      w_n = (2 / (K N_T)) eta_n (cos(w t_n) - 1/4) cos(w t_n) / cos(wbar t_n)
+  give sum_n w_n cos(wbar t_n) = sum_n (2/(K N_T)) eta_n (cos - 1/4) cos = 1,
+  so Pi_h v = v.  Needs w dt / 2 < 1, i.e. N_T >= 4; the denominator can come
+  close to zero, the risk the remark names.
 * Affine split (Sec. 4.5, eq. (amat_non_sym)):  A_h = I - S_h with S_h = Pi_h
   at f = 0, and b = Pi_h 0.
 * Discrete energy (Sec. 4.1, eq. (8), in the corrected form):
@@ -39,6 +51,7 @@ from .operator import Operator
 
 CORRECTED = "corrected"
 STANDARD = "standard"
+MODIFIED = "modified"          # standard stepping, modified trapezoid weights
 
 
 def steps_per_period(gershgorin_bound, omega, cfl=0.8):
@@ -52,6 +65,26 @@ def correction_factor(omega, dt):
     """c = (wt / w)^2 = (sin(w dt / 2) / (w dt / 2))^2  (Sec. 4.3)."""
     x = 0.5 * omega * dt
     return (math.sin(x) / x) ** 2
+
+
+def modified_forcing_frequency(omega, dt):
+    """wbar = (2 / dt) asin(w dt / 2): the standard leapfrog forced at wbar has
+    the time-harmonic solution of the Helmholtz problem at w."""
+    x = 0.5 * omega * dt
+    if not x < 1.0:
+        raise ValueError("modified weights need omega dt / 2 < 1 (N_T >= 4)")
+    return 2.0 * math.asin(x) / dt
+
+
+def modified_filter_weights(nt, omega, periods=1):
+    """Weights and forcing factors of the modified trapezoid rule (reading in
+    the module docstring): w_n cos(w t_n) / cos(wbar t_n) and cos(wbar t_n)."""
+    w, cosn = filter_weights(nt, periods)
+    dt = 2.0 * math.pi / (omega * nt)
+    wbar = modified_forcing_frequency(omega, dt)
+    t = dt * np.arange(periods * nt + 1)
+    cbar = np.cos(wbar * t)
+    return w * cosn / cbar, cbar
 
 
 def filter_weights(nt, periods=1):
@@ -80,7 +113,10 @@ class WaveHoltz:
         self.dt = self.T / self.nt
         self.scheme = scheme
         self.c = correction_factor(self.omega, self.dt) if scheme == CORRECTED else 1.0
-        self.weights, self.cosn = filter_weights(self.nt, self.periods)
+        if scheme == MODIFIED:
+            self.weights, self.cosn = modified_filter_weights(self.nt, self.omega, self.periods)
+        else:
+            self.weights, self.cosn = filter_weights(self.nt, self.periods)
         self.a = self.c * self.dt ** 2 / op.rho_dof          # per dof
 
     # ---- the time-stepping filter -----------------------------------------

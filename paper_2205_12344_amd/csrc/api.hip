@@ -7,7 +7,7 @@
 // residual per iteration off the critical path.  Conjugate residual (Remark
 // of Sec. 4.5; also the fallback after a CG breakdown) and restarted GMRES
 // with classical Gram-Schmidt applied twice (used for non-symmetric problems
-// in Sec. 5.3) are host-driven over the same FP64 reductions.  The FP32 path
+// in Sec. 5.4) are host-driven over the same FP64 reductions.  The FP32 path
 // runs CG with FP32-stepped applications and FP64 vectors and replaces the
 // residual by b - A_h x from an FP64 application whenever it has fallen by
 // inner_tol, keeping the search direction (reliable updates); it stops on

@@ -267,7 +267,7 @@ def random_field(shape, seed):
 
 def sector_grid(nq, nr, n_an, arc=5.0):
     """Node coordinates (x, y), each of shape (nr + 1, nq + 1), of the annular
-    sectors of the iterations-vs-frequency experiment (Sec. 5.4): q in [0, 1]
+    sectors of the iterations-vs-frequency experiment (Sec. 5.5): q in [0, 1]
     runs radially from r_in to r_out = r_in + 1, r in [0, 1] along the arc,
     the outer arc has length `arc`; n_an = 1 is the quarter annulus
     (r_out = 2 arc / pi), n_an = 2 the half annulus (r_out = arc / pi)."""
@@ -321,7 +321,7 @@ def media_mapped(x, y, seed):
 
 
 def sector_case(k, n_an=1, seed=None, arc=5.0):
-    """The iterations-vs-frequency setup of Sec. 5.4 on an annular sector:
+    """The iterations-vs-frequency setup of Sec. 5.5 on an annular sector:
     omega = k + sqrt(2)/10, n_q = int(4 omega + 1) radial and
     n_r = int(4 arc omega + 1) arc-wise cells (about 20 points per shear
     wavelength), a discrete point source in u of amplitude omega^2 (divided
@@ -348,7 +348,7 @@ def ring_grid(nq, nr, r_in=1.0, r_out=2.0, angle=math.pi):
     """Node coordinates of a ring sector with q along the arc and r radial
     (r = 0 the inner arc of radius r_in, r = 1 the outer arc of radius
     r_out; the angle decreases with q so the map is right-handed): the
-    cross-section of the partial toroidal shell of Sec. 5.9 (1 <= r <= 2,
+    cross-section of the partial toroidal shell of Sec. 5.11 (1 <= r <= 2,
     0 <= theta <= pi), whose curved surfaces are traction-free."""
     Q, R = np.meshgrid(np.arange(nq + 1) / nq, np.arange(nr + 1) / nr)
     rad = r_in + (r_out - r_in) * R

@@ -1,6 +1,6 @@
 """GPU parity on mapped (curvilinear) 2-D grids: the HIP path through the C ABI
 (elwh_create_mapped) against the CPU FP64 oracle (oracle/curvilinear.py) on
-the same seeded inputs -- quarter and half annular sectors (Sec. 5.4) and a
+the same seeded inputs -- quarter and half annular sectors (Sec. 5.5) and a
 strongly non-orthogonal warped square.
 
 Bars as in test_gpu_parity.py: FP64 rel-L2 <= 1e-12 per application, FP32
@@ -174,7 +174,7 @@ def test_mapped_cr_point_source_matches_oracle(E, geometry):
 
 
 def test_mapped_full_size_fixed_point(E):
-    """The benchmark's mapped workload (quarter annulus of Sec. 5.4 at
+    """The benchmark's mapped workload (quarter annulus of Sec. 5.5 at
     omega = 200 + sqrt(2)/10: 801 x 4003 cells, random media) in the launch
     configuration it times: with the forcing of a discrete manufactured v*
     (f = omega^2 rho v* + J^-1 L_h v*, from the oracle's stencil form) the
@@ -277,7 +277,7 @@ def test_mapped_free_sides_fp32(E):
 
 
 def test_ring_sector_with_free_arcs_cr_matches_oracle(E):
-    """A 2-D analogue of the toroidal shell of Sec. 5.9: the ring sector
+    """A 2-D analogue of the toroidal shell of Sec. 5.11: the ring sector
     1 <= radius <= 2, 0 <= angle <= pi with traction-free inner and outer arcs
     and Dirichlet cuts, the paper's forcing form (sqrt(sigma^3)/20) (1, 1)
     exp(-zeta^2), sigma = 100 omega, at omega = 5.1234, conjugate residual to

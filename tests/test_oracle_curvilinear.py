@@ -1,5 +1,5 @@
 """Pins of the mapped-grid oracle (curvilinear finite differences, Sec. 4.1;
-the annular sectors of Sec. 5.4).
+the annular sectors of Sec. 5.5).
 
 Each pin ties oracle/curvilinear.py to something other than itself:
 * the Cartesian operator (independently pinned) for a scaled identity map;
@@ -12,7 +12,7 @@ Each pin ties oracle/curvilinear.py to something other than itself:
   stress divergence comes from exact jets (themselves checked against
   finite differences);
 * the paper's observation that iteration counts on the quarter and half
-  annulus are very close to the rectangle's (Sec. 5.4).
+  annulus are very close to the rectangle's (Sec. 5.5).
 """
 
 import math
@@ -203,7 +203,7 @@ def test_filter_fixed_point_on_a_mapped_grid():
     assert rel(direct.solve(op, omega, f), vs) <= 1e-10
 
 
-# ---- Sec. 5.4: the geometry hardly changes the iteration count ---------------------
+# ---- Sec. 5.5: the geometry hardly changes the iteration count ---------------------
 
 def sector_cr_iterations(k, geometry):
     """CR iterations to 1e-8 (standard scheme, lambda = 2, mu = rho = 1,
@@ -244,7 +244,7 @@ def test_sector_iterations_match_the_rectangle():
         assert np.all(ratio > 0.6) and np.all(ratio < 1.4), (its, ratio)
 
 
-# ---- traction-free r sides (the free curved surfaces of Sec. 5.9, in 2-D) ----------
+# ---- traction-free r sides (the free curved surfaces of Sec. 5.11, in 2-D) ----------
 
 @pytest.mark.parametrize("bc", [(0, 0, 1, 1), (0, 0, 0, 1), (0, 0, 1, 0)])
 def test_free_sides_of_a_scaled_identity_map_are_the_cartesian_closure(bc):

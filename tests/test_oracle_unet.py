@@ -53,3 +53,78 @@ def test_im2col_col2im_adjoint():
     X = rng.standard_normal((2, 8, 6, 3))
     C = rng.standard_normal((2 * 8 * 6, 27))
     assert np.sum(unet.im2col(X) * C) == pytest.approx(np.sum(X * unet.col2im(C, X.shape)), rel=1e-12)
+
+
+def _ref_conv(X, W, b, act):
+    """A 3x3 zero-padded convolution layer written independently of the
+    oracle's im2col: per (input, output) channel pair a 2-D correlation
+    (scipy.signal.correlate2d, mode 'same') with the kernel
+    K[ky, kx] = W[(ky * 3 + kx) * cin + ci, co]."""
+    from scipy.signal import correlate2d
+    B, H, Wd, C = X.shape
+    co_n = W.shape[1]
+    out = np.zeros((B, H, Wd, co_n))
+    K = W.reshape(3, 3, C, co_n)
+    for bi in range(B):
+        for co in range(co_n):
+            acc = np.full((H, Wd), b[co])
+            for ci in range(C):
+                acc += correlate2d(X[bi, :, :, ci], K[:, :, ci, co], mode="same", boundary="fill")
+            out[bi, :, :, co] = acc
+    return out * (1.0 / (1.0 + np.exp(-out))) if act else out
+
+
+def _ref_forward(theta, x):
+    """The network's definition restated with the reference convolution,
+    block means for pooling and Kronecker products for upsampling."""
+    P = unet.unpack(theta)
+    B = x.shape[0]
+
+    def pool(h):
+        b_, H, W, C = h.shape
+        return h.reshape(b_, H // 2, 2, W // 2, 2, C).mean(axis=(2, 4))
+
+    def up(h):
+        return np.kron(h, np.ones((1, 2, 2, 1)))
+
+    h, skips = x, []
+    for lev in range(5):
+        for l in (2 * lev, 2 * lev + 1):
+            h = _ref_conv(h, *P[l], unet.LAYERS[l][2])
+        skips.append(h)
+        if lev < 4:
+            h = pool(h)
+    for lev in (3, 2, 1, 0):
+        la = 10 + 2 * (3 - lev)
+        h = np.concatenate([up(h), skips[lev]], axis=3)
+        for l in (la, la + 1):
+            h = _ref_conv(h, *P[l], unet.LAYERS[l][2])
+    assert h.shape[0] == B
+    return _ref_conv(h, *P[18], unet.LAYERS[18][2])
+
+
+def test_conv_layer_matches_direct_correlation():
+    rng = np.random.default_rng(4)
+    X = rng.standard_normal((2, 8, 6, 5))
+    W = rng.standard_normal((9 * 5, 3))
+    b = rng.standard_normal(3)
+    for act in (0, 1):
+        _, got = unet._conv(X, W, b, act)
+        np.testing.assert_allclose(got, _ref_conv(X, W, b, act), rtol=1e-12, atol=1e-12)
+
+
+def test_forward_matches_independent_restatement():
+    theta, x, _, _ = _setup(seed=3, B=1, H=16)
+    got, _ = unet.forward(theta, x)
+    np.testing.assert_allclose(got, _ref_forward(theta, x), rtol=1e-10, atol=1e-10)
+
+
+def test_conv_pin_catches_a_flipped_kernel():
+    """A convolution (flipped kernel) instead of a correlation fails the pin."""
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((1, 6, 6, 2))
+    W = rng.standard_normal((18, 2))
+    b = np.zeros(2)
+    Wf = W.reshape(3, 3, 2, 2)[::-1, ::-1].reshape(18, 2)
+    _, got = unet._conv(X, Wf, b, 0)
+    assert np.abs(got - _ref_conv(X, W, b, 0)).max() > 1e-3
