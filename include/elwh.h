@@ -63,8 +63,16 @@ typedef enum {
  * ones return ELWH_ERR_ARG on such a context). */
 enum { ELWH_BC_DIRICHLET = 0, ELWH_BC_TRACTION_FREE = 1, ELWH_BC_IMPEDANCE = 2 };
 enum { ELWH_FP64 = 0, ELWH_FP32_STEP = 1 };
-enum { ELWH_KRYLOV_CG = 0, ELWH_KRYLOV_GMRES = 1, ELWH_KRYLOV_CR = 2 };
-enum { ELWH_SCHEME_CORRECTED = 0, ELWH_SCHEME_STANDARD = 1 };
+enum { ELWH_KRYLOV_CG = 0, ELWH_KRYLOV_GMRES = 1, ELWH_KRYLOV_CR = 2, ELWH_KRYLOV_MINRES = 3 };
+/* ELWH_SCHEME_MODIFIED: the standard (uncorrected) leapfrog with the modified
+ * trapezoid weights of the remark closing Sec. 4.4.  The stepping is forced at
+ * wbar = (2 / dt) asin(omega dt / 2), whose discrete time-harmonic solution
+ * solves the Helmholtz system at omega exactly, and the filter weights are
+ * w_n cos(omega t_n) / cos(wbar t_n), so the fixed point carries no time
+ * error either.  Needs N_T >= 4 (else ELWH_ERR_ARG); a weight grows large when
+ * a time level falls close to a zero of cos(wbar t), the risk the remark
+ * names.  One-field contexts only. */
+enum { ELWH_SCHEME_CORRECTED = 0, ELWH_SCHEME_STANDARD = 1, ELWH_SCHEME_MODIFIED = 2 };
 
 /* dim = 2 or 3; n[a] = cells along axis a (nodes n[a]+1, n[a] >= 2);
  * len[a] = box length, h[a] = len[a]/n[a].  Unused entries are ignored. */
@@ -82,10 +90,12 @@ typedef struct {
     int prec;          /* ELWH_FP64, or ELWH_FP32_STEP: FP32 state and stencil,
                           FP64 accumulator, FP64 Krylov vectors and inner
                           products, FP64 residual replacements */
-    int krylov;        /* ELWH_KRYLOV_CG (default), _GMRES, _CR; with
-                          ELWH_FP32_STEP only CG (else ELWH_ERR_ARG) */
+    int krylov;        /* ELWH_KRYLOV_CG (default), _GMRES, _CR, _MINRES (the
+                          remedy the remark in Sec. 4.4 recommends for an
+                          indefinite A_h); with ELWH_FP32_STEP only CG (else
+                          ELWH_ERR_ARG) */
     int gmres_m;       /* GMRES restart length (default 30) */
-    int scheme;        /* ELWH_SCHEME_CORRECTED (default, Sec. 4.3) or _STANDARD */
+    int scheme;        /* ELWH_SCHEME_CORRECTED (default, Sec. 4.3), _STANDARD or _MODIFIED */
     int compensated;   /* FP32 path: Neumaier-compensated FP64 accumulator (default 1) */
     double inner_tol;  /* FP32 path: reduction of the recursive residual between two
                           FP64 residual replacements (default 1e-2) */
@@ -100,12 +110,15 @@ typedef struct {
                           (x0, A_h x0)_M <= 0), so the start is never worse than
                           x0 = 0 in that norm; costs no extra application
                           (default 0) */
-    int cr_fallback;   /* CG paths: 1 (default) = when CG breaks down ((p, A_h p)_M
-                          <= 0: A_h slightly indefinite near resonance, the
-                          remark of Sec. 4.4), continue from the current iterate
-                          with the conjugate residual method in FP64 (the
-                          MINRES-type remedy the remark recommends); 0 = return
-                          ELWH_ERR_BREAKDOWN */
+    int cr_fallback;   /* CG paths: when CG breaks down ((p, A_h p)_M <= 0: A_h
+                          slightly indefinite near resonance, the remark of
+                          Sec. 4.4), continue from the current iterate in FP64
+                          with 1 (default) = the conjugate residual method, which
+                          minimises the same residual norm as MINRES but can
+                          itself break down when (r, A_h r)_M = 0 (reported as
+                          ELWH_ERR_BREAKDOWN), or 2 = MINRES, the method the
+                          remark recommends, which does not break down on a
+                          nonsingular A_h; 0 = return ELWH_ERR_BREAKDOWN */
     int fp64_fallback; /* FP32 path: 1 (default) = when the FP64-recomputed
                           residual has not halved over the last two segments
                           (FP32 applications no longer improve x), finish with
@@ -115,7 +128,8 @@ typedef struct {
 
 typedef struct {
     int iters;          /* Krylov iterations */
-    int outer;          /* FP64 residual replacements (FP32 path), else 0 */
+    int outer;          /* FP64 residual replacements: FP32 path, and FP64 CG when the
+                           true residual lagged the recurrence at tol; else 0 */
     int nt;             /* steps per period N_T */
     int napply;         /* operator applications (each periods*N_T steps) */
     double dt;          /* time step T / N_T */
@@ -124,7 +138,7 @@ typedef struct {
     double relres;      /* last Krylov residual ||r||_M / ||b||_M (recurrence) */
     double relres_fp64; /* final ||b - A_h v||_M / ||b||_M recomputed with an FP64 apply */
     double cond_est;    /* Lanczos condition estimate from the CG coefficients (CG only) */
-    int cr_iters;       /* conjugate-residual iterations after a CG breakdown (cr_fallback), else 0 */
+    int cr_iters;       /* CR or MINRES iterations after a CG breakdown (cr_fallback), else 0 */
     int fp64_iters;     /* FP32 path: FP64 CG iterations after a stagnation (fp64_fallback), else 0;
                            included in iters */
 } elwh_info;
@@ -305,9 +319,15 @@ elwh_status elwh_apply_A(elwh_ctx* ctx, const double* x, double* y);
 /*
  * Solve A_h v = b, b = Pi_h 0 with forcing f (Sec. 4.5), by the Krylov
  * method in opts (CG in the M inner product by default), from x0 (NULL =
- * zero guess) until ||r||_M <= tol ||b||_M or maxit iterations.  tol <= 0
- * runs exactly maxit iterations and returns ELWH_OK.  The final residual is
- * recomputed with an FP64 apply (info->relres_fp64).  FP32 path: CG with
+ * zero guess) until the true residual ||b - A_h v||_M, recomputed with an
+ * FP64 application (info->relres_fp64), is <= tol ||b||_M, or maxit
+ * iterations.  Every method iterates until its own recurrence residual
+ * (info->relres) meets tol and then checks the true one; when that is still
+ * above tol the residual is replaced by the true one and the iteration goes
+ * on (CG keeps its search direction; CR and MINRES restart from the
+ * iterate; GMRES restarts anyway).  tol <= 0 runs exactly maxit iterations
+ * and returns ELWH_OK.  When ||b||_M = 0 the solution is v = 0: it is
+ * returned with ELWH_OK and no iteration, whatever x0.  FP32 path: CG with
  * FP32-stepped applications and FP64 vectors; whenever the recursive
  * residual has fallen by inner_tol, it is replaced by b - A_h x from an FP64
  * application and CG continues along the same search direction (a reliable
@@ -322,7 +342,8 @@ elwh_status elwh_solve(elwh_ctx* ctx, const double* f, const double* x0, double 
 /*
  * Stepwise CG in the M inner product (the loop of elwh_solve, exposed for
  * timing and for resume-by-restart):
- *   elwh_cg_begin    b = Pi_h 0 with f; r = b - A_h x0; p = r
+ *   elwh_cg_begin    b = Pi_h 0 with f; r = b - A_h x0; p = r (when
+ *                    ||b||_M = 0: x = 0, and elwh_cg_iterate returns at once)
  *   elwh_cg_iterate  k iterations (one A_h apply each, FP64 reductions,
  *                    fused vector updates); writes the current ||r||_M/||b||_M;
  *                    stops early (returns ELWH_OK) once it is <= tol
@@ -341,6 +362,16 @@ elwh_status elwh_cg_result(elwh_ctx* ctx, double* v, elwh_info* info);
 elwh_status elwh_dot_M(elwh_ctx* ctx, const double* x, const double* y, double* out);
 
 /*
+ * Measurement aid (not part of the method): the STREAM triad a = b + s c
+ * over n doubles (n a multiple of 4, arrays 32-byte aligned, DEVICE
+ * pointers), one 32-byte vector per thread, asynchronous on stream.  Timed
+ * over arrays far larger than the 256 MiB Infinity Cache it gives the HBM
+ * bandwidth a plain streaming kernel reaches (24 bytes per element).
+ * Errors: ELWH_ERR_ARG, ELWH_ERR_HIP.
+ */
+elwh_status elwh_stream_triad(double* a, const double* b, const double* c, double s, long long n, void* stream);
+
+/*
  * Kernel timing for measurement.  While enabled, every fused-step launch of
  * the filter (Sec. 4.3 step + trapezoid accumulation; the half-step launch
  * is counted separately) is bracketed by a pair of HIP events on the
@@ -354,9 +385,10 @@ elwh_status elwh_profile_read(elwh_ctx* ctx, double* step_ms, int* nstep, double
 
 /*
  * Tiling of the fused step kernel for precision prec (ELWH_FP64 or
- * ELWH_FP32_STEP): vec nodes per lane along x (2-D: 1 or 2, FP32 also 4;
- * 3-D: 1) and rows (2-D: 4, 8, 16 rows; 3-D: 4, 8, 16, 32 planes) marched
- * per wavefront.  The tiling changes speed only, never results.
+ * ELWH_FP32_STEP): 2-D: vec nodes per lane along x (1 or 2, FP32 also 4)
+ * and rows (4, 8, 16) marched per wavefront; 3-D: vec = y rows per
+ * workgroup, one wavefront each (1, 2, 4, 8), and rows = z planes marched
+ * per wavefront (4, 8, 16, 32).  The tiling changes speed only, never results.
  * elwh_autotune times every supported tiling on reps operator applications
  * (HIP events), in three round-robin passes, and keeps the tiling with the
  * fastest pass (contexts with impedance faces time the two-field step);

@@ -383,12 +383,136 @@ elwh_status solve_cr(elwh_ctx* c, bool x_zero, double tol, int maxit, int* iters
         apply_A(c, r, Ar, false);
         double rAr_new;
         CKST(dot_host(c, r, Ar, &rAr_new));
+        if (rAr_new == 0.0) {
+            // r is M-orthogonal to A_h r: the next step would not move x
+            c->err = "CR breakdown: (r, A_h r)_M = 0 (A_h indefinite; MINRES does not break down here)";
+            return ELWH_ERR_BREAKDOWN;
+        }
         const double beta = rAr_new / rAr;
         launch_axpby(c, 1.0, r, beta, p, c->stream);
         launch_axpby(c, 1.0, Ar, beta, Ap, c->stream);
         rAr = rAr_new;
     }
     return tol > 0 ? ELWH_ERR_NOT_CONVERGED : ELWH_OK;
+}
+
+// MINRES in the M inner product (the remedy the remark in Sec. 4.4 recommends
+// when A_h is slightly indefinite near resonance): x_k minimises ||b - A_h x||_M
+// over x_0 + K_k(A_h, r_0).  The Lanczos process in the M inner product
+// (A_h is M-self-adjoint) builds A_h V_k = V_{k+1} Tbar_k; the small
+// least-squares problem min ||beta_1 e_1 - Tbar_k y|| is solved by one Givens
+// rotation per column (Paige and Saunders), and x is updated through the
+// direction vectors D_k = V_k R_k^{-1}.  Host-driven: one application and two
+// FP64 M-dots per iteration.  Iterate in VX, right-hand side in VB; uses VR,
+// VP, VQ, VD, VRI as work vectors.
+elwh_status solve_minres(elwh_ctx* c, bool x_zero, double tol, int maxit, int* iters, double* relres) {
+    double* x = c->vec[VX];
+    const double* b = c->vec[VB];
+    double* vprev = c->vec[VR];   // v_{j-1}
+    double* v = c->vec[VP];       // v_j
+    double* q = c->vec[VQ];       // A_h v_j, then beta_{j+1} v_{j+1}
+    double* d1 = c->vec[VD];      // d_{j-1}
+    double* d2 = c->vec[VRI];     // d_{j-2}, overwritten by d_j
+    if (x_zero) {
+        launch_copy(c, b, v, c->stream);
+    } else {
+        apply_A(c, x, q, false);
+        launch_copy(c, b, v, c->stream);
+        launch_axpby(c, -1.0, q, 1.0, v, c->stream);
+    }
+    double bb, rr;
+    CKST(dot_host(c, b, b, &bb));
+    CKST(dot_host(c, v, v, &rr));
+    if (!std::isfinite(rr)) {
+        c->err = "non-finite residual: the time step is unstable";
+        return ELWH_ERR_UNSTABLE;
+    }
+    const double bn = std::sqrt(bb);
+    double beta = std::sqrt(rr);   // beta_1 = ||r_0||_M
+    *relres = beta / bn;
+    *iters = 0;
+    if ((tol > 0 && *relres <= tol) || beta == 0.0) return ELWH_OK;
+    launch_axpby(c, 0.0, v, 1.0 / beta, v, c->stream);
+    const size_t bytes = c->L.field_elems() * sizeof(double);
+    HIPCK(hipMemsetAsync(vprev, 0, bytes, c->stream));
+    HIPCK(hipMemsetAsync(d1, 0, bytes, c->stream));
+    HIPCK(hipMemsetAsync(d2, 0, bytes, c->stream));
+    double c2 = 1.0, s2 = 0.0, c1 = 1.0, s1 = 0.0;   // rotations G_{j-2}, G_{j-1}
+    double g = beta;                                  // rotated right-hand side entry j
+    for (int k = 1; k <= maxit; ++k) {
+        apply_A(c, v, q, false);
+        double alpha;
+        CKST(dot_host(c, v, q, &alpha));
+        launch_axpby(c, -alpha, v, 1.0, q, c->stream);
+        if (k > 1) launch_axpby(c, -beta, vprev, 1.0, q, c->stream);
+        double qq;
+        CKST(dot_host(c, q, q, &qq));
+        if (!std::isfinite(alpha) || !std::isfinite(qq)) {
+            c->err = "non-finite Lanczos coefficient: the time step is unstable";
+            return ELWH_ERR_UNSTABLE;
+        }
+        const double beta_next = std::sqrt(qq);
+        // column k of Tbar is (beta_k, alpha_k, beta_{k+1}) in rows k-1, k, k+1
+        // (no entry above the first diagonal); apply G_{k-2}, G_{k-1}, then
+        // form G_k, which zeroes beta_{k+1}
+        const double bk = k > 1 ? beta : 0.0;
+        const double eps = s2 * bk, t = c2 * bk;
+        const double delta = c1 * t + s1 * alpha;
+        const double gbar = -s1 * t + c1 * alpha;
+        const double gamma = std::hypot(gbar, beta_next);
+        if (!(gamma > 0)) {
+            c->err = "MINRES breakdown: singular Lanczos tridiagonal (A_h singular)";
+            return ELWH_ERR_BREAKDOWN;
+        }
+        const double cs = gbar / gamma, sn = beta_next / gamma;
+        const double tau = cs * g;
+        g = -sn * g;
+        // d_k = (v_k - delta d_{k-1} - eps d_{k-2}) / gamma, x += tau d_k
+        launch_axpby(c, 1.0 / gamma, v, -eps / gamma, d2, c->stream);
+        launch_axpby(c, -delta / gamma, d1, 1.0, d2, c->stream);
+        launch_axpby(c, tau, d2, 1.0, x, c->stream);
+        *iters = k;
+        *relres = std::fabs(g) / bn;
+        if ((tol > 0 && *relres <= tol) || beta_next == 0.0) return ELWH_OK;
+        std::swap(d1, d2);
+        launch_axpby(c, 0.0, q, 1.0 / beta_next, q, c->stream);   // v_{k+1}
+        double* old = vprev;
+        vprev = v;
+        v = q;
+        q = old;
+        c2 = c1; s2 = s1; c1 = cs; s1 = sn;
+        beta = beta_next;
+    }
+    return tol > 0 ? ELWH_ERR_NOT_CONVERGED : ELWH_OK;
+}
+
+// A residual-minimising method (CR or MINRES) from the iterate in VX, judged
+// on the true residual: when its recurrence residual meets tol but
+// ||b - A_h x||_M from an FP64 application does not, it restarts from x.
+// relfp64 receives the last true residual (-1 when none was computed).
+constexpr int kMaxReplace = 8;
+typedef elwh_status (*MinResMethod)(elwh_ctx*, bool, double, int, int*, double*);
+
+elwh_status solve_checked(elwh_ctx* c, MinResMethod method, bool x_zero, double tol, int maxit, int* iters,
+                          double* relres, double* relfp64) {
+    double bb;
+    CKST(dot_host(c, c->vec[VB], c->vec[VB], &bb));
+    *iters = 0;
+    *relfp64 = -1.0;
+    elwh_status st = ELWH_OK;
+    for (int rep = 0;; ++rep) {
+        int it = 0;
+        st = method(c, x_zero && rep == 0, tol, maxit - *iters, &it, relres);
+        *iters += it;
+        if (st != ELWH_OK || tol <= 0) break;
+        CKST(final_residual(c, c->vec[VX], bb, relfp64));
+        if (*relfp64 <= tol) break;
+        if (*iters >= maxit || rep + 1 >= kMaxReplace) {
+            st = ELWH_ERR_NOT_CONVERGED;
+            break;
+        }
+    }
+    return st;
 }
 
 // Device buffers of the GMRES orthogonalisation for restart length m: the
@@ -511,10 +635,14 @@ elwh_status solve_gmres(elwh_ctx* c, bool x_zero, double tol, int maxit, int* it
 // ============================================================================
 
 namespace elwh {
-// Conjugate residual in FP64 from the iterate in VX (right-hand side in VB),
-// for the batch's fallback after a CG breakdown.
-elwh_status ctx_solve_cr(elwh_ctx* c, double tol, int maxit, int* iters, double* relres) {
-    return solve_cr(c, false, tol, maxit, iters, relres);
+void set_create_error(const std::string& msg) { g_create_err = msg; }
+
+// Conjugate residual (method 1) or MINRES (method 2) in FP64 from the
+// iterate in VX (right-hand side in VB), judged on the true residual, for the
+// batch's fallback after a CG breakdown.
+elwh_status ctx_solve_fallback(elwh_ctx* c, int method, double tol, int maxit, int* iters, double* relres) {
+    double relfp64;
+    return solve_checked(c, method == 2 ? solve_minres : solve_cr, false, tol, maxit, iters, relres, &relfp64);
 }
 }  // namespace elwh
 
@@ -556,6 +684,10 @@ elwh_status create_impl(const elwh_grid* grid_in, const double* xc, const double
         }
         if (o.prec != ELWH_FP64) {
             g_create_err = "impedance faces need FP64 stepping";
+            return ELWH_ERR_ARG;
+        }
+        if (o.scheme == ELWH_SCHEME_MODIFIED) {
+            g_create_err = "the modified trapezoid weights are for one-field contexts (no impedance faces)";
             return ELWH_ERR_ARG;
         }
         (f < 2 ? ximp[f] : imp[f - 2]) = 1;
@@ -617,14 +749,20 @@ elwh_status create_impl(const elwh_grid* grid_in, const double* xc, const double
     if (st != ELWH_OK) return fail(st);
 
     // weights of the (K-period) trapezoid filter and the forcing factors
+    // cos(omega t_n); the modified-weights scheme (remark closing Sec. 4.4)
+    // forces at wbar = (2 / dt) asin(omega dt / 2) and multiplies each weight by
+    // cos(omega t_n) / cos(wbar t_n)
     const int ntot = c->plan.nt * o.periods;
+    const bool modified = o.scheme == ELWH_SCHEME_MODIFIED;
+    const double wbar = modified ? 2.0 * std::asin(0.5 * omega * c->plan.dt) / c->plan.dt : omega;
     c->w.resize(ntot + 1);
     c->cosn.resize(ntot + 1);
     for (int n = 0; n <= ntot; ++n) {
         const double cn = std::cos(2.0 * M_PI * n / c->plan.nt);
         const double eta = (n == 0 || n == ntot) ? 0.5 : 1.0;
-        c->cosn[n] = cn;
-        c->w[n] = (2.0 / ntot) * eta * (cn - 0.25);
+        const double cbar = modified ? std::cos(wbar * n * c->plan.dt) : cn;
+        c->cosn[n] = cbar;
+        c->w[n] = (2.0 / ntot) * eta * (cn - 0.25) * (modified ? cn / cbar : 1.0);
     }
 
     const Layout& L = c->L;
@@ -942,37 +1080,120 @@ elwh_status elwh_dot_M(elwh_ctx* c, const double* x, const double* y, double* ou
     return dot_host(c, c->vec[VT], c->vec[VD], out);
 }
 
-elwh_status elwh_cg_begin(elwh_ctx* c, const double* f, const double* x0) {
-    if (!c || !f) return ELWH_ERR_ARG;
-    if (c->imp[0] || c->imp[1]) {
-        c->err = "a context with impedance faces takes the two-field entry points (elwh_apply_filter2, "
-                 "elwh_apply_A2, elwh_solve2)";
+}  // extern "C"
+
+namespace {
+
+elwh_status impedance_error(elwh_ctx* c) {
+    c->err = "a context with impedance faces takes the two-field entry points (elwh_apply_filter2, "
+             "elwh_apply_A2, elwh_solve2)";
+    return ELWH_ERR_ARG;
+}
+
+// b = Pi_h 0 (VB) with the forcing f, FP64 stepping; *bb = ||b||_M^2.
+elwh_status prepare_rhs(elwh_ctx* c, const double* f, double* bb) {
+    pack_forcing(c, f, false);
+    compute_rhs(c);
+    CKST(dot_host(c, c->vec[VB], c->vec[VB], bb));
+    if (!std::isfinite(*bb)) {
+        c->err = "non-finite right-hand side";
         return ELWH_ERR_ARG;
     }
+    return ELWH_OK;
+}
+
+void load_start(elwh_ctx* c, const double* x0) {
+    if (x0)
+        launch_pack(c->L, c->bc, x0, c->vec[VX], c->L.dim, c->stream);
+    else
+        (void)hipMemsetAsync(c->vec[VX], 0, c->L.field_elems() * sizeof(double), c->stream);
+}
+
+// Stepwise CG from x0 once b is in VB (bb > 0): r = b - A_h x0, p = r.
+elwh_status cg_begin_rhs(elwh_ctx* c, const double* x0) {
+    load_start(c, x0);
+    c->alphas.clear();
+    c->betas.clear();
+    double rr;
+    CKST(cg_start(c, c->vec[VB], c->vec[VX], x0 == nullptr, c->vec[VR], c->vec[VP], c->vec[VQ], false, &c->cg_bb,
+                  &rr));
+    c->cg_iters = 0;
+    c->cg_active = true;
+    c->cg_qready = false;
+    c->cg_zero = false;
+    return ELWH_OK;
+}
+
+// Zero right-hand side: the solution of A_h v = 0 is v = 0.
+elwh_status cg_begin_zero(elwh_ctx* c) {
+    HIPCK(hipMemsetAsync(c->vec[VX], 0, c->L.field_elems() * sizeof(double), c->stream));
+    HIPCK(hipMemsetAsync(c->vec[VR], 0, c->L.field_elems() * sizeof(double), c->stream));
+    c->alphas.clear();
+    c->betas.clear();
+    c->cg_bb = 0.0;
+    c->cg_iters = 0;
+    c->cg_active = true;
+    c->cg_qready = false;
+    c->cg_zero = true;
+    return ELWH_OK;
+}
+
+void fill_plan(const elwh_ctx* c, elwh_info* info) {
+    info->nt = c->plan.nt;
+    info->dt = c->plan.dt;
+    info->c = c->plan.c;
+    info->lambda_bound = c->plan.lambda_bound;
+}
+
+// v = x and the CG record; known_relfp64 >= 0 is a true residual of the
+// current x computed already (saves one application).
+elwh_status cg_result_impl(elwh_ctx* c, double* v, elwh_info* info, double known_relfp64) {
+    if (v) launch_unpack(c->L, c->bc, c->vec[VX], v, c->L.dim, c->stream);
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->iters = c->cg_iters;
+        fill_plan(c, info);
+        if (c->cg_zero) {
+            info->relres = info->relres_fp64 = 0.0;
+            info->cond_est = NAN;
+        } else {
+            double rr;
+            CKST(dot_host(c, c->vec[VR], c->vec[VR], &rr));
+            info->relres = std::sqrt(rr / c->cg_bb);
+            if (known_relfp64 >= 0)
+                info->relres_fp64 = known_relfp64;
+            else
+                CKST(final_residual(c, c->vec[VX], c->cg_bb, &info->relres_fp64));
+            info->cond_est = lanczos_cond(c->alphas, c->betas);
+        }
+        info->napply = c->napply;
+    }
+    HIPCK(hipStreamSynchronize(c->stream));
+    return ELWH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+elwh_status elwh_cg_begin(elwh_ctx* c, const double* f, const double* x0) {
+    if (!c || !f) return ELWH_ERR_ARG;
+    if (c->imp[0] || c->imp[1]) return impedance_error(c);
     if (c->opts.prec != ELWH_FP64) {
         c->err = "the stepwise CG interface is FP64 only";
         return ELWH_ERR_ARG;
     }
-    pack_forcing(c, f, false);
-    compute_rhs(c);
-    if (x0)
-        launch_pack(c->L, c->bc, x0, c->vec[VX], c->L.dim, c->stream);
-    else
-        HIPCK(hipMemsetAsync(c->vec[VX], 0, c->L.field_elems() * sizeof(double), c->stream));
-    double rr;
-    c->alphas.clear();
-    c->betas.clear();
-    CKST(cg_start(c, c->vec[VB], c->vec[VX], x0 == nullptr, c->vec[VR], c->vec[VP], c->vec[VQ], false, &c->cg_bb,
-                  &rr));
-
-    c->cg_iters = 0;
-    c->cg_active = true;
-    c->cg_qready = false;
-    return ELWH_OK;
+    double bb;
+    CKST(prepare_rhs(c, f, &bb));
+    return bb > 0 ? cg_begin_rhs(c, x0) : cg_begin_zero(c);
 }
 
 elwh_status elwh_cg_iterate(elwh_ctx* c, int k, double tol, double* relres) {
     if (!c || !c->cg_active || k < 0) return ELWH_ERR_ARG;
+    if (c->cg_zero) {
+        if (relres) *relres = 0.0;
+        return ELWH_OK;
+    }
     CGOut o;
     elwh_status st = cg_steps_pipelined(c, c->vec[VX], c->vec[VR], c->vec[VP], c->vec[VQ], c->cg_bb, k, tol, &o);
     c->cg_iters += o.iters;
@@ -982,81 +1203,89 @@ elwh_status elwh_cg_iterate(elwh_ctx* c, int k, double tol, double* relres) {
 
 elwh_status elwh_cg_result(elwh_ctx* c, double* v, elwh_info* info) {
     if (!c || !c->cg_active) return ELWH_ERR_ARG;
-    if (v) launch_unpack(c->L, c->bc, c->vec[VX], v, c->L.dim, c->stream);
-    if (info) {
-        std::memset(info, 0, sizeof(*info));
-        info->iters = c->cg_iters;
-        info->nt = c->plan.nt;
-        info->dt = c->plan.dt;
-        info->c = c->plan.c;
-        info->lambda_bound = c->plan.lambda_bound;
-        double rr;
-        CKST(dot_host(c, c->vec[VR], c->vec[VR], &rr));
-        info->relres = std::sqrt(rr / c->cg_bb);
-        CKST(final_residual(c, c->vec[VX], c->cg_bb, &info->relres_fp64));
-        info->cond_est = lanczos_cond(c->alphas, c->betas);
-        info->napply = c->napply;
-    }
-    HIPCK(hipStreamSynchronize(c->stream));
-    return ELWH_OK;
+    return cg_result_impl(c, v, info, -1.0);
 }
 
 elwh_status elwh_solve(elwh_ctx* c, const double* f, const double* x0, double tol, int maxit, double* v,
                        elwh_info* info) {
     if (!c || !f || !v || maxit < 0) return ELWH_ERR_ARG;
-    if (c->imp[0] || c->imp[1]) {
-        c->err = "a context with impedance faces takes the two-field entry points (elwh_apply_filter2, "
-                 "elwh_apply_A2, elwh_solve2)";
-        return ELWH_ERR_ARG;
-    }
+    if (c->imp[0] || c->imp[1]) return impedance_error(c);
     c->napply = 0;
     elwh_info inf;
     std::memset(&inf, 0, sizeof(inf));
-    inf.nt = c->plan.nt;
-    inf.dt = c->plan.dt;
-    inf.c = c->plan.c;
-    inf.lambda_bound = c->plan.lambda_bound;
+    fill_plan(c, &inf);
     elwh_status st = ELWH_OK;
+    double bb;
+    CKST(prepare_rhs(c, f, &bb));
+    if (!(bb > 0)) {
+        // A_h v = 0: v = 0 whatever the start
+        HIPCK(hipMemsetAsync(c->vec[VX], 0, c->L.field_elems() * sizeof(double), c->stream));
+        launch_unpack(c->L, c->bc, c->vec[VX], v, c->L.dim, c->stream);
+        HIPCK(hipStreamSynchronize(c->stream));
+        inf.napply = c->napply;
+        if (info) *info = inf;
+        return ELWH_OK;
+    }
 
     if (c->opts.prec == ELWH_FP64 && c->opts.krylov == ELWH_KRYLOV_CG) {
-        CKST(elwh_cg_begin(c, f, x0));
+        CKST(cg_begin_rhs(c, x0));
         double rel = 0;
         st = elwh_cg_iterate(c, maxit, tol, &rel);
+        // Convergence is judged on the true residual: once the recurrence
+        // residual meets tol, r is replaced by b - A_h x from an FP64
+        // application and CG goes on along the same search direction until the
+        // true residual meets tol too (a reliable update).
+        double relfp64 = -1.0;
+        int replaced = 0;
+        for (int rep = 0; st == ELWH_OK && tol > 0; ++rep) {
+            double rr;
+            CKST(final_residual(c, c->vec[VX], c->cg_bb, &relfp64));   // VT = b - A_h x
+            if (relfp64 <= tol) break;
+            if (c->cg_iters >= maxit || rep + 1 >= kMaxReplace) {
+                st = ELWH_ERR_NOT_CONVERGED;
+                break;
+            }
+            rr = relfp64 * relfp64 * c->cg_bb;
+            launch_copy(c, c->vec[VT], c->vec[VR], c->stream);
+            CKST(set_scalar(c, S_RR, rr));
+            c->cg_qready = false;   // final_residual overwrote q
+            relfp64 = -1.0;
+            ++replaced;
+            st = elwh_cg_iterate(c, maxit - c->cg_iters, tol, &rel);
+        }
         if (st == ELWH_ERR_BREAKDOWN && c->opts.cr_fallback) {
-            // A_h slightly indefinite: conjugate residual from the last CG iterate
+            // A_h slightly indefinite: CR or MINRES from the last CG iterate
             int it = 0;
-            double relcr = 1.0;
-            st = solve_cr(c, false, tol, std::max(1, maxit - c->cg_iters), &it, &relcr);
-            inf.cr_iters = it;
+            double relfb = 1.0;
+            st = solve_checked(c, c->opts.cr_fallback == 2 ? solve_minres : solve_cr, false, tol,
+                               std::max(1, maxit - c->cg_iters), &it, &relfb, &relfp64);
             if (st != ELWH_OK && st != ELWH_ERR_NOT_CONVERGED) return st;
-            elwh_status st2 = elwh_cg_result(c, v, &inf);
-            if (st2 != ELWH_OK) return st2;
+            CKST(cg_result_impl(c, v, &inf, relfp64));
             inf.cr_iters = it;
-            inf.relres = relcr;
-            if (tol > 0 && !(relcr <= tol)) st = ELWH_ERR_NOT_CONVERGED;
+            inf.relres = relfb;
         } else {
             if (st != ELWH_OK && st != ELWH_ERR_NOT_CONVERGED) return st;
-            elwh_status st2 = elwh_cg_result(c, v, &inf);
-            if (st2 != ELWH_OK) return st2;
-            if (tol > 0 && !(inf.relres <= tol)) st = ELWH_ERR_NOT_CONVERGED;
+            CKST(cg_result_impl(c, v, &inf, relfp64));
         }
+        inf.outer = replaced;
+        if (tol > 0) st = inf.relres_fp64 <= tol ? ELWH_OK : ELWH_ERR_NOT_CONVERGED;
     } else if (c->opts.prec == ELWH_FP64) {
-        pack_forcing(c, f, false);
-        compute_rhs(c);
-        if (x0)
-            launch_pack(c->L, c->bc, x0, c->vec[VX], c->L.dim, c->stream);
-        else
-            HIPCK(hipMemsetAsync(c->vec[VX], 0, c->L.field_elems() * sizeof(double), c->stream));
+        load_start(c, x0);
         int it = 0;
-        double rel = 0;
-        st = c->opts.krylov == ELWH_KRYLOV_CR ? solve_cr(c, x0 == nullptr, tol, maxit, &it, &rel)
-                                              : solve_gmres(c, x0 == nullptr, tol, maxit, &it, &rel);
+        double rel = 0, relfp64 = -1.0;
+        if (c->opts.krylov == ELWH_KRYLOV_GMRES)
+            st = solve_gmres(c, x0 == nullptr, tol, maxit, &it, &rel);
+        else
+            st = solve_checked(c, c->opts.krylov == ELWH_KRYLOV_MINRES ? solve_minres : solve_cr, x0 == nullptr, tol,
+                               maxit, &it, &rel, &relfp64);
         if (st != ELWH_OK && st != ELWH_ERR_NOT_CONVERGED) return st;
         inf.iters = it;
         inf.relres = rel;
-        double bb;
-        CKST(dot_host(c, c->vec[VB], c->vec[VB], &bb));
-        CKST(final_residual(c, c->vec[VX], bb, &inf.relres_fp64));
+        if (relfp64 >= 0)
+            inf.relres_fp64 = relfp64;
+        else
+            CKST(final_residual(c, c->vec[VX], bb, &inf.relres_fp64));
+        if (tol > 0) st = inf.relres_fp64 <= tol ? ELWH_OK : ELWH_ERR_NOT_CONVERGED;
         launch_unpack(c->L, c->bc, c->vec[VX], v, c->L.dim, c->stream);
     } else {
         // FP32 stepping inside CG with FP64 reliable updates.  x, r, p and
@@ -1067,18 +1296,7 @@ elwh_status elwh_solve(elwh_ctx* c, const double* f, const double* x0, double to
         // (p = r + beta p with beta = (r, r)_M / (r_k, r_k)_M of the last CG
         // step).  Restarting CG at every replacement instead discards the
         // Krylov space and costs two to three times the iterations here.
-        pack_forcing(c, f, false);
-        compute_rhs(c);
-        if (x0)
-            launch_pack(c->L, c->bc, x0, c->vec[VX], c->L.dim, c->stream);
-        else
-            HIPCK(hipMemsetAsync(c->vec[VX], 0, c->L.field_elems() * sizeof(double), c->stream));
-        double bb;
-        CKST(dot_host(c, c->vec[VB], c->vec[VB], &bb));
-        if (!std::isfinite(bb) || !(bb > 0)) {
-            c->err = "zero or non-finite right-hand side";
-            return ELWH_ERR_ARG;
-        }
+        load_start(c, x0);
         auto true_residual = [&](bool xzero, double* rr, bool first) -> elwh_status {
             if (xzero) {
                 launch_copy(c, c->vec[VB], c->vec[VR], c->stream);
@@ -1347,7 +1565,8 @@ elwh_status elwh_autotune(elwh_ctx* c, int prec, int reps, double* best_step_us)
             for (int TY : {4, 8, 16})
                 if (tile_valid_2d(fp32, V, TY)) cands.push_back(Tile{V, TY});
     } else {
-        for (int TZ : {4, 8, 16, 32}) cands.push_back(Tile{1, TZ});
+        for (int RB : {1, 2, 4})
+            for (int TZ : {8, 16, 32}) cands.push_back(Tile{RB, TZ});
     }
     double* in = c->vec[VT];
     double* out = c->vec[VD];

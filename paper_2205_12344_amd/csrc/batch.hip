@@ -30,6 +30,7 @@ using namespace elwh;
 namespace {
 enum { VX = 0, VR, VP, VQ, VB, VT, VD, VRI };
 constexpr int GRAPH_TICKS = 32;   // ticks per graph replay (one host check of the active count each)
+constexpr int kBatchMaxReplace = 8;   // true-residual checks of the FP64 CG per solve
 }  // namespace
 
 struct elwh_batch {
@@ -286,7 +287,8 @@ elwh_status cr_fallback(elwh_batch* b, std::vector<int>& status, std::vector<int
         if (status[p] != ELWH_ERR_BREAKDOWN) continue;
         int it = 0;
         double rel = 1.0;
-        elwh_status st = ctx_solve_cr(b->ctx[p], tol, std::max(1, maxit - iters[p]), &it, &rel);
+        elwh_status st = ctx_solve_fallback(b->ctx[p], b->opts.cr_fallback, tol, std::max(1, maxit - iters[p]), &it,
+                                            &rel);
         if (st != ELWH_OK && st != ELWH_ERR_NOT_CONVERGED && st != ELWH_ERR_BREAKDOWN) {
             b->err = elwh_last_error(b->ctx[p]);
             return st;
@@ -614,6 +616,17 @@ elwh_status elwh_batch_solve(elwh_batch* b, const double* const* f, const double
     std::vector<double> relres(np, 1.0), relfp64(np, 1.0);
     std::vector<int> has_x(np, 0);
     for (int p = 0; p < np; ++p) has_x[p] = (x0 && x0[p]) ? 1 : 0;
+    for (int p = 0; p < np; ++p) {
+        if (!std::isfinite(bb[p])) {
+            (void)hipEventDestroy(ev);
+            b->err = "non-finite right-hand side";
+            return ELWH_ERR_ARG;
+        }
+        if (bb[p] > 0) continue;
+        // A_h v = 0: the solution is v = 0 whatever the start
+        has_x[p] = 0;
+        BCK(hipMemsetAsync(b->ctx[p]->vec[VX], 0, b->ctx[p]->L.field_elems() * sizeof(double), b->stream));
+    }
     long long max_nsteps = 0;
     for (auto* c : b->ctx) max_nsteps = std::max<long long>(max_nsteps, (long long)c->plan.nt * c->opts.periods);
     const long long tick_budget = (long long)(maxit + 2) * max_nsteps + 64;
@@ -642,7 +655,7 @@ elwh_status elwh_batch_solve(elwh_batch* b, const double* const* f, const double
             s.status = ELWH_ERR_NOT_CONVERGED;
             const bool done = !(bb[p] > 0) || (tol > 0 && rr[p] <= s.tol2 * bb[p]) || maxit == 0;
             s.active = done ? 0 : 1;
-            if (done) s.status = (bb[p] > 0 || maxit == 0) ? ELWH_OK : ELWH_ERR_ARG;
+            if (done) s.status = ELWH_OK;
         }
         BST(run_cg(b, false, VX, VR, VP, VQ, tick_budget));
         for (int p = 0; p < np; ++p) {
@@ -651,11 +664,58 @@ elwh_status elwh_batch_solve(elwh_batch* b, const double* const* f, const double
             if (tol <= 0 && status[p] == ELWH_ERR_NOT_CONVERGED) status[p] = ELWH_OK;
             relres[p] = bb[p] > 0 ? std::sqrt(b->h_st[p].rr / bb[p]) : 0.0;
         }
-        // final residual recomputed with an FP64 apply
-        BST(run_apply(b, false, false, true, VX, VQ, all));
-        BST(lincomb(b, all, VT, VB, 1.0, VQ, -1.0));
-        BST(dots(b, all, VT, VT, rr));
-        for (int p = 0; p < np; ++p) relfp64[p] = bb[p] > 0 ? std::sqrt(rr[p] / bb[p]) : 0.0;
+        // Convergence is judged on the true residual, recomputed with an FP64
+        // apply: a problem whose recurrence residual met tol but whose true
+        // residual did not has r replaced by b - A_h x and continues CG along
+        // the same search direction (a reliable update), like elwh_solve.
+        for (int rep = 0;; ++rep) {
+            BST(run_apply(b, false, false, true, VX, VQ, all));
+            BST(lincomb(b, all, VT, VB, 1.0, VQ, -1.0));
+            BST(dots(b, all, VT, VT, rr));
+            std::vector<int> more(np, 0);
+            bool any = false;
+            for (int p = 0; p < np; ++p) {
+                relfp64[p] = bb[p] > 0 ? std::sqrt(rr[p] / bb[p]) : 0.0;
+                if (tol <= 0 || !(bb[p] > 0) || status[p] != ELWH_OK || relfp64[p] <= tol) continue;
+                if (iters[p] >= maxit || rep + 1 >= kBatchMaxReplace) {
+                    status[p] = ELWH_ERR_NOT_CONVERGED;
+                    continue;
+                }
+                more[p] = 1;
+                any = true;
+            }
+            if (!any) break;
+            // r = b - A_h x; p = r + beta p with beta = (r, r)_M / (r_k, r_k)_M, r_k
+            // the residual before the last CG step (rr_k = rr / beta of that step)
+            std::vector<double> beta(np, 0.0);
+            for (int p = 0; p < np; ++p) {
+                const BState& s = b->h_st[p];
+                if (more[p] && s.beta > 0 && s.rr > 0) beta[p] = rr[p] / (s.rr / s.beta);
+            }
+            BST(lincomb(b, more, VR, VT, 1.0, -1, 0.0));
+            BST(lincomb(b, more, VP, VR, 1.0, VP, 0.0, &beta));
+            for (int p = 0; p < np; ++p) {
+                BState& s = b->h_st[p];
+                const int keep_iters = iters[p];
+                std::memset(&s, 0, sizeof(s));
+                if (!more[p]) continue;
+                s.rr = rr[p];
+                s.bb = bb[p];
+                s.tol2 = tol * tol;
+                s.maxit = std::max(1, maxit - keep_iters);
+                s.status = ELWH_ERR_NOT_CONVERGED;
+                s.active = 1;
+            }
+            BST(run_cg(b, false, VX, VR, VP, VQ, tick_budget));
+            for (int p = 0; p < np; ++p) {
+                if (!more[p]) continue;
+                outer[p]++;
+                iters[p] += b->h_st[p].iters;
+                status[p] = b->h_st[p].status;
+                if (status[p] == ELWH_ERR_NOT_CONVERGED && iters[p] < maxit) status[p] = ELWH_OK;
+                relres[p] = std::sqrt(b->h_st[p].rr / bb[p]);
+            }
+        }
         if (b->opts.cr_fallback) BST(cr_fallback(b, status, iters, cr_iters, relres, relfp64, bb, tol, maxit));
     } else {
         // FP32 stepping inside CG with FP64 reliable updates (as elwh_solve):

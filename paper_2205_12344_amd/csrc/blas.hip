@@ -385,3 +385,36 @@ void launch_copy(const elwh_ctx* c, const double* x, double* y, hipStream_t s) {
 }
 
 }  // namespace elwh
+
+// ---- HBM ceiling probe ---------------------------------------------------------
+// STREAM triad a = b + s c over n doubles: each thread moves one 32-byte
+// vector of each array (three 16-byte vector accesses per array half), the
+// grid covers the arrays once, so every byte crosses HBM exactly once when
+// the arrays exceed the 256 MiB Infinity Cache.
+namespace {
+__global__ __launch_bounds__(256) void triad_kernel(double* __restrict__ a, const double* __restrict__ b,
+                                                    const double* __restrict__ c, double s, int64_t n4) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= n4) return;
+    const double4 bv = reinterpret_cast<const double4*>(b)[t];
+    const double4 cv = reinterpret_cast<const double4*>(c)[t];
+    double4 r;
+    r.x = bv.x + s * cv.x;
+    r.y = bv.y + s * cv.y;
+    r.z = bv.z + s * cv.z;
+    r.w = bv.w + s * cv.w;
+    reinterpret_cast<double4*>(a)[t] = r;
+}
+}  // namespace
+
+extern "C" elwh_status elwh_stream_triad(double* a, const double* b, const double* c, double s, long long n,
+                                         void* stream) {
+    if (!a || !b || !c || n <= 0 || n % 4 != 0 || ((uintptr_t)a | (uintptr_t)b | (uintptr_t)c) % 32 != 0)
+        return ELWH_ERR_ARG;
+    const int64_t n4 = n / 4;
+    const int64_t blocks = (n4 + 255) / 256;
+    if (blocks > 0x7fffffffLL) return ELWH_ERR_ARG;
+    hipLaunchKernelGGL(triad_kernel, dim3((unsigned)blocks), dim3(256), 0, static_cast<hipStream_t>(stream), a, b, c,
+                       s, n4);
+    return hipGetLastError() == hipSuccess ? ELWH_OK : ELWH_ERR_HIP;
+}

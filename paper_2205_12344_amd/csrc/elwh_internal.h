@@ -195,6 +195,7 @@ struct elwh_ctx {
     hipEvent_t ev_scal = nullptr;      // marks the device-to-host copy of the CG scalars
     int cg_iters = 0;
     double cg_bb = 0;
+    bool cg_zero = false;              // ||b||_M = 0: the solution is x = 0
     std::vector<double> alphas, betas;
     int napply = 0;
 };
@@ -230,9 +231,12 @@ March make_march(const elwh_grid* g, const int bc[6]);
 // (nsteps = number of step launches of this application).
 void prof_mark(elwh_ctx* c, int phase, int nsteps = 0);
 bool tile_valid_2d(bool fp32, int V, int TY);
-// Conjugate residual (FP64 applications) from the iterate in vec[0] with the
-// right-hand side in vec[4], on the context's stream (api.hip).
-elwh_status ctx_solve_cr(elwh_ctx* c, double tol, int maxit, int* iters, double* relres);
+// Conjugate residual (method 1) or MINRES (method 2), FP64 applications, from
+// the iterate in vec[0] with the right-hand side in vec[4], on the context's
+// stream, restarted while the true residual misses tol (api.hip).
+elwh_status ctx_solve_fallback(elwh_ctx* c, int method, double tol, int maxit, int* iters, double* relres);
+// The message elwh_last_error(NULL) returns (calls without a context).
+void set_create_error(const std::string& msg);
 bool tile_valid_3d(bool fp32, int V, int TZ);
 bool tile_valid_curv(bool fp32, int V, int TY);
 // One filter application on a mapped 2-D grid (kernels2d_curv.hip).

@@ -9,11 +9,16 @@
 // are closed from the discrete energy (one-sided normal differences, the
 // trapezoid weight 1/2 divided out).
 //
-// Mapping: one 64-lane wavefront per block owns 64 x nodes (62 computed) of
-// one y row and marches TZ planes in z.  Three planes x three rows of the
-// displacement live in registers and roll in z; x neighbours come from the
-// adjacent lanes; y-neighbour rows are separate coalesced row loads that
-// hit in cache (they are the own rows of the neighbouring wavefronts).
+// Mapping: a workgroup of RB 64-lane wavefronts owns 64 x nodes (62
+// computed) of RB consecutive y rows, one row per wavefront, and marches TZ
+// planes in z.  Three planes x three rows of the displacement live in
+// registers and roll in z; x neighbours come from the adjacent lanes;
+// y-neighbour rows are separate coalesced row loads.  The rows j - 1 and
+// j + 1 a wavefront loads are the own rows of the wavefronts beside it in the
+// same workgroup, which load them at about the same time on the same CU, so
+// they are served by that CU's cache and the L2 instead of being fetched
+// again after the L2 has dropped them (RB = 1 leaves that reuse to chance
+// across workgroups).
 #include "elwh_internal.h"
 #include "lanes.h"
 #include "xcd.h"
@@ -55,24 +60,25 @@ __device__ __forceinline__ void acc_add3(double& hi, double& lo, double x, bool 
     }
 }
 
-template <typename T, typename U, int TZ, int MODE, bool FORCE, bool COMP>
-__global__ __launch_bounds__(64) void step3d_kernel(const U* __restrict__ u, const T* uprev, T* unext,
+template <typename T, typename U, int TZ, int RB, int MODE, bool FORCE, bool COMP>
+__global__ __launch_bounds__(64 * RB) void step3d_kernel(const U* __restrict__ u, const T* uprev, T* unext,
                                                    const double* __restrict__ xbase, T* __restrict__ u0out,
                                                    double* __restrict__ acc, double* __restrict__ acclo,
                                                    const T* __restrict__ ca, const T* __restrict__ cl,
                                                    const T* __restrict__ cm, const T* __restrict__ f,
                                                    Args3D A) {
-    const int lane = threadIdx.x;
-    // tiles (x-strip, y-row, z-chunk) in XCD bands, x fastest
-    const int nbx = (A.nx - 1 + 61) / 62, nyr = A.ny - 1;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // tiles (x-strip, group of RB y-rows, z-chunk) in XCD bands, x fastest
+    const int nbx = (A.nx - 1 + 61) / 62, nyg = (A.ny - 1 + RB - 1) / RB;
     const int nzc = (A.khi - A.klo + 1 + TZ - 1) / TZ;
     int t;
-    if (!xcd_tile((int)blockIdx.x, nbx * nyr * nzc, t)) return;
+    if (!xcd_tile((int)blockIdx.x, nbx * nyg * nzc, t)) return;
     const int i = 62 * (t % nbx) + lane;
-    const int j = 1 + (t / nbx) % nyr;
+    const int j = 1 + ((t / nbx) % nyg) * RB + wave;
+    if (j > A.ny - 1) return;   // the last row group is ragged (wavefront-uniform exit)
     const bool colv = i <= A.nx;
     const bool store = lane >= 1 && lane <= 62 && i >= 1 && i <= A.nx - 1;
-    const int k0 = A.klo + (t / (nbx * nyr)) * TZ;
+    const int k0 = A.klo + (t / (nbx * nyg)) * TZ;
     if (k0 > A.khi) return;
     const int k1 = min(k0 + TZ - 1, A.khi);
     const int64_t P = A.P, PS = A.PS, CS = A.CS;
@@ -247,13 +253,13 @@ __global__ __launch_bounds__(64) void step3d_kernel(const U* __restrict__ u, con
     }
 }
 
-template <typename T, typename U, int TZ, int MODE>
+template <typename T, typename U, int TZ, int RB, int MODE>
 static void launch3_t(bool force, bool comp, dim3 grid, hipStream_t s, const U* u, const T* uprev, T* unext,
                       const double* xbase, T* u0out, double* acc, double* acclo, const T* ca, const T* cl,
                       const T* cm, const T* f, const Args3D& A) {
-#define ELWH_L3(F, CMP)                                                                                   \
-    hipLaunchKernelGGL((step3d_kernel<T, U, TZ, MODE, F, CMP>), grid, dim3(64), 0, s, u, uprev, unext, xbase, \
-                       u0out, acc, acclo, ca, cl, cm, f, A)
+#define ELWH_L3(F, CMP)                                                                                          \
+    hipLaunchKernelGGL((step3d_kernel<T, U, TZ, RB, MODE, F, CMP>), grid, dim3(64 * RB), 0, s, u, uprev, unext, \
+                       xbase, u0out, acc, acclo, ca, cl, cm, f, A)
     if (force) {
         if (comp) ELWH_L3(true, true); else ELWH_L3(true, false);
     } else {
@@ -262,28 +268,39 @@ static void launch3_t(bool force, bool comp, dim3 grid, hipStream_t s, const U* 
 #undef ELWH_L3
 }
 
+// 3-D tiling: V = y rows per workgroup (one wavefront each), TZ = planes
+// marched per wavefront.
 bool tile_valid_3d(bool fp32, int V, int TZ) {
     (void)fp32;
-    return V == 1 && (TZ == 4 || TZ == 8 || TZ == 16 || TZ == 32);
+    return (V == 1 || V == 2 || V == 4 || V == 8) && (TZ == 4 || TZ == 8 || TZ == 16 || TZ == 32);
 }
 
 template <typename T, typename U, int MODE>
-static void launch3_z(int TZ, bool force, bool comp, const Args3D& A, hipStream_t s, const U* u, const T* uprev,
-                      T* unext, const double* xbase, T* u0out, double* acc, double* acclo, const T* ca, const T* cl,
-                      const T* cm, const T* f) {
+static void launch3_z(int RB, int TZ, bool force, bool comp, const Args3D& A, hipStream_t s, const U* u,
+                      const T* uprev, T* unext, const double* xbase, T* u0out, double* acc, double* acclo,
+                      const T* ca, const T* cl, const T* cm, const T* f) {
     const int nplanes = A.khi - A.klo + 1;
-    auto grid = [&](int tz) {
-        return dim3((unsigned)xcd_grid(((A.nx - 1 + 61) / 62) * (A.ny - 1) * ((nplanes + tz - 1) / tz)), 1, 1);
+    auto grid = [&](int rb, int tz) {
+        const int nyg = (A.ny - 1 + rb - 1) / rb;
+        return dim3((unsigned)xcd_grid(((A.nx - 1 + 61) / 62) * nyg * ((nplanes + tz - 1) / tz)), 1, 1);
     };
-#define ELWH_Z(TT)                                                                                              \
-    if (TZ == TT) {                                                                                             \
-        launch3_t<T, U, TT, MODE>(force, comp, grid(TT), s, u, uprev, unext, xbase, u0out, acc, acclo, ca, cl, cm, \
-                                  f, A);                                                                        \
-        return;                                                                                                 \
+    // the half step (MODE 1) runs once per application: one wavefront per block
+    if constexpr (MODE == 1) RB = 1;
+#define ELWH_Z(RR, TT)                                                                                           \
+    if (RB == RR && TZ == TT) {                                                                                  \
+        launch3_t<T, U, TT, RR, MODE>(force, comp, grid(RR, TT), s, u, uprev, unext, xbase, u0out, acc, acclo, ca, \
+                                      cl, cm, f, A);                                                             \
+        return;                                                                                                  \
     }
-    ELWH_Z(4) ELWH_Z(8) ELWH_Z(16) ELWH_Z(32)
+    ELWH_Z(1, 4) ELWH_Z(1, 8) ELWH_Z(1, 16) ELWH_Z(1, 32)
+    if constexpr (MODE == 0) {
+        ELWH_Z(2, 4) ELWH_Z(2, 8) ELWH_Z(2, 16) ELWH_Z(2, 32)
+        ELWH_Z(4, 4) ELWH_Z(4, 8) ELWH_Z(4, 16) ELWH_Z(4, 32)
+        ELWH_Z(8, 4) ELWH_Z(8, 8) ELWH_Z(8, 16) ELWH_Z(8, 32)
+    }
 #undef ELWH_Z
-    launch3_t<T, U, 16, MODE>(force, comp, grid(16), s, u, uprev, unext, xbase, u0out, acc, acclo, ca, cl, cm, f, A);
+    launch3_t<T, U, 16, 1, MODE>(force, comp, grid(1, 16), s, u, uprev, unext, xbase, u0out, acc, acclo, ca, cl, cm,
+                                 f, A);
 }
 
 void run_filter_3d(elwh_ctx* c, const double* x, bool with_force, bool amode, bool fp32, double* out) {
@@ -310,6 +327,7 @@ void run_filter_3d(elwh_ctx* c, const double* x, bool with_force, bool amode, bo
     A.cfyz = c->st.cfyz;
     A.final_ = 0;
     const int TZ = fp32 ? c->tile32.TY : c->tile64.TY;
+    const int RB = fp32 ? c->tile32.V : c->tile64.V;
     const int nsteps = c->plan.nt * c->opts.periods;
     const double sgn = amode ? -1.0 : 1.0;
     const bool comp = fp32 && c->opts.compensated;
@@ -321,7 +339,7 @@ void run_filter_3d(elwh_ctx* c, const double* x, bool with_force, bool amode, bo
     if (!fp32) {
         double *b0 = c->s64[0], *b1 = c->s64[1];
         prof_mark(c, 0);
-        launch3_z<double, double, 1>(TZ, with_force, false, A, s, x, nullptr, b1, amode ? x : nullptr, nullptr, acc,
+        launch3_z<double, double, 1>(RB, TZ, with_force, false, A, s, x, nullptr, b1, amode ? x : nullptr, nullptr, acc,
                                      lo, c->ca, c->cl, c->cm, c->f64);
         prof_mark(c, 1);
         const double* prev = x;
@@ -330,7 +348,7 @@ void run_filter_3d(elwh_ctx* c, const double* x, bool with_force, bool amode, bo
             double* nxt = (n == 1) ? b0 : const_cast<double*>(prev);
             A.w = sgn * c->w[n + 1];
             A.fc = c->cosn[n];
-            launch3_z<double, double, 0>(TZ, with_force, false, A, s, cur, prev, nxt, nullptr, nullptr, acc, lo,
+            launch3_z<double, double, 0>(RB, TZ, with_force, false, A, s, cur, prev, nxt, nullptr, nullptr, acc, lo,
                                          c->ca, c->cl, c->cm, c->f64);
             prev = cur;
             cur = nxt;
@@ -338,7 +356,7 @@ void run_filter_3d(elwh_ctx* c, const double* x, bool with_force, bool amode, bo
     } else {
         float *b0 = c->s32[0], *b1 = c->s32[1];
         prof_mark(c, 0);
-        launch3_z<float, double, 1>(TZ, with_force, comp, A, s, x, nullptr, b1, amode ? x : nullptr, b0, acc, lo,
+        launch3_z<float, double, 1>(RB, TZ, with_force, comp, A, s, x, nullptr, b1, amode ? x : nullptr, b0, acc, lo,
                                     c->fa, c->fl, c->fm, c->f32);
         prof_mark(c, 1);
         float* prev = b0;
@@ -347,7 +365,7 @@ void run_filter_3d(elwh_ctx* c, const double* x, bool with_force, bool amode, bo
             A.w = sgn * c->w[n + 1];
             A.fc = c->cosn[n];
             A.final_ = (n == nsteps - 1);
-            launch3_z<float, float, 0>(TZ, with_force, comp, A, s, cur, prev, prev, nullptr, nullptr, acc, lo,
+            launch3_z<float, float, 0>(RB, TZ, with_force, comp, A, s, cur, prev, prev, nullptr, nullptr, acc, lo,
                                        c->fa, c->fl, c->fm, c->f32);
             float* t = prev;
             prev = cur;

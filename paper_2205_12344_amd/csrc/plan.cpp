@@ -402,10 +402,16 @@ elwh_status plan_from_bound(double G, double omega, const elwh_opts* o, Plan* ou
         if (!(q < 1e8)) { *err = "too many steps per period"; return ELWH_ERR_ARG; }
         nt = std::max(3, (int)q);
     }
+    if (o && o->scheme == ELWH_SCHEME_MODIFIED && nt < 4) {
+        // the forcing frequency (2 / dt) asin(omega dt / 2) needs omega dt / 2 = pi / N_T < 1
+        *err = "the modified trapezoid weights need at least 4 steps per period";
+        return ELWH_ERR_ARG;
+    }
     out->nt = nt;
     out->T = T;
     out->dt = T / nt;
     out->lambda_bound = G;
+    // the standard and the modified-weights schemes step with the uncorrected leapfrog
     const bool corrected = !o || o->scheme == ELWH_SCHEME_CORRECTED;
     const double x = 0.5 * omega * out->dt;
     out->c = corrected ? (std::sin(x) / x) * (std::sin(x) / x) : 1.0;
@@ -584,13 +590,15 @@ elwh_status check_config(const elwh_grid* g, const int bc[6], const elwh_opts* o
         if (o->nt < 0 || (o->nt > 0 && o->nt < 3)) { *err = "nt must be 0 (rule) or >= 3"; return ELWH_ERR_ARG; }
         if (o->periods < 1 || o->periods > 1000) { *err = "periods must be in [1, 1000]"; return ELWH_ERR_ARG; }
         if (o->prec != ELWH_FP64 && o->prec != ELWH_FP32_STEP) { *err = "bad precision"; return ELWH_ERR_ARG; }
-        if (o->krylov < 0 || o->krylov > 2) { *err = "bad krylov method"; return ELWH_ERR_ARG; }
+        if (o->krylov < 0 || o->krylov > 3) { *err = "bad krylov method"; return ELWH_ERR_ARG; }
+        if (o->cr_fallback < 0 || o->cr_fallback > 2) { *err = "cr_fallback must be 0, 1 or 2"; return ELWH_ERR_ARG; }
         if (o->prec == ELWH_FP32_STEP && o->krylov != ELWH_KRYLOV_CG) {
-            *err = "FP32 stepping solves with CG (residual-replacement segments); GMRES and CR need FP64";
+            *err = "FP32 stepping solves with CG (residual-replacement segments); GMRES, CR and MINRES need FP64";
             return ELWH_ERR_ARG;
         }
         if (o->gmres_m < 1 || o->gmres_m > 200) { *err = "gmres_m must be in [1, 200]"; return ELWH_ERR_ARG; }
-        if (o->scheme != ELWH_SCHEME_CORRECTED && o->scheme != ELWH_SCHEME_STANDARD) { *err = "bad scheme"; return ELWH_ERR_ARG; }
+        if (o->scheme != ELWH_SCHEME_CORRECTED && o->scheme != ELWH_SCHEME_STANDARD &&
+            o->scheme != ELWH_SCHEME_MODIFIED) { *err = "bad scheme"; return ELWH_ERR_ARG; }
         if (o->fuse < 1 || o->fuse > 4) { *err = "fuse must be in [1, 4]"; return ELWH_ERR_ARG; }
     }
     return ELWH_OK;

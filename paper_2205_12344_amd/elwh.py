@@ -20,8 +20,9 @@ OK, ERR_ARG, ERR_ALLOC, ERR_HIP, ERR_UNSTABLE, ERR_NOT_CONVERGED, ERR_BREAKDOWN 
 STATUS_NAMES = ["OK", "ERR_ARG", "ERR_ALLOC", "ERR_HIP", "ERR_UNSTABLE", "ERR_NOT_CONVERGED", "ERR_BREAKDOWN"]
 BC_DIRICHLET, BC_TRACTION_FREE, BC_IMPEDANCE = 0, 1, 2
 FP64, FP32_STEP = 0, 1
-KRYLOV_CG, KRYLOV_GMRES, KRYLOV_CR = 0, 1, 2
-SCHEME_CORRECTED, SCHEME_STANDARD = 0, 1
+KRYLOV_CG, KRYLOV_GMRES, KRYLOV_CR, KRYLOV_MINRES = 0, 1, 2, 3
+SCHEME_CORRECTED, SCHEME_STANDARD, SCHEME_MODIFIED = 0, 1, 2
+FALLBACK_NONE, FALLBACK_CR, FALLBACK_MINRES = 0, 1, 2
 
 EXPORTED = [
     "elwh_default_opts", "elwh_plan", "elwh_create", "elwh_plan_mapped", "elwh_create_mapped",
@@ -34,7 +35,7 @@ EXPORTED = [
     "elwh_batch_last_error", "elwh_batch_destroy",
     "elwh_ws_create", "elwh_ws_destroy", "elwh_ws_last_error", "elwh_ws_num_params", "elwh_ws_params",
     "elwh_ws_forward", "elwh_ws_loss_grad", "elwh_ws_train_step", "elwh_ws_features", "elwh_ws_from_field",
-    "elwh_ws_predict",
+    "elwh_ws_predict", "elwh_stream_triad",
 ]
 
 
@@ -105,6 +106,7 @@ def _load():
     lib.elwh_cg_iterate.argtypes = [P, I, D, ctypes.POINTER(D)]
     lib.elwh_cg_result.argtypes = [P, P, ctypes.POINTER(Info)]
     lib.elwh_dot_M.argtypes = [P, P, P, ctypes.POINTER(D)]
+    lib.elwh_stream_triad.argtypes = [P, P, P, D, ctypes.c_longlong, P]
     lib.elwh_set_tile.argtypes = [P, I, I, I]
     lib.elwh_get_tile.argtypes = [P, I, ctypes.POINTER(I), ctypes.POINTER(I)]
     lib.elwh_autotune.argtypes = [P, I, I, ctypes.POINTER(D)]
@@ -199,6 +201,19 @@ def plan(dim, n, rho, lam, mu, omega, bc, length=None, **opts):
     if st != OK:
         raise ElwhError(st, lib.elwh_last_error(None).decode())
     return {"nt": info.nt, "dt": info.dt, "c": info.c, "lambda_bound": info.lambda_bound}
+
+
+def stream_triad(a, b, c, s=3.0, stream=None):
+    """a = b + s c on the GPU (elwh_stream_triad), asynchronous; a, b, c
+    contiguous float64 CUDA tensors of one length (a multiple of 4)."""
+    n = a.numel()
+    if not all(isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+               and t.numel() == n for t in (a, b, c)):
+        raise TypeError("expected three contiguous float64 CUDA tensors of one length")
+    st = (torch.cuda.current_stream() if stream is None else stream).cuda_stream
+    r = lib.elwh_stream_triad(a.data_ptr(), b.data_ptr(), c.data_ptr(), float(s), int(n), ctypes.c_void_p(st))
+    if r != OK:
+        raise ElwhError(r, "elwh_stream_triad")
 
 
 def filter_diagnostics(nt, periods=1, omega=1.0, scheme=0):

@@ -236,9 +236,12 @@ def test_solve_square64_matches_direct_and_oracle_cg(E):
     _say("square64 solve", info)
     v = v.cpu().numpy()
     assert info["iters"] <= 20
-    assert info["relres_fp64"] <= 1.1e-10
+    assert info["relres_fp64"] <= 1e-10
     assert _rel(prob.gather(v), vstar) <= 1e-10
     res = krylov.cg(wh.apply_A, wh.rhs(fv), op.m, tol=1e-10, maxit=200)
+    # no residual replacement was needed here: the recurrence residual and
+    # the true one agree, so the solve is the oracle's plain CG
+    assert info["outer"] == 0
     assert res.iters == info["iters"]
     assert _rel(prob.gather(v), res.x) <= 1e-12
     assert info["cond_est"] == pytest.approx(res.lanczos_cond(), rel=1e-6)
@@ -470,7 +473,7 @@ def _tiles(dim, fp32):
     if dim == 2:
         vs = (1, 2, 4) if fp32 else (1, 2)
         return [(v, ty) for v in vs for ty in (4, 8, 16)]
-    return [(1, tz) for tz in (4, 8, 16, 32)]
+    return [(rb, tz) for rb in (1, 2, 4, 8) for tz in (4, 8, 16, 32)]
 
 
 @pytest.mark.parametrize("dim", [2, 3])

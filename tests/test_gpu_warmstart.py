@@ -162,6 +162,6 @@ def test_trained_network_start_vs_zero_start(E):
          "reduction", float(np.mean([1 - a / b for a, b in zip(l, z)])))
     assert st0 == st1 == "OK"
     for a, b, i in zip(l, z, learned):
-        assert i["relres_fp64"] <= 2e-8
+        assert i["relres_fp64"] <= 1e-8
         assert a <= b + 2
     net.close()
