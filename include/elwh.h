@@ -362,6 +362,31 @@ elwh_status elwh_cg_result(elwh_ctx* ctx, double* v, elwh_info* info);
 elwh_status elwh_dot_M(elwh_ctx* ctx, const double* x, const double* y, double* out);
 
 /*
+ * elwh_dot_M_noalloc: the same M inner product as elwh_dot_M, for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): it needs no context and
+ * makes no hipMalloc, hipFree or other allocating call.
+ *   grid    dim 2 or 3, n[a] >= 2 cells per axis, at most 2^31 nodes per
+ *           component (ELWH_ERR_ARG beyond); len is not used
+ *   rho     DEVICE array, node layout (one component); the weight of node i
+ *           is rho_i times 1/2 per traction-type face (free or impedance) it
+ *           lies on, 0 on Dirichlet faces -- the M of elwh_create.  On a
+ *           mapped grid pass rho J to get the M of elwh_create_mapped.
+ *   bc      the faces, as in elwh_create (the first 2*dim entries are read)
+ *   x, y    DEVICE fields in the caller layout [dim][nodes]
+ *   stream  hipStream_t to run on (NULL: the null stream)
+ *   out     HOST double; the call synchronises the stream
+ * The two reduction passes keep their 512 partial sums and the result in a
+ * fixed 4.5 KiB device array of the library (one per GPU, held until the
+ * process ends), so the result is deterministic and does not depend on the
+ * grid size; every call on one GPU shares that array, so calls that overlap
+ * on one GPU (other streams or host threads) race.  Errors: ELWH_ERR_ARG,
+ * ELWH_ERR_HIP; the message is elwh_last_error(NULL).
+ */
+elwh_status elwh_dot_M_noalloc(const elwh_grid* grid, const double* rho, const int bc[6], const double* x,
+                               const double* y, void* stream, double* out);
+
+/*
  * Measurement aid (not part of the method): the STREAM triad a = b + s c
  * over n doubles (n a multiple of 4, arrays 32-byte aligned, DEVICE
  * pointers), one 32-byte vector per thread, asynchronous on stream.  Timed

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libelwh.so")
 SOURCES = ["api.hip", "batch.hip", "batch_kernels.hip", "kernels2d.hip", "kernels2d_multi.hip", "kernels2d_curv.hip", "kernels2d_damped.hip", "kernels3d.hip", "blas.hip", "nn.hip", "nn_kernels.hip",
-           "plan.cpp"]
+           "noalloc.hip", "plan.cpp"]
 ARCH = "gfx950"
 
 

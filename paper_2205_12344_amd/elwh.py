@@ -35,7 +35,7 @@ EXPORTED = [
     "elwh_batch_last_error", "elwh_batch_destroy",
     "elwh_ws_create", "elwh_ws_destroy", "elwh_ws_last_error", "elwh_ws_num_params", "elwh_ws_params",
     "elwh_ws_forward", "elwh_ws_loss_grad", "elwh_ws_train_step", "elwh_ws_features", "elwh_ws_from_field",
-    "elwh_ws_predict", "elwh_stream_triad",
+    "elwh_ws_predict", "elwh_dot_M_noalloc", "elwh_stream_triad",
 ]
 
 
@@ -107,6 +107,7 @@ def _load():
     lib.elwh_cg_result.argtypes = [P, P, ctypes.POINTER(Info)]
     lib.elwh_dot_M.argtypes = [P, P, P, ctypes.POINTER(D)]
     lib.elwh_stream_triad.argtypes = [P, P, P, D, ctypes.c_longlong, P]
+    lib.elwh_dot_M_noalloc.argtypes = [ctypes.POINTER(Grid), P, ctypes.POINTER(I), P, P, P, ctypes.POINTER(D)]
     lib.elwh_set_tile.argtypes = [P, I, I, I]
     lib.elwh_get_tile.argtypes = [P, I, ctypes.POINTER(I), ctypes.POINTER(I)]
     lib.elwh_autotune.argtypes = [P, I, I, ctypes.POINTER(D)]
@@ -201,6 +202,22 @@ def plan(dim, n, rho, lam, mu, omega, bc, length=None, **opts):
     if st != OK:
         raise ElwhError(st, lib.elwh_last_error(None).decode())
     return {"nt": info.nt, "dt": info.dt, "c": info.c, "lambda_bound": info.lambda_bound}
+
+
+def dot_M_noalloc(dim, n, rho, bc, x, y, stream=None):
+    """(x, y)_M without a context and without device allocation
+    (elwh_dot_M_noalloc); rho, x, y CUDA float64 tensors in node layout."""
+    g = make_grid(dim, n)
+    for name, t in (("rho", rho), ("x", x), ("y", y)):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+            raise TypeError(f"{name}: expected a contiguous float64 CUDA tensor")
+    s = (torch.cuda.current_stream() if stream is None else stream).cuda_stream
+    r = ctypes.c_double()
+    st = lib.elwh_dot_M_noalloc(ctypes.byref(g), rho.data_ptr(), _bc_array(bc), x.data_ptr(), y.data_ptr(),
+                                ctypes.c_void_p(s), ctypes.byref(r))
+    if st != OK:
+        raise ElwhError(st, lib.elwh_last_error(None).decode())
+    return r.value
 
 
 def stream_triad(a, b, c, s=3.0, stream=None):
