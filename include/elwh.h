@@ -485,6 +485,9 @@ void elwh_batch_destroy(elwh_batch* b);
  *                     f_x / max|f|, f_y / max|f|, 5 omega / n, omega / 60),
  *                     w = M weight of the node (0 on Dirichlet nodes)
  *   elwh_ws_from_field targets y = v omega^2 / (max|f| k), k the output scale
+ *   elwh_ws_normalize  y[b] /= its w-weighted RMS over both components (the
+ *                     solver rescales the guess optimally, so the network
+ *                     learns shapes; asynchronous)
  *   elwh_ws_predict   forward pass, then x0 = y max|f| k / omega^2 on the
  *                     unknown nodes (0 elsewhere), written to x0[b] (caller
  *                     layout [2][n+1][n+1])
@@ -516,6 +519,7 @@ elwh_status elwh_ws_features(elwh_ws* ws, int B, int n, const double* const* rho
                              float* w);
 elwh_status elwh_ws_from_field(elwh_ws* ws, int B, int n, const double* const* f, const double* const* v,
                                const double* omega_dev, float* y);
+elwh_status elwh_ws_normalize(elwh_ws* ws, int B, float* y, const float* w);
 elwh_status elwh_ws_predict(elwh_ws* ws, int B, int n, const float* x, const double* const* f,
                             const double* omega_dev, double* const* x0);
 

@@ -247,6 +247,38 @@ __global__ void fmax_kernel(const double* const* __restrict__ f, int nn, double*
     if (threadIdx.x == 0) out[blockIdx.x] = red[0] > 0 ? red[0] : 1.0;
 }
 
+// Per-sample target normalisation: y[b] /= sqrt(sum w y^2 / (2 sum w)), the
+// w-weighted RMS over both components (one block per sample, FP64 sums;
+// samples with no weight or a zero target are left as they are).
+__global__ void normalize_kernel(float* __restrict__ y, const float* __restrict__ w, int npix) {
+    float* yb = y + (int64_t)blockIdx.x * npix * 2;
+    const float* wb = w + (int64_t)blockIdx.x * npix;
+    double sy = 0.0, sw = 0.0;
+    for (int p = threadIdx.x; p < npix; p += blockDim.x) {
+        const double wp = wb[p], a = yb[2 * p], c = yb[2 * p + 1];
+        sy += wp * (a * a + c * c);
+        sw += wp;
+    }
+    __shared__ double r1[256], r2[256];
+    __shared__ float scale;
+    r1[threadIdx.x] = sy;
+    r2[threadIdx.x] = sw;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) {
+            r1[threadIdx.x] += r1[threadIdx.x + st];
+            r2[threadIdx.x] += r2[threadIdx.x + st];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double rms = r2[0] > 0 ? sqrt(r1[0] / (2.0 * r2[0])) : 0.0;
+        scale = rms > 0 ? (float)(1.0 / rms) : 1.0f;
+    }
+    __syncthreads();
+    for (int p = threadIdx.x; p < 2 * npix; p += blockDim.x) yb[p] *= scale;
+}
+
 // x[b,py,px,:] = (log rho/0.2, log mu/0.2, log(lam/mu)/0.5, fx/fmax, fy/fmax, 5 omega h, omega/60)
 // w[b,py,px] = M weight of the node (trapezoid weight * rho), 0 on Dirichlet nodes
 __global__ void features_kernel(const double* const* __restrict__ rho, const double* const* __restrict__ lam,
@@ -520,6 +552,13 @@ elwh_status elwh_ws_from_field(elwh_ws* ws, int B, int n, const double* const* f
     hipLaunchKernelGGL(from_field_kernel, dim3(g1((int64_t)B * n * n)), dim3(256), 0, ws->stream, d + 4 * M,
                        omega_dev, ws->fmax, ws->out_scale, n, y, B);
     WCK(hipStreamSynchronize(ws->stream));
+    WCK(hipGetLastError());
+    return ELWH_OK;
+}
+
+elwh_status elwh_ws_normalize(elwh_ws* ws, int B, float* y, const float* w) {
+    if (!ws || B < 1 || B > ws->maxB || !y || !w) return ELWH_ERR_ARG;
+    hipLaunchKernelGGL(normalize_kernel, dim3(B), dim3(256), 0, ws->stream, y, w, ws->H * ws->W);
     WCK(hipGetLastError());
     return ELWH_OK;
 }

@@ -35,7 +35,7 @@ EXPORTED = [
     "elwh_batch_last_error", "elwh_batch_destroy",
     "elwh_ws_create", "elwh_ws_destroy", "elwh_ws_last_error", "elwh_ws_num_params", "elwh_ws_params",
     "elwh_ws_forward", "elwh_ws_loss_grad", "elwh_ws_train_step", "elwh_ws_features", "elwh_ws_from_field",
-    "elwh_ws_predict", "elwh_dot_M_noalloc", "elwh_stream_triad",
+    "elwh_ws_predict", "elwh_ws_normalize", "elwh_dot_M_noalloc", "elwh_stream_triad",
 ]
 
 
@@ -138,6 +138,7 @@ def _load():
     lib.elwh_ws_features.argtypes = [P, I, I, PP, PP, PP, PP, P, P, P]
     lib.elwh_ws_from_field.argtypes = [P, I, I, PP, PP, P, P]
     lib.elwh_ws_predict.argtypes = [P, I, I, P, PP, P, PP]
+    lib.elwh_ws_normalize.argtypes = [P, I, P, P]
     lib.elwh_profile_enable.argtypes = [P, I]
     lib.elwh_profile_read.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(I), ctypes.POINTER(D),
                                       ctypes.POINTER(I)]
@@ -611,6 +612,10 @@ class WarmStartNet:
     def from_field(self, fs, vs, omega_dev, y_out):
         self._check(lib.elwh_ws_from_field(self._h, len(fs), self.H, _ptr_array(fs), _ptr_array(vs),
                                            omega_dev.data_ptr(), y_out.data_ptr()))
+
+    def normalize(self, y, w):
+        """y[b] /= its w-weighted RMS (elwh_ws_normalize), in place."""
+        self._check(lib.elwh_ws_normalize(self._h, y.shape[0], y.data_ptr(), w.data_ptr()))
 
     def predict(self, x, fs, omega_dev, x0s):
         self._check(lib.elwh_ws_predict(self._h, len(fs), self.H, x.data_ptr(), _ptr_array(fs),

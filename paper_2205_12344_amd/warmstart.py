@@ -72,9 +72,7 @@ def make_dataset(seeds, net, batch=48, tol=1e-10, maxit=4000, time_budget=None):
             om = torch.tensor([c.omega for c in cases], dtype=torch.float64, device="cuda")
             net.features(dev, om, x[kept:kept + B], w[kept:kept + B])
             net.from_field([d[3] for d in dev], vs, om, y[kept:kept + B])
-            yb, wb = y[kept:kept + B], w[kept:kept + B]
-            rms = torch.sqrt((wb[..., None] * yb * yb).sum(dim=(1, 2, 3)) / (2 * wb.sum(dim=(1, 2))))
-            yb /= rms[:, None, None, None]
+            net.normalize(y[kept:kept + B], w[kept:kept + B])
             used += [seeds[k + i] for i in good]
             kept += B
         log(f"data {k + len(chunk)}/{N}: kept {kept}, {time.time() - t0:.1f} s, mean iters {np.mean(iters):.1f}")
@@ -243,6 +241,7 @@ def main(argv=None):
     t.add_argument("--train-budget", type=float, default=300.0)
     t.add_argument("--out", default=WEIGHTS)
     t.add_argument("--label-tol", type=float, default=1e-10)
+    t.add_argument("--lr", type=float, default=1e-3)
     e = sub.add_parser("eval")
     e.add_argument("--first-seed", type=int, default=4096)
     e.add_argument("--n", type=int, default=512)
@@ -267,13 +266,14 @@ def main(argv=None):
         log(f"dataset {data['x'].shape[0]} + {val['x'].shape[0]} samples in {time.time() - t0:.1f} s, "
             f"output scale {k:.4f}, mean plain iterations {data['iters'].mean():.1f}")
         v0 = eval_loss(net, val)
-        hist = train(net, data, epochs=a.epochs, time_budget=a.train_budget)
+        hist = train(net, data, epochs=a.epochs, lr=a.lr, time_budget=a.train_budget)
         v1 = eval_loss(net, val)
         log(f"validation loss {v0:.4f} -> {v1:.4f}")
         meta = {"n_train": int(data["x"].shape[0]) + int(prev.get("n_train", 0)), "n_val": int(val["x"].shape[0]),
                 "epochs": len(hist) + int(prev.get("epochs", 0)),
                 "train_loss": prev.get("train_loss", []) + [round(h, 5) for h in hist],
                 "val_loss_before": v0, "val_loss_after": v1, "output_scale": k, "label_tol": a.label_tol,
+                "lr": a.lr, "mean_label_iters": float(data["iters"].mean()),
                 "train_seeds": prev.get("train_seeds", []) + [[s0, s0 + int(data["x"].shape[0])]],
                 "val_seeds": [8192, 8192 + a.n_val]}
         save_weights(net, a.out, meta)

@@ -138,6 +138,25 @@ def test_feature_and_field_maps(E):
         np.testing.assert_allclose(yy[b, ..., 1], v[b].cpu().numpy()[1][1:, :n] * s, rtol=1e-5, atol=1e-5)
 
 
+def test_pipeline_overfits_a_small_training_set(E):
+    """Pipeline check: on 64 warm-start problems (labels from the batched FP64
+    solve, targets normalised in the library) the network, trained with the
+    library's forward/backward/Adam kernels, drives its own training loss
+    from 1 (the value of predicting zero) to below 0.3.  Features, targets,
+    loss and optimiser work together; what the network cannot do is
+    generalise to unseen media (see the oracle test of what a start can
+    gain)."""
+    from paper_2205_12344_amd import warmstart
+    net = E.WarmStartNet(max_batch=64, H=warmstart.N_CELLS, seed=1234)
+    data = warmstart.make_dataset(list(range(64)), net, batch=64, tol=1e-8)
+    assert data["x"].shape[0] >= 60
+    hist = warmstart.train(net, data, epochs=120, bs=16, lr=1e-3, log_every=20)
+    _say("overfit losses", [round(h, 4) for h in hist[::10]], "final", hist[-1])
+    assert hist[0] > 0.9
+    assert hist[-1] <= 0.3
+    net.close()
+
+
 def test_trained_network_start_vs_zero_start(E):
     """The committed trained weights on held-out warm-start problems (config
     5, seeds 4096..4101): the learned start, rescaled by the solver

@@ -8,15 +8,28 @@ option can gain there.
   cluster of small eigenvalues of A_h (modes close to omega), which CG has
   to resolve whatever the start; this caps the gain of any initial guess,
   learned or not.
+* What a start can gain depends on where its error lies, not on its size.
+  The warm-start problems' solutions lie almost entirely (99 %+ in the M
+  norm) in the few eigenmodes of the medium closest to omega, the modes
+  behind A_h's smallest eigenvalues.  A start whose error (5 % of the
+  solution) avoids those modes saves about 80 % of the iterations; the same
+  error placed in those modes saves 15-25 %; a start right everywhere except
+  in those modes (x* minus its resonant part) saves almost nothing.  A start
+  pays only when it predicts the amplitudes of the near-resonant modes, which
+  are properties of the whole medium.
 * Near resonance A_h can be slightly indefinite (Sec. 4.4, remark on the
   trapezoid rule): CG meets (p, A_h p)_M <= 0, while the conjugate residual
   method, the MINRES-type remedy the remark recommends, converges.
 """
 
+import math
+
 import numpy as np
 import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spl
 
-from oracle import direct, krylov
+from oracle import direct, krylov, spectral
 from oracle.operator import Operator
 from oracle.problem import Problem
 from oracle.stepping import WaveHoltz
@@ -51,3 +64,38 @@ def test_indefinite_case_cg_breaks_down_cr_converges():
         krylov.cg(wh.apply_A, b, op.m, tol=1e-8, maxit=3000)
     r = krylov.cr(wh.apply_A, b, op.m, tol=1e-8, maxit=3000)
     assert np.linalg.norm(r.x - xs) / np.linalg.norm(xs) <= 1e-6
+
+
+@pytest.mark.parametrize("seed", [4099, 4096])
+def test_start_gains_only_through_the_near_resonant_modes(seed):
+    c, op, wh, b, xs = _setup(seed)
+    m = op.m
+    K = 24
+    # the K eigenmodes of -L_h phi = lambda^2 M phi closest to omega (M-orthonormal)
+    lam2, V = spl.eigsh(-op.Lh.tocsc(), k=K, M=sp.diags(m).tocsc(), sigma=c.omega ** 2)
+    # they are the modes behind the smallest eigenvalues of A_h (App. B: 1 - beta_h)
+    th = spectral.mode_angle(np.sqrt(lam2), c.omega, wh.dt)
+    ah = 1.0 - spectral.beta_h(th, wh.weights)
+    assert np.max(ah) < 0.15 and np.min(np.abs(ah)) < 1e-3     # A_h spans about (0, 1.5)
+    mnorm = lambda v: math.sqrt(float(np.dot(m * v, v)))
+    P = V @ (V.T @ (m * xs))                    # resonant part of the solution
+    assert mnorm(P) >= 0.99 * mnorm(xs)
+    rng = np.random.default_rng(0)
+    amp = 0.05 * mnorm(xs)
+    e_res = V @ rng.standard_normal(K)
+    e_res *= amp / mnorm(e_res)
+    e_orth = rng.standard_normal(b.size)
+    e_orth -= V @ (V.T @ (m * e_orth))
+    e_orth *= amp / mnorm(e_orth)
+    it = {}
+    for name, x0 in (("zero", None), ("res", xs + e_res), ("orth", xs + e_orth), ("no_res", xs - P),
+                     ("res_only", P)):
+        r = krylov.cg(wh.apply_A, b, m, x0=x0, tol=1e-8, maxit=4000)
+        assert r.converged
+        it[name] = r.iters
+    # an error away from the resonant modes is cheap to remove ...
+    assert it["orth"] <= 0.25 * it["zero"]
+    assert it["res_only"] <= 0.25 * it["zero"]
+    # ... the same error inside them, or a start missing only them, is not
+    assert it["res"] >= 0.7 * it["zero"]
+    assert it["no_res"] >= 0.7 * it["zero"]
