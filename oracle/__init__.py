@@ -20,6 +20,8 @@ Modules
   spectral  continuous and trapezoid filter transfer functions (Sec. 3, App. B)
   curvilinear  the stress divergence on a mapped 2-D grid (Sec. 4.1; the
             annular sectors of Sec. 5.5), same interface as operator
+  curvilinear3d  the same on a mapped 3-D grid (Sec. 4.1; the partial
+            toroidal shell of Sec. 5.11)
   twofield  the two-field (displacement, velocity) filter for impedance faces
             (the remark of Sec. 3), damped corrected leapfrog, GMRES
 
@@ -29,4 +31,4 @@ defers the exact boundary stencils to another publication) and its absolute
 values are "parity unpinned" beyond the invariants listed there.
 """
 
-from . import problem, operator, stepping, krylov, direct, spectral, curvilinear, twofield  # noqa: F401
+from . import problem, operator, stepping, krylov, direct, spectral, curvilinear, curvilinear3d, twofield  # noqa: F401

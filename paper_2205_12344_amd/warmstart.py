@@ -251,7 +251,7 @@ def main(argv=None):
     e.add_argument("--fp32-batches", type=int, default=None)
     a = ap.parse_args(argv)
     torch.cuda.set_device(0)
-    net = elwh.WarmStartNet(max_batch=96, H=N_CELLS, seed=1234)
+    net = elwh.WarmStartNet(max_batch=max(96, a.batch), H=N_CELLS, seed=1234)
     if a.cmd == "train":
         t0 = time.time()
         s0 = a.first_seed
