@@ -102,8 +102,11 @@ typedef struct {
     int max_outer;     /* FP32 path: maximum residual replacements (default 50) */
     void* stream;      /* hipStream_t the context works on; NULL = the null stream */
     int autotune;      /* 1 (default): pick the step-kernel tiling by timing at create */
-    int fuse;          /* 2-D: time steps per step-kernel launch, 1 to 4 (default
-                          2); 3-D always steps singly */
+    int fuse;          /* time steps per step-kernel launch: 2-D Cartesian 1 to 4,
+                          3-D Cartesian 1 or 2 (larger values act as 2, and
+                          the tiling may still choose single steps); default
+                          2; mapped grids and the two-field step always step
+                          singly */
     int scale_x0;      /* CG paths: 1 = replace a given x0 by alpha x0 with
                           alpha = (x0, b)_M / (x0, A_h x0)_M, the factor that
                           minimises the A_h-norm error along x0 (0 when
@@ -205,6 +208,39 @@ elwh_status elwh_create_mapped(const elwh_grid* grid, const double* x, const dou
                                const double* rho, const double* lam, const double* mu,
                                double omega, const int bc[4], const elwh_opts* opts,
                                elwh_ctx** out);
+
+/*
+ * Mapped (curvilinear) 3-D grids (Sec. 4.1 in three dimensions; the partial
+ * toroidal shell of Sec. 5.11).  The domain is the image of the unit cube
+ * under a smooth one-to-one map (q, r, s) -> (x, y, z); x, y, z hold the
+ * physical coordinates of the (n[0]+1) x (n[1]+1) x (n[2]+1) nodes of the
+ * uniform (q, r, s) grid in the node layout (q fastest; grid->dim must be 3,
+ * grid->len is ignored: h_a = 1/n[a]).  With G_a = J grad a (G_q = x_r x x_s,
+ * G_r = x_s x x_q, G_s = x_q x x_r from second-order differences of the node
+ * coordinates, one-sided over three nodes on the faces of the cube) and the
+ * 3x3 blocks K^ab = (1/J) [lam G_a G_b^T + mu (G_a . G_b) I + mu G_b G_a^T],
+ * L_h is minus the gradient of the discrete energy
+ *   1/2 sum_a sum_{a-edges} w_e (D+a U)^T Kbar^aa (D+a U)
+ *   + sum_{a < b} sum_{unknown nodes} w_n (Dh_a U)^T K^ab (Dh_b U)
+ * (Kbar the two-node mean, Dh central or one-sided into the domain on a free
+ * face, w = 1/2 on a free face); mass rho J, forcing J f, so the solution
+ * satisfies omega^2 rho v + div T(v) = f discretely.  bc: the six faces
+ * (-q, +q, -r, +r, -s, +s); the q and r faces must be Dirichlet, each s face
+ * Dirichlet or traction-free (the free radial surfaces of the shell).  The
+ * filter, A_h, the solvers, K periods, FP32 stepping and elwh_dot_M (M = w
+ * rho J) work unchanged; one time step per launch, one thread per node.
+ * x, y, z, rho, lam, mu are DEVICE pointers, copied.  Errors: ELWH_ERR_ARG
+ * (also for a folded or left-handed map: J <= 0 at some node),
+ * ELWH_ERR_ALLOC, ELWH_ERR_HIP; on error *out is NULL.
+ * elwh_plan_mapped3 is the host-only plan (HOST pointers): G is the
+ * Gershgorin bound of (w rho J)^-1 L_h over the unknown rows.
+ */
+elwh_status elwh_create_mapped3(const elwh_grid* grid, const double* x, const double* y, const double* z,
+                                const double* rho, const double* lam, const double* mu, double omega, const int bc[6],
+                                const elwh_opts* opts, elwh_ctx** out);
+elwh_status elwh_plan_mapped3(const elwh_grid* grid, const double* x, const double* y, const double* z,
+                              const double* rho, const double* lam, const double* mu, double omega, const int bc[6],
+                              const elwh_opts* opts, elwh_info* info);
 
 /* elwh_plan for a mapped grid: HOST pointers, no GPU use; G is the
  * Gershgorin bound of (rho J)^-1 L_h over the interior rows.  Errors as
@@ -412,8 +448,12 @@ elwh_status elwh_profile_read(elwh_ctx* ctx, double* step_ms, int* nstep, double
  * Tiling of the fused step kernel for precision prec (ELWH_FP64 or
  * ELWH_FP32_STEP): 2-D: vec nodes per lane along x (1 or 2, FP32 also 4)
  * and rows (4, 8, 16) marched per wavefront; 3-D: vec = y rows per
- * workgroup, one wavefront each (1, 2, 4, 8), and rows = z planes marched
- * per wavefront (4, 8, 16, 32).  The tiling changes speed only, never results.
+ * workgroup, one wavefront each, and rows = z planes marched per wavefront:
+ * (1, 2, 4, 8) x (4, 8, 16, 32) for single-step launches (opts.fuse = 1),
+ * (2, 4, 6) x (8, 16, 32) for two-step launches (fuse >= 2; the workgroup
+ * adds two halo rows), where vec = 1 with rows 4 to 32 makes every step a
+ * single-step launch (the FP64 choice on large cubes).  The tiling changes
+ * speed only, never results.
  * elwh_autotune times every supported tiling on reps operator applications
  * (HIP events), in three round-robin passes, and keeps the tiling with the
  * fastest pass (contexts with impedance faces time the two-field step);

@@ -37,7 +37,8 @@ Parity: pinned by the reduction to the Cartesian 3-D operator for a scaled
 identity map, exact rotation equivariance, symmetry and semi-definiteness,
 translations in the kernel of the full Hessian, second-order convergence of
 the interior truncation error against the continuous stress divergence on a
-section of the torus, and the exact WaveHoltz fixed point (Sec. 4.3).  The
+section of the torus (node coordinates from inputs.torus_section), and the
+exact WaveHoltz fixed point (Sec. 4.3).  The
 paper's own closure is another publication's and prints no values for these
 grids (only CR iteration counts, Sec. 5.11), so absolute values are
 otherwise "parity unpinned".
@@ -144,22 +145,3 @@ class MappedOperator3D:
         """max over unknown rows of sum_j |(rho^-1 Ltilde)_ij|."""
         rows = np.asarray(abs(self.Lt).sum(axis=1)).ravel() / self.rho_dof
         return float(rows.max())
-
-
-def torus_section(nq, nr, ns, R=4.0, r_in=1.0, r_out=2.0, theta=np.pi, phi=np.pi, phi0=0.0):
-    """Node coordinates of a partial toroidal shell (Sec. 5.11):
-        x = (R + r cos th) cos ph,  y = (R + r cos th) sin ph,  z = r sin th,
-    with q -> ph in [phi0, phi0 + phi], r -> th in [0, theta], s -> r in
-    [r_in, r_out] (the printed y uses cos ph, a typo: the map would fold).
-    The orientation (q, r, s) = (ph, th, r) is right-handed for this map."""
-    q = np.linspace(0.0, 1.0, nq + 1)
-    rr = np.linspace(0.0, 1.0, nr + 1)
-    s = np.linspace(0.0, 1.0, ns + 1)
-    S, Rr, Q = np.meshgrid(s, rr, q, indexing="ij")
-    ph = phi0 + phi * Q
-    th = theta * Rr
-    rad = r_in + (r_out - r_in) * S
-    x = (R + rad * np.cos(th)) * np.cos(ph)
-    y = (R + rad * np.cos(th)) * np.sin(ph)
-    z = rad * np.sin(th)
-    return x, y, z

@@ -14,7 +14,7 @@ import time
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libelwh.so")
-SOURCES = ["api.hip", "batch.hip", "batch_kernels.hip", "kernels2d.hip", "kernels2d_multi.hip", "kernels2d_curv.hip", "kernels2d_damped.hip", "kernels3d.hip", "blas.hip", "nn.hip", "nn_kernels.hip",
+SOURCES = ["api.hip", "batch.hip", "batch_kernels.hip", "kernels2d.hip", "kernels2d_multi.hip", "kernels2d_curv.hip", "kernels2d_damped.hip", "kernels3d.hip", "kernels3d_k2.hip", "kernels3d_curv.hip", "blas.hip", "nn.hip", "nn_kernels.hip",
            "noalloc.hip", "plan.cpp"]
 ARCH = "gfx950"
 

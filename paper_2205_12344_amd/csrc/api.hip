@@ -50,7 +50,9 @@ void prof_mark(elwh_ctx* c, int phase, int nsteps) {
 }
 
 void run_filter(elwh_ctx* c, const double* x, bool with_force, bool amode, bool fp32, double* out) {
-    if (c->mapped)
+    if (c->mapped && c->L.dim == 3)
+        run_filter_curv3d(c, x, with_force, amode, fp32, out);
+    else if (c->mapped)
         run_filter_curv2d(c, x, with_force, amode, fp32, out);
     else if (c->L.dim == 2)
         run_filter_2d(c, x, with_force, amode, fp32, out);
@@ -649,7 +651,7 @@ elwh_status ctx_solve_fallback(elwh_ctx* c, int method, double tol, int maxit, i
 namespace {
 // Create a context; xc/yc non-null: a mapped 2-D grid with these node
 // coordinates (host copies are taken here, like the materials).
-elwh_status create_impl(const elwh_grid* grid_in, const double* xc, const double* yc, const double* rho,
+elwh_status create_impl(const elwh_grid* grid_in, const double* xc, const double* yc, const double* zc, const double* rho,
                         const double* lam, const double* mu, double omega, const int* bc_in, const elwh_opts* opts,
                         elwh_ctx** out) {
     if (!out) return ELWH_ERR_ARG;
@@ -666,13 +668,15 @@ elwh_status create_impl(const elwh_grid* grid_in, const double* xc, const double
     elwh_grid gbuf = *grid_in;
     int bc[6] = {ELWH_BC_DIRICHLET, ELWH_BC_DIRICHLET, ELWH_BC_DIRICHLET,
                  ELWH_BC_DIRICHLET, ELWH_BC_DIRICHLET, ELWH_BC_DIRICHLET};
-    for (int f = 0; f < (mapped ? 4 : 2 * (gbuf.dim == 3 ? 3 : 2)); ++f) bc[f] = bc_in[f];
+    const bool mapped3 = mapped && zc != nullptr;
+    for (int f = 0; f < (mapped && !mapped3 ? 4 : 2 * (gbuf.dim == 3 ? 3 : 2)); ++f) bc[f] = bc_in[f];
     if (mapped) {
-        if (gbuf.dim != 2) {
-            g_create_err = "mapped grids are two-dimensional";
+        if (gbuf.dim != (mapped3 ? 3 : 2)) {
+            g_create_err = mapped3 ? "3-D mapped grids need dim = 3" : "mapped grids of elwh_create_mapped are two-dimensional";
             return ELWH_ERR_ARG;
         }
-        gbuf.len[0] = gbuf.len[1] = 1.0;   // the reference square: h_q = 1/n_q, h_r = 1/n_r
+        // the reference square or cube: h_a = 1/n_a
+        gbuf.len[0] = gbuf.len[1] = gbuf.len[2] = 1.0;
     }
     // impedance faces: traction-type faces of the energy plus boundary damping
     int imp[2] = {0, 0}, ximp[2] = {0, 0};
@@ -741,8 +745,19 @@ elwh_status create_impl(const elwh_grid* grid_in, const double* xc, const double
             c->err = "copying the node coordinates failed (device pointers expected)";
             return fail(ELWH_ERR_HIP);
         }
-        st = make_plan_mapped(grid, hx.data(), hy.data(), hr.data(), hl.data(), hm.data(), omega, c->bc, &o,
-                              &c->plan, &met, &c->err);
+        if (mapped3) {
+            std::vector<double> hz(nn);
+            if (hipMemcpyAsync(hz.data(), zc, nn * sizeof(double), hipMemcpyDefault, c->stream) != hipSuccess ||
+                hipStreamSynchronize(c->stream) != hipSuccess) {
+                c->err = "copying the node coordinates failed (device pointers expected)";
+                return fail(ELWH_ERR_HIP);
+            }
+            st = make_plan_mapped3(grid, hx.data(), hy.data(), hz.data(), hr.data(), hl.data(), hm.data(), omega,
+                                   c->bc, &o, &c->plan, &met, &c->err);
+        } else {
+            st = make_plan_mapped(grid, hx.data(), hy.data(), hr.data(), hl.data(), hm.data(), omega, c->bc, &o,
+                                  &c->plan, &met, &c->err);
+        }
     } else {
         st = make_plan(grid, hr.data(), hl.data(), hm.data(), omega, c->bc, &o, &c->plan, &c->err, x_free_ok);
     }
@@ -773,17 +788,20 @@ elwh_status create_impl(const elwh_grid* grid_in, const double* xc, const double
         return fail(st);
     for (auto& v : c->vec)
         if ((st = alloc_t(c, &v, FE))) return fail(st);
-    if (L.dim == 2 && ((st = alloc_t(c, &c->s64[2], FE)) || (st = alloc_t(c, &c->s64[3], FE)))) return fail(st);
+    // four state levels where a launch takes two or more steps (2-D; 3-D Cartesian with fuse >= 2)
+    const bool four = L.dim == 2 || (!mapped && o.fuse >= 2);
+    if (four && ((st = alloc_t(c, &c->s64[2], FE)) || (st = alloc_t(c, &c->s64[3], FE)))) return fail(st);
     if (o.prec == ELWH_FP32_STEP) {
         if ((st = alloc_t(c, &c->fa, CS)) || (st = alloc_t(c, &c->fl, CS)) || (st = alloc_t(c, &c->fm, CS)) ||
             (st = alloc_t(c, &c->s32[0], FE)) || (st = alloc_t(c, &c->s32[1], FE)) ||
             (st = alloc_t(c, &c->f32, FE)))
             return fail(st);
-        if (L.dim == 2 && ((st = alloc_t(c, &c->s32[2], FE)) || (st = alloc_t(c, &c->s32[3], FE))))
+        if (four && ((st = alloc_t(c, &c->s32[2], FE)) || (st = alloc_t(c, &c->s32[3], FE))))
             return fail(st);
     }
+    const int nmetric = mapped3 ? 9 : 4;
     if (mapped) {
-        for (int k = 0; k < 4; ++k)
+        for (int k = 0; k < nmetric; ++k)
             if ((st = alloc_t(c, &c->cg[k], CS)) ||
                 (o.prec == ELWH_FP32_STEP && (st = alloc_t(c, &c->fg[k], CS))))
                 return fail(st);
@@ -801,9 +819,9 @@ elwh_status create_impl(const elwh_grid* grid_in, const double* xc, const double
     // coefficient arrays in the padded layout, built on the host in FP64
     {
         std::vector<double> ha(CS, 0.0), hlam(CS, 0.0), hmu(CS, 0.0), hmw(CS, 0.0);
-        std::vector<double> hg[4], hj;
+        std::vector<double> hg[9], hj;
         if (mapped) {
-            for (auto& v : hg) v.assign(CS, 0.0);
+            for (int k = 0; k < nmetric; ++k) hg[k].assign(CS, 0.0);
             hj.assign(CS, 0.0);
         }
         const double cdt2 = c->plan.c * c->plan.dt * c->plan.dt;
@@ -818,7 +836,7 @@ elwh_status create_impl(const elwh_grid* grid_in, const double* xc, const double
                     hlam[dst] = hl[src] / jw;
                     hmu[dst] = hm[src] / jw;
                     if (mapped) {
-                        for (int k = 0; k < 4; ++k) hg[k][dst] = met.g[k][src];
+                        for (int k = 0; k < nmetric; ++k) hg[k][dst] = met.g[k][src];
                         hj[dst] = jw;
                     }
                     bool unknown = true;
@@ -844,14 +862,14 @@ elwh_status create_impl(const elwh_grid* grid_in, const double* xc, const double
         }
         if (mapped) {
             bool ok = hipMemcpyAsync(c->jac, hj.data(), CS * 8, hipMemcpyHostToDevice, c->stream) == hipSuccess;
-            for (int k = 0; k < 4 && ok; ++k)
+            for (int k = 0; k < nmetric && ok; ++k)
                 ok = hipMemcpyAsync(c->cg[k], hg[k].data(), CS * 8, hipMemcpyHostToDevice, c->stream) == hipSuccess;
             if (!ok) {
                 c->err = "uploading the metric failed";
                 return fail(ELWH_ERR_HIP);
             }
             if (o.prec == ELWH_FP32_STEP)
-                for (int k = 0; k < 4; ++k) launch_convert_f32(L, c->cg[k], c->fg[k], 1, c->stream);
+                for (int k = 0; k < nmetric; ++k) launch_convert_f32(L, c->cg[k], c->fg[k], 1, c->stream);
         }
         if (o.prec == ELWH_FP32_STEP) {
             launch_convert_f32(L, c->ca, c->fa, 1, c->stream);
@@ -905,7 +923,10 @@ elwh_status create_impl(const elwh_grid* grid_in, const double* xc, const double
         }
     }
     // default tiling, then (optionally) the timed choice
-    if (mapped) {
+    if (mapped3) {
+        c->tile64 = Tile{1, 4};
+        c->tile32 = Tile{1, 4};
+    } else if (mapped) {
         c->tile64 = Tile{1, 8};
         c->tile32 = Tile{2, 8};
     } else if (imp[0] || imp[1] || ximp[0] || ximp[1]) {
@@ -914,6 +935,9 @@ elwh_status create_impl(const elwh_grid* grid_in, const double* xc, const double
     } else if (c->L.dim == 2) {
         c->tile64 = Tile{2, 8};
         c->tile32 = Tile{4, 8};
+    } else if (o.fuse >= 2) {
+        c->tile64 = Tile{6, 32};   // two-step launches: RB rows (plus two halo rows), TZ planes
+        c->tile32 = Tile{6, 32};
     } else {
         c->tile64 = Tile{1, 16};
         c->tile32 = Tile{1, 16};
@@ -978,7 +1002,7 @@ elwh_status elwh_plan(const elwh_grid* grid, const double* rho, const double* la
 
 elwh_status elwh_create(const elwh_grid* grid, const double* rho, const double* lam, const double* mu,
                         double omega, const int bc[6], const elwh_opts* opts, elwh_ctx** out) {
-    return create_impl(grid, nullptr, nullptr, rho, lam, mu, omega, bc, opts, out);
+    return create_impl(grid, nullptr, nullptr, nullptr, rho, lam, mu, omega, bc, opts, out);
 }
 
 elwh_status elwh_create_mapped(const elwh_grid* grid, const double* x, const double* y, const double* rho,
@@ -989,11 +1013,45 @@ elwh_status elwh_create_mapped(const elwh_grid* grid, const double* x, const dou
         g_create_err = "null coordinate array";
         return ELWH_ERR_ARG;
     }
-    return create_impl(grid, x, y, rho, lam, mu, omega, bc, opts, out);
+    return create_impl(grid, x, y, nullptr, rho, lam, mu, omega, bc, opts, out);
 }
 
 elwh_status elwh_filter_diagnostics(int nt, int periods, double omega, int scheme, elwh_filter_diag* out) {
     return filter_diagnostics(nt, periods, omega, scheme, out, &g_create_err);
+}
+
+elwh_status elwh_create_mapped3(const elwh_grid* grid, const double* x, const double* y, const double* z,
+                                const double* rho, const double* lam, const double* mu, double omega, const int bc[6],
+                                const elwh_opts* opts, elwh_ctx** out) {
+    if (!x || !y || !z) {
+        if (out) *out = nullptr;
+        g_create_err = "null coordinate array";
+        return ELWH_ERR_ARG;
+    }
+    return create_impl(grid, x, y, z, rho, lam, mu, omega, bc, opts, out);
+}
+
+elwh_status elwh_plan_mapped3(const elwh_grid* grid, const double* x, const double* y, const double* z,
+                              const double* rho, const double* lam, const double* mu, double omega, const int bc[6],
+                              const elwh_opts* opts, elwh_info* info) {
+    elwh_opts o;
+    elwh_default_opts(&o);
+    if (opts) o = *opts;
+    if (!bc) {
+        g_create_err = "null bc";
+        return ELWH_ERR_ARG;
+    }
+    Plan p;
+    elwh_status st = make_plan_mapped3(grid, x, y, z, rho, lam, mu, omega, bc, &o, &p, nullptr, &g_create_err);
+    if (st != ELWH_OK) return st;
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->nt = p.nt;
+        info->dt = p.dt;
+        info->c = p.c;
+        info->lambda_bound = p.lambda_bound;
+    }
+    return ELWH_OK;
 }
 
 elwh_status elwh_plan_mapped(const elwh_grid* grid, const double* x, const double* y, const double* rho,
@@ -1448,8 +1506,10 @@ elwh_status elwh_profile_read(elwh_ctx* c, double* step_ms, int* nstep, double* 
 elwh_status elwh_set_tile(elwh_ctx* c, int prec, int vec, int rows) {
     if (!c) return ELWH_ERR_ARG;
     const bool fp32 = prec == ELWH_FP32_STEP;
-    const bool ok = c->mapped ? tile_valid_curv(fp32, vec, rows)
-                              : (c->L.dim == 2 ? tile_valid_2d(fp32, vec, rows) : tile_valid_3d(fp32, vec, rows));
+    const bool ok = c->mapped ? (c->L.dim == 3 ? tile_valid_curv3(fp32, vec, rows) : tile_valid_curv(fp32, vec, rows))
+                              : (c->L.dim == 2 ? tile_valid_2d(fp32, vec, rows)
+                                               : (c->opts.fuse >= 2 ? tile_valid_3d_k2(fp32, vec, rows)
+                                                                    : tile_valid_3d(fp32, vec, rows)));
     if (!ok) {
         c->err = "unsupported tile";
         return ELWH_ERR_ARG;
@@ -1528,7 +1588,7 @@ elwh_status elwh_autotune(elwh_ctx* c, int prec, int reps, double* best_step_us)
     }
     // a context with impedance faces runs the two-field step kernel: tune that
     const bool twofield = !fp32 && (c->imp[0] || c->imp[1] || c->ximp[0] || c->ximp[1]);
-    const int steps = c->L.dim == 2 && !c->mapped && !twofield ? c->opts.fuse : 1;
+    const int steps = !c->mapped && !twofield ? (c->L.dim == 2 ? c->opts.fuse : std::min(c->opts.fuse, 2)) : 1;
     const int comp = (fp32 && c->opts.compensated ? 1 : 0) | ((steps - 1) << 1) | (c->mapped ? 8 : 0) |
                      (twofield ? 16 : 0);
     const TuneKey key(c->L.dim, fp32 ? 1 : 0, comp, c->L.nx, c->L.ny, c->L.nz);
@@ -1556,6 +1616,8 @@ elwh_status elwh_autotune(elwh_ctx* c, int prec, int reps, double* best_step_us)
         for (int V : {1, 2})
             for (int TY : {4, 8, 16})
                 if (tile_valid_damped(V, TY)) cands.push_back(Tile{V, TY});
+    } else if (c->mapped && c->L.dim == 3) {
+        cands.push_back(Tile{1, 4});   // one tiling: a thread per node
     } else if (c->mapped) {
         for (int V : {1, 2})
             for (int TY : {8, 16})
@@ -1564,6 +1626,11 @@ elwh_status elwh_autotune(elwh_ctx* c, int prec, int reps, double* best_step_us)
         for (int V : {1, 2, 4})
             for (int TY : {4, 8, 16})
                 if (tile_valid_2d(fp32, V, TY)) cands.push_back(Tile{V, TY});
+    } else if (steps >= 2) {
+        // two-step tilings, and single steps (RB 1) where they are faster
+        for (int RB : {2, 4, 6})
+            for (int TZ : {8, 16, 32}) cands.push_back(Tile{RB, TZ});
+        for (int TZ : {16, 32}) cands.push_back(Tile{1, TZ});
     } else {
         for (int RB : {1, 2, 4})
             for (int TZ : {8, 16, 32}) cands.push_back(Tile{RB, TZ});

@@ -142,8 +142,9 @@ struct elwh_ctx {
     // metric arrays cg = (J grad q, J grad r) (FP32 copies fg), and J itself
     // (the forcing enters as J f)
     bool mapped = false;
-    double* cg[4] = {nullptr, nullptr, nullptr, nullptr};
-    float* fg[4] = {nullptr, nullptr, nullptr, nullptr};
+    // (3-D mapped grids: nine metric arrays, G_q, G_r, G_s by component)
+    double* cg[9] = {};
+    float* fg[9] = {};
     double* jac = nullptr;
 
     // FP64 state buffers (2 time levels), accumulator and its compensation
@@ -206,10 +207,17 @@ namespace elwh {
 // Metric terms of a mapped 2-D grid (Sec. 4.1) in the caller's node layout:
 // J = x_q y_r - x_r y_q and g = (J grad q, J grad r) = (y_r, -x_r, -y_q, x_q),
 // from second-order differences of the node coordinates.
+// 3-D: J = x_q . (x_r x x_s) and G_q = x_r x x_s, G_r = x_s x x_q,
+// G_s = x_q x x_r (g[3a + i] = component i of G_a).
 struct MappedMetric {
-    std::vector<double> J, g[4];
+    std::vector<double> J, g[9];
 };
 elwh_status mapped_metric(int nq, int nr, const double* x, const double* y, MappedMetric* m, std::string* err);
+elwh_status mapped_metric3(int nq, int nr, int ns, const double* x, const double* y, const double* z,
+                           MappedMetric* m, std::string* err);
+elwh_status make_plan_mapped3(const elwh_grid* g, const double* x, const double* y, const double* z,
+                              const double* rho, const double* lam, const double* mu, double omega, const int bc[6],
+                              const elwh_opts* o, Plan* out, MappedMetric* met, std::string* err);
 elwh_status make_plan_mapped(const elwh_grid* g, const double* x, const double* y, const double* rho,
                              const double* lam, const double* mu, double omega, const int bc[6], const elwh_opts* o,
                              Plan* out, MappedMetric* met, std::string* err);
@@ -238,9 +246,21 @@ elwh_status ctx_solve_fallback(elwh_ctx* c, int method, double tol, int maxit, i
 // The message elwh_last_error(NULL) returns (calls without a context).
 void set_create_error(const std::string& msg);
 bool tile_valid_3d(bool fp32, int V, int TZ);
+// Two-step 3-D launches (kernels3d_k2.hip): RB y rows per workgroup plus two
+// halo rows, TZ planes; reads u^n (u), u^{n-1} (uprev), writes u^{n+1} (outA)
+// and u^{n+2} (outB), four distinct buffers.
+bool tile_valid_3d_k2(bool fp32, int RB, int TZ);
+struct Args3D;
+template <typename T>
+void launch_step3d_k2(int RB, int TZ, bool force, bool comp, hipStream_t s, const T* u, const T* uprev, T* outA,
+                      T* outB, double* acc, double* acclo, const T* ca, const T* cl, const T* cm, const T* f,
+                      const Args3D& A);
 bool tile_valid_curv(bool fp32, int V, int TY);
+bool tile_valid_curv3(bool fp32, int V, int TY);
 // One filter application on a mapped 2-D grid (kernels2d_curv.hip).
 void run_filter_curv2d(elwh_ctx* c, const double* x, bool with_force, bool amode, bool fp32, double* out);
+// One filter application on a mapped 3-D grid (kernels3d_curv.hip).
+void run_filter_curv3d(elwh_ctx* c, const double* x, bool with_force, bool amode, bool fp32, double* out);
 // Two-field step of the impedance path (kernels2d_damped.hip).  mode 1 (start):
 // u = u^0, uprev = the second field, base0/base1 the A_h bases or null;
 // mode 0: u = u^n, uprev = u^{n-1} (unext may alias it), acc0/acc1 updated.

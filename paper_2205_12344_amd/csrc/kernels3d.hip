@@ -21,18 +21,10 @@
 // across workgroups).
 #include "elwh_internal.h"
 #include "lanes.h"
+#include "step3d_common.h"
 #include "xcd.h"
 
 namespace elwh {
-
-struct Args3D {
-    int nx, ny, nz;
-    int64_t P, PS, CS;
-    int klo, khi, free_lo, free_hi;
-    double cxx2, cyy2, czz2, cxy, cxz, cyz, czzf, cfxz, cfyz;
-    double w, w0, fc;
-    int final_;
-};
 
 template <typename T>
 struct Plane {
@@ -47,18 +39,6 @@ struct Centre3 {
     double h[3], l[3];
     T f[3];
 };
-
-__device__ __forceinline__ void acc_add3(double& hi, double& lo, double x, bool comp) {
-    if (comp) {
-        const double t = hi + x;
-        const double z = t - hi;
-        const double e = (hi - (t - z)) + (x - z);
-        hi = t;
-        lo += e;
-    } else {
-        hi += x;
-    }
-}
 
 template <typename T, typename U, int TZ, int RB, int MODE, bool FORCE, bool COMP>
 __global__ __launch_bounds__(64 * RB) void step3d_kernel(const U* __restrict__ u, const T* uprev, T* unext,
@@ -83,9 +63,6 @@ __global__ __launch_bounds__(64 * RB) void step3d_kernel(const U* __restrict__ u
     const int k1 = min(k0 + TZ - 1, A.khi);
     const int64_t P = A.P, PS = A.PS, CS = A.CS;
     const T two = (T)2;
-    const T cxx2 = (T)A.cxx2, cyy2 = (T)A.cyy2, czz2 = (T)A.czz2;
-    const T cxy = (T)A.cxy, cxz = (T)A.cxz, cyz = (T)A.cyz;
-    const T czzf = (T)A.czzf, cfxz = (T)A.cfxz, cfyz = (T)A.cfyz;
 
     auto load_plane = [&](int k, Plane<T>& q) {
         if (colv && k >= 0 && k <= A.nz) {
@@ -146,70 +123,33 @@ __global__ __launch_bounds__(64 * RB) void step3d_kernel(const U* __restrict__ u
             load_ctr(k + 1, ctrN);
         }
         const int64_t o = (int64_t)k * PS + (int64_t)j * P + i;
-        const T lam_m = ctr.lam_m, lam_p = ctr.lam_p, mu_m = ctr.mu_m, mu_p = ctr.mu_p;
-        // x neighbours by lane moves (all lanes take part)
-        const T lamL = lane_from_left(C.lam), lamR = lane_from_right(C.lam);
-        const T muL = lane_from_left(C.mu), muR = lane_from_right(C.mu);
-        const T uL = lane_from_left(C.u[1]), uR = lane_from_right(C.u[1]);
-        const T vL = lane_from_left(C.v[1]), vR = lane_from_right(C.v[1]);
-        const T wL = lane_from_left(C.w[1]), wR = lane_from_right(C.w[1]);
-        const T u_mL = lane_from_left(C.u[0]), u_mR = lane_from_right(C.u[0]);
-        const T u_pL = lane_from_left(C.u[2]), u_pR = lane_from_right(C.u[2]);
-        const T v_mL = lane_from_left(C.v[0]), v_mR = lane_from_right(C.v[0]);
-        const T v_pL = lane_from_left(C.v[2]), v_pR = lane_from_right(C.v[2]);
-        const T u_DL = lane_from_left(D.u[1]), u_DR = lane_from_right(D.u[1]);
-        const T u_UL = lane_from_left(Up.u[1]), u_UR = lane_from_right(Up.u[1]);
-        const T w_DL = lane_from_left(D.w[1]), w_DR = lane_from_right(D.w[1]);
-        const T w_UL = lane_from_left(Up.w[1]), w_UR = lane_from_right(Up.w[1]);
-
-        const T uc = C.u[1], vc = C.v[1], wc = C.w[1];
-        const T lc = C.lam, mc = C.mu;
-        const T AL = lamL + two * muL, AC = lc + two * mc, AR = lamR + two * muR;
-        const T Am = lam_m + two * mu_m, Ap = lam_p + two * mu_p;
-
-        // in-plane compact and xy mixed terms (all plane kinds)
-        T Lu = cxx2 * ((AR + AC) * (uR - uc) - (AC + AL) * (uc - uL)) +
-               cyy2 * ((mu_p + mc) * (C.u[2] - uc) - (mc + mu_m) * (uc - C.u[0])) +
-               cxy * (lamR * (v_pR - v_mR) - lamL * (v_pL - v_mL) + mu_p * (v_pR - v_pL) - mu_m * (v_mR - v_mL));
-        T Lv = cxx2 * ((muR + mc) * (vR - vc) - (mc + muL) * (vc - vL)) +
-               cyy2 * ((Ap + AC) * (C.v[2] - vc) - (AC + Am) * (vc - C.v[0])) +
-               cxy * (muR * (u_pR - u_mR) - muL * (u_pL - u_mL) + lam_p * (u_pR - u_pL) - lam_m * (u_mR - u_mL));
-        T Lw = cxx2 * ((muR + mc) * (wR - wc) - (mc + muL) * (wc - wL)) +
-               cyy2 * ((mu_p + mc) * (C.w[2] - wc) - (mc + mu_m) * (wc - C.w[0]));
-
-        if (A.free_hi && k == A.nz) {
-            const T lD = D.lam, mD = D.mu, AD = lD + two * mD;
-            Lu += -czzf * (mc + mD) * (uc - D.u[1]) - cfxz * (mc * (wR - wL) + mD * (w_DR - w_DL)) +
-                  cfxz * (lamR * (wR - w_DR) - lamL * (wL - w_DL));
-            Lv += -czzf * (mc + mD) * (vc - D.v[1]) - cfyz * (mc * (C.w[2] - C.w[0]) + mD * (D.w[2] - D.w[0])) +
-                  cfyz * (lam_p * (C.w[2] - D.w[2]) - lam_m * (C.w[0] - D.w[0]));
-            Lw += -czzf * (AC + AD) * (wc - D.w[1]) - cfxz * (lc * (uR - uL) + lD * (u_DR - u_DL)) +
-                  cfxz * (muR * (uR - u_DR) - muL * (uL - u_DL)) -
-                  cfyz * (lc * (C.v[2] - C.v[0]) + lD * (D.v[2] - D.v[0])) +
-                  cfyz * (mu_p * (C.v[2] - D.v[2]) - mu_m * (C.v[0] - D.v[0]));
-        } else if (A.free_lo && k == 0) {
-            const T lU = Up.lam, mU = Up.mu, AU = lU + two * mU;
-            Lu += czzf * (mc + mU) * (Up.u[1] - uc) + cfxz * (mc * (wR - wL) + mU * (w_UR - w_UL)) +
-                  cfxz * (lamR * (w_UR - wR) - lamL * (w_UL - wL));
-            Lv += czzf * (mc + mU) * (Up.v[1] - vc) + cfyz * (mc * (C.w[2] - C.w[0]) + mU * (Up.w[2] - Up.w[0])) +
-                  cfyz * (lam_p * (Up.w[2] - C.w[2]) - lam_m * (Up.w[0] - C.w[0]));
-            Lw += czzf * (AC + AU) * (Up.w[1] - wc) + cfxz * (lc * (uR - uL) + lU * (u_UR - u_UL)) +
-                  cfxz * (muR * (u_UR - uR) - muL * (u_UL - uL)) +
-                  cfyz * (lc * (C.v[2] - C.v[0]) + lU * (Up.v[2] - Up.v[0])) +
-                  cfyz * (mu_p * (Up.v[2] - C.v[2]) - mu_m * (Up.v[0] - C.v[0]));
-        } else {
-            const T lD = D.lam, mD = D.mu, lU = Up.lam, mU = Up.mu;
-            const T AD = lD + two * mD, AU = lU + two * mU;
-            Lu += czz2 * ((mU + mc) * (Up.u[1] - uc) - (mc + mD) * (uc - D.u[1])) +
-                  cxz * (lamR * (w_UR - w_DR) - lamL * (w_UL - w_DL) + mU * (w_UR - w_UL) - mD * (w_DR - w_DL));
-            Lv += czz2 * ((mU + mc) * (Up.v[1] - vc) - (mc + mD) * (vc - D.v[1])) +
-                  cyz * (lam_p * (Up.w[2] - D.w[2]) - lam_m * (Up.w[0] - D.w[0]) + mU * (Up.w[2] - Up.w[0]) -
-                         mD * (D.w[2] - D.w[0]));
-            Lw += czz2 * ((AU + AC) * (Up.w[1] - wc) - (AC + AD) * (wc - D.w[1])) +
-                  cxz * (muR * (u_UR - u_DR) - muL * (u_UL - u_DL) + lU * (u_UR - u_UL) - lD * (u_DR - u_DL)) +
-                  cyz * (mu_p * (Up.v[2] - D.v[2]) - mu_m * (Up.v[0] - D.v[0]) + lU * (Up.v[2] - Up.v[0]) -
-                         lD * (D.v[2] - D.v[0]));
-        }
+        // the footprint: x neighbours by lane moves (all lanes take part)
+        Nb3<T> nb;
+        nb.uc = C.u[1]; nb.vc = C.v[1]; nb.wc = C.w[1];
+        nb.uL = lane_from_left(C.u[1]); nb.uR = lane_from_right(C.u[1]);
+        nb.vL = lane_from_left(C.v[1]); nb.vR = lane_from_right(C.v[1]);
+        nb.wL = lane_from_left(C.w[1]); nb.wR = lane_from_right(C.w[1]);
+        nb.u0 = C.u[0]; nb.u2 = C.u[2]; nb.v0 = C.v[0]; nb.v2 = C.v[2]; nb.w0 = C.w[0]; nb.w2 = C.w[2];
+        nb.u_mL = lane_from_left(C.u[0]); nb.u_mR = lane_from_right(C.u[0]);
+        nb.u_pL = lane_from_left(C.u[2]); nb.u_pR = lane_from_right(C.u[2]);
+        nb.v_mL = lane_from_left(C.v[0]); nb.v_mR = lane_from_right(C.v[0]);
+        nb.v_pL = lane_from_left(C.v[2]); nb.v_pR = lane_from_right(C.v[2]);
+        nb.Du = D.u[1]; nb.Dv = D.v[1]; nb.Dw = D.w[1];
+        nb.Dv0 = D.v[0]; nb.Dv2 = D.v[2]; nb.Dw0 = D.w[0]; nb.Dw2 = D.w[2];
+        nb.u_DL = lane_from_left(D.u[1]); nb.u_DR = lane_from_right(D.u[1]);
+        nb.w_DL = lane_from_left(D.w[1]); nb.w_DR = lane_from_right(D.w[1]);
+        nb.Uu = Up.u[1]; nb.Uv = Up.v[1]; nb.Uw = Up.w[1];
+        nb.Uv0 = Up.v[0]; nb.Uv2 = Up.v[2]; nb.Uw0 = Up.w[0]; nb.Uw2 = Up.w[2];
+        nb.u_UL = lane_from_left(Up.u[1]); nb.u_UR = lane_from_right(Up.u[1]);
+        nb.w_UL = lane_from_left(Up.w[1]); nb.w_UR = lane_from_right(Up.w[1]);
+        nb.lc = C.lam; nb.mc = C.mu;
+        nb.lamL = lane_from_left(C.lam); nb.lamR = lane_from_right(C.lam);
+        nb.muL = lane_from_left(C.mu); nb.muR = lane_from_right(C.mu);
+        nb.lam_m = ctr.lam_m; nb.lam_p = ctr.lam_p; nb.mu_m = ctr.mu_m; nb.mu_p = ctr.mu_p;
+        nb.lD = D.lam; nb.mD = D.mu; nb.lU = Up.lam; nb.mU = Up.mu;
+        T Lu, Lv, Lw;
+        stencil3d(nb, k, A, Lu, Lv, Lw);
+        const T uc = nb.uc, vc = nb.vc, wc = nb.wc;
 
         if (store) {
             const T a = ctr.a;
@@ -303,6 +243,60 @@ static void launch3_z(int RB, int TZ, bool force, bool comp, const Args3D& A, hi
                                  f, A);
 }
 
+// The two state buffers of bufs[0..3] that are neither a nor b.
+template <typename T>
+static void free_pair3(T* const* bufs, const void* a, const void* b, T** x, T** y) {
+    T* got[2] = {nullptr, nullptr};
+    int k = 0;
+    for (int i = 0; i < 4 && k < 2; ++i)
+        if (bufs[i] != a && bufs[i] != b) got[k++] = bufs[i];
+    *x = got[0];
+    *y = got[1];
+}
+
+// Steps 1 .. nsteps-1 after the half step: two-step launches while two or
+// more steps remain (fuse >= 2), then single steps.  prev/cur hold u^0/u^1 on
+// entry; prev may be the caller's vector (never written).  With fuse = 1 the
+// single steps alternate between two buffers as before.
+template <typename T>
+static void run_steps_3d(elwh_ctx* c, Args3D A, int RB1, int TZ, bool k2, int RB2, bool with_force, bool comp,
+                         double sgn, const T* prev, T* cur, T* const* bufs, double* acc, double* lo, const T* ca,
+                         const T* cl, const T* cm, const T* f, int nsteps) {
+    hipStream_t s = c->stream;
+    int n = 1;
+    if (k2) {
+        while (nsteps - n >= 2) {
+            T *x1, *x2;
+            free_pair3(bufs, prev, cur, &x1, &x2);
+            A.w = sgn * c->w[n + 1];
+            A.fc = c->cosn[n];
+            A.w1 = sgn * c->w[n + 2];
+            A.fc1 = c->cosn[n + 1];
+            A.final_ = (n + 2 == nsteps);
+            launch_step3d_k2<T>(RB2, TZ, with_force, comp, s, cur, prev, x1, x2, acc, lo, ca, cl, cm, f, A);
+            prev = x1;
+            cur = x2;
+            n += 2;
+        }
+    }
+    for (; n < nsteps; ++n) {
+        // u^{n+1} overwrites u^{n-1} when that is one of the state buffers
+        T* nxt = nullptr;
+        for (int i = 0; i < 4; ++i)
+            if (bufs[i] && bufs[i] == prev) nxt = bufs[i];
+        if (!nxt) {
+            T* dummy;
+            free_pair3(bufs, prev, cur, &nxt, &dummy);
+        }
+        A.w = sgn * c->w[n + 1];
+        A.fc = c->cosn[n];
+        A.final_ = (n == nsteps - 1);
+        launch3_z<T, T, 0>(RB1, TZ, with_force, comp, A, s, cur, prev, nxt, nullptr, nullptr, acc, lo, ca, cl, cm, f);
+        prev = cur;
+        cur = nxt;
+    }
+}
+
 void run_filter_3d(elwh_ctx* c, const double* x, bool with_force, bool amode, bool fp32, double* out) {
     hipStream_t s = c->stream;
     Args3D A;
@@ -325,9 +319,15 @@ void run_filter_3d(elwh_ctx* c, const double* x, bool with_force, bool amode, bo
     A.czzf = c->st.czzf;
     A.cfxz = c->st.cfxz;
     A.cfyz = c->st.cfyz;
+    A.w1 = A.fc1 = 0.0;
     A.final_ = 0;
-    const int TZ = fp32 ? c->tile32.TY : c->tile64.TY;
-    const int RB = fp32 ? c->tile32.V : c->tile64.V;
+    const Tile tk = fp32 ? c->tile32 : c->tile64;
+    // with fuse >= 2 the tile holds the two-step tiling (RB 2, 4, 6), or RB 1
+    // for single steps throughout; the half step and a single remaining step
+    // take a single-step tiling of the same TZ
+    const bool k2 = c->opts.fuse >= 2 && tk.V >= 2;
+    const int TZ = tk.TY;
+    const int RB1 = k2 ? (tile_valid_3d(fp32, tk.V, TZ) ? tk.V : 2) : tk.V;
     const int nsteps = c->plan.nt * c->opts.periods;
     const double sgn = amode ? -1.0 : 1.0;
     const bool comp = fp32 && c->opts.compensated;
@@ -337,40 +337,21 @@ void run_filter_3d(elwh_ctx* c, const double* x, bool with_force, bool amode, bo
     A.w = sgn * c->w[1];
     A.fc = c->cosn[0];
     if (!fp32) {
-        double *b0 = c->s64[0], *b1 = c->s64[1];
+        double* b1 = c->s64[1];
         prof_mark(c, 0);
-        launch3_z<double, double, 1>(RB, TZ, with_force, false, A, s, x, nullptr, b1, amode ? x : nullptr, nullptr, acc,
-                                     lo, c->ca, c->cl, c->cm, c->f64);
+        launch3_z<double, double, 1>(RB1, TZ, with_force, false, A, s, x, nullptr, b1, amode ? x : nullptr, nullptr,
+                                     acc, lo, c->ca, c->cl, c->cm, c->f64);
         prof_mark(c, 1);
-        const double* prev = x;
-        double* cur = b1;
-        for (int n = 1; n < nsteps; ++n) {
-            double* nxt = (n == 1) ? b0 : const_cast<double*>(prev);
-            A.w = sgn * c->w[n + 1];
-            A.fc = c->cosn[n];
-            launch3_z<double, double, 0>(RB, TZ, with_force, false, A, s, cur, prev, nxt, nullptr, nullptr, acc, lo,
-                                         c->ca, c->cl, c->cm, c->f64);
-            prev = cur;
-            cur = nxt;
-        }
+        run_steps_3d<double>(c, A, RB1, TZ, k2, tk.V, with_force, false, sgn, x, b1, c->s64, acc, lo, c->ca, c->cl,
+                             c->cm, c->f64, nsteps);
     } else {
         float *b0 = c->s32[0], *b1 = c->s32[1];
         prof_mark(c, 0);
-        launch3_z<float, double, 1>(RB, TZ, with_force, comp, A, s, x, nullptr, b1, amode ? x : nullptr, b0, acc, lo,
-                                    c->fa, c->fl, c->fm, c->f32);
+        launch3_z<float, double, 1>(RB1, TZ, with_force, comp, A, s, x, nullptr, b1, amode ? x : nullptr, b0, acc,
+                                    lo, c->fa, c->fl, c->fm, c->f32);
         prof_mark(c, 1);
-        float* prev = b0;
-        float* cur = b1;
-        for (int n = 1; n < nsteps; ++n) {
-            A.w = sgn * c->w[n + 1];
-            A.fc = c->cosn[n];
-            A.final_ = (n == nsteps - 1);
-            launch3_z<float, float, 0>(RB, TZ, with_force, comp, A, s, cur, prev, prev, nullptr, nullptr, acc, lo,
-                                       c->fa, c->fl, c->fm, c->f32);
-            float* t = prev;
-            prev = cur;
-            cur = t;
-        }
+        run_steps_3d<float>(c, A, RB1, TZ, k2, tk.V, with_force, comp, sgn, b0, b1, c->s32, acc, lo, c->fa, c->fl,
+                            c->fm, c->f32, nsteps);
     }
     prof_mark(c, 2, nsteps - 1);
 }

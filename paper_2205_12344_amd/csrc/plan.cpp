@@ -565,6 +565,221 @@ elwh_status make_plan_mapped(const elwh_grid* g, const double* x, const double* 
     return plan_from_bound(G, omega, o, out, err);
 }
 
+// ---- mapped 3-D grids ---------------------------------------------------------
+
+namespace {
+
+// K^{ab} at node o, row-major 3x3: (lam/J) G_a G_b^T + (mu/J) (G_b G_a^T + (G_a . G_b) I).
+void block3(const MappedMetric& m, const double* lam, const double* mu, int64_t o, int a, int b, double K[9]) {
+    const double l = lam[o] / m.J[o], u = mu[o] / m.J[o];
+    double ga[3], gb[3];
+    for (int i = 0; i < 3; ++i) {
+        ga[i] = m.g[3 * a + i][o];
+        gb[i] = m.g[3 * b + i][o];
+    }
+    const double dot = ga[0] * gb[0] + ga[1] * gb[1] + ga[2] * gb[2];
+    for (int i = 0; i < 3; ++i)
+        for (int k = 0; k < 3; ++k) K[3 * i + k] = l * ga[i] * gb[k] + u * gb[i] * ga[k] + (i == k ? u * dot : 0.0);
+}
+
+// Entries of the node difference Dh along one axis at index t (0..N):
+// central inside, one-sided into the domain on a free face, none on a
+// Dirichlet face.  Returns the count; off[] are index offsets.
+int dcoef(int t, int N, double h, bool free_lo, bool free_hi, int off[2], double cf[2]) {
+    if (t >= 1 && t <= N - 1) {
+        off[0] = 1; cf[0] = 0.5 / h;
+        off[1] = -1; cf[1] = -0.5 / h;
+        return 2;
+    }
+    if (t == 0 && free_lo) {
+        off[0] = 1; cf[0] = 1.0 / h;
+        off[1] = 0; cf[1] = -1.0 / h;
+        return 2;
+    }
+    if (t == N && free_hi) {
+        off[0] = 0; cf[0] = 1.0 / h;
+        off[1] = -1; cf[1] = -1.0 / h;
+        return 2;
+    }
+    return 0;
+}
+
+// Gershgorin row sums of (w_p rho J)^-1 L_h on a mapped 3-D grid, L_h = -grad
+// of the energy E_h (edge terms with the mean K^aa of their two nodes,
+// weight 1/2 for edges in a free s face; node terms w_n (Dh_a U)^T K^ab
+// (Dh_b U) over ordered pairs a != b at unknown nodes): the 3x3 coefficient
+// block of every neighbour of each unknown row, summed before taking
+// absolute values, over unknown columns only.
+double gershgorin_mapped3(int nq, int nr, int ns, const MappedMetric& m, const double* rho, const double* lam,
+                          const double* mu, bool free_lo, bool free_hi) {
+    const int N[3] = {nq, nr, ns};
+    const double h[3] = {1.0 / nq, 1.0 / nr, 1.0 / ns};
+    const int64_t st[3] = {1, (int64_t)nq + 1, (int64_t)(nq + 1) * (nr + 1)};
+    const int klo = free_lo ? 0 : 1, khi = free_hi ? ns : ns - 1;
+    auto unknown = [&](const int t[3]) {
+        if (t[0] <= 0 || t[0] >= nq || t[1] <= 0 || t[1] >= nr) return false;
+        return t[2] >= klo && t[2] <= khi;
+    };
+    auto wnode = [&](int k) { return ((k == 0 && free_lo) || (k == ns && free_hi)) ? 0.5 : 1.0; };
+    unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    nth = std::min<unsigned>(nth, (unsigned)std::max(1, khi - klo + 1));
+    std::vector<double> part(nth, 0.0);
+    auto work = [&](unsigned th) {
+        double best = 0.0;
+        double C[27][9];
+        for (int k = klo + (int)th; k <= khi; k += (int)nth)
+            for (int j = 1; j <= nr - 1; ++j)
+                for (int i = 1; i <= nq - 1; ++i) {
+                    const int tp[3] = {i, j, k};
+                    const int64_t p = k * st[2] + j * st[1] + i;
+                    std::memset(C, 0, sizeof(C));
+                    auto cell = [](const int d[3]) { return (d[2] + 1) * 9 + (d[1] + 1) * 3 + (d[0] + 1); };
+                    double K0[9], K1[9];
+                    // edge terms
+                    for (int a = 0; a < 3; ++a) {
+                        block3(m, lam, mu, p, a, a, K0);
+                        for (int sg = -1; sg <= 1; sg += 2) {
+                            const int t = tp[a] + sg;
+                            if (t < 0 || t > N[a]) continue;
+                            block3(m, lam, mu, p + sg * st[a], a, a, K1);
+                            const double we = (a < 2 && ((k == 0 && free_lo) || (k == ns && free_hi))) ? 0.5 : 1.0;
+                            int d[3] = {0, 0, 0};
+                            d[a] = sg;
+                            const double f = we * 0.5 / (h[a] * h[a]);
+                            for (int e = 0; e < 9; ++e) {
+                                C[cell(d)][e] += f * (K0[e] + K1[e]);
+                                C[13][e] -= f * (K0[e] + K1[e]);
+                            }
+                        }
+                    }
+                    // node terms: -sum_n (Dh_a)_{n,p} w_n K^ab_n (Dh_b U)_n
+                    for (int a = 0; a < 3; ++a)
+                        for (int b = 0; b < 3; ++b) {
+                            if (a == b) continue;
+                            for (int da = -1; da <= 1; ++da) {
+                                int tn[3] = {i, j, k};
+                                tn[a] += da;
+                                if (!unknown(tn)) continue;
+                                int oa[2], ob[2];
+                                double ca[2], cb[2];
+                                const int na = dcoef(tn[a], N[a], h[a], a == 2 && free_lo, a == 2 && free_hi, oa, ca);
+                                double cpa = 0.0;
+                                for (int q = 0; q < na; ++q)
+                                    if (tn[a] + oa[q] == tp[a]) cpa += ca[q];
+                                if (cpa == 0.0) continue;
+                                const int64_t n = p + da * st[a];
+                                const double wn = wnode(tn[2]);
+                                double K[9];
+                                block3(m, lam, mu, n, a, b, K);
+                                const int nb = dcoef(tn[b], N[b], h[b], b == 2 && free_lo, b == 2 && free_hi, ob, cb);
+                                for (int q = 0; q < nb; ++q) {
+                                    int d[3] = {tn[0] - i, tn[1] - j, tn[2] - k};
+                                    d[b] += ob[q];
+                                    const double f = cpa * cb[q] * wn;
+                                    for (int e = 0; e < 9; ++e) C[cell(d)][e] -= f * K[e];
+                                }
+                            }
+                        }
+                    const double scale = 1.0 / (rho[p] * m.J[p] * wnode(k));
+                    for (int c = 0; c < 3; ++c) {
+                        double row = 0.0;
+                        for (int dz = -1; dz <= 1; ++dz)
+                            for (int dy = -1; dy <= 1; ++dy)
+                                for (int dx = -1; dx <= 1; ++dx) {
+                                    const int tm[3] = {i + dx, j + dy, k + dz};
+                                    if (!unknown(tm)) continue;
+                                    const int d[3] = {dx, dy, dz};
+                                    for (int e = 0; e < 3; ++e) row += std::fabs(C[cell(d)][3 * c + e]);
+                                }
+                        best = std::max(best, row * scale);
+                    }
+                }
+        part[th] = best;
+    };
+    std::vector<std::thread> thr;
+    for (unsigned t = 1; t < nth; ++t) thr.emplace_back(work, t);
+    work(0);
+    for (auto& x : thr) x.join();
+    return *std::max_element(part.begin(), part.end());
+}
+
+}  // namespace
+
+elwh_status mapped_metric3(int nq, int nr, int ns, const double* x, const double* y, const double* z,
+                           MappedMetric* m, std::string* err) {
+    const int64_t sy = nq + 1, sz = sy * (nr + 1), nn = sz * (ns + 1);
+    for (int64_t i = 0; i < nn; ++i)
+        if (!std::isfinite(x[i]) || !std::isfinite(y[i]) || !std::isfinite(z[i])) {
+            *err = "node coordinates must be finite";
+            return ELWH_ERR_ARG;
+        }
+    const double hq = 1.0 / nq, hr = 1.0 / nr, hs = 1.0 / ns;
+    m->J.assign(nn, 0.0);
+    for (auto& g : m->g) g.assign(nn, 0.0);
+    const double* X[3] = {x, y, z};
+    for (int k = 0; k <= ns; ++k)
+        for (int j = 0; j <= nr; ++j)
+            for (int i = 0; i <= nq; ++i) {
+                const int64_t o = k * sz + j * sy + i;
+                double dq[3], dr[3], ds[3];
+                for (int c = 0; c < 3; ++c) {
+                    dq[c] = diff1(X[c], o, 1, i, nq, hq);
+                    dr[c] = diff1(X[c], o, sy, j, nr, hr);
+                    ds[c] = diff1(X[c], o, sz, k, ns, hs);
+                }
+                auto cross = [](const double* a, const double* b, double* out) {
+                    out[0] = a[1] * b[2] - a[2] * b[1];
+                    out[1] = a[2] * b[0] - a[0] * b[2];
+                    out[2] = a[0] * b[1] - a[1] * b[0];
+                };
+                double Gq[3], Gr[3], Gs[3];
+                cross(dr, ds, Gq);
+                cross(ds, dq, Gr);
+                cross(dq, dr, Gs);
+                const double J = dq[0] * Gq[0] + dq[1] * Gq[1] + dq[2] * Gq[2];
+                if (!(J > 0)) {
+                    *err = "the map must be one-to-one and orientation preserving (J > 0 at every node)";
+                    return ELWH_ERR_ARG;
+                }
+                m->J[o] = J;
+                for (int c = 0; c < 3; ++c) {
+                    m->g[c][o] = Gq[c];
+                    m->g[3 + c][o] = Gr[c];
+                    m->g[6 + c][o] = Gs[c];
+                }
+            }
+    return ELWH_OK;
+}
+
+elwh_status make_plan_mapped3(const elwh_grid* g, const double* x, const double* y, const double* z,
+                              const double* rho, const double* lam, const double* mu, double omega, const int bc[6],
+                              const elwh_opts* o, Plan* out, MappedMetric* met, std::string* err) {
+    if (!g || !bc) { *err = "null grid or bc"; return ELWH_ERR_ARG; }
+    if (g->dim != 3) { *err = "3-D mapped grids need dim = 3"; return ELWH_ERR_ARG; }
+    for (int f = 0; f < 4; ++f)
+        if (bc[f] != ELWH_BC_DIRICHLET) {
+            *err = "3-D mapped grids need Dirichlet q and r faces (traction-free is supported on the s faces)";
+            return ELWH_ERR_ARG;
+        }
+    elwh_grid unit = *g;
+    unit.len[0] = unit.len[1] = unit.len[2] = 1.0;
+    elwh_status st = check_config(&unit, bc, o, err);
+    if (st != ELWH_OK) return st;
+    if (!x || !y || !z || !rho || !lam || !mu) { *err = "null coordinate or material array"; return ELWH_ERR_ARG; }
+    if (!(omega > 0) || !std::isfinite(omega)) { *err = "omega must be positive and finite"; return ELWH_ERR_ARG; }
+    const int nq = g->n[0], nr = g->n[1], ns = g->n[2];
+    if (!positive_materials((int64_t)(nq + 1) * (nr + 1) * (ns + 1), rho, lam, mu)) {
+        *err = "materials must be positive and finite";
+        return ELWH_ERR_ARG;
+    }
+    MappedMetric local;
+    MappedMetric* m = met ? met : &local;
+    if ((st = mapped_metric3(nq, nr, ns, x, y, z, m, err)) != ELWH_OK) return st;
+    const double G = gershgorin_mapped3(nq, nr, ns, *m, rho, lam, mu, bc[4] == ELWH_BC_TRACTION_FREE,
+                                        bc[5] == ELWH_BC_TRACTION_FREE);
+    return plan_from_bound(G, omega, o, out, err);
+}
+
 elwh_status check_config(const elwh_grid* g, const int bc[6], const elwh_opts* o, std::string* err,
                          bool x_free_ok) {
     if (!g || !bc) { *err = "null grid or bc"; return ELWH_ERR_ARG; }

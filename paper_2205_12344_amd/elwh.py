@@ -26,6 +26,7 @@ FALLBACK_NONE, FALLBACK_CR, FALLBACK_MINRES = 0, 1, 2
 
 EXPORTED = [
     "elwh_default_opts", "elwh_plan", "elwh_create", "elwh_plan_mapped", "elwh_create_mapped",
+    "elwh_plan_mapped3", "elwh_create_mapped3",
     "elwh_filter_diagnostics", "elwh_destroy", "elwh_query", "elwh_last_error",
     "elwh_apply_filter", "elwh_apply_A", "elwh_solve", "elwh_cg_begin", "elwh_cg_iterate",
     "elwh_apply_filter2", "elwh_apply_A2", "elwh_solve2",
@@ -90,6 +91,10 @@ def _load():
                                        ctypes.POINTER(Opts), ctypes.POINTER(P)]
     lib.elwh_plan_mapped.argtypes = [ctypes.POINTER(Grid), P, P, P, P, P, D, ctypes.POINTER(I),
                                      ctypes.POINTER(Opts), ctypes.POINTER(Info)]
+    lib.elwh_create_mapped3.argtypes = [ctypes.POINTER(Grid), P, P, P, P, P, P, D, ctypes.POINTER(I),
+                                        ctypes.POINTER(Opts), ctypes.POINTER(P)]
+    lib.elwh_plan_mapped3.argtypes = [ctypes.POINTER(Grid), P, P, P, P, P, P, D, ctypes.POINTER(I),
+                                      ctypes.POINTER(Opts), ctypes.POINTER(Info)]
     lib.elwh_filter_diagnostics.argtypes = [I, I, D, I, ctypes.POINTER(FilterDiag)]
     lib.elwh_destroy.argtypes = [P]
     lib.elwh_destroy.restype = None
@@ -457,6 +462,56 @@ class MappedContext(Context):
             raise ElwhError(st, lib.elwh_last_error(None).decode())
         self._h = h
         self.opts = o
+
+
+class MappedContext3(Context):
+    """One problem on a mapped 3-D grid (wraps elwh_create_mapped3): x, y, z
+    are the node coordinates, shape (n_s + 1, n_r + 1, n_q + 1), q along the
+    last axis; bc = (-q, +q, -r, +r, -s, +s) faces, q and r faces Dirichlet,
+    s faces Dirichlet (0) or traction-free (1).  Every Context method applies."""
+
+    def __init__(self, x, y, z, rho, lam, mu, omega, bc=(0,) * 6, stream=None, **opts):
+        if not torch.cuda.is_available():
+            raise RuntimeError("libelwh needs a GPU")
+        xs, ys, zs = _dev(x, "x"), _dev(y, "y"), _dev(z, "z")
+        if xs.dim() != 3 or tuple(ys.shape) != tuple(xs.shape) or tuple(zs.shape) != tuple(xs.shape):
+            raise ValueError("x, y and z must be node arrays of one 3-D shape")
+        ns, nr, nq = (k - 1 for k in xs.shape)
+        self.dim = 3
+        self.n = (nq, nr, ns)
+        self.node_shape = tuple(xs.shape)
+        self.field_shape = (3,) + self.node_shape
+        self.stream = torch.cuda.current_stream() if stream is None else stream
+        g = make_grid(3, (nq, nr, ns))
+        o = default_opts(stream=self.stream.cuda_stream, **opts)
+        r, l, m = _dev(rho, "rho"), _dev(lam, "lam"), _dev(mu, "mu")
+        for t in (r, l, m):
+            if tuple(t.shape) != self.node_shape:
+                raise ValueError(f"material shape {tuple(t.shape)} != {self.node_shape}")
+        h = ctypes.c_void_p()
+        st = lib.elwh_create_mapped3(ctypes.byref(g), xs.data_ptr(), ys.data_ptr(), zs.data_ptr(), r.data_ptr(),
+                                     l.data_ptr(), m.data_ptr(), float(omega), _bc_array(bc), ctypes.byref(o),
+                                     ctypes.byref(h))
+        if st != OK:
+            raise ElwhError(st, lib.elwh_last_error(None).decode())
+        self._h = h
+        self.opts = o
+
+
+def plan_mapped3(x, y, z, rho, lam, mu, omega, bc=(0,) * 6, **opts):
+    """Time-step plan of a mapped 3-D grid on the host (no GPU)."""
+    xs, ys, zs = _host(x), _host(y), _host(z)
+    ns, nr, nq = (k - 1 for k in xs.shape)
+    g = make_grid(3, (nq, nr, ns))
+    r, l, m = _host(rho), _host(lam), _host(mu)
+    o = default_opts(**opts)
+    info = Info()
+    st = lib.elwh_plan_mapped3(ctypes.byref(g), xs.ctypes.data, ys.ctypes.data, zs.ctypes.data, r.ctypes.data,
+                               l.ctypes.data, m.ctypes.data, float(omega), _bc_array(bc), ctypes.byref(o),
+                               ctypes.byref(info))
+    if st != OK:
+        raise ElwhError(st, lib.elwh_last_error(None).decode())
+    return {"nt": info.nt, "dt": info.dt, "c": info.c, "lambda_bound": info.lambda_bound}
 
 
 def context_from_case(case, **opts):

@@ -354,3 +354,24 @@ def ring_grid(nq, nr, r_in=1.0, r_out=2.0, angle=math.pi):
     rad = r_in + (r_out - r_in) * R
     th = angle * (1.0 - Q)
     return rad * np.cos(th), rad * np.sin(th)
+
+
+def torus_section(nq, nr, ns, R=4.0, r_in=1.0, r_out=2.0, theta=math.pi, phi=math.pi, phi0=0.0):
+    """Node coordinates of a partial toroidal shell (the 3-D curvilinear
+    experiment, Sec. 5.11):
+        x = (R + r cos th) cos ph,  y = (R + r cos th) sin ph,  z = r sin th,
+    with q -> ph in [phi0, phi0 + phi], r -> th in [0, theta], s -> r in
+    [r_in, r_out] (the printed y uses cos ph, a typo: that map would fold).
+    The orientation (q, r, s) = (ph, th, r) is right-handed.  Arrays of shape
+    (ns + 1, nr + 1, nq + 1), q along the last axis."""
+    q = np.linspace(0.0, 1.0, nq + 1)
+    rr = np.linspace(0.0, 1.0, nr + 1)
+    s = np.linspace(0.0, 1.0, ns + 1)
+    S, Rr, Q = np.meshgrid(s, rr, q, indexing="ij")
+    ph = phi0 + phi * Q
+    th = theta * Rr
+    rad = r_in + (r_out - r_in) * S
+    x = (R + rad * np.cos(th)) * np.cos(ph)
+    y = (R + rad * np.cos(th)) * np.sin(ph)
+    z = rad * np.sin(th)
+    return x, y, z

@@ -369,3 +369,32 @@ def test_plan_property_random_grids(elwh):
         assert p["nt"] == steps_per_period(G, omega)
 
     check()
+
+
+@pytest.mark.parametrize("bc", [(0,) * 6, (0, 0, 0, 0, 1, 1), (0, 0, 0, 0, 0, 1)])
+def test_plan_mapped3_matches_oracle(elwh, bc):
+    """Host plan of a mapped 3-D grid (a torus section with random media):
+    Gershgorin bound and N_T equal the oracle's, which sums the rows of the
+    assembled energy Hessian."""
+    from oracle.curvilinear3d import MappedOperator3D
+    from paper_2205_12344_amd.inputs import torus_section
+    from oracle.stepping import steps_per_period
+    x, y, z = torus_section(9, 7, 5, theta=1.7, phi=1.3)
+    rng = np.random.default_rng(8)
+    rho = np.exp(0.2 * rng.standard_normal(x.shape))
+    mu = np.exp(0.2 * rng.standard_normal(x.shape))
+    lam = 2.0 * mu * np.exp(0.2 * rng.standard_normal(x.shape))
+    op = MappedOperator3D(x, y, z, rho, lam, mu, bc=bc)
+    p = elwh.plan_mapped3(x, y, z, rho, lam, mu, 3.3, bc=bc)
+    assert p["lambda_bound"] == pytest.approx(op.gershgorin(), rel=1e-12)
+    assert p["nt"] == steps_per_period(op.gershgorin(), 3.3)
+
+
+def test_plan_mapped3_rejects_bad_input(elwh):
+    from paper_2205_12344_amd.inputs import torus_section
+    x, y, z = torus_section(6, 5, 4)
+    one = np.ones(x.shape)
+    with pytest.raises(elwh.ElwhError):          # free q face
+        elwh.plan_mapped3(x, y, z, one, one, one, 1.0, bc=(1, 0, 0, 0, 0, 0))
+    with pytest.raises(elwh.ElwhError):          # left-handed map
+        elwh.plan_mapped3(x[:, :, ::-1], y[:, :, ::-1], z[:, :, ::-1], one, one, one, 1.0)

@@ -1,0 +1,193 @@
+"""GPU parity on mapped 3-D grids (Sec. 4.1 in three dimensions; the partial
+toroidal shell of Sec. 5.11): the HIP path through the C ABI against the
+CPU FP64 oracle on the same seeded inputs.  FP64: rel-L2 <= 1e-12 per
+application; FP32 stepping: <= fp32_bound(N_T) as for Cartesian grids;
+solves: oracle iteration counts (+-1), the FP64 residual and the direct
+solution."""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import direct, krylov
+from oracle import stepping as S
+from oracle.curvilinear3d import MappedOperator3D
+from paper_2205_12344_amd.inputs import torus_section
+from oracle.problem import DIRICHLET, FREE
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+U32 = 2.0 ** -24
+
+
+def fp32_bound(nt):
+    return 2.0 * U32 * math.sqrt(nt) * nt / (2 * math.pi) + 8.0 * U32
+
+
+def _say(*a):
+    print("[gpu-mapped3]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def E():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2205_12344_amd import elwh
+    return elwh
+
+
+def _media(shape, seed, s=0.2):
+    rng = np.random.default_rng(seed)
+    rho = np.exp(s * rng.standard_normal(shape))
+    mu = np.exp(s * rng.standard_normal(shape))
+    return rho, 2.0 * mu * np.exp(s * rng.standard_normal(shape)), mu
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+
+
+# (cells q, r, s), faces, torus section angles: ragged in q (one and two
+# wavefronts), thin and thick in s, free and Dirichlet s faces
+CASES = [
+    ((70, 9, 5), (0, 0, 0, 0, 1, 1), (1.9, 1.1)),
+    ((40, 12, 7), (0, 0, 0, 0, 0, 0), (1.2, 2.0)),
+    ((63, 6, 4), (0, 0, 0, 0, 0, 1), (2.5, 0.9)),
+    ((129, 5, 3), (0, 0, 0, 0, 1, 0), (3.0, 1.0)),
+]
+
+
+def _setup(n, bc, ang, seed, omega=2.1, **kw):
+    x, y, z = torus_section(*n, phi=ang[0], theta=ang[1])
+    rho, lam, mu = _media(x.shape, seed)
+    op = MappedOperator3D(x, y, z, rho, lam, mu, bc=bc)
+    wh = S.WaveHoltz(op, omega, **kw)
+    return (x, y, z, rho, lam, mu), op, wh
+
+
+@pytest.mark.parametrize("n,bc,ang", CASES)
+@pytest.mark.parametrize("force", [False, True])
+def test_filter_fp64(E, n, bc, ang, force):
+    data, op, wh = _setup(n, bc, ang, 11)
+    prob = op.prob
+    rng = np.random.default_rng(5)
+    u0 = rng.standard_normal(prob.field_shape) * prob.unknown_mask()
+    f = rng.standard_normal(prob.field_shape) * prob.unknown_mask() if force else None
+    ref = prob.scatter(wh.apply_filter(prob.gather(u0), None if f is None else prob.gather(f)))
+    ctx = E.MappedContext3(*data, 2.1, bc=bc)
+    assert ctx.info()["nt"] == wh.nt
+    got = ctx.apply_filter(u0, f).cpu().numpy()
+    err = _rel(got, ref)
+    _say(n, bc, force, "nt", wh.nt, "err", err)
+    assert err <= FP64_TOL
+    # A_h = I - S_h
+    gotA = ctx.apply_A(u0).cpu().numpy()
+    refA = prob.scatter(wh.apply_A(prob.gather(u0)))
+    assert _rel(gotA, refA) <= FP64_TOL
+
+
+def test_filter_fp32_and_periods_and_standard_scheme(E):
+    n, bc, ang = CASES[0]
+    data, op, wh = _setup(n, bc, ang, 12)
+    prob = op.prob
+    u0 = np.random.default_rng(6).standard_normal(prob.field_shape) * prob.unknown_mask()
+    ref = prob.scatter(wh.apply_filter(prob.gather(u0)))
+    for comp in (1, 0):
+        ctx = E.MappedContext3(*data, 2.1, bc=bc, prec=E.FP32_STEP, compensated=comp)
+        err = _rel(ctx.apply_filter(u0).cpu().numpy(), ref)
+        _say("fp32", comp, err, "bound", fp32_bound(wh.nt))
+        assert err <= fp32_bound(wh.nt)
+    for kw, okw in (({"periods": 2}, {"periods": 2}), ({"scheme": 1}, {"scheme": S.STANDARD})):
+        _, _, wk = _setup(n, bc, ang, 12, **okw)
+        refk = prob.scatter(wk.apply_filter(prob.gather(u0)))
+        ctx = E.MappedContext3(*data, 2.1, bc=bc, **kw)
+        assert _rel(ctx.apply_filter(u0).cpu().numpy(), refk) <= FP64_TOL
+
+
+def test_dot_M_is_rho_J_weighted(E):
+    n, bc, ang = CASES[0]
+    data, op, wh = _setup(n, bc, ang, 13)
+    prob = op.prob
+    rng = np.random.default_rng(7)
+    x = rng.standard_normal(prob.field_shape)
+    y = rng.standard_normal(prob.field_shape)
+    ctx = E.MappedContext3(*data, 2.1, bc=bc)
+    assert ctx.dot_M(x, y) == pytest.approx(float(np.dot(op.m * prob.gather(x), prob.gather(y))), rel=1e-13)
+
+
+@pytest.mark.parametrize("bc", [(0,) * 6, (0, 0, 0, 0, 1, 1)])
+def test_cg_matches_oracle_and_direct(E, bc):
+    data, op, wh = _setup((30, 8, 5), bc, (2.0, 1.5), 14, omega=2.7)
+    prob = op.prob
+    f = np.random.default_rng(8).standard_normal(prob.field_shape) * prob.unknown_mask()
+    fv = prob.gather(f)
+    vstar = direct.solve(op, 2.7, fv)
+    ref = krylov.cg(wh.apply_A, wh.rhs(fv), op.m, tol=1e-10, maxit=2000)
+    ctx = E.MappedContext3(*data, 2.7, bc=bc)
+    v, info = ctx.solve(f, tol=1e-10, maxit=2000)
+    _say("cg", bc, info["iters"], ref.iters, info["relres_fp64"])
+    assert info["status"] == "OK" and info["relres_fp64"] <= 1e-10
+    assert abs(info["iters"] - ref.iters) <= 1
+    assert _rel(prob.gather(v.cpu().numpy()), vstar) <= 1e-8
+    # FP32 stepping with FP64 residual replacement reaches the same solution
+    c32 = E.MappedContext3(*data, 2.7, bc=bc, prec=E.FP32_STEP)
+    v32, i32 = c32.solve(f, tol=1e-10, maxit=4000)
+    assert i32["relres_fp64"] <= 1e-10
+    assert _rel(prob.gather(v32.cpu().numpy()), vstar) <= 1e-7
+
+
+def test_toroidal_shell_conjugate_residual(E):
+    """The partial toroidal shell of Sec. 5.11 (R = 4, 1 <= r <= 2, 0 <= theta,
+    phi <= pi, free radial faces, the paper's forcing), coarsened to
+    48 x 16 x 6 cells at omega = 2.5: conjugate residual to 1e-5 takes the
+    oracle's iteration count (the paper reports 1490 at omega = 5.1234 on 400 x
+    120 x 40 points: context only)."""
+    x, y, z = torus_section(48, 16, 6)
+    bc = (0, 0, 0, 0, 1, 1)
+    om = 2.5
+    op = MappedOperator3D(x, y, z, 1.0, 2.0, 1.0, bc=bc)
+    sig = 100 * om
+    g = np.sqrt(sig ** 3) / 20 * np.exp(-0.5 * sig * ((x - 4) ** 2 + (y - 0.5) ** 2 + (z - 1) ** 2))
+    f = np.stack([g, g, g]) * op.prob.unknown_mask()
+    wh = S.WaveHoltz(op, om)
+    ref = krylov.cr(wh.apply_A, wh.rhs(op.prob.gather(f)), op.m, tol=1e-5, maxit=4000)
+    one = np.ones(x.shape)
+    ctx = E.MappedContext3(x, y, z, one, 2 * one, one, om, bc=bc, krylov=E.KRYLOV_CR)
+    v, info = ctx.solve(f, tol=1e-5, maxit=4000)
+    _say("torus CR", info["iters"], ref.iters, info["relres_fp64"])
+    assert info["status"] == "OK" and info["relres_fp64"] <= 1e-5
+    assert abs(info["iters"] - ref.iters) <= 1
+    # Stopped at 1e-5, this iterate is sensitive at the 1e-5 level to rounding
+    # alone: perturbing b by 1e-15 (relative) moves the oracle's own CR iterate
+    # by 1.1e-5 at the same count.  So compare to the oracle within 1e-4 and
+    # to the direct solution no worse than the oracle's iterate is.
+    vg = op.prob.gather(v.cpu().numpy())
+    assert _rel(vg, ref.x) <= 1e-4
+    vstar = direct.solve(op, om, op.prob.gather(f))
+    assert _rel(vg, vstar) <= 1.05 * _rel(ref.x, vstar) + 1e-5
+
+
+def test_manufactured_fixed_point(E):
+    """Pi_h v* = v* for v* = the direct solve (no time error on mapped 3-D
+    grids either)."""
+    n, bc, ang = CASES[2]
+    data, op, wh = _setup(n, bc, ang, 15)
+    prob = op.prob
+    fv = np.random.default_rng(9).standard_normal(op.ndof)
+    v = direct.solve(op, 2.1, fv)
+    ctx = E.MappedContext3(*data, 2.1, bc=bc)
+    got = ctx.apply_filter(prob.scatter(v), prob.scatter(fv)).cpu().numpy()
+    assert _rel(prob.gather(got), v) <= 1e-11
+
+
+def test_rejections(E):
+    x, y, z = torus_section(8, 6, 4)
+    one = np.ones(x.shape)
+    with pytest.raises(E.ElwhError):
+        E.MappedContext3(x, y, z, one, one, one, 1.0, bc=(0, 0, 1, 0, 0, 0))
+    with pytest.raises(E.ElwhError):
+        E.MappedContext3(x[:, :, ::-1].copy(), y[:, :, ::-1].copy(), z[:, :, ::-1].copy(), one, one, one, 1.0)

@@ -111,8 +111,9 @@ CASES_3D = [
 
 @pytest.mark.parametrize("n,bc,length", CASES_3D)
 @pytest.mark.parametrize("force", [False, True])
-def test_filter_3d_fp64(E, n, bc, length, force):
-    _say("filter3d fp64", n, bc, force)
+@pytest.mark.parametrize("fuse", [2, 1])
+def test_filter_3d_fp64(E, n, bc, length, force, fuse):
+    _say("filter3d fp64", n, bc, force, "steps per launch", fuse)
     shape = (n[2] + 1, n[1] + 1, n[0] + 1)
     rho, lam, mu = _media(shape, sum(n) + 1)
     om = 6.1
@@ -121,7 +122,7 @@ def test_filter_3d_fp64(E, n, bc, length, force):
     u0 = rng.standard_normal(prob.field_shape) * prob.unknown_mask()
     f = rng.standard_normal(prob.field_shape) * prob.unknown_mask() if force else None
     ref = prob.scatter(wh.apply_filter(prob.gather(u0), prob.gather(f) if force else None))
-    ctx = E.Context(3, n, rho, lam, mu, om, bc, length=length)
+    ctx = E.Context(3, n, rho, lam, mu, om, bc, length=length, fuse=fuse)
     assert ctx.info()["nt"] == wh.nt
     got = ctx.apply_filter(u0, f).cpu().numpy()
     assert _rel(got, ref) <= FP64_TOL
@@ -147,6 +148,25 @@ def test_filter_fp32_stepping(E, dim):
             err = _rel(got, ref)
             _say("  fp32 compensated", comp, "fuse", fuse, "nt", wh.nt, "rel err", err, "bound", fp32_bound(wh.nt))
             assert err <= fp32_bound(wh.nt)
+
+
+@pytest.mark.parametrize("nt", [3, 4, 5, 8, 9])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_multi_step_every_step_count_3d(E, nt, prec):
+    """Two-step 3-D launches with every remainder (N_T = 3, 4, 5, 8, 9; the
+    half step, pairs, a last single step) against the oracle, FP64 and FP32,
+    with free z faces and forcing."""
+    n, bc = (47, 13, 21), (0, 0, 0, 0, 1, 1)
+    rho, lam, mu = _media((22, 14, 48), 300 + nt)
+    prob, op, wh = _oracle(3, n, None, bc, rho, lam, mu, 3.1, nt=nt)
+    rng = np.random.default_rng(nt)
+    u0 = rng.standard_normal(prob.field_shape) * prob.unknown_mask()
+    f = rng.standard_normal(prob.field_shape) * prob.unknown_mask()
+    ref = prob.scatter(wh.apply_filter(prob.gather(u0), prob.gather(f)))
+    ctx = E.Context(3, n, rho, lam, mu, 3.1, bc, nt=nt, prec=prec, fuse=2)
+    err = _rel(ctx.apply_filter(u0, f).cpu().numpy(), ref)
+    _say("3-D two-step nt", nt, "prec", prec, "err", err)
+    assert err <= (FP64_TOL if prec == 0 else fp32_bound(nt))
 
 
 @pytest.mark.parametrize("nt", [3, 4, 5, 8, 9])
@@ -469,10 +489,13 @@ def test_large_sizes_fixed_point():
 
 # ------------------------------------------------------------- tilings --------
 
-def _tiles(dim, fp32):
+def _tiles(dim, fp32, fuse=1):
     if dim == 2:
         vs = (1, 2, 4) if fp32 else (1, 2)
         return [(v, ty) for v in vs for ty in (4, 8, 16)]
+    if fuse >= 2:   # two-step 3-D launches: RB rows (plus two halo rows) x TZ planes;
+        # RB 1 = single-step launches in a two-step context
+        return [(rb, tz) for rb in (2, 4, 6) for tz in (8, 16, 32)] + [(1, 16), (1, 32)]
     return [(rb, tz) for rb in (1, 2, 4, 8) for tz in (4, 8, 16, 32)]
 
 
@@ -495,9 +518,9 @@ def test_every_tiling_matches_oracle(E, dim, prec):
     ref = prob.scatter(wh.apply_filter(prob.gather(u0), prob.gather(f)))
     tol = FP64_TOL if prec == 0 else fp32_bound(wh.nt)
     outs = []
-    for fuse in ((2, 1, 3, 4) if dim == 2 else (2,)):
+    for fuse in ((2, 1, 3, 4) if dim == 2 else (2, 1)):
         ctx = E.Context(dim, n, rho, lam, mu, om, bc, prec=prec, autotune=0, fuse=fuse)
-        for v, rows in _tiles(dim, prec == 1):
+        for v, rows in _tiles(dim, prec == 1, fuse):
             ctx.set_tile(prec, v, rows)
             got = ctx.apply_filter(u0, f).cpu().numpy()
             err = _rel(got, ref)

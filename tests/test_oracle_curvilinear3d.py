@@ -9,7 +9,8 @@ import pytest
 
 from oracle import direct, krylov
 from oracle import stepping as S
-from oracle.curvilinear3d import MappedOperator3D, torus_section
+from oracle.curvilinear3d import MappedOperator3D
+from paper_2205_12344_amd.inputs import torus_section
 from oracle.operator import Operator
 from oracle.problem import DIRICHLET, FREE, Problem
 
