@@ -127,6 +127,16 @@ typedef struct {
                           (FP32 applications no longer improve x), finish with
                           FP64 CG from the current iterate (info.fp64_iters);
                           0 = stay with FP32 applications until maxit */
+    double fp32_switch;/* FP32 path: the relative residual below which FP32
+                          stepping takes over.  0 (default) = FP32 applications
+                          from the start; s > 0 = FP64 CG until ||r||_M <=
+                          s ||b||_M, then (after a residual replacement that keeps
+                          the search direction) FP32 segments.  An FP32
+                          application perturbs A_h by a relative eps (about
+                          1e-5 at N_T = 63); an inexact Krylov method tolerates a
+                          perturbation of about tol ||b|| / ||r|| at a residual r,
+                          so s = tol / eps spends the FP32 error only where it
+                          costs no accuracy. */
 } elwh_opts;
 
 typedef struct {

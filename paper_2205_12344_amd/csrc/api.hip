@@ -973,6 +973,7 @@ void elwh_default_opts(elwh_opts* o) {
     o->scale_x0 = 0;
     o->cr_fallback = 1;
     o->fp64_fallback = 1;
+    o->fp32_switch = 0.0;
 }
 
 elwh_status elwh_plan(const elwh_grid* grid, const double* rho, const double* lam, const double* mu, double omega,
@@ -1379,11 +1380,51 @@ elwh_status elwh_solve(elwh_ctx* c, const double* f, const double* x0, double to
         double relfp64 = std::sqrt(rr / bb), seg = rr;
         inf.relres = relfp64;
         int outer = 0, iters = 0;
+        bool finished = false;   // set when the FP64 phase ends the solve (CG breakdown)
+        // FP64 first (opts.fp32_switch > 0): CG with FP64 applications down to
+        // the switch residual, then a residual replacement that keeps the
+        // search direction, and the FP32 segments below continue the same
+        // Krylov sequence.
+        const double sw = std::max(c->opts.fp32_switch, tol);
+        if (c->opts.fp32_switch > 0 && tol > 0 && relfp64 > sw && maxit > 0) {
+            CGOut o;
+            const elwh_status si = cg_steps(c, c->vec[VX], c->vec[VR], c->vec[VP], c->vec[VQ], false, bb, maxit, sw,
+                                            &o, false);
+            iters += o.iters;
+            inf.fp64_iters += o.iters;
+            inf.relres = o.relres;
+            if (si == ELWH_ERR_BREAKDOWN && c->opts.cr_fallback) {
+                int it = 0;
+                double relcr = 1.0, relchk = -1.0;
+                st = solve_checked(c, c->opts.cr_fallback == 2 ? solve_minres : solve_cr, false, tol,
+                                   std::max(1, maxit - iters), &it, &relcr, &relchk);
+                if (st != ELWH_OK && st != ELWH_ERR_NOT_CONVERGED) return st;
+                inf.cr_iters = it;
+                inf.relres = relcr;
+                CKST(final_residual(c, c->vec[VX], bb, &relfp64));
+                st = relfp64 <= tol ? ELWH_OK : ELWH_ERR_NOT_CONVERGED;
+                finished = true;
+            } else if (si != ELWH_OK) {
+                return si;
+            } else if (o.converged) {
+                // (not converged: maxit was reached, and the loop below ends)
+                const double rr_new = c->hscal[S_RR], beta_k = c->hscal[S_BETA];
+                const double rr_k = beta_k > 0 ? rr_new / beta_k : 0.0;
+                CKST(true_residual(false, &rr, false));
+                relfp64 = std::sqrt(rr / bb);
+                seg = rr;
+                CKST(set_scalar(c, S_BETA, rr_k > 0 ? rr / rr_k : 0.0));
+                CKST(set_scalar(c, S_RR, rr));
+                launch_cg_update_p(c, c->vec[VP], c->vec[VR], c->stream);
+            } else {
+                relfp64 = o.relres;
+            }
+        }
         std::vector<double> hist{relfp64};   // FP64 residual after each segment
         bool stagnated = false;
         int longest = 0;                      // iterations of the longest segment so far
-        st = ELWH_ERR_NOT_CONVERGED;
-        while (true) {
+        st = finished ? st : ELWH_ERR_NOT_CONVERGED;
+        while (!finished) {
             if (tol > 0 && relfp64 <= tol) {
                 st = ELWH_OK;
                 break;
@@ -1406,8 +1447,9 @@ elwh_status elwh_solve(elwh_ctx* c, const double* f, const double* x0, double to
                 // conjugate residual in FP64 from the current iterate
                 iters += o.iters;
                 int it = 0;
-                double relcr = 1.0;
-                st = solve_cr(c, false, tol, std::max(1, maxit - iters), &it, &relcr);
+                double relcr = 1.0, relchk = -1.0;
+                st = solve_checked(c, c->opts.cr_fallback == 2 ? solve_minres : solve_cr, false, tol,
+                                   std::max(1, maxit - iters), &it, &relcr, &relchk);
                 if (st != ELWH_OK && st != ELWH_ERR_NOT_CONVERGED) return st;
                 inf.cr_iters = it;
                 inf.relres = relcr;
@@ -1446,20 +1488,38 @@ elwh_status elwh_solve(elwh_ctx* c, const double* f, const double* x0, double to
             c->opts.scale_x0 = keep;
             CKST(s0);
             c->cg_qready = false;
-            CGOut o2;
-            st = cg_steps_pipelined(c, c->vec[VX], c->vec[VR], c->vec[VP], c->vec[VQ], bb2, maxit - iters, tol, &o2);
-            inf.fp64_iters = o2.iters;
-            iters += o2.iters;
-            inf.relres = o2.relres;
-            if (st == ELWH_ERR_BREAKDOWN && c->opts.cr_fallback) {
-                int it = 0;
-                double relcr = 1.0;
-                st = solve_cr(c, false, tol, std::max(1, maxit - iters), &it, &relcr);
-                inf.cr_iters = it;
-                inf.relres = relcr;
+            // The pipelined recurrence stops on its own residual, which can sit
+            // well below the true one: when b - A_h x is still above tol, CG
+            // restarts from x (r = b - A_h x), at most kMaxReplace times.
+            for (int rep = 0;; ++rep) {
+                CGOut o2;
+                st = cg_steps_pipelined(c, c->vec[VX], c->vec[VR], c->vec[VP], c->vec[VQ], bb2, maxit - iters, tol,
+                                        &o2);
+                inf.fp64_iters += o2.iters;
+                iters += o2.iters;
+                inf.relres = o2.relres;
+                if (st == ELWH_ERR_BREAKDOWN && c->opts.cr_fallback) {
+                    int it = 0;
+                    double relcr = 1.0, relchk = -1.0;
+                    st = solve_checked(c, c->opts.cr_fallback == 2 ? solve_minres : solve_cr, false, tol,
+                                       std::max(1, maxit - iters), &it, &relcr, &relchk);
+                    inf.cr_iters = it;
+                    inf.relres = relcr;
+                    if (st != ELWH_OK && st != ELWH_ERR_NOT_CONVERGED) return st;
+                    CKST(final_residual(c, c->vec[VX], bb, &relfp64));
+                    break;
+                }
+                if (st != ELWH_OK && st != ELWH_ERR_NOT_CONVERGED) return st;
+                CKST(final_residual(c, c->vec[VX], bb, &relfp64));
+                if (relfp64 <= tol || st != ELWH_OK || iters >= maxit || rep + 1 >= kMaxReplace) break;
+                ++outer;
+                c->opts.scale_x0 = 0;
+                const elwh_status s1 = cg_start(c, c->vec[VB], c->vec[VX], false, c->vec[VR], c->vec[VP],
+                                                c->vec[VQ], false, &bb2, &rr2);
+                c->opts.scale_x0 = keep;
+                CKST(s1);
+                c->cg_qready = false;
             }
-            if (st != ELWH_OK && st != ELWH_ERR_NOT_CONVERGED) return st;
-            CKST(final_residual(c, c->vec[VX], bb, &relfp64));
             st = relfp64 <= tol ? ELWH_OK : ELWH_ERR_NOT_CONVERGED;
         }
         inf.iters = iters;

@@ -631,6 +631,65 @@ elwh_status elwh_batch_solve(elwh_batch* b, const double* const* f, const double
     for (auto* c : b->ctx) max_nsteps = std::max<long long>(max_nsteps, (long long)c->plan.nt * c->opts.periods);
     const long long tick_budget = (long long)(maxit + 2) * max_nsteps + 64;
 
+    // Convergence is judged on the true residual, recomputed with an FP64
+    // apply: a problem of sel whose recurrence residual met tol but whose true
+    // residual did not has r replaced by b - A_h x and continues FP64 CG along
+    // the same search direction (a reliable update), like elwh_solve.  Sets
+    // relfp64 of every problem in sel; the iterations go to iters (and to
+    // extra, when given).
+    auto true_residual_continue = [&](const std::vector<int>& sel, std::vector<int>* extra) -> elwh_status {
+        for (int rep = 0;; ++rep) {
+            BST(run_apply(b, false, false, true, VX, VQ, sel));
+            BST(lincomb(b, sel, VT, VB, 1.0, VQ, -1.0));
+            BST(dots(b, sel, VT, VT, rr));
+            std::vector<int> more(np, 0);
+            bool any = false;
+            for (int p = 0; p < np; ++p) {
+                if (!sel[p]) continue;
+                relfp64[p] = bb[p] > 0 ? std::sqrt(rr[p] / bb[p]) : 0.0;
+                if (tol <= 0 || !(bb[p] > 0) || status[p] != ELWH_OK || relfp64[p] <= tol) continue;
+                if (iters[p] >= maxit || rep + 1 >= kBatchMaxReplace) {
+                    status[p] = ELWH_ERR_NOT_CONVERGED;
+                    continue;
+                }
+                more[p] = 1;
+                any = true;
+            }
+            if (!any) return ELWH_OK;
+            // r = b - A_h x; p = r + beta p with beta = (r, r)_M / (r_k, r_k)_M, r_k
+            // the residual before the last CG step (rr_k = rr / beta of that step)
+            std::vector<double> beta(np, 0.0);
+            for (int p = 0; p < np; ++p) {
+                const BState& s = b->h_st[p];
+                if (more[p] && s.beta > 0 && s.rr > 0) beta[p] = rr[p] / (s.rr / s.beta);
+            }
+            BST(lincomb(b, more, VR, VT, 1.0, -1, 0.0));
+            BST(lincomb(b, more, VP, VR, 1.0, VP, 0.0, &beta));
+            for (int p = 0; p < np; ++p) {
+                BState& s = b->h_st[p];
+                const int keep_iters = iters[p];
+                std::memset(&s, 0, sizeof(s));
+                if (!more[p]) continue;
+                s.rr = rr[p];
+                s.bb = bb[p];
+                s.tol2 = tol * tol;
+                s.maxit = std::max(1, maxit - keep_iters);
+                s.status = ELWH_ERR_NOT_CONVERGED;
+                s.active = 1;
+            }
+            BST(run_cg(b, false, VX, VR, VP, VQ, tick_budget));
+            for (int p = 0; p < np; ++p) {
+                if (!more[p]) continue;
+                outer[p]++;
+                iters[p] += b->h_st[p].iters;
+                if (extra) (*extra)[p] += b->h_st[p].iters;
+                status[p] = b->h_st[p].status;
+                if (status[p] == ELWH_ERR_NOT_CONVERGED && iters[p] < maxit) status[p] = ELWH_OK;
+                relres[p] = std::sqrt(b->h_st[p].rr / bb[p]);
+            }
+        }
+    };
+
     if (!fp32) {
         // r = b - A x0, p = r
         bool anyx = false;
@@ -664,58 +723,7 @@ elwh_status elwh_batch_solve(elwh_batch* b, const double* const* f, const double
             if (tol <= 0 && status[p] == ELWH_ERR_NOT_CONVERGED) status[p] = ELWH_OK;
             relres[p] = bb[p] > 0 ? std::sqrt(b->h_st[p].rr / bb[p]) : 0.0;
         }
-        // Convergence is judged on the true residual, recomputed with an FP64
-        // apply: a problem whose recurrence residual met tol but whose true
-        // residual did not has r replaced by b - A_h x and continues CG along
-        // the same search direction (a reliable update), like elwh_solve.
-        for (int rep = 0;; ++rep) {
-            BST(run_apply(b, false, false, true, VX, VQ, all));
-            BST(lincomb(b, all, VT, VB, 1.0, VQ, -1.0));
-            BST(dots(b, all, VT, VT, rr));
-            std::vector<int> more(np, 0);
-            bool any = false;
-            for (int p = 0; p < np; ++p) {
-                relfp64[p] = bb[p] > 0 ? std::sqrt(rr[p] / bb[p]) : 0.0;
-                if (tol <= 0 || !(bb[p] > 0) || status[p] != ELWH_OK || relfp64[p] <= tol) continue;
-                if (iters[p] >= maxit || rep + 1 >= kBatchMaxReplace) {
-                    status[p] = ELWH_ERR_NOT_CONVERGED;
-                    continue;
-                }
-                more[p] = 1;
-                any = true;
-            }
-            if (!any) break;
-            // r = b - A_h x; p = r + beta p with beta = (r, r)_M / (r_k, r_k)_M, r_k
-            // the residual before the last CG step (rr_k = rr / beta of that step)
-            std::vector<double> beta(np, 0.0);
-            for (int p = 0; p < np; ++p) {
-                const BState& s = b->h_st[p];
-                if (more[p] && s.beta > 0 && s.rr > 0) beta[p] = rr[p] / (s.rr / s.beta);
-            }
-            BST(lincomb(b, more, VR, VT, 1.0, -1, 0.0));
-            BST(lincomb(b, more, VP, VR, 1.0, VP, 0.0, &beta));
-            for (int p = 0; p < np; ++p) {
-                BState& s = b->h_st[p];
-                const int keep_iters = iters[p];
-                std::memset(&s, 0, sizeof(s));
-                if (!more[p]) continue;
-                s.rr = rr[p];
-                s.bb = bb[p];
-                s.tol2 = tol * tol;
-                s.maxit = std::max(1, maxit - keep_iters);
-                s.status = ELWH_ERR_NOT_CONVERGED;
-                s.active = 1;
-            }
-            BST(run_cg(b, false, VX, VR, VP, VQ, tick_budget));
-            for (int p = 0; p < np; ++p) {
-                if (!more[p]) continue;
-                outer[p]++;
-                iters[p] += b->h_st[p].iters;
-                status[p] = b->h_st[p].status;
-                if (status[p] == ELWH_ERR_NOT_CONVERGED && iters[p] < maxit) status[p] = ELWH_OK;
-                relres[p] = std::sqrt(b->h_st[p].rr / bb[p]);
-            }
-        }
+        BST(true_residual_continue(all, nullptr));
         if (b->opts.cr_fallback) BST(cr_fallback(b, status, iters, cr_iters, relres, relfp64, bb, tol, maxit));
     } else {
         // FP32 stepping inside CG with FP64 reliable updates (as elwh_solve):
@@ -741,8 +749,57 @@ elwh_status elwh_batch_solve(elwh_batch* b, const double* const* f, const double
         for (int p = 0; p < np; ++p) {
             relfp64[p] = bb[p] > 0 ? std::sqrt(rr[p] / bb[p]) : 0.0;
             relres[p] = relfp64[p];
-            hist[p].push_back(relfp64[p]);
         }
+        // FP64 first (opts.fp32_switch > 0): FP64 CG down to the switch
+        // residual, then a residual replacement that keeps the search
+        // direction; the FP32 segments below continue the same Krylov sequence
+        if (b->opts.fp32_switch > 0 && tol > 0 && maxit > 0) {
+            const double sw = std::max(b->opts.fp32_switch, tol);
+            std::vector<int> ph(np, 0), repl(np, 0);
+            bool anyph = false;
+            for (int p = 0; p < np; ++p) {
+                BState& s = b->h_st[p];
+                std::memset(&s, 0, sizeof(s));
+                if (!(bb[p] > 0) || !(relfp64[p] > sw)) continue;
+                ph[p] = 1;
+                anyph = true;
+                s.active = 1;
+                s.rr = rr[p];
+                s.bb = bb[p];
+                s.tol2 = sw * sw;
+                s.maxit = maxit;
+                s.status = ELWH_ERR_NOT_CONVERGED;
+            }
+            if (anyph) {
+                BST(run_cg(b, false, VX, VR, VP, VQ, tick_budget));
+                for (int p = 0; p < np; ++p) {
+                    if (!ph[p]) continue;
+                    const BState& s = b->h_st[p];
+                    iters[p] += s.iters;
+                    fp64_iters[p] += s.iters;
+                    relres[p] = std::sqrt(s.rr / bb[p]);
+                    if (s.status == ELWH_ERR_BREAKDOWN || s.status == ELWH_ERR_UNSTABLE) {
+                        status[p] = s.status;   // (a breakdown goes to the CR fallback below)
+                    } else if (s.status == ELWH_OK) {
+                        repl[p] = 1;
+                        rr_k[p] = s.beta > 0 ? s.rr / s.beta : 0.0;
+                    } else {
+                        relfp64[p] = relres[p];   // out of iterations: the loop head ends it
+                    }
+                }
+                BST(run_apply(b, false, false, true, VX, VQ, repl));
+                BST(lincomb(b, repl, VR, VB, 1.0, VQ, -1.0));
+                BST(dots(b, repl, VR, VR, rr));
+                for (int p = 0; p < np; ++p) {
+                    if (!repl[p]) continue;
+                    relfp64[p] = std::sqrt(rr[p] / bb[p]);
+                    seg[p] = rr[p];
+                    beta[p] = rr_k[p] > 0 ? rr[p] / rr_k[p] : 0.0;
+                }
+                BST(lincomb(b, repl, VP, VR, 1.0, VP, 0.0, &beta));
+            }
+        }
+        for (int p = 0; p < np; ++p) hist[p].push_back(relfp64[p]);
         for (int o = 0;; ++o) {
             std::vector<int> pending(np, 0);
             bool any = false;
@@ -835,16 +892,13 @@ elwh_status elwh_batch_solve(elwh_batch* b, const double* const* f, const double
             BST(run_cg(b, false, VX, VR, VP, VQ, tick_budget));
             for (int p = 0; p < np; ++p) {
                 if (!stag[p]) continue;
-                fp64_iters[p] = b->h_st[p].iters;
+                fp64_iters[p] += b->h_st[p].iters;
                 iters[p] += b->h_st[p].iters;
                 status[p] = b->h_st[p].status;
                 relres[p] = std::sqrt(b->h_st[p].rr / bb[p]);
             }
-            BST(run_apply(b, false, false, true, VX, VQ, stag));
-            BST(lincomb(b, stag, VT, VB, 1.0, VQ, -1.0));
-            BST(dots(b, stag, VT, VT, rr));
-            for (int p = 0; p < np; ++p)
-                if (stag[p]) relfp64[p] = std::sqrt(rr[p] / bb[p]);
+            // judged on the true residual, as the FP64 path
+            BST(true_residual_continue(stag, &fp64_iters));
         }
         if (b->opts.cr_fallback) BST(cr_fallback(b, status, iters, cr_iters, relres, relfp64, bb, tol, maxit));
     }

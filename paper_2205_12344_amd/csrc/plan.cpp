@@ -815,6 +815,10 @@ elwh_status check_config(const elwh_grid* g, const int bc[6], const elwh_opts* o
         if (o->scheme != ELWH_SCHEME_CORRECTED && o->scheme != ELWH_SCHEME_STANDARD &&
             o->scheme != ELWH_SCHEME_MODIFIED) { *err = "bad scheme"; return ELWH_ERR_ARG; }
         if (o->fuse < 1 || o->fuse > 4) { *err = "fuse must be in [1, 4]"; return ELWH_ERR_ARG; }
+        if (!(o->fp32_switch >= 0.0 && o->fp32_switch < 1.0)) {
+            *err = "fp32_switch must be in [0, 1)";
+            return ELWH_ERR_ARG;
+        }
     }
     return ELWH_OK;
 }

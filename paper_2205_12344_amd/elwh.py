@@ -50,7 +50,7 @@ class Opts(ctypes.Structure):
                 ("scheme", ctypes.c_int), ("compensated", ctypes.c_int), ("inner_tol", ctypes.c_double),
                 ("max_outer", ctypes.c_int), ("stream", ctypes.c_void_p), ("autotune", ctypes.c_int),
                 ("fuse", ctypes.c_int), ("scale_x0", ctypes.c_int), ("cr_fallback", ctypes.c_int),
-                ("fp64_fallback", ctypes.c_int)]
+                ("fp64_fallback", ctypes.c_int), ("fp32_switch", ctypes.c_double)]
 
 
 class Info(ctypes.Structure):

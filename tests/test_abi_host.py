@@ -47,6 +47,15 @@ def test_default_opts(elwh):
     o = elwh.default_opts()
     assert o.cfl == 0.8 and o.periods == 1 and o.nt == 0 and o.prec == 0 and o.compensated == 1 and o.autotune == 1
     assert o.fuse == 2 and o.scale_x0 == 0 and o.inner_tol == 1e-2 and o.cr_fallback == 1 and o.fp64_fallback == 1
+    assert o.fp32_switch == 0.0
+
+
+def test_fp32_switch_is_validated(elwh):
+    ok = np.ones((9, 9))
+    for bad in (-1e-3, 1.0, float("nan")):
+        with pytest.raises(elwh.ElwhError, match="ERR_ARG"):
+            elwh.plan(2, (8, 8), ok, ok, ok, 3.0, (0, 0, 0, 0), prec=1, fp32_switch=bad)
+    elwh.plan(2, (8, 8), ok, ok, ok, 3.0, (0, 0, 0, 0), prec=1, fp32_switch=1e-3)
 
 
 def _media(shape, seed):
