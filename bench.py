@@ -11,11 +11,16 @@ accumulation.
 
 The JSON line also carries the roofline of the fused step-pair kernel
 (HIP-event durations of the step launches over a profiled repeat of the
-timed steps), the FP32-stepping and single-step variants, the step kernel
-of mapped (curvilinear) grids on an annular sector, and the CPU oracle's
-rate on a bounded sample.
+timed steps), the HBM ceiling a STREAM triad reaches, the FP32-stepping and
+single-step variants, the step kernels of the 3-D cube, of mapped 2-D and 3-D
+grids and of the two-field operator, the time to residual 1e-8 of the
+benchmark problem and of a 3-D cube, the 48-problem ragged batch, the
+learned-start comparison on the 512 held-out warm-start problems, and the
+CPU oracle's rate on all host cores and on one core.  The optional parts
+run in order of importance inside a time budget (--budget seconds); a part
+that would not fit is reported as skipped.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-3d] [--mapped-only]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--budget S] [--no-cpu] [--quick]
 """
 
 import argparse
@@ -52,6 +57,11 @@ BYTES_PER_LUP = {
     (3, "f64", 1): 144, (3, "f32c", 1): 144, (3, "f32", 1): 96,
 }
 BYTES_PER_MULTI_LAUNCH = {"f64": 120, "f32c": 108, "f32": 76}
+# 3-D two-step kernel, per node and launch (two lattice updates): read u^n,
+# u^{n-1} (2x3x8), a, lambda, mu (3x8), acc (3x8); write u^{n+1}, u^{n+2}
+# (2x3x8), acc (3x8) = 168 (FP64); FP32 state with the compensated FP64
+# accumulator: 2x12 + 12 + acc hi+lo 48 read, 2x12 + 48 written = 156
+BYTES_PER_LAUNCH_3D_K2 = {"f64": 168, "f32c": 156}
 # Mapped (curvilinear) 2-D grids, single-step kernel: the three coefficient
 # arrays become seven (a = c dt^2/(rho J), lambda/J, mu/J and the metric
 # vectors J grad q, J grad r):
@@ -101,9 +111,9 @@ def unknown_nodes(case):
     return cnt
 
 
-def read_traffic(kernel_tag, tile):
+def read_traffic(kernel_tag, tile, family="2d"):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    one exists for this kernel, workload and tiling and the kernel sources
+    one exists for this kernel, workload and tiling and the kernel's sources
     have not changed since (else None)."""
     path = os.path.join(ROOT, "profiles", f"{kernel_tag}_counters.txt")
     if not os.path.exists(path):
@@ -118,15 +128,23 @@ def read_traffic(kernel_tag, tile):
     if key not in vals:
         return None
     src_hash = vals.get("kernel_source_hash")
-    if src_hash and src_hash != kernel_source_hash():
+    if src_hash != kernel_source_hash(family):
         return None          # the kernel changed since the counters were taken
     return float(vals[key])
 
 
-def kernel_source_hash():
+# the sources each step-kernel family is built from (a counters summary holds
+# the hash of its family's sources at the time of collection)
+KERNEL_SOURCES = {
+    "2d": ("kernels2d.hip", "kernels2d_multi.hip", "step2d_common.h", "xcd.h", "lanes.h"),
+    "3d": ("kernels3d.hip", "kernels3d_k2.hip", "step3d_common.h", "xcd.h", "lanes.h"),
+}
+
+
+def kernel_source_hash(family="2d"):
     import hashlib
     h = hashlib.sha256()
-    for f in ("kernels2d.hip", "kernels2d_multi.hip", "step2d_common.h", "xcd.h", "kernels3d.hip", "lanes.h"):
+    for f in KERNEL_SOURCES[family]:
         h.update(open(os.path.join(ROOT, "paper_2205_12344_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -229,19 +247,19 @@ def twofield_rates(elwh, inputs, napply=3, solve=True):
     return out
 
 
-def cpu_baseline(case, budget_s=12.0):
-    """The oracle as it stands, timed on the host: A_h applications on the
-    benchmark workload until the budget is spent (single-threaded sparse
-    matrix-vector products and NumPy vector updates)."""
+def cpu_worker(seconds):
+    """One CPU process of the oracle baseline: A_h applications of the oracle
+    (sparse matrix-vector products and NumPy vector updates, one thread) on
+    the benchmark workload for about `seconds`; prints one JSON line."""
     import numpy as np
     from oracle.operator import Operator
     from oracle.problem import Problem
     from oracle.stepping import WaveHoltz
-    t0 = time.perf_counter()
+    from paper_2205_12344_amd import inputs
+    case = inputs.random_square()
     prob = Problem(case.dim, case.n, length=case.length, bc=case.bc)
     op = Operator(prob, case.rho, case.lam, case.mu)
     wh = WaveHoltz(op, case.omega)
-    t_setup = time.perf_counter() - t0
     x = np.random.default_rng(0).standard_normal(op.ndof)
     napply = 0
     t0 = time.perf_counter()
@@ -249,13 +267,118 @@ def cpu_baseline(case, budget_s=12.0):
         x = wh.apply_A(x)
         x /= np.linalg.norm(x)
         napply += 1
-        if time.perf_counter() - t0 >= budget_s:
+        if time.perf_counter() - t0 >= seconds:
             break
     el = time.perf_counter() - t0
-    lups = napply * wh.nt * unknown_nodes(case)
-    return {"value": lups / el, "unit": "LUP/s", "cores": 1, "kind": "oracle",
-            "sample": f"{napply} A_h applications ({wh.nt} steps each) of the oracle on the same 1024^2 "
-                      f"workload, {el:.1f} s; operator assembly {t_setup:.1f} s excluded"}
+    print(json.dumps({"napply": napply, "seconds": el, "nt": wh.nt, "nodes": unknown_nodes(case)}))
+
+
+def cpu_baseline(seconds=10.0):
+    """The oracle timed on the host: one worker process alone (one core), then
+    one worker per core on every core the box gives this job (os.cpu_count(),
+    at most 16), each doing A_h applications on the same 1024^2 workload;
+    the all-core figure is the aggregate rate.  Worker processes are plain
+    child processes with one thread each (no GPU use)."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-worker", str(seconds)]
+
+    def run(n):
+        procs = [subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.DEVNULL, env=env) for _ in range(n)]
+        outs = []
+        for p in procs:
+            out, _ = p.communicate(timeout=seconds + 300)
+            if p.returncode != 0:
+                raise RuntimeError(f"cpu worker failed ({p.returncode})")
+            outs.append(json.loads(out.decode().strip().splitlines()[-1]))
+        return outs
+
+    one = run(1)[0]
+    ncores = max(1, min(os.cpu_count() or 1, 16))
+    many = run(ncores) if ncores > 1 else [one]
+    lup1 = one["napply"] * one["nt"] * one["nodes"] / one["seconds"]
+    lupn = sum(o["napply"] * o["nt"] * o["nodes"] / o["seconds"] for o in many)
+    sample = (f"A_h applications ({one['nt']} steps each) of the oracle on the same 1024^2 workload for "
+              f"about {seconds:.0f} s per process (operator assembly excluded): one process alone "
+              f"({one['napply']} applications), then {ncores} processes at once "
+              f"({sum(o['napply'] for o in many)} applications in all)")
+    return {"value": lupn, "unit": "LUP/s", "cores": ncores, "kind": "oracle", "sample": sample,
+            "os_cpu_count": os.cpu_count(), "one_core": {"value": lup1, "unit": "LUP/s", "cores": 1}}
+
+
+def triad_ceiling(elwh, n=2 ** 28, reps=10):
+    """The HBM bandwidth a STREAM triad (the library's elwh_stream_triad)
+    reaches over three 2 GiB arrays, and a device copy for comparison."""
+    import torch
+    a = torch.empty(n, dtype=torch.float64, device="cuda")
+    b = torch.ones(n, dtype=torch.float64, device="cuda")
+    c = torch.ones(n, dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        elwh.stream_triad(a, b, c)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        elwh.stream_triad(a, b, c)
+    e1.record()
+    torch.cuda.synchronize()
+    triad = 24 * n * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    e0.record()
+    for _ in range(reps):
+        a.copy_(b)
+    e1.record()
+    torch.cuda.synchronize()
+    copy = 16 * n * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b, c
+    torch.cuda.empty_cache()
+    return {"triad_GBs": round(triad, 1), "copy_GBs": round(copy, 1), "frac_of_peak": round(triad / HBM_PEAK_GBS, 4),
+            "arrays": "3 x 2 GiB FP64 (triad a = b + s c, 24 B per element); copy 2 x 2 GiB"}
+
+
+def time_to_tol(elwh, case, tol=1e-8, maxit=20000, **kw):
+    """Wall time of one solve to tol (context creation excluded)."""
+    import torch
+    ctx = elwh.context_from_case(case, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, info = ctx.solve(case.f, tol=tol, maxit=maxit, raise_on_fail=False)
+    el = time.perf_counter() - t0
+    ctx.close()
+    return {"seconds": round(el, 3), "iters": info["iters"], "status": info["status"],
+            "relres_fp64": info["relres_fp64"], "outer": info["outer"], "fp64_iters": info["fp64_iters"],
+            "nt": info["nt"]}
+
+
+def solves_2d_and_3d(elwh, inputs):
+    """Time to 1e-8 of the layered cube at 64^3, FP64 stepping against FP32
+    stepping with the compensated FP64 accumulator; and five CG iterations of
+    the 256^3 cube per precision (the full 256^3 solve needs on the order of
+    1e5 iterations: the count grows like omega^3 in 3-D, Sec. 5.5).  (The
+    1024^2 benchmark problem is not solved here: its A_h is near-singular,
+    a condition estimate of 1.6e11 from the CG Lanczos coefficients, and no
+    Krylov method reaches 1e-8 on it within 3e4 iterations.)"""
+    import torch
+    out = {}
+    c64 = inputs.layered_cube(n=64)
+    out["cube64"] = {"fp64": time_to_tol(elwh, c64), "fp32c": time_to_tol(elwh, c64, prec=elwh.FP32_STEP),
+                     "omega": c64.omega}
+    log(f"64^3 to 1e-8: {out['cube64']}")
+    c256 = inputs.layered_cube()
+    per = {}
+    for tag, kw in (("fp64", {}), ("fp32c", {"prec": elwh.FP32_STEP})):
+        ctx = elwh.context_from_case(c256, **kw)
+        ctx.solve(c256.f, tol=0.0, maxit=1, raise_on_fail=False)          # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info = ctx.solve(c256.f, tol=0.0, maxit=5, raise_on_fail=False)
+        el = time.perf_counter() - t0
+        per[tag] = {"seconds_for_5_iterations": round(el, 3), "napply": info["napply"],
+                    "relres_after_5": info["relres_fp64"]}
+        ctx.close()
+        torch.cuda.empty_cache()
+    out["cube256_iterations"] = per
+    log(f"256^3 five CG iterations: {per}")
+    return out
 
 
 def ragged_batch_solve(elwh, inputs, nprob=48, precisions=("fp64", "fp32")):
@@ -287,26 +410,63 @@ def ragged_batch_solve(elwh, inputs, nprob=48, precisions=("fp64", "fp32")):
     return out
 
 
-def time_to_tol(elwh, nprob=24, first_seed=4096):
-    """Wall time to relative residual 1e-8 on held-out warm-start problems
-    (warm-start workload, seeds first_seed..): plain FP64 from zero against the learned
-    start with FP32 stepping (and with FP64), one batch each."""
+def learned_start_comparison(elwh, nprob=512, first_seed=4096, batch=48, learned_fp64_batches=2):
+    """The time-to-1e-8 half of the metric on the warm-start workload: nprob
+    held-out problems (seeds first_seed..) in batches of `batch`, plain FP64
+    from zero against the learned start with FP32 stepping (every batch), and
+    the learned start with FP64 stepping on the first batches (the start's own
+    iteration reduction, apart from the precision's effect).  Both stop at an
+    FP64-recomputed relative residual of 1e-8."""
     from paper_2205_12344_amd import warmstart
-    net = elwh.WarmStartNet(max_batch=nprob, H=warmstart.N_CELLS, seed=0)
+    net = elwh.WarmStartNet(max_batch=batch, H=warmstart.N_CELLS, seed=0)
     meta = warmstart.load_weights(net)
-    r = warmstart.evaluate(net, list(range(first_seed, first_seed + nprob)), batch=nprob, tol=1e-8,
-                           zero_fp32=False)
+    r = warmstart.evaluate(net, list(range(first_seed, first_seed + nprob)), batch=batch, tol=1e-8,
+                           zero_fp32=False, learned_fp64_batches=learned_fp64_batches)
     net.close()
-    r["workload"] = (f"warm-start workload: {nprob} held-out problems (seeds {first_seed}..{first_seed + nprob - 1}), 256^2 "
-                     f"cells, omega ~ U[20, 60], 1-4 Gaussian sources of width U[2h, 6h]")
-    r["weights"] = {k: meta.get(k) for k in ("n_train", "epochs", "val_loss_after")}
+    r["workload"] = (f"warm-start workload: {nprob} held-out problems (seeds {first_seed}..{first_seed + nprob - 1}) "
+                     f"in batches of {batch}, 256^2 cells, omega ~ U[20, 60], 1-4 Gaussian sources of width U[2h, 6h]")
+    r["weights"] = {k: meta.get(k) for k in ("n_train", "epochs", "val_loss_after", "label_tol")}
     return r
 
 
-def counters_pass_3d(tz, prec):
-    """Dispatches for the HBM-traffic counters of the 3-D step kernel: the
+# Mapped 3-D grids, one step per launch: state u^n, u^{n-1} read, u^{n+1}
+# written (3 x 3 x 8), twelve coefficient arrays (a = c dt^2/(rho J),
+# lambda/J, mu/J and the nine metric values, 12 x 8), accumulator read and
+# written (2 x 3 x 8): 216 B; FP32 state and coefficients with the
+# compensated FP64 accumulator: 36 + 48 + 96 = 180 B
+BYTES_PER_LUP_MAPPED3 = {"f64": 216, "f32c": 180}
+MAPPED3_WORKLOAD = ("the partial toroidal shell of the 3-D curvilinear experiment (R = 4, 1 <= r <= 2, 0 <= theta, "
+                    "phi <= pi, free radial faces) on its smaller grid, 400 x 120 x 40 points, omega = 5.1234, "
+                    "constant lambda = 2, mu = rho = 1")
+
+
+def mapped3_rates(elwh, napply=2):
+    """Step-kernel rate of the mapped 3-D kernel on the toroidal shell."""
+    import numpy as np
+    from paper_2205_12344_amd.inputs import torus_section
+    x, y, z = torus_section(399, 119, 39)
+    one = np.ones(x.shape)
+    nodes = 398 * 118 * 40
+    out = {}
+    for tag, kw in (("f64", {}), ("f32c", {"prec": elwh.FP32_STEP, "compensated": 1})):
+        ctx = elwh.MappedContext3(x, y, z, one, 2 * one, one, 5.1234, bc=(0, 0, 0, 0, 1, 1), **kw)
+        p = kernel_rate(ctx, napply)
+        avg_s = p["step_ms"] * 1e-3 / max(p["nstep"], 1)
+        bb = BYTES_PER_LUP_MAPPED3[tag]
+        out[tag] = {"workload": MAPPED3_WORKLOAD, "nt": ctx.info()["nt"], "kernel": "curv3d_kernel",
+                    "step_kernel_us": round(1e6 * avg_s, 3), "glup_s_kernel": round(nodes / avg_s / 1e9, 3),
+                    "bytes_per_lup": bb, "achieved_GBs": round(bb * nodes / avg_s / 1e9, 1),
+                    "frac": round(bb * nodes / avg_s / 1e9 / HBM_PEAK_GBS, 4)}
+        log(f"mapped 3-D {tag}: {out[tag]}")
+        ctx.close()
+    return out
+
+
+def counters_pass_3d(rb, tz, prec):
+    """Dispatches for the HBM-traffic counters of the 3-D step kernels: the
     256 MiB calibration copy, then two A_h applications of the 256^3
-    layered-cube workload with the fixed tiling TZ, FP64 or FP32 compensated."""
+    layered-cube workload with the fixed tiling (RB, TZ) (RB 2, 4, 6: two
+    steps per launch; RB 1: single steps), FP64 or FP32 compensated."""
     import torch
     from paper_2205_12344_amd import elwh, inputs
     x = torch.ones(2 ** 25, dtype=torch.float64, device="cuda")
@@ -315,12 +475,12 @@ def counters_pass_3d(tz, prec):
     torch.cuda.synchronize()
     kw = {} if prec == "f64" else {"prec": elwh.FP32_STEP, "compensated": 1}
     ctx = elwh.context_from_case(inputs.layered_cube(), autotune=0, **kw)
-    ctx.set_tile(elwh.FP64 if prec == "f64" else elwh.FP32_STEP, 1, int(tz))
+    ctx.set_tile(elwh.FP64 if prec == "f64" else elwh.FP32_STEP, int(rb), int(tz))
     z = torch.zeros(ctx.field_shape, dtype=torch.float64, device="cuda")
     for _ in range(2):
         ctx.apply_A(z)
     torch.cuda.synchronize()
-    log(f"3-D counters pass done (TZ={tz}, {prec})")
+    log(f"3-D counters pass done (RB={rb}, TZ={tz}, {prec})")
 
 
 def counters_pass_twofield(tile):
@@ -373,33 +533,36 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--budget", type=float, default=540.0,
+                    help="seconds the whole run may take; optional parts that would not fit are skipped")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-3d", action="store_true", help="skip the 3-D 256^3 layered-cube step-kernel measurement")
-    ap.add_argument("--no-extra", action="store_true", help="skip the time-to-1e-8 (warm-start workload) measurement")
-    ap.add_argument("--batch", action="store_true",
-                    help="also solve the ragged batch (48 problems) in FP32 and FP64 (several minutes)")
+    ap.add_argument("--quick", action="store_true", help="headline, roofline and kernel rates only")
+    ap.add_argument("--cpu-worker", type=float, default=None, help=argparse.SUPPRESS)
     ap.add_argument("--batch-only", action="store_true",
-                    help="only the ragged-batch solve, FP64 (for kernel traces; see --batch-problems)")
+                    help="only the ragged-batch FP64 solve (for kernel traces)")
     ap.add_argument("--batch-problems", type=int, default=48,
-                    help="with --batch-only: solve the first N problems of the ragged batch")
+                    help="with --batch-only: the first N problems of the ragged batch")
     ap.add_argument("--counters", default=None, metavar="V,TY",
-                    help="counter-collection pass for rocprofv3 --pmc: a 256 MiB calibration copy, then 3 "
-                         "A_h applications of the benchmark workload with the fixed FP64 tiling V,TY")
+                    help="only the dispatches for the HBM-traffic counters (benchmark workload, FP64 tiling)")
     ap.add_argument("--counters-mapped", default=None, metavar="V,TY",
-                    help="the same counter pass on the mapped workload (curvilinear step kernel)")
-    ap.add_argument("--counters-3d", default=None, metavar="TZ,PREC",
-                    help="counter pass on the 3-D 256^3 workload (PREC f64 or f32c)")
+                    help="the same for the mapped-grid workload")
+    ap.add_argument("--counters-3d", default=None, metavar="RB,TZ,PREC",
+                    help="the same for the 256^3 layered cube (PREC f64 or f32c; RB 1 = single steps)")
     ap.add_argument("--counters-twofield", default=None, metavar="V,TY",
-                    help="counter pass of the two-field (impedance) step kernel on the 1024^2 absorbing workload")
+                    help="the same for the two-field (impedance) workload")
     ap.add_argument("--twofield-only", action="store_true",
-                    help="only the two-field (impedance) step-kernel measurement and its GMRES solve")
+                    help="only the two-field step-kernel measurement and its GMRES solve")
     ap.add_argument("--mapped-only", action="store_true",
                     help="only the mapped-grid step-kernel measurement (for kernel traces and counters)")
     args = ap.parse_args()
+    if args.cpu_worker is not None:
+        cpu_worker(args.cpu_worker)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the hot path runs on a single MI355X "
               "(sharding across GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
+    t_start = time.perf_counter()
 
     import torch
     from paper_2205_12344_amd import elwh, inputs
@@ -415,8 +578,8 @@ def main():
         counters_pass_twofield(args.counters_twofield)
         return
     if args.counters_3d:
-        tz, prec = args.counters_3d.split(",")
-        counters_pass_3d(tz, prec)
+        rb, tz, prec = args.counters_3d.split(",")
+        counters_pass_3d(rb, tz, prec)
         return
     if args.mapped_only:
         print(json.dumps(mapped_rates(elwh, inputs)))
@@ -490,54 +653,83 @@ def main():
         log(f"{tag}: {variants[tag]}")
         c2.close()
 
+    ceiling = triad_ceiling(elwh)
+    log(f"HBM ceiling: {ceiling}")
+
+    # 3-D step kernels on the 256^3 layered cube: the tiling the autotuner
+    # picks (two steps per launch where that is faster), and single steps
+    c3 = inputs.layered_cube()
+    n3 = unknown_nodes(c3)
+    for tag, kw in (("f64", {}), ("f32c", {"prec": elwh.FP32_STEP, "compensated": 1})):
+        for fuse3 in (2, 1):
+            ctx3 = elwh.context_from_case(c3, fuse=fuse3, **kw)
+            nt3 = ctx3.info()["nt"]
+            p = kernel_rate(ctx3, 2)
+            step_us = 1e3 * p["step_ms"] / max(p["nstep"], 1)      # per time step
+            rb, tz = ctx3.get_tile(elwh.FP32_STEP if tag != "f64" else elwh.FP64)
+            two = fuse3 >= 2 and rb >= 2
+            # the N_T - 1 steps after the half step: pair launches, and one
+            # single step when N_T - 1 is odd
+            pairs = (nt3 - 1) // 2 if two else 0
+            single = (nt3 - 1) - 2 * pairs
+            bytes_app = (pairs * BYTES_PER_LAUNCH_3D_K2[tag] + single * BYTES_PER_LUP[(3, tag, 1)]) * n3
+            bytes_per_lup = bytes_app / ((nt3 - 1) * n3)
+            gbs = bytes_per_lup * n3 / step_us / 1e3
+            key = "3d_" + tag + ("" if fuse3 >= 2 else "_single")
+            variants[key] = {"workload": c3.name, "nt": nt3, "tile_rows_planes": [rb, tz],
+                             "steps_per_launch": 2 if two else 1, "step_us": round(step_us, 2),
+                             "launches_per_application": pairs + single,
+                             "glup_s_kernel": round(n3 / step_us / 1e3, 3),
+                             "bytes_per_lup": round(bytes_per_lup, 2), "achieved_GBs": round(gbs, 1),
+                             "frac": round(gbs / HBM_PEAK_GBS, 4),
+                             "frac_of_triad": round(gbs / ceiling["triad_GBs"], 4),
+                             # lattice updates per second times the single-step
+                             # algorithmic bytes (144 B/LUP)
+                             "effective_frac": round(BYTES_PER_LUP[(3, tag, 1)] * n3 / step_us / 1e3
+                                                     / HBM_PEAK_GBS, 4),
+                             "traffic": read_traffic(f"step3d_{tag}_cube256", (rb, tz), "3d")}
+            log(f"3d {tag} fuse {fuse3}: tile {rb},{tz}, {step_us:.1f} us per step, {gbs:.0f} GB/s")
+            ctx3.close()
+    del c3
+    torch.cuda.empty_cache()
+
     for tag, v in mapped_rates(elwh, inputs).items():
         variants["mapped_" + tag] = v
-    variants["twofield_f64"] = twofield_rates(elwh, inputs, solve=not args.no_extra)
+    for tag, v in mapped3_rates(elwh).items():
+        variants["mapped3d_" + tag] = v
+    variants["twofield_f64"] = twofield_rates(elwh, inputs, solve=False)
+    torch.cuda.empty_cache()
 
-    if not args.no_3d:
-        c3 = inputs.layered_cube()
-        n3 = unknown_nodes(c3)
-        for tag, kw in (("f64", {}), ("f32c", {"prec": elwh.FP32_STEP, "compensated": 1})):
-            ctx3 = elwh.context_from_case(c3, **kw)
-            p = kernel_rate(ctx3, 2)
-            avg = p["step_ms"] / max(p["nstep"], 1)
-            bb = BYTES_PER_LUP[(3, tag, 1)]
-            t3 = ctx3.get_tile(elwh.FP32_STEP if tag != "f64" else elwh.FP64)
-            variants["3d_" + tag] = {"workload": c3.name, "nt": ctx3.info()["nt"], "tile": list(t3),
-                                     "step_kernel_us": round(1e3 * avg, 3),
-                                     "glup_s_kernel": round(n3 / avg / 1e6, 3), "bytes_per_lup": bb,
-                                     "achieved_GBs": round(bb * n3 / avg / 1e6, 1),
-                                     "frac": round(bb * n3 / avg / 1e6 / HBM_PEAK_GBS, 4)}
-            log(f"3d {tag}: step kernel {1e3 * avg:.1f} us, {variants['3d_' + tag]['achieved_GBs']} GB/s")
-            ctx3.close()
-
+    # optional parts, in order of importance, inside the time budget
     extra = {}
-    if not args.no_extra:
-        extra["time_to_1e-8"] = time_to_tol(elwh)
-        log(f"time to 1e-8: {json.dumps(extra['time_to_1e-8'])}")
-    if args.batch:
-        extra["ragged_batch48"] = ragged_batch_solve(elwh, inputs)
+    deadline = t_start + args.budget
+    cpu_s = 0.0 if args.no_cpu else 40.0       # what the CPU leg at the end needs
 
-    # practical HBM ceiling: a plain device-to-device copy of 2 GiB (beyond
-    # the 256 MB last-level cache)
-    x = torch.empty(2 ** 28, dtype=torch.float64, device="cuda").fill_(1.0)
-    y = torch.empty_like(x)
-    y.copy_(x)
+    def fits(name, est_s):
+        left = deadline - time.perf_counter() - cpu_s
+        if args.quick or left < est_s:
+            why = "--quick" if args.quick else f"time budget (needs about {est_s:.0f} s, {max(left, 0):.0f} s left)"
+            extra[name] = {"skipped": why}
+            log(f"{name}: skipped")
+            return False
+        return True
+
+    if fits("time_to_1e-8", 210):
+        extra["time_to_1e-8"] = learned_start_comparison(elwh)
+        log(f"time to 1e-8: {json.dumps(extra['time_to_1e-8'])}")
+    if fits("ragged_batch48", 165):
+        extra["ragged_batch48"] = ragged_batch_solve(elwh, inputs, precisions=("fp32",))
+    if fits("solves_to_1e-8", 60):
+        extra["solves_to_1e-8"] = solves_2d_and_3d(elwh, inputs)
+    if fits("ragged_batch48_fp64", 130):
+        extra.setdefault("ragged_batch48", {}).update(ragged_batch_solve(elwh, inputs, precisions=("fp64",)))
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(5):
-        y.copy_(x)
-    e1.record()
-    torch.cuda.synchronize()
-    copy_gbs = 5 * 2 * x.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9
-    del x, y
-    log(f"copy ceiling: {copy_gbs:.0f} GB/s")
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(case)
-        log(f"cpu oracle: {cpu['value'] / 1e6:.2f} MLUP/s ({cpu['sample']})")
+        cpu = cpu_baseline()
+        log(f"cpu oracle: {cpu['value'] / 1e6:.2f} MLUP/s on {cpu['cores']} cores, "
+            f"{cpu['one_core']['value'] / 1e6:.2f} MLUP/s on one ({cpu['sample']})")
 
     out = {
         "metric": METRIC, "value": value, "unit": "LUP/s", "n_gpus": 1, "steps": args.steps,
@@ -549,8 +741,8 @@ def main():
                                "per step",
                    "grid": list(case.n), "omega": case.omega, "nt": nt, "unknown_nodes": nodes,
                    "lup_per_step": lup_per_step},
-        "roofline": roofline, "cpu_baseline": cpu, "variants": variants, **extra,
-        "copy_ceiling_GBs": round(copy_gbs, 1),
+        "roofline": roofline, "cpu_baseline": cpu, "hbm_ceiling": ceiling, "variants": variants, **extra,
+        "bench_seconds": round(time.perf_counter() - t_start, 1),
     }
     print(json.dumps(out))
 
