@@ -153,7 +153,8 @@ def predict_x0(net, cases):
     return x0
 
 
-def evaluate(net, seeds, batch=48, tol=1e-8, maxit=4000, fp32_batches=None, zero_fp32=True):
+def evaluate(net, seeds, batch=48, tol=1e-8, maxit=4000, fp32_batches=None, zero_fp32=True,
+             learned_fp64_batches=None):
     """Held-out comparison on the same GPU, per batch of problems:
     plain_fp64    FP64 stepping, zero initial guess
     learned_fp64  FP64 stepping from the network's x0
@@ -161,7 +162,8 @@ def evaluate(net, seeds, batch=48, tol=1e-8, maxit=4000, fp32_batches=None, zero
     zero_fp32     FP32 stepping from zero (separates the precision's effect)
     The learned starts are rescaled by the solver (scale_x0) and their times
     include the feature maps and inference.  The FP32 runs cover the first
-    fp32_batches batches only (all when None).  Batch creation is excluded."""
+    fp32_batches batches only and the learned FP64 run the first
+    learned_fp64_batches (all when None).  Batch creation is excluded."""
     keys = ("plain_fp64", "learned_fp64", "learned_fp32", "zero_fp32")
     res = {k: {"seconds": 0.0, "iters": [], "relres": [], "status": [], "seeds": []} for k in keys}
     plain_batch_s = []
@@ -191,8 +193,9 @@ def evaluate(net, seeds, batch=48, tol=1e-8, maxit=4000, fp32_batches=None, zero
         x0 = predict_x0(net, cases)
         torch.cuda.synchronize()
         t_inf = time.perf_counter() - t0
-        _, inf, st = b64.solve(f, x0s=x0, tol=tol, maxit=maxit)
-        record("learned_fp64", b64, inf, st, t_inf, chunk)
+        if learned_fp64_batches is None or k // batch < learned_fp64_batches:
+            _, inf, st = b64.solve(f, x0s=x0, tol=tol, maxit=maxit)
+            record("learned_fp64", b64, inf, st, t_inf, chunk)
         b64.close()
         if fp32_batches is None or k // batch < fp32_batches:
             b32 = elwh.Batch(cases, prec=elwh.FP32_STEP, scale_x0=1)
@@ -211,9 +214,9 @@ def evaluate(net, seeds, batch=48, tol=1e-8, maxit=4000, fp32_batches=None, zero
         out[key] = {"n": len(r["iters"]), "seconds": r["seconds"], "mean_iters": float(it.mean()),
                     "median_iters": float(np.median(it)), "max_relres_fp64": float(np.max(r["relres"])),
                     "all_ok": all(s == "OK" for s in r["status"])}
-    z = np.array(res["plain_fp64"]["iters"], float)
     lf = np.array(res["learned_fp64"]["iters"], float)
-    out["iteration_reduction_learned_vs_zero_fp64"] = {"mean": float(np.mean(1 - lf / z)),
+    z = np.array(res["plain_fp64"]["iters"], float)[:lf.size]
+    out["iteration_reduction_learned_vs_zero_fp64"] = {"problems": int(lf.size), "mean": float(np.mean(1 - lf / z)),
                                                        "median": float(np.median(1 - lf / z))}
     if res["learned_fp32"]["iters"]:
         # wall time to tol on the problems the FP32 runs covered
@@ -222,7 +225,8 @@ def evaluate(net, seeds, batch=48, tol=1e-8, maxit=4000, fp32_batches=None, zero
             "problems": len(res["learned_fp32"]["iters"]), "plain_fp64_s": plain_s,
             "learned_fp32_s": res["learned_fp32"]["seconds"],
             "speedup_learned_fp32_vs_plain_fp64": plain_s / res["learned_fp32"]["seconds"]}
-    out["speedup_learned_fp64_vs_plain_fp64"] = res["plain_fp64"]["seconds"] / res["learned_fp64"]["seconds"]
+    nl = len(res["learned_fp64"]["status"])
+    out["speedup_learned_fp64_vs_plain_fp64"] = sum(plain_batch_s[:nl]) / res["learned_fp64"]["seconds"]
     return out
 
 
