@@ -462,6 +462,39 @@ def mapped3_rates(elwh, napply=2):
     return out
 
 
+TORUS_CASES = {1: (5.1234, (399, 119, 39), 1490), 2: (10.2468, (399, 119, 39), 2875),
+               3: (20.276, (1599, 479, 159), 3713)}
+
+
+def torus_shell_solve(elwh, case, tol=1e-5, maxit=20000):
+    """The toroidal-shell experiment of Sec. 5.11: the partial shell R = 4,
+    1 <= r <= 2, 0 <= theta, phi <= pi with free radial faces, lambda = 2,
+    mu = rho = 1, forced by sqrt(sigma^3)/20 (1, 1, 1) exp(-zeta^2),
+    sigma = 100 omega, zeta^2 = sigma |x - (4, 0.5, 1)|^2 / 2; the conjugate
+    residual method to a relative residual of 1e-5, as in the paper.  The
+    paper's iteration count (another discretisation) is context only."""
+    import numpy as np
+    import torch
+    from paper_2205_12344_amd.inputs import torus_section
+    om, cells, paper_iters = TORUS_CASES[case]
+    x, y, z = torus_section(*cells)
+    one = np.ones(x.shape)
+    sig = 100.0 * om
+    g = math.sqrt(sig ** 3) / 20.0 * np.exp(-0.5 * sig * ((x - 4.0) ** 2 + (y - 0.5) ** 2 + (z - 1.0) ** 2))
+    f = np.stack([g, g, g])
+    ctx = elwh.MappedContext3(x, y, z, one, 2.0 * one, one, om, bc=(0, 0, 0, 0, 1, 1), krylov=elwh.KRYLOV_CR)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, info = ctx.solve(f, tol=tol, maxit=maxit, raise_on_fail=False)
+    el = time.perf_counter() - t0
+    ctx.close()
+    out = {"case": case, "omega": om, "points": [c + 1 for c in cells], "tol": tol, "seconds": round(el, 2),
+           "iters": info["iters"], "status": info["status"], "relres_fp64": info["relres_fp64"], "nt": info["nt"],
+           "paper_iters_context": paper_iters}
+    log(f"toroidal shell case {case}: {out}")
+    return out
+
+
 def counters_pass_3d(rb, tz, prec):
     """Dispatches for the HBM-traffic counters of the 3-D step kernels: the
     256 MiB calibration copy, then two A_h applications of the 256^3
@@ -552,6 +585,8 @@ def main():
                     help="the same for the two-field (impedance) workload")
     ap.add_argument("--twofield-only", action="store_true",
                     help="only the two-field step-kernel measurement and its GMRES solve")
+    ap.add_argument("--torus-shell", default=None, metavar="CASES",
+                    help="only the toroidal-shell CR solves of Sec. 5.11 (cases 1, 2, 3, comma-separated)")
     ap.add_argument("--mapped-only", action="store_true",
                     help="only the mapped-grid step-kernel measurement (for kernel traces and counters)")
     args = ap.parse_args()
@@ -580,6 +615,9 @@ def main():
     if args.counters_3d:
         rb, tz, prec = args.counters_3d.split(",")
         counters_pass_3d(rb, tz, prec)
+        return
+    if args.torus_shell:
+        print(json.dumps([torus_shell_solve(elwh, int(k)) for k in args.torus_shell.split(",")]))
         return
     if args.mapped_only:
         print(json.dumps(mapped_rates(elwh, inputs)))

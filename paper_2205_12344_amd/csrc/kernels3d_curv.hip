@@ -20,7 +20,8 @@
 // Mapping: one thread per node, 64 consecutive q nodes per wavefront, one
 // (r, s) row per workgroup, XCD-banded; every neighbour value is loaded
 // (the 19-point footprint and the coefficients of the six face neighbours
-// are served by the caches), one time step per launch.
+// are served by the caches) in straight-line code, so a wavefront has its
+// whole footprint in flight at once; one time step per launch.
 #include "elwh_internal.h"
 #include "xcd.h"
 
@@ -52,27 +53,6 @@ __device__ __forceinline__ void acc_add_c3(double& hi, double& lo, double x, boo
     }
 }
 
-// Dh along one axis at index t (0..N): central inside, one-sided into the
-// domain on a free face, nothing on a Dirichlet face.
-__device__ __forceinline__ int dh_coef(int t, int N, double h, bool flo, bool fhi, int off[2], double cf[2]) {
-    if (t >= 1 && t <= N - 1) {
-        off[0] = 1; cf[0] = 0.5 / h;
-        off[1] = -1; cf[1] = -0.5 / h;
-        return 2;
-    }
-    if (t == 0 && flo) {
-        off[0] = 1; cf[0] = 1.0 / h;
-        off[1] = 0; cf[1] = -1.0 / h;
-        return 2;
-    }
-    if (t == N && fhi) {
-        off[0] = 0; cf[0] = 1.0 / h;
-        off[1] = -1; cf[1] = -1.0 / h;
-        return 2;
-    }
-    return 0;
-}
-
 template <typename T, typename U, int MODE, bool FORCE, bool COMP>
 __global__ __launch_bounds__(64) void curv3d_kernel(const U* __restrict__ u, const T* uprev, T* unext,
                                                    const double* __restrict__ xbase, T* __restrict__ u0out,
@@ -88,99 +68,137 @@ __global__ __launch_bounds__(64) void curv3d_kernel(const U* __restrict__ u, con
     const int k = A.klo + t / (nbx * nrr);
     if (i > A.nq - 1) return;
     const int64_t P = A.P, PS = A.PS, CS = A.CS;
-    const int64_t st[3] = {1, P, PS};
-    const int N[3] = {A.nq, A.nr, A.ns};
-    const double h[3] = {A.hq, A.hr, A.hs};
-    const int tp[3] = {i, j, k};
     const int64_t o = (int64_t)k * PS + (int64_t)j * P + i;
 
-    auto load3 = [&](int64_t q, T v[3]) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) v[c] = (T)u[q + c * CS];
+    // The gather below is straight-line code: every load is issued without a
+    // branch between it and the next, so a wavefront has its whole footprint
+    // in flight at once.  j and k are uniform over the wavefront (one (r, s)
+    // row per workgroup), so every test on them is a uniform branch; the two
+    // tests on i (the q neighbours' being unknowns) are masks.
+    const bool flo = A.free_lo && k == 0, fhi = A.free_hi && k == A.ns;
+    const bool on_free = flo || fhi;
+    const T wp = on_free ? (T)0.5 : (T)1;   // node weight of p, and of its in-plane edges
+    const T cq = (T)(0.5 / A.hq), cr = (T)(0.5 / A.hr);
+    // D_s at the plane of p: central, one-sided on a free face (the missing
+    // plane is read clamped, i.e. as the plane of p itself, and the
+    // coefficient doubles)
+    const T csp = on_free ? (T)(1.0 / A.hs) : (T)(0.5 / A.hs);
+    const int64_t sm = k > 0 ? -PS : 0, sp = k < A.ns ? PS : 0;
+    const T iq2 = (T)(1.0 / (A.hq * A.hq)), ir2 = (T)(1.0 / (A.hr * A.hr)), is2 = (T)(1.0 / (A.hs * A.hs));
+
+    struct V3 {
+        T x, y, z;
     };
-    // out = K^ab_n v
-    auto kv = [&](int64_t n, int a, int b, const T v[3], T out[3]) {
-        const T l = cl[n], m = cm[n];
-        T ga[3], gb[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            ga[c] = G.g[3 * a + c][n];
-            gb[c] = G.g[3 * b + c][n];
-        }
-        const T gbv = gb[0] * v[0] + gb[1] * v[1] + gb[2] * v[2];
-        const T gav = ga[0] * v[0] + ga[1] * v[1] + ga[2] * v[2];
-        const T gab = ga[0] * gb[0] + ga[1] * gb[1] + ga[2] * gb[2];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) out[c] = l * ga[c] * gbv + m * (gb[c] * gav + gab * v[c]);
+    struct Co {
+        T l, m;        // lambda / J, mu / J
+        V3 g[3];       // G_q, G_r, G_s
     };
-    auto unknown = [&](int ti, int tj, int tk) {
-        return ti >= 1 && ti <= A.nq - 1 && tj >= 1 && tj <= A.nr - 1 && tk >= A.klo && tk <= A.khi;
+    auto ld = [&](int64_t q) { return V3{(T)u[q], (T)u[q + CS], (T)u[q + 2 * CS]}; };
+    auto ldc = [&](int64_t q) {
+        Co c;
+        c.l = cl[q];
+        c.m = cm[q];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) c.g[a] = V3{G.g[3 * a][q], G.g[3 * a + 1][q], G.g[3 * a + 2][q]};
+        return c;
     };
-    auto wnode = [&](int tk) {
-        return ((A.free_lo && tk == 0) || (A.free_hi && tk == A.ns)) ? (T)0.5 : (T)1;
+    auto dot = [](const V3& p, const V3& q) { return p.x * q.x + p.y * q.y + p.z * q.z; };
+    auto sub = [](const V3& p, const V3& q) { return V3{p.x - q.x, p.y - q.y, p.z - q.z}; };
+    // K^ab v = (lambda/J) G_a (G_b . v) + (mu/J) (G_b (G_a . v) + (G_a . G_b) v)
+    auto kab = [&](const Co& c, int a, int b, const V3& v) {
+        const V3& ga = c.g[a];
+        const V3& gb = c.g[b];
+        const T gbv = dot(gb, v), gav = dot(ga, v), gab = dot(ga, gb);
+        return V3{c.l * ga.x * gbv + c.m * (gb.x * gav + gab * v.x), c.l * ga.y * gbv + c.m * (gb.y * gav + gab * v.y),
+                  c.l * ga.z * gbv + c.m * (gb.z * gav + gab * v.z)};
+    };
+    T Lx = 0, Ly = 0, Lz = 0;
+    auto acc3 = [&](T s_, const V3& v) {
+        Lx += s_ * v.x;
+        Ly += s_ * v.y;
+        Lz += s_ * v.z;
     };
 
-    T uc[3];
-    load3(o, uc);
-    T L[3] = {(T)0, (T)0, (T)0};
-    // edge terms
-    const bool in_free_s = (A.free_lo && k == 0) || (A.free_hi && k == A.ns);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const T we = (a < 2 && in_free_s) ? (T)0.5 : (T)1;
-        const T ih2 = (T)(1.0 / (h[a] * h[a]));
-#pragma unroll
-        for (int sg = -1; sg <= 1; sg += 2) {
-            const int tn = tp[a] + sg;
-            if (tn < 0 || tn > N[a]) continue;
-            const int64_t n = o + sg * st[a];
-            T un[3], d[3], k0[3], k1[3];
-            load3(n, un);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) d[c] = un[c] - uc[c];
-            kv(o, a, a, d, k0);
-            kv(n, a, a, d, k1);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) L[c] += we * (T)0.5 * ih2 * (k0[c] + k1[c]);
+    // footprint of u: p, its six face neighbours, its twelve in-plane diagonal neighbours
+    const V3 u0 = ld(o);
+    const V3 uqm = ld(o - 1), uqp = ld(o + 1), urm = ld(o - P), urp = ld(o + P), usm = ld(o + sm), usp = ld(o + sp);
+    const V3 qr_mm = ld(o - 1 - P), qr_mp = ld(o - 1 + P), qr_pm = ld(o + 1 - P), qr_pp = ld(o + 1 + P);
+    const V3 qs_mm = ld(o - 1 + sm), qs_mp = ld(o - 1 + sp), qs_pm = ld(o + 1 + sm), qs_pp = ld(o + 1 + sp);
+    const V3 rs_mm = ld(o - P + sm), rs_mp = ld(o - P + sp), rs_pm = ld(o + P + sm), rs_pp = ld(o + P + sp);
+    const V3 dqm = sub(uqm, u0), dqp = sub(uqp, u0), drm = sub(urm, u0), drp = sub(urp, u0);
+    const V3 dsm = sub(usm, u0), dsp = sub(usp, u0);   // 0 across a free face (clamped)
+
+    // edge terms, p's half: sum_a sum_+- w_e/2 K^aa_p (U_n - U_p) / h_a^2
+    {
+        const Co c = ldc(o);
+        const T eq = (T)0.5 * wp * iq2, er = (T)0.5 * wp * ir2, es = (T)0.5 * is2;
+        acc3(eq, kab(c, 0, 0, dqm));
+        acc3(eq, kab(c, 0, 0, dqp));
+        acc3(er, kab(c, 1, 1, drm));
+        acc3(er, kab(c, 1, 1, drp));
+        acc3(es, kab(c, 2, 2, dsm));
+        acc3(es, kab(c, 2, 2, dsp));
+        if (on_free) {
+            // the one-sided D_s at p itself: (D_s)_pp = -+1/h_s, weight 1/2
+            const T s0 = (T)(flo ? 0.5 / A.hs : -0.5 / A.hs);   // -(D_s)_pp w_p
+            acc3(s0, kab(c, 2, 0, V3{(uqp.x - uqm.x) * cq, (uqp.y - uqm.y) * cq, (uqp.z - uqm.z) * cq}));
+            acc3(s0, kab(c, 2, 1, V3{(urp.x - urm.x) * cr, (urp.y - urm.y) * cr, (urp.z - urm.z) * cr}));
         }
     }
-    // node terms over the ordered axis pairs
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-#pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            if (a == b) continue;
-            for (int da = -1; da <= 1; ++da) {
-                int tn[3] = {i, j, k};
-                tn[a] += da;
-                if (!unknown(tn[0], tn[1], tn[2])) continue;
-                int oa[2], ob[2];
-                double cfa[2], cfb[2];
-                const int na = dh_coef(tn[a], N[a], h[a], a == 2 && A.free_lo, a == 2 && A.free_hi, oa, cfa);
-                double cpa = 0.0;
-                for (int q = 0; q < na; ++q)
-                    if (tn[a] + oa[q] == tp[a]) cpa += cfa[q];
-                if (cpa == 0.0) continue;
-                const int64_t n = o + da * st[a];
-                const int nb = dh_coef(tn[b], N[b], h[b], b == 2 && A.free_lo, b == 2 && A.free_hi, ob, cfb);
-                T dbu[3] = {(T)0, (T)0, (T)0};
-                for (int q = 0; q < nb; ++q) {
-                    T um[3];
-                    load3(n + ob[q] * st[b], um);
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) dbu[c] += (T)cfb[q] * um[c];
-                }
-                T F[3];
-                kv(n, a, b, dbu, F);
-                const T s = (T)cpa * wnode(tn[2]);
-#pragma unroll
-                for (int c = 0; c < 3; ++c) L[c] -= s * F[c];
-            }
+    // q neighbours: the other half of their edge term, and their cross terms
+    // -(D_q)_np w_n K^qb_n (D_b U)_n, (D_q)_np = -+1/(2 h_q) for n = p +- e_q
+    {
+        const T mm = i - 1 >= 1 ? (T)1 : (T)0, mp = i + 1 <= A.nq - 1 ? (T)1 : (T)0;   // unknowns
+        const Co cm_ = ldc(o - 1), cp_ = ldc(o + 1);
+        const T eq = (T)0.5 * wp * iq2;
+        acc3(eq, kab(cm_, 0, 0, dqm));
+        acc3(eq, kab(cp_, 0, 0, dqp));
+        const T sm_ = -cq * wp * mm, sp_ = cq * wp * mp;   // -(D_q)_np w_n, masked
+        acc3(sm_, kab(cm_, 0, 1, V3{(qr_mp.x - qr_mm.x) * cr, (qr_mp.y - qr_mm.y) * cr, (qr_mp.z - qr_mm.z) * cr}));
+        acc3(sm_, kab(cm_, 0, 2, V3{(qs_mp.x - qs_mm.x) * csp, (qs_mp.y - qs_mm.y) * csp, (qs_mp.z - qs_mm.z) * csp}));
+        acc3(sp_, kab(cp_, 0, 1, V3{(qr_pp.x - qr_pm.x) * cr, (qr_pp.y - qr_pm.y) * cr, (qr_pp.z - qr_pm.z) * cr}));
+        acc3(sp_, kab(cp_, 0, 2, V3{(qs_pp.x - qs_pm.x) * csp, (qs_pp.y - qs_pm.y) * csp, (qs_pp.z - qs_pm.z) * csp}));
+    }
+    // r neighbours (uniform tests)
+    {
+        const Co cm_ = ldc(o - P), cp_ = ldc(o + P);
+        const T er = (T)0.5 * wp * ir2;
+        acc3(er, kab(cm_, 1, 1, drm));
+        acc3(er, kab(cp_, 1, 1, drp));
+        if (j - 1 >= 1) {
+            const T s_ = -cr * wp;
+            acc3(s_, kab(cm_, 1, 0, V3{(qr_pm.x - qr_mm.x) * cq, (qr_pm.y - qr_mm.y) * cq, (qr_pm.z - qr_mm.z) * cq}));
+            acc3(s_, kab(cm_, 1, 2, V3{(rs_mp.x - rs_mm.x) * csp, (rs_mp.y - rs_mm.y) * csp, (rs_mp.z - rs_mm.z) * csp}));
+        }
+        if (j + 1 <= A.nr - 1) {
+            const T s_ = cr * wp;
+            acc3(s_, kab(cp_, 1, 0, V3{(qr_pp.x - qr_mp.x) * cq, (qr_pp.y - qr_mp.y) * cq, (qr_pp.z - qr_mp.z) * cq}));
+            acc3(s_, kab(cp_, 1, 2, V3{(rs_pp.x - rs_pm.x) * csp, (rs_pp.y - rs_pm.y) * csp, (rs_pp.z - rs_pm.z) * csp}));
         }
     }
+    // s neighbours (uniform tests): across a free face there is none (its
+    // edge difference is 0 by the clamped read); -(D_s)_np w_n is +-1/(2 h_s)
+    // also where n lies on a free face (one-sided coefficient 1/h_s, weight 1/2)
+    {
+        const Co cm_ = ldc(o + sm), cp_ = ldc(o + sp);
+        const T es = (T)0.5 * is2;
+        acc3(es, kab(cm_, 2, 2, dsm));
+        acc3(es, kab(cp_, 2, 2, dsp));
+        const T cs2 = (T)(0.5 / A.hs);
+        if (k - 1 >= A.klo) {
+            acc3(-cs2, kab(cm_, 2, 0, V3{(qs_pm.x - qs_mm.x) * cq, (qs_pm.y - qs_mm.y) * cq, (qs_pm.z - qs_mm.z) * cq}));
+            acc3(-cs2, kab(cm_, 2, 1, V3{(rs_pm.x - rs_mm.x) * cr, (rs_pm.y - rs_mm.y) * cr, (rs_pm.z - rs_mm.z) * cr}));
+        }
+        if (k + 1 <= A.khi) {
+            acc3(cs2, kab(cp_, 2, 0, V3{(qs_pp.x - qs_mp.x) * cq, (qs_pp.y - qs_mp.y) * cq, (qs_pp.z - qs_mp.z) * cq}));
+            acc3(cs2, kab(cp_, 2, 1, V3{(rs_pp.x - rs_mp.x) * cr, (rs_pp.y - rs_mp.y) * cr, (rs_pp.z - rs_mp.z) * cr}));
+        }
+    }
+    const T uc[3] = {u0.x, u0.y, u0.z};
+    const T L[3] = {Lx, Ly, Lz};
 
     // L_h / w_p, then the corrected leapfrog with the trapezoid accumulation
-    const T iw = (T)1 / wnode(k);
+    const T iw = (T)1 / wp;
     const T a_ = ca[o];
 #pragma unroll
     for (int q = 0; q < 3; ++q) {

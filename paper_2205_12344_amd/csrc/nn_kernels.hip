@@ -24,8 +24,10 @@ __device__ __forceinline__ float bf2f(unsigned short b) { return __uint_as_float
 // C[z][m][n] = sum_{k in split z} A(m,k) B(k,n);  A(m,k) = TA ? A[k*lda+m] : A[m*lda+k],
 // B(k,n) = TB ? B[n*ldb+k] : B[k*ldb+n].  Block: 256 threads = 4 wavefronts in a
 // 2x2 arrangement of 32x32 output tiles (64x64 per block); K in chunks of 32
-// staged through LDS with k contiguous; v_mfma_f32_32x32x8bf16_1k per 8 k.
-typedef short short4_t __attribute__((ext_vector_type(4)));
+// staged through LDS with k contiguous; gfx950's v_mfma_f32_32x32x16_bf16 per
+// 16 k (lane l holds A(row l mod 32, k 8 (l / 32) .. + 7) and the same slice
+// of B; twice the k of the older 32x32x8 instruction per issue).
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float float16_t __attribute__((ext_vector_type(16)));
 
 constexpr int GT = 64, GK = 32, GKP = GK + 8;   // tile, k chunk, padded LDS row
@@ -79,17 +81,17 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K, int
         }
         __syncthreads();
 #pragma unroll
-        for (int ks = 0; ks < GK; ks += 8) {
-            const int kk = ks + (lane >> 5) * 4;
+        for (int ks = 0; ks < GK; ks += 16) {
+            const int kk = ks + (lane >> 5) * 8;   // <= 31 < GKP
             const unsigned short* ap = &As[wm * 32 + (lane & 31)][kk];
             const unsigned short* bp = &Bs[wn * 32 + (lane & 31)][kk];
-            short4_t a, b;
+            bf16x8_t a, b;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                a[e] = (short)ap[e];
-                b[e] = (short)bp[e];
+            for (int e = 0; e < 8; ++e) {
+                a[e] = __builtin_bit_cast(__bf16, ap[e]);
+                b[e] = __builtin_bit_cast(__bf16, bp[e]);
             }
-            acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
         }
         __syncthreads();
     }
