@@ -460,7 +460,7 @@ elwh_status elwh_profile_read(elwh_ctx* ctx, double* step_ms, int* nstep, double
  * and rows (4, 8, 16) marched per wavefront; 3-D: vec = y rows per
  * workgroup, one wavefront each, and rows = z planes marched per wavefront:
  * (1, 2, 4, 8) x (4, 8, 16, 32) for single-step launches (opts.fuse = 1),
- * (2, 4, 6) x (8, 16, 32) for two-step launches (fuse >= 2; the workgroup
+ * (2, 4, 6) x (8, 16, 32, 64) for two-step launches (fuse >= 2; the workgroup
  * adds two halo rows), where vec = 1 with rows 4 to 32 makes every step a
  * single-step launch (the FP64 choice on large cubes).  The tiling changes
  * speed only, never results.

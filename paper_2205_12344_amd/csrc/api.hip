@@ -1689,7 +1689,7 @@ elwh_status elwh_autotune(elwh_ctx* c, int prec, int reps, double* best_step_us)
     } else if (steps >= 2) {
         // two-step tilings, and single steps (RB 1) where they are faster
         for (int RB : {2, 4, 6})
-            for (int TZ : {8, 16, 32}) cands.push_back(Tile{RB, TZ});
+            for (int TZ : {8, 16, 32, 64}) cands.push_back(Tile{RB, TZ});
         for (int TZ : {16, 32}) cands.push_back(Tile{1, TZ});
     } else {
         for (int RB : {1, 2, 4})

@@ -323,12 +323,12 @@ __global__ __launch_bounds__(64 * (RB + 2)) void step3d_k2_kernel(const T* __res
 }
 
 // Tilings of a context that takes two steps per launch: RB = 2, 4, 6 rows
-// with TZ = 8, 16, 32 planes, or RB = 1, which has no two-step form and runs
+// with TZ = 8, 16, 32, 64 planes, or RB = 1, which has no two-step form and runs
 // every step as a single-step launch of TZ planes (on some grids, FP64 among
 // them, that is the faster choice).
 bool tile_valid_3d_k2(bool fp32, int RB, int TZ) {
     if (RB == 1) return tile_valid_3d(fp32, 1, TZ);
-    return (RB == 2 || RB == 4 || RB == 6) && (TZ == 8 || TZ == 16 || TZ == 32);
+    return (RB == 2 || RB == 4 || RB == 6) && (TZ == 8 || TZ == 16 || TZ == 32 || TZ == 64);
 }
 
 template <typename T>
@@ -360,9 +360,9 @@ void launch_step3d_k2(int RB, int TZ, bool force, bool comp, hipStream_t s, cons
         }                                                                                                       \
         return;                                                                                                 \
     }
-    ELWH_K2(2, 8) ELWH_K2(2, 16) ELWH_K2(2, 32)
-    ELWH_K2(4, 8) ELWH_K2(4, 16) ELWH_K2(4, 32)
-    ELWH_K2(6, 8) ELWH_K2(6, 16) ELWH_K2(6, 32)
+    ELWH_K2(2, 8) ELWH_K2(2, 16) ELWH_K2(2, 32) ELWH_K2(2, 64)
+    ELWH_K2(4, 8) ELWH_K2(4, 16) ELWH_K2(4, 32) ELWH_K2(4, 64)
+    ELWH_K2(6, 8) ELWH_K2(6, 16) ELWH_K2(6, 32) ELWH_K2(6, 64)
 #undef ELWH_K2
 }
 

@@ -495,7 +495,7 @@ def _tiles(dim, fp32, fuse=1):
         return [(v, ty) for v in vs for ty in (4, 8, 16)]
     if fuse >= 2:   # two-step 3-D launches: RB rows (plus two halo rows) x TZ planes;
         # RB 1 = single-step launches in a two-step context
-        return [(rb, tz) for rb in (2, 4, 6) for tz in (8, 16, 32)] + [(1, 16), (1, 32)]
+        return [(rb, tz) for rb in (2, 4, 6) for tz in (8, 16, 32, 64)] + [(1, 16), (1, 32)]
     return [(rb, tz) for rb in (1, 2, 4, 8) for tz in (4, 8, 16, 32)]
 
 
