@@ -43,6 +43,14 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+def _fp32_bound(nt):
+    """The FP32-stepping bound of one filter application (as in the parity
+    tests): one rounding per step, a random walk over N_T steps amplified by
+    N_T / (2 pi), twice, plus the rounding of the inputs."""
+    u32 = 2.0 ** -24
+    return 2.0 * u32 * np.sqrt(nt) * nt / (2 * np.pi) + 8.0 * u32
+
+
 def test_batch_fp64_matches_direct_and_oracle_cg(E):
     cases = _cases()
     bt = E.Batch(cases)
@@ -143,7 +151,8 @@ def test_ragged_batch48_full_size_matches_single_contexts(E):
     """The ragged batch at full size (48 problems, 256^2..1024^2 cells, omega in
     [10, 80], N_T up to ~3000) in one batch: two CG iterations of every
     problem equal those of the single-problem path (itself pinned to the
-    oracle), which runs other kernels (K-step launches)."""
+    oracle), which runs other kernels (K-step launches); and one iteration
+    of two of its problems equals the oracle's, in FP64 and FP32."""
     cases = inputs.ragged_batch()
     bt = E.Batch(cases)
     _say("ragged batch tiles", bt.stats())
@@ -160,6 +169,41 @@ def test_ragged_batch48_full_size_matches_single_contexts(E):
         ctx.close()
     _say("ragged batch: worst rel diff batch vs single", worst)
     assert worst <= 1e-12
+    # The oracle at full size, in the same batch launch (all 48 problems):
+    # one CG iteration from zero is x1 = alpha0 b with b = Pi_h f and
+    # alpha0 = (b, b)_M / (b, A_h b)_M.  Checked on the largest grid among
+    # the problems with omega >= 50 (1002^2; the oracle's cost grows like
+    # n^3 / omega) and on the longest period (N_T) among grids up to 400^2,
+    # FP64 and FP32
+    # stepping (FP32: alpha0 carries the FP32 error of one application of
+    # A_h, relative to the Rayleigh quotient (b, A_h b)_M / (b, b)_M).
+    nts = [i["nt"] for i in infos]
+    sel = [max((p for p in range(len(cases)) if cases[p].omega >= 50.0), key=lambda p: cases[p].n[0]),
+           max((p for p in range(len(cases)) if cases[p].n[0] <= 400), key=lambda p: nts[p])]
+    refs = {}
+    for p in sel:
+        c = cases[p]
+        prob = Problem(2, c.n, bc=c.bc)
+        op = Operator(prob, c.rho, c.lam, c.mu)
+        wh = S.WaveHoltz(op, c.omega)
+        assert wh.nt == nts[p]
+        b = wh.rhs(prob.gather(c.f))
+        Ab = wh.apply_A(b)
+        bb, bAb = float(np.dot(op.m * b, b)), float(np.dot(op.m * b, Ab))
+        refs[p] = (prob, (bb / bAb) * b, bAb / bb)
+    for prec in (E.FP64, E.FP32_STEP):
+        bt1 = bt if prec == E.FP64 else E.Batch(cases, prec=prec)
+        v1s, _, st1 = bt1.solve([c.f for c in cases], tol=0.0, maxit=1)
+        assert st1 == "OK"
+        for p in sel:
+            prob, ref, rq = refs[p]
+            err = _rel(prob.gather(v1s[p].cpu().numpy()), ref)
+            tol = 1e-11 if prec == E.FP64 else 2.0 * _fp32_bound(nts[p]) / rq
+            _say("ragged batch vs oracle", "fp64" if prec == E.FP64 else "fp32", "n", cases[p].n, "nt", nts[p],
+                 "rayleigh", rq, "err", err, "tol", tol)
+            assert err <= tol
+        if bt1 is not bt:
+            bt1.close()
 
 
 @pytest.mark.parametrize("prec", [0, 1])
