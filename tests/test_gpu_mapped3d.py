@@ -15,7 +15,7 @@ from oracle import direct, krylov
 from oracle import stepping as S
 from oracle.curvilinear3d import MappedOperator3D
 from paper_2205_12344_amd.inputs import torus_section
-from oracle.problem import DIRICHLET, FREE
+from oracle.problem import DIRICHLET, FREE, Problem
 
 pytestmark = pytest.mark.gpu
 
@@ -191,3 +191,32 @@ def test_rejections(E):
         E.MappedContext3(x, y, z, one, one, one, 1.0, bc=(0, 0, 1, 0, 0, 0))
     with pytest.raises(E.ElwhError):
         E.MappedContext3(x[:, :, ::-1].copy(), y[:, :, ::-1].copy(), z[:, :, ::-1].copy(), one, one, one, 1.0)
+
+
+def test_shell_at_benchmark_size_properties(E):
+    """The benchmark's shell (400 x 120 x 40 points, omega = 5.1234, free radial
+    faces, N_T = 245), in the launch configuration the benchmark times:
+    properties that hold at any size.  A_h is M-self-adjoint, so
+    (a, A_h b)_M = (A_h a, b)_M for random a, b (1e-11 relative to
+    ||a||_M ||A_h b||_M), and FP32 stepping stays within fp32_bound of the
+    FP64 application (the oracle runs the same map at small sizes above)."""
+    x, y, z = torus_section(399, 119, 39)
+    one = np.ones(x.shape)
+    bc = (0, 0, 0, 0, 1, 1)
+    ctx = E.MappedContext3(x, y, z, one, 2 * one, one, 5.1234, bc=bc)
+    nt = ctx.info()["nt"]
+    rng = np.random.default_rng(17)
+    prob = Problem(3, (399, 119, 39), bc=bc)   # (the grid's unknown mask)
+    a = rng.standard_normal(prob.field_shape) * prob.unknown_mask()
+    b = rng.standard_normal(prob.field_shape) * prob.unknown_mask()
+    Aa = ctx.apply_A(a)
+    Ab = ctx.apply_A(b)
+    lhs = ctx.dot_M(a, Ab)
+    rhs = ctx.dot_M(Aa, b)
+    scale = math.sqrt(ctx.dot_M(a, a) * ctx.dot_M(Ab, Ab))
+    _say("shell symmetry", nt, lhs, rhs, abs(lhs - rhs) / scale)
+    assert abs(lhs - rhs) <= 1e-11 * scale
+    c32 = E.MappedContext3(x, y, z, one, 2 * one, one, 5.1234, bc=bc, prec=E.FP32_STEP)
+    err = _rel(c32.apply_A(a).cpu().numpy(), Aa.cpu().numpy())
+    _say("shell fp32 vs fp64", err, "bound", fp32_bound(nt))
+    assert err <= fp32_bound(nt)
