@@ -462,6 +462,50 @@ def mapped3_rates(elwh, napply=2):
     return out
 
 
+def omega_sweep(elwh, inputs, ks=range(3, 41), tol=1e-8):
+    """The iterations-against-frequency experiment of Sec. 5.5 on the GPU: the
+    5 x 1 rectangle and the quarter and half annuli (outer arc 5), lambda = 2,
+    mu = rho = 1, Dirichlet sides, the standard explicit scheme, about 20
+    points per wavelength (n = 4 L omega + 1 cells along a side of length L),
+    a discrete point source of amplitude omega^2, omega = k + sqrt(2)/10,
+    conjugate residual to 1e-8.  The paper shows the counts only as a figure
+    and states that they grow like omega^2 in 2-D; the log-log slope of each
+    geometry's counts is reported beside them."""
+    import numpy as np
+    import torch
+    out = {"tol": tol, "scheme": "standard", "krylov": "CR", "rows": []}
+    for k in ks:
+        w = k + math.sqrt(2) / 10
+        row = {"k": k, "omega": round(w, 4)}
+        # rectangle, x along the long side
+        n = (int(20 * w + 1), int(4 * w + 1))
+        shape = (n[1] + 1, n[0] + 1)
+        one = np.ones(shape)
+        f = np.zeros((2,) + shape)
+        f[0, n[1] // 2, n[0] // 10] = w * w / ((5.0 / n[0]) * (1.0 / n[1]))
+        runs = [("rectangle", lambda: elwh.Context(2, n, one, 2 * one, one, w, (0, 0, 0, 0), length=(5.0, 1.0),
+                                                   scheme=elwh.SCHEME_STANDARD, krylov=elwh.KRYLOV_CR), f)]
+        for n_an, key in ((1, "quarter"), (2, "half")):
+            x, y, rho, lam, mu, wa, fa = inputs.sector_case(k, n_an)
+            runs.append((key, lambda x=x, y=y, rho=rho, lam=lam, mu=mu, wa=wa: elwh.MappedContext(
+                x, y, rho, lam, mu, wa, scheme=elwh.SCHEME_STANDARD, krylov=elwh.KRYLOV_CR), fa))
+        for key, make, fk in runs:
+            ctx = make()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, info = ctx.solve(fk, tol=tol, maxit=20000, raise_on_fail=False)
+            el = time.perf_counter() - t0
+            ctx.close()
+            row[key] = {"iters": info["iters"], "seconds": round(el, 3), "status": info["status"], "nt": info["nt"]}
+        out["rows"].append(row)
+        log(f"omega sweep k = {k}: " + ", ".join(f"{g} {row[g]['iters']}" for g in ("rectangle", "quarter", "half")))
+    for g in ("rectangle", "quarter", "half"):
+        ws = [r["omega"] for r in out["rows"] if r[g]["status"] == "OK"]
+        its = [r[g]["iters"] for r in out["rows"] if r[g]["status"] == "OK"]
+        out[f"slope_{g}"] = round(float(np.polyfit(np.log(ws), np.log(its), 1)[0]), 3) if len(ws) > 1 else None
+    return out
+
+
 TORUS_CASES = {1: (5.1234, (399, 119, 39), 1490), 2: (10.2468, (399, 119, 39), 2875),
                3: (20.276, (1599, 479, 159), 3713)}
 
@@ -585,6 +629,8 @@ def main():
                     help="the same for the two-field (impedance) workload")
     ap.add_argument("--twofield-only", action="store_true",
                     help="only the two-field step-kernel measurement and its GMRES solve")
+    ap.add_argument("--omega-sweep", action="store_true",
+                    help="only the iterations-against-frequency experiment of Sec. 5.5 (k = 3..40, three geometries)")
     ap.add_argument("--torus-shell", default=None, metavar="CASES",
                     help="only the toroidal-shell CR solves of Sec. 5.11 (cases 1, 2, 3, comma-separated)")
     ap.add_argument("--mapped-only", action="store_true",
@@ -615,6 +661,9 @@ def main():
     if args.counters_3d:
         rb, tz, prec = args.counters_3d.split(",")
         counters_pass_3d(rb, tz, prec)
+        return
+    if args.omega_sweep:
+        print(json.dumps(omega_sweep(elwh, inputs)))
         return
     if args.torus_shell:
         print(json.dumps([torus_shell_solve(elwh, int(k)) for k in args.torus_shell.split(",")]))
