@@ -135,6 +135,45 @@ def test_minres_fallback_after_cg_breakdown(E, prec):
         assert _rel(pr.gather(vv.cpu().numpy()), direct.solve(o, cc.omega, pr.gather(cc.f))) <= 1e-3
 
 
+@pytest.mark.parametrize("fallback", [1, 2])
+def test_fp64_first_phase_breakdown_finishes_by_fallback(E, fallback):
+    """FP32 stepping with opts.fp32_switch: on the near-resonant problem the FP64
+    CG of the first phase breaks down before it reaches the switch residual;
+    the solve then finishes with the conjugate residual method or MINRES
+    (cr_fallback 1 / 2) from that iterate and meets tol on the FP64 residual,
+    alone and inside a batch."""
+    c = _near_resonant()
+    prob, op, wh = _case_oracle(c)
+    xs = direct.solve(op, c.omega, prob.gather(c.f))
+    ctx = E.context_from_case(c, prec=E.FP32_STEP, fp32_switch=1e-6, cr_fallback=fallback)
+    v, info = ctx.solve(c.f, tol=1e-8, maxit=4000)
+    _say("fp64-first breakdown", fallback, info)
+    assert info["status"] == "OK" and info["cr_iters"] > 0 and info["fp64_iters"] > 0
+    assert info["relres_fp64"] <= 1e-8
+    assert _rel(prob.gather(v.cpu().numpy()), xs) <= 1e-3   # condition ~1e6, as above
+    cases = [c, inputs.random_problem_2d(40, 9.5, seed=201)]
+    bt = E.Batch(cases, prec=E.FP32_STEP, fp32_switch=1e-6, cr_fallback=fallback)
+    vs, infos, status = bt.solve([k.f for k in cases], tol=1e-8, maxit=4000)
+    _say("batched fp64-first breakdown", fallback, status, [(i["iters"], i["fp64_iters"], i["cr_iters"],
+                                                             i["relres_fp64"]) for i in infos])
+    assert status == "OK" and infos[0]["cr_iters"] > 0
+    for ii in infos:
+        assert ii["relres_fp64"] <= 1e-8
+
+
+def test_fp32_stagnation_fallback_meets_the_true_residual_in_3d(E):
+    """The 64^3 layered cube with FP32 stepping: FP32 segments stagnate, the
+    FP64 CG that continues breaks down (A_h is slightly indefinite here) and
+    the conjugate residual method finishes.  Every stage is held to the true
+    residual: the CR fallback once stopped on its own recurrence at 1e-8 with
+    b - A_h x at 5.5e-8."""
+    c = inputs.layered_cube(n=64)
+    ctx = E.context_from_case(c, prec=E.FP32_STEP)
+    _, info = ctx.solve(c.f, tol=1e-8, maxit=20000)
+    _say("cube64 fp32", info)
+    assert info["status"] == "OK" and info["relres_fp64"] <= 1e-8 and info["fp64_iters"] > 0
+
+
 # ------------------------------------------------ modified trapezoid weights --
 
 @pytest.mark.parametrize("fuse", [1, 2, 3, 4])
