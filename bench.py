@@ -41,33 +41,33 @@ METRIC = "elastic lattice updates/s (% HBM roofline); time-to-1e-8 residual lear
 # Single-step kernel (fuse = 1; the 3-D kernel):
 #   FP64: read u^n (2x8), u^{n-1} (2x8), a, lambda, mu (3x8), acc (2x8);
 #         write u^{n+1} (2x8), acc (2x8)                                  = 104
-#   FP32 state, compensated FP64 accumulator: state 3x2x4, coefficients
-#         3x4, acc hi+lo read and written 4x2x8                           = 100
+#   FP32 state, compensated FP64 accumulator (FP64 hi, FP32 lo): state
+#         3x2x4, coefficients 3x4, acc hi+lo read and written 2x2x(8+4)    = 84
 #   FP32 state, plain FP64 accumulator: 24 + 12 + 32                      = 68
 #   3-D: three components; FP64 3x3x8 + 3x8 + 2x3x8 = 144; FP32
-#         compensated 36 + 12 + 96 = 144; FP32 plain 36 + 12 + 48 = 96
+#         compensated 36 + 12 + 72 = 120; FP32 plain 36 + 12 + 48 = 96
 # K-step kernel (2-D, fuse = K = 2..4), per node and launch (K lattice
 # updates), independent of K:
 #   FP64: read u^n, u^{n-1} (2x2x8), a, lambda, mu (3x8), acc (2x8);
 #         write u^{n+K-1}, u^{n+K} (2x2x8), acc (2x8) = 120, i.e. 120/K per LUP
-#   FP32 compensated: state 4x2x4 + 3x4 + acc hi+lo 4x2x8 = 108
+#   FP32 compensated: state 4x2x4 + 3x4 + acc hi+lo 2x2x(8+4) = 92
 #   FP32 plain accumulator: 32 + 12 + 32 = 76
 BYTES_PER_LUP = {
-    (2, "f64", 1): 104, (2, "f32c", 1): 100, (2, "f32", 1): 68,
-    (3, "f64", 1): 144, (3, "f32c", 1): 144, (3, "f32", 1): 96,
+    (2, "f64", 1): 104, (2, "f32c", 1): 84, (2, "f32", 1): 68,
+    (3, "f64", 1): 144, (3, "f32c", 1): 120, (3, "f32", 1): 96,
 }
-BYTES_PER_MULTI_LAUNCH = {"f64": 120, "f32c": 108, "f32": 76}
+BYTES_PER_MULTI_LAUNCH = {"f64": 120, "f32c": 92, "f32": 76}
 # 3-D two-step kernel, per node and launch (two lattice updates): read u^n,
 # u^{n-1} (2x3x8), a, lambda, mu (3x8), acc (3x8); write u^{n+1}, u^{n+2}
 # (2x3x8), acc (3x8) = 168 (FP64); FP32 state with the compensated FP64
-# accumulator: 2x12 + 12 + acc hi+lo 48 read, 2x12 + 48 written = 156
-BYTES_PER_LAUNCH_3D_K2 = {"f64": 168, "f32c": 156}
+# accumulator: 2x12 + 12 + acc hi+lo 36 read, 2x12 + 36 written = 132
+BYTES_PER_LAUNCH_3D_K2 = {"f64": 168, "f32c": 132}
 # Mapped (curvilinear) 2-D grids, single-step kernel: the three coefficient
 # arrays become seven (a = c dt^2/(rho J), lambda/J, mu/J and the metric
 # vectors J grad q, J grad r):
 #   FP64: state 3x2x8 + 7x8 + acc 2x2x8 = 136; FP32 compensated:
-#   24 + 28 + 64 = 116; FP32 plain accumulator: 24 + 28 + 32 = 84
-BYTES_PER_LUP_MAPPED = {"f64": 136, "f32c": 116, "f32": 84}
+#   24 + 28 + 48 = 100; FP32 plain accumulator: 24 + 28 + 32 = 84
+BYTES_PER_LUP_MAPPED = {"f64": 136, "f32c": 100, "f32": 84}
 # Two-field step with impedance faces (FP64, one step per launch): state u^n,
 # u^{n-1} read and u^{n+1} written (3 x 2 x 8), a, lambda, mu (3 x 8), the
 # displacement and velocity accumulators read and written (2 x 2 x 2 x 8)
@@ -433,8 +433,8 @@ def learned_start_comparison(elwh, nprob=512, first_seed=4096, batch=48, learned
 # written (3 x 3 x 8), twelve coefficient arrays (a = c dt^2/(rho J),
 # lambda/J, mu/J and the nine metric values, 12 x 8), accumulator read and
 # written (2 x 3 x 8): 216 B; FP32 state and coefficients with the
-# compensated FP64 accumulator: 36 + 48 + 96 = 180 B
-BYTES_PER_LUP_MAPPED3 = {"f64": 216, "f32c": 180}
+# compensated FP64 accumulator: 36 + 48 + 72 = 156 B
+BYTES_PER_LUP_MAPPED3 = {"f64": 216, "f32c": 156}
 MAPPED3_WORKLOAD = ("the partial toroidal shell of the 3-D curvilinear experiment (R = 4, 1 <= r <= 2, 0 <= theta, "
                     "phi <= pi, free radial faces) on its smaller grid, 400 x 120 x 40 points, omega = 5.1234, "
                     "constant lambda = 2, mu = rho = 1")
@@ -723,7 +723,8 @@ def main():
     for k in (1, 2, 3, 4):
         if k != fuse:
             vlist.append((f"f64_fuse{k}", "f64", {"fuse": k}))
-    vlist.append(("f32c_fuse1", "f32c", {"prec": elwh.FP32_STEP, "compensated": 1, "fuse": 1}))
+    for k in (1, 3, 4):
+        vlist.append((f"f32c_fuse{k}", "f32c", {"prec": elwh.FP32_STEP, "compensated": 1, "fuse": k}))
     for tag, prec, kw in vlist:
         fuse_v = kw.setdefault("fuse", fuse)
         c2 = elwh.context_from_case(case, **kw)

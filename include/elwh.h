@@ -96,7 +96,9 @@ typedef struct {
                           ELWH_ERR_ARG) */
     int gmres_m;       /* GMRES restart length (default 30) */
     int scheme;        /* ELWH_SCHEME_CORRECTED (default, Sec. 4.3), _STANDARD or _MODIFIED */
-    int compensated;   /* FP32 path: Neumaier-compensated FP64 accumulator (default 1) */
+    int compensated;   /* FP32 path: TwoSum-compensated FP64 accumulator, the
+                          compensation word held in FP32 between launches
+                          (default 1) */
     double inner_tol;  /* FP32 path: reduction of the recursive residual between two
                           FP64 residual replacements (default 1e-2) */
     int max_outer;     /* FP32 path: maximum residual replacements (default 50) */

@@ -91,7 +91,7 @@ struct BProb2D {
     void* s[4];               // state buffers (FP64 or FP32)
     const double* src;        // u^0 of the application
     double* out;              // accumulator = result of the application (q in CG)
-    double* lo;               // compensation
+    float* lo;               // compensation
     const void *ca, *cl, *cm, *f;
     const double* m;          // M weights
     double *cx, *cr, *cp;     // CG iterate, residual, direction
@@ -151,7 +151,8 @@ struct elwh_ctx {
     // (four for 2-D: the step-pair kernel writes two new levels beside the two it reads)
     double *s64[4] = {nullptr, nullptr, nullptr, nullptr};
     float *s32[4] = {nullptr, nullptr, nullptr, nullptr};
-    double *acc = nullptr, *acc_lo = nullptr;
+    double* acc = nullptr;
+    float* acc_lo = nullptr;       // FP32 compensation word of the accumulator
     // forcing (internal layout) in FP64 and FP32
     double* f64 = nullptr;
     float* f32 = nullptr;
@@ -253,7 +254,7 @@ bool tile_valid_3d_k2(bool fp32, int RB, int TZ);
 struct Args3D;
 template <typename T>
 void launch_step3d_k2(int RB, int TZ, bool force, bool comp, hipStream_t s, const T* u, const T* uprev, T* outA,
-                      T* outB, double* acc, double* acclo, const T* ca, const T* cl, const T* cm, const T* f,
+                      T* outB, double* acc, float* acclo, const T* ca, const T* cl, const T* cm, const T* f,
                       const Args3D& A);
 bool tile_valid_curv(bool fp32, int V, int TY);
 bool tile_valid_curv3(bool fp32, int V, int TY);
@@ -281,7 +282,7 @@ void launch_scale_field(const Layout& L, double* dst, const double* w, int ncomp
 // step n+s-1.
 template <typename T>
 void launch_multi2d(int K, int V, int TY, bool force, bool comp, hipStream_t s, int nrows, const T* u,
-                    const T* uprev, T* outA, T* outB, double* acc, double* acclo, const T* ca, const T* cl,
+                    const T* uprev, T* outA, T* outB, double* acc, float* acclo, const T* ca, const T* cl,
                     const T* cm, const T* f, const Args2D& A);
 
 // ---- kernels (kernels2d.hip / kernels3d.hip / blas.hip) --------------------

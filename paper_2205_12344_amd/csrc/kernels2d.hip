@@ -19,7 +19,9 @@
 // nodes (one vector load per array and row), so a wavefront covers 64 V
 // columns of which the outer halo columns are loaded but not computed
 // (W = 62, 126, 252 computed columns for V = 1, 2, 4).  The wavefront marches
-// TY rows up in y: rows j-1, j, j+1 live in registers and roll, the loads of
+// TY rows in y (up in even row chunks, down in odd ones, so that two
+// neighbouring chunks read their shared rows together): rows j-1, j, j+1
+// live in registers and roll, the loads of
 // row j+2 and of the centre-row arrays of row j+1 are issued one iteration
 // ahead, and x neighbours across lanes come from DPP wavefront shifts.
 // Every array element is read from memory once per row visit.
@@ -32,7 +34,7 @@ struct Centre {
     T a[V];
     T up[V], vp[V];             // u^{n-1} (MODE 0)
     double hu[V], hv[V];        // accumulator (MODE 0) or base x (MODE 1)
-    double lu[V], lv[V];        // compensation (MODE 0, COMP)
+    float lu[V], lv[V];         // compensation (MODE 0, COMP), widened where it is used
     T fu[V], fv[V];             // forcing
 };
 
@@ -42,7 +44,7 @@ struct Centre {
 template <typename T, typename U, int V, int TY, int MODE, bool FORCE, bool COMP>
 __device__ __forceinline__ void step2d_body(int bx, int by, const U* __restrict__ u, const T* uprev, T* unext,
                                             const double* __restrict__ xbase, T* __restrict__ u0out,
-                                            double* __restrict__ acc, double* __restrict__ acclo,
+                                            double* __restrict__ acc, float* __restrict__ acclo,
                                             const T* __restrict__ ca, const T* __restrict__ cl,
                                             const T* __restrict__ cm, const T* __restrict__ f, const Args2D& A) {
     constexpr int W = Cols<V>::W;
@@ -55,11 +57,20 @@ __device__ __forceinline__ void step2d_body(int bx, int by, const U* __restrict_
     const int j1 = min(j0 + TY - 1, A.jhi);
     const int P = (int)A.P;
     const int64_t CS = A.CS;
-    const T cxx2 = (T)A.cxx2, cyy2 = (T)A.cyy2, cxy = (T)A.cxy, cyyf = (T)A.cyyf, cfx = (T)A.cfx;
+    // Mirrored march: odd row chunks march downwards, so that neighbouring
+    // chunks read the rows they share at the same time and the second read
+    // finds them in L2.  Virtual row v is physical row jb + dir * v; mirrored,
+    // the stencil exchanges the rows below and above, i.e. negates the
+    // mixed-derivative coefficients and swaps the two free-row kinds.
+    const int dir = (by & 1) ? -1 : 1;
+    const int jb = dir > 0 ? 0 : j0 + j1;
+    auto phys = [&](int v) { return jb + dir * v; };
+    const T cxx2 = (T)A.cxx2, cyy2 = (T)A.cyy2, cxy = (T)(dir * A.cxy), cyyf = (T)A.cyyf, cfx = (T)(dir * A.cfx);
     const T two = (T)2;
     const int ilo = max(c0 + 1, 1), ihi = min(c0 + W, A.nx - 1);   // computed column range
 
-    auto load_raw = [&](int j, RawRow<T, V>& r) {
+    auto load_raw = [&](int jv, RawRow<T, V>& r) {
+        const int j = phys(jv);
         if (colv && j >= 0 && j <= A.ny) {
             const int64_t o = (int64_t)j * P + col;
             vload<U, T, V>(u + o, r.u);
@@ -87,8 +98,9 @@ __device__ __forceinline__ void step2d_body(int bx, int by, const U* __restrict_
         o.vR = lane_from_right(r.v[0]);
     };
     using Ctr = Centre<T, V, COMP, FORCE, MODE>;
-    auto load_ctr = [&](int j, Ctr& c) {
-        if (colv && j <= A.jhi) {
+    auto load_ctr = [&](int jv, Ctr& c) {
+        const int j = phys(jv);
+        if (colv && j >= A.jlo && j <= A.jhi) {
             const int64_t o = (int64_t)j * P + col;
             vload<T, T, V>(ca + o, c.a);
             if constexpr (MODE == 0) {
@@ -97,8 +109,8 @@ __device__ __forceinline__ void step2d_body(int bx, int by, const U* __restrict_
                 vload<double, double, V>(acc + o, c.hu);
                 vload<double, double, V>(acc + o + CS, c.hv);
                 if constexpr (COMP) {
-                    vload<double, double, V>(acclo + o, c.lu);
-                    vload<double, double, V>(acclo + o + CS, c.lv);
+                    vload<float, float, V>(acclo + o, c.lu);
+                    vload<float, float, V>(acclo + o + CS, c.lv);
                 }
             } else {
                 if (xbase) {
@@ -140,8 +152,10 @@ __device__ __forceinline__ void step2d_body(int bx, int by, const U* __restrict_
         finish(rawN, N);
         const T lamL0 = lane_from_left(C.l[V - 1]), lamR0 = lane_from_right(C.l[0]);
         const T muL0 = lane_from_left(C.m[V - 1]), muR0 = lane_from_right(C.m[0]);
-        const int kind = (A.free_hi && j == A.ny) ? 1 : ((A.free_lo && j == 0) ? 2 : 0);
-        const int64_t o = (int64_t)j * P + col;
+        const int pj = phys(j);
+        const int kind0 = (A.free_hi && pj == A.ny) ? 1 : ((A.free_lo && pj == 0) ? 2 : 0);
+        const int kind = dir > 0 || kind0 == 0 ? kind0 : 3 - kind0;
+        const int64_t o = (int64_t)pj * P + col;
 
 #pragma unroll
         for (int k = 0; k < V; ++k) {
@@ -191,8 +205,8 @@ __device__ __forceinline__ void step2d_body(int bx, int by, const U* __restrict_
                 acc[o + k] = hu;
                 acc[o + k + CS] = hv;
                 if constexpr (COMP) {
-                    acclo[o + k] = lu;
-                    acclo[o + k + CS] = lv;
+                    acclo[o + k] = (float)lu;
+                    acclo[o + k + CS] = (float)lv;
                 }
             }
         }
@@ -208,7 +222,7 @@ __device__ __forceinline__ void step2d_body(int bx, int by, const U* __restrict_
 template <typename T, typename U, int V, int TY, int MODE, bool FORCE, bool COMP>
 __global__ __launch_bounds__(64) void step2d_kernel(const U* __restrict__ u, const T* uprev, T* unext,
                                                    const double* __restrict__ xbase, T* __restrict__ u0out,
-                                                   double* __restrict__ acc, double* __restrict__ acclo,
+                                                   double* __restrict__ acc, float* __restrict__ acclo,
                                                    const T* __restrict__ ca, const T* __restrict__ cl,
                                                    const T* __restrict__ cm, const T* __restrict__ f, Args2D A) {
     const int nbx = (A.nx - 1 + Cols<V>::W - 1) / Cols<V>::W;
@@ -223,7 +237,7 @@ __global__ __launch_bounds__(64) void step2d_kernel(const U* __restrict__ u, con
 
 template <typename T, typename U, int V, int TY, int MODE>
 static void launch_t(bool force, bool comp, dim3 grid, hipStream_t s, const U* u, const T* uprev, T* unext,
-                     const double* xbase, T* u0out, double* acc, double* acclo, const T* ca, const T* cl,
+                     const double* xbase, T* u0out, double* acc, float* acclo, const T* ca, const T* cl,
                      const T* cm, const T* f, const Args2D& A) {
 #define ELWH_L2(F, CMP)                                                                                  \
     hipLaunchKernelGGL((step2d_kernel<T, U, V, TY, MODE, F, CMP>), grid, dim3(64), 0, s, u, uprev, unext, \
@@ -239,7 +253,7 @@ static void launch_t(bool force, bool comp, dim3 grid, hipStream_t s, const U* u
 // Dispatch over the tunable (V, TY) pairs.
 template <typename T, typename U, int MODE>
 static void launch_v(int V, int TY, bool force, bool comp, int nx, int nrows, hipStream_t s, const U* u,
-                     const T* uprev, T* unext, const double* xbase, T* u0out, double* acc, double* acclo,
+                     const T* uprev, T* unext, const double* xbase, T* u0out, double* acc, float* acclo,
                      const T* ca, const T* cl, const T* cm, const T* f, const Args2D& A) {
     auto grid_for = [&](int W, int ty) {
         return dim3((unsigned)xcd_grid(((nx - 1 + W - 1) / W) * ((nrows + ty - 1) / ty)), 1, 1);
@@ -400,7 +414,7 @@ static void free_pair(T* const* bufs, const void* a, const void* b, T** x, T** y
 // caller's vector (never written).
 template <typename T>
 static void run_steps_2d(elwh_ctx* c, Args2D A, int nrows, Tile t, bool with_force, bool comp, double sgn,
-                         const T* prev, T* cur, T* const* bufs, double* acc, double* lo, const T* ca, const T* cl,
+                         const T* prev, T* cur, T* const* bufs, double* acc, float* lo, const T* ca, const T* cl,
                          const T* cm, const T* f, int nsteps) {
     hipStream_t s = c->stream;
     int n = 1;
@@ -448,7 +462,7 @@ void run_filter_2d(elwh_ctx* c, const double* x, bool with_force, bool amode, bo
     const double sgn = amode ? -1.0 : 1.0;
     const bool comp = fp32 && c->opts.compensated;
     double* acc = out;
-    double* lo = c->acc_lo;
+    float* lo = c->acc_lo;
     A.w0 = sgn * c->w[0];
     A.w = sgn * c->w[1];
     A.fc = c->cosn[0];

@@ -62,7 +62,7 @@ struct CCtr {
     T a[V];
     T up[V], vp[V];
     double hu[V], hv[V];
-    double lu[V], lv[V];
+    float lu[V], lv[V];   // compensation, widened where it is used
     T fu[V], fv[V];
 };
 
@@ -78,7 +78,7 @@ __device__ __forceinline__ T at_right(const T (&x)[V], int k, T edge) {
 template <typename T, typename U, int V, int TY, int MODE, bool FORCE, bool COMP>
 __device__ __forceinline__ void curv2d_body(int bx, int by, const U* __restrict__ u, const T* uprev, T* unext,
                                             const double* __restrict__ xbase, T* __restrict__ u0out,
-                                            double* __restrict__ acc, double* __restrict__ acclo,
+                                            double* __restrict__ acc, float* __restrict__ acclo,
                                             const T* __restrict__ ca, const T* __restrict__ cl,
                                             const T* __restrict__ cm, const T* __restrict__ g0,
                                             const T* __restrict__ g1, const T* __restrict__ g2,
@@ -163,8 +163,8 @@ __device__ __forceinline__ void curv2d_body(int bx, int by, const U* __restrict_
                 vload<double, double, V>(acc + o, c.hu);
                 vload<double, double, V>(acc + o + CS, c.hv);
                 if constexpr (COMP) {
-                    vload<double, double, V>(acclo + o, c.lu);
-                    vload<double, double, V>(acclo + o + CS, c.lv);
+                    vload<float, float, V>(acclo + o, c.lu);
+                    vload<float, float, V>(acclo + o + CS, c.lv);
                 }
             } else {
                 if (xbase) {
@@ -302,8 +302,8 @@ __device__ __forceinline__ void curv2d_body(int bx, int by, const U* __restrict_
                 acc[o + k] = hu;
                 acc[o + k + CS] = hv;
                 if constexpr (COMP) {
-                    acclo[o + k] = lu;
-                    acclo[o + k + CS] = lv;
+                    acclo[o + k] = (float)lu;
+                    acclo[o + k + CS] = (float)lv;
                 }
             }
         }
@@ -323,7 +323,7 @@ struct Metric4 {
 template <typename T, typename U, int V, int TY, int MODE, bool FORCE, bool COMP>
 __global__ __launch_bounds__(64) void curv2d_kernel(const U* __restrict__ u, const T* uprev, T* unext,
                                                    const double* __restrict__ xbase, T* __restrict__ u0out,
-                                                   double* __restrict__ acc, double* __restrict__ acclo,
+                                                   double* __restrict__ acc, float* __restrict__ acclo,
                                                    const T* __restrict__ ca, const T* __restrict__ cl,
                                                    const T* __restrict__ cm, Metric4 g, const T* __restrict__ f,
                                                    Args2D A) {
@@ -339,7 +339,7 @@ __global__ __launch_bounds__(64) void curv2d_kernel(const U* __restrict__ u, con
 
 template <typename T, typename U, int V, int TY, int MODE>
 void curv_launch_t(bool force, bool comp, dim3 grid, hipStream_t s, const U* u, const T* uprev, T* unext,
-                   const double* xbase, T* u0out, double* acc, double* acclo, const T* ca, const T* cl, const T* cm,
+                   const double* xbase, T* u0out, double* acc, float* acclo, const T* ca, const T* cl, const T* cm,
                    const Metric4& g, const T* f, const Args2D& A) {
 #define ELWH_LC(F, CMP)                                                                                  \
     hipLaunchKernelGGL((curv2d_kernel<T, U, V, TY, MODE, F, CMP>), grid, dim3(64), 0, s, u, uprev, unext, \
@@ -354,7 +354,7 @@ void curv_launch_t(bool force, bool comp, dim3 grid, hipStream_t s, const U* u, 
 
 template <typename T, typename U, int MODE>
 void curv_launch(int V, int TY, bool force, bool comp, int nx, int nrows, hipStream_t s, const U* u,
-                 const T* uprev, T* unext, const double* xbase, T* u0out, double* acc, double* acclo, const T* ca,
+                 const T* uprev, T* unext, const double* xbase, T* u0out, double* acc, float* acclo, const T* ca,
                  const T* cl, const T* cm, const Metric4& g, const T* f, const Args2D& A) {
     auto grid_for = [&](int W, int ty) {
         return dim3((unsigned)xcd_grid(((nx - 1 + W - 1) / W) * ((nrows + ty - 1) / ty)), 1, 1);
@@ -389,7 +389,7 @@ void run_filter_curv2d(elwh_ctx* c, const double* x, bool with_force, bool amode
     const double sgn = amode ? -1.0 : 1.0;
     const bool comp = fp32 && c->opts.compensated;
     double* acc = out;
-    double* lo = c->acc_lo;
+    float* lo = c->acc_lo;
     A.w0 = sgn * c->w[0];
     A.w = sgn * c->w[1];
     A.fc = c->cosn[0];

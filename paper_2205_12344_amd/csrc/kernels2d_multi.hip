@@ -12,8 +12,9 @@
 // registers.
 //
 // Mapping.  As the single-step kernel (one 64-lane wavefront per block, V
-// nodes per lane, rows marched upwards with the stencil rows in registers and
-// DPP for the x neighbours), with a K-stage pipeline along the march: at row
+// nodes per lane, rows marched with the stencil rows in registers and DPP for
+// the x neighbours; odd row chunks march downwards, see below), with a
+// K-stage pipeline along the march: at row
 // iteration r, stage s computes u^{n+s} at row r-s+1 from the three rows of
 // u^{n+s-1} that stage s-1 has left in registers (stage 1 from u^n).  Level
 // s is needed K-s nodes beyond the block on every side, so each wavefront
@@ -83,7 +84,7 @@ __device__ __forceinline__ Half<T, V> half_of(const Row<T, V>& r) {
 template <typename T, int V, int TY, int K, bool FORCE, bool COMP>
 __device__ __forceinline__ void multi2d_body(int bx, int by, const T* __restrict__ u, const T* __restrict__ uprev,
                                              T* __restrict__ outA, T* __restrict__ outB,
-                                             double* __restrict__ acc, double* __restrict__ acclo,
+                                             double* __restrict__ acc, float* __restrict__ acclo,
                                              const T* __restrict__ ca, const T* __restrict__ cl,
                                              const T* __restrict__ cm, const T* __restrict__ f, const Args2D& A) {
     constexpr int W = MultiCols<V, K>::W, H = MultiCols<V, K>::H;
@@ -96,11 +97,25 @@ __device__ __forceinline__ void multi2d_body(int bx, int by, const T* __restrict
     const int j1 = min(j0 + TY - 1, A.jhi);
     const int P = (int)A.P;
     const int64_t CS = A.CS;
-    const T cxx2 = (T)A.cxx2, cyy2 = (T)A.cyy2, cxy = (T)A.cxy, cyyf = (T)A.cyyf, cfx = (T)A.cfx;
+    // Mirrored march (K = 2).  Odd row chunks march downwards, so that two
+    // neighbouring chunks read the halo rows they share at the same time
+    // (both at the start or both at the end of their marches) and the second
+    // read finds them in L2.  The march below runs over virtual rows v in
+    // [j0 - K + 1, j1 + K - 1]; row v is physical row jb + dir * v.  Mirrored
+    // about the chunk, the stencil of a node keeps its form with the roles of
+    // the rows below and above exchanged, which is the same stencil with the
+    // mixed-derivative coefficients negated and a traction-free top row taken
+    // as a free bottom row (and the reverse).  (For K = 3, 4, which are bound
+    // by instruction issue, the mirrored march measured 4 % slower.)
+    const int dir = (K == 2 && (by & 1)) ? -1 : 1;
+    const int jb = dir > 0 ? 0 : j0 + j1;
+    auto phys = [&](int v) { return jb + dir * v; };
+    const T cxx2 = (T)A.cxx2, cyy2 = (T)A.cyy2, cxy = (T)(dir * A.cxy), cyyf = (T)A.cyyf, cfx = (T)(dir * A.cfx);
     const T two = (T)2;
     const int olo = max(own0, 1), ohi = min(own0 + W - 1, A.nx - 1);   // owned columns
 
-    auto load_raw = [&](int j, RawRow<T, V>& r) {
+    auto load_raw = [&](int jv, RawRow<T, V>& r) {
+        const int j = phys(jv);
         if (colv && j >= 0 && j <= A.ny) {
             const int64_t o = (int64_t)j * P + col;
             vload<T, T, V>(u + o, r.u);
@@ -127,7 +142,8 @@ __device__ __forceinline__ void multi2d_body(int bx, int by, const T* __restrict
         o.vL = lane_from_left(r.v[V - 1]);
         o.vR = lane_from_right(r.v[0]);
     };
-    auto load_c1 = [&](int j, Ctr1<T, V>& c) {
+    auto load_c1 = [&](int jv, Ctr1<T, V>& c) {
+        const int j = phys(jv);
         if (colv && j >= A.jlo && j <= A.jhi) {
             const int64_t o = (int64_t)j * P + col;
             vload<T, T, V>(ca + o, c.a);
@@ -147,18 +163,26 @@ __device__ __forceinline__ void multi2d_body(int bx, int by, const T* __restrict
             }
         }
     };
-    auto load_acc = [&](int j, double (&hu)[V], double (&hv)[V], double (&lu)[V], double (&lv)[V]) {
-        if (colv && j >= j0 && j <= j1) {
-            const int64_t o = (int64_t)j * P + col;
+    // (the FP32 compensation words are widened when the row enters the
+    // pipeline, not at the load, which would wait for it there)
+    auto load_acc = [&](int jv, double (&hu)[V], double (&hv)[V], float (&lu)[V], float (&lv)[V]) {
+        if (colv && jv >= j0 && jv <= j1) {
+            const int64_t o = (int64_t)phys(jv) * P + col;
             vload<double, double, V>(acc + o, hu);
             vload<double, double, V>(acc + o + CS, hv);
             if constexpr (COMP) {
-                vload<double, double, V>(acclo + o, lu);
-                vload<double, double, V>(acclo + o + CS, lv);
+                vload<float, float, V>(acclo + o, lu);
+                vload<float, float, V>(acclo + o + CS, lv);
             }
         }
     };
-    auto kind_of = [&](int j) { return (A.free_hi && j == A.ny) ? 1 : ((A.free_lo && j == 0) ? 2 : 0); };
+    // stencil kind of virtual row v: 1 a traction-free row whose neighbour
+    // is the row before it in the march, 2 one whose neighbour is the row after
+    auto kind_of = [&](int v) {
+        const int j = phys(v);
+        const int k = (A.free_hi && j == A.ny) ? 1 : ((A.free_lo && j == 0) ? 2 : 0);
+        return dir > 0 || k == 0 ? k : 3 - k;
+    };
 
     const int r0 = j0 - K + 1, r1 = j1 + K - 1;
     // u^n rows r-1 (S), r (C), r+1 (N), with lambda, mu; older coefficient
@@ -195,7 +219,17 @@ __device__ __forceinline__ void multi2d_body(int bx, int by, const T* __restrict
         vzero<double, V>(alu[d]);
         vzero<double, V>(alv[d]);
     }
-    load_acc(r0, ahu[0], ahv[0], alu[0], alv[0]);
+    {
+        float l0u[V], l0v[V];
+        vzero<float, V>(l0u);
+        vzero<float, V>(l0v);
+        load_acc(r0, ahu[0], ahv[0], l0u, l0v);
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            alu[0][k] = l0u[k];
+            alv[0][k] = l0v[k];
+        }
+    }
     // computed levels 1..K-1: rows (q-2, q-1, q) of the last stage-s row q
     Half<T, V> L[K - 1][3];
 #pragma unroll
@@ -210,11 +244,12 @@ __device__ __forceinline__ void multi2d_body(int bx, int by, const T* __restrict
     for (int r = r0; r <= r1; ++r) {
         RawRow<T, V> rawNN;
         Ctr1<T, V> c1N;
-        double nhu[V], nhv[V], nlu[V], nlv[V];
+        double nhu[V], nhv[V];
+        float nlu[V], nlv[V];
         vzero<double, V>(nhu);
         vzero<double, V>(nhv);
-        vzero<double, V>(nlu);
-        vzero<double, V>(nlv);
+        vzero<float, V>(nlu);
+        vzero<float, V>(nlv);
         if (r < r1) {
             load_raw(r + 2, rawNN);
             load_c1(r + 1, c1N);
@@ -232,9 +267,10 @@ __device__ __forceinline__ void multi2d_body(int bx, int by, const T* __restrict
 
         auto stage = [&](auto sc) {
             constexpr int s = decltype(sc)::value;
-            const int q = r - s + 1;                          // row of stage s
+            const int q = r - s + 1;                          // (virtual) row of stage s
+            const int pq = phys(q);
             // level s is needed on rows j0-(K-s) .. j1+(K-s); zero on boundary rows
-            const bool rowv = q >= j0 - (K - s) && q >= A.jlo && q <= A.jhi;
+            const bool rowv = q >= j0 - (K - s) && pq >= A.jlo && pq <= A.jhi;
             const bool own = q >= j0 && q <= j1;
             const int ilo = max(own0 - (K - s), 1), ihi = min(own0 + W - 1 + (K - s), A.nx - 1);
             // coefficient rows q-1, q, q+1; row r-d is N (d = -1), C (0), S (1), Ol[d-2] (d >= 2)
@@ -275,7 +311,7 @@ __device__ __forceinline__ void multi2d_body(int bx, int by, const T* __restrict
             const int kind = kind_of(q);
             const double wgt = A.wk[s - 1];
             const T fcs = (T)A.fck[s - 1];
-            const int64_t o = (int64_t)q * P + col;
+            const int64_t o = (int64_t)pq * P + col;
             Half<T, V> nw;
 #pragma unroll
             for (int k = 0; k < V; ++k) {
@@ -326,8 +362,8 @@ __device__ __forceinline__ void multi2d_body(int bx, int by, const T* __restrict
                                 acc[o + k] = ahu[s - 1][k];
                                 acc[o + k + CS] = ahv[s - 1][k];
                                 if constexpr (COMP) {
-                                    acclo[o + k] = alu[s - 1][k];
-                                    acclo[o + k + CS] = alv[s - 1][k];
+                                    acclo[o + k] = (float)alu[s - 1][k];
+                                    acclo[o + k + CS] = (float)alv[s - 1][k];
                                 }
                             }
                         }
@@ -395,7 +431,7 @@ __device__ __forceinline__ void multi2d_body(int bx, int by, const T* __restrict
 template <typename T, int V, int TY, int K, bool FORCE, bool COMP>
 __global__ __launch_bounds__(64) void multi2d_kernel(const T* __restrict__ u, const T* __restrict__ uprev,
                                                     T* __restrict__ outA, T* __restrict__ outB,
-                                                    double* __restrict__ acc, double* __restrict__ acclo,
+                                                    double* __restrict__ acc, float* __restrict__ acclo,
                                                     const T* __restrict__ ca, const T* __restrict__ cl,
                                                     const T* __restrict__ cm, const T* __restrict__ f, Args2D A) {
     constexpr int W = MultiCols<V, K>::W;
@@ -408,7 +444,7 @@ __global__ __launch_bounds__(64) void multi2d_kernel(const T* __restrict__ u, co
 
 template <typename T, int V, int TY, int K>
 static void multi_launch_t(bool force, bool comp, hipStream_t s, int nrows, const T* u, const T* uprev, T* outA,
-                           T* outB, double* acc, double* acclo, const T* ca, const T* cl, const T* cm, const T* f,
+                           T* outB, double* acc, float* acclo, const T* ca, const T* cl, const T* cm, const T* f,
                            const Args2D& A) {
     constexpr int W = MultiCols<V, K>::W;
     const dim3 grid((unsigned)xcd_grid(((A.nx - 1 + W) / W) * ((nrows + TY - 1) / TY)), 1, 1);
@@ -430,7 +466,7 @@ static void multi_launch_t(bool force, bool comp, hipStream_t s, int nrows, cons
 
 template <typename T, int K>
 static void multi_launch_k(int V, int TY, bool force, bool comp, hipStream_t s, int nrows, const T* u,
-                           const T* uprev, T* outA, T* outB, double* acc, double* acclo, const T* ca, const T* cl,
+                           const T* uprev, T* outA, T* outB, double* acc, float* acclo, const T* ca, const T* cl,
                            const T* cm, const T* f, const Args2D& A) {
 #define ELWH_MC(VV, TT)                                                                                            \
     if (V == VV && TY == TT) {                                                                                     \
@@ -448,7 +484,7 @@ static void multi_launch_k(int V, int TY, bool force, bool comp, hipStream_t s, 
 
 template <typename T>
 void launch_multi2d(int K, int V, int TY, bool force, bool comp, hipStream_t s, int nrows, const T* u,
-                    const T* uprev, T* outA, T* outB, double* acc, double* acclo, const T* ca, const T* cl,
+                    const T* uprev, T* outA, T* outB, double* acc, float* acclo, const T* ca, const T* cl,
                     const T* cm, const T* f, const Args2D& A) {
     if (K == 4)
         multi_launch_k<T, 4>(V, TY, force, comp, s, nrows, u, uprev, outA, outB, acc, acclo, ca, cl, cm, f, A);
@@ -459,10 +495,10 @@ void launch_multi2d(int K, int V, int TY, bool force, bool comp, hipStream_t s, 
 }
 
 template void launch_multi2d<double>(int, int, int, bool, bool, hipStream_t, int, const double*, const double*,
-                                     double*, double*, double*, double*, const double*, const double*,
+                                     double*, double*, double*, float*, const double*, const double*,
                                      const double*, const double*, const Args2D&);
 template void launch_multi2d<float>(int, int, int, bool, bool, hipStream_t, int, const float*, const float*,
-                                    float*, float*, double*, double*, const float*, const float*, const float*,
+                                    float*, float*, double*, float*, const float*, const float*, const float*,
                                     const float*, const Args2D&);
 
 }  // namespace elwh

@@ -36,14 +36,15 @@ template <typename T, bool COMP, bool FORCE, int MODE>
 struct Centre3 {
     T a, lam_m, lam_p, mu_m, mu_p;   // a; lambda, mu at rows j-1, j+1 of the plane
     T up[3];
-    double h[3], l[3];
+    double h[3];
+    float l[3];          // compensation, widened where it is used
     T f[3];
 };
 
 template <typename T, typename U, int TZ, int RB, int MODE, bool FORCE, bool COMP>
 __global__ __launch_bounds__(64 * RB) void step3d_kernel(const U* __restrict__ u, const T* uprev, T* unext,
                                                    const double* __restrict__ xbase, T* __restrict__ u0out,
-                                                   double* __restrict__ acc, double* __restrict__ acclo,
+                                                   double* __restrict__ acc, float* __restrict__ acclo,
                                                    const T* __restrict__ ca, const T* __restrict__ cl,
                                                    const T* __restrict__ cm, const T* __restrict__ f,
                                                    Args3D A) {
@@ -180,7 +181,7 @@ __global__ __launch_bounds__(64 * RB) void step3d_kernel(const U* __restrict__ u
                     acc[oq] = hq + lq;
                 } else {
                     acc[oq] = hq;
-                    if constexpr (COMP) acclo[oq] = lq;
+                    if constexpr (COMP) acclo[oq] = (float)lq;
                 }
             }
         }
@@ -195,7 +196,7 @@ __global__ __launch_bounds__(64 * RB) void step3d_kernel(const U* __restrict__ u
 
 template <typename T, typename U, int TZ, int RB, int MODE>
 static void launch3_t(bool force, bool comp, dim3 grid, hipStream_t s, const U* u, const T* uprev, T* unext,
-                      const double* xbase, T* u0out, double* acc, double* acclo, const T* ca, const T* cl,
+                      const double* xbase, T* u0out, double* acc, float* acclo, const T* ca, const T* cl,
                       const T* cm, const T* f, const Args3D& A) {
 #define ELWH_L3(F, CMP)                                                                                          \
     hipLaunchKernelGGL((step3d_kernel<T, U, TZ, RB, MODE, F, CMP>), grid, dim3(64 * RB), 0, s, u, uprev, unext, \
@@ -217,7 +218,7 @@ bool tile_valid_3d(bool fp32, int V, int TZ) {
 
 template <typename T, typename U, int MODE>
 static void launch3_z(int RB, int TZ, bool force, bool comp, const Args3D& A, hipStream_t s, const U* u,
-                      const T* uprev, T* unext, const double* xbase, T* u0out, double* acc, double* acclo,
+                      const T* uprev, T* unext, const double* xbase, T* u0out, double* acc, float* acclo,
                       const T* ca, const T* cl, const T* cm, const T* f) {
     const int nplanes = A.khi - A.klo + 1;
     auto grid = [&](int rb, int tz) {
@@ -260,7 +261,7 @@ static void free_pair3(T* const* bufs, const void* a, const void* b, T** x, T** 
 // single steps alternate between two buffers as before.
 template <typename T>
 static void run_steps_3d(elwh_ctx* c, Args3D A, int RB1, int TZ, bool k2, int RB2, bool with_force, bool comp,
-                         double sgn, const T* prev, T* cur, T* const* bufs, double* acc, double* lo, const T* ca,
+                         double sgn, const T* prev, T* cur, T* const* bufs, double* acc, float* lo, const T* ca,
                          const T* cl, const T* cm, const T* f, int nsteps) {
     hipStream_t s = c->stream;
     int n = 1;
@@ -332,7 +333,7 @@ void run_filter_3d(elwh_ctx* c, const double* x, bool with_force, bool amode, bo
     const double sgn = amode ? -1.0 : 1.0;
     const bool comp = fp32 && c->opts.compensated;
     double* acc = out;
-    double* lo = c->acc_lo;
+    float* lo = c->acc_lo;
     A.w0 = sgn * c->w[0];
     A.w = sgn * c->w[1];
     A.fc = c->cosn[0];

@@ -56,7 +56,7 @@ __device__ __forceinline__ void acc_add_c3(double& hi, double& lo, double x, boo
 template <typename T, typename U, int MODE, bool FORCE, bool COMP>
 __global__ __launch_bounds__(64) void curv3d_kernel(const U* __restrict__ u, const T* uprev, T* unext,
                                                    const double* __restrict__ xbase, T* __restrict__ u0out,
-                                                   double* __restrict__ acc, double* __restrict__ acclo,
+                                                   double* __restrict__ acc, float* __restrict__ acclo,
                                                    const T* __restrict__ ca, const T* __restrict__ cl,
                                                    const T* __restrict__ cm, Metric3<T> G, const T* __restrict__ f,
                                                    ArgsC3 A) {
@@ -223,7 +223,7 @@ __global__ __launch_bounds__(64) void curv3d_kernel(const U* __restrict__ u, con
             acc[oq] = hq + lq;
         } else {
             acc[oq] = hq;
-            if constexpr (COMP) acclo[oq] = lq;
+            if constexpr (COMP) acclo[oq] = (float)lq;
         }
     }
 }
@@ -235,7 +235,7 @@ bool tile_valid_curv3(bool fp32, int V, int TY) {
 
 template <typename T, typename U, int MODE>
 static void launch_c3(bool force, bool comp, const ArgsC3& A, hipStream_t s, const U* u, const T* uprev, T* unext,
-                      const double* xbase, T* u0out, double* acc, double* acclo, const T* ca, const T* cl,
+                      const double* xbase, T* u0out, double* acc, float* acclo, const T* ca, const T* cl,
                       const T* cm, const Metric3<T>& G, const T* f) {
     const int nbx = (A.nq - 1 + 63) / 64;
     const dim3 grid((unsigned)xcd_grid(nbx * (A.nr - 1) * (A.khi - A.klo + 1)));
@@ -271,7 +271,7 @@ void run_filter_curv3d(elwh_ctx* c, const double* x, bool with_force, bool amode
     const double sgn = amode ? -1.0 : 1.0;
     const bool comp = fp32 && c->opts.compensated;
     double* acc = out;
-    double* lo = c->acc_lo;
+    float* lo = c->acc_lo;
     A.w0 = sgn * c->w[0];
     A.w = sgn * c->w[1];
     A.fc = c->cosn[0];

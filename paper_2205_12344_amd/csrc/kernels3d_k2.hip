@@ -15,8 +15,9 @@
 // Stage 1 is exact on lanes 1..62, stage 2 on lanes 2..61: a strip computes
 // 60 columns.  Per node the launch reads u^n, u^{n-1}, the coefficients and
 // the accumulator once and writes u^{n+1}, u^{n+2} and the accumulator once,
-// instead of twice each: 168 (FP64) or 156 (FP32 state, compensated FP64
-// accumulator) bytes for two lattice updates, against 144 per update.  The
+// instead of twice each: 168 (FP64) or 132 (FP32 state, compensated FP64
+// accumulator with an FP32 compensation word) bytes for two lattice
+// updates, against 144 per update.  The
 // accumulation order per node (w_{n+1} u^{n+1}, then w_{n+2} u^{n+2}) is that
 // of two single steps.
 #include "elwh_internal.h"
@@ -46,7 +47,7 @@ struct CtrK2 {
 template <typename T, int TZ, int RB, bool FORCE, bool COMP>
 __global__ __launch_bounds__(64 * (RB + 2)) void step3d_k2_kernel(const T* __restrict__ u, const T* __restrict__ uprev,
                                                                  T* __restrict__ outA, T* __restrict__ outB,
-                                                                 double* __restrict__ acc, double* __restrict__ acclo,
+                                                                 double* __restrict__ acc, float* __restrict__ acclo,
                                                                  const T* __restrict__ ca, const T* __restrict__ cl,
                                                                  const T* __restrict__ cm, const T* __restrict__ f,
                                                                  Args3D A) {
@@ -139,8 +140,11 @@ __global__ __launch_bounds__(64 * (RB + 2)) void step3d_k2_kernel(const T* __res
     constexpr bool PF = sizeof(T) == 4;
     // (masked: the accumulator is written in this launch, and only a lane's
     // own stage-2 node is its to read)
-    auto load_acc = [&](int k, double* h, double* l) {
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, b0 = 0.0, b1 = 0.0, b2 = 0.0;
+    // (the compensation words stay FP32 until they are used: converting at
+    // the load would wait for it there)
+    auto load_acc = [&](int k, double* h, float* l) {
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+        float b0 = 0.0f, b1 = 0.0f, b2 = 0.0f;
         if (inner && xin2 && yin && k >= k0 && k <= k1 && k >= A.klo && k <= A.khi) {
             const int64_t o = (int64_t)k * PS + (int64_t)j * P + i;
             a0 = acc[o];
@@ -165,11 +169,12 @@ __global__ __launch_bounds__(64 * (RB + 2)) void step3d_k2_kernel(const T* __res
     // them instead of copying was measured: it needs more registers than it
     // saves moves.)
     using Acc3 = double[3];
+    using Lo3 = float[3];
     T Dp_lam = (T)0, Dp_mu = (T)0;   // lambda, mu of plane kk - 2 (row j)
     const int kA = k0 - 1, kB = k1 + 1;
 
     auto sub = [&](const int kk, PlaneK2<T>& D, PlaneK2<T>& C, PlaneK2<T>& Up, PlaneK2<T>& Up2, CtrK2<T>& prv,
-                   CtrK2<T>& ctr, CtrK2<T>& ctrN, Acc3& accH, Acc3& accL, Acc3& accHN, Acc3& accLN) {
+                   CtrK2<T>& ctr, CtrK2<T>& ctrN, Acc3& accH, Lo3& accL, Acc3& accHN, Lo3& accLN) {
         if (kk + 1 <= kB) {
             load_plane(kk + 2, Up2);
             load_ctr(kk + 1, ctrN);
@@ -285,7 +290,7 @@ __global__ __launch_bounds__(64 * (RB + 2)) void step3d_k2_kernel(const T* __res
                         acc[o + q * CS + i] = hq + lq;
                     } else {
                         acc[o + q * CS + i] = hq;
-                        if constexpr (COMP) acclo[o + q * CS + i] = lq;
+                        if constexpr (COMP) acclo[o + q * CS + i] = (float)lq;
                     }
                 }
             }
@@ -297,7 +302,8 @@ __global__ __launch_bounds__(64 * (RB + 2)) void step3d_k2_kernel(const T* __res
 
     PlaneK2<T> P0, P1, P2, P3;
     CtrK2<T> Q0, Q1, Q2;
-    Acc3 H0 = {0.0, 0.0, 0.0}, L0 = {0.0, 0.0, 0.0}, H1, L1;
+    Acc3 H0 = {0.0, 0.0, 0.0}, H1;
+    Lo3 L0 = {0.0f, 0.0f, 0.0f}, L1;
     load_plane(kA - 1, P0);
     load_plane(kA, P1);
     load_plane(kA + 1, P2);
@@ -333,7 +339,7 @@ bool tile_valid_3d_k2(bool fp32, int RB, int TZ) {
 
 template <typename T>
 void launch_step3d_k2(int RB, int TZ, bool force, bool comp, hipStream_t s, const T* u, const T* uprev, T* outA,
-                      T* outB, double* acc, double* acclo, const T* ca, const T* cl, const T* cm, const T* f,
+                      T* outB, double* acc, float* acclo, const T* ca, const T* cl, const T* cm, const T* f,
                       const Args3D& A) {
     const int nbx = (A.nx - 1 + 59) / 60;
     auto grid = [&](int rb, int tz) {
@@ -367,10 +373,10 @@ void launch_step3d_k2(int RB, int TZ, bool force, bool comp, hipStream_t s, cons
 }
 
 template void launch_step3d_k2<double>(int, int, bool, bool, hipStream_t, const double*, const double*, double*,
-                                       double*, double*, double*, const double*, const double*, const double*,
+                                       double*, double*, float*, const double*, const double*, const double*,
                                        const double*, const Args3D&);
 template void launch_step3d_k2<float>(int, int, bool, bool, hipStream_t, const float*, const float*, float*, float*,
-                                      double*, double*, const float*, const float*, const float*, const float*,
+                                      double*, float*, const float*, const float*, const float*, const float*,
                                       const Args3D&);
 
 }  // namespace elwh

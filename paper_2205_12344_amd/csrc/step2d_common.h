@@ -59,7 +59,11 @@ __device__ __forceinline__ Nb<T> node_of(const Row<T, V>& r, int k) {
 
 __device__ __forceinline__ void acc_add(double& hi, double& lo, double x, bool comp) {
     if (comp) {
-        // Knuth's TwoSum: hi + x = t + e exactly; e goes to the compensation
+        // Knuth's TwoSum: hi + x = t + e exactly; e goes to the compensation.
+        // Between launches the compensation is stored in FP32: it holds only
+        // rounding errors, below 2^-53 of the accumulator per term, so its
+        // own rounding is near 2^-77 of the accumulator and the word costs 4
+        // instead of 8 bytes per component and pass.
         const double t = hi + x;
         const double z = t - hi;
         const double e = (hi - (t - z)) + (x - z);

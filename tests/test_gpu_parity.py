@@ -141,13 +141,23 @@ def test_filter_fp32_stepping(E, dim):
     u0 = rng.standard_normal(prob.field_shape) * prob.unknown_mask()
     f = rng.standard_normal(prob.field_shape) * prob.unknown_mask()
     ref = prob.scatter(wh.apply_filter(prob.gather(u0), prob.gather(f)))
+    runs = {}
     for comp in (1, 0):
-        for fuse in ((2, 1, 3, 4) if dim == 2 else (2,)):
+        for fuse in ((2, 1, 3, 4) if dim == 2 else (2, 1)):
             ctx = E.Context(dim, n, rho, lam, mu, om, bc, prec=E.FP32_STEP, compensated=comp, fuse=fuse)
-            got = ctx.apply_filter(u0, f).cpu().numpy()
+            got = runs[comp, fuse] = ctx.apply_filter(u0, f).cpu().numpy()
             err = _rel(got, ref)
             _say("  fp32 compensated", comp, "fuse", fuse, "nt", wh.nt, "rel err", err, "bound", fp32_bound(wh.nt))
             assert err <= fp32_bound(wh.nt)
+    # The FP32 states do not depend on how the accumulator is summed, so the
+    # compensated and plain results differ only by the plain FP64 summation's
+    # rounding (about N_T * 2^-53 of the terms): a compensation word read or
+    # written wrongly would show far above that.
+    for (comp, fuse), got in runs.items():
+        if comp:
+            d = _rel(got, runs[0, fuse])
+            _say("  compensated vs plain, fuse", fuse, d)
+            assert d <= 1e-12
 
 
 @pytest.mark.parametrize("nt", [3, 4, 5, 8, 9])
