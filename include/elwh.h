@@ -117,8 +117,12 @@ typedef struct {
                           (default 0) */
     int cr_fallback;   /* CG paths: when CG breaks down ((p, A_h p)_M <= 0: A_h
                           slightly indefinite near resonance, the remark of
-                          Sec. 4.4), continue from the current iterate in FP64
-                          with 1 (default) = the conjugate residual method, which
+                          Sec. 4.4), solve again in FP64 from the iterate the
+                          broken CG sequence started from (x0 or 0; in the FP32
+                          path after a stagnation, where its FP64 CG began; the
+                          last CG iterate is not used: near a breakdown CG
+                          steps far along nearly A_h-null directions) with
+                          1 (default) = the conjugate residual method, which
                           minimises the same residual norm as MINRES but can
                           itself break down when (r, A_h r)_M = 0 (reported as
                           ELWH_ERR_BREAKDOWN), or 2 = MINRES, the method the
@@ -153,7 +157,8 @@ typedef struct {
     double relres;      /* last Krylov residual ||r||_M / ||b||_M (recurrence) */
     double relres_fp64; /* final ||b - A_h v||_M / ||b||_M recomputed with an FP64 apply */
     double cond_est;    /* Lanczos condition estimate from the CG coefficients (CG only) */
-    int cr_iters;       /* CR or MINRES iterations after a CG breakdown (cr_fallback), else 0 */
+    int cr_iters;       /* CR or MINRES iterations after a CG breakdown (cr_fallback), else 0;
+                           not included in iters */
     int fp64_iters;     /* FP32 path: FP64 CG iterations after a stagnation (fp64_fallback), else 0;
                            included in iters */
 } elwh_info;

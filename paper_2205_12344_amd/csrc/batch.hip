@@ -275,16 +275,21 @@ elwh_status scale_start(elwh_batch* b, const std::vector<int>& sel) {
     return ELWH_OK;
 }
 
-// Problems whose CG broke down ((p, A_h p)_M <= 0) continue from their
-// current iterate with the conjugate residual method in FP64, one after the
+// Problems whose CG broke down ((p, A_h p)_M <= 0) are solved with the
+// conjugate residual method (or MINRES) in FP64 from the iterate their CG
+// sequence started from (kept in VRI: the last CG iterate before a breakdown
+// carries error along nearly A_h-null directions that takes a residual-
+// minimising method far longer to remove than a fresh start), one after the
 // other on the batch stream; their FP64 residual is then recomputed.
 elwh_status cr_fallback(elwh_batch* b, std::vector<int>& status, std::vector<int>& iters, std::vector<int>& cr_iters,
                         std::vector<double>& relres, std::vector<double>& relfp64, const std::vector<double>& bb,
                         double tol, int maxit) {
-    std::vector<int> sel(b->np, 0);
+    std::vector<int> sel(b->np, 0), broken(b->np, 0);
     bool any = false;
+    for (int p = 0; p < b->np; ++p) broken[p] = status[p] == ELWH_ERR_BREAKDOWN;
+    BST(lincomb(b, broken, VX, VRI, 1.0, -1, 0.0));
     for (int p = 0; p < b->np; ++p) {
-        if (status[p] != ELWH_ERR_BREAKDOWN) continue;
+        if (!broken[p]) continue;
         int it = 0;
         double rel = 1.0;
         elwh_status st = ctx_solve_fallback(b->ctx[p], b->opts.cr_fallback, tol, std::max(1, maxit - iters[p]), &it,
@@ -703,6 +708,7 @@ elwh_status elwh_batch_solve(elwh_batch* b, const double* const* f, const double
         for (int p = 0; p < np; ++p) nox[p] = !has_x[p];
         BST(lincomb(b, nox, VR, VB, 1.0, -1, 0.0));
         BST(lincomb(b, all, VP, VR, 1.0, -1, 0.0));
+        BST(lincomb(b, all, VRI, VX, 1.0, -1, 0.0));   // the start, for a fallback after a breakdown
         BST(dots(b, all, VR, VR, rr));
         for (int p = 0; p < np; ++p) {
             BState& s = b->h_st[p];
@@ -742,6 +748,7 @@ elwh_status elwh_batch_solve(elwh_batch* b, const double* const* f, const double
         for (int p = 0; p < np; ++p) nox[p] = !has_x[p];
         BST(lincomb(b, nox, VR, VB, 1.0, -1, 0.0));
         BST(lincomb(b, all, VP, VR, 1.0, -1, 0.0));
+        BST(lincomb(b, all, VRI, VX, 1.0, -1, 0.0));   // the start, for a fallback after a breakdown
         BST(dots(b, all, VR, VR, rr));
         std::vector<double> seg = rr, rr_k(np, 0.0), beta(np, 0.0);
         std::vector<int> done_p(np, 0), stag(np, 0), longest(np, 0), capped(np, 0);
@@ -873,6 +880,7 @@ elwh_status elwh_batch_solve(elwh_batch* b, const double* const* f, const double
             anystag |= stag[p] != 0;
         }
         if (anystag) {
+            BST(lincomb(b, stag, VRI, VX, 1.0, -1, 0.0));   // a new CG sequence starts here
             BST(run_apply(b, false, false, true, VX, VQ, stag));
             BST(lincomb(b, stag, VR, VB, 1.0, VQ, -1.0));
             BST(lincomb(b, stag, VP, VR, 1.0, -1, 0.0));

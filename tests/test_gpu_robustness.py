@@ -120,7 +120,8 @@ def test_minres_fallback_after_cg_breakdown(E, prec):
     assert info["relres_fp64"] <= 1e-8
     # A_h has an eigenvalue of about -1e-6 here (condition ~1e6): a residual of
     # 1e-8 bounds the error only to ~1e-2, and the iterate the fallback starts
-    # from decides where in that ball MINRES lands (from zero it is 2e-7)
+    # from decides where in that ball MINRES lands (it starts from the start,
+    # zero here, from where the oracle's MINRES lands at 2e-7)
     assert _rel(prob.gather(v.cpu().numpy()), xs) <= 1e-3
     # the same problem inside a batch with two definite ones
     cases = [c, inputs.random_problem_2d(40, 9.5, seed=201), inputs.random_problem_2d(33, 4.2, seed=202)]
@@ -133,6 +134,28 @@ def test_minres_fallback_after_cg_breakdown(E, prec):
         assert ii["relres_fp64"] <= 1e-8
         pr, o, _ = _case_oracle(cc)
         assert _rel(pr.gather(vv.cpu().numpy()), direct.solve(o, cc.omega, pr.gather(cc.f))) <= 1e-3
+
+
+def test_fallback_starts_from_the_start_not_from_the_last_cg_iterate(E):
+    """Held-out warm-start problem 4288 (256^2 cells, N_T = 120): CG breaks
+    down after about 1070 iterations.  Conjugate residual from the last CG
+    iterate did not reach 1e-8 within 6929 iterations (near the breakdown CG
+    stepped far along nearly A_h-null directions); from the start it takes
+    about 1085.  Within maxit = 4000 (CG and fallback together) the solve must
+    converge, alone and inside a batch."""
+    c = inputs.warmstart_problem(4288, n=256)
+    ctx = E.context_from_case(c)
+    v, info = ctx.solve(c.f, tol=1e-8, maxit=4000)
+    _say("fallback from the start", info["status"], info["iters"], info["cr_iters"], info["relres_fp64"])
+    assert info["status"] == "OK" and info["cr_iters"] > 0 and info["relres_fp64"] <= 1e-8
+    assert info["iters"] + info["cr_iters"] <= 2500
+    other = inputs.warmstart_problem(4289, n=256)
+    bt = E.Batch([c, other], scale_x0=1)
+    vs, infos, st = bt.solve([c.f, other.f], tol=1e-8, maxit=4000)
+    _say("batched", st, [(i["iters"], i["cr_iters"], i["relres_fp64"]) for i in infos])
+    assert st == "OK" and infos[0]["cr_iters"] > 0
+    assert all(i["relres_fp64"] <= 1e-8 for i in infos)
+    assert infos[0]["iters"] + infos[0]["cr_iters"] <= 2500
 
 
 @pytest.mark.parametrize("fallback", [1, 2])
