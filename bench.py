@@ -794,9 +794,10 @@ def main():
                              "bytes_per_lup": round(bytes_per_lup, 2), "achieved_GBs": round(gbs, 1),
                              "frac": round(gbs / HBM_PEAK_GBS, 4),
                              "frac_of_triad": round(gbs / ceiling["triad_GBs"], 4),
-                             # lattice updates per second times the single-step
-                             # algorithmic bytes (144 B/LUP)
-                             "effective_frac": round(BYTES_PER_LUP[(3, tag, 1)] * n3 / step_us / 1e3
+                             # lattice updates per second times the FP64
+                             # single-step algorithmic bytes (144 B/LUP) in
+                             # both precisions, so that FP64 and FP32 compare
+                             "effective_frac": round(BYTES_PER_LUP[(3, "f64", 1)] * n3 / step_us / 1e3
                                                      / HBM_PEAK_GBS, 4),
                              "traffic": read_traffic(f"step3d_{tag}_cube256", (rb, tz), "3d")}
             log(f"3d {tag} fuse {fuse3}: tile {rb},{tz}, {step_us:.1f} us per step, {gbs:.0f} GB/s")
