@@ -18,7 +18,8 @@
 // (a/2)(L_h u^0 - J f) and seeds the accumulator, as on Cartesian grids.
 //
 // Mapping.  One 64-lane wavefront per block; lane k owns V consecutive q
-// nodes; a wavefront marches TY rows up in r.  Each row is loaded once per
+// nodes; a wavefront marches TY rows in r (up in even row chunks, down in
+// odd ones).  Each row is loaded once per
 // row visit (u, v, lam/J, mu/J and the four metric values); when it enters
 // the register ring its blocks K^qq, K^rr, K^qr and the vector
 // Q = (K^qr)^T (U_{i+1} - U_{i-1}) are formed in registers, so the cross
@@ -93,12 +94,22 @@ __device__ __forceinline__ void curv2d_body(int bx, int by, const U* __restrict_
     const int j1 = min(j0 + TY - 1, A.jhi);
     const int P = (int)A.P;
     const int64_t CS = A.CS;
-    const T cqq2 = (T)A.cxx2, crr2 = (T)A.cyy2, cqr = (T)A.cxy;
-    const T crrf = (T)A.cyyf, cqrf = (T)A.cfx;   // free rows: 1/h_r^2, 1/(2 h_q h_r)
+    // Mirrored march: odd row chunks march downwards, so that neighbouring
+    // chunks read the rows they share at the same time and the second read
+    // finds them in L2.  Virtual row v is physical row jb + dir * v.  With
+    // the rows below and above exchanged, P changes sign and the compact r
+    // term does not, so the mirrored stencil is the same stencil with both
+    // cross-term coefficients negated and the two free-row kinds swapped.
+    const int dir = (by & 1) ? -1 : 1;
+    const int jb = dir > 0 ? 0 : j0 + j1;
+    auto phys = [&](int v) { return jb + dir * v; };
+    const T cqq2 = (T)A.cxx2, crr2 = (T)A.cyy2, cqr = (T)(dir * A.cxy);
+    const T crrf = (T)A.cyyf, cqrf = (T)(dir * A.cfx);   // free rows: 1/h_r^2, +-1/(2 h_q h_r)
     const T two = (T)2;
     const int ilo = max(c0 + 1, 1), ihi = min(c0 + W, A.nx - 1);
 
-    auto load_raw = [&](int j, CRaw<T, V>& r) {
+    auto load_raw = [&](int jv, CRaw<T, V>& r) {
+        const int j = phys(jv);
         if (colv && j >= 0 && j <= A.ny) {
             const int64_t o = (int64_t)j * P + col;
             vload<U, T, V>(u + o, r.u);
@@ -153,8 +164,9 @@ __device__ __forceinline__ void curv2d_body(int bx, int by, const U* __restrict_
         }
     };
     using Ctr = CCtr<T, V, COMP, FORCE, MODE>;
-    auto load_ctr = [&](int j, Ctr& c) {
-        if (colv && j <= A.jhi) {
+    auto load_ctr = [&](int jv, Ctr& c) {
+        const int j = phys(jv);
+        if (colv && j >= A.jlo && j <= A.jhi) {
             const int64_t o = (int64_t)j * P + col;
             vload<T, T, V>(ca + o, c.a);
             if constexpr (MODE == 0) {
@@ -205,7 +217,9 @@ __device__ __forceinline__ void curv2d_body(int bx, int by, const U* __restrict_
         finish(rawN, N);
         // K^qq of the q neighbours and P = K^qr (U_N - U_S) (one-sided on a
         // free row), across the lane edges
-        const int kind = (A.free_hi && j == A.ny) ? 1 : ((A.free_lo && j == 0) ? 2 : 0);
+        const int pj = phys(j);
+        const int kind0 = (A.free_hi && pj == A.ny) ? 1 : ((A.free_lo && pj == 0) ? 2 : 0);
+        const int kind = dir > 0 || kind0 == 0 ? kind0 : 3 - kind0;
         T P0[V], P1[V];
 #pragma unroll
         for (int k = 0; k < V; ++k) {
@@ -219,7 +233,7 @@ __device__ __forceinline__ void curv2d_body(int bx, int by, const U* __restrict_
         const T qq2L = lane_from_left(C.qq2[V - 1]), qq2R = lane_from_right(C.qq2[0]);
         const T P0L = lane_from_left(P0[V - 1]), P0R = lane_from_right(P0[0]);
         const T P1L = lane_from_left(P1[V - 1]), P1R = lane_from_right(P1[0]);
-        const int64_t o = (int64_t)j * P + col;
+        const int64_t o = (int64_t)pj * P + col;
 
 #pragma unroll
         for (int k = 0; k < V; ++k) {
