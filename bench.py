@@ -273,6 +273,60 @@ def cpu_worker(seconds):
     print(json.dumps({"napply": napply, "seconds": el, "nt": wh.nt, "nodes": unknown_nodes(case)}))
 
 
+def cpu_extras_worker():
+    """The oracle's other reference timings, one process and one thread:
+    config 1 (64^2 constant medium, omega = 10) solved by CG to 1e-10 and by a
+    sparse LU of the discrete Helmholtz system, and one A_h application in
+    FP64 on a 64^3 sample of the 3-D layered cube (the same construction as the
+    256^3 workload; the 256^3 operator would need tens of GB as a sparse
+    matrix).  Operator assembly is timed apart.  Prints one JSON line."""
+    import numpy as np
+    from oracle import direct, krylov
+    from oracle.operator import Operator
+    from oracle.problem import Problem
+    from oracle.stepping import WaveHoltz
+    from paper_2205_12344_amd import inputs
+    out = {}
+    c1 = inputs.constant_square64()
+    t0 = time.perf_counter()
+    prob = Problem(c1.dim, c1.n, length=c1.length, bc=c1.bc)
+    op = Operator(prob, c1.rho, c1.lam, c1.mu)
+    wh = WaveHoltz(op, c1.omega)
+    t1 = time.perf_counter()
+    fv = prob.gather(c1.f)
+    res = krylov.cg(wh.apply_A, wh.rhs(fv), op.m, tol=1e-10, maxit=1000)
+    t2 = time.perf_counter()
+    xs = direct.solve(op, c1.omega, fv)
+    t3 = time.perf_counter()
+    out["config1"] = {"assembly_s": round(t1 - t0, 4), "cg_s": round(t2 - t1, 4), "cg_iters": res.iters,
+                      "splu_s": round(t3 - t2, 4), "nt": wh.nt, "dof": int(op.ndof),
+                      "cg_vs_direct_rel": float(np.linalg.norm(res.x - xs) / np.linalg.norm(xs))}
+    c3 = inputs.layered_cube(n=64)
+    t0 = time.perf_counter()
+    prob3 = Problem(c3.dim, c3.n, length=c3.length, bc=c3.bc)
+    op3 = Operator(prob3, c3.rho, c3.lam, c3.mu)
+    wh3 = WaveHoltz(op3, c3.omega)
+    t1 = time.perf_counter()
+    x = np.random.default_rng(0).standard_normal(op3.ndof)
+    wh3.apply_A(x)
+    t2 = time.perf_counter()
+    nodes = op3.ndof // 3
+    out["config3_sample64"] = {"assembly_s": round(t1 - t0, 3), "apply_s": round(t2 - t1, 3), "nt": wh3.nt,
+                               "nodes": int(nodes), "lup_s": wh3.nt * nodes / (t2 - t1)}
+    print(json.dumps(out))
+
+
+def cpu_extras():
+    """Run cpu_extras_worker in a child process with one thread."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    p = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-extras-worker"], stdout=subprocess.PIPE,
+                       stderr=subprocess.DEVNULL, env=env, timeout=600)
+    if p.returncode != 0:
+        raise RuntimeError(f"cpu extras worker failed ({p.returncode})")
+    return json.loads(p.stdout.decode().strip().splitlines()[-1])
+
+
 def cpu_baseline(seconds=10.0):
     """The oracle timed on the host: one worker process alone (one core), then
     one worker per core on every core the box gives this job (os.cpu_count(),
@@ -359,6 +413,13 @@ def solves_2d_and_3d(elwh, inputs):
     Krylov method reaches 1e-8 on it within 3e4 iterations.)"""
     import torch
     out = {}
+    # config 1 (64^2 constant medium, CG to 1e-10): launch-latency bound on
+    # the GPU; the oracle's CG and sparse LU of the same problem are timed in
+    # the CPU leg
+    c1 = inputs.constant_square64()
+    time_to_tol(elwh, c1, tol=1e-10)                                       # warm-up
+    out["config1_cg_1e-10"] = time_to_tol(elwh, c1, tol=1e-10)
+    log(f"config 1 to 1e-10: {out['config1_cg_1e-10']}")
     c64 = inputs.layered_cube(n=64)
     out["cube64"] = {"fp64": time_to_tol(elwh, c64), "fp32c": time_to_tol(elwh, c64, prec=elwh.FP32_STEP),
                      "omega": c64.omega}
@@ -615,6 +676,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="headline, roofline and kernel rates only")
     ap.add_argument("--cpu-worker", type=float, default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-extras-worker", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--batch-only", action="store_true",
                     help="only the ragged-batch FP64 solve (for kernel traces)")
     ap.add_argument("--batch-problems", type=int, default=48,
@@ -638,6 +700,9 @@ def main():
     args = ap.parse_args()
     if args.cpu_worker is not None:
         cpu_worker(args.cpu_worker)
+        return
+    if args.cpu_extras_worker:
+        cpu_extras_worker()
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the hot path runs on a single MI355X "
@@ -815,7 +880,7 @@ def main():
     # optional parts, in order of importance, inside the time budget
     extra = {}
     deadline = t_start + args.budget
-    cpu_s = 0.0 if args.no_cpu else 40.0       # what the CPU leg at the end needs
+    cpu_s = 0.0 if args.no_cpu else 60.0       # what the CPU leg at the end needs
 
     def fits(name, est_s):
         left = deadline - time.perf_counter() - cpu_s
@@ -842,6 +907,8 @@ def main():
         cpu = cpu_baseline()
         log(f"cpu oracle: {cpu['value'] / 1e6:.2f} MLUP/s on {cpu['cores']} cores, "
             f"{cpu['one_core']['value'] / 1e6:.2f} MLUP/s on one ({cpu['sample']})")
+        cpu["other_timings_one_core"] = cpu_extras()
+        log(f"cpu oracle, config 1 and a 64^3 sample of config 3: {cpu['other_timings_one_core']}")
 
     out = {
         "metric": METRIC, "value": value, "unit": "LUP/s", "n_gpus": 1, "steps": args.steps,
