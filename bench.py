@@ -403,6 +403,26 @@ def time_to_tol(elwh, case, tol=1e-8, maxit=20000, **kw):
             "nt": info["nt"]}
 
 
+def sequential_plain(elwh, first_seed=4096, n=48, tol=1e-8, maxit=4000):
+    """The first n held-out warm-start problems solved one after the other,
+    each in its own context (plain FP64 from zero; creation excluded): the
+    unbatched context for the batched time to tol."""
+    import torch
+    from paper_2205_12344_amd import inputs
+    secs, iters, ok = 0.0, [], True
+    for s in range(first_seed, first_seed + n):
+        c = inputs.warmstart_problem(s, n=256)
+        ctx = elwh.context_from_case(c)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info = ctx.solve(c.f, tol=tol, maxit=maxit, raise_on_fail=False)
+        secs += time.perf_counter() - t0
+        iters.append(info["iters"] + info["cr_iters"])
+        ok &= info["status"] == "OK" and info["relres_fp64"] <= tol
+        ctx.close()
+    return {"problems": n, "seconds": round(secs, 3), "mean_iters": float(sum(iters) / n), "all_ok": bool(ok)}
+
+
 def solves_2d_and_3d(elwh, inputs):
     """Time to 1e-8 of the layered cube at 64^3, FP64 stepping against FP32
     stepping with the compensated FP64 accumulator; and five CG iterations of
@@ -894,6 +914,12 @@ def main():
     if fits("time_to_1e-8", 210):
         extra["time_to_1e-8"] = learned_start_comparison(elwh)
         log(f"time to 1e-8: {json.dumps(extra['time_to_1e-8'])}")
+        if fits("time_to_1e-8_sequential", 40):
+            seq = sequential_plain(elwh)
+            per = extra["time_to_1e-8"].get("plain_fp64_seconds_per_batch") or [None]
+            seq["batched_seconds_same_problems"] = per[0]
+            extra["time_to_1e-8"]["plain_fp64_unbatched_first48"] = seq
+            log(f"unbatched plain FP64, first 48: {seq}")
     if fits("ragged_batch48", 165):
         extra["ragged_batch48"] = ragged_batch_solve(elwh, inputs, precisions=("fp32",))
     if fits("solves_to_1e-8", 60):

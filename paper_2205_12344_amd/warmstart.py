@@ -231,6 +231,7 @@ def evaluate(net, seeds, batch=48, tol=1e-8, maxit=4000, fp32_batches=None, zero
             "speedup_learned_fp32_vs_plain_fp64": plain_s / res["learned_fp32"]["seconds"]}
     nl = len(res["learned_fp64"]["status"])
     out["speedup_learned_fp64_vs_plain_fp64"] = sum(plain_batch_s[:nl]) / res["learned_fp64"]["seconds"]
+    out["plain_fp64_seconds_per_batch"] = plain_batch_s
     return out
 
 
