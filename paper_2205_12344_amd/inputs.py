@@ -219,6 +219,32 @@ def layered_cube(n=256, seed=3, ppw=8.0):
                 tol=1e-8, meta={"seed": seed, "center": x0.tolist(), "direction": e.tolist()})
 
 
+BC_FREE_Z_3D = (0, 0, 0, 0, 1, 1)    # Dirichlet sides, traction-free z = 0 and z = 1
+
+
+def cube_bc_case(omega, free_z=False, h_omega=0.4, sigma_per_omega=10.0):
+    """The boundary-condition experiment on the unit cube (Sec. 5.6): all
+    Dirichlet, or traction-free z = 0 and z = 1 with Dirichlet elsewhere;
+    h omega = 0.4 (n = round(omega / 0.4) cells per side), lambda = 2,
+    mu = rho = 1, and per component j a Gaussian A_j exp(-sigma/2 |x - x_j|^2)
+    with A_j = sigma^(3/2) and sigma = 10 omega (the section states only
+    sigma ~ omega and A_j ~ sigma^(d/2)), the centres x_j slightly apart so
+    that the forcing has both curl and divergence."""
+    n = max(4, int(round(omega / h_omega)))
+    shape = (n + 1,) * 3
+    sigma = sigma_per_omega * omega
+    centres = [(0.50, 0.50, 0.50), (0.53, 0.48, 0.51), (0.48, 0.52, 0.47)]
+    c = np.arange(n + 1) / n
+    z, y, x = np.meshgrid(c, c, c, indexing="ij")
+    f = np.zeros((3,) + shape)
+    for j, (cx, cy, cz) in enumerate(centres):
+        f[j] = sigma ** 1.5 * np.exp(-0.5 * sigma * ((x - cx) ** 2 + (y - cy) ** 2 + (z - cz) ** 2))
+    one = np.ones(shape)
+    bc = BC_FREE_Z_3D if free_z else BC_ALL_DIRICHLET_3D
+    return Case(f"cube_bc_{'free' if free_z else 'dirichlet'}_w{omega:g}", 3, (n, n, n), omega, one, 2 * one, one,
+                f, bc, tol=1e-9, meta={"sigma": sigma, "centres": centres})
+
+
 def random_problem_2d(n, omega, seed, nsrc=None, width_h=(3.2, 3.2), rng=None):
     """One random 2-D problem: random log-normal media, 1-4 Gaussians in [0.2,0.8]^2."""
     h = 1.0 / n
