@@ -426,8 +426,9 @@ def sequential_plain(elwh, first_seed=4096, n=48, tol=1e-8, maxit=4000):
 def solves_2d_and_3d(elwh, inputs):
     """Time to 1e-8 of the layered cube at 64^3, FP64 stepping against FP32
     stepping with the compensated FP64 accumulator; and five CG iterations of
-    the 256^3 cube per precision (the full 256^3 solve needs on the order of
-    1e5 iterations: the count grows like omega^3 in 3-D, Sec. 5.5).  (The
+    the 256^3 cube per precision (the 64^3 cube needs about 1e4 iterations
+    and the count grows like omega^3 in 3-D, Sec. 5.6, so the full 256^3
+    solve would need some 5e5: hours of GPU time).  (The
     1024^2 benchmark problem is not solved here: its A_h is near-singular,
     a condition estimate of 1.6e11 from the CG Lanczos coefficients, and no
     Krylov method reaches 1e-8 on it within 3e4 iterations.)"""
