@@ -2,16 +2,17 @@
 
 A step is one Krylov iteration of the solve on the 2-D 1024 x 1024 random
 log-normal medium with a traction-free top (FP64): one A_h = I - S_h
-application (the half-step launch and (N_T - 1) / 2 fused step-pair
-launches over every unknown node, each with its trapezoid accumulation)
+application (the half-step launch and the fused launches of K = 4 time
+steps each, plus one shorter launch when 4 does not divide N_T - 1, over
+every unknown node, each step with its trapezoid accumulation)
 plus the FP64 M-inner-product reductions and the CG vector updates.  Inputs are resident
 in HBM before timing.  value = lattice updates per second, one lattice
 update = one unknown node advanced one time step (both components), with its
 accumulation.
 
-The JSON line also carries the roofline of the fused step-pair kernel
-(HIP-event durations of the step launches over a profiled repeat of the
-timed steps), the HBM ceiling a STREAM triad reaches, the FP32-stepping and
+The JSON line also carries the roofline of the fused K-step kernel (HIP-event
+durations of its launches on the same workload and tiling, with N_T rounded
+so that every launch takes K steps), the HBM ceiling a STREAM triad reaches, the FP32-stepping and
 single-step variants, the step kernels of the 3-D cube, of mapped 2-D and 3-D
 grids and of the two-field operator, the time to residual 1e-8 of the
 benchmark problem and of a 3-D cube, the 48-problem ragged batch, the
@@ -817,16 +818,27 @@ def main():
     lup_per_step = nt * nodes
     value = lup_per_step * args.steps / el
     ms_per_step = 1e3 * el / args.steps
-    # every application runs N_T - 1 steps after the half step
+    # every application runs N_T - 1 steps after the half step: K-step
+    # launches and, when K does not divide N_T - 1, one shorter launch
     napp = prof["nstep"] // max(nt - 1, 1)
     fuse = elwh.default_opts().fuse
     bytes_app, launches_app = phase_bytes(2, "f64", fuse, nt, nodes)
-    step_avg_ms = prof["step_ms"] / max(napp * launches_app, 1)
-    achieved = bytes_app * napp / (prof["step_ms"] * 1e-3) / 1e9
+    phase_gbs = bytes_app * napp / (prof["step_ms"] * 1e-3) / 1e9
+    # the dominant kernel alone: the same workload and tiling with N_T
+    # rounded up so that K divides N_T - 1 (the weights change, the kernel's
+    # work per launch does not); HIP events on the context's stream
+    nt_k = fuse * ((nt - 1 + fuse - 1) // fuse) + 1
+    ck = elwh.context_from_case(case, nt=nt_k, autotune=0)
+    ck.set_tile(elwh.FP64, tv, tr)
+    pk = kernel_rate(ck, 10)
+    ck.close()
+    step_avg_ms = pk["step_ms"] / max(pk["nstep"] // fuse, 1)
+    achieved = BYTES_PER_MULTI_LAUNCH["f64"] * nodes / (step_avg_ms * 1e-3) / 1e9
     traffic = read_traffic(f"multi2d_k{fuse}_f64_square1024", (tv, tr))
     log(f"tile V={tv} TY={tr}")
-    log(f"fp64: {ms_per_step:.3f} ms/step, {value / 1e9:.2f} GLUP/s, {fuse}-step kernel {1e3 * step_avg_ms:.1f} us "
-        f"({napp * launches_app} launches), {achieved:.0f} GB/s")
+    log(f"fp64: {ms_per_step:.3f} ms/step, {value / 1e9:.2f} GLUP/s, {fuse}-step kernel {1e3 * step_avg_ms:.2f} us "
+        f"({pk['nstep'] // fuse} launches at N_T = {nt_k}), {achieved:.0f} GB/s; step phase of the CG "
+        f"iteration {phase_gbs:.0f} GB/s")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic,
@@ -834,6 +846,8 @@ def main():
                 "bytes_per_lup": BYTES_PER_MULTI_LAUNCH["f64"] / fuse, "lup_per_launch": fuse * nodes,
                 "bytes_per_launch": BYTES_PER_MULTI_LAUNCH["f64"] * nodes,
                 "avg_launch_us": round(1e3 * step_avg_ms, 3),
+                "launch_timing": f"{pk['nstep'] // fuse} launches, same workload and tiling at N_T = {nt_k}",
+                "step_phase_GBs": round(phase_gbs, 1),
                 # effective fraction: lattice updates per second times the
                 # single-step algorithmic bytes (104 B/LUP), the measure under
                 # which temporal blocking can exceed 1 (the K-step kernel

@@ -106,9 +106,10 @@ typedef struct {
     int autotune;      /* 1 (default): pick the step-kernel tiling by timing at create */
     int fuse;          /* time steps per step-kernel launch: 2-D Cartesian 1 to 4,
                           3-D Cartesian 1 or 2 (larger values act as 2, and
-                          the tiling may still choose single steps); default
-                          2; mapped grids and the two-field step always step
-                          singly */
+                          the tiling may still choose single steps); the
+                          batch takes two-step launches for any value >= 2;
+                          default 4; mapped grids and the two-field step
+                          always step singly */
     int scale_x0;      /* CG paths: 1 = replace a given x0 by alpha x0 with
                           alpha = (x0, b)_M / (x0, A_h x0)_M, the factor that
                           minimises the A_h-norm error along x0 (0 when
@@ -464,8 +465,9 @@ elwh_status elwh_profile_read(elwh_ctx* ctx, double* step_ms, int* nstep, double
 /*
  * Tiling of the fused step kernel for precision prec (ELWH_FP64 or
  * ELWH_FP32_STEP): 2-D: vec nodes per lane along x (1 or 2, FP32 also 4)
- * and rows (4, 8, 16) marched per wavefront; 3-D: vec = y rows per
- * workgroup, one wavefront each, and rows = z planes marched per wavefront:
+ * and rows (4, 8, 16; with vec = 1 also 10, 12) marched per wavefront;
+ * 3-D: vec = y rows per workgroup, one wavefront each, and rows = z planes
+ * marched per wavefront:
  * (1, 2, 4, 8) x (4, 8, 16, 32) for single-step launches (opts.fuse = 1),
  * (2, 4, 6) x (8, 16, 32, 64) for two-step launches (fuse >= 2; the workgroup
  * adds two halo rows), where vec = 1 with rows 4 to 32 makes every step a

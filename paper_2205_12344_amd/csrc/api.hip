@@ -980,7 +980,7 @@ void elwh_default_opts(elwh_opts* o) {
     o->max_outer = 50;
     o->stream = nullptr;
     o->autotune = 1;
-    o->fuse = 2;
+    o->fuse = 4;
     o->scale_x0 = 0;
     o->cr_fallback = 1;
     o->fp64_fallback = 1;
@@ -1703,7 +1703,7 @@ elwh_status elwh_autotune(elwh_ctx* c, int prec, int reps, double* best_step_us)
                 if (tile_valid_curv(fp32, V, TY)) cands.push_back(Tile{V, TY});
     } else if (c->L.dim == 2) {
         for (int V : {1, 2, 4})
-            for (int TY : {4, 8, 16})
+            for (int TY : {4, 8, 10, 12, 16})
                 if (tile_valid_2d(fp32, V, TY)) cands.push_back(Tile{V, TY});
     } else if (steps >= 2) {
         // two-step tilings, and single steps (RB 1) where they are faster

@@ -264,7 +264,7 @@ static void launch_v(int V, int TY, bool force, bool comp, int nx, int nrows, hi
                                      acc, acclo, ca, cl, cm, f, A);                                      \
         return;                                                                                          \
     }
-    ELWH_CASE(1, 4) ELWH_CASE(1, 8) ELWH_CASE(1, 16)
+    ELWH_CASE(1, 4) ELWH_CASE(1, 8) ELWH_CASE(1, 10) ELWH_CASE(1, 12) ELWH_CASE(1, 16)
     ELWH_CASE(2, 4) ELWH_CASE(2, 8) ELWH_CASE(2, 16)
     if constexpr (sizeof(T) == 4) {
         ELWH_CASE(4, 4) ELWH_CASE(4, 8) ELWH_CASE(4, 16)
@@ -298,7 +298,7 @@ Args2D make_args2d(const elwh_ctx* c) {
 
 bool tile_valid_2d(bool fp32, int V, int TY) {
     const bool v_ok = V == 1 || V == 2 || (fp32 && V == 4);
-    return v_ok && (TY == 4 || TY == 8 || TY == 16);
+    return v_ok && (TY == 4 || TY == 8 || TY == 16 || (V == 1 && (TY == 10 || TY == 12)));
 }
 
 // ===========================================================================

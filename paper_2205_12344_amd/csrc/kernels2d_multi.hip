@@ -473,7 +473,7 @@ static void multi_launch_k(int V, int TY, bool force, bool comp, hipStream_t s, 
         multi_launch_t<T, VV, TT, K>(force, comp, s, nrows, u, uprev, outA, outB, acc, acclo, ca, cl, cm, f, A); \
         return;                                                                                                    \
     }
-    ELWH_MC(1, 4) ELWH_MC(1, 8) ELWH_MC(1, 16)
+    ELWH_MC(1, 4) ELWH_MC(1, 8) ELWH_MC(1, 10) ELWH_MC(1, 12) ELWH_MC(1, 16)
     ELWH_MC(2, 4) ELWH_MC(2, 8) ELWH_MC(2, 16)
     if constexpr (sizeof(T) == 4) {
         ELWH_MC(4, 4) ELWH_MC(4, 8) ELWH_MC(4, 16)

@@ -46,7 +46,7 @@ def test_struct_sizes_match_header(elwh):
 def test_default_opts(elwh):
     o = elwh.default_opts()
     assert o.cfl == 0.8 and o.periods == 1 and o.nt == 0 and o.prec == 0 and o.compensated == 1 and o.autotune == 1
-    assert o.fuse == 2 and o.scale_x0 == 0 and o.inner_tol == 1e-2 and o.cr_fallback == 1 and o.fp64_fallback == 1
+    assert o.fuse == 4 and o.scale_x0 == 0 and o.inner_tol == 1e-2 and o.cr_fallback == 1 and o.fp64_fallback == 1
     assert o.fp32_switch == 0.0
 
 

@@ -502,7 +502,7 @@ def test_large_sizes_fixed_point():
 def _tiles(dim, fp32, fuse=1):
     if dim == 2:
         vs = (1, 2, 4) if fp32 else (1, 2)
-        return [(v, ty) for v in vs for ty in (4, 8, 16)]
+        return [(v, ty) for v in vs for ty in (4, 8, 16)] + [(1, 10), (1, 12)]
     if fuse >= 2:   # two-step 3-D launches: RB rows (plus two halo rows) x TZ planes;
         # RB 1 = single-step launches in a two-step context
         return [(rb, tz) for rb in (2, 4, 6) for tz in (8, 16, 32, 64)] + [(1, 16), (1, 32)]
