@@ -88,7 +88,7 @@ thread_local std::string g_batch_err;
 elwh_status set_phase(elwh_batch* b, bool fp32, int isrc, int iout, int ix, int ir, int ip, int* nblocks,
                       int* nblocks2 = nullptr) {
     const Tile& t = b->tile[fp32 ? 1 : 0];
-    const int W = batch_cols(t.V), W2 = batch_cols2(t.V);
+    const int W = batch_cols(t.V), W2 = batch_cols_k(t.V, batch_kb(b->opts.fuse));
     int off = 0, off2 = 0;
     b->h_pr.resize(b->np);
     for (int p = 0; p < b->np; ++p) {
@@ -195,11 +195,11 @@ elwh_status upload_mask(elwh_batch* b, const std::vector<int>& mask) {
     return ELWH_OK;
 }
 
-// Ticks of one application: the half step, then two-step ticks while two or
-// more steps are left (fuse2), single steps otherwise.
-int ticks_per_application(int nsteps, int fuse2) {
+// Ticks of one application: the half step, then kb-step ticks while kb or
+// more steps are left, single steps otherwise.
+int ticks_per_application(int nsteps, int kb) {
     const int rest = nsteps - 1;
-    return 1 + (fuse2 ? rest / 2 + rest % 2 : rest);
+    return 1 + (kb >= 2 ? rest / kb + rest % kb : rest);
 }
 
 // One filter application per selected problem: out = Pi_h src (with the
@@ -208,14 +208,14 @@ elwh_status run_apply(elwh_batch* b, bool fp32, bool force, bool amode, int isrc
                       const std::vector<int>& sel) {
     int nblocks = 0, nblocks2 = 0;
     BST(set_phase(b, fp32, isrc, iout, -1, -1, -1, &nblocks, &nblocks2));
-    const int fuse2 = b->opts.fuse >= 2 ? 1 : 0;
+    const int kb = batch_kb(b->opts.fuse);
     int maxticks = 0;
     for (int p = 0; p < b->np; ++p) {
         BState& s = b->h_st[p];
         s.n = 0;
         s.end = 0;
         s.active = sel[p] ? 1 : 0;
-        if (sel[p]) maxticks = std::max(maxticks, ticks_per_application(b->h_pr[p].nsteps, fuse2));
+        if (sel[p]) maxticks = std::max(maxticks, ticks_per_application(b->h_pr[p].nsteps, kb));
     }
     BST(upload_states(b));
     const Tile& t = b->tile[fp32 ? 1 : 0];
@@ -223,11 +223,11 @@ elwh_status run_apply(elwh_batch* b, bool fp32, bool force, bool amode, int isrc
     const double sgn = amode ? -1.0 : 1.0;
     for (int k = 0; k < maxticks; ++k) {
         launch_batch_step(fp32, t.V, t.TY, force, comp, nblocks, b->stream, b->d_pr, b->d_st, b->np, sgn,
-                          amode ? 1 : 0, fuse2);
-        if (fuse2)
-            launch_batch_multi(fp32, t.V, t.TY, force, comp, nblocks2, b->stream, b->d_pr, b->d_st, b->np, sgn,
+                          amode ? 1 : 0, kb);
+        if (kb)
+            launch_batch_multi(fp32, t.V, t.TY, kb, force, comp, nblocks2, b->stream, b->d_pr, b->d_st, b->np, sgn,
                                amode ? 1 : 0);
-        launch_batch_advance(b->stream, b->d_pr, b->d_st, b->np, 1, fuse2, fp32 ? 1 : 0);
+        launch_batch_advance(b->stream, b->d_pr, b->d_st, b->np, 1, kb, fp32 ? 1 : 0);
         b->ticks++;
     }
     BCK(hipGetLastError());
@@ -317,12 +317,13 @@ elwh_status cr_fallback(elwh_batch* b, std::vector<int>& status, std::vector<int
 void enqueue_ticks(elwh_batch* b, bool fp32, int nblocks, int nblocks2, int nticks) {
     const Tile& t = b->tile[fp32 ? 1 : 0];
     const bool comp = fp32 && b->opts.compensated;
-    const int fuse2 = b->opts.fuse >= 2 ? 1 : 0;
+    const int kb = batch_kb(b->opts.fuse);
     for (int k = 0; k < nticks; ++k) {
-        launch_batch_step(fp32, t.V, t.TY, false, comp, nblocks, b->stream, b->d_pr, b->d_st, b->np, -1.0, 1, fuse2);
-        if (fuse2)
-            launch_batch_multi(fp32, t.V, t.TY, false, comp, nblocks2, b->stream, b->d_pr, b->d_st, b->np, -1.0, 1);
-        launch_batch_advance(b->stream, b->d_pr, b->d_st, b->np, 0, fuse2, fp32 ? 1 : 0);
+        launch_batch_step(fp32, t.V, t.TY, false, comp, nblocks, b->stream, b->d_pr, b->d_st, b->np, -1.0, 1, kb);
+        if (kb)
+            launch_batch_multi(fp32, t.V, t.TY, kb, false, comp, nblocks2, b->stream, b->d_pr, b->d_st, b->np, -1.0,
+                               1);
+        launch_batch_advance(b->stream, b->d_pr, b->d_st, b->np, 0, kb, fp32 ? 1 : 0);
         for (int mode = 0; mode < 3; ++mode)
             launch_batch_cg(b->stream, mode, b->d_pr, b->d_st, b->np, b->d_plist, b->nplist, b->d_partials,
                             b->d_arrive, b->d_active);
@@ -434,8 +435,8 @@ elwh_status autotune_batch(elwh_batch* b, bool fp32) {
     std::vector<int> all(b->np, 1);
     std::vector<Tile> cands;
     for (int V : {1, 2, 4})
-        for (int TY : {4, 8, 16})
-            if (batch_tile_valid(fp32, V, TY)) cands.push_back(Tile{V, TY});
+        for (int TY : {4, 8, 10, 16})
+            if (batch_tile_valid(fp32, V, TY, batch_kb(b->opts.fuse))) cands.push_back(Tile{V, TY});
     for (int p = 0; p < b->np; ++p)
         BCK(hipMemsetAsync(b->ctx[p]->vec[VT], 0, b->ctx[p]->L.field_elems() * sizeof(double), b->stream));
     hipEvent_t e0, e1;
@@ -536,8 +537,10 @@ elwh_status elwh_batch_create(int nprob, const elwh_grid* grids, const double* c
     }
     b->h_st.assign(nprob, BState{});
     b->info.assign(nprob, elwh_info{});
-    b->tile[0] = Tile{2, 8};
-    b->tile[1] = Tile{2, 8};
+    // untuned tiles: supported by the single-step and the kb-step batch kernels
+    const Tile t0 = batch_kb(o.fuse) == 4 ? Tile{1, 10} : Tile{2, 8};
+    b->tile[0] = t0;
+    b->tile[1] = t0;
     if (o.autotune) {
         if (autotune_batch(b, false) != ELWH_OK) return fail(ELWH_ERR_HIP, b->err);
         if (o.prec == ELWH_FP32_STEP && autotune_batch(b, true) != ELWH_OK) return fail(ELWH_ERR_HIP, b->err);

@@ -13,7 +13,7 @@ namespace elwh {
 // application per problem (deactivate when it completes).  After the half
 // step u^{n-1} = u^0 is src in FP64 and s[0] in FP32.
 __global__ void batch_advance_kernel(const BProb2D* __restrict__ pr, BState* __restrict__ st, int np, int single,
-                                     int fuse2, int fp32) {
+                                     int kb, int fp32) {
     const int p = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (p >= np || !st[p].active) return;
     BState& s = st[p];
@@ -22,12 +22,13 @@ __global__ void batch_advance_kernel(const BProb2D* __restrict__ pr, BState* __r
     if (neff == 0) {
         s.ip = fp32 ? 0 : -1;
         s.ic = 1;
-    } else if (batch_two_step(neff, pr[p].nsteps, fuse2)) {
+    } else if (batch_multi_step(neff, pr[p].nsteps, kb)) {
+        // u^{n+kb-1} and u^{n+kb} went to the two free buffers
         int x1, x2;
         batch_free_two(s.ic, s.ip, x1, x2);
         s.ip = x1;
         s.ic = x2;
-        steps = 2;
+        steps = kb;
     } else {
         const int nxt = batch_single_target(s.ic, s.ip);
         s.ip = s.ic;
@@ -212,8 +213,8 @@ __global__ __launch_bounds__(64) void batch_dot_final_kernel(int np, const int* 
     if (threadIdx.x == 0) out[p] = s;
 }
 
-void launch_batch_advance(hipStream_t s, const BProb2D* pr, BState* st, int np, int single, int fuse2, int fp32) {
-    hipLaunchKernelGGL(batch_advance_kernel, dim3((np + 63) / 64), dim3(64), 0, s, pr, st, np, single, fuse2, fp32);
+void launch_batch_advance(hipStream_t s, const BProb2D* pr, BState* st, int np, int single, int kb, int fp32) {
+    hipLaunchKernelGGL(batch_advance_kernel, dim3((np + 63) / 64), dim3(64), 0, s, pr, st, np, single, kb, fp32);
 }
 
 void launch_batch_cg(hipStream_t s, int mode, const BProb2D* pr, BState* st, int np, const int* plist, int nplist,

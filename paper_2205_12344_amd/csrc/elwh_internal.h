@@ -84,7 +84,7 @@ struct Damp2D {
 struct BProb2D {
     Args2D A;                 // geometry and stencil constants
     int nbx, nblk, off;       // single-step launch: blocks along x, blocks, first block
-    int nbx2, nblk2, off2;    // two-step launch: the same for its tiling
+    int nbx2, nblk2, off2;    // multi-step launch (K = 2 or 4): the same for its tiling
     int nsteps;               // steps per application (K N_T)
     const double* w;          // filter weights w_n (sign +1), n = 0..nsteps
     const double* cosn;       // forcing factors cos(2 pi n / N_T)
@@ -328,17 +328,21 @@ void launch_multiaxpy2(const elwh_ctx* c, const double* const* V, int k, const d
 enum { RED_SUM = 0, RED_PQ = 1, RED_RR = 2 };
 
 // ---- ragged batch (kernels2d.hip) --------------------------------------------
-bool batch_tile_valid(bool fp32, int V, int TY);
+// Steps per multi-step launch of a batch tick (kb): 4 when the options ask
+// for four steps per launch, 2 for two or three, 0 for single steps only.
+inline int batch_kb(int fuse) { return fuse >= 4 ? 4 : (fuse >= 2 ? 2 : 0); }
+bool batch_tile_valid(bool fp32, int V, int TY, int kb);
 int batch_cols(int V);
 Args2D make_args2d(const elwh_ctx* c);
 void launch_batch_step(bool fp32, int V, int TY, bool force, bool comp, int nblocks, hipStream_t s,
-                       const BProb2D* pr, const BState* st, int np, double sgn, int amode, int fuse2);
-// fuse2: problems with two or more steps left take a two-step launch
-void launch_batch_advance(hipStream_t s, const BProb2D* pr, BState* st, int np, int single, int fuse2, int fp32);
-int batch_cols2(int V);
-// Two-step tick of every active problem with at least two steps left in its
-// application (kernels2d_multi.hip); nblocks2 = tiles of the two-step tiling.
-void launch_batch_multi(bool fp32, int V, int TY, bool force, bool comp, int nblocks2, hipStream_t s,
+                       const BProb2D* pr, const BState* st, int np, double sgn, int amode, int kb);
+// problems with kb or more steps left (kb = 2, 4) take a kb-step launch
+void launch_batch_advance(hipStream_t s, const BProb2D* pr, BState* st, int np, int single, int kb, int fp32);
+// computed columns per wavefront of the kb-step tiling (kb = 2 or 4)
+int batch_cols_k(int V, int kb);
+// kb-step tick of every active problem with at least kb steps left in its
+// application (kernels2d_multi.hip); nblocks2 = tiles of the kb-step tiling.
+void launch_batch_multi(bool fp32, int V, int TY, int kb, bool force, bool comp, int nblocks2, hipStream_t s,
                         const BProb2D* pr, const BState* st, int np, double sgn, int amode);
 // CG update kernels of the ragged batch for the nplist problems listed in
 // plist (device array of problem indices); arrive: one zeroed counter per

@@ -311,11 +311,12 @@ bool tile_valid_2d(bool fp32, int V, int TY) {
 // ===========================================================================
 
 // Single-step tick: the half step that starts an application, and every
-// step of problems that do not take a two-step launch this tick (fuse2 = 0,
-// or one step left).  u^{n+1} overwrites u^{n-1} when that is a state buffer.
+// step of problems that do not take a kb-step launch this tick (kb = 0, or
+// fewer than kb steps left).  u^{n+1} overwrites u^{n-1} when that is a
+// state buffer.
 template <typename T, int V, int TY, bool FORCE, bool COMP>
 __global__ __launch_bounds__(64) void batch_step2d_kernel(const BProb2D* __restrict__ pr, const BState* __restrict__ st,
-                                                          int np, int ntiles, double sgn, int amode, int fuse2) {
+                                                          int np, int ntiles, double sgn, int amode, int kb) {
     // XCD bands over the concatenated tiles of all problems
     int b;
     if (!xcd_tile((int)blockIdx.x, ntiles, b)) return;
@@ -323,7 +324,7 @@ __global__ __launch_bounds__(64) void batch_step2d_kernel(const BProb2D* __restr
     const BProb2D& q = pr[p];
     if (!st[p].active) return;
     const int neff = st[p].end ? 0 : st[p].n;
-    if (batch_two_step(neff, q.nsteps, fuse2)) return;
+    if (batch_multi_step(neff, q.nsteps, kb)) return;
     const int local = b - q.off;
     if (local >= q.nblk) return;
     const int bx = local % q.nbx, by = local / q.nbx;
@@ -357,10 +358,10 @@ __global__ __launch_bounds__(64) void batch_step2d_kernel(const BProb2D* __restr
 
 template <typename T, int V, int TY>
 static void batch_step_t(bool force, bool comp, int nblocks, hipStream_t s, const BProb2D* pr, const BState* st,
-                         int np, double sgn, int amode, int fuse2) {
+                         int np, double sgn, int amode, int kb) {
 #define ELWH_B2(F, C) \
     hipLaunchKernelGGL((batch_step2d_kernel<T, V, TY, F, C>), dim3((unsigned)xcd_grid(nblocks)), dim3(64), 0, s, pr, st, \
-                       np, nblocks, sgn, amode, fuse2)
+                       np, nblocks, sgn, amode, kb)
     if (force) {
         if (comp) ELWH_B2(true, true); else ELWH_B2(true, false);
     } else {
@@ -369,7 +370,8 @@ static void batch_step_t(bool force, bool comp, int nblocks, hipStream_t s, cons
 #undef ELWH_B2
 }
 
-bool batch_tile_valid(bool fp32, int V, int TY) {
+bool batch_tile_valid(bool fp32, int V, int TY, int kb) {
+    if (kb == 4) return (V == 1 && (TY == 4 || TY == 8 || TY == 10)) || (fp32 && V == 2 && TY == 8);
     if (V == 1 && (TY == 4 || TY == 8)) return true;
     if (V == 2 && (TY == 4 || TY == 8 || TY == 16)) return true;
     return fp32 && V == 4 && TY == 8;
@@ -378,18 +380,18 @@ bool batch_tile_valid(bool fp32, int V, int TY) {
 int batch_cols(int V) { return V == 1 ? Cols<1>::W : (V == 2 ? Cols<2>::W : Cols<4>::W); }
 
 void launch_batch_step(bool fp32, int V, int TY, bool force, bool comp, int nblocks, hipStream_t s,
-                       const BProb2D* pr, const BState* st, int np, double sgn, int amode, int fuse2) {
+                       const BProb2D* pr, const BState* st, int np, double sgn, int amode, int kb) {
 #define ELWH_BT(T, VV, TT)                                                                          \
     if (V == VV && TY == TT) {                                                                      \
-        batch_step_t<T, VV, TT>(force, comp, nblocks, s, pr, st, np, sgn, amode, fuse2);            \
+        batch_step_t<T, VV, TT>(force, comp, nblocks, s, pr, st, np, sgn, amode, kb);               \
         return;                                                                                     \
     }
     if (fp32) {
-        ELWH_BT(float, 1, 4) ELWH_BT(float, 1, 8) ELWH_BT(float, 2, 4) ELWH_BT(float, 2, 8) ELWH_BT(float, 2, 16)
-        ELWH_BT(float, 4, 8)
+        ELWH_BT(float, 1, 4) ELWH_BT(float, 1, 8) ELWH_BT(float, 1, 10) ELWH_BT(float, 2, 4) ELWH_BT(float, 2, 8)
+        ELWH_BT(float, 2, 16) ELWH_BT(float, 4, 8)
     } else {
-        ELWH_BT(double, 1, 4) ELWH_BT(double, 1, 8) ELWH_BT(double, 2, 4) ELWH_BT(double, 2, 8)
-        ELWH_BT(double, 2, 16)
+        ELWH_BT(double, 1, 4) ELWH_BT(double, 1, 8) ELWH_BT(double, 1, 10) ELWH_BT(double, 2, 4)
+        ELWH_BT(double, 2, 8) ELWH_BT(double, 2, 16)
     }
 #undef ELWH_BT
 }

@@ -504,14 +504,14 @@ template void launch_multi2d<float>(int, int, int, bool, bool, hipStream_t, int,
 }  // namespace elwh
 
 // ===========================================================================
-// Ragged batch: the two-step tick of every active problem with at least two
-// steps left in its application (the other problems take the single-step
-// tick of kernels2d.hip in the same tick).  Tiles of the two-step tiling of
-// all problems are concatenated and dealt in XCD bands.
+// Ragged batch: the K-step tick (K = 2 or 4) of every active problem with at
+// least K steps left in its application (the other problems take the
+// single-step tick of kernels2d.hip in the same tick).  Tiles of the K-step
+// tiling of all problems are concatenated and dealt in XCD bands.
 // ===========================================================================
 namespace elwh {
 
-template <typename T, int V, int TY, bool FORCE, bool COMP>
+template <typename T, int V, int TY, int K, bool FORCE, bool COMP>
 __global__ __launch_bounds__(64) void batch_multi2d_kernel(const BProb2D* __restrict__ pr,
                                                            const BState* __restrict__ st, int np, int ntiles,
                                                            double sgn) {
@@ -521,32 +521,32 @@ __global__ __launch_bounds__(64) void batch_multi2d_kernel(const BProb2D* __rest
     const BProb2D& q = pr[p];
     if (!st[p].active) return;
     const int neff = st[p].end ? 0 : st[p].n;
-    if (!batch_two_step(neff, q.nsteps, 1)) return;
+    if (!batch_multi_step(neff, q.nsteps, K)) return;
     const int local = b - q.off2;
     if (local >= q.nblk2) return;
     Args2D A = q.A;
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < K; ++k) {
         A.wk[k] = sgn * q.w[neff + 1 + k];
         A.fck[k] = q.cosn[neff + k];
     }
-    A.final_ = neff + 2 == q.nsteps;
+    A.final_ = neff + K == q.nsteps;
     const int ic = st[p].ic, ip = st[p].ip;
     int x1, x2;
     batch_free_two(ic, ip, x1, x2);
     const T* prev = ip >= 0 ? reinterpret_cast<const T*>(q.s[ip]) : reinterpret_cast<const T*>(q.src);
-    multi2d_body<T, V, TY, 2, FORCE, COMP>(local % q.nbx2, local / q.nbx2, reinterpret_cast<const T*>(q.s[ic]), prev,
+    multi2d_body<T, V, TY, K, FORCE, COMP>(local % q.nbx2, local / q.nbx2, reinterpret_cast<const T*>(q.s[ic]), prev,
                                            reinterpret_cast<T*>(q.s[x1]), reinterpret_cast<T*>(q.s[x2]), q.out, q.lo,
                                            reinterpret_cast<const T*>(q.ca), reinterpret_cast<const T*>(q.cl),
                                            reinterpret_cast<const T*>(q.cm), reinterpret_cast<const T*>(q.f), A);
 }
 
-template <typename T, int V, int TY>
+template <typename T, int V, int TY, int K>
 static void batch_multi_t(bool force, bool comp, int nblocks2, hipStream_t s, const BProb2D* pr, const BState* st,
                           int np, double sgn) {
-#define ELWH_BM(F, C)                                                                                        \
-    hipLaunchKernelGGL((batch_multi2d_kernel<T, V, TY, F, C>), dim3((unsigned)xcd_grid(nblocks2)), dim3(64), 0, s, \
-                       pr, st, np, nblocks2, sgn)
+#define ELWH_BM(F, C)                                                                                           \
+    hipLaunchKernelGGL((batch_multi2d_kernel<T, V, TY, K, F, C>), dim3((unsigned)xcd_grid(nblocks2)), dim3(64), 0, \
+                       s, pr, st, np, nblocks2, sgn)
     if constexpr (sizeof(T) == 8) {
         if (force) ELWH_BM(true, false); else ELWH_BM(false, false);
     } else {
@@ -559,25 +559,28 @@ static void batch_multi_t(bool force, bool comp, int nblocks2, hipStream_t s, co
 #undef ELWH_BM
 }
 
-int batch_cols2(int V) {
+int batch_cols_k(int V, int kb) {
+    if (kb == 4) return V == 1 ? MultiCols<1, 4>::W : (V == 2 ? MultiCols<2, 4>::W : MultiCols<4, 4>::W);
     return V == 1 ? MultiCols<1, 2>::W : (V == 2 ? MultiCols<2, 2>::W : MultiCols<4, 2>::W);
 }
 
-void launch_batch_multi(bool fp32, int V, int TY, bool force, bool comp, int nblocks2, hipStream_t s,
+void launch_batch_multi(bool fp32, int V, int TY, int kb, bool force, bool comp, int nblocks2, hipStream_t s,
                         const BProb2D* pr, const BState* st, int np, double sgn, int amode) {
     (void)amode;   // the sign of the weights carries the A_h form
     if (nblocks2 <= 0) return;
-#define ELWH_BMT(T, VV, TT)                                                       \
-    if (V == VV && TY == TT) {                                                    \
-        batch_multi_t<T, VV, TT>(force, comp, nblocks2, s, pr, st, np, sgn);      \
-        return;                                                                   \
+#define ELWH_BMT(T, VV, TT, KK)                                                       \
+    if (V == VV && TY == TT && kb == KK) {                                            \
+        batch_multi_t<T, VV, TT, KK>(force, comp, nblocks2, s, pr, st, np, sgn);      \
+        return;                                                                       \
     }
     if (fp32) {
-        ELWH_BMT(float, 1, 4) ELWH_BMT(float, 1, 8) ELWH_BMT(float, 2, 4) ELWH_BMT(float, 2, 8)
-        ELWH_BMT(float, 2, 16) ELWH_BMT(float, 4, 8)
+        ELWH_BMT(float, 1, 4, 2) ELWH_BMT(float, 1, 8, 2) ELWH_BMT(float, 2, 4, 2) ELWH_BMT(float, 2, 8, 2)
+        ELWH_BMT(float, 2, 16, 2) ELWH_BMT(float, 4, 8, 2)
+        ELWH_BMT(float, 1, 4, 4) ELWH_BMT(float, 1, 8, 4) ELWH_BMT(float, 1, 10, 4) ELWH_BMT(float, 2, 8, 4)
     } else {
-        ELWH_BMT(double, 1, 4) ELWH_BMT(double, 1, 8) ELWH_BMT(double, 2, 4) ELWH_BMT(double, 2, 8)
-        ELWH_BMT(double, 2, 16)
+        ELWH_BMT(double, 1, 4, 2) ELWH_BMT(double, 1, 8, 2) ELWH_BMT(double, 2, 4, 2) ELWH_BMT(double, 2, 8, 2)
+        ELWH_BMT(double, 2, 16, 2)
+        ELWH_BMT(double, 1, 4, 4) ELWH_BMT(double, 1, 8, 4) ELWH_BMT(double, 1, 10, 4)
     }
 #undef ELWH_BMT
 }

@@ -120,10 +120,11 @@ __device__ __forceinline__ int batch_problem_of(const BProb2D* __restrict__ pr, 
     return lo;
 }
 
-// Step count of problem p at this tick (neff: steps done in its application)
-// and whether it takes a two-step launch.
-__host__ __device__ __forceinline__ bool batch_two_step(int neff, int nsteps, int fuse2) {
-    return fuse2 && neff >= 1 && nsteps - neff >= 2;
+// Whether problem p takes a kb-step launch at this tick (neff: steps done in
+// its application): it has taken the half step and has kb or more steps
+// left; otherwise it takes a single step.
+__host__ __device__ __forceinline__ bool batch_multi_step(int neff, int nsteps, int kb) {
+    return kb >= 2 && neff >= 1 && nsteps - neff >= kb;
 }
 
 // The first two state buffers other than ic and ip (ip may be -1).
