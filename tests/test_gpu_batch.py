@@ -29,7 +29,8 @@ def E():
 
 
 def _cases():
-    spec = [(24, 6.0), (40, 9.5), (33, 4.2), (50, 12.0), (29, 7.7), (64, 15.0)]
+    # (N_T - 1) mod 4 = 0, 1, 1, 1, 2, 0, 3: every remainder of a four-step tick
+    spec = [(24, 6.0), (40, 9.5), (33, 4.2), (50, 12.0), (29, 7.7), (64, 15.0), (36, 7.9)]
     return [inputs.random_problem_2d(n, om, seed=200 + k) for k, (n, om) in enumerate(spec)]
 
 
@@ -51,10 +52,13 @@ def _fp32_bound(nt):
     return 2.0 * u32 * np.sqrt(nt) * nt / (2 * np.pi) + 8.0 * u32
 
 
-def test_batch_fp64_matches_direct_and_oracle_cg(E):
+@pytest.mark.parametrize("fuse", [4, 2, 1])
+def test_batch_fp64_matches_direct_and_oracle_cg(E, fuse):
+    """Four-step ticks (the default), two-step ticks and single steps; the
+    problems' N_T leave every remainder of the tick length."""
     cases = _cases()
-    bt = E.Batch(cases)
-    _say("tiles", bt.stats())
+    bt = E.Batch(cases, fuse=fuse)
+    _say("tiles", fuse, bt.stats())
     vs, infos, status = bt.solve([c.f for c in cases], tol=1e-10, maxit=500)
     assert status == "OK"
     for c, v, info in zip(cases, vs, infos):
