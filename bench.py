@@ -684,7 +684,9 @@ def counters_pass_twofield(tile):
     fixed tiling."""
     import torch
     from paper_2205_12344_amd import elwh, inputs
-    v, ty = (int(t) for t in tile.split(","))
+    parts = [int(t) for t in tile.split(",")]
+    v, ty = parts[0], parts[1]
+    kw = {"fuse": parts[2]} if len(parts) > 2 else {}     # steps per launch (default: the library's)
     x = torch.ones(2 ** 25, dtype=torch.float64, device="cuda")
     y = torch.empty_like(x)
     y.copy_(x)
@@ -705,7 +707,9 @@ def counters_pass(tile, mapped=False):
     a fixed FP64 tiling."""
     import torch
     from paper_2205_12344_amd import elwh, inputs
-    v, ty = (int(t) for t in tile.split(","))
+    parts = [int(t) for t in tile.split(",")]
+    v, ty = parts[0], parts[1]
+    kw = {"fuse": parts[2]} if len(parts) > 2 else {}     # steps per launch (default: the library's)
     x = torch.ones(2 ** 25, dtype=torch.float64, device="cuda")
     y = torch.empty_like(x)
     y.copy_(x)
@@ -714,7 +718,7 @@ def counters_pass(tile, mapped=False):
         xs, ys, rho, lam, mu, om, _ = inputs.sector_case(200, 1, seed=14)
         ctx = elwh.MappedContext(xs, ys, rho, lam, mu, om, autotune=0)
     else:
-        ctx = elwh.context_from_case(inputs.random_square(), autotune=0)
+        ctx = elwh.context_from_case(inputs.random_square(), autotune=0, **kw)
     ctx.set_tile(elwh.FP64, v, ty)
     z = torch.zeros(ctx.field_shape, dtype=torch.float64, device="cuda")
     for _ in range(3):
@@ -738,7 +742,7 @@ def main():
                     help="only the ragged-batch FP64 solve (for kernel traces)")
     ap.add_argument("--batch-problems", type=int, default=48,
                     help="with --batch-only: the first N problems of the ragged batch")
-    ap.add_argument("--counters", default=None, metavar="V,TY",
+    ap.add_argument("--counters", default=None, metavar="V,TY[,K]",
                     help="only the dispatches for the HBM-traffic counters (benchmark workload, FP64 tiling)")
     ap.add_argument("--counters-mapped", default=None, metavar="V,TY",
                     help="the same for the mapped-grid workload")
