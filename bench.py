@@ -851,6 +851,8 @@ def main():
                 "bytes_per_launch": BYTES_PER_MULTI_LAUNCH["f64"] * nodes,
                 "avg_launch_us": round(1e3 * step_avg_ms, 3),
                 "launch_timing": f"{pk['nstep'] // fuse} launches, same workload and tiling at N_T = {nt_k}",
+                # bytes the counters saw moved per launch over the same duration
+                "traffic_GBs": round(traffic / (step_avg_ms * 1e-3) / 1e9, 1) if traffic else None,
                 "step_phase_GBs": round(phase_gbs, 1),
                 # effective fraction: lattice updates per second times the
                 # single-step algorithmic bytes (104 B/LUP), the measure under

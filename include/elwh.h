@@ -531,8 +531,8 @@ void elwh_batch_destroy(elwh_batch* b);
  * (H, W multiples of 16): five resolution levels of two 3x3 convolutions
  * with bias and SiLU (widths 32, 64, 96, 128, 128), 2x2 average pooling,
  * nearest upsampling with skip concatenation, and a 3x3 output convolution
- * to 2 channels; 1 644 578 parameters.  Convolutions are implicit GEMMs on
- * MFMA (BF16 operands, FP32 accumulation); master weights, activations,
+ * to 2 channels; 1 644 578 parameters.  Convolutions are GEMMs on MFMA over
+ * a BF16 im2col matrix (FP32 accumulation); master weights, activations,
  * gradients and the Adam state are FP32.  Tensors are NHWC float32 device
  * arrays: inputs x [B][H][W][7], outputs y [B][H][W][2], loss weights
  * w [B][H][W].  The flat parameter vector holds, per layer in order,

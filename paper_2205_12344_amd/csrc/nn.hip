@@ -5,8 +5,8 @@
 // skip concatenation; 1 644 578 parameters) maps the problem data on the node
 // grid -- log rho, log mu, log(lambda/mu), the forcing normalised by its
 // maximum, omega h and omega -- to the displacement, and its output seeds the
-// solve (x0).  Convolutions are implicit GEMMs on MFMA with BF16 operands
-// and FP32 accumulation; master weights, activations, gradients and Adam
+// solve (x0).  Convolutions are GEMMs on MFMA over a BF16 im2col matrix
+// with FP32 accumulation; master weights, activations, gradients and Adam
 // state are FP32.  Training minimises the relative error in the M-weighted
 // norm against solutions computed by the solver itself.
 #include <cmath>

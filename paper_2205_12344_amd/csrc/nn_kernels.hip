@@ -1,5 +1,5 @@
 // Kernels of the warm-start network: BF16 MFMA GEMM with FP32 accumulation
-// (the convolutions' implicit GEMMs), im2col / col2im, SiLU, pooling,
+// (the convolutions, as GEMMs over an im2col matrix), im2col / col2im, SiLU, pooling,
 // upsampling, channel copies, loss and Adam.  Activations are NHWC FP32;
 // GEMM operands are BF16.
 #include <hip/hip_runtime.h>
