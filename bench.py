@@ -860,7 +860,11 @@ def main():
                 # needs 120/K B/LUP, frac above)
                 "effective_frac_kernel": round(fuse * nodes / (step_avg_ms * 1e-3) * BYTES_PER_LUP[(2, "f64", 1)]
                                                / (HBM_PEAK_GBS * 1e9), 4),
-                "effective_frac_end_to_end": round(value * BYTES_PER_LUP[(2, "f64", 1)] / (HBM_PEAK_GBS * 1e9), 4)}
+                "effective_frac_end_to_end": round(value * BYTES_PER_LUP[(2, "f64", 1)] / (HBM_PEAK_GBS * 1e9), 4),
+                "note": (f"temporal blocking: {fuse} time steps per launch at 120 B per node and launch "
+                         f"({BYTES_PER_MULTI_LAUNCH['f64'] / fuse:g} B per lattice update); frac prices the kernel "
+                         "at its own bytes, effective_frac_* price lattice updates at the single step's 104 B; "
+                         "the launch is latency- and issue-bound at two waves per SIMD, not bandwidth-bound")}
     ctx.close()
 
     variants = {}
