@@ -488,11 +488,13 @@ elwh_status elwh_autotune(elwh_ctx* ctx, int prec, int reps, double* best_step_u
 
 /*
  * Ragged batch of independent 2-D problems (sizes, media, omega and N_T may
- * all differ), solved together: one launch per time step advances every
- * unfinished problem by one step of its own filter application; a problem
- * whose application ends runs its CG update on the device in the same
- * step and starts its next application at the next one; converged problems
- * drop out.  The CG phase is captured as a hipGraph of several steps and
+ * all differ), solved together: each batched step ("tick") advances every
+ * unfinished problem by opts->fuse >= 4 ? 4 : 2 steps of its own filter
+ * application where that many are left (one step where not, and always
+ * for opts->fuse = 1), in one multi-step and one single-step launch over
+ * all problems; a problem whose application ends runs its CG update on the
+ * device in the same tick and starts its next application at the next one;
+ * converged problems drop out.  The CG phase is captured as a hipGraph of several steps and
  * replayed (elwh_batch_set_graph(b, 0) runs the same launches eagerly).
  * Each problem's solve is the one of elwh_solve (Sec. 4.5): CG on A_h in the
  * M inner product with b = Pi_h 0; FP64, or (opts->prec = ELWH_FP32_STEP)
